@@ -1,0 +1,245 @@
+"""Oracle: local projections, the filtered GenEO eigenproblem, the coarse
+space, the two-level additive Schwarz preconditioner and PCG.
+
+Paper passages:
+  * b_i(U,V) = (A_i U, V) and xi_0i, the b_i-orthogonal projection onto
+    span(G_i) (Section 2, eq. (b), Definition of orthogonal projections and
+    complements, eq. (Giortho), and the lemma with eq. (inverseBw));
+  * the generalised eigenproblem (I - xi_j^T) D_j A_j D_j (I - xi_j) V =
+    lambda A_j^Neu V, eigenvectors with lambda > tau, coarse vectors
+    R_j^T D_j (I - xi_j) V (Section 3.2, GEVP "tauthresholdAS",
+    eq. (eigAtildeBAS)); tau = 10 (Section 5);
+  * the classical GenEO pencil D_j A_j D_j V = lambda A_j^Neu V (Section 3.2,
+    eq. (eigGenEOClassis)) for comparison;
+  * the split near-kernel space V_G = span(R_i^T D_i G_i) (Definition
+    "Split near-kernel coarse space") and V_0 = V_G + V_GenEO (eq. (V0GenEOAS));
+  * E = Z^T A Z, P_0 = Z E^-1 Z^T A and the balanced two-level form
+    M^-1 = Z E^-1 Z^T + (I - P_0) sum_i R_i^T A_i^-1 R_i (I - P_0^T)
+    (Section 2, eq. (AS) and eq. (AS2); Section 3.2, the explicit M_AS,2);
+  * the condition number bound kappa <= (1 + k1 tau) k0 (Section 3.2, main
+    theorem; k0 eq. (k0), k1 after it).
+
+Readings: the paper solves with right-preconditioned GMRES at rtol 1e-6;
+this oracle runs preconditioned conjugate gradients (the preconditioner is
+symmetric positive definite) from x0 = 0, stopping at the first iterate with
+||r_k||_2 <= rtol ||b||_2 (recurrence residual).
+"""
+from __future__ import annotations
+
+import numpy as np
+import scipy.linalg as sla
+import scipy.sparse as sp
+import scipy.sparse.linalg as spla
+
+
+def xi_projection(Ai, Gi):
+    """xi_0i = G_i (G_i^T A_i G_i)^-1 G_i^T A_i, dense n_i x n_i: the
+    A_i-orthogonal projection onto span(G_i) (Section 2)."""
+    Ai = np.asarray(Ai)
+    Gd = Gi.toarray() if sp.issparse(Gi) else np.asarray(Gi)
+    S = Gd.T @ Ai @ Gd
+    return Gd @ np.linalg.solve(S, Gd.T @ Ai)
+
+
+def filtered_pencil(Ai, Neu, Di, Gi):
+    """Left and right matrices of the filtered GEVP (eq. (eigAtildeBAS))."""
+    Ai = np.asarray(Ai)
+    xi = xi_projection(Ai, Gi)
+    Q = np.eye(Ai.shape[0]) - xi
+    DAD = Di[:, None] * Ai * Di[None, :]
+    At = Q.T @ DAD @ Q
+    At = 0.5 * (At + At.T)
+    return At, np.asarray(Neu)
+
+
+def gevp(Ai, Neu, Di, Gi, tau=10.0, nev_max=20, classical=False):
+    """Solve the local GEVP with a dense symmetric-definite eigensolver.
+
+    Returns (lam_desc, V_desc, sel): all eigenvalues in decreasing order with
+    B-normalised eigenvectors, and the number selected: those with
+    lambda > tau, at most nev_max (0 = no cap)."""
+    if classical:
+        Ai = np.asarray(Ai)
+        At = Di[:, None] * Ai * Di[None, :]
+        B = np.asarray(Neu)
+    else:
+        At, B = filtered_pencil(Ai, Neu, Di, Gi)
+    lam, V = sla.eigh(At, B)
+    lam, V = lam[::-1], V[:, ::-1]
+    sel = int((lam > tau).sum())
+    if nev_max:
+        sel = min(sel, nev_max)
+    return lam, V, sel
+
+
+def geneo_vectors(Ai, Gi, Di, V):
+    """Local coarse vectors D_i (I - xi_i) V (to be extended by R_i^T)."""
+    xi = xi_projection(np.asarray(Ai), Gi)
+    return Di[:, None] * (V - xi @ V)
+
+
+def greedy_cholesky(E, drop_tol=1e-8):
+    """Cholesky factor of E restricted to a basis chosen greedily from the
+    columns of Z, left to right.
+
+    The columns R_i^T D_i G_i span V_G but are not linearly independent in
+    general (several subdomains hold the same node where the partition of
+    unity is locally proportional, or D_i vanishes on a node's whole edge
+    star), so E = Z^T A Z is only semi-definite.  Column j is kept iff its
+    squared A-distance to the span of the kept columns before it (the Schur
+    complement pivot) exceeds drop_tol * E_jj; the kept columns are then a
+    basis of V_0 and Z_K E_KK^-1 Z_K^T is the coarse operator of V_0
+    (identical to Z E^+ Z^T).  Returns (L of E_KK, boolean mask of kept)."""
+    S = np.array(E, dtype=np.float64, copy=True)
+    n = S.shape[0]
+    d = np.diag(S).copy()
+    kept = np.zeros(n, dtype=bool)
+    for j in range(n):
+        p = S[j, j]
+        if not (p > drop_tol * d[j]) or d[j] <= 0:
+            S[j:, j] = 0.0
+            S[j, j:] = 0.0
+            continue
+        kept[j] = True
+        col = S[j + 1:, j] / np.sqrt(p)
+        S[j + 1:, j + 1:] -= np.outer(col, col)
+    Ek = E[np.ix_(kept, kept)]
+    return sla.cholesky(Ek, lower=True), kept
+
+
+class TwoLevel:
+    """M_AS,2 with the SNK (+ GenEO) coarse space, built from a Decomposition.
+
+    variant: 'snk_geneo' (the method), 'snk' (tau = infinity), 'as' (one
+    level, no coarse space), 'nk' / 'nk_geneo' (Z from the global G)."""
+
+    def __init__(self, dec, tau=10.0, nev_max=20, variant="snk_geneo", classical=False,
+                 drop_tol=1e-8):
+        self.dec = dec
+        sysm = dec.sys
+        n = sysm.n
+        self.variant = variant
+        self.local_L = []
+        self.eig = []
+        self.G_locals = []
+        cols_snk = []
+        geneo_cols = []
+        self.geneo_counts = []
+        for i in range(dec.N):
+            Ai = dec.A_dir(i).toarray()
+            self.local_L.append(sla.cholesky(Ai, lower=True))
+            Gi, gnodes, _ = dec.G_local(i)
+            self.G_locals.append((Gi, gnodes))
+            if variant in ("snk", "snk_geneo"):
+                Zi = sp.diags(dec.D[i]) @ Gi            # D_i G_i, n_i x p_i
+                cols_snk.append((dec.dofs[i], Zi.tocoo()))
+            if variant in ("snk_geneo", "nk_geneo"):
+                Neu = dec.A_neu(i).toarray()
+                lam, V, sel = gevp(Ai, Neu, dec.D[i], Gi, tau, nev_max, classical=classical)
+                self.eig.append((lam, V, sel))
+                self.geneo_counts.append(sel)
+                if sel:
+                    W = geneo_vectors(Ai, Gi, dec.D[i], V[:, :sel])
+                    full = np.zeros((n, sel))
+                    full[dec.dofs[i]] = W
+                    geneo_cols.append(full)
+        blocks = []
+        if variant in ("snk", "snk_geneo"):
+            r, c, v = [], [], []
+            off = 0
+            for dofs, Zi in cols_snk:
+                r.append(dofs[Zi.row])
+                c.append(Zi.col + off)
+                v.append(Zi.data)
+                off += Zi.shape[1]
+            blocks.append(sp.csc_matrix((np.concatenate(v), (np.concatenate(r), np.concatenate(c))),
+                                        shape=(n, off)))
+        elif variant in ("nk", "nk_geneo"):
+            blocks.append(sysm.G.tocsc())
+        self.n_snk = blocks[0].shape[1] if blocks else 0
+        if geneo_cols:
+            blocks.append(sp.csc_matrix(np.concatenate(geneo_cols, axis=1)))
+        self.n_geneo = sum(g.shape[1] for g in geneo_cols)
+        if blocks:
+            self.Z = sp.hstack(blocks).tocsc()
+            self.AZ = (sysm.A @ self.Z).tocsc()
+            E = (self.Z.T @ self.AZ).toarray()
+            self.E = 0.5 * (E + E.T)
+            self.n0 = E.shape[0]
+            self.E_L, self.kept = greedy_cholesky(self.E, drop_tol)
+            self.rank = int(self.kept.sum())
+        else:
+            self.Z = None
+            self.n0 = 0
+
+    def coarse_solve(self, v):
+        """E^+ v restricted to the kept (basis) columns; dropped entries 0."""
+        k = self.kept
+        out = np.zeros_like(v)
+        out[k] = sla.cho_solve((self.E_L, True), v[k])
+        return out
+
+    def one_level(self, r):
+        """sum_i R_i^T A_i^-1 R_i r (eq. (AS)), dense Cholesky solves."""
+        y = np.zeros_like(r)
+        for i, L in enumerate(self.local_L):
+            d = self.dec.dofs[i]
+            y[d] += sla.cho_solve((L, True), r[d])
+        return y
+
+    def apply(self, r):
+        """z = M_AS,2^-1 r = Z E^-1 Z^T r + (I - P_0) M_AS^-1 (I - P_0^T) r."""
+        if self.Z is None:
+            return self.one_level(r)
+        c = self.coarse_solve(self.Z.T @ r)
+        y = self.one_level(r - self.AZ @ c)
+        c2 = self.coarse_solve(self.AZ.T @ y)
+        return self.Z @ c + y - self.Z @ c2
+
+    def matrix(self):
+        """Dense M^-1 (tiny cases only)."""
+        n = self.dec.sys.n
+        return np.column_stack([self.apply(e) for e in np.eye(n)])
+
+
+def pcg(A, b, M=None, rtol=1e-8, maxit=1000):
+    """Preconditioned conjugate gradients (Hestenes-Stiefel) from x0 = 0.
+    Returns (x, iterations, residual history ||r_k||/||b||)."""
+    x = np.zeros_like(b)
+    r = b.copy()
+    nb = np.linalg.norm(b)
+    z = M(r) if M is not None else r.copy()
+    p = z.copy()
+    rz = r @ z
+    hist = [1.0]
+    for k in range(1, maxit + 1):
+        q = A @ p
+        alpha = rz / (p @ q)
+        x += alpha * p
+        r -= alpha * q
+        rn = np.linalg.norm(r)
+        hist.append(rn / nb)
+        if rn <= rtol * nb:
+            return x, k, hist
+        z = M(r) if M is not None else r.copy()
+        rz_new = r @ z
+        p = z + (rz_new / rz) * p
+        rz = rz_new
+    return x, maxit, hist
+
+
+def k0_k1(dec):
+    """k0 = max_i #{j : R_j A R_i^T != 0} (eq. (k0)); k1 = the largest number
+    of subdomains whose intersection has non-zero measure (cells shared)."""
+    A = dec.sys.A
+    N = dec.N
+    k0 = 0
+    for i in range(N):
+        touched = np.zeros(dec.sys.n, bool)
+        touched[A[dec.dofs[i]].indices] = True
+        k0 = max(k0, sum(1 for j in range(N) if touched[dec.dofs[j]].any()))
+    H = int(dec.sys.mesh["hex_of_tet"].max()) + 1
+    cnt = np.zeros(H, np.int64)
+    for c in dec.cells:
+        cnt[c] += 1
+    return k0, int(cnt.max())

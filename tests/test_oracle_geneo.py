@@ -1,0 +1,202 @@
+"""Pins of the oracle's decomposition, GEVP, coarse space and two-level
+preconditioner (no GPU)."""
+import numpy as np
+import pytest
+import scipy.linalg as sla
+import scipy.sparse as sp
+import scipy.sparse.linalg as spla
+
+import workloads as W
+from oracle import decomp, fem, geneo
+
+
+def _case(dims, p, overlap=1, rule="all", gamma=1e-3, contrast=1e3, seed=0, removed=None):
+    mesh = W.hex_box_mesh(dims, removed=removed)
+    T = mesh["tets"].shape[0]
+    rng = np.random.default_rng(seed)
+    H = mesh["hex_ijk"].shape[0]
+    mu_h = np.where(rng.random(H) < 0.2, contrast, 1.0)
+    s = fem.System(mesh, mu_h[mesh["hex_of_tet"]], np.ones(T), gamma,
+                   W.dirichlet_flags(mesh["bface_tag"], rule))
+    part = decomp.box_partition(mesh, p)
+    return s, decomp.Decomposition(s, part, overlap)
+
+
+@pytest.fixture(scope="module")
+def tiny():
+    return _case((4, 4, 4), (2, 2, 1))
+
+
+@pytest.fixture(scope="module")
+def floating():
+    # 3x3x3 boxes of a 6^3 cube: the centre subdomain touches no boundary
+    return _case((6, 6, 6), (3, 3, 3), gamma=1e-2, contrast=1e2, seed=1)
+
+
+def test_paper_snk_count_beam_n8():
+    """Section 5, Table 1: SNK size 25K for N = 8 strips of the 64x16x16-hex
+    beam with one layer of overlap.  SNK counts every node of every
+    overlapping subdomain (end strips 9 hexes, inner strips 10 hexes long):
+    2*10*289 + 6*11*289 = 24,854."""
+    mesh = W.hex_box_mesh((64, 16, 16), h=1.0 / 16)
+    part = decomp.box_partition(mesh, (8, 1, 1))
+    adj = decomp.cell_adjacency(mesh)
+    hot = mesh["hex_of_tet"]
+    total = 0
+    for i in range(8):
+        inside = part == i
+        inside = inside | (adj @ inside.astype(float) > 0)
+        tets = np.nonzero(inside[hot])[0]
+        total += np.unique(mesh["tets"][tets]).size
+    assert total == 24_854
+
+
+def test_partition_of_unity(tiny, floating):
+    """sum_i R_i^T D_i R_i = I (Section 2, eq. (PoU))."""
+    for s, dec in (tiny, floating):
+        I = sum(dec.R(i).T @ sp.diags(dec.D[i]) @ dec.R(i) for i in range(dec.N))
+        assert abs(I - sp.eye(s.n)).max() < 1e-14
+        assert all((d >= 0).all() for d in dec.D)
+
+
+def test_dirichlet_and_neumann_local_matrices(tiny):
+    """A_i = R_i A R_i^T; A_i^Neu <= A_i (the Dirichlet matrix adds the
+    contributions of the outside elements touching the interface), both SPD
+    because gamma > 0 (Section 2)."""
+    s, dec = tiny
+    for i in range(dec.N):
+        Ri = dec.R(i)
+        Ai = dec.A_dir(i).toarray()
+        assert np.allclose(Ai, (Ri @ s.A @ Ri.T).toarray())
+        Neu = dec.A_neu(i).toarray()
+        assert np.linalg.eigvalsh(Neu).min() > 0
+        assert np.linalg.eigvalsh(Ai - Neu).min() > -1e-12 * abs(Ai).max()
+
+
+def test_xi_projection_identities(tiny, floating):
+    """xi_0i is the b_i-orthogonal projection on span(G_i) (Section 2):
+    xi^2 = xi, xi G_i = G_i, A_i xi symmetric."""
+    for s, dec in (tiny, floating):
+        for i in range(dec.N):
+            Ai = dec.A_dir(i).toarray()
+            Gi, _, _ = dec.G_local(i)
+            X = geneo.xi_projection(Ai, Gi)
+            assert np.allclose(X @ X, X, atol=1e-9)
+            assert np.allclose(X @ Gi.toarray(), Gi.toarray(), atol=1e-9)
+            AX = Ai @ X
+            assert np.allclose(AX, AX.T, atol=1e-9 * abs(AX).max())
+
+
+def test_floating_component_dropped(floating):
+    """The centre subdomain reaches no Dirichlet node: its G_i loses exactly
+    one column, and what remains has full column rank."""
+    s, dec = floating
+    drops = [dec.G_local(i)[2] for i in range(dec.N)]
+    assert sum(drops) == 1 and drops[13] == 1
+    for i in range(dec.N):
+        Gi = dec.G_local(i)[0].toarray()
+        assert np.linalg.matrix_rank(Gi) == Gi.shape[1]
+
+
+def test_gevp_against_brute_force(tiny):
+    """The filtered GEVP (Section 3.2, eq. (eigAtildeBAS)): its eigenvalues
+    equal those of the non-symmetric matrix B^-1 Atilde (numpy.linalg.eig),
+    all are >= 0, G_i lies in the lambda = 0 eigenspace, and eigenvectors
+    with lambda > 0 are B-orthogonal to span(G_i)."""
+    s, dec = tiny
+    for i in range(dec.N):
+        Ai = dec.A_dir(i).toarray()
+        Neu = dec.A_neu(i).toarray()
+        Gi, _, _ = dec.G_local(i)
+        lam, V, sel = geneo.gevp(Ai, Neu, dec.D[i], Gi, tau=10.0, nev_max=0)
+        At, B = geneo.filtered_pencil(Ai, Neu, dec.D[i], Gi)
+        ev = np.sort(np.linalg.eig(np.linalg.solve(B, At))[0].real)[::-1]
+        assert np.allclose(lam[:10], ev[:10], rtol=1e-8)
+        assert lam.min() > -1e-10 * lam.max()
+        assert np.allclose(At @ Gi.toarray(), 0, atol=1e-9 * abs(At).max())
+        pos = lam > 1e-8 * lam[0]
+        Gd = Gi.toarray()
+        assert abs(Gd.T @ B @ V[:, pos]).max() < 1e-8 * np.sqrt(abs(B).max())
+
+
+def test_gevp_lemma_bound(tiny):
+    """Lemma (GEVP bound, Section 3.2): for all U,
+    (A_i D (I-xi)(I-pi)U, D (I-xi)(I-pi)U) <= tau (A_i^Neu U, U), where pi
+    projects on the eigenvectors with lambda > tau (no cap)."""
+    s, dec = tiny
+    rng = np.random.default_rng(5)
+    tau = 2.0   # small tau so that the space being removed is not empty
+    for i in range(dec.N):
+        Ai = dec.A_dir(i).toarray()
+        Neu = dec.A_neu(i).toarray()
+        Gi, _, _ = dec.G_local(i)
+        lam, V, sel = geneo.gevp(Ai, Neu, dec.D[i], Gi, tau=tau, nev_max=0)
+        Vt = V[:, :sel]
+        xi = geneo.xi_projection(Ai, Gi)
+        Q = np.eye(Ai.shape[0]) - xi
+        for _ in range(5):
+            U = rng.normal(size=Ai.shape[0])
+            U1 = U - Vt @ (Vt.T @ (Neu @ U))      # (I - pi) U, pi B-orthogonal
+            w = dec.D[i] * (Q @ U1)
+            assert w @ Ai @ w <= tau * (U @ Neu @ U) * (1 + 1e-9)
+
+
+def test_classical_pencil_has_more_large_eigenvalues(tiny):
+    """Section 3.2, remark: the classical pencil D A D V = lambda A^Neu V has
+    many more eigenvalues above tau than the filtered one."""
+    s, dec = tiny
+    i = 0
+    Ai = dec.A_dir(i).toarray()
+    Neu = dec.A_neu(i).toarray()
+    Gi, _, _ = dec.G_local(i)
+    lf, _, sf = geneo.gevp(Ai, Neu, dec.D[i], Gi, tau=10.0, nev_max=0)
+    lc, _, sc = geneo.gevp(Ai, Neu, dec.D[i], Gi, tau=10.0, nev_max=0, classical=True)
+    assert sc > sf + 10
+
+
+def test_coarse_basis_rank_and_operator(tiny, floating):
+    """The greedy basis keeps exactly rank(Z) columns (SVD) and gives the same
+    coarse operator as the pseudo-inverse: Z_K E_K^-1 Z_K^T = Z E^+ Z^T."""
+    for s, dec in (tiny, floating):
+        pre = geneo.TwoLevel(dec, tau=10.0, nev_max=20)
+        Z = pre.Z.toarray()
+        sv = np.linalg.svd(Z, compute_uv=False)
+        assert pre.rank == int((sv > 1e-10 * sv[0]).sum())
+        Zk = Z[:, pre.kept]
+        C1 = Zk @ np.linalg.solve(pre.E[np.ix_(pre.kept, pre.kept)], Zk.T)
+        C2 = Z @ np.linalg.pinv(pre.E, rcond=1e-12, hermitian=True) @ Z.T
+        assert np.allclose(C1, C2, atol=1e-7 * abs(C1).max())
+
+
+def test_two_level_preconditioner_properties(tiny):
+    """M_AS,2^-1 is symmetric positive definite, P_0 is a projection with
+    P_0 Z = Z, and the spectrum of M^-1 A lies in [1/(1 + k1 tau), k0]
+    (main theorem, Section 3.2, with c_R = k0 from the continuity lemma)."""
+    s, dec = tiny
+    tau = 10.0
+    pre = geneo.TwoLevel(dec, tau=tau, nev_max=0)
+    Minv = pre.matrix()
+    assert np.allclose(Minv, Minv.T, atol=1e-10 * abs(Minv).max())
+    A = s.A.toarray()
+    Zk = pre.Z.toarray()[:, pre.kept]
+    P0 = Zk @ np.linalg.solve(Zk.T @ A @ Zk, Zk.T @ A)
+    assert np.allclose(P0 @ P0, P0, atol=1e-8)
+    assert np.allclose(P0 @ Zk, Zk, atol=1e-8)
+    ev = np.sort(sla.eigvals(Minv @ A).real)
+    k0, k1 = geneo.k0_k1(dec)
+    assert ev[0] >= 1.0 / (1.0 + k1 * tau) - 1e-10
+    assert ev[-1] <= k0 + 1e-10
+    assert np.linalg.eigvalsh(0.5 * (Minv + Minv.T)).min() > 0
+
+
+def test_pcg_converges_to_direct_solution(floating):
+    s, dec = floating
+    pre = geneo.TwoLevel(dec, tau=10.0, nev_max=20)
+    b = np.random.default_rng(7).standard_normal(s.n)
+    x, it, hist = geneo.pcg(s.A, b, pre.apply, rtol=1e-8)
+    xs = spla.spsolve(s.A.tocsc(), b)
+    assert np.linalg.norm(b - s.A @ x) <= 1.5e-8 * np.linalg.norm(b)
+    assert np.linalg.norm(x - xs) <= 1e-6 * np.linalg.norm(xs)
+    # the two-level method needs fewer iterations than one-level AS
+    _, it1, _ = geneo.pcg(s.A, b, geneo.TwoLevel(dec, variant="as").apply, rtol=1e-8)
+    assert it < it1
