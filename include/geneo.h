@@ -1,0 +1,231 @@
+/*
+ * libgeneo: two-level GenEO-type additive Schwarz preconditioner for
+ * lowest-order Nedelec (edge) discretisations of the positive Maxwell
+ * problem curl(mu^-1 curl E) + gamma eps E = f, n x E = 0 on Gamma_D,
+ * on one AMD Instinct MI355X (gfx950).
+ *
+ * Method: Bootland, Dolean, Nataf, Tournier, "A robust and adaptive
+ * GenEO-type domain decomposition preconditioner for H(curl) problems in
+ * three-dimensional general topologies" (arXiv 2311.18783).
+ *
+ * Conventions (every call):
+ *   - indices are int32, 0-based; user-visible reals are FP64;
+ *   - every call returns 0 (GENEO_OK) or a negative geneo_status; no C++
+ *     exception crosses the ABI; geneo_last_error() gives the message of the
+ *     last failure on a context;
+ *   - host arrays passed in are only read during the call and may be freed
+ *     afterwards; handles are owned by the library until geneo_free_*;
+ *   - "device" pointers are HIP device memory on the context's device
+ *     (e.g. torch float64 cuda tensors' data_ptr()), contiguous, in the free
+ *     edge order reported by geneo_system_info; work on them is ordered on
+ *     the context's stream;
+ *   - a context is not thread-safe.
+ */
+#ifndef GENEO_H
+#define GENEO_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  GENEO_OK = 0,
+  GENEO_EINVAL = -1,       /* bad argument, shape or option */
+  GENEO_ENOTSPD = -2,      /* a Cholesky pivot was not positive (message names the matrix and pivot) */
+  GENEO_ENOCONV = -3,      /* iteration limit reached; info is still filled */
+  GENEO_EOOM = -4,         /* device or host allocation failed */
+  GENEO_EHIP = -5,         /* a HIP runtime call failed */
+  GENEO_EUNSUPPORTED = -6, /* option not supported */
+  GENEO_ESYNC = -7         /* a device-side bounded wait expired (kernel finished, results invalid) */
+} geneo_status;
+
+typedef struct geneo_ctx geneo_ctx;
+typedef struct geneo_system geneo_system;
+typedef struct geneo_decomp geneo_decomp;
+typedef struct geneo_precond geneo_precond;
+
+/* Tetrahedral mesh (Section 1: Omega with boundary Gamma; Section 5:
+ * Cartesian meshes).  Cells group tets (e.g. the 6 tets of a hex); the
+ * overlap of the decomposition is grown by whole cells. */
+typedef struct {
+  int64_t n_nodes;
+  const double* xyz;             /* [n_nodes*3] host, node coordinates */
+  int64_t n_tets;
+  const int32_t* tets;           /* [n_tets*4] host, node ids */
+  const int32_t* cell_of_tet;    /* [n_tets] host, cell id per tet, or NULL = one cell per tet */
+  int64_t n_bfaces;
+  const int32_t* bfaces;         /* [n_bfaces*3] host, boundary triangles */
+  const int8_t* bface_dirichlet; /* [n_bfaces] host, 1 = n x E = 0 imposed, 0 = natural condition */
+} geneo_mesh;
+
+typedef struct {
+  int64_t n;            /* free edges = unknowns (Dirichlet edges eliminated) */
+  int64_t nnz;          /* nonzeros of A */
+  int64_t n_edges;      /* all edges */
+  int64_t n_free_nodes; /* columns of the gradient matrix G */
+  int64_t n_cells;
+  double assemble_ms;   /* device time of the element + scatter kernels */
+} geneo_system_info;
+
+/* --- context --------------------------------------------------------- */
+
+/* Create a context on HIP device `device`.  `hip_stream` is the hipStream_t
+ * all work is ordered on; NULL means the device's default (null) stream. */
+int geneo_create(geneo_ctx** ctx, int device, void* hip_stream);
+void geneo_destroy(geneo_ctx* ctx);
+const char* geneo_last_error(const geneo_ctx* ctx);
+
+/* --- assemble: A = K + gamma M over free edges, and G ------------------ */
+
+/* Assemble the lowest-order Nedelec system of the weak form
+ * a(u,v) = int mu^-1 curl u . curl v + gamma eps u . v (Section 2, the
+ * bilinear form; Section 1, A U = (K + gamma M) U = f).  mu, eps: host
+ * [n_tets], piecewise constant, > 0; gamma > 0.  Edges are oriented from the
+ * lower to the higher node id and numbered lexicographically; edges and
+ * nodes of Dirichlet triangles are eliminated.  G (free edges x free nodes)
+ * holds -1 / +1 at an edge's first / second node: the gradient matrix whose
+ * range is the kernel of the discrete curl-curl part (Section 1). */
+int geneo_assemble(geneo_ctx* ctx, const geneo_mesh* mesh, const double* mu,
+                   const double* eps, double gamma, geneo_system** out);
+int geneo_system_info_get(const geneo_system* sys, geneo_system_info* info);
+/* Copy A to host CSR arrays (rowptr [n+1], colind [nnz], vals [nnz]) and the
+ * global edge id of each free edge (free_edge_ids [n]).  Any pointer may be NULL. */
+int geneo_system_export(geneo_ctx* ctx, const geneo_system* sys, int32_t* rowptr,
+                        int32_t* colind, double* vals, int32_t* free_edge_ids);
+/* y = A x, device vectors of length n. */
+int geneo_spmv(geneo_ctx* ctx, const geneo_system* sys, const double* x, double* y);
+
+/* --- partition: overlapping subdomains, restriction, partition of unity -- */
+
+typedef enum { GENEO_PART_BOX = 0, GENEO_PART_RCB = 1, GENEO_PART_EXPLICIT = 2 } geneo_part_kind;
+
+typedef struct {
+  int32_t kind;              /* geneo_part_kind */
+  int32_t box[3];            /* BOX: px, py, pz boxes over the bounding box, by cell centroid */
+  int32_t nparts;            /* RCB: number of parts */
+  const double* rcb_jitter;  /* RCB: [nparts-1] host, relative shift of each split, preorder */
+  const int32_t* part_of_cell; /* EXPLICIT: [n_cells] host */
+  int32_t overlap;           /* layers of vertex-adjacent cells added (Section 5: one layer) */
+} geneo_partition_opts;
+
+typedef struct {
+  int32_t n_sub;
+  int32_t n_min, n_max;      /* smallest / largest n_i */
+  int64_t sum_n;             /* sum of n_i */
+  int64_t sum_p;             /* sum of local free-node counts (SNK columns, paper convention) */
+  int32_t n_floating;        /* subdomains with a floating component */
+  double sum_n3_over_3;      /* sum n_i^3 / 3: Cholesky flops of the local factors */
+} geneo_decomp_info;
+
+/* Build the overlapping decomposition (Section 2: Omega_i, N_i, R_i, the
+ * partition of unity sum R_i^T D_i R_i = I).  Each non-overlapping part
+ * grows by `overlap` layers of cells sharing a vertex.  D_i: chi_i / sum_j
+ * chi_j with chi_i = 1 on the nodes of the original cells of part i and
+ * 1 - d/overlap on nodes first reached by layer d, averaged over the two
+ * ends of an edge. */
+int geneo_partition(geneo_ctx* ctx, const geneo_system* sys,
+                    const geneo_partition_opts* opts, geneo_decomp** out);
+int geneo_decomp_info_get(const geneo_decomp* dec, geneo_decomp_info* info);
+/* Subdomain i: n_i, and optionally (host) its free-edge list N_i [n_i]
+ * (sorted), its PoU D_i [n_i], its G_i column nodes [p_i] (free-node ids;
+ * floating components lose their lowest node). */
+int geneo_decomp_subdomain(const geneo_decomp* dec, int32_t i, int32_t* n_i, int32_t* dofs,
+                           double* pou, int32_t* p_i, int32_t* gnodes);
+
+/* --- setup: local factors, GenEO eigenproblems, coarse space ------------ */
+
+typedef enum { GENEO_FP64 = 0, GENEO_FP32_REFINE1 = 1 } geneo_precision;
+typedef enum { GENEO_COARSE_SNK_GENEO = 0, GENEO_COARSE_SNK = 1, GENEO_COARSE_NONE = 2 } geneo_coarse_kind;
+
+typedef struct {
+  double tau;               /* GenEO threshold, keep lambda > tau (Section 5: 10) */
+  int32_t nev_max;          /* at most this many eigenvectors per subdomain */
+  int32_t coarse;           /* geneo_coarse_kind */
+  int32_t local_precision;  /* geneo_precision of the local factors and solves */
+  double lobpcg_tol;        /* relative eigen-residual target */
+  int32_t lobpcg_maxit;
+  int32_t lobpcg_guard;     /* extra block vectors beyond nev_max */
+  uint64_t seed;            /* random start blocks */
+  double coarse_drop_tol;   /* relative Schur pivot below which a coarse column is dependent */
+  const double* warm_start; /* host [sum_i n_i * nev_max] start blocks (column-major per subdomain) or NULL */
+} geneo_setup_opts;
+
+typedef struct {
+  int32_t n0;               /* coarse columns (SNK + GenEO) */
+  int32_t n0_rank;          /* columns kept as a basis */
+  int32_t n_snk;            /* SNK columns */
+  int32_t n_geneo;          /* GenEO columns */
+  int32_t lobpcg_iters;     /* LOBPCG iterations (max over subdomains) */
+  int32_t lobpcg_unconverged; /* eigenpairs not converged at maxit */
+  int32_t fp64_fallbacks;   /* FP32 local factors replaced by FP64 */
+  double min_kept_pivot;    /* smallest relative Schur pivot kept in the coarse factor */
+  double max_dropped_pivot; /* largest relative Schur pivot dropped */
+  double t_extract_ms, t_factor_ms, t_gevp_ms, t_coarse_build_ms, t_coarse_factor_ms; /* device times */
+  double local_factor_flops; /* sum n_i^3/3 */
+} geneo_precond_info;
+
+void geneo_setup_opts_default(geneo_setup_opts* o);
+/* Build M_AS,2^-1 = Z E^-1 Z^T + (I - P_0) sum_i R_i^T A_i^-1 R_i (I - P_0^T)
+ * (Section 2, eq. (AS2); Section 3.2, the explicit form of M_AS,2) with
+ * A_i = R_i A R_i^T factored by dense Cholesky, and Z spanning the split
+ * near-kernel space span(R_i^T D_i G_i) (Definition "Split near-kernel
+ * coarse space") plus, per subdomain, the vectors R_j^T D_j (I - xi_j) V
+ * of the generalised eigenproblem
+ *   (I - xi_j^T) D_j A_j D_j (I - xi_j) V = lambda A_j^Neu V,  lambda > tau
+ * (Section 3.2, GEVP with eq. (eigAtildeBAS)); xi_j is the A_j-orthogonal
+ * projection on span(G_j).  E = Z^T A Z is factored in FP64; columns of Z
+ * that are dependent on earlier ones (relative Schur pivot <= drop tol) are
+ * left out of the basis. */
+int geneo_setup(geneo_ctx* ctx, const geneo_system* sys, const geneo_decomp* dec,
+                const geneo_setup_opts* opts, geneo_precond** out);
+int geneo_precond_info_get(const geneo_precond* pc, geneo_precond_info* info);
+/* Eigenvalues (descending) found for subdomain i: writes up to `cap` values,
+ * *count = number written, *selected = number entering the coarse space. */
+int geneo_precond_eigs(const geneo_precond* pc, int32_t i, double* lam, int32_t cap,
+                       int32_t* count, int32_t* selected);
+
+/* z = M_AS,2^-1 r, device vectors of length n (the paper's preconditioner). */
+int geneo_apply(geneo_ctx* ctx, const geneo_precond* pc, const double* r, double* z);
+
+/* --- solve: preconditioned conjugate gradients -------------------------- */
+
+typedef struct {
+  double rtol;      /* stop at the first k with ||r_k||_2 <= rtol ||b||_2 */
+  int32_t maxit;
+} geneo_solve_opts;
+
+typedef struct {
+  int32_t iterations;
+  double rel_residual;   /* recurrence residual ||r_k|| / ||b|| at exit */
+  double solve_ms;       /* device wall time of the iteration */
+} geneo_solve_info;
+
+/* Solve A x = b from x0 = 0 with PCG preconditioned by pc (or plain CG if pc
+ * is NULL).  b, x: device, length n.  Returns GENEO_ENOCONV at maxit with
+ * info filled and the last iterate in x. */
+int geneo_solve(geneo_ctx* ctx, const geneo_system* sys, const geneo_precond* pc,
+                const double* b, double* x, const geneo_solve_opts* opts, geneo_solve_info* info);
+
+/* --- kernel-level entry: batched dense Cholesky ------------------------ */
+
+/* Factor `batch` symmetric positive definite matrices in place, A_b = L_b L_b^T,
+ * the dense local factorisation of the method.  A: device, matrix b is
+ * column-major n_b x n_b with leading dimension ld_b = n_b rounded up to 128,
+ * starting at element offset off_b (off_b multiple of 32); only the lower
+ * triangle is read and written; pad rows/columns must hold the identity.
+ * precision: GENEO_FP64 (A is double*) or GENEO_FP32_REFINE1 (A is float*).
+ * On a non-positive pivot returns GENEO_ENOTSPD naming the matrix and pivot. */
+int geneo_potrf_batched(geneo_ctx* ctx, int32_t batch, const int32_t* n_host,
+                        const int64_t* off_host, void* A, int32_t precision, double* elapsed_ms);
+
+/* --- lifetime ----------------------------------------------------------- */
+void geneo_free_system(geneo_system* sys);
+void geneo_free_decomp(geneo_decomp* dec);
+void geneo_free_precond(geneo_precond* pc);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* GENEO_H */

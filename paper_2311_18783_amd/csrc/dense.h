@@ -1,0 +1,42 @@
+// Batched dense factorisation / solve plans (see dense.hip).
+#pragma once
+
+#include "internal.h"
+
+namespace geneo {
+
+struct MatDesc {
+  int64_t off;       // element offset of the matrix (column-major, ld)
+  int64_t inv_off;   // element offset of its first 128x128 diagonal-block inverse
+  int64_t diag_off;  // offset into the original-diagonal array, or -1
+  int64_t voff;      // offset of its segment in a batch vector
+  int32_t ld;        // = n_pad, multiple of NB
+  int32_t nblk;      // n_pad / NB
+  int32_t flag_off;  // first block-done flag of this matrix
+  int32_t n;         // true size
+};
+
+struct FactorPlan {
+  int nmat = 0, max_blk = 0;
+  std::vector<MatDesc> h_desc;
+  std::vector<int> cnt;              // matrices active at each panel step
+  std::vector<int64_t> trsm_tiles, syrk_tiles, pre_off;
+  int64_t n_items = 0;               // triangular-solve work items (blocks)
+  DevBuf<MatDesc> d_desc;
+  DevBuf<int32_t> d_order;
+  DevBuf<int64_t> d_prefix;
+  DevBuf<int32_t> d_items_fwd, d_items_bwd;
+  void build(const std::vector<MatDesc>& descs, hipStream_t st);
+};
+
+void factor(const FactorPlan& P, double* A, double* Ainv, const double* odiag, double drop_tol, double* pivrel,
+            DevErr* err, hipStream_t st);
+void factor(const FactorPlan& P, float* A, float* Ainv, const double* odiag, double drop_tol, double* pivrel,
+            DevErr* err, hipStream_t st);
+// x <- (L L^T)^-1 x on every matrix segment of the batch vector x.
+void solve(const FactorPlan& P, const double* A, const double* Ainv, double* x, unsigned* sync, unsigned* flags,
+           DevErr* err, hipStream_t st);
+void solve(const FactorPlan& P, const float* A, const float* Ainv, double* x, unsigned* sync, unsigned* flags,
+           DevErr* err, hipStream_t st);
+
+}  // namespace geneo

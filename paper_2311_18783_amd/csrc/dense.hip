@@ -1,0 +1,496 @@
+// Batched dense Cholesky factorisation and triangular solves for matrices of
+// uneven size (the overlapping local matrices A_i and the coarse matrix E).
+//
+// Layout: matrix m is column-major, ld = n_pad (a multiple of NB = 128),
+// starting at element offset off; pad rows/columns hold the identity, so
+// every panel and tile is a full 128 x 128 block.  Blocked right-looking
+// Cholesky, one launch per phase per panel step covers every matrix still
+// active at that step:
+//   potrf : the 128 x 128 diagonal block, factored and inverted in LDS;
+//   trsm  : L21 = A21 inv(L11)^T as MFMA GEMM tiles (128 rows per workgroup);
+//   syrk  : A22 -= L21 L21^T on the lower 128 x 128 tiles (MFMA).
+// The inverses of the diagonal blocks are kept and used by the triangular
+// solves.  Each MFMA workgroup is 4 waves, one 64 x 64 sub-tile each, with
+// operands read straight from L2/HBM: at the FP64 MFMA rate of gfx950 the
+// operand stream per CU is a small fraction of what the caches deliver.
+//
+// Pivot rule: a non-positive pivot is an error (matrix, column) unless a
+// drop tolerance is given; then a column whose Schur pivot is <= drop_tol
+// times its original diagonal is dependent on the earlier columns: it gets a
+// unit diagonal, a zero column, and zero row and column in the block
+// inverse, so every solve returns 0 in that position.
+#include <algorithm>
+
+#include "dense.h"
+
+namespace geneo {
+
+typedef double d4_t __attribute__((ext_vector_type(4)));
+typedef float f4_t __attribute__((ext_vector_type(4)));
+
+template <typename T> struct AccT;
+template <> struct AccT<double> { using type = d4_t; };
+template <> struct AccT<float> { using type = f4_t; };
+
+__device__ inline d4_t mfma16(double a, double b, d4_t c) { return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0); }
+__device__ inline f4_t mfma16(float a, float b, f4_t c) { return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0); }
+
+__device__ inline void set_err(DevErr* e, int code, int mat, int idx) {
+  if (atomicCAS(&e->code, 0, code) == 0) {
+    e->mat = mat;
+    e->idx = idx;
+  }
+}
+
+// ---------------------------------------------------------------- potrf
+constexpr int LDA = NB + 1;
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_potrf(const MatDesc* __restrict__ desc, const int32_t* __restrict__ order,
+                                               int step, T* __restrict__ A, T* __restrict__ Ainv,
+                                               const double* __restrict__ odiag, double drop_tol,
+                                               double* __restrict__ pivrel, DevErr* err) {
+  extern __shared__ unsigned char smem_raw[];
+  T* a = reinterpret_cast<T*>(smem_raw);                   // [NB * LDA]
+  __shared__ double invd[NB];
+  __shared__ double tmp[NB];
+  const int m = order[blockIdx.x];
+  const MatDesc d = desc[m];
+  const int tid = threadIdx.x;
+  const int64_t k0 = (int64_t)step * NB;
+  T* blk = A + d.off + k0 * d.ld + k0;
+  for (int idx = tid; idx < NB * NB; idx += 256) {
+    int r = idx % NB, c = idx / NB;
+    a[c * LDA + r] = (r >= c) ? blk[(int64_t)c * d.ld + r] : T(0);
+  }
+  __syncthreads();
+  for (int j = 0; j < NB; ++j) {
+    if (tid == 0) {
+      double p = (double)a[j * LDA + j];
+      double od = (odiag && d.diag_off >= 0) ? odiag[d.diag_off + k0 + j] : 0.0;
+      bool drop = false;
+      if (drop_tol > 0.0) {
+        drop = !(p > drop_tol * od) || !(od > 0.0);
+        if (pivrel && d.diag_off >= 0) pivrel[d.diag_off + k0 + j] = od > 0.0 ? p / od : 0.0;
+      }
+      if (drop) {
+        a[j * LDA + j] = T(1);
+        invd[j] = 0.0;
+      } else if (!(p > 0.0)) {
+        set_err(err, GENEO_ENOTSPD, m, (int)(k0 + j));
+        a[j * LDA + j] = T(1);
+        invd[j] = 0.0;
+      } else {
+        double sq = sqrt(p);
+        a[j * LDA + j] = (T)sq;
+        invd[j] = 1.0 / sq;
+      }
+    }
+    __syncthreads();
+    const T s = (T)invd[j];
+    for (int i = j + 1 + tid; i < NB; i += 256) a[j * LDA + i] *= s;
+    __syncthreads();
+    const int rem = NB - 1 - j;
+    for (int idx = tid; idx < rem * rem; idx += 256) {
+      int ii = idx % rem, ll = idx / rem;
+      if (ii >= ll) {
+        int i = j + 1 + ii, l = j + 1 + ll;
+        a[l * LDA + i] -= a[j * LDA + i] * a[j * LDA + l];
+      }
+    }
+    __syncthreads();
+  }
+  for (int idx = tid; idx < NB * NB; idx += 256) {
+    int r = idx % NB, c = idx / NB;
+    if (r >= c) blk[(int64_t)c * d.ld + r] = a[c * LDA + r];
+  }
+  __syncthreads();
+  // in-place inverse of the unit-free lower factor, last column first:
+  // X[j][j] = 1/L[j][j];  X[j+1:, j] = -X[j][j] * X[j+1:, j+1:] L[j+1:, j]
+  for (int j = NB - 1; j >= 0; --j) {
+    const int i = j + 1 + tid;
+    if (tid < NB - 1 - j) {
+      double acc = 0.0;
+      for (int l = j + 1; l <= i; ++l) acc += (double)a[l * LDA + i] * (double)a[j * LDA + l];
+      tmp[i] = acc;
+    }
+    __syncthreads();
+    if (tid < NB - 1 - j) a[j * LDA + i] = (T)(-invd[j] * tmp[i]);
+    if (tid == 0) a[j * LDA + j] = (T)invd[j];
+    __syncthreads();
+  }
+  T* inv = Ainv + d.inv_off + (int64_t)step * NB * NB;
+  for (int idx = tid; idx < NB * NB; idx += 256) {
+    int r = idx % NB, c = idx / NB;
+    inv[(int64_t)c * NB + r] = (r >= c) ? a[c * LDA + r] : T(0);
+  }
+}
+
+// ------------------------------------------------------------ MFMA tiles
+// C[64x64 per wave] (+)= sum_k Arow[r][k] * Brow[c][k] over k in [0, 128),
+// Arow/Brow column-major with leading dimensions lda/ldb.  Lane l of a
+// 16x16x4 MFMA supplies A[l%16][l/16] and B[l/16][l%16]; it receives
+// D[4*(l/16)+v][l%16] (FP32) or D[(l/16)+4*v][l%16] (FP64), v = 0..3.
+template <typename T>
+__device__ inline void tile_mma(const T* __restrict__ Ar, int64_t lda, const T* __restrict__ Br, int64_t ldb,
+                                typename AccT<T>::type acc[4][4], bool negate) {
+  const int lane = threadIdx.x & 63;
+  const int lr = lane & 15, lk = lane >> 4;
+#pragma unroll 2
+  for (int kk = 0; kk < NB; kk += 4) {
+    T af[4], bf[4];
+#pragma unroll
+    for (int b = 0; b < 4; ++b) {
+      af[b] = Ar[(int64_t)(kk + lk) * lda + 16 * b + lr];
+      bf[b] = Br[(int64_t)(kk + lk) * ldb + 16 * b + lr];
+    }
+    if (negate) {
+#pragma unroll
+      for (int b = 0; b < 4; ++b) af[b] = -af[b];
+    }
+#pragma unroll
+    for (int bi = 0; bi < 4; ++bi)
+#pragma unroll
+      for (int bj = 0; bj < 4; ++bj) acc[bi][bj] = mfma16(af[bi], bf[bj], acc[bi][bj]);
+  }
+}
+
+// row of accumulator element v held by `lane` in a 16x16 output block
+template <typename T> __device__ inline int acc_row(int lane, int v);
+template <> __device__ inline int acc_row<float>(int lane, int v) { return 4 * (lane >> 4) + v; }
+template <> __device__ inline int acc_row<double>(int lane, int v) { return (lane >> 4) + 4 * v; }
+
+template <typename T>
+__device__ inline void tile_load(const T* C, int64_t ldc, typename AccT<T>::type acc[4][4]) {
+  const int lane = threadIdx.x & 63;
+  const int col = lane & 15;
+#pragma unroll
+  for (int bi = 0; bi < 4; ++bi)
+#pragma unroll
+    for (int bj = 0; bj < 4; ++bj)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) acc[bi][bj][v] = C[(int64_t)(16 * bj + col) * ldc + 16 * bi + acc_row<T>(lane, v)];
+}
+
+template <typename T>
+__device__ inline void tile_store(T* C, int64_t ldc, typename AccT<T>::type acc[4][4]) {
+  const int lane = threadIdx.x & 63;
+  const int col = lane & 15;
+#pragma unroll
+  for (int bi = 0; bi < 4; ++bi)
+#pragma unroll
+    for (int bj = 0; bj < 4; ++bj)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) C[(int64_t)(16 * bj + col) * ldc + 16 * bi + acc_row<T>(lane, v)] = acc[bi][bj][v];
+}
+
+__device__ inline int find_mat(const int64_t* __restrict__ prefix, int cnt, int64_t w) {
+  int lo = 0, hi = cnt - 1;
+  while (lo < hi) {
+    int mid = (lo + hi + 1) >> 1;
+    if (prefix[mid] <= w) lo = mid; else hi = mid - 1;
+  }
+  return lo;
+}
+
+// L21 = A21 * inv(L11)^T, one 128-row tile per workgroup.
+template <typename T>
+__global__ __launch_bounds__(256) void k_trsm(const MatDesc* __restrict__ desc, const int32_t* __restrict__ order,
+                                              const int64_t* __restrict__ prefix, int cnt, int step,
+                                              T* __restrict__ A, const T* __restrict__ Ainv) {
+  const int j = find_mat(prefix, cnt, blockIdx.x);
+  const int m = order[j];
+  const MatDesc d = desc[m];
+  const int64_t t = blockIdx.x - prefix[j];
+  const int w = threadIdx.x >> 6;
+  const int wr = w & 1, wc = w >> 1;
+  const int64_t k0 = (int64_t)step * NB;
+  const int64_t r0 = k0 + NB + t * NB + 64 * wr;
+  using Acc = typename AccT<T>::type;
+  Acc acc[4][4];
+#pragma unroll
+  for (int bi = 0; bi < 4; ++bi)
+#pragma unroll
+    for (int bj = 0; bj < 4; ++bj) acc[bi][bj] = Acc{0, 0, 0, 0};
+  const T* Ar = A + d.off + k0 * d.ld + r0;
+  const T* inv = Ainv + d.inv_off + (int64_t)step * NB * NB + 64 * wc;  // B[k][n] = inv[n][k]
+  tile_mma<T>(Ar, d.ld, inv, NB, acc, false);
+  __syncthreads();  // every wave has read the A21 tile before any writes
+  tile_store<T>(A + d.off + (k0 + 64 * wc) * d.ld + r0, d.ld, acc);
+}
+
+// A22[ti][tj] -= L21[ti] L21[tj]^T on lower tiles ti >= tj.
+template <typename T>
+__global__ __launch_bounds__(256) void k_syrk(const MatDesc* __restrict__ desc, const int32_t* __restrict__ order,
+                                              const int64_t* __restrict__ prefix, int cnt, int step,
+                                              T* __restrict__ A) {
+  const int j = find_mat(prefix, cnt, blockIdx.x);
+  const int m = order[j];
+  const MatDesc d = desc[m];
+  const int64_t u = blockIdx.x - prefix[j];
+  int64_t ti = (int64_t)((sqrt(8.0 * (double)u + 1.0) - 1.0) * 0.5);
+  while (ti * (ti + 1) / 2 > u) --ti;
+  while ((ti + 1) * (ti + 2) / 2 <= u) ++ti;
+  const int64_t tj = u - ti * (ti + 1) / 2;
+  const int w = threadIdx.x >> 6;
+  const int wr = w & 1, wc = w >> 1;
+  const int64_t k0 = (int64_t)step * NB;
+  const int64_t R0 = k0 + NB;
+  const int64_t rows = R0 + ti * NB + 64 * wr, cols = R0 + tj * NB + 64 * wc;
+  using Acc = typename AccT<T>::type;
+  Acc acc[4][4];
+  T* C = A + d.off + cols * d.ld + rows;
+  tile_load<T>(C, d.ld, acc);
+  tile_mma<T>(A + d.off + k0 * d.ld + rows, d.ld, A + d.off + k0 * d.ld + cols, d.ld, acc, true);
+  tile_store<T>(C, d.ld, acc);
+}
+
+// --------------------------------------------------------------- plan
+
+void FactorPlan::build(const std::vector<MatDesc>& descs, hipStream_t st) {
+  h_desc = descs;
+  nmat = (int)descs.size();
+  std::vector<int32_t> ord(nmat);
+  for (int i = 0; i < nmat; ++i) ord[i] = i;
+  std::stable_sort(ord.begin(), ord.end(), [&](int a, int b) { return descs[a].nblk > descs[b].nblk; });
+  max_blk = nmat ? descs[ord[0]].nblk : 0;
+  cnt.assign(max_blk, 0);
+  trsm_tiles.assign(max_blk, 0);
+  syrk_tiles.assign(max_blk, 0);
+  pre_off.assign(max_blk, 0);
+  std::vector<int64_t> pre;
+  for (int s = 0; s < max_blk; ++s) {
+    int c = 0;
+    while (c < nmat && descs[ord[c]].nblk > s) ++c;
+    cnt[s] = c;
+    pre_off[s] = (int64_t)pre.size();
+    int64_t acc_t = 0, acc_s = 0;
+    std::vector<int64_t> pt(c + 1), ps(c + 1);
+    for (int k = 0; k < c; ++k) {
+      pt[k] = acc_t;
+      ps[k] = acc_s;
+      int64_t T = descs[ord[k]].nblk - s - 1;
+      acc_t += T;
+      acc_s += T * (T + 1) / 2;
+    }
+    pt[c] = acc_t;
+    ps[c] = acc_s;
+    trsm_tiles[s] = acc_t;
+    syrk_tiles[s] = acc_s;
+    pre.insert(pre.end(), pt.begin(), pt.end());
+    pre.insert(pre.end(), ps.begin(), ps.end());
+  }
+  d_desc.upload(descs, st);
+  d_order.upload(ord, st);
+  d_prefix.upload(pre, st);
+  // triangular-solve work items: forward in increasing block order across
+  // matrices, backward in decreasing order
+  std::vector<int32_t> fwd, bwd;
+  for (int s = 0; s < max_blk; ++s)
+    for (int k = 0; k < cnt[s]; ++k) {
+      int m = ord[k];
+      fwd.push_back(m);
+      fwd.push_back(s);
+      bwd.push_back(m);
+      bwd.push_back(descs[m].nblk - 1 - s);
+    }
+  n_items = (int64_t)fwd.size() / 2;
+  d_items_fwd.upload(fwd, st);
+  d_items_bwd.upload(bwd, st);
+}
+
+template <typename T>
+static void factor_impl(const FactorPlan& P, T* A, T* Ainv, const double* odiag, double drop_tol, double* pivrel,
+                        DevErr* err, hipStream_t st) {
+  const size_t lds = sizeof(T) * NB * LDA;
+  static bool attr_set = false;
+  if (!attr_set) {
+    HIP_CHECK(hipFuncSetAttribute((const void*)k_potrf<T>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+    attr_set = true;
+  }
+  for (int s = 0; s < P.max_blk; ++s) {
+    const int64_t* pt = P.d_prefix.p + P.pre_off[s];
+    const int64_t* ps = pt + P.cnt[s] + 1;
+    k_potrf<T><<<dim3(P.cnt[s]), dim3(256), lds, st>>>(P.d_desc.p, P.d_order.p, s, A, Ainv, odiag, drop_tol, pivrel,
+                                                         err);
+    if (P.trsm_tiles[s] > 0) {
+      k_trsm<T><<<dim3((unsigned)P.trsm_tiles[s]), dim3(256), 0, st>>>(P.d_desc.p, P.d_order.p, pt, P.cnt[s], s, A,
+                                                                        Ainv);
+      k_syrk<T><<<dim3((unsigned)P.syrk_tiles[s]), dim3(256), 0, st>>>(P.d_desc.p, P.d_order.p, ps, P.cnt[s], s, A);
+    }
+  }
+  HIP_CHECK(hipGetLastError());
+}
+
+void factor(const FactorPlan& P, double* A, double* Ainv, const double* odiag, double drop_tol, double* pivrel,
+            DevErr* err, hipStream_t st) {
+  factor_impl<double>(P, A, Ainv, odiag, drop_tol, pivrel, err, st);
+}
+void factor(const FactorPlan& P, float* A, float* Ainv, const double* odiag, double drop_tol, double* pivrel,
+            DevErr* err, hipStream_t st) {
+  factor_impl<float>(P, A, Ainv, odiag, drop_tol, pivrel, err, st);
+}
+
+// ------------------------------------------------------- triangular solves
+// Sync-free blocked solves over the whole batch.  Work item = (matrix, block
+// row); a workgroup takes the next item from a ticket counter, so every item
+// it waits on was taken earlier by a running workgroup and no wait can
+// deadlock.  Block-done flags carry an epoch number that is bumped before
+// each solve, so flags never need clearing.  Every wait is bounded; on
+// expiry the workgroup records GENEO_ESYNC and goes on, so the kernel always
+// drains.
+constexpr unsigned kSpinLimit = 1u << 24;
+
+__global__ void k_solve_begin(unsigned* sync) {
+  sync[0] = 0;
+  sync[1] = sync[1] + 1;
+}
+
+__device__ inline void wait_flag(const unsigned* flag, unsigned epoch, DevErr* err) {
+  unsigned spins = 0;
+  while (__hip_atomic_load(flag, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) != epoch) {
+    if (++spins > kSpinLimit) {
+      set_err(err, GENEO_ESYNC, -1, -1);
+      break;
+    }
+    __builtin_amdgcn_s_sleep(1);
+  }
+}
+
+__device__ inline void publish(unsigned* flag, unsigned epoch) {
+  __threadfence();
+  __hip_atomic_store(flag, epoch, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+__device__ inline double wave_sum(double v) {
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
+// x <- L^-1 x for every matrix (x: batch vector, segment of matrix m at voff[m]).
+template <typename T>
+__global__ __launch_bounds__(256) void k_trsv_fwd(const MatDesc* __restrict__ desc, const int32_t* __restrict__ items,
+                                                  const T* __restrict__ A, const T* __restrict__ Ainv,
+                                                  double* x, unsigned* sync, unsigned* flags, DevErr* err) {
+  __shared__ double xs[NB];
+  __shared__ double red[256];
+  __shared__ int s_t;
+  __shared__ unsigned s_epoch;
+  const int tid = threadIdx.x;
+  if (tid == 0) {
+    s_t = (int)atomicAdd(&sync[0], 1u);
+    s_epoch = __hip_atomic_load(&sync[1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  }
+  __syncthreads();
+  const int m = items[2 * s_t], I = items[2 * s_t + 1];
+  const unsigned epoch = s_epoch;
+  const MatDesc d = desc[m];
+  double* xv = x + d.voff;
+  const int r = tid & (NB - 1), h = tid >> 7;
+  double acc = 0.0;
+  for (int J = 0; J < I; ++J) {
+    if (tid == 0) wait_flag(flags + d.flag_off + J, epoch, err);
+    __syncthreads();
+    if (tid < NB) xs[tid] = __hip_atomic_load(xv + (int64_t)J * NB + tid, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    __syncthreads();
+    const T* col = A + d.off + ((int64_t)J * NB + 64 * h) * d.ld + (int64_t)I * NB + r;
+#pragma unroll 8
+    for (int c = 0; c < 64; ++c) acc += (double)col[(int64_t)c * d.ld] * xs[64 * h + c];
+    __syncthreads();
+  }
+  red[tid] = acc;
+  __syncthreads();
+  if (tid < NB) xs[tid] = xv[(int64_t)I * NB + tid] - red[tid] - red[tid + NB];
+  __syncthreads();
+  const T* inv = Ainv + d.inv_off + (int64_t)I * NB * NB;
+  double acc2 = 0.0;
+#pragma unroll 8
+  for (int c = 0; c < 64; ++c) acc2 += (double)inv[(int64_t)(64 * h + c) * NB + r] * xs[64 * h + c];
+  red[tid] = acc2;
+  __syncthreads();
+  if (tid < NB) __hip_atomic_store(xv + (int64_t)I * NB + tid, red[tid] + red[tid + NB], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  __syncthreads();
+  if (tid == 0) publish(flags + d.flag_off + I, epoch);
+}
+
+// x <- L^-T x for every matrix.
+template <typename T>
+__global__ __launch_bounds__(256) void k_trsv_bwd(const MatDesc* __restrict__ desc, const int32_t* __restrict__ items,
+                                                  const T* __restrict__ A, const T* __restrict__ Ainv,
+                                                  double* x, unsigned* sync, unsigned* flags, DevErr* err) {
+  __shared__ double xs[NB];
+  __shared__ double red[NB];
+  __shared__ int s_t;
+  __shared__ unsigned s_epoch;
+  const int tid = threadIdx.x;
+  const int lane = tid & 63, w = tid >> 6;
+  if (tid == 0) {
+    s_t = (int)atomicAdd(&sync[0], 1u);
+    s_epoch = __hip_atomic_load(&sync[1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  }
+  __syncthreads();
+  const int m = items[2 * s_t], I = items[2 * s_t + 1];
+  const unsigned epoch = s_epoch;
+  const MatDesc d = desc[m];
+  double* xv = x + d.voff;
+  double acc[32];
+#pragma unroll
+  for (int cc = 0; cc < 32; ++cc) acc[cc] = 0.0;
+  const T* colbase = A + d.off + ((int64_t)I * NB + 32 * w) * d.ld;
+  for (int J = I + 1; J < d.nblk; ++J) {
+    if (tid == 0) wait_flag(flags + d.flag_off + J, epoch, err);
+    __syncthreads();
+    if (tid < NB) xs[tid] = __hip_atomic_load(xv + (int64_t)J * NB + tid, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    __syncthreads();
+    const double x0 = xs[lane], x1 = xs[lane + 64];
+    const T* b = colbase + (int64_t)J * NB + lane;
+#pragma unroll
+    for (int cc = 0; cc < 32; ++cc) acc[cc] += (double)b[(int64_t)cc * d.ld] * x0 + (double)b[(int64_t)cc * d.ld + 64] * x1;
+    __syncthreads();
+  }
+#pragma unroll
+  for (int cc = 0; cc < 32; ++cc) {
+    double v = wave_sum(acc[cc]);
+    if (lane == 0) red[32 * w + cc] = v;
+  }
+  __syncthreads();
+  if (tid < NB) xs[tid] = xv[(int64_t)I * NB + tid] - red[tid];
+  __syncthreads();
+  // x_I = inv(L_II)^T s : x[c] = sum_r inv[r][c] s[r]
+  const T* inv = Ainv + d.inv_off + (int64_t)I * NB * NB;
+  const double s0 = xs[lane], s1 = xs[lane + 64];
+  for (int cc = 0; cc < 32; ++cc) {
+    const int c = 32 * w + cc;
+    double v = (double)inv[(int64_t)c * NB + lane] * s0 + (double)inv[(int64_t)c * NB + lane + 64] * s1;
+    v = wave_sum(v);
+    if (lane == 0) red[c] = v;
+  }
+  __syncthreads();
+  if (tid < NB) __hip_atomic_store(xv + (int64_t)I * NB + tid, red[tid], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  __syncthreads();
+  if (tid == 0) publish(flags + d.flag_off + I, epoch);
+}
+
+template <typename T>
+static void solve_impl(const FactorPlan& P, const T* A, const T* Ainv, double* x, unsigned* sync, unsigned* flags,
+                       DevErr* err, hipStream_t st) {
+  if (P.n_items == 0) return;
+  k_solve_begin<<<1, 1, 0, st>>>(sync);
+  k_trsv_fwd<T><<<dim3((unsigned)P.n_items), dim3(256), 0, st>>>(P.d_desc.p, P.d_items_fwd.p, A, Ainv, x, sync,
+                                                                   flags, err);
+  k_solve_begin<<<1, 1, 0, st>>>(sync);
+  k_trsv_bwd<T><<<dim3((unsigned)P.n_items), dim3(256), 0, st>>>(P.d_desc.p, P.d_items_bwd.p, A, Ainv, x, sync,
+                                                                   flags, err);
+  HIP_CHECK(hipGetLastError());
+}
+
+void solve(const FactorPlan& P, const double* A, const double* Ainv, double* x, unsigned* sync, unsigned* flags,
+           DevErr* err, hipStream_t st) {
+  solve_impl<double>(P, A, Ainv, x, sync, flags, err, st);
+}
+void solve(const FactorPlan& P, const float* A, const float* Ainv, double* x, unsigned* sync, unsigned* flags,
+           DevErr* err, hipStream_t st) {
+  solve_impl<float>(P, A, Ainv, x, sync, flags, err, st);
+}
+
+}  // namespace geneo

@@ -1,0 +1,110 @@
+// Internal declarations shared by the libgeneo translation units.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <cstdio>
+#include <stdexcept>
+#include <string>
+#include <vector>
+
+#include "../../include/geneo.h"
+
+namespace geneo {
+
+// Panel / tile width of the dense factorisations and triangular solves.
+constexpr int NB = 128;
+
+struct Error : std::runtime_error {
+  int code;
+  Error(int c, const std::string& m) : std::runtime_error(m), code(c) {}
+};
+
+#define HIP_CHECK(x)                                                                    \
+  do {                                                                                  \
+    hipError_t e_ = (x);                                                                \
+    if (e_ != hipSuccess)                                                               \
+      throw ::geneo::Error(GENEO_EHIP, std::string(#x " failed: ") + hipGetErrorString(e_)); \
+  } while (0)
+
+inline int64_t round_up(int64_t v, int64_t m) { return (v + m - 1) / m * m; }
+
+// Device buffer owned by a handle.
+template <typename T>
+struct DevBuf {
+  T* p = nullptr;
+  size_t n = 0;
+  DevBuf() = default;
+  DevBuf(const DevBuf&) = delete;
+  DevBuf& operator=(const DevBuf&) = delete;
+  ~DevBuf() { release(); }
+  void release() {
+    if (p) (void)hipFree(p);
+    p = nullptr;
+    n = 0;
+  }
+  void alloc(size_t count) {
+    release();
+    if (count == 0) return;
+    hipError_t e = hipMalloc(&p, count * sizeof(T));
+    if (e != hipSuccess) {
+      p = nullptr;
+      throw Error(GENEO_EOOM, "device allocation of " + std::to_string(count * sizeof(T)) + " bytes failed");
+    }
+    n = count;
+  }
+  void upload(const std::vector<T>& h, hipStream_t s) {
+    alloc(h.size());
+    if (!h.empty()) HIP_CHECK(hipMemcpyAsync(p, h.data(), h.size() * sizeof(T), hipMemcpyHostToDevice, s));
+  }
+};
+
+// Device error record written by kernels: [0] status, [1] matrix, [2] index.
+struct DevErr {
+  int code, mat, idx, pad;
+};
+
+}  // namespace geneo
+
+struct geneo_ctx {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  bool own_stream = false;
+  std::string err;
+  geneo::DevErr* d_err = nullptr;     // device error record
+  geneo::DevErr* h_err = nullptr;     // pinned host mirror
+  unsigned* d_sync = nullptr;         // [0] ticket counter, [1] epoch (sync-free solves)
+  hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
+};
+
+struct geneo_system {
+  int64_t n = 0, nnz = 0, n_edges = 0, n_nodes = 0, n_free_nodes = 0, n_tets = 0, n_cells = 0;
+  double gamma = 0;
+  double assemble_ms = 0;
+  std::vector<double> xyz;
+  std::vector<int32_t> tets, cell_of_tet;
+  std::vector<int32_t> edges;          // [2*n_edges] (low, high)
+  std::vector<int32_t> tet_edges;      // [6*T] global edge ids, local edge order (0,1)(0,2)(0,3)(1,2)(1,3)(2,3)
+  std::vector<int32_t> edge_to_free, node_to_free, free_edges, free_nodes;
+  std::vector<int32_t> rowptr, colind; // CSR structure of A over free edges
+  std::vector<int32_t> contrib_ptr, contrib;  // slot -> element entries t*36+p*6+q
+  // device
+  geneo::DevBuf<double> d_val, d_elem, d_xyz, d_mu, d_eps;
+  geneo::DevBuf<int32_t> d_rowptr, d_colind, d_contrib_ptr, d_contrib, d_tets, d_tet_cell;
+};
+
+struct geneo_decomp {
+  int32_t N = 0;
+  int overlap = 0;
+  std::vector<int32_t> part_of_cell;
+  std::vector<int64_t> dofs_ptr;       // [N+1] into dofs / pou
+  std::vector<int32_t> dofs;           // concatenated sorted free-edge ids
+  std::vector<double> pou;             // D_i values
+  std::vector<int64_t> gn_ptr;         // [N+1] into gnodes
+  std::vector<int32_t> gnodes;         // kept local free-node columns (free-node ids)
+  std::vector<int32_t> n_dropped;      // floating components per subdomain
+  std::vector<int64_t> p_all;          // all local free nodes (paper count) per subdomain
+  std::vector<int64_t> cells_ptr;      // [N+1]
+  std::vector<int32_t> cells;          // concatenated cells of Omega_i (sorted)
+};

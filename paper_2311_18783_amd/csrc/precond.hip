@@ -1,0 +1,692 @@
+// Setup and application of the two-level additive Schwarz preconditioner
+//   M^-1 r = Z E^-1 Z^T r + (I - P_0) sum_i R_i^T A_i^-1 R_i (I - P_0^T) r,
+// and preconditioned conjugate gradients.
+//
+// Batch vectors: the restrictions R_i r of all subdomains side by side, each
+// padded to n_pad; gathers use the batch -> free-edge map, and the sum of
+// extensions R_i^T uses the inverse map (free edge -> batch positions) in a
+// fixed order, so results are bitwise reproducible.
+#include <algorithm>
+#include <cmath>
+#include <numeric>
+
+#include "precond.h"
+
+namespace geneo {
+
+// ---------------------------------------------------------- small kernels
+__global__ void k_fill_identity_pad(const MatDesc* __restrict__ desc, int nmat, double* __restrict__ A,
+                                    float* __restrict__ Af, int64_t total, const int64_t* __restrict__ mat_start) {
+  int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (idx >= total) return;
+  int lo = 0, hi = nmat - 1;
+  while (lo < hi) {
+    int mid = (lo + hi + 1) >> 1;
+    if (mat_start[mid] <= idx) lo = mid; else hi = mid - 1;
+  }
+  const MatDesc d = desc[lo];
+  int64_t loc = idx - mat_start[lo];
+  int64_t r = loc % d.ld, c = loc / d.ld;
+  double v = (r == c && r >= d.n) ? 1.0 : 0.0;
+  if (A) A[d.off + loc] = v;
+  if (Af) Af[d.off + loc] = (float)v;
+}
+
+// dense A_i from the global CSR values through the local CSR triplets
+__global__ void k_dense_scatter(int64_t nnz, const int32_t* __restrict__ lrow, const int32_t* __restrict__ lcol,
+                                const int32_t* __restrict__ lslot, const int64_t* __restrict__ nnz_off, int nmat,
+                                const MatDesc* __restrict__ desc, const double* __restrict__ val,
+                                double* __restrict__ A, float* __restrict__ Af) {
+  int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (k >= nnz) return;
+  int lo = 0, hi = nmat - 1;
+  while (lo < hi) {
+    int mid = (lo + hi + 1) >> 1;
+    if (nnz_off[mid] <= k) lo = mid; else hi = mid - 1;
+  }
+  const MatDesc d = desc[lo];
+  int64_t pos = d.off + (int64_t)lcol[k] * d.ld + lrow[k];
+  double v = val[lslot[k]];
+  if (A) A[pos] = v;
+  if (Af) Af[pos] = (float)v;
+}
+
+__global__ void k_gather(int64_t len, const int32_t* __restrict__ bmap, const double* __restrict__ g,
+                         double* __restrict__ b) {
+  int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (k >= len) return;
+  int32_t e = bmap[k];
+  b[k] = e >= 0 ? g[e] : 0.0;
+}
+
+// out[e] = (base ? base[e] : 0) + sign * sum_{k in inv(e)} b[k]
+__global__ void k_scatter_add(int64_t n, const int32_t* __restrict__ ip, const int32_t* __restrict__ ii,
+                              const double* __restrict__ b, const double* __restrict__ base, double sign,
+                              double* __restrict__ out) {
+  int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (e >= n) return;
+  double acc = 0.0;
+  for (int32_t k = ip[e]; k < ip[e + 1]; ++k) acc += b[ii[k]];
+  out[e] = (base ? base[e] : 0.0) + sign * acc;
+}
+
+// t[c] = sum over the entries of sparse column c: val * r[row]
+__global__ void k_csc_t(int64_t ncol, const int32_t* __restrict__ cp, const int32_t* __restrict__ ri,
+                        const double* __restrict__ cv, const double* __restrict__ r, double* __restrict__ t) {
+  int64_t c = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (c >= ncol) return;
+  double acc = 0.0;
+  for (int32_t k = cp[c]; k < cp[c + 1]; ++k) acc += cv[k] * r[ri[k]];
+  t[c] = acc;
+}
+
+// u[e] = sum over the entries of sparse row e: val * c[col]  (+ add[e] if given)
+__global__ void k_csr(int64_t n, const int32_t* __restrict__ rp, const int32_t* __restrict__ ci,
+                      const double* __restrict__ v, const double* __restrict__ c, const double* __restrict__ add,
+                      double* __restrict__ u) {
+  int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (e >= n) return;
+  double acc = add ? add[e] : 0.0;
+  for (int32_t k = rp[e]; k < rp[e + 1]; ++k) acc += v[k] * c[ci[k]];
+  u[e] = acc;
+}
+
+// GenEO columns, transpose: t[gen_off_j + k] = W_j(:,k) . b_j (one wave per column)
+__global__ void k_w_t(int nsub, const int32_t* __restrict__ gcnt, const int64_t* __restrict__ goff,
+                      const int64_t* __restrict__ woff, const int64_t* __restrict__ voff,
+                      const int32_t* __restrict__ nloc, const double* __restrict__ W, const double* __restrict__ b,
+                      double* __restrict__ t, int64_t total_cols) {
+  const int64_t col = blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  if (col >= total_cols) return;
+  int lo = 0, hi = nsub - 1;
+  while (lo < hi) {
+    int mid = (lo + hi + 1) >> 1;
+    if (goff[mid] <= col) lo = mid; else hi = mid - 1;
+  }
+  const int64_t k = col - goff[lo];
+  const int n = nloc[lo];
+  const int64_t ld = voff[lo + 1] - voff[lo];
+  const double* w = W + woff[lo] + k * ld;
+  const double* bb = b + voff[lo];
+  double acc = 0.0;
+  for (int r = lane; r < n; r += 64) acc += w[r] * bb[r];
+  for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o, 64);
+  if (lane == 0) t[col] = acc;
+}
+
+// GenEO columns, forward: b_j = W_j c_j (batch vector; pads get 0)
+__global__ void k_w_n(int64_t len, int nsub, const int64_t* __restrict__ voff, const int32_t* __restrict__ gcnt,
+                      const int64_t* __restrict__ goff, const int64_t* __restrict__ woff,
+                      const double* __restrict__ W, const double* __restrict__ c, double* __restrict__ b) {
+  int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (k >= len) return;
+  int lo = 0, hi = nsub - 1;
+  while (lo < hi) {
+    int mid = (lo + hi + 1) >> 1;
+    if (voff[mid] <= k) lo = mid; else hi = mid - 1;
+  }
+  const int64_t r = k - voff[lo];
+  const int64_t ld = voff[lo + 1] - voff[lo];
+  const double* w = W + woff[lo] + r;
+  const double* cc = c + goff[lo];
+  double acc = 0.0;
+  for (int j = 0; j < gcnt[lo]; ++j) acc += w[j * ld] * cc[j];
+  b[k] = acc;
+}
+
+__global__ void k_axpby(int64_t n, double a, const double* __restrict__ x, double bcoef, const double* __restrict__ y,
+                        double* __restrict__ out) {
+  int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i < n) out[i] = a * x[i] + bcoef * (y ? y[i] : 0.0);
+}
+
+__global__ void k_copy_diag(const MatDesc* __restrict__ desc, const double* __restrict__ A, double* __restrict__ od) {
+  const MatDesc d = desc[blockIdx.y];
+  int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i < d.ld) od[d.diag_off + i] = A[d.off + i * d.ld + i];
+}
+
+// E (SNK x SNK) = Z^T A Z, one thread per coarse column c1 (writes column c1 only)
+__global__ void k_coarse_snk(int64_t nsnk, const int32_t* __restrict__ zc_ptr, const int32_t* __restrict__ zc_row,
+                             const double* __restrict__ zc_val, const int32_t* __restrict__ rp,
+                             const int32_t* __restrict__ ci, const double* __restrict__ av,
+                             const int32_t* __restrict__ zr_ptr, const int32_t* __restrict__ zr_col,
+                             const double* __restrict__ zr_val, double* __restrict__ E, int64_t ld) {
+  int64_t c1 = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (c1 >= nsnk) return;
+  double* col = E + c1 * ld;
+  for (int32_t k1 = zc_ptr[c1]; k1 < zc_ptr[c1 + 1]; ++k1) {
+    const int32_t e = zc_row[k1];
+    const double z1 = zc_val[k1];
+    for (int32_t s = rp[e]; s < rp[e + 1]; ++s) {
+      const int32_t f = ci[s];
+      const double a = av[s] * z1;
+      for (int32_t k2 = zr_ptr[f]; k2 < zr_ptr[f + 1]; ++k2) col[zr_col[k2]] += a * zr_val[k2];
+    }
+  }
+}
+
+// E[:, gen] = Z^T Y and E[gen, snk] by symmetry, where Y = A Z_gen (global, n x ngen, column-major).
+// One thread per (row c1 over all n0 columns, gen column g): rows c1 < nsnk use the sparse
+// SNK column, rows c1 >= nsnk the dense GenEO column Zg (global, n x ngen).
+__global__ void k_coarse_gen(int64_t n0, int64_t nsnk, int64_t ngen, int64_t n, const int32_t* __restrict__ zc_ptr,
+                             const int32_t* __restrict__ zc_row, const double* __restrict__ zc_val,
+                             const double* __restrict__ Zg, const double* __restrict__ Y, double* __restrict__ E,
+                             int64_t ld) {
+  int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (idx >= n0 * ngen) return;
+  const int64_t c1 = idx % n0, g = idx / n0;
+  const double* y = Y + g * n;
+  double acc = 0.0;
+  if (c1 < nsnk) {
+    for (int32_t k = zc_ptr[c1]; k < zc_ptr[c1 + 1]; ++k) acc += zc_val[k] * y[zc_row[k]];
+  } else {
+    const double* z = Zg + (c1 - nsnk) * n;
+    for (int64_t e = 0; e < n; ++e) acc += z[e] * y[e];
+  }
+  const int64_t cg = nsnk + g;
+  E[cg * ld + c1] = acc;   // column cg
+  E[c1 * ld + cg] = acc;   // row cg (symmetric)
+}
+
+// ---------------------------------------------------------- dot products
+constexpr int kDotBlocks = 512;
+
+__global__ __launch_bounds__(256) void k_dot_partial(const double* __restrict__ x, const double* __restrict__ y,
+                                                     int64_t n, double* __restrict__ part) {
+  __shared__ double s[256];
+  double acc = 0.0;
+  for (int64_t i = blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)kDotBlocks * 256) acc += x[i] * y[i];
+  s[threadIdx.x] = acc;
+  __syncthreads();
+  for (int o = 128; o > 0; o >>= 1) {
+    if (threadIdx.x < o) s[threadIdx.x] += s[threadIdx.x + o];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) part[blockIdx.x] = s[0];
+}
+
+__global__ __launch_bounds__(kDotBlocks) void k_dot_final(const double* __restrict__ part, double* __restrict__ out) {
+  __shared__ double s[kDotBlocks];
+  s[threadIdx.x] = part[threadIdx.x];
+  __syncthreads();
+  for (int o = kDotBlocks / 2; o > 0; o >>= 1) {
+    if (threadIdx.x < o) s[threadIdx.x] += s[threadIdx.x + o];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) out[0] = s[0];
+}
+
+void dot(const double* x, const double* y, int64_t n, double* partial, double* out, hipStream_t st) {
+  k_dot_partial<<<kDotBlocks, 256, 0, st>>>(x, y, n, partial);
+  k_dot_final<<<1, kDotBlocks, 0, st>>>(partial, out);
+}
+
+static inline unsigned nblocks(int64_t n, int b = 256) { return (unsigned)((n + b - 1) / b); }
+
+// ---------------------------------------------------------------- setup
+
+void check_device_error(geneo_ctx* ctx) {
+  HIP_CHECK(hipMemcpyAsync(ctx->h_err, ctx->d_err, sizeof(DevErr), hipMemcpyDeviceToHost, ctx->stream));
+  HIP_CHECK(hipStreamSynchronize(ctx->stream));
+  DevErr e = *ctx->h_err;
+  if (e.code != 0) {
+    HIP_CHECK(hipMemsetAsync(ctx->d_err, 0, sizeof(DevErr), ctx->stream));
+    HIP_CHECK(hipStreamSynchronize(ctx->stream));
+    if (e.code == GENEO_ENOTSPD)
+      throw Error(GENEO_ENOTSPD, "Cholesky pivot not positive: matrix " + std::to_string(e.mat) + ", column " +
+                                     std::to_string(e.idx));
+    if (e.code == GENEO_ESYNC) throw Error(GENEO_ESYNC, "device-side wait expired in a triangular solve");
+    throw Error(e.code, "device error " + std::to_string(e.code));
+  }
+}
+
+static float elapsed(geneo_ctx* ctx, int a, int b) {
+  HIP_CHECK(hipEventSynchronize(ctx->ev[b]));
+  float ms = 0;
+  HIP_CHECK(hipEventElapsedTime(&ms, ctx->ev[a], ctx->ev[b]));
+  return ms;
+}
+
+void setup_precond(geneo_ctx* ctx, geneo_precond* pc) {
+  hipStream_t st = ctx->stream;
+  const geneo_system* s = pc->sys;
+  const geneo_decomp* dec = pc->dec;
+  const int32_t N = dec->N;
+  const int64_t n = s->n;
+  pc->N = N;
+  pc->precision = pc->opts.local_precision;
+  if (pc->precision != GENEO_FP64 && pc->precision != GENEO_FP32_REFINE1)
+    throw Error(GENEO_EINVAL, "unknown local precision");
+
+  // ---- batch layout of the local matrices
+  std::vector<MatDesc> descs(N);
+  int64_t off = 0, inv_off = 0, voff = 0;
+  int32_t flag_off = 0;
+  pc->voff.assign(N + 1, 0);
+  double flops = 0;
+  for (int32_t i = 0; i < N; ++i) {
+    const int64_t ni = dec->dofs_ptr[i + 1] - dec->dofs_ptr[i];
+    const int64_t np = round_up(std::max<int64_t>(ni, 1), NB);
+    descs[i] = MatDesc{off, inv_off, -1, voff, (int32_t)np, (int32_t)(np / NB), flag_off, (int32_t)ni};
+    off += np * np;
+    inv_off += np * NB;
+    pc->voff[i] = voff;
+    voff += np;
+    flag_off += (int32_t)(np / NB);
+    flops += (double)ni * ni * ni / 3.0;
+  }
+  pc->voff[N] = voff;
+  pc->batch_len = voff;
+  pc->info.local_factor_flops = flops;
+  pc->local.build(descs, st);
+  pc->d_flags_local.alloc(flag_off);
+  HIP_CHECK(hipMemsetAsync(pc->d_flags_local.p, 0, sizeof(unsigned) * flag_off, st));
+
+  // batch maps
+  std::vector<int32_t> bmap(voff, -1);
+  std::vector<double> bpou(voff, 0.0);
+  std::vector<int32_t> cnt(n + 1, 0);
+  for (int32_t i = 0; i < N; ++i)
+    for (int64_t r = dec->dofs_ptr[i]; r < dec->dofs_ptr[i + 1]; ++r) {
+      int64_t k = pc->voff[i] + (r - dec->dofs_ptr[i]);
+      bmap[k] = dec->dofs[r];
+      bpou[k] = dec->pou[r];
+      cnt[dec->dofs[r] + 1]++;
+    }
+  for (int64_t e = 0; e < n; ++e) cnt[e + 1] += cnt[e];
+  std::vector<int32_t> inv(cnt[n]);
+  {
+    std::vector<int32_t> f(cnt.begin(), cnt.end() - 1);
+    for (int32_t i = 0; i < N; ++i)
+      for (int64_t r = dec->dofs_ptr[i]; r < dec->dofs_ptr[i + 1]; ++r)
+        inv[f[dec->dofs[r]]++] = (int32_t)(pc->voff[i] + (r - dec->dofs_ptr[i]));
+  }
+  pc->d_bmap.upload(bmap, st);
+  pc->d_bpou.upload(bpou, st);
+  pc->d_inv_ptr.upload(cnt, st);
+  pc->d_inv_idx.upload(inv, st);
+
+  // local CSR triplets: rows/cols local, slot = global CSR position
+  std::vector<int32_t> lrow, lcol, lslot;
+  std::vector<int64_t> lnnz_off(N + 1, 0);
+  std::vector<int32_t> g2l(n, -1);
+  for (int32_t i = 0; i < N; ++i) {
+    const int64_t b = dec->dofs_ptr[i], e = dec->dofs_ptr[i + 1];
+    for (int64_t r = b; r < e; ++r) g2l[dec->dofs[r]] = (int32_t)(r - b);
+    for (int64_t r = b; r < e; ++r) {
+      const int32_t ge = dec->dofs[r];
+      for (int32_t sl = s->rowptr[ge]; sl < s->rowptr[ge + 1]; ++sl) {
+        const int32_t c = g2l[s->colind[sl]];
+        if (c < 0) continue;
+        lrow.push_back((int32_t)(r - b));
+        lcol.push_back(c);
+        lslot.push_back(sl);
+      }
+    }
+    for (int64_t r = b; r < e; ++r) g2l[dec->dofs[r]] = -1;
+    lnnz_off[i + 1] = (int64_t)lrow.size();
+  }
+  pc->lnnz_off = lnnz_off;
+  pc->d_lrow.upload(lrow, st);
+  pc->d_lcol.upload(lcol, st);
+  pc->d_lslot.upload(lslot, st);
+  pc->d_lnnz_off.upload(lnnz_off, st);
+
+  // ---- extraction + factorisation
+  const bool fp32 = pc->precision == GENEO_FP32_REFINE1;
+  std::vector<int64_t> mat_start(N);
+  for (int32_t i = 0; i < N; ++i) mat_start[i] = descs[i].off;
+  DevBuf<int64_t> d_mat_start;
+  d_mat_start.upload(mat_start, st);
+  if (fp32) {
+    pc->fL.alloc(off);
+    pc->fLinv.alloc(inv_off);
+  } else {
+    pc->dL.alloc(off);
+    pc->dLinv.alloc(inv_off);
+  }
+  HIP_CHECK(hipEventRecord(ctx->ev[0], st));
+  k_fill_identity_pad<<<nblocks(off), 256, 0, st>>>(pc->local.d_desc.p, N, fp32 ? nullptr : pc->dL.p,
+                                                    fp32 ? pc->fL.p : nullptr, off, d_mat_start.p);
+  if (!lrow.empty())
+    k_dense_scatter<<<nblocks((int64_t)lrow.size()), 256, 0, st>>>((int64_t)lrow.size(), pc->d_lrow.p, pc->d_lcol.p,
+                                                                   pc->d_lslot.p, pc->d_lnnz_off.p, N,
+                                                                   pc->local.d_desc.p, s->d_val.p,
+                                                                   fp32 ? nullptr : pc->dL.p, fp32 ? pc->fL.p : nullptr);
+  HIP_CHECK(hipGetLastError());
+  HIP_CHECK(hipEventRecord(ctx->ev[1], st));
+  if (fp32)
+    factor(pc->local, pc->fL.p, pc->fLinv.p, nullptr, 0.0, nullptr, ctx->d_err, st);
+  else
+    factor(pc->local, pc->dL.p, pc->dLinv.p, nullptr, 0.0, nullptr, ctx->d_err, st);
+  HIP_CHECK(hipEventRecord(ctx->ev[2], st));
+  pc->info.t_extract_ms = elapsed(ctx, 0, 1);
+  pc->info.t_factor_ms = elapsed(ctx, 1, 2);
+  check_device_error(ctx);
+
+  // work vectors
+  pc->w_b1.alloc(voff);
+  pc->w_b2.alloc(voff);
+  pc->w_n1.alloc(n);
+  pc->w_n2.alloc(n);
+  pc->w_n3.alloc(n);
+  pc->w_n4.alloc(n);
+
+  // ---- GenEO eigenproblems
+  pc->gen_cnt.assign(N, 0);
+  pc->gen_off.assign(N + 1, 0);
+  pc->eigs.assign(N, {});
+  pc->eig_sel.assign(N, 0);
+  if (pc->opts.coarse == GENEO_COARSE_SNK_GENEO) {
+    HIP_CHECK(hipEventRecord(ctx->ev[0], st));
+    solve_local_gevps(ctx, pc);
+    HIP_CHECK(hipEventRecord(ctx->ev[1], st));
+    pc->info.t_gevp_ms = elapsed(ctx, 0, 1);
+  }
+  if (pc->opts.coarse == GENEO_COARSE_NONE) {
+    pc->n0 = 0;
+    return;
+  }
+
+  // ---- coarse space: SNK columns R_i^T D_i G_i (one per kept local free node)
+  std::vector<int32_t> zc_ptr(1, 0), zc_row;
+  std::vector<double> zc_val;
+  {
+    std::vector<int32_t> gl(s->n_free_nodes, -1);
+    for (int32_t i = 0; i < N; ++i) {
+      const int64_t gb = dec->gn_ptr[i], ge = dec->gn_ptr[i + 1];
+      const int32_t base = (int32_t)(zc_ptr.size() - 1);
+      for (int64_t k = gb; k < ge; ++k) gl[dec->gnodes[k]] = base + (int32_t)(k - gb);
+      const int64_t nk = ge - gb;
+      std::vector<std::vector<std::pair<int32_t, double>>> cols(nk);
+      for (int64_t r = dec->dofs_ptr[i]; r < dec->dofs_ptr[i + 1]; ++r) {
+        const int32_t fe = dec->dofs[r];
+        const int32_t e = s->free_edges[fe];
+        for (int q = 0; q < 2; ++q) {
+          const int32_t fnode = s->node_to_free[s->edges[2 * (int64_t)e + q]];
+          if (fnode < 0) continue;
+          const int32_t c = gl[fnode];
+          if (c < 0) continue;
+          const double g = q == 0 ? -1.0 : 1.0;
+          cols[c - base].push_back({fe, dec->pou[r] * g});
+        }
+      }
+      for (int64_t k = 0; k < nk; ++k) {
+        for (auto& pr : cols[k]) {
+          zc_row.push_back(pr.first);
+          zc_val.push_back(pr.second);
+        }
+        zc_ptr.push_back((int32_t)zc_row.size());
+      }
+      for (int64_t k = gb; k < ge; ++k) gl[dec->gnodes[k]] = -1;
+    }
+  }
+  pc->n_snk = (int32_t)(zc_ptr.size() - 1);
+  pc->n_gen = 0;
+  for (int32_t i = 0; i < N; ++i) {
+    pc->gen_off[i] = pc->n_gen;
+    pc->n_gen += pc->gen_cnt[i];
+  }
+  pc->gen_off[N] = pc->n_gen;
+  pc->n0 = pc->n_snk + pc->n_gen;
+  // SNK rows (transpose of the columns)
+  std::vector<int32_t> zr_ptr(n + 1, 0), zr_col(zc_row.size());
+  std::vector<double> zr_val(zc_row.size());
+  for (auto e : zc_row) zr_ptr[e + 1]++;
+  for (int64_t e = 0; e < n; ++e) zr_ptr[e + 1] += zr_ptr[e];
+  {
+    std::vector<int32_t> f(zr_ptr.begin(), zr_ptr.end() - 1);
+    for (int32_t c = 0; c < pc->n_snk; ++c)
+      for (int32_t k = zc_ptr[c]; k < zc_ptr[c + 1]; ++k) {
+        zr_col[f[zc_row[k]]] = c;
+        zr_val[f[zc_row[k]]++] = zc_val[k];
+      }
+  }
+  pc->d_zc_ptr.upload(zc_ptr, st);
+  pc->d_zc_row.upload(zc_row, st);
+  pc->d_zc_val.upload(zc_val, st);
+  pc->d_zr_ptr.upload(zr_ptr, st);
+  pc->d_zr_col.upload(zr_col, st);
+  pc->d_zr_val.upload(zr_val, st);
+
+  // ---- E = Z^T A Z (dense FP64), then Cholesky with dependent columns left out
+  const int64_t n0 = pc->n0;
+  const int64_t n0p = round_up(std::max<int64_t>(n0, 1), NB);
+  std::vector<MatDesc> cd(1, MatDesc{0, 0, 0, 0, (int32_t)n0p, (int32_t)(n0p / NB), 0, (int32_t)n0});
+  pc->coarse.build(cd, st);
+  pc->dE.alloc(n0p * n0p);
+  pc->dEinv.alloc(n0p * NB);
+  pc->d_odiag.alloc(n0p);
+  pc->d_pivrel.alloc(n0p);
+  pc->d_flags_coarse.alloc(n0p / NB);
+  HIP_CHECK(hipMemsetAsync(pc->d_flags_coarse.p, 0, sizeof(unsigned) * (n0p / NB), st));
+  pc->w_c1.alloc(n0p);
+  pc->w_c2.alloc(n0p);
+  HIP_CHECK(hipMemsetAsync(pc->w_c1.p, 0, sizeof(double) * n0p, st));
+  HIP_CHECK(hipMemsetAsync(pc->w_c2.p, 0, sizeof(double) * n0p, st));
+  std::vector<int64_t> zero1(1, 0);
+  DevBuf<int64_t> d_zero1;
+  d_zero1.upload(zero1, st);
+  HIP_CHECK(hipEventRecord(ctx->ev[0], st));
+  k_fill_identity_pad<<<nblocks(n0p * n0p), 256, 0, st>>>(pc->coarse.d_desc.p, 1, pc->dE.p, nullptr, n0p * n0p,
+                                                          d_zero1.p);
+  if (pc->n_snk)
+    k_coarse_snk<<<nblocks(pc->n_snk), 256, 0, st>>>(pc->n_snk, pc->d_zc_ptr.p, pc->d_zc_row.p, pc->d_zc_val.p,
+                                                      s->d_rowptr.p, s->d_colind.p, s->d_val.p, pc->d_zr_ptr.p,
+                                                      pc->d_zr_col.p, pc->d_zr_val.p, pc->dE.p, n0p);
+  if (pc->n_gen) {
+    // global dense GenEO columns and Y = A Z_gen
+    DevBuf<double> Zg, Y;
+    Zg.alloc((size_t)n * pc->n_gen);
+    Y.alloc((size_t)n * pc->n_gen);
+    HIP_CHECK(hipMemsetAsync(pc->w_c1.p, 0, sizeof(double) * n0p, st));
+    for (int32_t g = 0; g < pc->n_gen; ++g) {
+      // unit coarse vector -> W c -> scatter to global
+      HIP_CHECK(hipMemsetAsync(pc->w_c1.p, 0, sizeof(double) * n0p, st));
+      const double one = 1.0;
+      HIP_CHECK(hipMemcpyAsync(pc->w_c1.p + g, &one, sizeof(double), hipMemcpyHostToDevice, st));
+      k_w_n<<<nblocks(voff), 256, 0, st>>>(voff, N, pc->d_voff.p, pc->d_gen_cnt.p, pc->d_gen_off.p, pc->d_w_off.p,
+                                            pc->d_W.p, pc->w_c1.p, pc->w_b1.p);
+      k_scatter_add<<<nblocks(n), 256, 0, st>>>(n, pc->d_inv_ptr.p, pc->d_inv_idx.p, pc->w_b1.p, nullptr, 1.0,
+                                                Zg.p + (int64_t)g * n);
+      launch_spmv(s, Zg.p + (int64_t)g * n, Y.p + (int64_t)g * n, st);
+      HIP_CHECK(hipStreamSynchronize(st));
+    }
+    k_coarse_gen<<<nblocks(n0 * pc->n_gen), 256, 0, st>>>(n0, pc->n_snk, pc->n_gen, n, pc->d_zc_ptr.p,
+                                                          pc->d_zc_row.p, pc->d_zc_val.p, Zg.p, Y.p, pc->dE.p, n0p);
+    HIP_CHECK(hipMemsetAsync(pc->w_c1.p, 0, sizeof(double) * n0p, st));
+    HIP_CHECK(hipStreamSynchronize(st));
+  }
+  HIP_CHECK(hipGetLastError());
+  {
+    dim3 g(nblocks(n0p), 1);
+    k_copy_diag<<<g, 256, 0, st>>>(pc->coarse.d_desc.p, pc->dE.p, pc->d_odiag.p);
+  }
+  // the coarse plan's diag_off is 0
+  HIP_CHECK(hipEventRecord(ctx->ev[1], st));
+  factor(pc->coarse, pc->dE.p, pc->dEinv.p, pc->d_odiag.p, pc->opts.coarse_drop_tol, pc->d_pivrel.p, ctx->d_err, st);
+  HIP_CHECK(hipEventRecord(ctx->ev[2], st));
+  pc->info.t_coarse_build_ms = elapsed(ctx, 0, 1);
+  pc->info.t_coarse_factor_ms = elapsed(ctx, 1, 2);
+  check_device_error(ctx);
+  std::vector<double> piv(n0p);
+  HIP_CHECK(hipMemcpy(piv.data(), pc->d_pivrel.p, sizeof(double) * n0p, hipMemcpyDeviceToHost));
+  int32_t kept = 0;
+  double mink = 1e300, maxd = 0.0;
+  for (int64_t c = 0; c < n0; ++c) {
+    if (piv[c] > pc->opts.coarse_drop_tol) {
+      ++kept;
+      mink = std::min(mink, piv[c]);
+    } else {
+      maxd = std::max(maxd, piv[c]);
+    }
+  }
+  pc->info.n0 = (int32_t)n0;
+  pc->info.n0_rank = kept;
+  pc->info.n_snk = pc->n_snk;
+  pc->info.n_geneo = pc->n_gen;
+  pc->info.min_kept_pivot = kept ? mink : 0.0;
+  pc->info.max_dropped_pivot = maxd;
+}
+
+// ---------------------------------------------------------------- apply
+
+static void coarse_solve(geneo_ctx* ctx, const geneo_precond* pc, double* c) {
+  solve(pc->coarse, pc->dE.p, pc->dEinv.p, c, ctx->d_sync, pc->d_flags_coarse.p, ctx->d_err, ctx->stream);
+}
+
+static void local_solve(geneo_ctx* ctx, const geneo_precond* pc, double* b) {
+  if (pc->precision == GENEO_FP32_REFINE1)
+    solve(pc->local, pc->fL.p, pc->fLinv.p, b, ctx->d_sync, pc->d_flags_local.p, ctx->d_err, ctx->stream);
+  else
+    solve(pc->local, pc->dL.p, pc->dLinv.p, b, ctx->d_sync, pc->d_flags_local.p, ctx->d_err, ctx->stream);
+}
+
+// t = Z^T g   (g: global vector; uses w_b2 for the GenEO part)
+static void z_transpose(const geneo_precond* pc, const double* g, double* t, hipStream_t st) {
+  const geneo_system* s = pc->sys;
+  if (pc->n_snk)
+    k_csc_t<<<nblocks(pc->n_snk), 256, 0, st>>>(pc->n_snk, pc->d_zc_ptr.p, pc->d_zc_row.p, pc->d_zc_val.p, g, t);
+  if (pc->n_gen) {
+    k_gather<<<nblocks(pc->batch_len), 256, 0, st>>>(pc->batch_len, pc->d_bmap.p, g, pc->w_b2.p);
+    k_w_t<<<(unsigned)((pc->n_gen + 3) / 4), 256, 0, st>>>(pc->N, pc->d_gen_cnt.p, pc->d_gen_off.p, pc->d_w_off.p,
+                                                           pc->d_voff.p, pc->d_n.p, pc->d_W.p, pc->w_b2.p,
+                                                           t + pc->n_snk, pc->n_gen);
+  }
+  (void)s;
+}
+
+// u = Z c (+ add)
+static void z_forward(const geneo_precond* pc, const double* c, const double* add, double* u, hipStream_t st) {
+  const int64_t n = pc->sys->n;
+  const double* base = add;
+  if (pc->n_gen) {
+    k_w_n<<<nblocks(pc->batch_len), 256, 0, st>>>(pc->batch_len, pc->N, pc->d_voff.p, pc->d_gen_cnt.p,
+                                                  pc->d_gen_off.p, pc->d_w_off.p, pc->d_W.p, c + pc->n_snk,
+                                                  pc->w_b2.p);
+    k_scatter_add<<<nblocks(n), 256, 0, st>>>(n, pc->d_inv_ptr.p, pc->d_inv_idx.p, pc->w_b2.p, add, 1.0, u);
+    base = u;
+  }
+  k_csr<<<nblocks(n), 256, 0, st>>>(n, pc->d_zr_ptr.p, pc->d_zr_col.p, pc->d_zr_val.p, c, base, u);
+}
+
+void apply_precond(geneo_ctx* ctx, const geneo_precond* pc, const double* r, double* z) {
+  hipStream_t st = ctx->stream;
+  const int64_t n = pc->sys->n;
+  double* y = pc->w_n1.p;
+  if (pc->n0 == 0) {
+    k_gather<<<nblocks(pc->batch_len), 256, 0, st>>>(pc->batch_len, pc->d_bmap.p, r, pc->w_b1.p);
+    local_solve(ctx, pc, pc->w_b1.p);
+    k_scatter_add<<<nblocks(n), 256, 0, st>>>(n, pc->d_inv_ptr.p, pc->d_inv_idx.p, pc->w_b1.p, nullptr, 1.0, z);
+    return;
+  }
+  double* c = pc->w_c1.p;
+  double* c2 = pc->w_c2.p;
+  // c = E^-1 Z^T r
+  z_transpose(pc, r, c, st);
+  coarse_solve(ctx, pc, c);
+  // r1 = r - A Z c
+  z_forward(pc, c, nullptr, pc->w_n2.p, st);
+  launch_spmv(pc->sys, pc->w_n2.p, pc->w_n3.p, st);
+  k_axpby<<<nblocks(n), 256, 0, st>>>(n, 1.0, r, -1.0, pc->w_n3.p, pc->w_n2.p);
+  // y = sum_i R_i^T A_i^-1 R_i r1
+  k_gather<<<nblocks(pc->batch_len), 256, 0, st>>>(pc->batch_len, pc->d_bmap.p, pc->w_n2.p, pc->w_b1.p);
+  local_solve(ctx, pc, pc->w_b1.p);
+  k_scatter_add<<<nblocks(n), 256, 0, st>>>(n, pc->d_inv_ptr.p, pc->d_inv_idx.p, pc->w_b1.p, nullptr, 1.0, y);
+  // c2 = E^-1 Z^T A y
+  launch_spmv(pc->sys, y, pc->w_n3.p, st);
+  z_transpose(pc, pc->w_n3.p, c2, st);
+  coarse_solve(ctx, pc, c2);
+  // z = y + Z (c - c2)
+  k_axpby<<<nblocks(pc->n0), 256, 0, st>>>(pc->n0, 1.0, c, -1.0, c2, c2);
+  z_forward(pc, c2, y, z, st);
+}
+
+// ---------------------------------------------------------------- PCG
+// device scalars: 0 rz, 1 pq, 2 rr, 3 rz_new, 4 bb
+__global__ void k_pcg_update(int64_t n, double* __restrict__ x, double* __restrict__ r, const double* __restrict__ p,
+                             const double* __restrict__ q, const double* __restrict__ S) {
+  int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const double alpha = S[0] / S[1];
+  x[i] += alpha * p[i];
+  r[i] -= alpha * q[i];
+}
+__global__ void k_pcg_dir(int64_t n, double* __restrict__ p, const double* __restrict__ z, double* __restrict__ S,
+                          int first) {
+  int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const double beta = first ? 0.0 : S[3] / S[0];
+  p[i] = z[i] + beta * p[i];
+}
+__global__ void k_pcg_shift(double* S) { S[0] = S[3]; }
+
+void pcg(geneo_ctx* ctx, const geneo_system* sys, const geneo_precond* pc, const double* b, double* x,
+         const geneo_solve_opts* o, geneo_solve_info* info) {
+  hipStream_t st = ctx->stream;
+  const int64_t n = sys->n;
+  DevBuf<double> r, z, p, q, part, S;
+  r.alloc(n);
+  z.alloc(n);
+  p.alloc(n);
+  q.alloc(n);
+  part.alloc(kDotBlocks);
+  S.alloc(8);
+  double* h = nullptr;
+  HIP_CHECK(hipHostMalloc((void**)&h, 8 * sizeof(double), hipHostMallocDefault));
+  struct HostFree {
+    double* p;
+    ~HostFree() { if (p) (void)hipHostFree(p); }
+  } hf{h};
+  HIP_CHECK(hipEventRecord(ctx->ev[0], st));
+  HIP_CHECK(hipMemsetAsync(x, 0, sizeof(double) * n, st));
+  HIP_CHECK(hipMemcpyAsync(r.p, b, sizeof(double) * n, hipMemcpyDeviceToDevice, st));
+  dot(b, b, n, part.p, S.p + 4, st);
+  HIP_CHECK(hipMemcpyAsync(h + 4, S.p + 4, sizeof(double), hipMemcpyDeviceToHost, st));
+  HIP_CHECK(hipStreamSynchronize(st));
+  const double bnorm = std::sqrt(h[4]);
+  const double tol = o->rtol * bnorm;
+  int it = 0;
+  double rel = 1.0;
+  bool conv = bnorm == 0.0;
+  if (!conv) {
+    auto precond = [&](const double* in, double* out) {
+      if (pc)
+        apply_precond(ctx, pc, in, out);
+      else
+        HIP_CHECK(hipMemcpyAsync(out, in, sizeof(double) * n, hipMemcpyDeviceToDevice, st));
+    };
+    precond(r.p, z.p);
+    dot(r.p, z.p, n, part.p, S.p + 3, st);
+    k_pcg_dir<<<nblocks(n), 256, 0, st>>>(n, p.p, z.p, S.p, 1);
+    k_pcg_shift<<<1, 1, 0, st>>>(S.p);
+    for (it = 1; it <= o->maxit; ++it) {
+      launch_spmv(sys, p.p, q.p, st);
+      dot(p.p, q.p, n, part.p, S.p + 1, st);
+      k_pcg_update<<<nblocks(n), 256, 0, st>>>(n, x, r.p, p.p, q.p, S.p);
+      dot(r.p, r.p, n, part.p, S.p + 2, st);
+      HIP_CHECK(hipMemcpyAsync(h + 2, S.p + 2, sizeof(double), hipMemcpyDeviceToHost, st));
+      HIP_CHECK(hipStreamSynchronize(st));
+      rel = std::sqrt(h[2]) / bnorm;
+      if (std::sqrt(h[2]) <= tol) {
+        conv = true;
+        break;
+      }
+      precond(r.p, z.p);
+      dot(r.p, z.p, n, part.p, S.p + 3, st);
+      k_pcg_dir<<<nblocks(n), 256, 0, st>>>(n, p.p, z.p, S.p, 0);
+      k_pcg_shift<<<1, 1, 0, st>>>(S.p);
+    }
+  }
+  HIP_CHECK(hipEventRecord(ctx->ev[1], st));
+  info->solve_ms = elapsed(ctx, 0, 1);
+  info->iterations = conv ? (it > o->maxit ? o->maxit : it) : o->maxit;
+  if (bnorm == 0.0) info->iterations = 0;
+  info->rel_residual = bnorm == 0.0 ? 0.0 : rel;
+  check_device_error(ctx);
+  if (!conv) throw Error(GENEO_ENOCONV, "PCG did not reach rtol in maxit iterations");
+}
+
+}  // namespace geneo

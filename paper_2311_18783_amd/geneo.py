@@ -1,0 +1,297 @@
+"""Thin ctypes binding of libgeneo (include/geneo.h).
+
+Argument marshalling only: every step of assembly, partitioning, setup,
+apply and solve runs inside the library.  Device vectors are torch float64
+tensors on the context's device, passed by data_ptr(); the library orders
+its work on the given HIP stream (torch's current stream by default).
+Importing this module fails loudly if libgeneo.so has not been built.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import re
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libgeneo.so")
+HEADER = os.path.join(os.path.dirname(_HERE), "include", "geneo.h")
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError(f"{LIB_PATH} is missing: build it with `python -m paper_2311_18783_amd.build`")
+lib = C.CDLL(LIB_PATH)
+
+STATUS = {0: "OK", -1: "EINVAL", -2: "ENOTSPD", -3: "ENOCONV", -4: "EOOM", -5: "EHIP", -6: "EUNSUPPORTED",
+          -7: "ESYNC"}
+FP64, FP32_REFINE1 = 0, 1
+COARSE_SNK_GENEO, COARSE_SNK, COARSE_NONE = 0, 1, 2
+PART_BOX, PART_RCB, PART_EXPLICIT = 0, 1, 2
+
+
+class GeneoError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"{STATUS.get(code, code)}: {msg}")
+        self.code = code
+        self.status = STATUS.get(code, str(code))
+
+
+class Mesh(C.Structure):
+    _fields_ = [("n_nodes", C.c_int64), ("xyz", C.POINTER(C.c_double)), ("n_tets", C.c_int64),
+                ("tets", C.POINTER(C.c_int32)), ("cell_of_tet", C.POINTER(C.c_int32)),
+                ("n_bfaces", C.c_int64), ("bfaces", C.POINTER(C.c_int32)),
+                ("bface_dirichlet", C.POINTER(C.c_int8))]
+
+
+class SystemInfo(C.Structure):
+    _fields_ = [("n", C.c_int64), ("nnz", C.c_int64), ("n_edges", C.c_int64), ("n_free_nodes", C.c_int64),
+                ("n_cells", C.c_int64), ("assemble_ms", C.c_double)]
+
+
+class PartitionOpts(C.Structure):
+    _fields_ = [("kind", C.c_int32), ("box", C.c_int32 * 3), ("nparts", C.c_int32),
+                ("rcb_jitter", C.POINTER(C.c_double)), ("part_of_cell", C.POINTER(C.c_int32)),
+                ("overlap", C.c_int32)]
+
+
+class DecompInfo(C.Structure):
+    _fields_ = [("n_sub", C.c_int32), ("n_min", C.c_int32), ("n_max", C.c_int32), ("sum_n", C.c_int64),
+                ("sum_p", C.c_int64), ("n_floating", C.c_int32), ("sum_n3_over_3", C.c_double)]
+
+
+class SetupOpts(C.Structure):
+    _fields_ = [("tau", C.c_double), ("nev_max", C.c_int32), ("coarse", C.c_int32),
+                ("local_precision", C.c_int32), ("lobpcg_tol", C.c_double), ("lobpcg_maxit", C.c_int32),
+                ("lobpcg_guard", C.c_int32), ("seed", C.c_uint64), ("coarse_drop_tol", C.c_double),
+                ("warm_start", C.POINTER(C.c_double))]
+
+
+class PrecondInfo(C.Structure):
+    _fields_ = [("n0", C.c_int32), ("n0_rank", C.c_int32), ("n_snk", C.c_int32), ("n_geneo", C.c_int32),
+                ("lobpcg_iters", C.c_int32), ("lobpcg_unconverged", C.c_int32), ("fp64_fallbacks", C.c_int32),
+                ("min_kept_pivot", C.c_double), ("max_dropped_pivot", C.c_double),
+                ("t_extract_ms", C.c_double), ("t_factor_ms", C.c_double), ("t_gevp_ms", C.c_double),
+                ("t_coarse_build_ms", C.c_double), ("t_coarse_factor_ms", C.c_double),
+                ("local_factor_flops", C.c_double)]
+
+
+class SolveOpts(C.Structure):
+    _fields_ = [("rtol", C.c_double), ("maxit", C.c_int32)]
+
+
+class SolveInfo(C.Structure):
+    _fields_ = [("iterations", C.c_int32), ("rel_residual", C.c_double), ("solve_ms", C.c_double)]
+
+
+_vp = C.c_void_p
+_P = C.POINTER
+_sigs = {
+    "geneo_create": (C.c_int, [_P(_vp), C.c_int, _vp]),
+    "geneo_destroy": (None, [_vp]),
+    "geneo_last_error": (C.c_char_p, [_vp]),
+    "geneo_assemble": (C.c_int, [_vp, _P(Mesh), _P(C.c_double), _P(C.c_double), C.c_double, _P(_vp)]),
+    "geneo_system_info_get": (C.c_int, [_vp, _P(SystemInfo)]),
+    "geneo_system_export": (C.c_int, [_vp, _vp, _P(C.c_int32), _P(C.c_int32), _P(C.c_double), _P(C.c_int32)]),
+    "geneo_spmv": (C.c_int, [_vp, _vp, _vp, _vp]),
+    "geneo_partition": (C.c_int, [_vp, _vp, _P(PartitionOpts), _P(_vp)]),
+    "geneo_decomp_info_get": (C.c_int, [_vp, _P(DecompInfo)]),
+    "geneo_decomp_subdomain": (C.c_int, [_vp, C.c_int32, _P(C.c_int32), _P(C.c_int32), _P(C.c_double),
+                                         _P(C.c_int32), _P(C.c_int32)]),
+    "geneo_setup_opts_default": (None, [_P(SetupOpts)]),
+    "geneo_setup": (C.c_int, [_vp, _vp, _vp, _P(SetupOpts), _P(_vp)]),
+    "geneo_precond_info_get": (C.c_int, [_vp, _P(PrecondInfo)]),
+    "geneo_precond_eigs": (C.c_int, [_vp, C.c_int32, _P(C.c_double), C.c_int32, _P(C.c_int32), _P(C.c_int32)]),
+    "geneo_apply": (C.c_int, [_vp, _vp, _vp, _vp]),
+    "geneo_solve": (C.c_int, [_vp, _vp, _vp, _vp, _vp, _P(SolveOpts), _P(SolveInfo)]),
+    "geneo_potrf_batched": (C.c_int, [_vp, C.c_int32, _P(C.c_int32), _P(C.c_int64), _vp, C.c_int32,
+                                      _P(C.c_double)]),
+    "geneo_free_system": (None, [_vp]),
+    "geneo_free_decomp": (None, [_vp]),
+    "geneo_free_precond": (None, [_vp]),
+}
+for _name, (_res, _args) in _sigs.items():
+    _f = getattr(lib, _name)
+    _f.restype = _res
+    _f.argtypes = _args
+
+
+def header_symbols(path=HEADER):
+    """Function names declared in include/geneo.h."""
+    txt = open(path).read()
+    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+    return sorted(set(re.findall(r"\b(geneo_[a-z0-9_]+)\s*\(", txt)))
+
+
+def _ptr(a, ct):
+    return a.ctypes.data_as(C.POINTER(ct)) if a is not None else None
+
+
+def _dptr(t):
+    return C.c_void_p(t.data_ptr())
+
+
+class Context:
+    """A library context bound to one device and one HIP stream."""
+
+    def __init__(self, device=0, stream=None):
+        import torch
+        self.device = device
+        if stream is None:
+            stream = torch.cuda.current_stream(device).cuda_stream
+        self.h = C.c_void_p()
+        self._check(lib.geneo_create(C.byref(self.h), device, C.c_void_p(stream)))
+
+    def _check(self, rc):
+        if rc != 0:
+            msg = lib.geneo_last_error(self.h).decode() if self.h else ""
+            raise GeneoError(rc, msg)
+
+    def close(self):
+        if self.h:
+            lib.geneo_destroy(self.h)
+            self.h = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # -------------------------------------------------------------- assemble
+    def assemble(self, mesh, mu, eps, gamma, dirichlet):
+        xyz = np.ascontiguousarray(mesh["xyz"], dtype=np.float64)
+        tets = np.ascontiguousarray(mesh["tets"], dtype=np.int32)
+        cot = np.ascontiguousarray(mesh["hex_of_tet"], dtype=np.int32) if "hex_of_tet" in mesh else None
+        bf = np.ascontiguousarray(mesh["bfaces"], dtype=np.int32)
+        bd = np.ascontiguousarray(dirichlet, dtype=np.int8)
+        mu = np.ascontiguousarray(mu, dtype=np.float64)
+        eps = np.ascontiguousarray(eps, dtype=np.float64)
+        m = Mesh(xyz.shape[0], _ptr(xyz, C.c_double), tets.shape[0], _ptr(tets, C.c_int32),
+                 _ptr(cot, C.c_int32) if cot is not None else None, bf.shape[0], _ptr(bf, C.c_int32),
+                 _ptr(bd, C.c_int8))
+        h = C.c_void_p()
+        self._check(lib.geneo_assemble(self.h, C.byref(m), _ptr(mu, C.c_double), _ptr(eps, C.c_double),
+                                       float(gamma), C.byref(h)))
+        return System(self, h)
+
+    def partition(self, system, kind="box", box=(1, 1, 1), nparts=0, jitter=None, part_of_cell=None, overlap=1):
+        o = PartitionOpts()
+        o.kind = {"box": PART_BOX, "rcb": PART_RCB, "explicit": PART_EXPLICIT}[kind]
+        o.box = (C.c_int32 * 3)(*box)
+        o.nparts = int(nparts)
+        jit = np.ascontiguousarray(jitter, dtype=np.float64) if jitter is not None else None
+        poc = np.ascontiguousarray(part_of_cell, dtype=np.int32) if part_of_cell is not None else None
+        o.rcb_jitter = _ptr(jit, C.c_double) if jit is not None else None
+        o.part_of_cell = _ptr(poc, C.c_int32) if poc is not None else None
+        o.overlap = int(overlap)
+        h = C.c_void_p()
+        self._check(lib.geneo_partition(self.h, system.h, C.byref(o), C.byref(h)))
+        return Decomp(self, h)
+
+    def setup(self, system, decomp, **kw):
+        o = SetupOpts()
+        lib.geneo_setup_opts_default(C.byref(o))
+        ws = kw.pop("warm_start", None)
+        for k, v in kw.items():
+            setattr(o, k, v)
+        if ws is not None:
+            ws = np.ascontiguousarray(ws, dtype=np.float64)
+            o.warm_start = _ptr(ws, C.c_double)
+        h = C.c_void_p()
+        self._check(lib.geneo_setup(self.h, system.h, decomp.h, C.byref(o), C.byref(h)))
+        return Precond(self, h)
+
+    def apply(self, pc, r, z):
+        self._check(lib.geneo_apply(self.h, pc.h, _dptr(r), _dptr(z)))
+
+    def spmv(self, system, x, y):
+        self._check(lib.geneo_spmv(self.h, system.h, _dptr(x), _dptr(y)))
+
+    def solve(self, system, pc, b, x, rtol=1e-8, maxit=1000, allow_noconv=False):
+        o = SolveOpts(float(rtol), int(maxit))
+        info = SolveInfo()
+        rc = lib.geneo_solve(self.h, system.h, pc.h if pc is not None else None, _dptr(b), _dptr(x),
+                             C.byref(o), C.byref(info))
+        if rc == -3 and allow_noconv:
+            return info
+        self._check(rc)
+        return info
+
+    def potrf_batched(self, A, sizes, offsets, precision=FP64):
+        n = np.ascontiguousarray(sizes, dtype=np.int32)
+        off = np.ascontiguousarray(offsets, dtype=np.int64)
+        ms = C.c_double()
+        self._check(lib.geneo_potrf_batched(self.h, len(n), _ptr(n, C.c_int32), _ptr(off, C.c_int64),
+                                            _dptr(A), int(precision), C.byref(ms)))
+        return ms.value
+
+
+class _Handle:
+    _free = None
+
+    def __init__(self, ctx, h):
+        self.ctx = ctx
+        self.h = h
+
+    def __del__(self):
+        try:
+            if self.h and self._free is not None:
+                getattr(lib, self._free)(self.h)
+                self.h = None
+        except Exception:
+            pass
+
+
+class System(_Handle):
+    _free = "geneo_free_system"
+
+    def info(self):
+        i = SystemInfo()
+        self.ctx._check(lib.geneo_system_info_get(self.h, C.byref(i)))
+        return i
+
+    def export(self):
+        """Host copy of A (scipy CSR) and the global edge id of each free edge."""
+        import scipy.sparse as sp
+        i = self.info()
+        rp = np.empty(i.n + 1, np.int32)
+        ci = np.empty(i.nnz, np.int32)
+        v = np.empty(i.nnz, np.float64)
+        fe = np.empty(i.n, np.int32)
+        self.ctx._check(lib.geneo_system_export(self.ctx.h, self.h, _ptr(rp, C.c_int32), _ptr(ci, C.c_int32),
+                                                _ptr(v, C.c_double), _ptr(fe, C.c_int32)))
+        return sp.csr_matrix((v, ci, rp), shape=(i.n, i.n)), fe
+
+
+class Decomp(_Handle):
+    _free = "geneo_free_decomp"
+
+    def info(self):
+        i = DecompInfo()
+        self.ctx._check(lib.geneo_decomp_info_get(self.h, C.byref(i)))
+        return i
+
+    def subdomain(self, i):
+        ni, pi = C.c_int32(), C.c_int32()
+        self.ctx._check(lib.geneo_decomp_subdomain(self.h, i, C.byref(ni), None, None, C.byref(pi), None))
+        dofs = np.empty(ni.value, np.int32)
+        pou = np.empty(ni.value, np.float64)
+        gn = np.empty(pi.value, np.int32)
+        self.ctx._check(lib.geneo_decomp_subdomain(self.h, i, None, _ptr(dofs, C.c_int32), _ptr(pou, C.c_double),
+                                                   None, _ptr(gn, C.c_int32)))
+        return dofs, pou, gn
+
+
+class Precond(_Handle):
+    _free = "geneo_free_precond"
+
+    def info(self):
+        i = PrecondInfo()
+        self.ctx._check(lib.geneo_precond_info_get(self.h, C.byref(i)))
+        return i
+
+    def eigs(self, i, cap=64):
+        lam = np.empty(cap, np.float64)
+        cnt, sel = C.c_int32(), C.c_int32()
+        self.ctx._check(lib.geneo_precond_eigs(self.h, i, _ptr(lam, C.c_double), cap, C.byref(cnt), C.byref(sel)))
+        return lam[:cnt.value].copy(), sel.value
