@@ -144,7 +144,7 @@ typedef struct {
   int32_t nev_max;          /* at most this many eigenvectors per subdomain */
   int32_t coarse;           /* geneo_coarse_kind */
   int32_t local_precision;  /* geneo_precision of the local factors and solves */
-  double lobpcg_tol;        /* relative eigen-residual target */
+  double lobpcg_tol;        /* ||Atilde x - theta B x|| / (|theta| ||B x||) target (default 1e-8) */
   int32_t lobpcg_maxit;
   int32_t lobpcg_guard;     /* extra block vectors beyond nev_max */
   uint64_t seed;            /* random start blocks */

@@ -183,7 +183,7 @@ void geneo_setup_opts_default(geneo_setup_opts* o) {
   o->coarse = GENEO_COARSE_SNK_GENEO;
   o->local_precision = GENEO_FP64;
   o->lobpcg_tol = 1e-8;
-  o->lobpcg_maxit = 300;
+  o->lobpcg_maxit = 100;
   o->lobpcg_guard = 4;
   o->seed = 12345;
   o->coarse_drop_tol = 1e-8;
@@ -262,7 +262,7 @@ int geneo_potrf_batched(geneo_ctx* ctx, int32_t batch, const int32_t* n_host, co
       if (n_host[i] < 1 || off_host[i] < 0 || off_host[i] % 32) throw Error(GENEO_EINVAL, "bad matrix size/offset");
       int64_t np = round_up(n_host[i], NB);
       descs[i] = MatDesc{off_host[i], inv_off, -1, 0, (int32_t)np, (int32_t)(np / NB), flag_off, n_host[i]};
-      inv_off += np * NB;
+      inv_off += 2 * np * NB;
       flag_off += (int32_t)(np / NB);
     }
     FactorPlan P;

@@ -7,7 +7,7 @@ namespace geneo {
 
 struct MatDesc {
   int64_t off;       // element offset of the matrix (column-major, ld)
-  int64_t inv_off;   // element offset of its first 128x128 diagonal-block inverse
+  int64_t inv_off;   // element offset of its diagonal-block inverses: nblk blocks of inv(L_II), then nblk of inv(U_II)
   int64_t diag_off;  // offset into the original-diagonal array, or -1
   int64_t voff;      // offset of its segment in a batch vector
   int32_t ld;        // = n_pad, multiple of NB
@@ -22,6 +22,8 @@ struct FactorPlan {
   std::vector<int> cnt;              // matrices active at each panel step
   std::vector<int64_t> trsm_tiles, syrk_tiles, pre_off;
   int64_t n_items = 0;               // triangular-solve work items (blocks)
+  int64_t mirror_tiles = 0;          // strictly-lower 128x128 blocks
+  DevBuf<int64_t> d_mirror_prefix;
   DevBuf<MatDesc> d_desc;
   DevBuf<int32_t> d_order;
   DevBuf<int64_t> d_prefix;
@@ -33,10 +35,17 @@ void factor(const FactorPlan& P, double* A, double* Ainv, const double* odiag, d
             DevErr* err, hipStream_t st);
 void factor(const FactorPlan& P, float* A, float* Ainv, const double* odiag, double drop_tol, double* pivrel,
             DevErr* err, hipStream_t st);
+// Factor in place; afterwards the strictly upper blocks hold U = L^T.
 // x <- (L L^T)^-1 x on every matrix segment of the batch vector x.
 void solve(const FactorPlan& P, const double* A, const double* Ainv, double* x, unsigned* sync, unsigned* flags,
            DevErr* err, hipStream_t st);
 void solve(const FactorPlan& P, const float* A, const float* Ainv, double* x, unsigned* sync, unsigned* flags,
            DevErr* err, hipStream_t st);
+// X <- (L L^T)^-1 X for k <= 32 columns: the block of matrix m starts at
+// X + voff_m * ldk, column q at + q * ld_m.
+void solve_multi(const FactorPlan& P, const double* A, const double* Ainv, double* X, int ldk, int k,
+                 unsigned* sync, unsigned* flags, DevErr* err, hipStream_t st);
+void solve_multi(const FactorPlan& P, const float* A, const float* Ainv, double* X, int ldk, int k,
+                 unsigned* sync, unsigned* flags, DevErr* err, hipStream_t st);
 
 }  // namespace geneo

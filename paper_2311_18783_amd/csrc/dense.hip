@@ -120,9 +120,11 @@ __global__ __launch_bounds__(256) void k_potrf(const MatDesc* __restrict__ desc,
     __syncthreads();
   }
   T* inv = Ainv + d.inv_off + (int64_t)step * NB * NB;
+  T* uinv = Ainv + d.inv_off + ((int64_t)d.nblk + step) * NB * NB;   // inv(U_II) = inv(L_II)^T
   for (int idx = tid; idx < NB * NB; idx += 256) {
     int r = idx % NB, c = idx / NB;
     inv[(int64_t)c * NB + r] = (r >= c) ? a[c * LDA + r] : T(0);
+    uinv[(int64_t)c * NB + r] = (c >= r) ? a[r * LDA + c] : T(0);
   }
 }
 
@@ -283,6 +285,13 @@ void FactorPlan::build(const std::vector<MatDesc>& descs, hipStream_t st) {
   d_desc.upload(descs, st);
   d_order.upload(ord, st);
   d_prefix.upload(pre, st);
+  std::vector<int64_t> mp(nmat + 1, 0);
+  for (int k = 0; k < nmat; ++k) {
+    int64_t T = descs[ord[k]].nblk;
+    mp[k + 1] = mp[k] + T * (T - 1) / 2;
+  }
+  mirror_tiles = mp[nmat];
+  d_mirror_prefix.upload(mp, st);
   // triangular-solve work items: forward in increasing block order across
   // matrices, backward in decreasing order
   std::vector<int32_t> fwd, bwd;
@@ -322,16 +331,28 @@ static void factor_impl(const FactorPlan& P, T* A, T* Ainv, const double* odiag,
   HIP_CHECK(hipGetLastError());
 }
 
+template <typename T>
+static void mirror_impl(const FactorPlan& P, T* A, hipStream_t st);
+
 void factor(const FactorPlan& P, double* A, double* Ainv, const double* odiag, double drop_tol, double* pivrel,
             DevErr* err, hipStream_t st) {
   factor_impl<double>(P, A, Ainv, odiag, drop_tol, pivrel, err, st);
+  mirror_impl<double>(P, A, st);
 }
 void factor(const FactorPlan& P, float* A, float* Ainv, const double* odiag, double drop_tol, double* pivrel,
             DevErr* err, hipStream_t st) {
   factor_impl<float>(P, A, Ainv, odiag, drop_tol, pivrel, err, st);
+  mirror_impl<float>(P, A, st);
 }
 
 // ------------------------------------------------------- triangular solves
+// After factorisation the strictly lower blocks of L are mirrored into the
+// (otherwise unused) strictly upper blocks, so U = L^T is stored
+// column-major as well, and the diagonal-block inverses are kept both as
+// inv(L_II) and inv(U_II) = inv(L_II)^T (second half of the inverse
+// buffer).  A backward solve with U then reads memory exactly like a
+// forward solve with L: block (I, J) at column J*NB+c, row I*NB+r.
+//
 // Sync-free blocked solves over the whole batch.  Work item = (matrix, block
 // row); a workgroup takes the next item from a ticket counter, so every item
 // it waits on was taken earlier by a running workgroup and no wait can
@@ -340,6 +361,35 @@ void factor(const FactorPlan& P, float* A, float* Ainv, const double* odiag, dou
 // expiry the workgroup records GENEO_ESYNC and goes on, so the kernel always
 // drains.
 constexpr unsigned kSpinLimit = 1u << 24;
+
+// U block (J, I) = L block (I, J)^T for every I > J, through LDS 64x64 tiles.
+template <typename T>
+__global__ __launch_bounds__(256) void k_mirror(const MatDesc* __restrict__ desc, const int32_t* __restrict__ order,
+                                                const int64_t* __restrict__ prefix, int cnt, T* __restrict__ A) {
+  __shared__ T tile[64][65];
+  const int j = find_mat(prefix, cnt, blockIdx.x);
+  const MatDesc d = desc[order[j]];
+  const int64_t u = blockIdx.x - prefix[j];
+  int64_t ti = (int64_t)((sqrt(8.0 * (double)u + 1.0) + 1.0) * 0.5);
+  while (ti * (ti - 1) / 2 > u) --ti;
+  while ((ti + 1) * ti / 2 <= u) ++ti;
+  const int64_t tj = u - ti * (ti - 1) / 2;   // ti > tj
+  const int tid = threadIdx.x;
+  for (int sub = 0; sub < 4; ++sub) {
+    const int64_t r0 = ti * NB + 64 * (sub & 1), c0 = tj * NB + 64 * (sub >> 1);
+    for (int idx = tid; idx < 64 * 64; idx += 256) {
+      int r = idx & 63, c = idx >> 6;
+      tile[c][r] = A[d.off + (c0 + c) * d.ld + r0 + r];
+    }
+    __syncthreads();
+    // destination: row c0 + c, column r0 + r  (U = L^T)
+    for (int idx = tid; idx < 64 * 64; idx += 256) {
+      int c = idx & 63, r = idx >> 6;
+      A[d.off + (r0 + r) * d.ld + c0 + c] = tile[c][r];
+    }
+    __syncthreads();
+  }
+}
 
 __global__ void k_solve_begin(unsigned* sync) {
   sync[0] = 0;
@@ -362,16 +412,19 @@ __device__ inline void publish(unsigned* flag, unsigned epoch) {
   __hip_atomic_store(flag, epoch, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-__device__ inline double wave_sum(double v) {
-  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
-  return v;
+__device__ inline double load_coherent(const double* p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ inline void store_coherent(double* p, double v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-// x <- L^-1 x for every matrix (x: batch vector, segment of matrix m at voff[m]).
-template <typename T>
-__global__ __launch_bounds__(256) void k_trsv_fwd(const MatDesc* __restrict__ desc, const int32_t* __restrict__ items,
-                                                  const T* __restrict__ A, const T* __restrict__ Ainv,
-                                                  double* x, unsigned* sync, unsigned* flags, DevErr* err) {
+// One triangular solve, single right-hand side: x <- L^-1 x (UPPER = false)
+// or x <- U^-1 x (UPPER = true) on every matrix segment of the batch vector.
+template <typename T, bool UPPER>
+__global__ __launch_bounds__(256) void k_trsv(const MatDesc* __restrict__ desc, const int32_t* __restrict__ items,
+                                              const T* __restrict__ A, const T* __restrict__ Ainv, double* x,
+                                              unsigned* sync, unsigned* flags, DevErr* err) {
   __shared__ double xs[NB];
   __shared__ double red[256];
   __shared__ int s_t;
@@ -388,10 +441,11 @@ __global__ __launch_bounds__(256) void k_trsv_fwd(const MatDesc* __restrict__ de
   double* xv = x + d.voff;
   const int r = tid & (NB - 1), h = tid >> 7;
   double acc = 0.0;
-  for (int J = 0; J < I; ++J) {
+  const int J0 = UPPER ? I + 1 : 0, J1 = UPPER ? d.nblk : I;
+  for (int J = J0; J < J1; ++J) {
     if (tid == 0) wait_flag(flags + d.flag_off + J, epoch, err);
     __syncthreads();
-    if (tid < NB) xs[tid] = __hip_atomic_load(xv + (int64_t)J * NB + tid, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if (tid < NB) xs[tid] = load_coherent(xv + (int64_t)J * NB + tid);
     __syncthreads();
     const T* col = A + d.off + ((int64_t)J * NB + 64 * h) * d.ld + (int64_t)I * NB + r;
 #pragma unroll 8
@@ -402,28 +456,30 @@ __global__ __launch_bounds__(256) void k_trsv_fwd(const MatDesc* __restrict__ de
   __syncthreads();
   if (tid < NB) xs[tid] = xv[(int64_t)I * NB + tid] - red[tid] - red[tid + NB];
   __syncthreads();
-  const T* inv = Ainv + d.inv_off + (int64_t)I * NB * NB;
+  const T* inv = Ainv + d.inv_off + ((UPPER ? d.nblk : 0) + (int64_t)I) * NB * NB;
   double acc2 = 0.0;
 #pragma unroll 8
   for (int c = 0; c < 64; ++c) acc2 += (double)inv[(int64_t)(64 * h + c) * NB + r] * xs[64 * h + c];
   red[tid] = acc2;
   __syncthreads();
-  if (tid < NB) __hip_atomic_store(xv + (int64_t)I * NB + tid, red[tid] + red[tid + NB], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  if (tid < NB) store_coherent(xv + (int64_t)I * NB + tid, red[tid] + red[tid + NB]);
   __syncthreads();
   if (tid == 0) publish(flags + d.flag_off + I, epoch);
 }
 
-// x <- L^-T x for every matrix.
-template <typename T>
-__global__ __launch_bounds__(256) void k_trsv_bwd(const MatDesc* __restrict__ desc, const int32_t* __restrict__ items,
-                                                  const T* __restrict__ A, const T* __restrict__ Ainv,
-                                                  double* x, unsigned* sync, unsigned* flags, DevErr* err) {
-  __shared__ double xs[NB];
-  __shared__ double red[NB];
+// Many right-hand sides (k <= KC columns): X <- L^-1 X or U^-1 X, X in block
+// batch layout (matrix m's block at xoff = voff*KC... given by xstride: the
+// block of matrix m starts at X + d.voff * ldk, column q at + q * d.ld).
+template <typename T, bool UPPER, int KC>
+__global__ __launch_bounds__(256) void k_trsm_multi(const MatDesc* __restrict__ desc,
+                                                    const int32_t* __restrict__ items, const T* __restrict__ A,
+                                                    const T* __restrict__ Ainv, double* X, int ldk, int k,
+                                                    unsigned* sync, unsigned* flags, DevErr* err) {
+  constexpr int H = KC / 2;
+  __shared__ double xs[NB * KC];   // [c][q]
   __shared__ int s_t;
   __shared__ unsigned s_epoch;
   const int tid = threadIdx.x;
-  const int lane = tid & 63, w = tid >> 6;
   if (tid == 0) {
     s_t = (int)atomicAdd(&sync[0], 1u);
     s_epoch = __hip_atomic_load(&sync[1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -432,43 +488,57 @@ __global__ __launch_bounds__(256) void k_trsv_bwd(const MatDesc* __restrict__ de
   const int m = items[2 * s_t], I = items[2 * s_t + 1];
   const unsigned epoch = s_epoch;
   const MatDesc d = desc[m];
-  double* xv = x + d.voff;
-  double acc[32];
+  double* Xm = X + d.voff * (int64_t)ldk;
+  const int r = tid & (NB - 1), g = tid >> 7;
+  double acc[H];
 #pragma unroll
-  for (int cc = 0; cc < 32; ++cc) acc[cc] = 0.0;
-  const T* colbase = A + d.off + ((int64_t)I * NB + 32 * w) * d.ld;
-  for (int J = I + 1; J < d.nblk; ++J) {
+  for (int q = 0; q < H; ++q) acc[q] = 0.0;
+  const int J0 = UPPER ? I + 1 : 0, J1 = UPPER ? d.nblk : I;
+  for (int J = J0; J < J1; ++J) {
     if (tid == 0) wait_flag(flags + d.flag_off + J, epoch, err);
     __syncthreads();
-    if (tid < NB) xs[tid] = __hip_atomic_load(xv + (int64_t)J * NB + tid, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    for (int idx = tid; idx < NB * KC; idx += 256) {
+      int rr = idx & (NB - 1), q = idx >> 7;
+      xs[rr * KC + q] = q < k ? load_coherent(Xm + (int64_t)q * d.ld + (int64_t)J * NB + rr) : 0.0;
+    }
     __syncthreads();
-    const double x0 = xs[lane], x1 = xs[lane + 64];
-    const T* b = colbase + (int64_t)J * NB + lane;
+    const T* col = A + d.off + (int64_t)J * NB * d.ld + (int64_t)I * NB + r;
+    for (int c = 0; c < NB; ++c) {
+      const double l = (double)col[(int64_t)c * d.ld];
 #pragma unroll
-    for (int cc = 0; cc < 32; ++cc) acc[cc] += (double)b[(int64_t)cc * d.ld] * x0 + (double)b[(int64_t)cc * d.ld + 64] * x1;
+      for (int q = 0; q < H; ++q) acc[q] += l * xs[c * KC + g * H + q];
+    }
     __syncthreads();
   }
+  // s = X_I - acc  -> xs
 #pragma unroll
-  for (int cc = 0; cc < 32; ++cc) {
-    double v = wave_sum(acc[cc]);
-    if (lane == 0) red[32 * w + cc] = v;
+  for (int q = 0; q < H; ++q) {
+    const int qq = g * H + q;
+    xs[r * KC + qq] = (qq < k ? Xm[(int64_t)qq * d.ld + (int64_t)I * NB + r] : 0.0) - acc[q];
   }
   __syncthreads();
-  if (tid < NB) xs[tid] = xv[(int64_t)I * NB + tid] - red[tid];
-  __syncthreads();
-  // x_I = inv(L_II)^T s : x[c] = sum_r inv[r][c] s[r]
-  const T* inv = Ainv + d.inv_off + (int64_t)I * NB * NB;
-  const double s0 = xs[lane], s1 = xs[lane + 64];
-  for (int cc = 0; cc < 32; ++cc) {
-    const int c = 32 * w + cc;
-    double v = (double)inv[(int64_t)c * NB + lane] * s0 + (double)inv[(int64_t)c * NB + lane + 64] * s1;
-    v = wave_sum(v);
-    if (lane == 0) red[c] = v;
+  const T* inv = Ainv + d.inv_off + ((UPPER ? d.nblk : 0) + (int64_t)I) * NB * NB;
+#pragma unroll
+  for (int q = 0; q < H; ++q) acc[q] = 0.0;
+  for (int c = 0; c < NB; ++c) {
+    const double l = (double)inv[(int64_t)c * NB + r];
+#pragma unroll
+    for (int q = 0; q < H; ++q) acc[q] += l * xs[c * KC + g * H + q];
   }
-  __syncthreads();
-  if (tid < NB) __hip_atomic_store(xv + (int64_t)I * NB + tid, red[tid], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+#pragma unroll
+  for (int q = 0; q < H; ++q) {
+    const int qq = g * H + q;
+    if (qq < k) store_coherent(Xm + (int64_t)qq * d.ld + (int64_t)I * NB + r, acc[q]);
+  }
   __syncthreads();
   if (tid == 0) publish(flags + d.flag_off + I, epoch);
+}
+
+template <typename T>
+static void mirror_impl(const FactorPlan& P, T* A, hipStream_t st) {
+  if (P.mirror_tiles > 0)
+    k_mirror<T><<<dim3((unsigned)P.mirror_tiles), dim3(256), 0, st>>>(P.d_desc.p, P.d_order.p, P.d_mirror_prefix.p,
+                                                                      P.nmat, A);
 }
 
 template <typename T>
@@ -476,13 +546,30 @@ static void solve_impl(const FactorPlan& P, const T* A, const T* Ainv, double* x
                        DevErr* err, hipStream_t st) {
   if (P.n_items == 0) return;
   k_solve_begin<<<1, 1, 0, st>>>(sync);
-  k_trsv_fwd<T><<<dim3((unsigned)P.n_items), dim3(256), 0, st>>>(P.d_desc.p, P.d_items_fwd.p, A, Ainv, x, sync,
-                                                                   flags, err);
+  k_trsv<T, false><<<dim3((unsigned)P.n_items), dim3(256), 0, st>>>(P.d_desc.p, P.d_items_fwd.p, A, Ainv, x, sync,
+                                                                     flags, err);
   k_solve_begin<<<1, 1, 0, st>>>(sync);
-  k_trsv_bwd<T><<<dim3((unsigned)P.n_items), dim3(256), 0, st>>>(P.d_desc.p, P.d_items_bwd.p, A, Ainv, x, sync,
-                                                                   flags, err);
+  k_trsv<T, true><<<dim3((unsigned)P.n_items), dim3(256), 0, st>>>(P.d_desc.p, P.d_items_bwd.p, A, Ainv, x, sync,
+                                                                    flags, err);
   HIP_CHECK(hipGetLastError());
 }
+
+template <typename T>
+static void solve_multi_impl(const FactorPlan& P, const T* A, const T* Ainv, double* X, int ldk, int k,
+                             unsigned* sync, unsigned* flags, DevErr* err, hipStream_t st) {
+  if (P.n_items == 0 || k == 0) return;
+  if (k > 32) throw Error(GENEO_EUNSUPPORTED, "more than 32 right-hand sides");
+  k_solve_begin<<<1, 1, 0, st>>>(sync);
+  k_trsm_multi<T, false, 32><<<dim3((unsigned)P.n_items), dim3(256), 0, st>>>(P.d_desc.p, P.d_items_fwd.p, A, Ainv,
+                                                                              X, ldk, k, sync, flags, err);
+  k_solve_begin<<<1, 1, 0, st>>>(sync);
+  k_trsm_multi<T, true, 32><<<dim3((unsigned)P.n_items), dim3(256), 0, st>>>(P.d_desc.p, P.d_items_bwd.p, A, Ainv,
+                                                                             X, ldk, k, sync, flags, err);
+  HIP_CHECK(hipGetLastError());
+}
+
+void mirror(const FactorPlan& P, double* A, hipStream_t st) { mirror_impl<double>(P, A, st); }
+void mirror(const FactorPlan& P, float* A, hipStream_t st) { mirror_impl<float>(P, A, st); }
 
 void solve(const FactorPlan& P, const double* A, const double* Ainv, double* x, unsigned* sync, unsigned* flags,
            DevErr* err, hipStream_t st) {
@@ -491,6 +578,14 @@ void solve(const FactorPlan& P, const double* A, const double* Ainv, double* x, 
 void solve(const FactorPlan& P, const float* A, const float* Ainv, double* x, unsigned* sync, unsigned* flags,
            DevErr* err, hipStream_t st) {
   solve_impl<float>(P, A, Ainv, x, sync, flags, err, st);
+}
+void solve_multi(const FactorPlan& P, const double* A, const double* Ainv, double* X, int ldk, int k,
+                 unsigned* sync, unsigned* flags, DevErr* err, hipStream_t st) {
+  solve_multi_impl<double>(P, A, Ainv, X, ldk, k, sync, flags, err, st);
+}
+void solve_multi(const FactorPlan& P, const float* A, const float* Ainv, double* X, int ldk, int k,
+                 unsigned* sync, unsigned* flags, DevErr* err, hipStream_t st) {
+  solve_multi_impl<float>(P, A, Ainv, X, ldk, k, sync, flags, err, st);
 }
 
 }  // namespace geneo

@@ -1,12 +1,1017 @@
-// Local generalised eigenproblems of the GenEO coarse space (see below).
+// Local generalised eigenproblems of the GenEO coarse space, all subdomains
+// at once (Section 3.2, GEVP "tauthresholdAS", eq. (eigAtildeBAS)):
+//   Atilde_j V = lambda B_j V,  Atilde_j = (I - xi_j)^T D_j A_j D_j (I - xi_j),
+//   B_j = A_j^Neu,  xi_j = G_j S_j^-1 G_j^T A_j,  S_j = G_j^T A_j G_j,
+// keep lambda > tau (at most nev_max), coarse vectors D_j (I - xi_j) V.
+//
+// Solver: block LOBPCG for the largest eigenvalues, preconditioned with
+// B_j^-1 (dense Cholesky of the Neumann matrix: with this preconditioner the
+// iterates stay B-orthogonal to span(G_j), which is the lambda = 0
+// eigenspace; the start block is B-orthogonally projected out of span(G_j)
+// with H_j = G_j^T B_j G_j).  Rayleigh-Ritz in FP64 on [X, W, P] through
+// an eigendecomposition of the B-Gram matrix (columns that are numerically
+// dependent are dropped) followed by a Jacobi eigensolver, one workgroup per
+// subdomain in LDS.  Residual of a Ritz pair: ||Atilde x - theta B x|| /
+// (|theta| ||B x||).
+#include <algorithm>
+#include <cmath>
+#include <cstdlib>
+#include <numeric>
+
 #include "precond.h"
 
 namespace geneo {
 
+static inline unsigned nb256(int64_t n) { return (unsigned)((n + 255) / 256); }
+
+__device__ inline int find_seg(const int64_t* __restrict__ off, int n, int64_t x) {
+  int lo = 0, hi = n - 1;
+  while (lo < hi) {
+    int mid = (lo + hi + 1) >> 1;
+    if (off[mid] <= x) lo = mid; else hi = mid - 1;
+  }
+  return lo;
+}
+
+// ------------------------------------------------------------ operators
+// Neumann values: local nonzero k of subdomain j sums the element entries of
+// its global slot whose tet lies in a cell of Omega_j.
+__global__ void k_neumann_vals(int64_t nnz, int nsub, const int64_t* __restrict__ nnz_off,
+                               const int32_t* __restrict__ lslot, const int32_t* __restrict__ cptr,
+                               const int32_t* __restrict__ cidx, const double* __restrict__ elem,
+                               const int32_t* __restrict__ tet_cell, const uint32_t* __restrict__ cellbits,
+                               int64_t words, double* __restrict__ bval) {
+  int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (k >= nnz) return;
+  const int j = find_seg(nnz_off, nsub, k);
+  const uint32_t* bits = cellbits + (int64_t)j * words;
+  const int32_t s = lslot[k];
+  double acc = 0.0;
+  for (int32_t c = cptr[s]; c < cptr[s + 1]; ++c) {
+    const int32_t e = cidx[c];
+    const int32_t cell = tet_cell[e / 36];
+    if ((bits[cell >> 5] >> (cell & 31)) & 1u) acc += elem[e];
+  }
+  bval[k] = acc;
+}
+
+// Y = M X (+ options) over blocks of k columns, one thread per (batch row, column):
+//   out = scale .* (M x)        if base == nullptr
+//   out = base - scale .* (M x) otherwise          (scale may be nullptr = 1)
+// M is the local CSR (rows of subdomain j: lrp[rp_off[j] + r] .. ), values
+// vals[k] if lvals else gval[lslot[k]].
+__global__ void k_spmm(int64_t len, int k, const int32_t* __restrict__ row_sub, const int64_t* __restrict__ voff,
+                       const int32_t* __restrict__ nloc, const int64_t* __restrict__ rp_off,
+                       const int32_t* __restrict__ lrp, const int32_t* __restrict__ lcol,
+                       const int32_t* __restrict__ lslot, const double* __restrict__ gval,
+                       const double* __restrict__ lvals, const double* __restrict__ X, const double* __restrict__ base,
+                       const double* __restrict__ scale, double* __restrict__ Y) {
+  int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (idx >= len * k) return;
+  const int64_t b = idx % len;
+  const int q = (int)(idx / len);
+  const int j = row_sub[b];
+  const int64_t r = b - voff[j];
+  const int64_t ld = voff[j + 1] - voff[j];
+  const int64_t blk = voff[j] * k + (int64_t)q * ld;   // column q of subdomain j's block
+  double acc = 0.0;
+  if (r < nloc[j]) {
+    const int32_t* rp = lrp + rp_off[j];
+    for (int32_t t = rp[r]; t < rp[r + 1]; ++t) {
+      const double v = lvals ? lvals[t] : gval[lslot[t]];
+      acc += v * X[blk + lcol[t]];
+    }
+    if (scale) acc *= scale[b];
+  }
+  const int64_t o = blk + r;
+  Y[o] = base ? base[o] - acc : acc;
+}
+
+// N = G^T X : node block (p_pad rows per subdomain), one thread per (node row, column)
+__global__ void k_gt(int64_t plen, int k, const int32_t* __restrict__ node_sub, const int64_t* __restrict__ poff,
+                     const int32_t* __restrict__ pl, const int64_t* __restrict__ voff,
+                     const int64_t* __restrict__ ne_off, const int32_t* __restrict__ ne_ptr,
+                     const int32_t* __restrict__ ne_edge, const int8_t* __restrict__ ne_sign,
+                     const double* __restrict__ X, double* __restrict__ N) {
+  int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (idx >= plen * k) return;
+  const int64_t b = idx % plen;
+  const int q = (int)(idx / plen);
+  const int j = node_sub[b];
+  const int64_t a = b - poff[j];
+  const int64_t pld = poff[j + 1] - poff[j];
+  const int64_t ld = voff[j + 1] - voff[j];
+  double acc = 0.0;
+  if (a < pl[j]) {
+    const int32_t* ptr = ne_ptr + ne_off[j];
+    const double* x = X + voff[j] * k + (int64_t)q * ld;
+    for (int32_t t = ptr[a]; t < ptr[a + 1]; ++t) acc += (double)ne_sign[t] * x[ne_edge[t]];
+  }
+  N[poff[j] * k + (int64_t)q * pld + a] = acc;
+}
+
+// out = [base -] scale .* (G N) : edge block; G row r = -node(na) + node(nb)
+__global__ void k_g(int64_t len, int k, const int32_t* __restrict__ row_sub, const int64_t* __restrict__ voff,
+                    const int32_t* __restrict__ nloc, const int64_t* __restrict__ poff,
+                    const int32_t* __restrict__ ena, const int32_t* __restrict__ enb, const double* __restrict__ N,
+                    const double* __restrict__ base, const double* __restrict__ scale, double* __restrict__ out) {
+  int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (idx >= len * k) return;
+  const int64_t b = idx % len;
+  const int q = (int)(idx / len);
+  const int j = row_sub[b];
+  const int64_t r = b - voff[j];
+  const int64_t ld = voff[j + 1] - voff[j];
+  const int64_t pld = poff[j + 1] - poff[j];
+  const int64_t o = voff[j] * k + (int64_t)q * ld + r;
+  double v = 0.0;
+  if (r < nloc[j]) {
+    const double* n = N + poff[j] * k + (int64_t)q * pld;
+    const int32_t a = ena[b], c = enb[b];
+    if (a >= 0) v -= n[a];
+    if (c >= 0) v += n[c];
+  }
+  double t = base ? base[o] - v : v;
+  out[o] = scale ? t * scale[b] : t;
+}
+
+// R = AX - BX diag(theta) (into W); also per-(subdomain, column) squared norms of R and BX
+__global__ __launch_bounds__(256) void k_residual(int k, const int64_t* __restrict__ voff, const double* __restrict__ AX,
+                                                  const double* __restrict__ BX, const double* __restrict__ theta,
+                                                  double* __restrict__ R, double* __restrict__ nrm) {
+  const int j = blockIdx.x / k, q = blockIdx.x % k;
+  const int64_t ld = voff[j + 1] - voff[j];
+  const int64_t o = voff[j] * k + (int64_t)q * ld;
+  const double th = theta[j * k + q];
+  double s1 = 0.0, s2 = 0.0;
+  for (int64_t r = threadIdx.x; r < ld; r += 256) {
+    const double bx = BX[o + r];
+    const double v = AX[o + r] - th * bx;
+    R[o + r] = v;
+    s1 += v * v;
+    s2 += bx * bx;
+  }
+  __shared__ double a1[256], a2[256];
+  a1[threadIdx.x] = s1;
+  a2[threadIdx.x] = s2;
+  __syncthreads();
+  for (int st = 128; st > 0; st >>= 1) {
+    if (threadIdx.x < st) {
+      a1[threadIdx.x] += a1[threadIdx.x + st];
+      a2[threadIdx.x] += a2[threadIdx.x + st];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    nrm[2 * (j * k + q)] = a1[0];
+    nrm[2 * (j * k + q) + 1] = a2[0];
+  }
+}
+
+// Gram partials: for row range [r0, r0 + 512) of subdomain j,
+//   GA[a][b] = sum_r L[r][a] RA[r][b],  GB[a][b] = sum_r L[r][a] RB[r][b]
+// where the "left" block is [L0 L1 L2] (nl blocks of k columns) and the right
+// blocks likewise.  Partials land in part[(chunk) * 2 m^2 ...].
+constexpr int kGramRows = 512, kGramSub = 32;
+__global__ __launch_bounds__(256) void k_gram(int k, int nl, const int64_t* __restrict__ voff,
+                                              const int64_t* __restrict__ chunk_off, int nsub,
+                                              const double* __restrict__ L0, const double* __restrict__ L1,
+                                              const double* __restrict__ L2, const double* __restrict__ A0,
+                                              const double* __restrict__ A1, const double* __restrict__ A2,
+                                              const double* __restrict__ B0, const double* __restrict__ B1,
+                                              const double* __restrict__ B2, double* __restrict__ part) {
+  extern __shared__ double sm[];
+  const int m = nl * k;
+  double* ls = sm;                          // [kGramSub][m]
+  double* as = ls + kGramSub * m;
+  double* bs = as + kGramSub * m;
+  const int j = find_seg(chunk_off, nsub, blockIdx.x);
+  const int64_t chunk = blockIdx.x - chunk_off[j];
+  const int64_t ld = voff[j + 1] - voff[j];
+  const int64_t base = voff[j] * k;
+  const int64_t rbeg = chunk * kGramRows, rend = min((int64_t)ld, rbeg + kGramRows);
+  const double* Ls[3] = {L0, L1, L2};
+  const double* As[3] = {A0, A1, A2};
+  const double* Bs[3] = {B0, B1, B2};
+  const int mm = m * m;
+  double accA[21], accB[21];
+  for (int t = 0; t < 21; ++t) accA[t] = accB[t] = 0.0;
+  for (int64_t r0 = rbeg; r0 < rend; r0 += kGramSub) {
+    for (int idx = threadIdx.x; idx < kGramSub * m; idx += 256) {
+      const int rr = idx % kGramSub, c = idx / kGramSub;
+      const int blk = c / k, q = c % k;
+      const int64_t r = r0 + rr;
+      const int64_t o = base + (int64_t)q * ld + r;
+      const bool ok = r < rend;
+      ls[rr * m + c] = ok ? Ls[blk][o] : 0.0;
+      as[rr * m + c] = ok ? As[blk][o] : 0.0;
+      bs[rr * m + c] = ok ? Bs[blk][o] : 0.0;
+    }
+    __syncthreads();
+    for (int t = 0; t < 21; ++t) {
+      const int e = threadIdx.x + 256 * t;
+      if (e >= mm) break;
+      const int a = e % m, b = e / m;
+      double sa = 0.0, sb = 0.0;
+      for (int rr = 0; rr < kGramSub; ++rr) {
+        const double l = ls[rr * m + a];
+        sa += l * as[rr * m + b];
+        sb += l * bs[rr * m + b];
+      }
+      accA[t] += sa;
+      accB[t] += sb;
+    }
+    __syncthreads();
+  }
+  double* out = part + (int64_t)blockIdx.x * 2 * mm;
+  for (int t = 0; t < 21; ++t) {
+    const int e = threadIdx.x + 256 * t;
+    if (e >= mm) break;
+    out[e] = accA[t];
+    out[mm + e] = accB[t];
+  }
+}
+
+// sum the Gram partials of each subdomain in chunk order
+__global__ void k_gram_reduce(int m, const int64_t* __restrict__ chunk_off, const double* __restrict__ part,
+                              double* __restrict__ gram) {
+  const int j = blockIdx.y;
+  const int mm2 = 2 * m * m;
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= mm2) return;
+  double acc = 0.0;
+  for (int64_t c = chunk_off[j]; c < chunk_off[j + 1]; ++c) acc += part[c * mm2 + e];
+  gram[(int64_t)j * mm2 + e] = acc;
+}
+
+// ---------------------------------------------------- Rayleigh-Ritz (LDS)
+constexpr int kMaxM = 72;
+
+// Jacobi eigendecomposition of the symmetric n x n matrix a (row-major, ld),
+// eigenvectors in v; parallel round-robin ordering, all threads of the block.
+__device__ void jacobi_eig(double* a, double* v, int n, int ld, double* rot_c, double* rot_s, int* pp, int* qq,
+                           double* red) {
+  const int tid = threadIdx.x;
+  for (int idx = tid; idx < n * n; idx += blockDim.x) v[(idx / n) * ld + idx % n] = (idx / n == idx % n) ? 1.0 : 0.0;
+  const int ne = n + (n & 1);   // even number of slots; slot n (if odd) is a dummy
+  __syncthreads();
+  for (int sweep = 0; sweep < 30; ++sweep) {
+    // convergence: off-diagonal mass vs diagonal
+    double off = 0.0, dia = 0.0;
+    for (int idx = tid; idx < n * n; idx += blockDim.x) {
+      const int i = idx / n, j = idx % n;
+      const double x = a[i * ld + j];
+      if (i == j) dia += x * x; else off += x * x;
+    }
+    red[tid] = off;
+    red[256 + tid] = dia;
+    __syncthreads();
+    for (int s = 128; s > 0; s >>= 1) {
+      if (tid < s) {
+        red[tid] += red[tid + s];
+        red[256 + tid] += red[256 + tid + s];
+      }
+      __syncthreads();
+    }
+    const bool done = red[0] <= 1e-30 * red[256] || red[0] == 0.0;
+    __syncthreads();
+    if (done) break;
+    for (int round = 0; round < ne - 1; ++round) {
+      if (tid < ne / 2) {
+        int p, q;
+        if (tid == 0) {
+          p = round;
+          q = ne - 1;
+        } else {
+          p = (round + tid) % (ne - 1);
+          q = (round - tid + (ne - 1)) % (ne - 1);
+        }
+        if (p > q) { int t = p; p = q; q = t; }
+        double c = 1.0, s = 0.0;
+        if (q < n) {
+          const double apq = a[p * ld + q];
+          if (apq != 0.0) {
+            const double tau = (a[q * ld + q] - a[p * ld + p]) / (2.0 * apq);
+            const double t = tau >= 0.0 ? 1.0 / (tau + sqrt(1.0 + tau * tau)) : -1.0 / (-tau + sqrt(1.0 + tau * tau));
+            c = 1.0 / sqrt(1.0 + t * t);
+            s = t * c;
+          }
+        }
+        pp[tid] = p;
+        qq[tid] = q;
+        rot_c[tid] = c;
+        rot_s[tid] = s;
+      }
+      __syncthreads();
+      // rows: A <- J^T A
+      for (int idx = tid; idx < (ne / 2) * n; idx += blockDim.x) {
+        const int slot = idx / n, col = idx % n;
+        const int p = pp[slot], q = qq[slot];
+        if (q >= n) continue;
+        const double c = rot_c[slot], s = rot_s[slot];
+        const double x = a[p * ld + col], y = a[q * ld + col];
+        a[p * ld + col] = c * x - s * y;
+        a[q * ld + col] = s * x + c * y;
+      }
+      __syncthreads();
+      // columns: A <- A J, V <- V J
+      for (int idx = tid; idx < (ne / 2) * n; idx += blockDim.x) {
+        const int slot = idx / n, row = idx % n;
+        const int p = pp[slot], q = qq[slot];
+        if (q >= n) continue;
+        const double c = rot_c[slot], s = rot_s[slot];
+        double x = a[row * ld + p], y = a[row * ld + q];
+        a[row * ld + p] = c * x - s * y;
+        a[row * ld + q] = s * x + c * y;
+        x = v[row * ld + p];
+        y = v[row * ld + q];
+        v[row * ld + p] = c * x - s * y;
+        v[row * ld + q] = s * x + c * y;
+      }
+      __syncthreads();
+    }
+  }
+}
+
+// One workgroup per subdomain: solve SA c = theta SB c on the m-dimensional
+// basis, write the k largest theta (descending) and coefficients coef (m x k,
+// column-major).  Inactive subdomains are skipped.
+// svqb != 0: only B-orthonormalise: coef = diag(dsc) U (m x n2, zero columns
+// up to k), theta untouched.
+__global__ __launch_bounds__(256) void k_rayleigh_ritz(int m, int k, const double* __restrict__ gram,
+                                                       const int32_t* __restrict__ active, double drop,
+                                                       double* __restrict__ theta, double* __restrict__ coef,
+                                                       int svqb) {
+  const int j = blockIdx.x;
+  if (active && !active[j]) return;
+  __shared__ double A[kMaxM * kMaxM], B[kMaxM * kMaxM], V[kMaxM * kMaxM];
+  __shared__ double dsc[kMaxM], lam[kMaxM], rc[kMaxM / 2 + 1], rs[kMaxM / 2 + 1], red[512];
+  __shared__ int pp[kMaxM / 2 + 1], qq[kMaxM / 2 + 1], keep[kMaxM], order[kMaxM];
+  __shared__ int nk;
+  const int tid = threadIdx.x;
+  const int mm = m * m;
+  const double* GA = gram + (int64_t)j * 2 * mm;
+  const double* GB = GA + mm;
+  // symmetrise; diagonal scaling of the B-Gram
+  for (int idx = tid; idx < mm; idx += 256) {
+    const int a = idx % m, b = idx / m;
+    A[a * m + b] = 0.5 * (GA[a + b * m] + GA[b + a * m]);
+    B[a * m + b] = 0.5 * (GB[a + b * m] + GB[b + a * m]);
+  }
+  __syncthreads();
+  if (tid < m) {
+    const double d = B[tid * m + tid];
+    dsc[tid] = d > 0.0 ? 1.0 / sqrt(d) : 0.0;
+  }
+  __syncthreads();
+  for (int idx = tid; idx < mm; idx += 256) {
+    const int a = idx / m, b = idx % m;
+    A[a * m + b] *= dsc[a] * dsc[b];
+    B[a * m + b] *= dsc[a] * dsc[b];
+  }
+  __syncthreads();
+  jacobi_eig(B, V, m, m, rc, rs, pp, qq, red);
+  if (tid < m) lam[tid] = B[tid * m + tid];
+  __syncthreads();
+  if (tid == 0) {
+    double mx = 0.0;
+    for (int i = 0; i < m; ++i) mx = fmax(mx, lam[i]);
+    int c = 0;
+    for (int i = 0; i < m; ++i)
+      if (lam[i] > drop * mx) keep[c++] = i;
+    nk = c;
+  }
+  __syncthreads();
+  const int n2 = nk;
+  // U = V[:, keep] / sqrt(lambda) stored in B (m x n2, row-major ld m)
+  for (int idx = tid; idx < m * n2; idx += 256) {
+    const int r = idx / n2, c = idx % n2;
+    const int col = keep[c];
+    B[r * m + c] = V[r * m + col] / sqrt(lam[col]);
+  }
+  __syncthreads();
+  if (svqb) {
+    for (int idx = tid; idx < m * k; idx += 256) {
+      const int r = idx % m, c = idx / m;
+      coef[(int64_t)j * m * k + (int64_t)c * m + r] = c < n2 ? dsc[r] * B[r * m + c] : 0.0;
+    }
+    return;
+  }
+  // V <- A U (m x n2), then A <- U^T V (n2 x n2)
+  for (int idx = tid; idx < m * n2; idx += 256) {
+    const int r = idx / n2, c = idx % n2;
+    double s = 0.0;
+    for (int t = 0; t < m; ++t) s += A[r * m + t] * B[t * m + c];
+    V[r * m + c] = s;
+  }
+  __syncthreads();
+  for (int idx = tid; idx < n2 * n2; idx += 256) {
+    const int r = idx / n2, c = idx % n2;
+    double s = 0.0;
+    for (int t = 0; t < m; ++t) s += B[t * m + r] * V[t * m + c];
+    A[r * m + c] = s;
+  }
+  __syncthreads();
+  for (int idx = tid; idx < n2 * n2; idx += 256) {
+    const int r = idx / n2, c = idx % n2;
+    if (r < c) {
+      const double s = 0.5 * (A[r * m + c] + A[c * m + r]);
+      A[r * m + c] = s;
+      A[c * m + r] = s;
+    }
+  }
+  __syncthreads();
+  jacobi_eig(A, V, n2, m, rc, rs, pp, qq, red);
+  if (tid == 0) {
+    for (int i = 0; i < n2; ++i) {
+      lam[i] = A[i * m + i];
+      order[i] = i;
+    }
+    for (int i = 1; i < n2; ++i) {   // insertion sort, descending
+      int o = order[i];
+      int t = i - 1;
+      while (t >= 0 && lam[order[t]] < lam[o]) {
+        order[t + 1] = order[t];
+        --t;
+      }
+      order[t + 1] = o;
+    }
+  }
+  __syncthreads();
+  // coef = diag(dsc) U Y[:, order[0..k)]  (m x k); missing columns -> 0
+  for (int idx = tid; idx < m * k; idx += 256) {
+    const int r = idx % m, c = idx / m;
+    double s = 0.0;
+    if (c < n2) {
+      const int col = order[c];
+      for (int t = 0; t < n2; ++t) s += B[r * m + t] * V[t * m + col];
+      s *= dsc[r];
+    }
+    coef[(int64_t)j * m * k + (int64_t)c * m + r] = s;
+  }
+  if (tid < k) theta[j * k + tid] = tid < n2 ? lam[order[tid]] : -1e300;
+}
+
+// out = [L0 L1 L2][:, cols from coefficient rows r0..m) * coef  (per subdomain, n_pad x k)
+// i.e. out[r][q] = sum_{c = c0}^{m-1} Lblk(c)[r][c % k] * coef[c][q]; inactive: out = keep
+__global__ void k_combine(int64_t len, int k, int m, int c0, const int32_t* __restrict__ row_sub,
+                          const int64_t* __restrict__ voff, const int32_t* __restrict__ active,
+                          const double* __restrict__ L0, const double* __restrict__ L1,
+                          const double* __restrict__ L2, const double* __restrict__ coef,
+                          const double* __restrict__ keep_src, double* __restrict__ out) {
+  int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (idx >= len * k) return;
+  const int64_t b = idx % len;
+  const int q = (int)(idx / len);
+  const int j = row_sub[b];
+  const int64_t r = b - voff[j];
+  const int64_t ld = voff[j + 1] - voff[j];
+  const int64_t o = voff[j] * k + (int64_t)q * ld + r;
+  if (active && !active[j]) {
+    out[o] = keep_src ? keep_src[o] : 0.0;
+    return;
+  }
+  const double* L[3] = {L0, L1, L2};
+  const double* cf = coef + (int64_t)j * m * k + (int64_t)q * m;
+  double acc = 0.0;
+  for (int c = c0; c < m; ++c) acc += L[c / k][voff[j] * k + (int64_t)(c % k) * ld + r] * cf[c];
+  out[o] = acc;
+}
+
+// out -= X C  with C = Gram block (k x k per subdomain, from gram[j] rows 0..k of the A part)
+__global__ void k_sub_xc(int64_t len, int k, const int32_t* __restrict__ row_sub, const int64_t* __restrict__ voff,
+                         const double* __restrict__ X, const double* __restrict__ C, int ldc_stride,
+                         double* __restrict__ out) {
+  int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (idx >= len * k) return;
+  const int64_t b = idx % len;
+  const int q = (int)(idx / len);
+  const int j = row_sub[b];
+  const int64_t r = b - voff[j];
+  const int64_t ld = voff[j + 1] - voff[j];
+  const double* cj = C + (int64_t)j * ldc_stride;   // column-major k x k
+  double acc = 0.0;
+  for (int c = 0; c < k; ++c) acc += X[voff[j] * k + (int64_t)c * ld + r] * cj[c + q * k];
+  out[voff[j] * k + (int64_t)q * ld + r] -= acc;
+}
+
+// random start block (counter-based splitmix64 -> standard normal via Box-Muller), pads 0
+__device__ inline uint64_t splitmix64(uint64_t x) {
+  x += 0x9E3779B97F4A7C15ull;
+  x = (x ^ (x >> 30)) * 0xBF58476D1CE4E5B9ull;
+  x = (x ^ (x >> 27)) * 0x94D049BB133111EBull;
+  return x ^ (x >> 31);
+}
+__global__ void k_random_block(int64_t len, int k, const int32_t* __restrict__ row_sub,
+                               const int64_t* __restrict__ voff, const int32_t* __restrict__ nloc, uint64_t seed,
+                               double* __restrict__ X) {
+  int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (idx >= len * k) return;
+  const int64_t b = idx % len;
+  const int q = (int)(idx / len);
+  const int j = row_sub[b];
+  const int64_t r = b - voff[j];
+  const int64_t ld = voff[j + 1] - voff[j];
+  double v = 0.0;
+  if (r < nloc[j]) {
+    const uint64_t h1 = splitmix64(seed ^ splitmix64((uint64_t)idx * 2 + 1));
+    const uint64_t h2 = splitmix64(h1 + 0x632BE59BD9B4E019ull);
+    const double u1 = ((h1 >> 11) + 1.0) * (1.0 / 9007199254740993.0);
+    const double u2 = (h2 >> 11) * (1.0 / 9007199254740992.0);
+    v = sqrt(-2.0 * log(u1)) * cos(6.283185307179586 * u2);
+  }
+  X[voff[j] * k + (int64_t)q * ld + r] = v;
+}
+
+__global__ void k_scale_rows(int64_t len, int k, const int32_t* __restrict__ row_sub,
+                             const int64_t* __restrict__ voff, const double* __restrict__ s,
+                             const double* __restrict__ X, double* __restrict__ out) {
+  int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (idx >= len * k) return;
+  const int64_t b = idx % len;
+  const int q = (int)(idx / len);
+  const int j = row_sub[b];
+  const int64_t ld = voff[j + 1] - voff[j];
+  const int64_t o = voff[j] * k + (int64_t)q * ld + (b - voff[j]);
+  out[o] = s[b] * X[o];
+}
+
+// dense p x p G^T M G (M = local A or B values), one thread per (subdomain, node row a)
+__global__ void k_gmg(int64_t plen, const int32_t* __restrict__ node_sub, const int64_t* __restrict__ poff,
+                      const int32_t* __restrict__ pl, const int64_t* __restrict__ ne_off,
+                      const int32_t* __restrict__ ne_ptr, const int32_t* __restrict__ ne_edge,
+                      const int8_t* __restrict__ ne_sign, const int64_t* __restrict__ voff,
+                      const int64_t* __restrict__ rp_off, const int32_t* __restrict__ lrp,
+                      const int32_t* __restrict__ lcol, const int32_t* __restrict__ lslot,
+                      const double* __restrict__ gval, const double* __restrict__ lvals,
+                      const int32_t* __restrict__ ena, const int32_t* __restrict__ enb,
+                      const MatDesc* __restrict__ ndesc, double* __restrict__ S) {
+  int64_t b = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (b >= plen) return;
+  const int j = node_sub[b];
+  const int64_t a = b - poff[j];
+  if (a >= pl[j]) return;
+  const MatDesc d = ndesc[j];
+  const int32_t* ptr = ne_ptr + ne_off[j];
+  const int32_t* rp = lrp + rp_off[j];
+  for (int32_t t = ptr[a]; t < ptr[a + 1]; ++t) {
+    const int32_t r = ne_edge[t];
+    const double sa = (double)ne_sign[t];
+    for (int32_t u = rp[r]; u < rp[r + 1]; ++u) {
+      const double v = sa * (lvals ? lvals[u] : gval[lslot[u]]);
+      const int64_t cb = voff[j] + lcol[u];
+      const int32_t na = ena[cb], nbb = enb[cb];
+      if (na >= 0) S[d.off + (int64_t)na * d.ld + a] -= v;
+      if (nbb >= 0) S[d.off + (int64_t)nbb * d.ld + a] += v;
+    }
+  }
+}
+
+__global__ void k_dense_scatter_vals(int64_t nnz, const int32_t* __restrict__ lrow, const int32_t* __restrict__ lcol,
+                                     const int64_t* __restrict__ nnz_off, int nmat, const MatDesc* __restrict__ desc,
+                                     const double* __restrict__ vals, double* __restrict__ A) {
+  int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (k >= nnz) return;
+  const int j = find_seg(nnz_off, nmat, k);
+  const MatDesc d = desc[j];
+  A[d.off + (int64_t)lcol[k] * d.ld + lrow[k]] = vals[k];
+}
+
+__global__ void k_fill_pad_identity(int64_t total, int nmat, const int64_t* __restrict__ mat_start,
+                                    const MatDesc* __restrict__ desc, double* __restrict__ A) {
+  int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (idx >= total) return;
+  const int j = find_seg(mat_start, nmat, idx);
+  const MatDesc d = desc[j];
+  const int64_t loc = idx - mat_start[j];
+  const int64_t r = loc % d.ld, c = loc / d.ld;
+  A[d.off + loc] = (r == c && r >= d.n) ? 1.0 : 0.0;
+}
+
+// ------------------------------------------------------------- driver
+
+struct EigWork {
+  int N = 0, k = 0;
+  int64_t len = 0, plen = 0;
+  std::vector<int64_t> voff, poff;
+  DevBuf<int32_t> row_sub, node_sub, pl, ne_ptr, ne_edge, ena, enb, lrp, nloc;
+  DevBuf<int8_t> ne_sign;
+  DevBuf<int64_t> voff_d, poff_d, ne_off, rp_off, chunk_off;
+  DevBuf<double> bval, LB, LBinv, S, Sinv, H, Hinv;
+  FactorPlan node;
+  DevBuf<unsigned> flags_node, flags_local;
+  int64_t nchunks = 0;
+};
+
+static void spmm(const geneo_precond* pc, EigWork& w, const double* lvals, const double* X, const double* base,
+                 const double* scale, double* Y, hipStream_t st) {
+  k_spmm<<<nb256(w.len * w.k), 256, 0, st>>>(w.len, w.k, w.row_sub.p, w.voff_d.p, w.nloc.p, w.rp_off.p, w.lrp.p,
+                                             pc->d_lcol.p, pc->d_lslot.p, pc->sys->d_val.p, lvals, X, base, scale,
+                                             Y);
+}
+static void gt(EigWork& w, const double* X, double* Nn, hipStream_t st) {
+  k_gt<<<nb256(w.plen * w.k), 256, 0, st>>>(w.plen, w.k, w.node_sub.p, w.poff_d.p, w.pl.p, w.voff_d.p, w.ne_off.p,
+                                            w.ne_ptr.p, w.ne_edge.p, w.ne_sign.p, X, Nn);
+}
+static void gmul(EigWork& w, const double* Nn, const double* base, const double* scale, double* out, hipStream_t st) {
+  k_g<<<nb256(w.len * w.k), 256, 0, st>>>(w.len, w.k, w.row_sub.p, w.voff_d.p, w.nloc.p, w.poff_d.p, w.ena.p, w.enb.p,
+                                          Nn, base, scale, out);
+}
+
+// out = Atilde X  (tmp1, tmp2: edge blocks; nt: node block)
+static void apply_atilde(geneo_ctx* ctx, const geneo_precond* pc, EigWork& w, const double* X, double* out,
+                         double* t1, double* t2, double* nt) {
+  hipStream_t st = ctx->stream;
+  const double* D = pc->d_bpou.p;
+  spmm(pc, w, nullptr, X, nullptr, nullptr, t1, st);                 // A X
+  gt(w, t1, nt, st);                                                 // G^T A X
+  solve_multi(w.node, w.S.p, w.Sinv.p, nt, w.k, w.k, ctx->d_sync, w.flags_node.p, ctx->d_err, st);
+  gmul(w, nt, X, D, t1, st);                                         // D (X - G S^-1 G^T A X)
+  spmm(pc, w, nullptr, t1, nullptr, D, t2, st);                      // y = D A D u
+  gt(w, t2, nt, st);
+  solve_multi(w.node, w.S.p, w.Sinv.p, nt, w.k, w.k, ctx->d_sync, w.flags_node.p, ctx->d_err, st);
+  gmul(w, nt, nullptr, nullptr, t1, st);                             // G S^-1 G^T y
+  spmm(pc, w, nullptr, t1, t2, nullptr, out, st);                    // y - A G S^-1 G^T y
+}
+
+static void gram(EigWork& w, int nl, const double* L0, const double* L1, const double* L2, const double* A0,
+                 const double* A1, const double* A2, const double* B0, const double* B1, const double* B2,
+                 DevBuf<double>& part, DevBuf<double>& g, hipStream_t st) {
+  const int m = nl * w.k;
+  const size_t lds = sizeof(double) * 3 * kGramSub * m;
+  k_gram<<<dim3((unsigned)w.nchunks), 256, lds, st>>>(w.k, nl, w.voff_d.p, w.chunk_off.p, w.N, L0, L1, L2, A0, A1,
+                                                       A2, B0, B1, B2, part.p);
+  dim3 grid((unsigned)((2 * m * m + 255) / 256), (unsigned)w.N);
+  k_gram_reduce<<<grid, 256, 0, st>>>(m, w.chunk_off.p, part.p, g.p);
+}
+
 void solve_local_gevps(geneo_ctx* ctx, geneo_precond* pc) {
-  (void)ctx;
-  (void)pc;
-  throw Error(GENEO_EUNSUPPORTED, "GenEO eigensolver not built yet");
+  hipStream_t st = ctx->stream;
+  const geneo_system* s = pc->sys;
+  const geneo_decomp* dec = pc->dec;
+  const int N = pc->N;
+  const int nev = pc->opts.nev_max;
+  const int k = std::min(32, nev + std::max(0, pc->opts.lobpcg_guard));
+  if (nev < 1) return;
+  if (3 * k > kMaxM) throw Error(GENEO_EUNSUPPORTED, "nev_max + guard must be <= 24");
+  EigWork w;
+  w.N = N;
+  w.k = k;
+  w.voff = pc->voff;
+  w.len = pc->batch_len;
+  // ---- host structures: row -> subdomain, local rowptr, G incidence, node layout
+  std::vector<int32_t> row_sub(w.len), nloc(N);
+  std::vector<int64_t> rp_off(N + 1, 0);
+  std::vector<int32_t> lrp;
+  for (int j = 0; j < N; ++j) {
+    for (int64_t b = w.voff[j]; b < w.voff[j + 1]; ++b) row_sub[b] = j;
+    const int64_t n = dec->dofs_ptr[j + 1] - dec->dofs_ptr[j];
+    nloc[j] = (int32_t)n;
+    rp_off[j] = (int64_t)lrp.size();
+    // local nnz of subdomain j are in row order, absolute indices from lnnz_off[j]
+    lrp.resize(lrp.size() + n + 1);
+    rp_off[j + 1] = (int64_t)lrp.size();
+  }
+  {
+    std::vector<int32_t> hrow(pc->d_lrow.n);
+    HIP_CHECK(hipMemcpy(hrow.data(), pc->d_lrow.p, sizeof(int32_t) * hrow.size(), hipMemcpyDeviceToHost));
+    for (int j = 0; j < N; ++j) {
+      const int64_t n = nloc[j];
+      int32_t* rp = lrp.data() + rp_off[j];
+      for (int64_t r = 0; r <= n; ++r) rp[r] = (int32_t)pc->lnnz_off[j];
+      for (int64_t t = pc->lnnz_off[j]; t < pc->lnnz_off[j + 1]; ++t) rp[hrow[t] + 1]++;
+      for (int64_t r = 0; r < n; ++r) rp[r + 1] += rp[r] - (int32_t)pc->lnnz_off[j];
+      // rp[r] now = lnnz_off[j] + count of rows < r  (absolute)
+    }
+  }
+  w.poff.assign(N + 1, 0);
+  std::vector<int32_t> pl(N), node_sub, ne_ptr, ne_edge, ena(w.len, -1), enb(w.len, -1);
+  std::vector<int8_t> ne_sign;
+  std::vector<int64_t> ne_off(N + 1, 0);
+  std::vector<MatDesc> ndesc(N);
+  {
+    int64_t off = 0, inv_off = 0, voff = 0;
+    int32_t flag_off = 0;
+    std::vector<int32_t> gl(s->n_free_nodes, -1);
+    for (int j = 0; j < N; ++j) {
+      const int64_t gb = dec->gn_ptr[j], ge = dec->gn_ptr[j + 1];
+      const int64_t p = ge - gb;
+      pl[j] = (int32_t)p;
+      const int64_t pp = round_up(std::max<int64_t>(p, 1), NB);
+      ndesc[j] = MatDesc{off, inv_off, -1, voff, (int32_t)pp, (int32_t)(pp / NB), flag_off, (int32_t)p};
+      off += pp * pp;
+      inv_off += 2 * pp * NB;
+      w.poff[j] = voff;
+      voff += pp;
+      flag_off += (int32_t)(pp / NB);
+      for (int64_t t = gb; t < ge; ++t) gl[dec->gnodes[t]] = (int32_t)(t - gb);
+      std::vector<std::vector<std::pair<int32_t, int8_t>>> inc(p);
+      for (int64_t r = dec->dofs_ptr[j]; r < dec->dofs_ptr[j + 1]; ++r) {
+        const int32_t lr = (int32_t)(r - dec->dofs_ptr[j]);
+        const int32_t e = s->free_edges[dec->dofs[r]];
+        const int32_t fa = s->node_to_free[s->edges[2 * (int64_t)e]];
+        const int32_t fb = s->node_to_free[s->edges[2 * (int64_t)e + 1]];
+        const int32_t la = fa >= 0 ? gl[fa] : -1, lb = fb >= 0 ? gl[fb] : -1;
+        ena[w.voff[j] + lr] = la;
+        enb[w.voff[j] + lr] = lb;
+        if (la >= 0) inc[la].push_back({lr, (int8_t)-1});
+        if (lb >= 0) inc[lb].push_back({lr, (int8_t)1});
+      }
+      ne_off[j] = (int64_t)ne_ptr.size();
+      int32_t acc = 0;
+      ne_ptr.push_back(0);
+      for (int64_t a = 0; a < p; ++a) {
+        for (auto& pr : inc[a]) {
+          ne_edge.push_back(pr.first);
+          ne_sign.push_back(pr.second);
+        }
+        acc += (int32_t)inc[a].size();
+        ne_ptr.push_back(acc);
+      }
+      for (int64_t t = gb; t < ge; ++t) gl[dec->gnodes[t]] = -1;
+    }
+    w.poff[N] = voff;
+    w.plen = voff;
+    node_sub.resize(w.plen);
+    for (int j = 0; j < N; ++j)
+      for (int64_t b = w.poff[j]; b < w.poff[j + 1]; ++b) node_sub[b] = j;
+    // edge offsets in ne_edge are per subdomain: ne_ptr indexes from ne_off-relative starts
+    // (ne_ptr segment of subdomain j starts at ne_off[j] and its values index ne_edge
+    //  relative to the first edge of the segment) -> make them absolute
+    int64_t base = 0;
+    for (int j = 0; j < N; ++j) {
+      for (int64_t a = 0; a <= pl[j]; ++a) ne_ptr[ne_off[j] + a] += (int32_t)base;
+      base += ne_ptr[ne_off[j] + pl[j]] - ne_ptr[ne_off[j]];
+    }
+    ne_off[N] = (int64_t)ne_ptr.size();
+    w.node.build(ndesc, st);
+    w.S.alloc(off);
+    w.H.alloc(off);
+    w.Sinv.alloc(inv_off);
+    w.Hinv.alloc(inv_off);
+    w.flags_node.alloc(flag_off);
+    HIP_CHECK(hipMemsetAsync(w.flags_node.p, 0, sizeof(unsigned) * flag_off, st));
+  }
+  w.row_sub.upload(row_sub, st);
+  w.nloc.upload(nloc, st);
+  w.rp_off.upload(rp_off, st);
+  w.lrp.upload(lrp, st);
+  w.voff_d.upload(w.voff, st);
+  w.poff_d.upload(w.poff, st);
+  w.pl.upload(pl, st);
+  w.node_sub.upload(node_sub, st);
+  w.ne_off.upload(ne_off, st);
+  w.ne_ptr.upload(ne_ptr, st);
+  w.ne_edge.upload(ne_edge, st);
+  w.ne_sign.upload(ne_sign, st);
+  w.ena.upload(ena, st);
+  w.enb.upload(enb, st);
+  std::vector<int64_t> chunk_off(N + 1, 0);
+  for (int j = 0; j < N; ++j) chunk_off[j + 1] = chunk_off[j] + (w.voff[j + 1] - w.voff[j] + kGramRows - 1) / kGramRows;
+  w.nchunks = chunk_off[N];
+  w.chunk_off.upload(chunk_off, st);
+
+  // ---- Neumann values, dense B_j, factor
+  const int64_t lnnz = pc->lnnz_off[N];
+  {
+    const int64_t words = (s->n_cells + 31) / 32;
+    std::vector<uint32_t> bits((size_t)words * N, 0u);
+    for (int j = 0; j < N; ++j)
+      for (int64_t t = dec->cells_ptr[j]; t < dec->cells_ptr[j + 1]; ++t) {
+        const int32_t c = dec->cells[t];
+        bits[(size_t)j * words + (c >> 5)] |= 1u << (c & 31);
+      }
+    DevBuf<uint32_t> dbits;
+    dbits.upload(bits, st);
+    w.bval.alloc(lnnz);
+    k_neumann_vals<<<nb256(lnnz), 256, 0, st>>>(lnnz, N, pc->d_lnnz_off.p, pc->d_lslot.p, s->d_contrib_ptr.p,
+                                                 s->d_contrib.p, s->d_elem.p, s->d_tet_cell.p, dbits.p, words,
+                                                 w.bval.p);
+    HIP_CHECK(hipStreamSynchronize(st));
+  }
+  const auto& ld = pc->local.h_desc;
+  const int64_t dense_total = ld.back().off + (int64_t)ld.back().ld * ld.back().ld;
+  std::vector<int64_t> mstart(N);
+  for (int j = 0; j < N; ++j) mstart[j] = ld[j].off;
+  DevBuf<int64_t> d_mstart;
+  d_mstart.upload(mstart, st);
+  w.LB.alloc(dense_total);
+  w.LBinv.alloc(pc->dLinv.n ? pc->dLinv.n : pc->fLinv.n);
+  k_fill_pad_identity<<<nb256(dense_total), 256, 0, st>>>(dense_total, N, d_mstart.p, pc->local.d_desc.p, w.LB.p);
+  k_dense_scatter_vals<<<nb256(lnnz), 256, 0, st>>>(lnnz, pc->d_lrow.p, pc->d_lcol.p, pc->d_lnnz_off.p, N,
+                                                     pc->local.d_desc.p, w.bval.p, w.LB.p);
+  factor(pc->local, w.LB.p, w.LBinv.p, nullptr, 0.0, nullptr, ctx->d_err, st);
+  w.flags_local.alloc(pc->d_flags_local.n);
+  HIP_CHECK(hipMemsetAsync(w.flags_local.p, 0, sizeof(unsigned) * pc->d_flags_local.n, st));
+
+  // ---- S_j = G^T A_j G, H_j = G^T B_j G, factor
+  {
+    std::vector<int64_t> nstart(N);
+    for (int j = 0; j < N; ++j) nstart[j] = ndesc[j].off;
+    DevBuf<int64_t> d_nstart;
+    d_nstart.upload(nstart, st);
+    const int64_t tot = w.S.n;
+    k_fill_pad_identity<<<nb256(tot), 256, 0, st>>>(tot, N, d_nstart.p, w.node.d_desc.p, w.S.p);
+    k_fill_pad_identity<<<nb256(tot), 256, 0, st>>>(tot, N, d_nstart.p, w.node.d_desc.p, w.H.p);
+    k_gmg<<<nb256(w.plen), 256, 0, st>>>(w.plen, w.node_sub.p, w.poff_d.p, w.pl.p, w.ne_off.p, w.ne_ptr.p,
+                                         w.ne_edge.p, w.ne_sign.p, w.voff_d.p, w.rp_off.p, w.lrp.p, pc->d_lcol.p,
+                                         pc->d_lslot.p, s->d_val.p, nullptr, w.ena.p, w.enb.p, w.node.d_desc.p,
+                                         w.S.p);
+    k_gmg<<<nb256(w.plen), 256, 0, st>>>(w.plen, w.node_sub.p, w.poff_d.p, w.pl.p, w.ne_off.p, w.ne_ptr.p,
+                                         w.ne_edge.p, w.ne_sign.p, w.voff_d.p, w.rp_off.p, w.lrp.p, pc->d_lcol.p,
+                                         pc->d_lslot.p, s->d_val.p, w.bval.p, w.ena.p, w.enb.p, w.node.d_desc.p,
+                                         w.H.p);
+    factor(w.node, w.S.p, w.Sinv.p, nullptr, 0.0, nullptr, ctx->d_err, st);
+    factor(w.node, w.H.p, w.Hinv.p, nullptr, 0.0, nullptr, ctx->d_err, st);
+    check_device_error(ctx);
+  }
+
+  // ---- LOBPCG
+  const int64_t blk = w.len * k;
+  DevBuf<double> X, Wb, P, AX, AW, AP, BX, BW, BP, Xn, Pn, T1, T2, Tv, Tb, NT, part, g, coef, theta, nrm;
+  for (auto* b : {&X, &Wb, &P, &AX, &AW, &AP, &BX, &BW, &BP, &Xn, &Pn, &T1, &T2, &Tv, &Tb}) b->alloc(blk);
+  NT.alloc(w.plen * k);
+  const int mmax = 3 * k;
+  part.alloc((size_t)w.nchunks * 2 * mmax * mmax);
+  g.alloc((size_t)N * 2 * mmax * mmax);
+  coef.alloc((size_t)N * mmax * k);
+  theta.alloc((size_t)N * k);
+  nrm.alloc((size_t)N * k * 2);
+  std::vector<int32_t> active(N, 1);
+  DevBuf<int32_t> d_active;
+  d_active.upload(active, st);
+  HIP_CHECK(hipFuncSetAttribute((const void*)k_gram, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                (int)(sizeof(double) * 3 * kGramSub * mmax)));
+
+  // start block: warm start if given, else random; B-orthogonal projection out of span(G_j)
+  if (pc->opts.warm_start) {
+    std::vector<double> h(blk, 0.0);
+    k_random_block<<<nb256(blk), 256, 0, st>>>(w.len, k, w.row_sub.p, w.voff_d.p, w.nloc.p, pc->opts.seed, X.p);
+    HIP_CHECK(hipMemcpy(h.data(), X.p, sizeof(double) * blk, hipMemcpyDeviceToHost));
+    int64_t src = 0;
+    for (int j = 0; j < N; ++j) {   // first nev columns from the warm start, guard columns random
+      const int64_t ldj = w.voff[j + 1] - w.voff[j];
+      for (int q = 0; q < std::min(k, nev); ++q)
+        for (int64_t r = 0; r < nloc[j]; ++r) h[w.voff[j] * k + q * ldj + r] = pc->opts.warm_start[src + (int64_t)q * nloc[j] + r];
+      src += (int64_t)nloc[j] * nev;
+    }
+    HIP_CHECK(hipMemcpy(X.p, h.data(), sizeof(double) * blk, hipMemcpyHostToDevice));
+  } else {
+    k_random_block<<<nb256(blk), 256, 0, st>>>(w.len, k, w.row_sub.p, w.voff_d.p, w.nloc.p, pc->opts.seed, X.p);
+  }
+  spmm(pc, w, w.bval.p, X.p, nullptr, nullptr, T1.p, st);        // B X
+  gt(w, T1.p, NT.p, st);
+  solve_multi(w.node, w.H.p, w.Hinv.p, NT.p, k, k, ctx->d_sync, w.flags_node.p, ctx->d_err, st);
+  gmul(w, NT.p, X.p, nullptr, X.p, st);                          // X - G H^-1 G^T B X
+
+  const double drop = 1e-12;
+  const int32_t* act = d_active.p;
+  auto bmul = [&](const double* V, double* BV) { spmm(pc, w, w.bval.p, V, nullptr, nullptr, BV, st); };
+  // V <- V - U (U^T B V), BV recomputed by the caller
+  auto orth = [&](const double* U, double* V, const double* BV) {
+    gram(w, 1, U, nullptr, nullptr, BV, nullptr, nullptr, BV, nullptr, nullptr, part, g, st);
+    k_sub_xc<<<nb256(blk), 256, 0, st>>>(w.len, k, w.row_sub.p, w.voff_d.p, U, g.p, 2 * k * k, V);
+  };
+  // B-orthonormalise V (numerically dependent columns become zero), twice
+  auto svqb2 = [&](DevBuf<double>& V, DevBuf<double>& BV, const int32_t* a) {
+    for (int t = 0; t < 2; ++t) {
+      gram(w, 1, V.p, nullptr, nullptr, BV.p, nullptr, nullptr, BV.p, nullptr, nullptr, part, g, st);
+      k_rayleigh_ritz<<<N, 256, 0, st>>>(k, k, g.p, a, drop, theta.p, coef.p, 1);
+      k_combine<<<nb256(blk), 256, 0, st>>>(w.len, k, k, 0, w.row_sub.p, w.voff_d.p, a, V.p, nullptr, nullptr,
+                                            coef.p, V.p, Tv.p);
+      k_combine<<<nb256(blk), 256, 0, st>>>(w.len, k, k, 0, w.row_sub.p, w.voff_d.p, a, BV.p, nullptr, nullptr,
+                                            coef.p, BV.p, Tb.p);
+      std::swap(V.p, Tv.p);
+      std::swap(BV.p, Tb.p);
+    }
+  };
+  bmul(X.p, BX.p);
+  svqb2(X, BX, nullptr);
+  apply_atilde(ctx, pc, w, X.p, AX.p, T1.p, T2.p, NT.p);
+  gram(w, 1, X.p, nullptr, nullptr, AX.p, nullptr, nullptr, BX.p, nullptr, nullptr, part, g, st);
+  k_rayleigh_ritz<<<N, 256, 0, st>>>(k, k, g.p, nullptr, drop, theta.p, coef.p, 0);
+  k_combine<<<nb256(blk), 256, 0, st>>>(w.len, k, k, 0, w.row_sub.p, w.voff_d.p, nullptr, X.p, nullptr, nullptr,
+                                        coef.p, nullptr, Xn.p);
+  std::swap(X.p, Xn.p);
+  // products are recomputed from the basis after every update (tracking them
+  // through the Rayleigh-Ritz coefficients drifts once the basis becomes
+  // ill-conditioned near convergence)
+  apply_atilde(ctx, pc, w, X.p, AX.p, T1.p, T2.p, NT.p);
+  bmul(X.p, BX.p);
+  HIP_CHECK(hipGetLastError());
+
+  const double tol = pc->opts.lobpcg_tol, tau = pc->opts.tau;
+  const bool verbose = std::getenv("GENEO_VERBOSE") != nullptr;
+  const double cert_tol = std::max(tol, 1e-4);
+  std::vector<double> h_theta(N * k), h_nrm(N * k * 2);
+  bool have_p = false;
+  int it = 0, unconv = 0;
+  const int maxit = std::max(1, pc->opts.lobpcg_maxit);
+  for (it = 1; it <= maxit; ++it) {
+    k_residual<<<N * k, 256, 0, st>>>(k, w.voff_d.p, AX.p, BX.p, theta.p, Wb.p, nrm.p);
+    HIP_CHECK(hipMemcpyAsync(h_theta.data(), theta.p, sizeof(double) * N * k, hipMemcpyDeviceToHost, st));
+    HIP_CHECK(hipMemcpyAsync(h_nrm.data(), nrm.p, sizeof(double) * N * k * 2, hipMemcpyDeviceToHost, st));
+    HIP_CHECK(hipStreamSynchronize(st));
+    int n_active = 0;
+    unconv = 0;
+    for (int j = 0; j < N; ++j) {
+      const double* th = h_theta.data() + j * k;
+      auto resid = [&](int q) {
+        return std::sqrt(h_nrm[2 * (j * k + q)]) / (std::fabs(th[q]) * std::sqrt(h_nrm[2 * (j * k + q) + 1]) + 1e-300);
+      };
+      int nsel = 0;
+      while (nsel < k && nsel < nev && th[nsel] > tau) ++nsel;
+      bool conv = true;
+      for (int q = 0; q < nsel; ++q)
+        if (!(resid(q) <= tol)) {
+          conv = false;
+          ++unconv;
+        }
+      // the first Ritz value below tau must be settled too
+      if (nsel < nev && nsel < k && !(resid(nsel) <= cert_tol)) conv = false;
+      active[j] = conv ? 0 : 1;
+      n_active += active[j];
+      if (verbose) {
+        double rmax = 0.0;
+        for (int q = 0; q < std::min(k, nsel + 1); ++q) rmax = std::max(rmax, resid(q));
+        std::fprintf(stderr, "[lobpcg] it %d sub %d nsel %d theta0 %.6g theta_k-1 %.6g maxres %.3g conv %d\n", it, j,
+                     nsel, th[0], th[k - 1], rmax, (int)conv);
+      }
+    }
+    if (n_active == 0 || it == maxit) break;
+    HIP_CHECK(hipMemcpyAsync(d_active.p, active.data(), sizeof(int32_t) * N, hipMemcpyHostToDevice, st));
+    // W = B^-1 R, B-orthogonal to X, B-orthonormal
+    solve_multi(pc->local, w.LB.p, w.LBinv.p, Wb.p, k, k, ctx->d_sync, w.flags_local.p, ctx->d_err, st);
+    for (int t = 0; t < 2; ++t) {
+      bmul(Wb.p, BW.p);
+      orth(X.p, Wb.p, BW.p);
+    }
+    bmul(Wb.p, BW.p);
+    svqb2(Wb, BW, act);
+    if (have_p) {   // P B-orthogonal to X and W, B-orthonormal
+      for (int t = 0; t < 2; ++t) {
+        bmul(P.p, BP.p);
+        orth(X.p, P.p, BP.p);
+        bmul(P.p, BP.p);
+        orth(Wb.p, P.p, BP.p);
+      }
+      bmul(P.p, BP.p);
+      svqb2(P, BP, act);
+      apply_atilde(ctx, pc, w, P.p, AP.p, T1.p, T2.p, NT.p);
+    }
+    apply_atilde(ctx, pc, w, Wb.p, AW.p, T1.p, T2.p, NT.p);
+    const int nl = have_p ? 3 : 2;
+    const int m = nl * k;
+    gram(w, nl, X.p, Wb.p, have_p ? P.p : nullptr, AX.p, AW.p, have_p ? AP.p : nullptr, BX.p, BW.p,
+         have_p ? BP.p : nullptr, part, g, st);
+    k_rayleigh_ritz<<<N, 256, 0, st>>>(m, k, g.p, act, drop, theta.p, coef.p, 0);
+    k_combine<<<nb256(blk), 256, 0, st>>>(w.len, k, m, 0, w.row_sub.p, w.voff_d.p, act, X.p, Wb.p,
+                                          have_p ? P.p : nullptr, coef.p, X.p, Xn.p);
+    k_combine<<<nb256(blk), 256, 0, st>>>(w.len, k, m, k, w.row_sub.p, w.voff_d.p, act, X.p, Wb.p,
+                                          have_p ? P.p : nullptr, coef.p, have_p ? P.p : nullptr, Pn.p);
+    std::swap(X.p, Xn.p);
+    std::swap(P.p, Pn.p);
+    apply_atilde(ctx, pc, w, X.p, AX.p, T1.p, T2.p, NT.p);
+    bmul(X.p, BX.p);
+    have_p = true;
+    HIP_CHECK(hipGetLastError());
+  }
+  check_device_error(ctx);
+  pc->info.lobpcg_iters = it > maxit ? maxit : it;
+  pc->info.lobpcg_unconverged = unconv;
+
+  // ---- selection and coarse vectors D_j (I - xi_j) X_sel
+  std::vector<int32_t> sel(N, 0);
+  for (int j = 0; j < N; ++j) {
+    const double* th = h_theta.data() + j * k;
+    pc->eigs[j].assign(th, th + k);
+    int c = 0;
+    while (c < k && c < nev && th[c] > tau) ++c;
+    sel[j] = c;
+    pc->eig_sel[j] = c;
+  }
+  // u = D (X - G S^-1 G^T A X) into T1 (all k columns), then pack the selected ones
+  spmm(pc, w, nullptr, X.p, nullptr, nullptr, T2.p, st);
+  gt(w, T2.p, NT.p, st);
+  solve_multi(w.node, w.S.p, w.Sinv.p, NT.p, k, k, ctx->d_sync, w.flags_node.p, ctx->d_err, st);
+  gmul(w, NT.p, X.p, pc->d_bpou.p, T1.p, st);
+  check_device_error(ctx);
+  pc->gen_cnt = sel;
+  pc->w_off.assign(N + 1, 0);
+  for (int j = 0; j < N; ++j) pc->w_off[j + 1] = pc->w_off[j] + (w.voff[j + 1] - w.voff[j]) * sel[j];
+  pc->d_W.alloc(std::max<int64_t>(pc->w_off[N], 1));
+  for (int j = 0; j < N; ++j)
+    if (sel[j])
+      HIP_CHECK(hipMemcpyAsync(pc->d_W.p + pc->w_off[j], T1.p + w.voff[j] * k,
+                               sizeof(double) * (w.voff[j + 1] - w.voff[j]) * sel[j], hipMemcpyDeviceToDevice, st));
+  std::vector<int64_t> goff(N + 1, 0);
+  for (int j = 0; j < N; ++j) goff[j + 1] = goff[j] + sel[j];
+  pc->d_gen_off.upload(goff, st);
+  pc->d_gen_cnt.upload(sel, st);
+  pc->d_w_off.upload(pc->w_off, st);
+  pc->d_voff.upload(w.voff, st);
+  pc->d_n.upload(nloc, st);
+  HIP_CHECK(hipStreamSynchronize(st));
 }
 
 }  // namespace geneo

@@ -167,7 +167,7 @@ __global__ void k_coarse_snk(int64_t nsnk, const int32_t* __restrict__ zc_ptr, c
   }
 }
 
-// E[:, gen] = Z^T Y and E[gen, snk] by symmetry, where Y = A Z_gen (global, n x ngen, column-major).
+// Lower triangle of the GenEO columns of E = Z^T Y, Y = A Z_gen (global, n x ngen, column-major).
 // One thread per (row c1 over all n0 columns, gen column g): rows c1 < nsnk use the sparse
 // SNK column, rows c1 >= nsnk the dense GenEO column Zg (global, n x ngen).
 __global__ void k_coarse_gen(int64_t n0, int64_t nsnk, int64_t ngen, int64_t n, const int32_t* __restrict__ zc_ptr,
@@ -186,8 +186,11 @@ __global__ void k_coarse_gen(int64_t n0, int64_t nsnk, int64_t ngen, int64_t n, 
     for (int64_t e = 0; e < n; ++e) acc += z[e] * y[e];
   }
   const int64_t cg = nsnk + g;
-  E[cg * ld + c1] = acc;   // column cg
-  E[c1 * ld + cg] = acc;   // row cg (symmetric)
+  // lower triangle only (the factorisation reads nothing else), one writer per entry
+  if (c1 < nsnk)
+    E[c1 * ld + cg] = acc;          // row cg > c1, column c1
+  else if (c1 >= cg)
+    E[cg * ld + c1] = acc;          // row c1, column cg
 }
 
 // ---------------------------------------------------------- dot products
@@ -271,7 +274,7 @@ void setup_precond(geneo_ctx* ctx, geneo_precond* pc) {
     const int64_t np = round_up(std::max<int64_t>(ni, 1), NB);
     descs[i] = MatDesc{off, inv_off, -1, voff, (int32_t)np, (int32_t)(np / NB), flag_off, (int32_t)ni};
     off += np * np;
-    inv_off += np * NB;
+    inv_off += 2 * np * NB;
     pc->voff[i] = voff;
     voff += np;
     flag_off += (int32_t)(np / NB);
@@ -457,7 +460,7 @@ void setup_precond(geneo_ctx* ctx, geneo_precond* pc) {
   std::vector<MatDesc> cd(1, MatDesc{0, 0, 0, 0, (int32_t)n0p, (int32_t)(n0p / NB), 0, (int32_t)n0});
   pc->coarse.build(cd, st);
   pc->dE.alloc(n0p * n0p);
-  pc->dEinv.alloc(n0p * NB);
+  pc->dEinv.alloc(2 * n0p * NB);
   pc->d_odiag.alloc(n0p);
   pc->d_pivrel.alloc(n0p);
   pc->d_flags_coarse.alloc(n0p / NB);
@@ -533,7 +536,16 @@ void setup_precond(geneo_ctx* ctx, geneo_precond* pc) {
 
 // ---------------------------------------------------------------- apply
 
+__global__ void k_fill(int64_t n, double v, double* __restrict__ x) {
+  int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i < n) x[i] = v;
+}
+
 static void coarse_solve(geneo_ctx* ctx, const geneo_precond* pc, double* c) {
+  // pad rows of the coarse vector carry no data: clear them so that nothing
+  // left there by an earlier call (e.g. a non-finite input) reaches the solve
+  const int64_t n0p = pc->coarse.h_desc[0].ld;
+  if (n0p > pc->n0) k_fill<<<nblocks(n0p - pc->n0), 256, 0, ctx->stream>>>(n0p - pc->n0, 0.0, c + pc->n0);
   solve(pc->coarse, pc->dE.p, pc->dEinv.p, c, ctx->d_sync, pc->d_flags_coarse.p, ctx->d_err, ctx->stream);
 }
 
@@ -618,8 +630,7 @@ __global__ void k_pcg_dir(int64_t n, double* __restrict__ p, const double* __res
                           int first) {
   int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (i >= n) return;
-  const double beta = first ? 0.0 : S[3] / S[0];
-  p[i] = z[i] + beta * p[i];
+  p[i] = first ? z[i] : z[i] + (S[3] / S[0]) * p[i];
 }
 __global__ void k_pcg_shift(double* S) { S[0] = S[3]; }
 
