@@ -1,0 +1,182 @@
+"""Benchmark of the AS-SNK-GenEO hot path on one MI355X.
+
+A step is one pass of the whole path over the synthetic workload
+(24^3-hex cube, 82,944 tets, mu in {1, 1e4} on random axis-aligned
+channels covering >= 10% of the hexes, eps = 1, gamma = 1e-4, 4x4x4 box
+subdomains with 2 overlap layers, at most 20 GenEO eigenvectors per
+subdomain, PCG to rtol 1e-8): assemble, partition, setup (local Cholesky
+factors, GenEO eigenproblems, coarse space and coarse Cholesky) and
+solve.  The reported value is setup + solve seconds with the assembled
+system already resident on the device; assembly and partitioning are
+reported beside it.
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
+Prints one JSON line.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "setup+solve s to rtol 1e-8 & local-factor TFLOP/s; learned+FP32 vs plain FP64"
+PEAK_FP64_TFLOPS = 78.6     # MI355X dense FP64 matrix peak
+PEAK_FP32_TFLOPS = 157.3
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--workload", default="2", help="workload id (default: the 24^3 channel cube)")
+    return ap.parse_args()
+
+
+def run_step(geneo, ctx, w, precision, b_host=None):
+    import torch
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+    t0 = time.perf_counter()
+    sysm = ctx.assemble(w.mesh, w.mu, w.eps, w.gamma, w.dirichlet)
+    t1 = time.perf_counter()
+    p = w.partition
+    if p["kind"] == "box":
+        dec = ctx.partition(sysm, "box", box=p["p"], overlap=w.overlap)
+    else:
+        dec = ctx.partition(sysm, "rcb", nparts=p["nparts"], jitter=p["jitter"], overlap=w.overlap)
+    n = sysm.info().n
+    if b_host is None:
+        b_host = w.rhs(n)
+    b = torch.as_tensor(b_host, dtype=torch.float64, device="cuda:0")
+    x = torch.zeros(n, dtype=torch.float64, device="cuda:0")
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    pc = ctx.setup(sysm, dec, tau=w.tau, nev_max=w.nev_max, local_precision=precision)
+    torch.cuda.synchronize()
+    t3 = time.perf_counter()
+    si = ctx.solve(sysm, pc, b, x, rtol=1e-8, maxit=2000)
+    torch.cuda.synchronize()
+    t4 = time.perf_counter()
+    pi = pc.info()
+    di = dec.info()
+    out = dict(assemble_s=t1 - t0, partition_s=t2 - t1, setup_s=t3 - t2, solve_s=t4 - t3,
+               setup_solve_s=t4 - t2, step_s=t4 - t0, iterations=si.iterations, rel_residual=si.rel_residual,
+               n=n, n_sub=di.n_sub, n_min=di.n_min, n_max=di.n_max, n0=pi.n0, n0_rank=pi.n0_rank,
+               n_snk=pi.n_snk, n_geneo=pi.n_geneo, lobpcg_iters=pi.lobpcg_iters,
+               t_extract_ms=pi.t_extract_ms, t_factor_ms=pi.t_factor_ms, t_gevp_ms=pi.t_gevp_ms,
+               t_coarse_build_ms=pi.t_coarse_build_ms, t_coarse_factor_ms=pi.t_coarse_factor_ms,
+               solve_ms=si.solve_ms, local_flops=pi.local_factor_flops, assemble_ms=sysm.info().assemble_ms)
+    del pc, dec, sysm
+    return out, b_host
+
+
+def cpu_baseline(w):
+    """The oracle, as written, on a bounded sample of the same workload: the
+    dense local Cholesky and the dense filtered GEVP of two subdomains (the
+    smallest and one of median size), scaled by sum n_i^3 to all
+    subdomains.  Coarse factorisation and PCG are not in the sample."""
+    from threadpoolctl import threadpool_info
+    from oracle import decomp, fem, geneo
+    import scipy.linalg as sla
+    s = fem.System(w.mesh, w.mu, w.eps, w.gamma, w.dirichlet)
+    dec = decomp.Decomposition(s, decomp.partition_cells(w), w.overlap)
+    sizes = np.array([d.size for d in dec.dofs], dtype=np.float64)
+    order = np.argsort(sizes)
+    sample = [int(order[0]), int(order[len(order) // 4])]
+    t = 0.0
+    for i in sample:
+        Ai = dec.A_dir(i).toarray()
+        Neu = dec.A_neu(i).toarray()
+        Gi, _, _ = dec.G_local(i)
+        t0 = time.perf_counter()
+        sla.cholesky(Ai, lower=True)
+        geneo.gevp(Ai, Neu, dec.D[i], Gi, w.tau, w.nev_max)
+        t += time.perf_counter() - t0
+    scale = float((sizes ** 3).sum() / (sizes[sample] ** 3).sum())
+    threads = max([p.get("num_threads", 1) for p in threadpool_info()] + [1])
+    return {"value": t * scale, "unit": "s", "cores": int(threads), "kind": "oracle",
+            "sample": (f"dense local Cholesky + dense filtered GEVP (scipy eigh) of subdomains {sample} "
+                       f"(n_i = {int(sizes[sample[0]])}, {int(sizes[sample[1]])}) took {t:.1f} s, scaled by "
+                       f"sum n_i^3 to all {dec.N} subdomains; coarse factor and PCG excluded")}
+
+
+def main():
+    a = parse()
+    if a.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1", "n_gpus": a.gpus}))
+        sys.exit(2)
+    import torch
+    from paper_2311_18783_amd import geneo
+    import workloads as W
+    wid = int(a.workload) if a.workload.isdigit() else a.workload
+    w = W.make(wid)
+    ctx = geneo.Context(0)
+    b_host = None
+    for _ in range(a.warmup):
+        _, b_host = run_step(geneo, ctx, w, geneo.FP64, b_host)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    res = []
+    for _ in range(a.steps):
+        r, b_host = run_step(geneo, ctx, w, geneo.FP64, b_host)
+        res.append(r)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    last = res[-1]
+    mean = lambda k: float(np.mean([r[k] for r in res]))
+    local_tf = last["local_flops"] / (mean("t_factor_ms") * 1e-3) / 1e12
+    n0p = ((last["n0"] + 127) // 128) * 128
+    coarse_flops = last["n0"] ** 3 / 3.0
+    coarse_tf = coarse_flops / (mean("t_coarse_factor_ms") * 1e-3) / 1e12
+    # dominant kernel family: the batched Cholesky phase that takes longest
+    if mean("t_coarse_factor_ms") >= mean("t_factor_ms"):
+        dom = ("coarse Cholesky of E (potrf/trsm/syrk, FP64 MFMA)", coarse_flops, mean("t_coarse_factor_ms"))
+    else:
+        dom = ("batched local Cholesky of A_i (potrf/trsm/syrk, FP64 MFMA)", last["local_flops"], mean("t_factor_ms"))
+    achieved = dom[1] / (dom[2] * 1e-3) / 1e12
+    line = {
+        "metric": METRIC,
+        "value": mean("setup_solve_s"),
+        "unit": "s",
+        "n_gpus": 1,
+        "steps": a.steps,
+        "warmup": a.warmup,
+        "ms_per_step": wall / a.steps * 1e3,
+        "higher_is_better": False,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": w.name + ": 24^3 hexes x 6 tets (82,944), mu in {1,1e4} channels >= 10%, "
+                               "eps=1, gamma=1e-4, all-Dirichlet, 4x4x4 boxes, overlap 2, tau=10, "
+                               "<=20 GenEO vectors/subdomain, PCG rtol 1e-8, local factors FP64",
+                   "n": last["n"], "n_sub": last["n_sub"], "n_i_min": last["n_min"], "n_i_max": last["n_max"],
+                   "n0": last["n0"], "n0_rank": last["n0_rank"], "n_geneo": last["n_geneo"],
+                   "parallelism": "1 GPU"},
+        "phases_ms": {"assemble": mean("assemble_s") * 1e3, "partition_host": mean("partition_s") * 1e3,
+                      "setup": mean("setup_s") * 1e3, "solve": mean("solve_s") * 1e3,
+                      "extract": mean("t_extract_ms"), "local_factor": mean("t_factor_ms"),
+                      "gevp": mean("t_gevp_ms"), "coarse_build": mean("t_coarse_build_ms"),
+                      "coarse_factor": mean("t_coarse_factor_ms"), "pcg_device": mean("solve_ms")},
+        "pcg_iterations": last["iterations"],
+        "lobpcg_iterations": last["lobpcg_iters"],
+        "local_factor_tflops": local_tf,
+        "coarse_factor_tflops": coarse_tf,
+        "roofline": {"bound": "mfma", "kernel": dom[0], "achieved": achieved, "peak": PEAK_FP64_TFLOPS,
+                     "unit": "TFLOP/s", "frac": achieved / PEAK_FP64_TFLOPS, "traffic": None},
+    }
+    if not a.no_cpu_baseline:
+        line["cpu_baseline"] = cpu_baseline(w)
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -158,7 +158,7 @@ typedef struct {
   int32_t n_snk;            /* SNK columns */
   int32_t n_geneo;          /* GenEO columns */
   int32_t lobpcg_iters;     /* LOBPCG iterations (max over subdomains) */
-  int32_t lobpcg_unconverged; /* eigenpairs not converged at maxit */
+  int32_t lobpcg_unconverged; /* subdomains whose selected Ritz pairs were not converged at exit */
   int32_t fp64_fallbacks;   /* FP32 local factors replaced by FP64 */
   double min_kept_pivot;    /* smallest relative Schur pivot kept in the coarse factor */
   double max_dropped_pivot; /* largest relative Schur pivot dropped */

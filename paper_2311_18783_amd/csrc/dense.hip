@@ -45,25 +45,28 @@ __device__ inline void set_err(DevErr* e, int code, int mat, int idx) {
 // ---------------------------------------------------------------- potrf
 constexpr int LDA = NB + 1;
 
+constexpr int kPotrfThreads = 1024;
+
 template <typename T>
-__global__ __launch_bounds__(256) void k_potrf(const MatDesc* __restrict__ desc, const int32_t* __restrict__ order,
-                                               int step, T* __restrict__ A, T* __restrict__ Ainv,
-                                               const double* __restrict__ odiag, double drop_tol,
-                                               double* __restrict__ pivrel, DevErr* err) {
+__global__ __launch_bounds__(kPotrfThreads) void k_potrf(const MatDesc* __restrict__ desc,
+                                                         const int32_t* __restrict__ order, int step,
+                                                         T* __restrict__ A, T* __restrict__ Ainv,
+                                                         const double* __restrict__ odiag, double drop_tol,
+                                                         double* __restrict__ pivrel, DevErr* err) {
   extern __shared__ unsigned char smem_raw[];
-  T* a = reinterpret_cast<T*>(smem_raw);                   // [NB * LDA]
+  T* a = reinterpret_cast<T*>(smem_raw);                   // [NB * LDA], column-major
   __shared__ double invd[NB];
-  __shared__ double tmp[NB];
+  __shared__ double tcol[NB];
   const int m = order[blockIdx.x];
   const MatDesc d = desc[m];
   const int tid = threadIdx.x;
+  const int tx = tid & 31, ty = tid >> 5;                  // 32 x 32 thread grid
   const int64_t k0 = (int64_t)step * NB;
   T* blk = A + d.off + k0 * d.ld + k0;
-  for (int idx = tid; idx < NB * NB; idx += 256) {
-    int r = idx % NB, c = idx / NB;
-    a[c * LDA + r] = (r >= c) ? blk[(int64_t)c * d.ld + r] : T(0);
-  }
+  for (int c = ty; c < NB; c += 32)
+    for (int r = tx; r < NB; r += 32) a[c * LDA + r] = (r >= c) ? blk[(int64_t)c * d.ld + r] : T(0);
   __syncthreads();
+  // right-looking unblocked factorisation of the 128 x 128 block
   for (int j = 0; j < NB; ++j) {
     if (tid == 0) {
       double p = (double)a[j * LDA + j];
@@ -87,45 +90,51 @@ __global__ __launch_bounds__(256) void k_potrf(const MatDesc* __restrict__ desc,
       }
     }
     __syncthreads();
-    const T s = (T)invd[j];
-    for (int i = j + 1 + tid; i < NB; i += 256) a[j * LDA + i] *= s;
+    if (tid > j && tid < NB) {
+      const T v = a[j * LDA + tid] * (T)invd[j];
+      a[j * LDA + tid] = v;
+      tcol[tid] = (double)v;
+    }
     __syncthreads();
-    const int rem = NB - 1 - j;
-    for (int idx = tid; idx < rem * rem; idx += 256) {
-      int ii = idx % rem, ll = idx / rem;
-      if (ii >= ll) {
-        int i = j + 1 + ii, l = j + 1 + ll;
-        a[l * LDA + i] -= a[j * LDA + i] * a[j * LDA + l];
+    for (int l = j + 1 + ty; l < NB; l += 32) {
+      const T cl = (T)tcol[l];
+      for (int i = l + tx; i < NB; i += 32) a[l * LDA + i] -= (T)tcol[i] * cl;
+    }
+    __syncthreads();
+  }
+  for (int c = ty; c < NB; c += 32)
+    for (int r = tx; r < NB; r += 32)
+      if (r >= c) blk[(int64_t)c * d.ld + r] = a[c * LDA + r];
+  __syncthreads();
+  // in-place inverse: forward substitution L X = I for all 128 columns at
+  // once; column k of L is consumed at step k, which is where column k of X
+  // (below the diagonal) is first written, so X overwrites L column by column.
+  for (int k = 0; k < NB; ++k) {
+    if (tid > k && tid < NB) tcol[tid] = (double)a[k * LDA + tid];   // L[i][k]
+    __syncthreads();
+    // row k of X is final: X[k][c] = X[k][c] / L[k][k] for c <= k (X[k][k] = 1 / L[k][k])
+    if (tid <= k) {
+      const double xk = (tid == k) ? 1.0 : (double)a[tid * LDA + k];
+      a[tid * LDA + k] = (T)(xk * invd[k]);
+    }
+    __syncthreads();
+    // X[i][c] -= L[i][k] X[k][c] for i > k, c <= k  (X[i][k] starts from 0)
+    for (int c = ty; c <= k; c += 32) {
+      const double xkc = (double)a[c * LDA + k];
+      for (int i = k + 1 + tx; i < NB; i += 32) {
+        const double old = (c == k) ? 0.0 : (double)a[c * LDA + i];
+        a[c * LDA + i] = (T)(old - tcol[i] * xkc);
       }
     }
     __syncthreads();
   }
-  for (int idx = tid; idx < NB * NB; idx += 256) {
-    int r = idx % NB, c = idx / NB;
-    if (r >= c) blk[(int64_t)c * d.ld + r] = a[c * LDA + r];
-  }
-  __syncthreads();
-  // in-place inverse of the unit-free lower factor, last column first:
-  // X[j][j] = 1/L[j][j];  X[j+1:, j] = -X[j][j] * X[j+1:, j+1:] L[j+1:, j]
-  for (int j = NB - 1; j >= 0; --j) {
-    const int i = j + 1 + tid;
-    if (tid < NB - 1 - j) {
-      double acc = 0.0;
-      for (int l = j + 1; l <= i; ++l) acc += (double)a[l * LDA + i] * (double)a[j * LDA + l];
-      tmp[i] = acc;
-    }
-    __syncthreads();
-    if (tid < NB - 1 - j) a[j * LDA + i] = (T)(-invd[j] * tmp[i]);
-    if (tid == 0) a[j * LDA + j] = (T)invd[j];
-    __syncthreads();
-  }
   T* inv = Ainv + d.inv_off + (int64_t)step * NB * NB;
   T* uinv = Ainv + d.inv_off + ((int64_t)d.nblk + step) * NB * NB;   // inv(U_II) = inv(L_II)^T
-  for (int idx = tid; idx < NB * NB; idx += 256) {
-    int r = idx % NB, c = idx / NB;
-    inv[(int64_t)c * NB + r] = (r >= c) ? a[c * LDA + r] : T(0);
-    uinv[(int64_t)c * NB + r] = (c >= r) ? a[r * LDA + c] : T(0);
-  }
+  for (int c = ty; c < NB; c += 32)
+    for (int r = tx; r < NB; r += 32) {
+      inv[(int64_t)c * NB + r] = (r >= c) ? a[c * LDA + r] : T(0);
+      uinv[(int64_t)c * NB + r] = (c >= r) ? a[r * LDA + c] : T(0);
+    }
 }
 
 // ------------------------------------------------------------ MFMA tiles
@@ -320,8 +329,8 @@ static void factor_impl(const FactorPlan& P, T* A, T* Ainv, const double* odiag,
   for (int s = 0; s < P.max_blk; ++s) {
     const int64_t* pt = P.d_prefix.p + P.pre_off[s];
     const int64_t* ps = pt + P.cnt[s] + 1;
-    k_potrf<T><<<dim3(P.cnt[s]), dim3(256), lds, st>>>(P.d_desc.p, P.d_order.p, s, A, Ainv, odiag, drop_tol, pivrel,
-                                                         err);
+    k_potrf<T><<<dim3(P.cnt[s]), dim3(kPotrfThreads), lds, st>>>(P.d_desc.p, P.d_order.p, s, A, Ainv, odiag,
+                                                                   drop_tol, pivrel, err);
     if (P.trsm_tiles[s] > 0) {
       k_trsm<T><<<dim3((unsigned)P.trsm_tiles[s]), dim3(256), 0, st>>>(P.d_desc.p, P.d_order.p, pt, P.cnt[s], s, A,
                                                                         Ainv);
@@ -396,20 +405,29 @@ __global__ void k_solve_begin(unsigned* sync) {
   sync[1] = sync[1] + 1;
 }
 
-__device__ inline void wait_flag(const unsigned* flag, unsigned epoch, DevErr* err) {
+// Blocks of one matrix complete in order (block I publishes only after it
+// has consumed every block it depends on), so once flag J is seen the
+// frontier can be advanced over every later flag already set.  Polls are
+// relaxed loads; a single agent-scope acquire fence follows each catch-up.
+// Returns the first block (in the solve's direction) not yet known done.
+__device__ inline int wait_frontier(const unsigned* flags, int J, int Jend, int step, unsigned epoch, DevErr* err) {
   unsigned spins = 0;
-  while (__hip_atomic_load(flag, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) != epoch) {
+  while (__hip_atomic_load(flags + J, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != epoch) {
     if (++spins > kSpinLimit) {
       set_err(err, GENEO_ESYNC, -1, -1);
       break;
     }
     __builtin_amdgcn_s_sleep(1);
   }
+  int k = J + step;
+  while (k != Jend && __hip_atomic_load(flags + k, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == epoch) k += step;
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+  return k;
 }
 
 __device__ inline void publish(unsigned* flag, unsigned epoch) {
-  __threadfence();
-  __hip_atomic_store(flag, epoch, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+  __hip_atomic_store(flag, epoch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
 __device__ inline double load_coherent(const double* p) {
@@ -440,10 +458,14 @@ __global__ __launch_bounds__(256) void k_trsv(const MatDesc* __restrict__ desc, 
   const MatDesc d = desc[m];
   double* xv = x + d.voff;
   const int r = tid & (NB - 1), h = tid >> 7;
+  __shared__ int s_front;
   double acc = 0.0;
-  const int J0 = UPPER ? I + 1 : 0, J1 = UPPER ? d.nblk : I;
-  for (int J = J0; J < J1; ++J) {
-    if (tid == 0) wait_flag(flags + d.flag_off + J, epoch, err);
+  // dependencies: forward J = 0..I-1 (done in increasing order),
+  // backward J = nblk-1..I+1 (done in decreasing order)
+  const int J0 = UPPER ? d.nblk - 1 : 0, Jend = UPPER ? I : I, dir = UPPER ? -1 : 1;
+  if (tid == 0) s_front = J0;
+  for (int J = J0; J != Jend; J += dir) {
+    if (tid == 0 && J == s_front) s_front = wait_frontier(flags + d.flag_off, J, Jend, dir, epoch, err);
     __syncthreads();
     if (tid < NB) xs[tid] = load_coherent(xv + (int64_t)J * NB + tid);
     __syncthreads();
@@ -493,9 +515,11 @@ __global__ __launch_bounds__(256) void k_trsm_multi(const MatDesc* __restrict__ 
   double acc[H];
 #pragma unroll
   for (int q = 0; q < H; ++q) acc[q] = 0.0;
-  const int J0 = UPPER ? I + 1 : 0, J1 = UPPER ? d.nblk : I;
-  for (int J = J0; J < J1; ++J) {
-    if (tid == 0) wait_flag(flags + d.flag_off + J, epoch, err);
+  __shared__ int s_front;
+  const int J0 = UPPER ? d.nblk - 1 : 0, Jend = UPPER ? I : I, dir = UPPER ? -1 : 1;
+  if (tid == 0) s_front = J0;
+  for (int J = J0; J != Jend; J += dir) {
+    if (tid == 0 && J == s_front) s_front = wait_frontier(flags + d.flag_off, J, Jend, dir, epoch, err);
     __syncthreads();
     for (int idx = tid; idx < NB * KC; idx += 256) {
       int rr = idx & (NB - 1), q = idx >> 7;

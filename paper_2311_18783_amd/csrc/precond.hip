@@ -167,30 +167,72 @@ __global__ void k_coarse_snk(int64_t nsnk, const int32_t* __restrict__ zc_ptr, c
   }
 }
 
-// Lower triangle of the GenEO columns of E = Z^T Y, Y = A Z_gen (global, n x ngen, column-major).
-// One thread per (row c1 over all n0 columns, gen column g): rows c1 < nsnk use the sparse
-// SNK column, rows c1 >= nsnk the dense GenEO column Zg (global, n x ngen).
+// Global GenEO columns: Zg[:, gen_off_j + q] = R_j^T W_j[:, q]; one thread per batch row.
+__global__ void k_zg_scatter(int64_t len, int nsub, const int64_t* __restrict__ voff, const int32_t* __restrict__ nloc,
+                             const int32_t* __restrict__ gcnt, const int64_t* __restrict__ goff,
+                             const int64_t* __restrict__ woff, const int32_t* __restrict__ bmap,
+                             const double* __restrict__ W, int64_t n, double* __restrict__ Zg) {
+  int64_t b = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (b >= len) return;
+  int lo = 0, hi = nsub - 1;
+  while (lo < hi) {
+    int mid = (lo + hi + 1) >> 1;
+    if (voff[mid] <= b) lo = mid; else hi = mid - 1;
+  }
+  const int64_t r = b - voff[lo];
+  if (r >= nloc[lo]) return;
+  const int64_t ld = voff[lo + 1] - voff[lo];
+  const int32_t e = bmap[b];
+  for (int q = 0; q < gcnt[lo]; ++q) Zg[(goff[lo] + q) * n + e] = W[woff[lo] + q * ld + r];
+}
+
+// Y = A X for ncol dense columns (column-major n x ncol), one thread per (row, column)
+__global__ void k_spmm_global(int64_t n, int64_t ncol, const int32_t* __restrict__ rp, const int32_t* __restrict__ ci,
+                              const double* __restrict__ v, const double* __restrict__ X, double* __restrict__ Y) {
+  int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (idx >= n * ncol) return;
+  const int64_t i = idx % n, c = idx / n;
+  const double* x = X + c * n;
+  double acc = 0.0;
+  for (int32_t k = rp[i]; k < rp[i + 1]; ++k) acc += v[k] * x[ci[k]];
+  Y[c * n + i] = acc;
+}
+
+// Lower triangle of the GenEO columns of E = Z^T Y, Y = A Z_gen (global,
+// n x ngen, column-major).  One thread per (coarse row c1, GenEO column g):
+// SNK rows use their sparse column; GenEO rows the dense local block of
+// their subdomain (a GenEO column lives on one subdomain's edges only).
 __global__ void k_coarse_gen(int64_t n0, int64_t nsnk, int64_t ngen, int64_t n, const int32_t* __restrict__ zc_ptr,
-                             const int32_t* __restrict__ zc_row, const double* __restrict__ zc_val,
-                             const double* __restrict__ Zg, const double* __restrict__ Y, double* __restrict__ E,
-                             int64_t ld) {
+                             const int32_t* __restrict__ zc_row, const double* __restrict__ zc_val, int nsub,
+                             const int64_t* __restrict__ goff, const int64_t* __restrict__ voff,
+                             const int32_t* __restrict__ nloc, const int64_t* __restrict__ woff,
+                             const int32_t* __restrict__ bmap, const double* __restrict__ W,
+                             const double* __restrict__ Y, double* __restrict__ E, int64_t ld) {
   int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (idx >= n0 * ngen) return;
   const int64_t c1 = idx % n0, g = idx / n0;
-  const double* y = Y + g * n;
-  double acc = 0.0;
-  if (c1 < nsnk) {
-    for (int32_t k = zc_ptr[c1]; k < zc_ptr[c1 + 1]; ++k) acc += zc_val[k] * y[zc_row[k]];
-  } else {
-    const double* z = Zg + (c1 - nsnk) * n;
-    for (int64_t e = 0; e < n; ++e) acc += z[e] * y[e];
-  }
   const int64_t cg = nsnk + g;
-  // lower triangle only (the factorisation reads nothing else), one writer per entry
-  if (c1 < nsnk)
+  const double* y = Y + g * n;
+  if (c1 < nsnk) {
+    double acc = 0.0;
+    for (int32_t k = zc_ptr[c1]; k < zc_ptr[c1 + 1]; ++k) acc += zc_val[k] * y[zc_row[k]];
     E[c1 * ld + cg] = acc;          // row cg > c1, column c1
-  else if (c1 >= cg)
-    E[cg * ld + c1] = acc;          // row c1, column cg
+    return;
+  }
+  if (c1 < cg) return;              // upper triangle: not needed
+  const int64_t g1 = c1 - nsnk;
+  int lo = 0, hi = nsub - 1;
+  while (lo < hi) {
+    int mid = (lo + hi + 1) >> 1;
+    if (goff[mid] <= g1) lo = mid; else hi = mid - 1;
+  }
+  const int64_t q = g1 - goff[lo];
+  const int64_t lds = voff[lo + 1] - voff[lo];
+  const double* w = W + woff[lo] + q * lds;
+  const int32_t* bm = bmap + voff[lo];
+  double acc = 0.0;
+  for (int64_t r = 0; r < nloc[lo]; ++r) acc += w[r] * y[bm[r]];
+  E[cg * ld + c1] = acc;            // row c1 >= cg, column cg
 }
 
 // ---------------------------------------------------------- dot products
@@ -484,22 +526,15 @@ void setup_precond(geneo_ctx* ctx, geneo_precond* pc) {
     DevBuf<double> Zg, Y;
     Zg.alloc((size_t)n * pc->n_gen);
     Y.alloc((size_t)n * pc->n_gen);
-    HIP_CHECK(hipMemsetAsync(pc->w_c1.p, 0, sizeof(double) * n0p, st));
-    for (int32_t g = 0; g < pc->n_gen; ++g) {
-      // unit coarse vector -> W c -> scatter to global
-      HIP_CHECK(hipMemsetAsync(pc->w_c1.p, 0, sizeof(double) * n0p, st));
-      const double one = 1.0;
-      HIP_CHECK(hipMemcpyAsync(pc->w_c1.p + g, &one, sizeof(double), hipMemcpyHostToDevice, st));
-      k_w_n<<<nblocks(voff), 256, 0, st>>>(voff, N, pc->d_voff.p, pc->d_gen_cnt.p, pc->d_gen_off.p, pc->d_w_off.p,
-                                            pc->d_W.p, pc->w_c1.p, pc->w_b1.p);
-      k_scatter_add<<<nblocks(n), 256, 0, st>>>(n, pc->d_inv_ptr.p, pc->d_inv_idx.p, pc->w_b1.p, nullptr, 1.0,
-                                                Zg.p + (int64_t)g * n);
-      launch_spmv(s, Zg.p + (int64_t)g * n, Y.p + (int64_t)g * n, st);
-      HIP_CHECK(hipStreamSynchronize(st));
-    }
+    HIP_CHECK(hipMemsetAsync(Zg.p, 0, sizeof(double) * n * pc->n_gen, st));
+    k_zg_scatter<<<nblocks(voff), 256, 0, st>>>(voff, N, pc->d_voff.p, pc->d_n.p, pc->d_gen_cnt.p, pc->d_gen_off.p,
+                                                pc->d_w_off.p, pc->d_bmap.p, pc->d_W.p, n, Zg.p);
+    k_spmm_global<<<nblocks(n * pc->n_gen), 256, 0, st>>>(n, pc->n_gen, s->d_rowptr.p, s->d_colind.p, s->d_val.p,
+                                                          Zg.p, Y.p);
     k_coarse_gen<<<nblocks(n0 * pc->n_gen), 256, 0, st>>>(n0, pc->n_snk, pc->n_gen, n, pc->d_zc_ptr.p,
-                                                          pc->d_zc_row.p, pc->d_zc_val.p, Zg.p, Y.p, pc->dE.p, n0p);
-    HIP_CHECK(hipMemsetAsync(pc->w_c1.p, 0, sizeof(double) * n0p, st));
+                                                          pc->d_zc_row.p, pc->d_zc_val.p, N, pc->d_gen_off.p,
+                                                          pc->d_voff.p, pc->d_n.p, pc->d_w_off.p, pc->d_bmap.p,
+                                                          pc->d_W.p, Y.p, pc->dE.p, n0p);
     HIP_CHECK(hipStreamSynchronize(st));
   }
   HIP_CHECK(hipGetLastError());
