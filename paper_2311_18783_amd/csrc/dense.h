@@ -16,6 +16,11 @@ struct MatDesc {
   int32_t n;         // true size
 };
 
+struct SyrkLaunch {
+  int64_t pre_off, tiles;   // prefix array offset (nmat+1 entries), total tiles
+  int kcol0, kb, b0, ncols; // panel group columns, first trailing block, column limit (0 = all)
+};
+
 struct FactorPlan {
   int nmat = 0, max_blk = 0;
   std::vector<MatDesc> h_desc;
@@ -23,6 +28,9 @@ struct FactorPlan {
   std::vector<int64_t> trsm_tiles, syrk_tiles, pre_off;
   int64_t n_items = 0;               // triangular-solve work items (blocks)
   int64_t mirror_tiles = 0;          // strictly-lower 128x128 blocks
+  int group = 8;                     // panels per trailing update
+  std::vector<SyrkLaunch> syrk;      // trailing-update launches in execution order
+  DevBuf<int64_t> d_syrk_prefix;
   DevBuf<int64_t> d_mirror_prefix;
   DevBuf<MatDesc> d_desc;
   DevBuf<int32_t> d_order;

@@ -20,6 +20,8 @@
 // unit diagonal, a zero column, and zero row and column in the block
 // inverse, so every solve returns 0 in that position.
 #include <algorithm>
+#include <cstdlib>
+#include <string>
 
 #include "dense.h"
 
@@ -45,7 +47,15 @@ __device__ inline void set_err(DevErr* e, int code, int mat, int idx) {
 // ---------------------------------------------------------------- potrf
 constexpr int LDA = NB + 1;
 
+// The diagonal block is factored and inverted with its elements held in
+// registers: each thread owns one row i and the 16 columns c = h + 8q of one
+// column phase h (q = 0..15).  Column j of the Schur complement travels
+// through a double-buffered LDS vector, so every column step costs one
+// barrier; chunks of columns and waves of rows that have left the active
+// trailing triangle skip their work.  This step is sequential (the rest of
+// the panel step waits on it), so its latency, not its flop rate, matters.
 constexpr int kPotrfThreads = 1024;
+constexpr int kPotrfCols = NB * NB / kPotrfThreads;   // 16 register columns per thread
 
 template <typename T>
 __global__ __launch_bounds__(kPotrfThreads) void k_potrf(const MatDesc* __restrict__ desc,
@@ -54,107 +64,173 @@ __global__ __launch_bounds__(kPotrfThreads) void k_potrf(const MatDesc* __restri
                                                          const double* __restrict__ odiag, double drop_tol,
                                                          double* __restrict__ pivrel, DevErr* err) {
   extern __shared__ unsigned char smem_raw[];
-  T* a = reinterpret_cast<T*>(smem_raw);                   // [NB * LDA], column-major
-  __shared__ double invd[NB];
-  __shared__ double tcol[NB];
+  T* Ls = reinterpret_cast<T*>(smem_raw);   // [NB * LDA] column-major: L, later X = inv(L)
+  __shared__ double colbuf[2][NB];          // current Schur column (unscaled)
+  __shared__ double xrow[2][NB];            // finished row of X
+  __shared__ double invd[NB];               // 1 / L[j][j], 0 for a dropped or failed pivot
+  __shared__ double od[NB];                 // original diagonal (drop rule)
+  constexpr int H = kPotrfThreads / NB;     // column phases (8)
   const int m = order[blockIdx.x];
   const MatDesc d = desc[m];
-  const int tid = threadIdx.x;
-  const int tx = tid & 31, ty = tid >> 5;                  // 32 x 32 thread grid
+  const int t = threadIdx.x;
+  // wave w holds rows 64 rh .. 64 rh + 63 for column phase h; rh alternates
+  // with w / 4 so that the waves of each SIMD (w mod 4) cover both row halves
+  const int w = t >> 6;
+  const int rh = (w >> 2) & 1;
+  const int h = (w & 3) + 4 * (w >> 3);
+  const int i = 64 * rh + (t & 63);
+  const int wave_row_max = (i | 63);
   const int64_t k0 = (int64_t)step * NB;
   T* blk = A + d.off + k0 * d.ld + k0;
-  for (int c = ty; c < NB; c += 32)
-    for (int r = tx; r < NB; r += 32) a[c * LDA + r] = (r >= c) ? blk[(int64_t)c * d.ld + r] : T(0);
+  const bool use_drop = drop_tol > 0.0;
+  const bool have_od = odiag && d.diag_off >= 0;
+  T a[kPotrfCols];
+#pragma unroll
+  for (int q = 0; q < kPotrfCols; ++q) {
+    const int c = h + H * q;
+    a[q] = (i >= c) ? blk[(int64_t)c * d.ld + i] : T(0);
+  }
+  if (h == 0) {
+    colbuf[0][i] = (double)a[0];
+    od[i] = have_od ? odiag[d.diag_off + k0 + i] : 0.0;
+  }
   __syncthreads();
-  // right-looking unblocked factorisation of the 128 x 128 block
+  // ---- factorisation, column by column
   for (int j = 0; j < NB; ++j) {
-    if (tid == 0) {
-      double p = (double)a[j * LDA + j];
-      double od = (odiag && d.diag_off >= 0) ? odiag[d.diag_off + k0 + j] : 0.0;
-      bool drop = false;
-      if (drop_tol > 0.0) {
-        drop = !(p > drop_tol * od) || !(od > 0.0);
-        if (pivrel && d.diag_off >= 0) pivrel[d.diag_off + k0 + j] = od > 0.0 ? p / od : 0.0;
-      }
-      if (drop) {
-        a[j * LDA + j] = T(1);
-        invd[j] = 0.0;
-      } else if (!(p > 0.0)) {
-        set_err(err, GENEO_ENOTSPD, m, (int)(k0 + j));
-        a[j * LDA + j] = T(1);
-        invd[j] = 0.0;
-      } else {
-        double sq = sqrt(p);
-        a[j * LDA + j] = (T)sq;
-        invd[j] = 1.0 / sq;
-      }
+    const double* buf = colbuf[j & 1];
+    const double p = buf[j];
+    const double o = od[j];
+    bool fail = false, drop = false;
+    if (use_drop) drop = !(p > drop_tol * o) || !(o > 0.0);
+    if (!drop && !(p > 0.0)) fail = true;
+    const double sq = (drop || fail) ? 1.0 : sqrt(p);
+    const double s = (drop || fail) ? 0.0 : 1.0 / sq;
+    if (t == 0) {
+      if (use_drop && pivrel && d.diag_off >= 0) pivrel[d.diag_off + k0 + j] = o > 0.0 ? p / o : 0.0;
+      if (fail) set_err(err, GENEO_ENOTSPD, m, (int)(k0 + j));
+      invd[j] = s;
     }
-    __syncthreads();
-    if (tid > j && tid < NB) {
-      const T v = a[j * LDA + tid] * (T)invd[j];
-      a[j * LDA + tid] = v;
-      tcol[tid] = (double)v;
-    }
-    __syncthreads();
-    for (int l = j + 1 + ty; l < NB; l += 32) {
-      const T cl = (T)tcol[l];
-      for (int i = l + tx; i < NB; i += 32) a[l * LDA + i] -= (T)tcol[i] * cl;
+    if (wave_row_max >= j) {
+      const T li = (i > j) ? (T)(buf[i] * s) : T(0);
+      T nxt = T(0);
+#pragma unroll
+      for (int g = 0; g < kPotrfCols / 4; ++g) {
+        if (32 * g + 31 >= j) {
+#pragma unroll
+          for (int e = 0; e < 4; ++e) {
+            const int q = 4 * g + e;
+            const int c = h + H * q;
+            T v = a[q];
+            if (c == j) {
+              v = (i == j) ? (T)sq : li;
+            } else if (c > j && i >= c) {
+              v -= li * (T)(buf[c] * s);
+            }
+            a[q] = v;
+            if (c == j + 1) nxt = v;
+          }
+        }
+      }
+      if (j + 1 < NB && h == ((j + 1) & (H - 1)) && i >= j + 1) colbuf[(j + 1) & 1][i] = (double)nxt;
     }
     __syncthreads();
   }
-  for (int c = ty; c < NB; c += 32)
-    for (int r = tx; r < NB; r += 32)
-      if (r >= c) blk[(int64_t)c * d.ld + r] = a[c * LDA + r];
+  // L back to the matrix (lower part of the block) and into LDS
+#pragma unroll
+  for (int q = 0; q < kPotrfCols; ++q) {
+    const int c = h + H * q;
+    if (i >= c) blk[(int64_t)c * d.ld + i] = a[q];
+    Ls[c * LDA + i] = a[q];
+    a[q] = T(0);
+  }
   __syncthreads();
-  // in-place inverse: forward substitution L X = I for all 128 columns at
-  // once; column k of L is consumed at step k, which is where column k of X
-  // (below the diagonal) is first written, so X overwrites L column by column.
+  // ---- X = inv(L) by forward substitution L X = I, one row of X per step:
+  // row k is final once the updates of steps < k are in; it is scaled by
+  // 1 / L[k][k] and broadcast, then rows i > k take X[i][c] -= L[i][k] X[k][c].
   for (int k = 0; k < NB; ++k) {
-    if (tid > k && tid < NB) tcol[tid] = (double)a[k * LDA + tid];   // L[i][k]
-    __syncthreads();
-    // row k of X is final: X[k][c] = X[k][c] / L[k][k] for c <= k (X[k][k] = 1 / L[k][k])
-    if (tid <= k) {
-      const double xk = (tid == k) ? 1.0 : (double)a[tid * LDA + k];
-      a[tid * LDA + k] = (T)(xk * invd[k]);
-    }
-    __syncthreads();
-    // X[i][c] -= L[i][k] X[k][c] for i > k, c <= k  (X[i][k] starts from 0)
-    for (int c = ty; c <= k; c += 32) {
-      const double xkc = (double)a[c * LDA + k];
-      for (int i = k + 1 + tx; i < NB; i += 32) {
-        const double old = (c == k) ? 0.0 : (double)a[c * LDA + i];
-        a[c * LDA + i] = (T)(old - tcol[i] * xkc);
+    double* xr = xrow[k & 1];
+    if (i == k) {
+      const double dk = invd[k];
+#pragma unroll
+      for (int q = 0; q < kPotrfCols; ++q) {
+        const int c = h + H * q;
+        if (c <= k) {
+          const T x = (c == k) ? (T)dk : (T)((double)a[q] * dk);
+          a[q] = x;
+          xr[c] = (double)x;
+        }
       }
     }
     __syncthreads();
+    if (wave_row_max > k) {
+      const T lik = (i > k) ? Ls[k * LDA + i] : T(0);
+#pragma unroll
+      for (int g = 0; g < kPotrfCols / 4; ++g) {
+        if (32 * g <= k) {
+#pragma unroll
+          for (int e = 0; e < 4; ++e) {
+            const int q = 4 * g + e;
+            const int c = h + H * q;
+            if (c <= k && i > k) a[q] -= lik * (T)xr[c];
+          }
+        }
+      }
+    }
   }
   T* inv = Ainv + d.inv_off + (int64_t)step * NB * NB;
   T* uinv = Ainv + d.inv_off + ((int64_t)d.nblk + step) * NB * NB;   // inv(U_II) = inv(L_II)^T
-  for (int c = ty; c < NB; c += 32)
-    for (int r = tx; r < NB; r += 32) {
-      inv[(int64_t)c * NB + r] = (r >= c) ? a[c * LDA + r] : T(0);
-      uinv[(int64_t)c * NB + r] = (c >= r) ? a[r * LDA + c] : T(0);
-    }
+#pragma unroll
+  for (int q = 0; q < kPotrfCols; ++q) {
+    const int c = h + H * q;
+    inv[(int64_t)c * NB + i] = (i >= c) ? a[q] : T(0);
+  }
+  __syncthreads();   // every read of L in LDS is done
+#pragma unroll
+  for (int q = 0; q < kPotrfCols; ++q) {
+    const int c = h + H * q;
+    Ls[c * LDA + i] = (i >= c) ? a[q] : T(0);
+  }
+  __syncthreads();
+  // uinv[c][r] (column-major) = X[c][r]: lanes over r for coalesced stores
+#pragma unroll
+  for (int q = 0; q < kPotrfCols; ++q) {
+    const int c = h + H * q;
+    uinv[(int64_t)c * NB + i] = Ls[i * LDA + c];
+  }
 }
 
 // ------------------------------------------------------------ MFMA tiles
-// C[64x64 per wave] (+)= sum_k Arow[r][k] * Brow[c][k] over k in [0, 128),
-// Arow/Brow column-major with leading dimensions lda/ldb.  Lane l of a
+// A workgroup owns a 128 x 128 output tile C and accumulates
+//   C (+)= sum_k Arow[r][k] * Brow[c][k]
+// with Arow/Brow column-major (leading dimensions lda/ldb).  Lane l of a
 // 16x16x4 MFMA supplies A[l%16][l/16] and B[l/16][l%16]; it receives
 // D[4*(l/16)+v][l%16] (FP32) or D[(l/16)+4*v][l%16] (FP64), v = 0..3.
-template <typename T>
-__device__ inline void tile_mma(const T* __restrict__ Ar, int64_t lda, const T* __restrict__ Br, int64_t ldb,
-                                typename AccT<T>::type acc[4][4], bool negate) {
+//
+// Tile modes: 0 = 4 waves of 64 x 64, operands straight from L2/HBM;
+// 1 = 8 waves of 64 x 32 (half the accumulators per wave, two workgroups
+// per CU to hide load latency); 2 = 4 waves, operands staged through LDS.
+template <int MODE> struct TileGeo {
+  static constexpr int WAVES = MODE == 1 ? 8 : 4;
+  static constexpr int BJ = MODE == 1 ? 2 : 4;    // 16-column blocks per wave
+  static constexpr int WCOL = 16 * BJ;            // columns per wave
+  __device__ static int wr() { return (threadIdx.x >> 6) & 1; }
+  __device__ static int wc() { return (threadIdx.x >> 6) >> 1; }
+};
+
+template <typename T, int MODE>
+__device__ inline void tile_mma_direct(const T* __restrict__ Ar, int64_t lda, const T* __restrict__ Br, int64_t ldb,
+                                       typename AccT<T>::type acc[4][TileGeo<MODE>::BJ], bool negate, int K) {
+  constexpr int BJ = TileGeo<MODE>::BJ;
   const int lane = threadIdx.x & 63;
   const int lr = lane & 15, lk = lane >> 4;
-#pragma unroll 2
-  for (int kk = 0; kk < NB; kk += 4) {
-    T af[4], bf[4];
+  Ar += 64 * TileGeo<MODE>::wr();
+  Br += TileGeo<MODE>::WCOL * TileGeo<MODE>::wc();
+  for (int kk = 0; kk < K; kk += 4) {
+    T af[4], bf[BJ];
 #pragma unroll
-    for (int b = 0; b < 4; ++b) {
-      af[b] = Ar[(int64_t)(kk + lk) * lda + 16 * b + lr];
-      bf[b] = Br[(int64_t)(kk + lk) * ldb + 16 * b + lr];
-    }
+    for (int b = 0; b < 4; ++b) af[b] = Ar[(int64_t)(kk + lk) * lda + 16 * b + lr];
+#pragma unroll
+    for (int b = 0; b < BJ; ++b) bf[b] = Br[(int64_t)(kk + lk) * ldb + 16 * b + lr];
     if (negate) {
 #pragma unroll
       for (int b = 0; b < 4; ++b) af[b] = -af[b];
@@ -162,7 +238,80 @@ __device__ inline void tile_mma(const T* __restrict__ Ar, int64_t lda, const T* 
 #pragma unroll
     for (int bi = 0; bi < 4; ++bi)
 #pragma unroll
-      for (int bj = 0; bj < 4; ++bj) acc[bi][bj] = mfma16(af[bi], bf[bj], acc[bi][bj]);
+      for (int bj = 0; bj < BJ; ++bj) acc[bi][bj] = mfma16(af[bi], bf[bj], acc[bi][bj]);
+  }
+}
+
+constexpr int KCH = 32;   // K-chunk staged through LDS (mode 2)
+
+// Mode 2: the workgroup's 128 A rows and 128 B rows are copied chunk by chunk
+// (32 columns, 16-byte loads) into a double-buffered LDS stage while the
+// MFMAs consume the previous chunk.
+template <typename T>
+__device__ inline void tile_mma_lds(const T* __restrict__ Ar, int64_t lda, const T* __restrict__ Br, int64_t ldb,
+                                    typename AccT<T>::type acc[4][4], bool negate, T* smem, int NCH) {
+  constexpr int E = 16 / sizeof(T);                 // elements per 16-byte unit
+  constexpr int UNITS = KCH * NB / E;               // units per matrix per chunk
+  constexpr int PER = UNITS / 256;                  // units per thread
+  const int tid = threadIdx.x;
+  const int lane = tid & 63, w = tid >> 6;
+  const int wr = w & 1, wc = w >> 1;
+  const int lr = lane & 15, lk = lane >> 4;
+  float4 ra[PER], rb[PER];
+  int koff[PER], roff[PER];
+#pragma unroll
+  for (int i = 0; i < PER; ++i) {
+    const int u = tid + 256 * i;
+    koff[i] = u / (NB / E);
+    roff[i] = (u % (NB / E)) * E;
+  }
+#pragma unroll
+  for (int i = 0; i < PER; ++i) {
+    ra[i] = *reinterpret_cast<const float4*>(Ar + (int64_t)koff[i] * lda + roff[i]);
+    rb[i] = *reinterpret_cast<const float4*>(Br + (int64_t)koff[i] * ldb + roff[i]);
+  }
+#pragma unroll
+  for (int i = 0; i < PER; ++i) {
+    *reinterpret_cast<float4*>(smem + koff[i] * NB + roff[i]) = ra[i];
+    *reinterpret_cast<float4*>(smem + KCH * NB + koff[i] * NB + roff[i]) = rb[i];
+  }
+  __syncthreads();
+  for (int c = 0; c < NCH; ++c) {
+    if (c + 1 < NCH) {
+#pragma unroll
+      for (int i = 0; i < PER; ++i) {
+        ra[i] = *reinterpret_cast<const float4*>(Ar + (int64_t)((c + 1) * KCH + koff[i]) * lda + roff[i]);
+        rb[i] = *reinterpret_cast<const float4*>(Br + (int64_t)((c + 1) * KCH + koff[i]) * ldb + roff[i]);
+      }
+    }
+    const T* As = smem + (c & 1) * 2 * KCH * NB + 64 * wr;
+    const T* Bs = smem + (c & 1) * 2 * KCH * NB + KCH * NB + 64 * wc;
+#pragma unroll
+    for (int kk = 0; kk < KCH; kk += 4) {
+      T af[4], bf[4];
+#pragma unroll
+      for (int b = 0; b < 4; ++b) {
+        af[b] = As[(kk + lk) * NB + 16 * b + lr];
+        bf[b] = Bs[(kk + lk) * NB + 16 * b + lr];
+      }
+      if (negate) {
+#pragma unroll
+        for (int b = 0; b < 4; ++b) af[b] = -af[b];
+      }
+#pragma unroll
+      for (int bi = 0; bi < 4; ++bi)
+#pragma unroll
+        for (int bj = 0; bj < 4; ++bj) acc[bi][bj] = mfma16(af[bi], bf[bj], acc[bi][bj]);
+    }
+    if (c + 1 < NCH) {
+      T* As1 = smem + ((c + 1) & 1) * 2 * KCH * NB;
+#pragma unroll
+      for (int i = 0; i < PER; ++i) {
+        *reinterpret_cast<float4*>(As1 + koff[i] * NB + roff[i]) = ra[i];
+        *reinterpret_cast<float4*>(As1 + KCH * NB + koff[i] * NB + roff[i]) = rb[i];
+      }
+    }
+    __syncthreads();
   }
 }
 
@@ -171,28 +320,38 @@ template <typename T> __device__ inline int acc_row(int lane, int v);
 template <> __device__ inline int acc_row<float>(int lane, int v) { return 4 * (lane >> 4) + v; }
 template <> __device__ inline int acc_row<double>(int lane, int v) { return (lane >> 4) + 4 * v; }
 
-template <typename T>
-__device__ inline void tile_load(const T* C, int64_t ldc, typename AccT<T>::type acc[4][4]) {
+// C points at the wave's 64 x (16 BJ) sub-tile
+template <typename T, int BJ>
+__device__ inline void tile_load(const T* C, int64_t ldc, typename AccT<T>::type acc[4][BJ]) {
   const int lane = threadIdx.x & 63;
   const int col = lane & 15;
 #pragma unroll
   for (int bi = 0; bi < 4; ++bi)
 #pragma unroll
-    for (int bj = 0; bj < 4; ++bj)
+    for (int bj = 0; bj < BJ; ++bj)
 #pragma unroll
       for (int v = 0; v < 4; ++v) acc[bi][bj][v] = C[(int64_t)(16 * bj + col) * ldc + 16 * bi + acc_row<T>(lane, v)];
 }
 
-template <typename T>
-__device__ inline void tile_store(T* C, int64_t ldc, typename AccT<T>::type acc[4][4]) {
+template <typename T, int BJ>
+__device__ inline void tile_store(T* C, int64_t ldc, typename AccT<T>::type acc[4][BJ]) {
   const int lane = threadIdx.x & 63;
   const int col = lane & 15;
 #pragma unroll
   for (int bi = 0; bi < 4; ++bi)
 #pragma unroll
-    for (int bj = 0; bj < 4; ++bj)
+    for (int bj = 0; bj < BJ; ++bj)
 #pragma unroll
       for (int v = 0; v < 4; ++v) C[(int64_t)(16 * bj + col) * ldc + 16 * bi + acc_row<T>(lane, v)] = acc[bi][bj][v];
+}
+
+template <typename T, int MODE>
+__device__ inline void tile_mma(const T* Ar, int64_t lda, const T* Br, int64_t ldb,
+                                typename AccT<T>::type acc[4][TileGeo<MODE>::BJ], bool negate, int K, T* smem) {
+  if constexpr (MODE == 2)
+    tile_mma_lds<T>(Ar, lda, Br, ldb, acc, negate, smem, K / KCH);
+  else
+    tile_mma_direct<T, MODE>(Ar, lda, Br, ldb, acc, negate, K);
 }
 
 __device__ inline int find_mat(const int64_t* __restrict__ prefix, int cnt, int64_t w) {
@@ -205,55 +364,68 @@ __device__ inline int find_mat(const int64_t* __restrict__ prefix, int cnt, int6
 }
 
 // L21 = A21 * inv(L11)^T, one 128-row tile per workgroup.
-template <typename T>
-__global__ __launch_bounds__(256) void k_trsm(const MatDesc* __restrict__ desc, const int32_t* __restrict__ order,
-                                              const int64_t* __restrict__ prefix, int cnt, int step,
-                                              T* __restrict__ A, const T* __restrict__ Ainv) {
+template <typename T, int MODE>
+__global__ __launch_bounds__(64 * TileGeo<MODE>::WAVES) __attribute__((amdgpu_waves_per_eu(1, MODE == 2 ? 1 : 4))) void k_trsm(
+    const MatDesc* __restrict__ desc, const int32_t* __restrict__ order, const int64_t* __restrict__ prefix, int cnt,
+    int step, T* __restrict__ A, const T* __restrict__ Ainv) {
+  using G = TileGeo<MODE>;
+  extern __shared__ unsigned char smem_raw[];
+  T* smem = reinterpret_cast<T*>(smem_raw);
   const int j = find_mat(prefix, cnt, blockIdx.x);
-  const int m = order[j];
-  const MatDesc d = desc[m];
+  const MatDesc d = desc[order[j]];
   const int64_t t = blockIdx.x - prefix[j];
-  const int w = threadIdx.x >> 6;
-  const int wr = w & 1, wc = w >> 1;
   const int64_t k0 = (int64_t)step * NB;
-  const int64_t r0 = k0 + NB + t * NB + 64 * wr;
+  const int64_t rt = k0 + NB + t * NB;            // first row of the tile
   using Acc = typename AccT<T>::type;
-  Acc acc[4][4];
+  Acc acc[4][G::BJ];
 #pragma unroll
   for (int bi = 0; bi < 4; ++bi)
 #pragma unroll
-    for (int bj = 0; bj < 4; ++bj) acc[bi][bj] = Acc{0, 0, 0, 0};
-  const T* Ar = A + d.off + k0 * d.ld + r0;
-  const T* inv = Ainv + d.inv_off + (int64_t)step * NB * NB + 64 * wc;  // B[k][n] = inv[n][k]
-  tile_mma<T>(Ar, d.ld, inv, NB, acc, false);
-  __syncthreads();  // every wave has read the A21 tile before any writes
-  tile_store<T>(A + d.off + (k0 + 64 * wc) * d.ld + r0, d.ld, acc);
+    for (int bj = 0; bj < G::BJ; ++bj) acc[bi][bj] = Acc{0, 0, 0, 0};
+  const T* inv = Ainv + d.inv_off + (int64_t)step * NB * NB;   // B rows: inv[c][k] at k*NB + c
+  tile_mma<T, MODE>(A + d.off + k0 * d.ld + rt, d.ld, inv, NB, acc, false, NB, smem);
+  __syncthreads();   // every wave has read the A21 tile: safe to overwrite
+  tile_store<T, G::BJ>(A + d.off + (k0 + G::WCOL * G::wc()) * d.ld + rt + 64 * G::wr(), d.ld, acc);
 }
 
-// A22[ti][tj] -= L21[ti] L21[tj]^T on lower tiles ti >= tj.
-template <typename T>
-__global__ __launch_bounds__(256) void k_syrk(const MatDesc* __restrict__ desc, const int32_t* __restrict__ order,
-                                              const int64_t* __restrict__ prefix, int cnt, int step,
-                                              T* __restrict__ A) {
+// Trailing update with a group of kb panels:
+//   C[ti][tj] -= sum over panel columns [kcol0*NB, (kcol0+kb)*NB) of L[ti] L[tj]^T
+// for block tiles ti >= tj >= b0; ncols == 0: every trailing column block,
+// else only the ncols block columns from b0 (enumerated column by column).
+template <typename T, int MODE>
+__global__ __launch_bounds__(64 * TileGeo<MODE>::WAVES) __attribute__((amdgpu_waves_per_eu(1, MODE == 2 ? 1 : 4))) void k_syrk(
+    const MatDesc* __restrict__ desc, const int32_t* __restrict__ order, const int64_t* __restrict__ prefix, int cnt,
+    int kcol0, int kb, int b0, int ncols, T* __restrict__ A) {
+  using G = TileGeo<MODE>;
   const int j = find_mat(prefix, cnt, blockIdx.x);
-  const int m = order[j];
-  const MatDesc d = desc[m];
-  const int64_t u = blockIdx.x - prefix[j];
-  int64_t ti = (int64_t)((sqrt(8.0 * (double)u + 1.0) - 1.0) * 0.5);
-  while (ti * (ti + 1) / 2 > u) --ti;
-  while ((ti + 1) * (ti + 2) / 2 <= u) ++ti;
-  const int64_t tj = u - ti * (ti + 1) / 2;
-  const int w = threadIdx.x >> 6;
-  const int wr = w & 1, wc = w >> 1;
-  const int64_t k0 = (int64_t)step * NB;
-  const int64_t R0 = k0 + NB;
-  const int64_t rows = R0 + ti * NB + 64 * wr, cols = R0 + tj * NB + 64 * wc;
+  const MatDesc d = desc[order[j]];
+  int64_t u = blockIdx.x - prefix[j];
+  int64_t ti, tj;
+  if (ncols == 0) {
+    ti = (int64_t)((sqrt(8.0 * (double)u + 1.0) - 1.0) * 0.5);
+    while (ti * (ti + 1) / 2 > u) --ti;
+    while ((ti + 1) * (ti + 2) / 2 <= u) ++ti;
+    tj = u - ti * (ti + 1) / 2;
+    ti += b0;
+    tj += b0;
+  } else {
+    tj = b0;
+    while (u >= d.nblk - tj) {
+      u -= d.nblk - tj;
+      ++tj;
+    }
+    ti = tj + u;
+  }
+  const int64_t k0 = (int64_t)kcol0 * NB;
+  extern __shared__ unsigned char smem_raw[];
+  T* smem = reinterpret_cast<T*>(smem_raw);
   using Acc = typename AccT<T>::type;
-  Acc acc[4][4];
-  T* C = A + d.off + cols * d.ld + rows;
-  tile_load<T>(C, d.ld, acc);
-  tile_mma<T>(A + d.off + k0 * d.ld + rows, d.ld, A + d.off + k0 * d.ld + cols, d.ld, acc, true);
-  tile_store<T>(C, d.ld, acc);
+  Acc acc[4][G::BJ];
+  T* C = A + d.off + (tj * NB + G::WCOL * G::wc()) * d.ld + ti * NB + 64 * G::wr();
+  tile_load<T, G::BJ>(C, d.ld, acc);
+  tile_mma<T, MODE>(A + d.off + k0 * d.ld + ti * NB, d.ld, A + d.off + k0 * d.ld + tj * NB, d.ld, acc, true,
+                    kb * NB, smem);
+  tile_store<T, G::BJ>(C, d.ld, acc);
 }
 
 // --------------------------------------------------------------- plan
@@ -294,6 +466,37 @@ void FactorPlan::build(const std::vector<MatDesc>& descs, hipStream_t st) {
   d_desc.upload(descs, st);
   d_order.upload(ord, st);
   d_prefix.upload(pre, st);
+  // trailing updates for panel groups of G panels: inside a group, panel g
+  // updates only the group's later block columns; after the group, one
+  // update with all G panels (K = G * NB) covers the rest
+  const char* ge = std::getenv("GENEO_PANEL_GROUP");
+  group = ge ? std::max(1, std::atoi(ge)) : 8;
+  syrk.clear();
+  std::vector<int64_t> spre;
+  auto add_launch = [&](int kcol0, int kb, int b0, int ncols) {
+    SyrkLaunch L{(int64_t)spre.size(), 0, kcol0, kb, b0, ncols};
+    int64_t acc = 0;
+    for (int k = 0; k < nmat; ++k) {
+      spre.push_back(acc);
+      const int64_t N = descs[ord[k]].nblk;
+      if (kb > 0 && b0 < N && kcol0 + kb <= N) {
+        const int64_t cend = ncols ? std::min<int64_t>(N, b0 + ncols) : N;
+        for (int64_t c = b0; c < cend; ++c) acc += N - c;
+      }
+    }
+    spre.push_back(acc);
+    L.tiles = acc;
+    syrk.push_back(L);
+  };
+  for (int s0 = 0; s0 < max_blk; s0 += group) {
+    for (int g = 0; g < group && s0 + g < max_blk; ++g) {
+      const int sg = s0 + g;
+      if (g + 1 < group) add_launch(sg, 1, sg + 1, group - 1 - g);   // thin, inside the group
+      else add_launch(-1, 0, 0, 0);                                   // placeholder: none
+    }
+    add_launch(s0, group, s0 + group, 0);                            // trailing, K = group * NB
+  }
+  d_syrk_prefix.upload(spre, st);
   std::vector<int64_t> mp(nmat + 1, 0);
   for (int k = 0; k < nmat; ++k) {
     int64_t T = descs[ord[k]].nblk;
@@ -317,27 +520,63 @@ void FactorPlan::build(const std::vector<MatDesc>& descs, hipStream_t st) {
   d_items_bwd.upload(bwd, st);
 }
 
-template <typename T>
-static void factor_impl(const FactorPlan& P, T* A, T* Ainv, const double* odiag, double drop_tol, double* pivrel,
-                        DevErr* err, hipStream_t st) {
+template <typename T, int MODE>
+static void factor_run(const FactorPlan& P, T* A, T* Ainv, const double* odiag, double drop_tol, double* pivrel,
+                       DevErr* err, hipStream_t st) {
   const size_t lds = sizeof(T) * NB * LDA;
+  const size_t mma_lds = MODE == 2 ? sizeof(T) * 4 * KCH * NB : 0;   // two stages of A and B chunks
+  const unsigned threads = 64 * TileGeo<MODE>::WAVES;
   static bool attr_set = false;
   if (!attr_set) {
     HIP_CHECK(hipFuncSetAttribute((const void*)k_potrf<T>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+    if (MODE == 2) {
+      HIP_CHECK(hipFuncSetAttribute((const void*)k_trsm<T, MODE>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                    (int)mma_lds));
+      HIP_CHECK(hipFuncSetAttribute((const void*)k_syrk<T, MODE>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                    (int)mma_lds));
+    }
     attr_set = true;
   }
-  for (int s = 0; s < P.max_blk; ++s) {
-    const int64_t* pt = P.d_prefix.p + P.pre_off[s];
-    const int64_t* ps = pt + P.cnt[s] + 1;
-    k_potrf<T><<<dim3(P.cnt[s]), dim3(kPotrfThreads), lds, st>>>(P.d_desc.p, P.d_order.p, s, A, Ainv, odiag,
-                                                                   drop_tol, pivrel, err);
-    if (P.trsm_tiles[s] > 0) {
-      k_trsm<T><<<dim3((unsigned)P.trsm_tiles[s]), dim3(256), 0, st>>>(P.d_desc.p, P.d_order.p, pt, P.cnt[s], s, A,
-                                                                        Ainv);
-      k_syrk<T><<<dim3((unsigned)P.syrk_tiles[s]), dim3(256), 0, st>>>(P.d_desc.p, P.d_order.p, ps, P.cnt[s], s, A);
+  const int G = P.group;
+  size_t li = 0;
+  auto run_syrk = [&](const SyrkLaunch& L) {
+    if (L.tiles > 0 && L.kb > 0)
+      k_syrk<T, MODE><<<dim3((unsigned)L.tiles), dim3(threads), mma_lds, st>>>(
+          P.d_desc.p, P.d_order.p, P.d_syrk_prefix.p + L.pre_off, P.nmat, L.kcol0, L.kb, L.b0, L.ncols, A);
+  };
+  for (int s0 = 0; s0 < P.max_blk; s0 += G) {
+    for (int g = 0; g < G && s0 + g < P.max_blk; ++g) {
+      const int s = s0 + g;
+      const int64_t* pt = P.d_prefix.p + P.pre_off[s];
+      k_potrf<T><<<dim3(P.cnt[s]), dim3(kPotrfThreads), lds, st>>>(P.d_desc.p, P.d_order.p, s, A, Ainv, odiag,
+                                                                     drop_tol, pivrel, err);
+      if (P.trsm_tiles[s] > 0)
+        k_trsm<T, MODE><<<dim3((unsigned)P.trsm_tiles[s]), dim3(threads), mma_lds, st>>>(P.d_desc.p, P.d_order.p,
+                                                                                          pt, P.cnt[s], s, A, Ainv);
+      run_syrk(P.syrk[li++]);
     }
+    run_syrk(P.syrk[li++]);
   }
   HIP_CHECK(hipGetLastError());
+}
+
+template <typename T>
+static void factor_impl(const FactorPlan& P, T* A, T* Ainv, const double* odiag, double drop_tol, double* pivrel,
+                        DevErr* err, hipStream_t st) {
+  // tile mode: GENEO_MMA = direct4 | direct8 | lds; defaults measured on MI355X
+  static const int mode = [] {
+    const char* e = std::getenv("GENEO_MMA");
+    if (e && std::string(e) == "direct4") return 0;
+    if (e && std::string(e) == "direct8") return 1;
+    if (e && std::string(e) == "lds") return 2;
+    return 0;
+  }();
+  if (mode == 0)
+    factor_run<T, 0>(P, A, Ainv, odiag, drop_tol, pivrel, err, st);
+  else if (mode == 1)
+    factor_run<T, 1>(P, A, Ainv, odiag, drop_tol, pivrel, err, st);
+  else
+    factor_run<T, 2>(P, A, Ainv, odiag, drop_tol, pivrel, err, st);
 }
 
 template <typename T>
