@@ -38,6 +38,7 @@ def parse():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--workload", default="2", help="workload id (default: the 24^3 channel cube)")
+    ap.add_argument("--precision", default="fp64", choices=["fp64", "fp32"])
     return ap.parse_args()
 
 
@@ -73,7 +74,8 @@ def run_step(geneo, ctx, w, precision, b_host=None):
                n_snk=pi.n_snk, n_geneo=pi.n_geneo, lobpcg_iters=pi.lobpcg_iters,
                t_extract_ms=pi.t_extract_ms, t_factor_ms=pi.t_factor_ms, t_gevp_ms=pi.t_gevp_ms,
                t_coarse_build_ms=pi.t_coarse_build_ms, t_coarse_factor_ms=pi.t_coarse_factor_ms,
-               solve_ms=si.solve_ms, local_flops=pi.local_factor_flops, assemble_ms=sysm.info().assemble_ms)
+               solve_ms=si.solve_ms, local_flops=pi.local_factor_flops, assemble_ms=sysm.info().assemble_ms,
+               fp64_fallbacks=pi.fp64_fallbacks, fp32_rho_est=pi.fp32_rho_est)
     del pc, dec, sysm
     return out, b_host
 
@@ -120,13 +122,14 @@ def main():
     w = W.make(wid)
     ctx = geneo.Context(0)
     b_host = None
+    prec = geneo.FP64 if a.precision == "fp64" else geneo.FP32_REFINE1
     for _ in range(a.warmup):
-        _, b_host = run_step(geneo, ctx, w, geneo.FP64, b_host)
+        _, b_host = run_step(geneo, ctx, w, prec, b_host)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     res = []
     for _ in range(a.steps):
-        r, b_host = run_step(geneo, ctx, w, geneo.FP64, b_host)
+        r, b_host = run_step(geneo, ctx, w, prec, b_host)
         res.append(r)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
@@ -167,6 +170,7 @@ def main():
                       "gevp": mean("t_gevp_ms"), "coarse_build": mean("t_coarse_build_ms"),
                       "coarse_factor": mean("t_coarse_factor_ms"), "pcg_device": mean("solve_ms")},
         "pcg_iterations": last["iterations"],
+        "fp64_fallbacks": last["fp64_fallbacks"], "fp32_rho_est": last["fp32_rho_est"],
         "lobpcg_iterations": last["lobpcg_iters"],
         "local_factor_tflops": local_tf,
         "coarse_factor_tflops": coarse_tf,

@@ -150,6 +150,8 @@ typedef struct {
   uint64_t seed;            /* random start blocks */
   double coarse_drop_tol;   /* relative Schur pivot below which a coarse column is dependent */
   const double* warm_start; /* host [sum_i n_i * nev_max] start blocks (column-major per subdomain) or NULL */
+  double fp32_rho_max;      /* FP32_REFINE1: a subdomain whose estimated rho(I - Ahat_i^-1 A_i) exceeds this
+                               is factored in FP64 instead (default 0.5; must be < 1) */
 } geneo_setup_opts;
 
 typedef struct {
@@ -164,6 +166,7 @@ typedef struct {
   double max_dropped_pivot; /* largest relative Schur pivot dropped */
   double t_extract_ms, t_factor_ms, t_gevp_ms, t_coarse_build_ms, t_coarse_factor_ms; /* device times */
   double local_factor_flops; /* sum n_i^3/3 */
+  double fp32_rho_est;      /* FP32_REFINE1: largest probe estimate of rho(I - Ahat_i^-1 A_i), else 0 */
 } geneo_precond_info;
 
 void geneo_setup_opts_default(geneo_setup_opts* o);

@@ -19,6 +19,14 @@ Paper passages:
   * the condition number bound kappa <= (1 + k1 tau) k0 (Section 3.2, main
     theorem; k0 eq. (k0), k1 after it).
 
+The paper leaves the local solver open (Section 2 only needs A_i^-1); the
+"fp32_refine1" local precision is the mixed-precision variant of the
+measured workload: A_i factored in FP32, then one FP64 refinement step
+y = yhat + Ahat^-1 (r_i - A_i yhat), yhat = Ahat^-1 r_i, which as a map is
+2 Ahat^-1 - Ahat^-1 A_i Ahat^-1 (symmetric; positive definite exactly when
+rho(I - Ahat^-1 A_i) < 1).  The triangular solves use the FP32 factor with
+FP64 vectors.
+
 Readings: the paper solves with right-preconditioned GMRES at rtol 1e-6;
 this oracle runs preconditioned conjugate gradients (the preconditioner is
 symmetric positive definite) from x0 = 0, stopping at the first iterate with
@@ -114,12 +122,16 @@ class TwoLevel:
     level, no coarse space), 'nk' / 'nk_geneo' (Z from the global G)."""
 
     def __init__(self, dec, tau=10.0, nev_max=20, variant="snk_geneo", classical=False,
-                 drop_tol=1e-8):
+                 drop_tol=1e-8, local_precision="fp64"):
         self.dec = dec
         sysm = dec.sys
         n = sysm.n
         self.variant = variant
+        if local_precision not in ("fp64", "fp32_refine1"):
+            raise ValueError(local_precision)
+        self.local_precision = local_precision
         self.local_L = []
+        self.local_A = []
         self.eig = []
         self.G_locals = []
         cols_snk = []
@@ -127,7 +139,11 @@ class TwoLevel:
         self.geneo_counts = []
         for i in range(dec.N):
             Ai = dec.A_dir(i).toarray()
-            self.local_L.append(sla.cholesky(Ai, lower=True))
+            if local_precision == "fp32_refine1":
+                self.local_L.append(sla.cholesky(Ai.astype(np.float32), lower=True).astype(np.float64))
+                self.local_A.append(Ai)
+            else:
+                self.local_L.append(sla.cholesky(Ai, lower=True))
             Gi, gnodes, _ = dec.G_local(i)
             self.G_locals.append((Gi, gnodes))
             if variant in ("snk", "snk_geneo"):
@@ -179,13 +195,27 @@ class TwoLevel:
         out[k] = sla.cho_solve((self.E_L, True), v[k])
         return out
 
+    def local_solve(self, i, ri):
+        """A_i^-1 r_i: FP64 Cholesky, or FP32 Cholesky plus one FP64 refinement step."""
+        L = self.local_L[i]
+        y = sla.cho_solve((L, True), ri)
+        if self.local_precision == "fp32_refine1":
+            y = y + sla.cho_solve((L, True), ri - self.local_A[i] @ y)
+        return y
+
     def one_level(self, r):
         """sum_i R_i^T A_i^-1 R_i r (eq. (AS)), dense Cholesky solves."""
         y = np.zeros_like(r)
-        for i, L in enumerate(self.local_L):
+        for i in range(len(self.local_L)):
             d = self.dec.dofs[i]
-            y[d] += sla.cho_solve((L, True), r[d])
+            y[d] += self.local_solve(i, r[d])
         return y
+
+    def fp32_rho(self, i):
+        """rho(I - Ahat_i^-1 A_i) of the FP32 factor (dense eigenvalues; small cases)."""
+        L = self.local_L[i]
+        T = np.eye(L.shape[0]) - sla.cho_solve((L, True), self.local_A[i])
+        return float(np.abs(np.linalg.eigvals(T)).max())
 
     def apply(self, r):
         """z = M_AS,2^-1 r = Z E^-1 Z^T r + (I - P_0) M_AS^-1 (I - P_0^T) r."""

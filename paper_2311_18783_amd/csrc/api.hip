@@ -188,6 +188,7 @@ void geneo_setup_opts_default(geneo_setup_opts* o) {
   o->seed = 12345;
   o->coarse_drop_tol = 1e-8;
   o->warm_start = nullptr;
+  o->fp32_rho_max = 0.5;
 }
 
 int geneo_setup(geneo_ctx* ctx, const geneo_system* s, const geneo_decomp* d, const geneo_setup_opts* o,
@@ -203,7 +204,8 @@ int geneo_setup(geneo_ctx* ctx, const geneo_system* s, const geneo_decomp* d, co
       pc->opts = *o;
     else
       geneo_setup_opts_default(&pc->opts);
-    if (!(pc->opts.tau > 0) || pc->opts.nev_max < 0 || !(pc->opts.coarse_drop_tol >= 0))
+    if (!(pc->opts.tau > 0) || pc->opts.nev_max < 0 || !(pc->opts.coarse_drop_tol >= 0) ||
+        !(pc->opts.fp32_rho_max >= 0 && pc->opts.fp32_rho_max < 1))
       throw Error(GENEO_EINVAL, "bad setup options");
     setup_precond(ctx, pc);
   });

@@ -39,10 +39,12 @@ struct FactorPlan {
   void build(const std::vector<MatDesc>& descs, hipStream_t st);
 };
 
+// failed: if given, a non-positive pivot of matrix m sets failed[m] = 1 and
+// the column is treated as dropped, instead of raising GENEO_ENOTSPD.
 void factor(const FactorPlan& P, double* A, double* Ainv, const double* odiag, double drop_tol, double* pivrel,
-            DevErr* err, hipStream_t st);
+            DevErr* err, hipStream_t st, int32_t* failed = nullptr);
 void factor(const FactorPlan& P, float* A, float* Ainv, const double* odiag, double drop_tol, double* pivrel,
-            DevErr* err, hipStream_t st);
+            DevErr* err, hipStream_t st, int32_t* failed = nullptr);
 // Factor in place; afterwards the strictly upper blocks hold U = L^T.
 // x <- (L L^T)^-1 x on every matrix segment of the batch vector x.
 void solve(const FactorPlan& P, const double* A, const double* Ainv, double* x, unsigned* sync, unsigned* flags,

@@ -62,7 +62,8 @@ __global__ __launch_bounds__(kPotrfThreads) void k_potrf(const MatDesc* __restri
                                                          const int32_t* __restrict__ order, int step,
                                                          T* __restrict__ A, T* __restrict__ Ainv,
                                                          const double* __restrict__ odiag, double drop_tol,
-                                                         double* __restrict__ pivrel, DevErr* err) {
+                                                         double* __restrict__ pivrel, DevErr* err,
+                                                         int32_t* __restrict__ failed) {
   extern __shared__ unsigned char smem_raw[];
   T* Ls = reinterpret_cast<T*>(smem_raw);   // [NB * LDA] column-major: L, later X = inv(L)
   __shared__ double colbuf[2][NB];          // current Schur column (unscaled)
@@ -107,7 +108,12 @@ __global__ __launch_bounds__(kPotrfThreads) void k_potrf(const MatDesc* __restri
     const double s = (drop || fail) ? 0.0 : 1.0 / sq;
     if (t == 0) {
       if (use_drop && pivrel && d.diag_off >= 0) pivrel[d.diag_off + k0 + j] = o > 0.0 ? p / o : 0.0;
-      if (fail) set_err(err, GENEO_ENOTSPD, m, (int)(k0 + j));
+      if (fail) {
+        if (failed)
+          failed[m] = 1;   // caller handles it (the column is treated as dropped)
+        else
+          set_err(err, GENEO_ENOTSPD, m, (int)(k0 + j));
+      }
       invd[j] = s;
     }
     if (wave_row_max >= j) {
@@ -522,7 +528,7 @@ void FactorPlan::build(const std::vector<MatDesc>& descs, hipStream_t st) {
 
 template <typename T, int MODE>
 static void factor_run(const FactorPlan& P, T* A, T* Ainv, const double* odiag, double drop_tol, double* pivrel,
-                       DevErr* err, hipStream_t st) {
+                       DevErr* err, hipStream_t st, int32_t* failed) {
   const size_t lds = sizeof(T) * NB * LDA;
   const size_t mma_lds = MODE == 2 ? sizeof(T) * 4 * KCH * NB : 0;   // two stages of A and B chunks
   const unsigned threads = 64 * TileGeo<MODE>::WAVES;
@@ -549,7 +555,7 @@ static void factor_run(const FactorPlan& P, T* A, T* Ainv, const double* odiag, 
       const int s = s0 + g;
       const int64_t* pt = P.d_prefix.p + P.pre_off[s];
       k_potrf<T><<<dim3(P.cnt[s]), dim3(kPotrfThreads), lds, st>>>(P.d_desc.p, P.d_order.p, s, A, Ainv, odiag,
-                                                                     drop_tol, pivrel, err);
+                                                                     drop_tol, pivrel, err, failed);
       if (P.trsm_tiles[s] > 0)
         k_trsm<T, MODE><<<dim3((unsigned)P.trsm_tiles[s]), dim3(threads), mma_lds, st>>>(P.d_desc.p, P.d_order.p,
                                                                                           pt, P.cnt[s], s, A, Ainv);
@@ -562,7 +568,7 @@ static void factor_run(const FactorPlan& P, T* A, T* Ainv, const double* odiag, 
 
 template <typename T>
 static void factor_impl(const FactorPlan& P, T* A, T* Ainv, const double* odiag, double drop_tol, double* pivrel,
-                        DevErr* err, hipStream_t st) {
+                        DevErr* err, hipStream_t st, int32_t* failed) {
   // tile mode: GENEO_MMA = direct4 | direct8 | lds; defaults measured on MI355X
   static const int mode = [] {
     const char* e = std::getenv("GENEO_MMA");
@@ -572,24 +578,24 @@ static void factor_impl(const FactorPlan& P, T* A, T* Ainv, const double* odiag,
     return 0;
   }();
   if (mode == 0)
-    factor_run<T, 0>(P, A, Ainv, odiag, drop_tol, pivrel, err, st);
+    factor_run<T, 0>(P, A, Ainv, odiag, drop_tol, pivrel, err, st, failed);
   else if (mode == 1)
-    factor_run<T, 1>(P, A, Ainv, odiag, drop_tol, pivrel, err, st);
+    factor_run<T, 1>(P, A, Ainv, odiag, drop_tol, pivrel, err, st, failed);
   else
-    factor_run<T, 2>(P, A, Ainv, odiag, drop_tol, pivrel, err, st);
+    factor_run<T, 2>(P, A, Ainv, odiag, drop_tol, pivrel, err, st, failed);
 }
 
 template <typename T>
 static void mirror_impl(const FactorPlan& P, T* A, hipStream_t st);
 
 void factor(const FactorPlan& P, double* A, double* Ainv, const double* odiag, double drop_tol, double* pivrel,
-            DevErr* err, hipStream_t st) {
-  factor_impl<double>(P, A, Ainv, odiag, drop_tol, pivrel, err, st);
+            DevErr* err, hipStream_t st, int32_t* failed) {
+  factor_impl<double>(P, A, Ainv, odiag, drop_tol, pivrel, err, st, failed);
   mirror_impl<double>(P, A, st);
 }
 void factor(const FactorPlan& P, float* A, float* Ainv, const double* odiag, double drop_tol, double* pivrel,
-            DevErr* err, hipStream_t st) {
-  factor_impl<float>(P, A, Ainv, odiag, drop_tol, pivrel, err, st);
+            DevErr* err, hipStream_t st, int32_t* failed) {
+  factor_impl<float>(P, A, Ainv, odiag, drop_tol, pivrel, err, st, failed);
   mirror_impl<float>(P, A, st);
 }
 

@@ -17,6 +17,16 @@ struct geneo_precond {
   geneo::DevBuf<double> dL, dLinv;
   geneo::DevBuf<float> fL, fLinv;
   geneo::DevBuf<unsigned> d_flags_local;
+  // FP32_REFINE1: subdomains that kept their FP32 factor and those refactored
+  // in FP64 after the probe (empty when none fell back: `local` serves all)
+  geneo::FactorPlan local32, local64;
+  int32_t n_fallback = 0;
+  geneo::DevBuf<unsigned> d_flags_local64;
+  geneo::DevBuf<int8_t> d_refine;            // batch row -> 1 if its subdomain is refined (FP32)
+  // batch-row CSR of the local matrices A_i (columns = batch positions,
+  // values = slots of the global CSR), for the FP64 residual of the refinement
+  geneo::DevBuf<int64_t> d_brp;
+  geneo::DevBuf<int32_t> d_bcol, d_bslot;
   int64_t batch_len = 0;                     // sum of n_pad
   std::vector<int64_t> voff;                 // batch offset of each subdomain
   geneo::DevBuf<int32_t> d_bmap;             // batch index -> free edge (-1 in pads)
@@ -52,7 +62,7 @@ struct geneo_precond {
   std::vector<int32_t> eig_sel;
 
   // work vectors
-  geneo::DevBuf<double> w_b1, w_b2;          // batch vectors
+  geneo::DevBuf<double> w_b1, w_b2, w_b3;    // batch vectors
   geneo::DevBuf<double> w_n1, w_n2, w_n3, w_n4;  // length n
   geneo::DevBuf<double> w_c1, w_c2;          // length n0_pad
 };

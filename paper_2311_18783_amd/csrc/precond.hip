@@ -270,6 +270,47 @@ void dot(const double* x, const double* y, int64_t n, double* partial, double* o
 
 static inline unsigned nblocks(int64_t n, int b = 256) { return (unsigned)((n + b - 1) / b); }
 
+// out = [b -] A_i x on every batch row (FP64), rows with mask 0 give 0;
+// out may alias b (each thread reads and writes only its own row).
+__global__ void k_local_residual(int64_t len, const int64_t* __restrict__ rp, const int32_t* __restrict__ bcol,
+                                 const int32_t* __restrict__ bslot, const double* __restrict__ gval,
+                                 const double* b, const double* __restrict__ x, const int8_t* __restrict__ mask,
+                                 double* out) {
+  const int64_t row = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (row >= len) return;
+  double acc = 0.0;
+  for (int64_t t = rp[row]; t < rp[row + 1]; ++t) acc += gval[bslot[t]] * x[bcol[t]];
+  const double v = (b ? b[row] : 0.0) - acc;
+  out[row] = (mask && !mask[row]) ? 0.0 : v;
+}
+
+// reproducible pseudo-random start vector in [-1, 1) on real batch rows (splitmix64)
+__global__ void k_hash_fill(int64_t len, const int32_t* __restrict__ bmap, uint64_t seed, double* __restrict__ x) {
+  const int64_t row = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (row >= len) return;
+  uint64_t z = seed + 0x9E3779B97F4A7C15ull * (uint64_t)(row + 1);
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  z ^= z >> 31;
+  x[row] = bmap[row] < 0 ? 0.0 : (double)(z >> 11) * 0x1.0p-52 - 1.0;
+}
+
+// out[i] = sum of squares of segment i (one block per subdomain, fixed order)
+__global__ __launch_bounds__(256) void k_seg_sumsq(const int64_t* __restrict__ voff, const double* __restrict__ x,
+                                                   double* __restrict__ out) {
+  __shared__ double red[256];
+  const int i = blockIdx.x;
+  double acc = 0.0;
+  for (int64_t r = voff[i] + threadIdx.x; r < voff[i + 1]; r += 256) acc += x[r] * x[r];
+  red[threadIdx.x] = acc;
+  __syncthreads();
+  for (int o = 128; o > 0; o >>= 1) {
+    if ((int)threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) out[i] = red[0];
+}
+
 // ---------------------------------------------------------------- setup
 
 void check_device_error(geneo_ctx* ctx) {
@@ -292,6 +333,92 @@ static float elapsed(geneo_ctx* ctx, int a, int b) {
   float ms = 0;
   HIP_CHECK(hipEventElapsedTime(&ms, ctx->ev[a], ctx->ev[b]));
   return ms;
+}
+
+// FP32 local factors with one FP64 refinement step apply the map
+//   y = yhat + Ahat^-1 (r - A_i yhat),  yhat = Ahat^-1 r,
+// i.e. (2 Ahat^-1 - Ahat^-1 A_i Ahat^-1) r, which is symmetric and positive
+// definite exactly when rho(I - Ahat^-1 A_i) < 1.  The probe estimates that
+// radius per subdomain by power iteration on I - Ahat^-1 A_i (FP64 residual,
+// FP32 solve) and refactors in FP64 every subdomain whose estimate exceeds
+// fp32_rho_max or is not finite.
+static void fp32_probe(geneo_ctx* ctx, geneo_precond* pc, const std::vector<MatDesc>& descs,
+                       const int32_t* d_failed) {
+  constexpr int kPowerSteps = 8;
+  hipStream_t st = ctx->stream;
+  const int32_t N = pc->N;
+  const int64_t len = pc->batch_len;
+  const geneo_system* s = pc->sys;
+  double* v = pc->w_b1.p;
+  double* t = pc->w_b2.p;
+  DevBuf<double> sq;
+  sq.alloc(2 * (int64_t)N);
+  DevBuf<int64_t> d_voff;
+  d_voff.upload(pc->voff, st);
+  k_hash_fill<<<nblocks(len), 256, 0, st>>>(len, pc->d_bmap.p, pc->opts.seed ^ 0x5eedull, v);
+  for (int it = 0; it < kPowerSteps; ++it) {
+    k_local_residual<<<nblocks(len), 256, 0, st>>>(len, pc->d_brp.p, pc->d_bcol.p, pc->d_bslot.p, s->d_val.p,
+                                                   nullptr, v, nullptr, t);
+    solve(pc->local, pc->fL.p, pc->fLinv.p, t, ctx->d_sync, pc->d_flags_local.p, ctx->d_err, st);
+    k_axpby<<<nblocks(len), 256, 0, st>>>(len, 1.0, v, 1.0, t, v);
+    if (it >= kPowerSteps - 2) k_seg_sumsq<<<N, 256, 0, st>>>(d_voff.p, v, sq.p + (it - (kPowerSteps - 2)) * N);
+  }
+  HIP_CHECK(hipGetLastError());
+  std::vector<double> h(2 * (size_t)N);
+  std::vector<int32_t> failed(N);
+  HIP_CHECK(hipMemcpyAsync(h.data(), sq.p, sizeof(double) * 2 * N, hipMemcpyDeviceToHost, st));
+  HIP_CHECK(hipMemcpyAsync(failed.data(), d_failed, sizeof(int32_t) * N, hipMemcpyDeviceToHost, st));
+  HIP_CHECK(hipStreamSynchronize(st));
+  check_device_error(ctx);
+  std::vector<MatDesc> d32, d64;
+  double rho_max = 0.0;
+  for (int32_t i = 0; i < N; ++i) {
+    double rho = h[i] > 0.0 ? std::sqrt(h[N + i] / h[i]) : (h[N + i] > 0.0 ? INFINITY : 0.0);
+    if (failed[i]) rho = INFINITY;
+    rho_max = std::max(rho_max, std::isfinite(rho) ? rho : INFINITY);
+    (rho <= pc->opts.fp32_rho_max ? d32 : d64).push_back(descs[i]);
+  }
+  pc->info.fp32_rho_est = rho_max;
+  pc->n_fallback = (int32_t)d64.size();
+  pc->info.fp64_fallbacks = pc->n_fallback;
+  if (d64.empty()) return;
+  auto renumber = [](std::vector<MatDesc>& d) {
+    int32_t f = 0;
+    for (auto& m : d) {
+      m.flag_off = f;
+      f += m.nblk;
+    }
+    return f;
+  };
+  const int32_t f32 = renumber(d32), f64 = renumber(d64);
+  if (!d32.empty()) pc->local32.build(d32, st);
+  pc->local64.build(d64, st);
+  pc->d_flags_local64.alloc(std::max(f64, 1));
+  HIP_CHECK(hipMemsetAsync(pc->d_flags_local64.p, 0, sizeof(unsigned) * std::max(f64, 1), st));
+  (void)f32;
+  // FP64 copies of the fallback matrices (extraction of every block is one
+  // cheap pass; only the fallback subset is factored)
+  const MatDesc& last = descs.back();
+  const int64_t total = last.off + (int64_t)last.ld * last.ld;
+  const int64_t inv_total = last.inv_off + 2 * (int64_t)last.ld * NB;
+  std::vector<int64_t> mat_start(N);
+  for (int32_t i = 0; i < N; ++i) mat_start[i] = descs[i].off;
+  DevBuf<int64_t> d_mat_start;
+  d_mat_start.upload(mat_start, st);
+  pc->dL.alloc(total);
+  pc->dLinv.alloc(inv_total);
+  k_fill_identity_pad<<<nblocks(total), 256, 0, st>>>(pc->local.d_desc.p, N, pc->dL.p, nullptr, total, d_mat_start.p);
+  const int64_t nnz = pc->lnnz_off[N];
+  if (nnz)
+    k_dense_scatter<<<nblocks(nnz), 256, 0, st>>>(nnz, pc->d_lrow.p, pc->d_lcol.p, pc->d_lslot.p, pc->d_lnnz_off.p,
+                                                  N, pc->local.d_desc.p, s->d_val.p, pc->dL.p, nullptr);
+  HIP_CHECK(hipGetLastError());
+  factor(pc->local64, pc->dL.p, pc->dLinv.p, nullptr, 0.0, nullptr, ctx->d_err, st);
+  std::vector<int8_t> refine(len, 0);
+  for (const auto& m : d32)
+    for (int64_t r = 0; r < m.ld; ++r) refine[m.voff + r] = 1;
+  pc->d_refine.upload(refine, st);
+  HIP_CHECK(hipStreamSynchronize(st));
 }
 
 void setup_precond(geneo_ctx* ctx, geneo_precond* pc) {
@@ -374,6 +501,20 @@ void setup_precond(geneo_ctx* ctx, geneo_precond* pc) {
     lnnz_off[i + 1] = (int64_t)lrow.size();
   }
   pc->lnnz_off = lnnz_off;
+  {
+    // the triplets come row by row: batch-row pointers, batch columns
+    std::vector<int64_t> brp(voff + 1, 0);
+    std::vector<int32_t> bcol(lrow.size());
+    for (int32_t i = 0; i < N; ++i)
+      for (int64_t t = lnnz_off[i]; t < lnnz_off[i + 1]; ++t) {
+        brp[pc->voff[i] + lrow[t] + 1]++;
+        bcol[t] = (int32_t)(pc->voff[i] + lcol[t]);
+      }
+    for (int64_t r = 0; r < voff; ++r) brp[r + 1] += brp[r];
+    pc->d_brp.upload(brp, st);
+    pc->d_bcol.upload(bcol, st);
+    pc->d_bslot.upload(lslot, st);
+  }
   pc->d_lrow.upload(lrow, st);
   pc->d_lcol.upload(lcol, st);
   pc->d_lslot.upload(lslot, st);
@@ -402,18 +543,27 @@ void setup_precond(geneo_ctx* ctx, geneo_precond* pc) {
                                                                    fp32 ? nullptr : pc->dL.p, fp32 ? pc->fL.p : nullptr);
   HIP_CHECK(hipGetLastError());
   HIP_CHECK(hipEventRecord(ctx->ev[1], st));
-  if (fp32)
-    factor(pc->local, pc->fL.p, pc->fLinv.p, nullptr, 0.0, nullptr, ctx->d_err, st);
-  else
+  // work vectors
+  pc->w_b1.alloc(voff);
+  pc->w_b2.alloc(voff);
+  pc->w_b3.alloc(voff);
+  if (fp32) {
+    // an FP32 factor that meets a non-positive pivot is flagged, not fatal:
+    // that subdomain falls back to FP64
+    DevBuf<int32_t> failed;
+    failed.alloc(N);
+    HIP_CHECK(hipMemsetAsync(failed.p, 0, sizeof(int32_t) * N, st));
+    factor(pc->local, pc->fL.p, pc->fLinv.p, nullptr, 0.0, nullptr, ctx->d_err, st, failed.p);
+    check_device_error(ctx);
+    fp32_probe(ctx, pc, descs, failed.p);
+  } else {
     factor(pc->local, pc->dL.p, pc->dLinv.p, nullptr, 0.0, nullptr, ctx->d_err, st);
+  }
   HIP_CHECK(hipEventRecord(ctx->ev[2], st));
   pc->info.t_extract_ms = elapsed(ctx, 0, 1);
   pc->info.t_factor_ms = elapsed(ctx, 1, 2);
   check_device_error(ctx);
 
-  // work vectors
-  pc->w_b1.alloc(voff);
-  pc->w_b2.alloc(voff);
   pc->w_n1.alloc(n);
   pc->w_n2.alloc(n);
   pc->w_n3.alloc(n);
@@ -584,11 +734,26 @@ static void coarse_solve(geneo_ctx* ctx, const geneo_precond* pc, double* c) {
   solve(pc->coarse, pc->dE.p, pc->dEinv.p, c, ctx->d_sync, pc->d_flags_coarse.p, ctx->d_err, ctx->stream);
 }
 
+// b <- A_i^-1 b on every segment; FP32 factors get one FP64 refinement step
 static void local_solve(geneo_ctx* ctx, const geneo_precond* pc, double* b) {
-  if (pc->precision == GENEO_FP32_REFINE1)
-    solve(pc->local, pc->fL.p, pc->fLinv.p, b, ctx->d_sync, pc->d_flags_local.p, ctx->d_err, ctx->stream);
-  else
-    solve(pc->local, pc->dL.p, pc->dLinv.p, b, ctx->d_sync, pc->d_flags_local.p, ctx->d_err, ctx->stream);
+  hipStream_t st = ctx->stream;
+  if (pc->precision != GENEO_FP32_REFINE1) {
+    solve(pc->local, pc->dL.p, pc->dLinv.p, b, ctx->d_sync, pc->d_flags_local.p, ctx->d_err, st);
+    return;
+  }
+  const int64_t len = pc->batch_len;
+  const FactorPlan& p32 = pc->n_fallback ? pc->local32 : pc->local;
+  double* rhs = pc->w_b3.p;
+  HIP_CHECK(hipMemcpyAsync(rhs, b, sizeof(double) * len, hipMemcpyDeviceToDevice, st));
+  if (p32.nmat) solve(p32, pc->fL.p, pc->fLinv.p, b, ctx->d_sync, pc->d_flags_local.p, ctx->d_err, st);
+  if (pc->n_fallback)
+    solve(pc->local64, pc->dL.p, pc->dLinv.p, b, ctx->d_sync, pc->d_flags_local64.p, ctx->d_err, st);
+  if (!p32.nmat) return;
+  // rhs <- rhs - A_i yhat on the refined subdomains (0 elsewhere), then the correction
+  k_local_residual<<<nblocks(len), 256, 0, st>>>(len, pc->d_brp.p, pc->d_bcol.p, pc->d_bslot.p, pc->sys->d_val.p, rhs,
+                                                 b, pc->n_fallback ? pc->d_refine.p : nullptr, rhs);
+  solve(p32, pc->fL.p, pc->fLinv.p, rhs, ctx->d_sync, pc->d_flags_local.p, ctx->d_err, st);
+  k_axpby<<<nblocks(len), 256, 0, st>>>(len, 1.0, b, 1.0, rhs, b);
 }
 
 // t = Z^T g   (g: global vector; uses w_b2 for the GenEO part)

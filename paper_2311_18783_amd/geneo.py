@@ -63,7 +63,7 @@ class SetupOpts(C.Structure):
     _fields_ = [("tau", C.c_double), ("nev_max", C.c_int32), ("coarse", C.c_int32),
                 ("local_precision", C.c_int32), ("lobpcg_tol", C.c_double), ("lobpcg_maxit", C.c_int32),
                 ("lobpcg_guard", C.c_int32), ("seed", C.c_uint64), ("coarse_drop_tol", C.c_double),
-                ("warm_start", C.POINTER(C.c_double))]
+                ("warm_start", C.POINTER(C.c_double)), ("fp32_rho_max", C.c_double)]
 
 
 class PrecondInfo(C.Structure):
@@ -72,7 +72,7 @@ class PrecondInfo(C.Structure):
                 ("min_kept_pivot", C.c_double), ("max_dropped_pivot", C.c_double),
                 ("t_extract_ms", C.c_double), ("t_factor_ms", C.c_double), ("t_gevp_ms", C.c_double),
                 ("t_coarse_build_ms", C.c_double), ("t_coarse_factor_ms", C.c_double),
-                ("local_factor_flops", C.c_double)]
+                ("local_factor_flops", C.c_double), ("fp32_rho_est", C.c_double)]
 
 
 class SolveOpts(C.Structure):

@@ -200,3 +200,53 @@ def test_pcg_converges_to_direct_solution(floating):
     # the two-level method needs fewer iterations than one-level AS
     _, it1, _ = geneo.pcg(s.A, b, geneo.TwoLevel(dec, variant="as").apply, rtol=1e-8)
     assert it < it1
+
+
+@pytest.fixture(scope="module")
+def stiff():
+    # small gamma and high contrast: kappa(A_i) large enough that an FP32
+    # factor leaves a visible error for the refinement to remove
+    return _case((4, 4, 4), (2, 2, 1), gamma=1e-4, contrast=1e4, seed=3)[1]
+
+
+def test_fp32_refinement_step(stiff):
+    """One FP64 refinement step after an FP32 Cholesky solve: the error
+    operator is squared, e1 = (I - Ahat^-1 A) e0, so in the A-norm
+    ||e1||_A <= rho^2 ||x||_A with rho the spectral radius of I - Ahat^-1 A
+    (Ahat^-1 A is A-self-adjoint); the map equals 2 Ahat^-1 - Ahat^-1 A Ahat^-1
+    and is symmetric."""
+    tl = geneo.TwoLevel(stiff, variant="as", local_precision="fp32_refine1")
+    rng = np.random.default_rng(0)
+    for i in range(stiff.N):
+        A = tl.local_A[i]
+        L = tl.local_L[i]
+        assert L.dtype == np.float64 and np.array_equal(L.astype(np.float32).astype(np.float64), L)
+        n = A.shape[0]
+        x = rng.standard_normal(n)
+        r = A @ x
+        yhat = sla.cho_solve((L, True), r)
+        y = tl.local_solve(i, r)
+        anorm = lambda v: float(np.sqrt(v @ (A @ v)))
+        rho = tl.fp32_rho(i)
+        assert 0.0 < rho < 1.0
+        e0, e1 = anorm(x - yhat), anorm(x - y)
+        assert e0 <= rho * anorm(x) * (1 + 1e-6) + 1e-12 * anorm(x)
+        assert e1 <= rho ** 2 * anorm(x) * (1 + 1e-6) + 1e-12 * anorm(x)
+        assert e1 < e0
+        Ahinv = sla.cho_solve((L, True), np.eye(n))
+        Mref = 2 * Ahinv - Ahinv @ A @ Ahinv
+        Mcol = np.column_stack([tl.local_solve(i, e) for e in np.eye(n)[:40]])
+        assert np.abs(Mcol - Mref[:, :40]).max() <= 1e-9 * np.abs(Mref).max()
+        assert np.abs(Mref - Mref.T).max() <= 1e-9 * np.abs(Mref).max()
+
+
+def test_fp32_refined_two_level_pcg(stiff):
+    """The FP32-refined preconditioner keeps PCG within one iteration of FP64."""
+    s = stiff.sys
+    b = np.random.default_rng(1).standard_normal(s.n)
+    it = {}
+    for prec in ("fp64", "fp32_refine1"):
+        tl = geneo.TwoLevel(stiff, local_precision=prec)
+        x, it[prec], _ = geneo.pcg(s.A, b, tl.apply, rtol=1e-8)
+        assert np.linalg.norm(b - s.A @ x) <= 1.01e-8 * np.linalg.norm(b)
+    assert it["fp32_refine1"] <= it["fp64"] + 1
