@@ -75,6 +75,7 @@ typedef struct {
  * all work is ordered on; NULL means the device's default (null) stream. */
 int geneo_create(geneo_ctx** ctx, int device, void* hip_stream);
 void geneo_destroy(geneo_ctx* ctx);
+/* NULL ctx: the message of the last failed geneo_create on this thread. */
 const char* geneo_last_error(const geneo_ctx* ctx);
 
 /* --- assemble: A = K + gamma M over free edges, and G ------------------ */
@@ -152,6 +153,9 @@ typedef struct {
   const double* warm_start; /* host [sum_i n_i * nev_max] start blocks (column-major per subdomain) or NULL */
   double fp32_rho_max;      /* FP32_REFINE1: a subdomain whose estimated rho(I - Ahat_i^-1 A_i) exceeds this
                                is factored in FP64 instead (default 0.5; must be < 1) */
+  const struct geneo_model* model; /* learned warm start of the eigensolver, or NULL (cold random start);
+                               ignored when warm_start is given */
+  int32_t keep_ritz;        /* 1: keep the final Ritz block for geneo_model_collect */
 } geneo_setup_opts;
 
 typedef struct {
@@ -167,6 +171,9 @@ typedef struct {
   double t_extract_ms, t_factor_ms, t_gevp_ms, t_coarse_build_ms, t_coarse_factor_ms; /* device times */
   double local_factor_flops; /* sum n_i^3/3 */
   double fp32_rho_est;      /* FP32_REFINE1: largest probe estimate of rho(I - Ahat_i^-1 A_i), else 0 */
+  int32_t learned_starts;   /* subdomains whose start block came from the model */
+  double start_residual;    /* largest eigen-residual of the top nev_max Ritz pairs after the first
+                               Rayleigh-Ritz step (start-block quality) */
 } geneo_precond_info;
 
 void geneo_setup_opts_default(geneo_setup_opts* o);
@@ -189,6 +196,13 @@ int geneo_precond_info_get(const geneo_precond* pc, geneo_precond_info* info);
 int geneo_precond_eigs(const geneo_precond* pc, int32_t i, double* lam, int32_t cap,
                        int32_t* count, int32_t* selected);
 
+/* Ritz vectors of subdomain i (setup with keep_ritz = 1): V [n_i x k]
+ * column-major (host), the top-k of the final eigensolver block in
+ * descending Ritz-value order, A_i^Neu-orthonormal (Section 3.2 GEVP);
+ * k = min(cap, block width); *k_out = columns written. */
+int geneo_precond_ritz(geneo_ctx* ctx, const geneo_precond* pc, int32_t i, double* V, int32_t cap,
+                       int32_t* k_out);
+
 /* z = M_AS,2^-1 r, device vectors of length n (the paper's preconditioner). */
 int geneo_apply(geneo_ctx* ctx, const geneo_precond* pc, const double* r, double* z);
 
@@ -210,6 +224,73 @@ typedef struct {
  * info filled and the last iterate in x. */
 int geneo_solve(geneo_ctx* ctx, const geneo_system* sys, const geneo_precond* pc,
                 const double* b, double* x, const geneo_solve_opts* opts, geneo_solve_info* info);
+
+/* --- learned warm start of the eigensolver ------------------------------ */
+/* The paper computes the GenEO eigenvectors from scratch in every subdomain
+ * (Section 3.2); the model below predicts start blocks for the eigensolver
+ * from the subdomain's coefficients.  A subdomain of a hexahedral mesh
+ * (cells split into six tetrahedra along the main diagonal) is placed,
+ * centred, on a canvas of C^3 cells; the input is, per canvas cell,
+ * log mu, log eps, occupancy, "owned by the subdomain before overlap" and
+ * the fraction of its nodes on the Dirichlet boundary, plus log10 gamma and
+ * a constant; the output is k values per canvas edge (start vectors over
+ * the subdomain's edges).  Network: in -> hidden -> hidden -> rows*k, ReLU,
+ * BF16 weights and activations, FP32 accumulation; trained with Adam on the
+ * span loss ||Y^T Y||_F^2 - 2 ||V^T Y||_F^2 + k (minimal, 0, when
+ * Y Y^T = V V^T) against the top-k eigenvectors V (orthonormalised) found
+ * by the eigensolver.  A subdomain that does not fit the canvas keeps the
+ * random start. */
+typedef struct geneo_model geneo_model;
+
+typedef struct {
+  int32_t canvas;   /* C: canvas cells per axis (default 12) */
+  int32_t hidden;   /* hidden width (default 256) */
+  int32_t k;        /* start vectors per subdomain (default 20) */
+  uint64_t seed;    /* weight initialisation */
+} geneo_model_opts;
+
+typedef struct {
+  int32_t in_dim, rows, k, hidden, canvas;
+  int64_t n_params;
+  int32_t n_train, n_holdout;   /* collected samples */
+} geneo_model_info;
+
+typedef struct {
+  int32_t epochs, batch;
+  double lr;
+  uint64_t seed;    /* sample order */
+} geneo_train_opts;
+
+typedef struct {
+  double loss_first, loss_last;   /* mean training loss of the first and last epoch */
+  double holdout_loss;            /* mean loss on the held-out samples after training (0 if none) */
+  double train_ms;
+} geneo_train_info;
+
+void geneo_model_opts_default(geneo_model_opts* o);
+int geneo_model_create(geneo_ctx* ctx, const geneo_model_opts* opts, geneo_model** out);
+int geneo_model_info_get(const geneo_model* m, geneo_model_info* info);
+/* Append one sample per subdomain of a finished setup (built with
+ * keep_ritz = 1 on a hexahedral mesh): its canvas features and its top-k
+ * Ritz vectors.  holdout = 1 keeps them out of training (evaluation only). */
+int geneo_model_collect(geneo_ctx* ctx, geneo_model* m, const geneo_system* sys, const geneo_decomp* dec,
+                        const geneo_precond* pc, int32_t holdout);
+int geneo_model_train(geneo_ctx* ctx, geneo_model* m, const geneo_train_opts* opts, geneo_train_info* info);
+/* Kernel-level entries (host arrays, row-major): predictions Y [batch x rows*k]
+ * for features X [batch x in_dim]; the loss (mean over the batch) and its
+ * gradients [n_params] in the order W1 (hidden x in), b1, W2, b2, W3
+ * (rows*k x hidden), b3 for targets V [batch x rows*k] and row masks
+ * [batch x rows] (V orthonormal on the masked rows). */
+int geneo_model_predict(geneo_ctx* ctx, const geneo_model* m, int32_t batch, const float* X, float* Y);
+int geneo_model_loss_grad(geneo_ctx* ctx, const geneo_model* m, int32_t batch, const float* X, const float* V,
+                          const uint8_t* mask, double* loss, float* grad);
+/* Parameters in the gradient order: get returns the BF16 values in use (as
+ * float); set rounds to BF16 and resets the optimiser state. */
+int geneo_model_get_params(const geneo_model* m, float* params);
+int geneo_model_set_params(geneo_ctx* ctx, geneo_model* m, const float* params);
+int geneo_model_save(const geneo_model* m, const char* path);
+int geneo_model_load(geneo_ctx* ctx, const char* path, geneo_model** out);
+void geneo_free_model(geneo_model* m);
 
 /* --- kernel-level entry: batched dense Cholesky ------------------------ */
 

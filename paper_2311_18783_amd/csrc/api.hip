@@ -2,7 +2,7 @@
 // returns a geneo_status; the message goes to the context.
 #include <cstring>
 
-#include "precond.h"
+#include "model.h"
 
 namespace geneo {
 void build_topology(geneo_system* s, const geneo_mesh* m);
@@ -30,6 +30,9 @@ static int guarded(geneo_ctx* ctx, F&& f) {
   }
 }
 
+// message of the last failed geneo_create (no context to hold it)
+static thread_local std::string g_create_err;
+
 extern "C" {
 
 int geneo_create(geneo_ctx** out, int device, void* hip_stream) {
@@ -54,6 +57,7 @@ int geneo_create(geneo_ctx** out, int device, void* hip_stream) {
     for (auto& e : ctx->ev) HIP_CHECK(hipEventCreate(&e));
   });
   if (rc != GENEO_OK) {
+    g_create_err = ctx->err;
     geneo_destroy(ctx);
     return rc;
   }
@@ -74,7 +78,7 @@ void geneo_destroy(geneo_ctx* ctx) {
   delete ctx;
 }
 
-const char* geneo_last_error(const geneo_ctx* ctx) { return ctx ? ctx->err.c_str() : "null context"; }
+const char* geneo_last_error(const geneo_ctx* ctx) { return ctx ? ctx->err.c_str() : g_create_err.c_str(); }
 
 int geneo_assemble(geneo_ctx* ctx, const geneo_mesh* mesh, const double* mu, const double* eps, double gamma,
                    geneo_system** out) {
@@ -189,6 +193,8 @@ void geneo_setup_opts_default(geneo_setup_opts* o) {
   o->coarse_drop_tol = 1e-8;
   o->warm_start = nullptr;
   o->fp32_rho_max = 0.5;
+  o->model = nullptr;
+  o->keep_ritz = 0;
 }
 
 int geneo_setup(geneo_ctx* ctx, const geneo_system* s, const geneo_decomp* d, const geneo_setup_opts* o,
@@ -232,6 +238,23 @@ int geneo_precond_eigs(const geneo_precond* pc, int32_t i, double* lam, int32_t 
   if (count) *count = c;
   if (selected) *selected = pc->eig_sel[i];
   return GENEO_OK;
+}
+
+int geneo_precond_ritz(geneo_ctx* ctx, const geneo_precond* pc, int32_t i, double* V, int32_t cap,
+                       int32_t* k_out) {
+  if (!ctx || !pc || i < 0 || i >= pc->N || cap < 0) return GENEO_EINVAL;
+  return guarded(ctx, [&] {
+    if (!pc->d_ritz.p) throw Error(GENEO_EINVAL, "setup without keep_ritz = 1");
+    const int32_t k = std::min(cap, pc->ritz_k);
+    const int64_t ni = pc->dec->dofs_ptr[i + 1] - pc->dec->dofs_ptr[i];
+    const int64_t ld = pc->voff[i + 1] - pc->voff[i];
+    if (V)
+      for (int32_t q = 0; q < k; ++q)
+        HIP_CHECK(hipMemcpyAsync(V + (int64_t)q * ni, pc->d_ritz.p + pc->voff[i] * pc->ritz_k + (int64_t)q * ld,
+                                 sizeof(double) * ni, hipMemcpyDeviceToHost, ctx->stream));
+    HIP_CHECK(hipStreamSynchronize(ctx->stream));
+    if (k_out) *k_out = k;
+  });
 }
 
 int geneo_apply(geneo_ctx* ctx, const geneo_precond* pc, const double* r, double* z) {
@@ -293,6 +316,98 @@ int geneo_potrf_batched(geneo_ctx* ctx, int32_t batch, const int32_t* n_host, co
     check_device_error(ctx);
   });
 }
+
+void geneo_model_opts_default(geneo_model_opts* o) {
+  if (!o) return;
+  o->canvas = 12;
+  o->hidden = 256;
+  o->k = 20;
+  o->seed = 2311;
+}
+
+int geneo_model_create(geneo_ctx* ctx, const geneo_model_opts* o, geneo_model** out) {
+  if (!ctx || !out) return GENEO_EINVAL;
+  *out = nullptr;
+  geneo_model_opts d;
+  geneo_model_opts_default(&d);
+  geneo_model* m = new (std::nothrow) geneo_model();
+  if (!m) return GENEO_EOOM;
+  int rc = guarded(ctx, [&] { model_init(m, o ? o : &d, ctx->stream); });
+  if (rc != GENEO_OK) {
+    delete m;
+    return rc;
+  }
+  *out = m;
+  return GENEO_OK;
+}
+
+int geneo_model_info_get(const geneo_model* m, geneo_model_info* info) {
+  if (!m || !info) return GENEO_EINVAL;
+  info->in_dim = m->in_dim;
+  info->rows = m->rows;
+  info->k = m->k;
+  info->hidden = m->hidden;
+  info->canvas = m->C;
+  info->n_params = model_n_params(m);
+  int32_t h = 0;
+  for (uint8_t x : m->holdout) h += x;
+  info->n_holdout = h;
+  info->n_train = (int32_t)m->holdout.size() - h;
+  return GENEO_OK;
+}
+
+int geneo_model_collect(geneo_ctx* ctx, geneo_model* m, const geneo_system* s, const geneo_decomp* d,
+                        const geneo_precond* pc, int32_t holdout) {
+  if (!ctx || !m || !s || !d || !pc) return GENEO_EINVAL;
+  return guarded(ctx, [&] { model_collect(ctx, m, s, d, pc, holdout); });
+}
+
+int geneo_model_train(geneo_ctx* ctx, geneo_model* m, const geneo_train_opts* o, geneo_train_info* info) {
+  if (!ctx || !m || !o || !info) return GENEO_EINVAL;
+  return guarded(ctx, [&] { model_train(ctx, m, o, info); });
+}
+
+int geneo_model_predict(geneo_ctx* ctx, const geneo_model* m, int32_t batch, const float* X, float* Y) {
+  if (!ctx || !m || !X || !Y) return GENEO_EINVAL;
+  return guarded(ctx, [&] { model_predict(ctx, m, batch, X, Y); });
+}
+
+int geneo_model_loss_grad(geneo_ctx* ctx, const geneo_model* m, int32_t batch, const float* X, const float* V,
+                          const uint8_t* mask, double* loss, float* grad) {
+  if (!ctx || !m || !X || !V || !mask || !loss) return GENEO_EINVAL;
+  return guarded(ctx, [&] { *loss = model_loss_grad(ctx, m, batch, X, V, mask, grad); });
+}
+
+int geneo_model_get_params(const geneo_model* m, float* params) {
+  if (!m || !params) return GENEO_EINVAL;
+  return guarded(nullptr, [&] { model_get_params(m, params); });
+}
+
+int geneo_model_set_params(geneo_ctx* ctx, geneo_model* m, const float* params) {
+  if (!ctx || !m || !params) return GENEO_EINVAL;
+  return guarded(ctx, [&] { model_set_params(ctx, m, params, true); });
+}
+
+int geneo_model_save(const geneo_model* m, const char* path) {
+  if (!m || !path) return GENEO_EINVAL;
+  return guarded(nullptr, [&] { model_save(m, path); });
+}
+
+int geneo_model_load(geneo_ctx* ctx, const char* path, geneo_model** out) {
+  if (!ctx || !path || !out) return GENEO_EINVAL;
+  *out = nullptr;
+  geneo_model* m = new (std::nothrow) geneo_model();
+  if (!m) return GENEO_EOOM;
+  int rc = guarded(ctx, [&] { model_load(ctx, m, path); });
+  if (rc != GENEO_OK) {
+    delete m;
+    return rc;
+  }
+  *out = m;
+  return GENEO_OK;
+}
+
+void geneo_free_model(geneo_model* m) { delete m; }
 
 void geneo_free_system(geneo_system* s) { delete s; }
 void geneo_free_decomp(geneo_decomp* d) { delete d; }

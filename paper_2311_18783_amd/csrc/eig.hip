@@ -18,7 +18,7 @@
 #include <cstdlib>
 #include <numeric>
 
-#include "precond.h"
+#include "model.h"
 
 namespace geneo {
 
@@ -878,6 +878,7 @@ void solve_local_gevps(geneo_ctx* ctx, geneo_precond* pc) {
     HIP_CHECK(hipMemcpy(X.p, h.data(), sizeof(double) * blk, hipMemcpyHostToDevice));
   } else {
     k_random_block<<<nb256(blk), 256, 0, st>>>(w.len, k, w.row_sub.p, w.voff_d.p, w.nloc.p, pc->opts.seed, X.p);
+    if (pc->opts.model) pc->info.learned_starts = model_warm_start(ctx, pc->opts.model, pc, k, nev, X.p);
   }
   spmm(pc, w, w.bval.p, X.p, nullptr, nullptr, T1.p, st);        // B X
   gt(w, T1.p, NT.p, st);
@@ -934,7 +935,8 @@ void solve_local_gevps(geneo_ctx* ctx, geneo_precond* pc) {
     HIP_CHECK(hipMemcpyAsync(h_theta.data(), theta.p, sizeof(double) * N * k, hipMemcpyDeviceToHost, st));
     HIP_CHECK(hipMemcpyAsync(h_nrm.data(), nrm.p, sizeof(double) * N * k * 2, hipMemcpyDeviceToHost, st));
     HIP_CHECK(hipStreamSynchronize(st));
-    int n_active = 0;
+    int n_active = 0, n_cert = 0;
+    double worst_sel = 0.0, worst_cert = 0.0;
     unconv = 0;
     for (int j = 0; j < N; ++j) {
       const double* th = h_theta.data() + j * k;
@@ -951,11 +953,18 @@ void solve_local_gevps(geneo_ctx* ctx, geneo_precond* pc) {
         best[j] = rsel;
         best_it[j] = it;
       }
+      if (it == 1)
+        for (int q = 0; q < std::min(k, nev); ++q) pc->info.start_residual = std::max(pc->info.start_residual, resid(q));
       const bool stalled = rsel <= 100.0 * tol && it - best_it[j] >= 5;
       bool conv = rsel <= tol || stalled;
       if (!conv) unconv += 1;
       // the first Ritz value below tau must be settled too
-      if (nsel < nev && nsel < k && !(resid(nsel) <= cert_tol)) conv = false;
+      if (nsel < nev && nsel < k && !(resid(nsel) <= cert_tol)) {
+        if (conv) ++n_cert;
+        conv = false;
+        worst_cert = std::max(worst_cert, resid(nsel));
+      }
+      if (rsel > tol) worst_sel = std::max(worst_sel, rsel);
       active[j] = conv ? 0 : 1;
       n_active += active[j];
       if (verbose && (!conv || it == 1) && (it % 10 == 1 || it == maxit)) {
@@ -965,6 +974,9 @@ void solve_local_gevps(geneo_ctx* ctx, geneo_precond* pc) {
                      nsel, th[0], th[k - 1], rmax, (int)conv);
       }
     }
+    if (verbose)
+      std::fprintf(stderr, "[lobpcg] it %d active %d (certification only %d) worst selected res %.3g worst cert res %.3g\n",
+                   it, n_active, n_cert, worst_sel, worst_cert);
     if (n_active == 0 || it == maxit) break;
     HIP_CHECK(hipMemcpyAsync(d_active.p, active.data(), sizeof(int32_t) * N, hipMemcpyHostToDevice, st));
     // W = B^-1 R, B-orthogonal to X, B-orthonormal
@@ -1006,6 +1018,12 @@ void solve_local_gevps(geneo_ctx* ctx, geneo_precond* pc) {
   check_device_error(ctx);
   pc->info.lobpcg_iters = it > maxit ? maxit : it;
   pc->info.lobpcg_unconverged = unconv;
+
+  if (pc->opts.keep_ritz) {
+    pc->d_ritz.alloc(blk);
+    HIP_CHECK(hipMemcpyAsync(pc->d_ritz.p, X.p, sizeof(double) * blk, hipMemcpyDeviceToDevice, st));
+    pc->ritz_k = k;
+  }
 
   // ---- selection and coarse vectors D_j (I - xi_j) X_sel
   std::vector<int32_t> sel(N, 0);

@@ -57,6 +57,10 @@ struct geneo_precond {
   geneo::DevBuf<int64_t> d_voff;
   geneo::DevBuf<int32_t> d_n;
 
+  // final Ritz block of the eigensolver (kept on request, for training the warm start)
+  geneo::DevBuf<double> d_ritz;
+  int32_t ritz_k = 0;
+
   // eigen results (host)
   std::vector<std::vector<double>> eigs;
   std::vector<int32_t> eig_sel;

@@ -13,6 +13,10 @@ import os
 import re
 
 import numpy as np
+# torch's ROCm libraries must be loaded before libgeneo: the two HIP runtimes
+# then share torch's HSA runtime; loading libgeneo first leaves the library's
+# runtime without a device once torch initialises.
+import torch  # noqa: F401
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libgeneo.so")
@@ -63,7 +67,8 @@ class SetupOpts(C.Structure):
     _fields_ = [("tau", C.c_double), ("nev_max", C.c_int32), ("coarse", C.c_int32),
                 ("local_precision", C.c_int32), ("lobpcg_tol", C.c_double), ("lobpcg_maxit", C.c_int32),
                 ("lobpcg_guard", C.c_int32), ("seed", C.c_uint64), ("coarse_drop_tol", C.c_double),
-                ("warm_start", C.POINTER(C.c_double)), ("fp32_rho_max", C.c_double)]
+                ("warm_start", C.POINTER(C.c_double)), ("fp32_rho_max", C.c_double),
+                ("model", C.c_void_p), ("keep_ritz", C.c_int32)]
 
 
 class PrecondInfo(C.Structure):
@@ -72,7 +77,26 @@ class PrecondInfo(C.Structure):
                 ("min_kept_pivot", C.c_double), ("max_dropped_pivot", C.c_double),
                 ("t_extract_ms", C.c_double), ("t_factor_ms", C.c_double), ("t_gevp_ms", C.c_double),
                 ("t_coarse_build_ms", C.c_double), ("t_coarse_factor_ms", C.c_double),
-                ("local_factor_flops", C.c_double), ("fp32_rho_est", C.c_double)]
+                ("local_factor_flops", C.c_double), ("fp32_rho_est", C.c_double),
+                ("learned_starts", C.c_int32), ("start_residual", C.c_double)]
+
+
+class ModelOpts(C.Structure):
+    _fields_ = [("canvas", C.c_int32), ("hidden", C.c_int32), ("k", C.c_int32), ("seed", C.c_uint64)]
+
+
+class ModelInfo(C.Structure):
+    _fields_ = [("in_dim", C.c_int32), ("rows", C.c_int32), ("k", C.c_int32), ("hidden", C.c_int32),
+                ("canvas", C.c_int32), ("n_params", C.c_int64), ("n_train", C.c_int32), ("n_holdout", C.c_int32)]
+
+
+class TrainOpts(C.Structure):
+    _fields_ = [("epochs", C.c_int32), ("batch", C.c_int32), ("lr", C.c_double), ("seed", C.c_uint64)]
+
+
+class TrainInfo(C.Structure):
+    _fields_ = [("loss_first", C.c_double), ("loss_last", C.c_double), ("holdout_loss", C.c_double),
+                ("train_ms", C.c_double)]
 
 
 class SolveOpts(C.Structure):
@@ -101,10 +125,24 @@ _sigs = {
     "geneo_setup": (C.c_int, [_vp, _vp, _vp, _P(SetupOpts), _P(_vp)]),
     "geneo_precond_info_get": (C.c_int, [_vp, _P(PrecondInfo)]),
     "geneo_precond_eigs": (C.c_int, [_vp, C.c_int32, _P(C.c_double), C.c_int32, _P(C.c_int32), _P(C.c_int32)]),
+    "geneo_precond_ritz": (C.c_int, [_vp, _vp, C.c_int32, _P(C.c_double), C.c_int32, _P(C.c_int32)]),
     "geneo_apply": (C.c_int, [_vp, _vp, _vp, _vp]),
     "geneo_solve": (C.c_int, [_vp, _vp, _vp, _vp, _vp, _P(SolveOpts), _P(SolveInfo)]),
     "geneo_potrf_batched": (C.c_int, [_vp, C.c_int32, _P(C.c_int32), _P(C.c_int64), _vp, C.c_int32,
                                       _P(C.c_double)]),
+    "geneo_model_opts_default": (None, [_P(ModelOpts)]),
+    "geneo_model_create": (C.c_int, [_vp, _P(ModelOpts), _P(_vp)]),
+    "geneo_model_info_get": (C.c_int, [_vp, _P(ModelInfo)]),
+    "geneo_model_collect": (C.c_int, [_vp, _vp, _vp, _vp, _vp, C.c_int32]),
+    "geneo_model_train": (C.c_int, [_vp, _vp, _P(TrainOpts), _P(TrainInfo)]),
+    "geneo_model_predict": (C.c_int, [_vp, _vp, C.c_int32, _P(C.c_float), _P(C.c_float)]),
+    "geneo_model_loss_grad": (C.c_int, [_vp, _vp, C.c_int32, _P(C.c_float), _P(C.c_float), _P(C.c_uint8),
+                                        _P(C.c_double), _P(C.c_float)]),
+    "geneo_model_get_params": (C.c_int, [_vp, _P(C.c_float)]),
+    "geneo_model_set_params": (C.c_int, [_vp, _vp, _P(C.c_float)]),
+    "geneo_model_save": (C.c_int, [_vp, C.c_char_p]),
+    "geneo_model_load": (C.c_int, [_vp, C.c_char_p, _P(_vp)]),
+    "geneo_free_model": (None, [_vp]),
     "geneo_free_system": (None, [_vp]),
     "geneo_free_decomp": (None, [_vp]),
     "geneo_free_precond": (None, [_vp]),
@@ -143,7 +181,7 @@ class Context:
 
     def _check(self, rc):
         if rc != 0:
-            msg = lib.geneo_last_error(self.h).decode() if self.h else ""
+            msg = lib.geneo_last_error(self.h if self.h else None).decode()
             raise GeneoError(rc, msg)
 
     def close(self):
@@ -192,8 +230,11 @@ class Context:
         o = SetupOpts()
         lib.geneo_setup_opts_default(C.byref(o))
         ws = kw.pop("warm_start", None)
+        model = kw.pop("model", None)
         for k, v in kw.items():
             setattr(o, k, v)
+        if model is not None:
+            o.model = model.h
         if ws is not None:
             ws = np.ascontiguousarray(ws, dtype=np.float64)
             o.warm_start = _ptr(ws, C.c_double)
@@ -224,6 +265,19 @@ class Context:
         self._check(lib.geneo_potrf_batched(self.h, len(n), _ptr(n, C.c_int32), _ptr(off, C.c_int64),
                                             _dptr(A), int(precision), C.byref(ms)))
         return ms.value
+
+
+    # -------------------------------------------------------------- learned warm start
+    def model_create(self, canvas=12, hidden=256, k=20, seed=2311):
+        o = ModelOpts(int(canvas), int(hidden), int(k), int(seed))
+        h = C.c_void_p()
+        self._check(lib.geneo_model_create(self.h, C.byref(o), C.byref(h)))
+        return Model(self, h)
+
+    def model_load(self, path):
+        h = C.c_void_p()
+        self._check(lib.geneo_model_load(self.h, str(path).encode(), C.byref(h)))
+        return Model(self, h)
 
 
 class _Handle:
@@ -290,8 +344,65 @@ class Precond(_Handle):
         self.ctx._check(lib.geneo_precond_info_get(self.h, C.byref(i)))
         return i
 
+    def ritz(self, i, n_i, cap=64):
+        kk = C.c_int32()
+        self.ctx._check(lib.geneo_precond_ritz(self.ctx.h, self.h, i, None, cap, C.byref(kk)))
+        V = np.empty((kk.value, n_i), np.float64)
+        self.ctx._check(lib.geneo_precond_ritz(self.ctx.h, self.h, i, _ptr(V, C.c_double), cap, C.byref(kk)))
+        return V.T.copy()
+
     def eigs(self, i, cap=64):
         lam = np.empty(cap, np.float64)
         cnt, sel = C.c_int32(), C.c_int32()
         self.ctx._check(lib.geneo_precond_eigs(self.h, i, _ptr(lam, C.c_double), cap, C.byref(cnt), C.byref(sel)))
         return lam[:cnt.value].copy(), sel.value
+
+
+class Model(_Handle):
+    """Learned warm start of the eigensolver (see include/geneo.h)."""
+    _free = "geneo_free_model"
+
+    def info(self):
+        i = ModelInfo()
+        self.ctx._check(lib.geneo_model_info_get(self.h, C.byref(i)))
+        return i
+
+    def collect(self, system, decomp, precond, holdout=False):
+        self.ctx._check(lib.geneo_model_collect(self.ctx.h, self.h, system.h, decomp.h, precond.h, int(holdout)))
+
+    def train(self, epochs=20, batch=32, lr=1e-3, seed=0):
+        o = TrainOpts(int(epochs), int(batch), float(lr), int(seed))
+        i = TrainInfo()
+        self.ctx._check(lib.geneo_model_train(self.ctx.h, self.h, C.byref(o), C.byref(i)))
+        return i
+
+    def predict(self, X):
+        X = np.ascontiguousarray(X, dtype=np.float32)
+        inf = self.info()
+        Y = np.empty((X.shape[0], inf.rows * inf.k), np.float32)
+        self.ctx._check(lib.geneo_model_predict(self.ctx.h, self.h, X.shape[0], _ptr(X, C.c_float),
+                                                _ptr(Y, C.c_float)))
+        return Y
+
+    def loss_grad(self, X, V, mask, with_grad=True):
+        X = np.ascontiguousarray(X, dtype=np.float32)
+        V = np.ascontiguousarray(V, dtype=np.float32)
+        mask = np.ascontiguousarray(mask, dtype=np.uint8)
+        loss = C.c_double()
+        g = np.empty(self.info().n_params, np.float32) if with_grad else None
+        self.ctx._check(lib.geneo_model_loss_grad(self.ctx.h, self.h, X.shape[0], _ptr(X, C.c_float),
+                                                  _ptr(V, C.c_float), _ptr(mask, C.c_uint8), C.byref(loss),
+                                                  _ptr(g, C.c_float) if g is not None else None))
+        return loss.value, g
+
+    def get_params(self):
+        p = np.empty(self.info().n_params, np.float32)
+        self.ctx._check(lib.geneo_model_get_params(self.h, _ptr(p, C.c_float)))
+        return p
+
+    def set_params(self, p):
+        p = np.ascontiguousarray(p, dtype=np.float32)
+        self.ctx._check(lib.geneo_model_set_params(self.ctx.h, self.h, _ptr(p, C.c_float)))
+
+    def save(self, path):
+        self.ctx._check(lib.geneo_model_save(self.h, str(path).encode()))

@@ -1,0 +1,130 @@
+"""GPU: the learned warm start's network against the oracle's numpy
+forward/backward (same BF16 rounding points), save/load, and the start
+blocks it hands to the eigensolver."""
+import os
+import tempfile
+
+import numpy as np
+import pytest
+
+import workloads as W
+from cases import lib_problem
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def g():
+    import torch
+    from paper_2311_18783_amd import geneo
+    assert torch.cuda.is_available()
+    ctx = geneo.Context(0)
+    yield geneo, ctx
+    ctx.close()
+
+
+def _batch(inf, B, seed):
+    rng = np.random.default_rng(seed)
+    X = rng.standard_normal((B, inf.in_dim)).astype(np.float32)
+    mask = (rng.random((B, inf.rows)) < 0.7).astype(np.uint8)
+    mask[:, :inf.k] = 1
+    V = np.zeros((B, inf.rows * inf.k), np.float32)
+    for s in range(B):
+        m = mask[s].astype(bool)
+        Vs = np.zeros((inf.rows, inf.k))
+        Vs[m] = np.linalg.qr(rng.standard_normal((int(m.sum()), inf.k)))[0]
+        V[s] = Vs.ravel()
+    return X, V, mask
+
+
+@pytest.mark.parametrize("shape", [(2, 32, 4, 3), (12, 256, 20, 2)])
+def test_network_matches_oracle(g, shape):
+    """Predictions, loss and all six gradient tensors agree with the oracle
+    evaluated at the model's BF16 parameters with the same rounding points;
+    the remaining differences come from FP32 versus FP64 accumulation and
+    the BF16 roundings they can flip (relative 1e-2 per tensor)."""
+    from oracle import mlp
+    geneo, ctx = g
+    C, h, k, B = shape
+    print("model", shape, flush=True)
+    m = ctx.model_create(canvas=C, hidden=h, k=k, seed=7)
+    inf = m.info()
+    # move the output layer away from its small initial scale so that the loss is not trivial
+    p = m.get_params()
+    rng = np.random.default_rng(3)
+    p += (rng.standard_normal(p.size) * 0.02).astype(np.float32)
+    m.set_params(p)
+    p = m.get_params()
+    R = inf.rows * inf.k
+    params = mlp.split_params(p, inf.in_dim, inf.hidden, R)
+    X, V, mask = _batch(inf, B, 4)
+    Y = m.predict(X)
+    Yo, _ = mlp.forward(params, X, rounding=True)
+    assert np.linalg.norm(Y - Yo) <= 1e-3 * np.linalg.norm(Yo)
+    loss, grad = m.loss_grad(X, V, mask)
+    lo, go = mlp.loss_and_grad(params, X, V, mask, inf.k, rounding=True)
+    assert abs(loss - lo) <= 1e-3 * abs(lo), (loss, lo)
+    off = 0
+    for i, G in enumerate(go):
+        gg = grad[off:off + G.size].reshape(G.shape)
+        off += G.size
+        assert np.linalg.norm(gg - G) <= 1e-2 * np.linalg.norm(G) + 1e-30, (i, np.linalg.norm(gg - G), np.linalg.norm(G))
+
+
+def test_save_load_roundtrip(g):
+    geneo, ctx = g
+    m = ctx.model_create(canvas=3, hidden=16, k=3, seed=9)
+    X, _, _ = _batch(m.info(), 2, 5)
+    with tempfile.TemporaryDirectory() as d:
+        path = os.path.join(d, "ws.bin")
+        m.save(path)
+        m2 = ctx.model_load(path)
+        assert np.array_equal(m.predict(X), m2.predict(X))
+        assert np.array_equal(m.get_params(), m2.get_params())
+
+
+def test_learned_start_feeds_the_eigensolver(g):
+    """A model trained on one instance's Ritz vectors supplies the start
+    blocks of every subdomain (the canvas fits), the eigensolver still
+    converges from them to the same eigenvalues (1e-8) and coarse space, and
+    the exported Ritz vectors are A_i^Neu-orthonormal eigenvectors of the
+    filtered pencil (checked against the oracle's dense pencil)."""
+    from cases import oracle_problem
+    from oracle import geneo as og
+    geneo, ctx = g
+    w = W.make("small_channels")
+    sysm, dec = lib_problem(ctx, w)
+    pc = ctx.setup(sysm, dec, tau=w.tau, nev_max=w.nev_max, keep_ritz=1)
+    cold = pc.info()
+    m = ctx.model_create(canvas=8, hidden=64, k=w.nev_max, seed=1)
+    m.collect(sysm, dec, pc)
+    assert m.info().n_train == dec.info().n_sub
+    ti = m.train(epochs=400, batch=8, lr=2e-3, seed=0)
+    assert ti.loss_last < 0.05 * ti.loss_first, (ti.loss_first, ti.loss_last)
+    pc2 = ctx.setup(sysm, dec, tau=w.tau, nev_max=w.nev_max, model=m)
+    warm = pc2.info()
+    print("cold", cold.lobpcg_iters, "warm", warm.lobpcg_iters, flush=True)
+    assert warm.learned_starts == dec.info().n_sub
+    assert warm.lobpcg_unconverged == 0
+    assert warm.n_geneo == cold.n_geneo and warm.n0_rank == cold.n0_rank
+    for i in range(dec.info().n_sub):
+        a, sa = pc.eigs(i)
+        b, sb = pc2.eigs(i)
+        assert sa == sb
+        if sa:
+            assert np.abs(a[:sa] - b[:sa]).max() <= 1e-8 * np.abs(a[:sa]).max()
+    # Ritz vectors of the subdomain with the most GenEO vectors against the oracle's pencil
+    j = int(np.argmax([pc.eigs(i)[1] for i in range(dec.info().n_sub)]))
+    s, odec = oracle_problem(w)
+    Ai = odec.A_dir(j).toarray()
+    Bn = odec.A_neu(j).toarray()
+    Gi, _, _ = odec.G_local(j)
+    At, _ = og.filtered_pencil(Ai, Bn, odec.D[j], Gi)
+    lam, sel = pc.eigs(j)
+    assert sel > 0
+    V = pc.ritz(j, Ai.shape[0], cap=w.nev_max)
+    VB = V[:, :sel].T @ Bn @ V[:, :sel]
+    assert np.abs(VB - np.eye(sel)).max() <= 1e-8
+    R = At @ V[:, :sel] - (Bn @ V[:, :sel]) * lam[:sel]
+    rel = np.linalg.norm(R, axis=0) / (np.abs(lam[:sel]) * np.linalg.norm(Bn @ V[:, :sel], axis=0))
+    assert rel.max() <= 1e-6, rel.max()

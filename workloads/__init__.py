@@ -211,8 +211,15 @@ def rcb_jitter(nparts, rng, spread=0.3):
     return rng.uniform(-spread, spread, size=max(nparts - 1, 0)) / depth
 
 
-def make(cfg, **over):
-    """Build workload `cfg` (1, 2, 3, 5, or a small named test case)."""
+def make(cfg, family=0, **over):
+    """Build workload `cfg` (1, 2, 3, 5, or a small named test case).
+
+    family > 0 (configs 2 and "small_channels"): another instance of the same
+    recipe, its coefficients drawn from the stream SeedSequence([seed, family])
+    instead of SeedSequence(seed); used to train the learned warm start on
+    instances disjoint from the measured one."""
+    def stream(seed):
+        return np.random.SeedSequence([seed, family] if family else seed).spawn(4)
     if cfg == 1:
         dims = (8, 8, 8)
         mesh = hex_box_mesh(dims)
@@ -223,7 +230,7 @@ def make(cfg, **over):
     elif cfg == 2:
         dims = (24, 24, 24)
         mesh = hex_box_mesh(dims)
-        ss = np.random.SeedSequence(1002).spawn(4)
+        ss = stream(1002)
         mu = per_hex(channel_mu(dims, np.random.default_rng(ss[0])), mesh)
         T = mesh["tets"].shape[0]
         w = Workload("cube24_channels", mesh, mu, np.ones(T), 1e-4,
@@ -259,7 +266,7 @@ def make(cfg, **over):
         # A small heterogeneous case whose GenEO space is not empty.
         dims = (8, 8, 8)
         mesh = hex_box_mesh(dims)
-        ss = np.random.SeedSequence(2001).spawn(4)
+        ss = stream(2001)
         mu = per_hex(channel_mu(dims, np.random.default_rng(ss[0]), frac=0.15), mesh)
         T = mesh["tets"].shape[0]
         w = Workload("cube8_channels", mesh, mu, np.ones(T), 1e-4,
@@ -300,6 +307,10 @@ def make(cfg, **over):
                      {"kind": "rcb", "nparts": 7, "jitter": jit}, 1, seed=2004)
     else:
         raise ValueError(f"unknown workload {cfg!r}")
+    if family:
+        if cfg not in (2, "small_channels"):
+            raise ValueError(f"no instance family for workload {cfg!r}")
+        w.name = f"{w.name}#{family}"
     for k, v in over.items():
         setattr(w, k, v)
     return w
