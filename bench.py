@@ -5,12 +5,17 @@ A step is one pass of the whole path over the synthetic workload
 channels covering >= 10% of the hexes, eps = 1, gamma = 1e-4, 4x4x4 box
 subdomains with 2 overlap layers, at most 20 GenEO eigenvectors per
 subdomain, PCG to rtol 1e-8): assemble, partition, setup (local Cholesky
-factors, GenEO eigenproblems, coarse space and coarse Cholesky) and
-solve.  The reported value is setup + solve seconds with the assembled
+factors, GenEO eigenproblems, coarse space and coarse Cholesky) and solve.
+Two configurations run on the same mesh: the headline one with FP32 local
+factors (probe + FP64 fallback) and the learned warm start of the
+eigensolver, and the plain FP64 one with random start blocks.  The model is
+trained beforehand (not timed) on other instances of the same workload
+recipe.  The reported value is setup + solve seconds with the assembled
 system already resident on the device; assembly and partitioning are
 reported beside it.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
+                       [--variant both|learned_fp32|fp64] [--train-instances F]
 Prints one JSON line.
 """
 from __future__ import annotations
@@ -38,11 +43,33 @@ def parse():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--workload", default="2", help="workload id (default: the 24^3 channel cube)")
-    ap.add_argument("--precision", default="fp64", choices=["fp64", "fp32"])
+    ap.add_argument("--variant", default="both", choices=["both", "learned_fp32", "fp64"])
+    ap.add_argument("--train-instances", type=int, default=8)
     return ap.parse_args()
 
 
-def run_step(geneo, ctx, w, precision, b_host=None):
+def train_model(geneo, ctx, n_inst):
+    """Train the warm-start model on instances 1..n_inst of the workload
+    recipe (the measured instance is instance 0); the last one is held out."""
+    import workloads as W
+    t0 = time.perf_counter()
+    m = ctx.model_create(canvas=12, hidden=256, k=20, seed=2311)
+    for f in range(1, n_inst + 1):
+        w = W.make(2, family=f)
+        sysm = ctx.assemble(w.mesh, w.mu, w.eps, w.gamma, w.dirichlet)
+        dec = ctx.partition(sysm, "box", box=w.partition["p"], overlap=w.overlap)
+        pc = ctx.setup(sysm, dec, tau=w.tau, nev_max=w.nev_max, keep_ritz=1)
+        m.collect(sysm, dec, pc, holdout=(f == n_inst and n_inst > 1))
+        del pc, dec, sysm
+    t1 = time.perf_counter()
+    ti = m.train(epochs=30, batch=32, lr=1e-3, seed=0)
+    inf = m.info()
+    return m, {"instances": n_inst, "samples_train": inf.n_train, "samples_holdout": inf.n_holdout,
+               "params": inf.n_params, "data_s": t1 - t0, "train_ms": ti.train_ms,
+               "loss_first_epoch": ti.loss_first, "loss_last_epoch": ti.loss_last, "holdout_loss": ti.holdout_loss}
+
+
+def run_step(geneo, ctx, w, precision, b_host=None, model=None):
     import torch
     ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
     t0 = time.perf_counter()
@@ -60,7 +87,8 @@ def run_step(geneo, ctx, w, precision, b_host=None):
     x = torch.zeros(n, dtype=torch.float64, device="cuda:0")
     torch.cuda.synchronize()
     t2 = time.perf_counter()
-    pc = ctx.setup(sysm, dec, tau=w.tau, nev_max=w.nev_max, local_precision=precision)
+    kw = {"model": model} if model is not None else {}
+    pc = ctx.setup(sysm, dec, tau=w.tau, nev_max=w.nev_max, local_precision=precision, **kw)
     torch.cuda.synchronize()
     t3 = time.perf_counter()
     si = ctx.solve(sysm, pc, b, x, rtol=1e-8, maxit=2000)
@@ -75,7 +103,8 @@ def run_step(geneo, ctx, w, precision, b_host=None):
                t_extract_ms=pi.t_extract_ms, t_factor_ms=pi.t_factor_ms, t_gevp_ms=pi.t_gevp_ms,
                t_coarse_build_ms=pi.t_coarse_build_ms, t_coarse_factor_ms=pi.t_coarse_factor_ms,
                solve_ms=si.solve_ms, local_flops=pi.local_factor_flops, assemble_ms=sysm.info().assemble_ms,
-               fp64_fallbacks=pi.fp64_fallbacks, fp32_rho_est=pi.fp32_rho_est)
+               fp64_fallbacks=pi.fp64_fallbacks, fp32_rho_est=pi.fp32_rho_est,
+               learned_starts=pi.learned_starts, start_residual=pi.start_residual)
     del pc, dec, sysm
     return out, b_host
 
@@ -110,6 +139,25 @@ def cpu_baseline(w):
                        f"sum n_i^3 to all {dec.N} subdomains; coarse factor and PCG excluded")}
 
 
+def summarize(res):
+    mean = lambda k: float(np.mean([r[k] for r in res]))
+    last = res[-1]
+    return {
+        "setup_solve_s": mean("setup_solve_s"),
+        "phases_ms": {"assemble": mean("assemble_s") * 1e3, "partition_host": mean("partition_s") * 1e3,
+                      "setup": mean("setup_s") * 1e3, "solve": mean("solve_s") * 1e3,
+                      "extract": mean("t_extract_ms"), "local_factor": mean("t_factor_ms"),
+                      "gevp": mean("t_gevp_ms"), "coarse_build": mean("t_coarse_build_ms"),
+                      "coarse_factor": mean("t_coarse_factor_ms"), "pcg_device": mean("solve_ms")},
+        "local_factor_tflops": last["local_flops"] / (mean("t_factor_ms") * 1e-3) / 1e12,
+        "coarse_factor_tflops": last["n0"] ** 3 / 3.0 / (mean("t_coarse_factor_ms") * 1e-3) / 1e12,
+        "pcg_iterations": last["iterations"], "rel_residual": last["rel_residual"],
+        "lobpcg_iterations": last["lobpcg_iters"], "start_residual": last["start_residual"],
+        "learned_starts": last["learned_starts"], "fp64_fallbacks": last["fp64_fallbacks"],
+        "fp32_rho_est": last["fp32_rho_est"] if np.isfinite(last["fp32_rho_est"]) else "inf",
+    }
+
+
 def main():
     a = parse()
     if a.gpus != 1:
@@ -121,38 +169,42 @@ def main():
     wid = int(a.workload) if a.workload.isdigit() else a.workload
     w = W.make(wid)
     ctx = geneo.Context(0)
+    variants = {"learned_fp32": (geneo.FP32_REFINE1, True), "fp64": (geneo.FP64, False)}
+    run = [v for v in ("learned_fp32", "fp64") if a.variant in ("both", v)]
+    model, training = None, None
+    if "learned_fp32" in run:
+        model, training = train_model(geneo, ctx, a.train_instances)
     b_host = None
-    prec = geneo.FP64 if a.precision == "fp64" else geneo.FP32_REFINE1
     for _ in range(a.warmup):
-        _, b_host = run_step(geneo, ctx, w, prec, b_host)
+        for v in run:
+            prec, learned = variants[v]
+            _, b_host = run_step(geneo, ctx, w, prec, b_host, model if learned else None)
     torch.cuda.synchronize()
+    res = {v: [] for v in run}
     t0 = time.perf_counter()
-    res = []
     for _ in range(a.steps):
-        r, b_host = run_step(geneo, ctx, w, prec, b_host)
-        res.append(r)
+        for v in run:
+            prec, learned = variants[v]
+            r, b_host = run_step(geneo, ctx, w, prec, b_host, model if learned else None)
+            res[v].append(r)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
-    last = res[-1]
-    mean = lambda k: float(np.mean([r[k] for r in res]))
-    local_tf = last["local_flops"] / (mean("t_factor_ms") * 1e-3) / 1e12
-    n0p = ((last["n0"] + 127) // 128) * 128
-    coarse_flops = last["n0"] ** 3 / 3.0
-    coarse_tf = coarse_flops / (mean("t_coarse_factor_ms") * 1e-3) / 1e12
-    # dominant kernel family: the batched Cholesky phase that takes longest
-    if mean("t_coarse_factor_ms") >= mean("t_factor_ms"):
-        dom = ("coarse Cholesky of E (potrf/trsm/syrk, FP64 MFMA)", coarse_flops, mean("t_coarse_factor_ms"))
-    else:
-        dom = ("batched local Cholesky of A_i (potrf/trsm/syrk, FP64 MFMA)", last["local_flops"], mean("t_factor_ms"))
-    achieved = dom[1] / (dom[2] * 1e-3) / 1e12
+    summ = {v: summarize(res[v]) for v in run}
+    head = run[0]
+    last = res[head][-1]
+    plain = res["fp64"] if "fp64" in res else res[head]
+    # dominant kernel family: the FP64 coarse Cholesky (potrf/trsm/syrk launches of one factorisation)
+    cf_ms = float(np.mean([r["t_coarse_factor_ms"] for r in plain]))
+    n0 = plain[-1]["n0"]
+    achieved = n0 ** 3 / 3.0 / (cf_ms * 1e-3) / 1e12
     line = {
         "metric": METRIC,
-        "value": mean("setup_solve_s"),
+        "value": summ[head]["setup_solve_s"],
         "unit": "s",
         "n_gpus": 1,
         "steps": a.steps,
         "warmup": a.warmup,
-        "ms_per_step": wall / a.steps * 1e3,
+        "ms_per_step": wall / (a.steps * len(run)) * 1e3,
         "higher_is_better": False,
         "scaling": "weak",
         "vs_baseline": None,
@@ -160,23 +212,19 @@ def main():
         "data": "synthetic",
         "config": {"workload": w.name + ": 24^3 hexes x 6 tets (82,944), mu in {1,1e4} channels >= 10%, "
                                "eps=1, gamma=1e-4, all-Dirichlet, 4x4x4 boxes, overlap 2, tau=10, "
-                               "<=20 GenEO vectors/subdomain, PCG rtol 1e-8, local factors FP64",
-                   "n": last["n"], "n_sub": last["n_sub"], "n_i_min": last["n_min"], "n_i_max": last["n_max"],
-                   "n0": last["n0"], "n0_rank": last["n0_rank"], "n_geneo": last["n_geneo"],
-                   "parallelism": "1 GPU"},
-        "phases_ms": {"assemble": mean("assemble_s") * 1e3, "partition_host": mean("partition_s") * 1e3,
-                      "setup": mean("setup_s") * 1e3, "solve": mean("solve_s") * 1e3,
-                      "extract": mean("t_extract_ms"), "local_factor": mean("t_factor_ms"),
-                      "gevp": mean("t_gevp_ms"), "coarse_build": mean("t_coarse_build_ms"),
-                      "coarse_factor": mean("t_coarse_factor_ms"), "pcg_device": mean("solve_ms")},
-        "pcg_iterations": last["iterations"],
-        "fp64_fallbacks": last["fp64_fallbacks"], "fp32_rho_est": last["fp32_rho_est"],
-        "lobpcg_iterations": last["lobpcg_iters"],
-        "local_factor_tflops": local_tf,
-        "coarse_factor_tflops": coarse_tf,
-        "roofline": {"bound": "mfma", "kernel": dom[0], "achieved": achieved, "peak": PEAK_FP64_TFLOPS,
-                     "unit": "TFLOP/s", "frac": achieved / PEAK_FP64_TFLOPS, "traffic": None},
+                               "<=20 GenEO vectors/subdomain, PCG rtol 1e-8",
+                   "variant": head, "n": last["n"], "n_sub": last["n_sub"], "n_i_min": last["n_min"],
+                   "n_i_max": last["n_max"], "n0": last["n0"], "n0_rank": last["n0_rank"],
+                   "n_geneo": last["n_geneo"], "parallelism": "1 GPU"},
+        "variants": summ,
+        "roofline": {"bound": "mfma", "kernel": "FP64 coarse Cholesky of E (potrf/trsm/syrk launches)",
+                     "achieved": achieved, "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
+                     "frac": achieved / PEAK_FP64_TFLOPS, "traffic": None},
     }
+    if "fp64" in summ and head != "fp64":
+        line["speedup_vs_plain_fp64"] = summ["fp64"]["setup_solve_s"] / summ[head]["setup_solve_s"]
+    if training:
+        line["warm_start_training"] = training
     if not a.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(w)
     print(json.dumps(line), flush=True)
