@@ -297,14 +297,14 @@ int geneo_potrf_batched(geneo_ctx* ctx, int32_t batch, const int32_t* n_host, co
       DevBuf<double> inv;
       inv.alloc(inv_off);
       HIP_CHECK(hipEventRecord(ctx->ev[0], ctx->stream));
-      factor(P, (double*)A, inv.p, nullptr, 0.0, nullptr, ctx->d_err, ctx->stream);
+      factor(P, (double*)A, inv.p, nullptr, 0.0, nullptr, ctx->d_err, ctx->stream, nullptr, false);
       HIP_CHECK(hipEventRecord(ctx->ev[1], ctx->stream));
       HIP_CHECK(hipEventSynchronize(ctx->ev[1]));
     } else if (precision == GENEO_FP32_REFINE1) {
       DevBuf<float> inv;
       inv.alloc(inv_off);
       HIP_CHECK(hipEventRecord(ctx->ev[0], ctx->stream));
-      factor(P, (float*)A, inv.p, nullptr, 0.0, nullptr, ctx->d_err, ctx->stream);
+      factor(P, (float*)A, inv.p, nullptr, 0.0, nullptr, ctx->d_err, ctx->stream, nullptr, false);
       HIP_CHECK(hipEventRecord(ctx->ev[1], ctx->stream));
       HIP_CHECK(hipEventSynchronize(ctx->ev[1]));
     } else {

@@ -41,11 +41,15 @@ struct FactorPlan {
 
 // failed: if given, a non-positive pivot of matrix m sets failed[m] = 1 and
 // the column is treated as dropped, instead of raising GENEO_ENOTSPD.
+// for_solves = false leaves L in the lower triangle (upper untouched);
+// otherwise the factor is put in solve form: the strictly upper blocks
+// receive U = L^T, then every off-diagonal block is premultiplied by the
+// inverse of its row's diagonal block (lower: inv(L_II) L(I,J); upper:
+// inv(U_II) U(I,J)); only solve() / solve_multi() read that form.
 void factor(const FactorPlan& P, double* A, double* Ainv, const double* odiag, double drop_tol, double* pivrel,
-            DevErr* err, hipStream_t st, int32_t* failed = nullptr);
+            DevErr* err, hipStream_t st, int32_t* failed = nullptr, bool for_solves = true);
 void factor(const FactorPlan& P, float* A, float* Ainv, const double* odiag, double drop_tol, double* pivrel,
-            DevErr* err, hipStream_t st, int32_t* failed = nullptr);
-// Factor in place; afterwards the strictly upper blocks hold U = L^T.
+            DevErr* err, hipStream_t st, int32_t* failed = nullptr, bool for_solves = true);
 // x <- (L L^T)^-1 x on every matrix segment of the batch vector x.
 void solve(const FactorPlan& P, const double* A, const double* Ainv, double* x, unsigned* sync, unsigned* flags,
            DevErr* err, hipStream_t st);

@@ -588,15 +588,22 @@ static void factor_impl(const FactorPlan& P, T* A, T* Ainv, const double* odiag,
 template <typename T>
 static void mirror_impl(const FactorPlan& P, T* A, hipStream_t st);
 
+template <typename T>
+static void qblocks_impl(const FactorPlan& P, T* A, const T* Ainv, hipStream_t st);
+
 void factor(const FactorPlan& P, double* A, double* Ainv, const double* odiag, double drop_tol, double* pivrel,
-            DevErr* err, hipStream_t st, int32_t* failed) {
+            DevErr* err, hipStream_t st, int32_t* failed, bool for_solves) {
   factor_impl<double>(P, A, Ainv, odiag, drop_tol, pivrel, err, st, failed);
+  if (!for_solves) return;
   mirror_impl<double>(P, A, st);
+  qblocks_impl<double>(P, A, Ainv, st);
 }
 void factor(const FactorPlan& P, float* A, float* Ainv, const double* odiag, double drop_tol, double* pivrel,
-            DevErr* err, hipStream_t st, int32_t* failed) {
+            DevErr* err, hipStream_t st, int32_t* failed, bool for_solves) {
   factor_impl<float>(P, A, Ainv, odiag, drop_tol, pivrel, err, st, failed);
+  if (!for_solves) return;
   mirror_impl<float>(P, A, st);
+  qblocks_impl<float>(P, A, Ainv, st);
 }
 
 // ------------------------------------------------------- triangular solves
@@ -645,6 +652,70 @@ __global__ __launch_bounds__(256) void k_mirror(const MatDesc* __restrict__ desc
   }
 }
 
+// C[m][n] = sum_k Ar[k lda + m] Bt[n ldb + k] over K = NB (B read transposed),
+// four waves of 64 x 64 as in mode 0
+template <typename T>
+__device__ inline void tile_mma_bt(const T* __restrict__ Ar, int64_t lda, const T* __restrict__ Bt, int64_t ldb,
+                                   typename AccT<T>::type acc[4][4]) {
+  const int lane = threadIdx.x & 63;
+  const int lr = lane & 15, lk = lane >> 4;
+  Ar += 64 * TileGeo<0>::wr();
+  Bt += 64 * TileGeo<0>::wc() * ldb;
+  for (int kk = 0; kk < NB; kk += 4) {
+    T af[4], bf[4];
+#pragma unroll
+    for (int b = 0; b < 4; ++b) {
+      af[b] = Ar[(int64_t)(kk + lk) * lda + 16 * b + lr];
+      bf[b] = Bt[(int64_t)(16 * b + lr) * ldb + kk + lk];
+    }
+#pragma unroll
+    for (int bi = 0; bi < 4; ++bi)
+#pragma unroll
+      for (int bj = 0; bj < 4; ++bj) acc[bi][bj] = mfma16(af[bi], bf[bj], acc[bi][bj]);
+  }
+}
+
+// Solve form of the factor: every strictly lower block L(I,J) becomes
+// inv(L_II) L(I,J) and every strictly upper block U(J,I) (the mirror)
+// becomes inv(U_JJ) U(J,I), in place.  A block solve then reads
+//   x_I = inv(L_II) b_I - sum_J [inv(L_II) L(I,J)] x_J,
+// so once the last dependency arrives only one block product remains on the
+// critical path.  One workgroup per pair of mirrored blocks.
+template <typename T>
+__global__ __launch_bounds__(256) void k_qblocks(const MatDesc* __restrict__ desc, const int32_t* __restrict__ order,
+                                                 const int64_t* __restrict__ prefix, int cnt, T* __restrict__ A,
+                                                 const T* __restrict__ Ainv) {
+  const int j = find_mat(prefix, cnt, blockIdx.x);
+  const MatDesc d = desc[order[j]];
+  const int64_t u = blockIdx.x - prefix[j];
+  int64_t ti = (int64_t)((sqrt(8.0 * (double)u + 1.0) + 1.0) * 0.5);
+  while (ti * (ti - 1) / 2 > u) --ti;
+  while ((ti + 1) * ti / 2 <= u) ++ti;
+  const int64_t tj = u - ti * (ti - 1) / 2;   // ti > tj
+  using Acc = typename AccT<T>::type;
+  Acc lo[4][4], up[4][4];
+#pragma unroll
+  for (int bi = 0; bi < 4; ++bi)
+#pragma unroll
+    for (int bj = 0; bj < 4; ++bj) {
+      lo[bi][bj] = Acc{0, 0, 0, 0};
+      up[bi][bj] = Acc{0, 0, 0, 0};
+    }
+  // lower block (ti, tj): column-major at column tj*NB, row ti*NB
+  T* L = A + d.off + tj * NB * d.ld + ti * NB;
+  // upper block (tj, ti): column-major at column ti*NB, row tj*NB
+  T* U = A + d.off + ti * NB * d.ld + tj * NB;
+  const T* invL = Ainv + d.inv_off + ti * NB * NB;
+  const T* invU = Ainv + d.inv_off + ((int64_t)d.nblk + tj) * NB * NB;
+  // B(k, n) = block[k][n] = block[n * ld + k]
+  tile_mma_bt<T>(invL, NB, L, d.ld, lo);
+  tile_mma_bt<T>(invU, NB, U, d.ld, up);
+  __syncthreads();   // both blocks fully read
+  const int64_t off = (int64_t)(TileGeo<0>::WCOL * TileGeo<0>::wc()) * d.ld + 64 * TileGeo<0>::wr();
+  tile_store<T, 4>(L + off, d.ld, lo);
+  tile_store<T, 4>(U + off, d.ld, up);
+}
+
 __global__ void k_solve_begin(unsigned* sync) {
   sync[0] = 0;
   sync[1] = sync[1] + 1;
@@ -683,7 +754,11 @@ __device__ inline void store_coherent(double* p, double v) {
 }
 
 // One triangular solve, single right-hand side: x <- L^-1 x (UPPER = false)
-// or x <- U^-1 x (UPPER = true) on every matrix segment of the batch vector.
+// or x <- U^-1 x (UPPER = true) on every matrix segment of the batch vector,
+// with the factor in solve form (k_qblocks): x_I = c_I - sum_J Q(I,J) x_J,
+// c_I = inv(D_II) b_I.  The workgroup computes c_I and loads the block of
+// its last dependency into registers before waiting, so when that
+// dependency lands only a register-resident 128 x 128 product is left.
 template <typename T, bool UPPER>
 __global__ __launch_bounds__(256) void k_trsv(const MatDesc* __restrict__ desc, const int32_t* __restrict__ items,
                                               const T* __restrict__ A, const T* __restrict__ Ainv, double* x,
@@ -704,12 +779,27 @@ __global__ __launch_bounds__(256) void k_trsv(const MatDesc* __restrict__ desc, 
   double* xv = x + d.voff;
   const int r = tid & (NB - 1), h = tid >> 7;
   __shared__ int s_front;
-  double acc = 0.0;
   // dependencies: forward J = 0..I-1 (done in increasing order),
-  // backward J = nblk-1..I+1 (done in decreasing order)
-  const int J0 = UPPER ? d.nblk - 1 : 0, Jend = UPPER ? I : I, dir = UPPER ? -1 : 1;
+  // backward J = nblk-1..I+1 (done in decreasing order); the last one is Jl
+  const int J0 = UPPER ? d.nblk - 1 : 0, Jend = I, dir = UPPER ? -1 : 1;
+  const int Jl = I - dir;
+  const bool has_dep = UPPER ? I < d.nblk - 1 : I > 0;
+  // block of the last dependency, register resident: q[c] = Q(I,Jl)[r][64h + c]
+  T q[64];
+  if (has_dep) {
+    const T* col = A + d.off + ((int64_t)Jl * NB + 64 * h) * d.ld + (int64_t)I * NB + r;
+#pragma unroll
+    for (int c = 0; c < 64; ++c) q[c] = col[(int64_t)c * d.ld];
+  }
+  // c_I = inv(D_II) b_I (b_I is this block's own entry, written before this launch)
+  if (tid < NB) xs[tid] = xv[(int64_t)I * NB + tid];
+  __syncthreads();
+  const T* inv = Ainv + d.inv_off + ((UPPER ? d.nblk : 0) + (int64_t)I) * NB * NB;
+  double acc = 0.0;
+#pragma unroll 8
+  for (int c = 0; c < 64; ++c) acc -= (double)inv[(int64_t)(64 * h + c) * NB + r] * xs[64 * h + c];
   if (tid == 0) s_front = J0;
-  for (int J = J0; J != Jend; J += dir) {
+  for (int J = J0; J != Jl && has_dep; J += dir) {
     if (tid == 0 && J == s_front) s_front = wait_frontier(flags + d.flag_off, J, Jend, dir, epoch, err);
     __syncthreads();
     if (tid < NB) xs[tid] = load_coherent(xv + (int64_t)J * NB + tid);
@@ -717,19 +807,18 @@ __global__ __launch_bounds__(256) void k_trsv(const MatDesc* __restrict__ desc, 
     const T* col = A + d.off + ((int64_t)J * NB + 64 * h) * d.ld + (int64_t)I * NB + r;
 #pragma unroll 8
     for (int c = 0; c < 64; ++c) acc += (double)col[(int64_t)c * d.ld] * xs[64 * h + c];
+  }
+  if (has_dep) {
+    if (tid == 0 && Jl == s_front) s_front = wait_frontier(flags + d.flag_off, Jl, Jend, dir, epoch, err);
     __syncthreads();
+    if (tid < NB) xs[tid] = load_coherent(xv + (int64_t)Jl * NB + tid);
+    __syncthreads();
+#pragma unroll
+    for (int c = 0; c < 64; ++c) acc += (double)q[c] * xs[64 * h + c];
   }
   red[tid] = acc;
   __syncthreads();
-  if (tid < NB) xs[tid] = xv[(int64_t)I * NB + tid] - red[tid] - red[tid + NB];
-  __syncthreads();
-  const T* inv = Ainv + d.inv_off + ((UPPER ? d.nblk : 0) + (int64_t)I) * NB * NB;
-  double acc2 = 0.0;
-#pragma unroll 8
-  for (int c = 0; c < 64; ++c) acc2 += (double)inv[(int64_t)(64 * h + c) * NB + r] * xs[64 * h + c];
-  red[tid] = acc2;
-  __syncthreads();
-  if (tid < NB) store_coherent(xv + (int64_t)I * NB + tid, red[tid] + red[tid + NB]);
+  if (tid < NB) store_coherent(xv + (int64_t)I * NB + tid, -(red[tid] + red[tid + NB]));
   __syncthreads();
   if (tid == 0) publish(flags + d.flag_off + I, epoch);
 }
@@ -758,8 +847,23 @@ __global__ __launch_bounds__(256) void k_trsm_multi(const MatDesc* __restrict__ 
   double* Xm = X + d.voff * (int64_t)ldk;
   const int r = tid & (NB - 1), g = tid >> 7;
   double acc[H];
+  // acc = -inv(D_II) B_I first (solve form of the factor, see k_qblocks)
+  for (int idx = tid; idx < NB * KC; idx += 256) {
+    int rr = idx & (NB - 1), q = idx >> 7;
+    xs[rr * KC + q] = q < k ? Xm[(int64_t)q * d.ld + (int64_t)I * NB + rr] : 0.0;
+  }
+  __syncthreads();
+  {
+    const T* inv = Ainv + d.inv_off + ((UPPER ? d.nblk : 0) + (int64_t)I) * NB * NB;
 #pragma unroll
-  for (int q = 0; q < H; ++q) acc[q] = 0.0;
+    for (int q = 0; q < H; ++q) acc[q] = 0.0;
+    for (int c = 0; c < NB; ++c) {
+      const double l = (double)inv[(int64_t)c * NB + r];
+#pragma unroll
+      for (int q = 0; q < H; ++q) acc[q] -= l * xs[c * KC + g * H + q];
+    }
+  }
+  __syncthreads();
   __shared__ int s_front;
   const int J0 = UPPER ? d.nblk - 1 : 0, Jend = UPPER ? I : I, dir = UPPER ? -1 : 1;
   if (tid == 0) s_front = J0;
@@ -779,25 +883,10 @@ __global__ __launch_bounds__(256) void k_trsm_multi(const MatDesc* __restrict__ 
     }
     __syncthreads();
   }
-  // s = X_I - acc  -> xs
 #pragma unroll
   for (int q = 0; q < H; ++q) {
     const int qq = g * H + q;
-    xs[r * KC + qq] = (qq < k ? Xm[(int64_t)qq * d.ld + (int64_t)I * NB + r] : 0.0) - acc[q];
-  }
-  __syncthreads();
-  const T* inv = Ainv + d.inv_off + ((UPPER ? d.nblk : 0) + (int64_t)I) * NB * NB;
-#pragma unroll
-  for (int q = 0; q < H; ++q) acc[q] = 0.0;
-  for (int c = 0; c < NB; ++c) {
-    const double l = (double)inv[(int64_t)c * NB + r];
-#pragma unroll
-    for (int q = 0; q < H; ++q) acc[q] += l * xs[c * KC + g * H + q];
-  }
-#pragma unroll
-  for (int q = 0; q < H; ++q) {
-    const int qq = g * H + q;
-    if (qq < k) store_coherent(Xm + (int64_t)qq * d.ld + (int64_t)I * NB + r, acc[q]);
+    if (qq < k) store_coherent(Xm + (int64_t)qq * d.ld + (int64_t)I * NB + r, -acc[q]);
   }
   __syncthreads();
   if (tid == 0) publish(flags + d.flag_off + I, epoch);
@@ -808,6 +897,14 @@ static void mirror_impl(const FactorPlan& P, T* A, hipStream_t st) {
   if (P.mirror_tiles > 0)
     k_mirror<T><<<dim3((unsigned)P.mirror_tiles), dim3(256), 0, st>>>(P.d_desc.p, P.d_order.p, P.d_mirror_prefix.p,
                                                                       P.nmat, A);
+}
+
+template <typename T>
+static void qblocks_impl(const FactorPlan& P, T* A, const T* Ainv, hipStream_t st) {
+  if (P.mirror_tiles > 0)
+    k_qblocks<T><<<dim3((unsigned)P.mirror_tiles), dim3(256), 0, st>>>(P.d_desc.p, P.d_order.p, P.d_mirror_prefix.p,
+                                                                       P.nmat, A, Ainv);
+  HIP_CHECK(hipGetLastError());
 }
 
 template <typename T>
