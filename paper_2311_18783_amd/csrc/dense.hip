@@ -892,6 +892,82 @@ __global__ __launch_bounds__(256) void k_trsm_multi(const MatDesc* __restrict__ 
   if (tid == 0) publish(flags + d.flag_off + I, epoch);
 }
 
+// FP64 many-right-hand-side solve on MFMA: the block products
+// Q(I,J) X_J (128 x 128 by 128 x 32) run as v_mfma_f64_16x16x4 tiles, wave
+// w owning rows 32w..32w+31 and all 32 columns; X_J is staged in LDS.
+template <bool UPPER>
+__global__ __launch_bounds__(256) void k_trsm_multi_mfma(const MatDesc* __restrict__ desc,
+                                                         const int32_t* __restrict__ items,
+                                                         const double* __restrict__ A,
+                                                         const double* __restrict__ Ainv, double* X, int ldk, int k,
+                                                         unsigned* sync, unsigned* flags, DevErr* err) {
+  constexpr int KC = 32, XP = KC + 1;
+  __shared__ double xs[NB * XP];   // [row][column]
+  __shared__ int s_t;
+  __shared__ unsigned s_epoch;
+  __shared__ int s_front;
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const int lr = lane & 15, lk = lane >> 4;
+  if (tid == 0) {
+    s_t = (int)atomicAdd(&sync[0], 1u);
+    s_epoch = __hip_atomic_load(&sync[1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  }
+  __syncthreads();
+  const int m = items[2 * s_t], I = items[2 * s_t + 1];
+  const unsigned epoch = s_epoch;
+  const MatDesc d = desc[m];
+  double* Xm = X + d.voff * (int64_t)ldk;
+  d4_t acc[2][2];
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j) acc[i][j] = d4_t{0, 0, 0, 0};
+  // acc += Ablk (128 x 128, element (r, c) at Ablk[c * lda + r]) times xs (128 x 32)
+  auto block_product = [&](const double* __restrict__ Ablk, int64_t lda) {
+    const double* Ar = Ablk + 32 * w + lr;
+    for (int kk = 0; kk < NB; kk += 4) {
+      const double a0 = Ar[(int64_t)(kk + lk) * lda], a1 = Ar[(int64_t)(kk + lk) * lda + 16];
+      const double b0 = xs[(kk + lk) * XP + lr], b1 = xs[(kk + lk) * XP + 16 + lr];
+      acc[0][0] = mfma16(a0, b0, acc[0][0]);
+      acc[0][1] = mfma16(a0, b1, acc[0][1]);
+      acc[1][0] = mfma16(a1, b0, acc[1][0]);
+      acc[1][1] = mfma16(a1, b1, acc[1][1]);
+    }
+  };
+  // -c_I = -inv(D_II) B_I
+  for (int idx = tid; idx < NB * KC; idx += 256) {
+    const int rr = idx & (NB - 1), q = idx >> 7;
+    xs[rr * XP + q] = q < k ? -Xm[(int64_t)q * d.ld + (int64_t)I * NB + rr] : 0.0;
+  }
+  __syncthreads();
+  block_product(Ainv + d.inv_off + ((UPPER ? d.nblk : 0) + (int64_t)I) * NB * NB, NB);
+  const int J0 = UPPER ? d.nblk - 1 : 0, Jend = I, dir = UPPER ? -1 : 1;
+  if (tid == 0) s_front = J0;
+  for (int J = J0; J != Jend; J += dir) {
+    if (tid == 0 && J == s_front) s_front = wait_frontier(flags + d.flag_off, J, Jend, dir, epoch, err);
+    __syncthreads();   // also: every wave is done with the previous xs
+    for (int idx = tid; idx < NB * KC; idx += 256) {
+      const int rr = idx & (NB - 1), q = idx >> 7;
+      xs[rr * XP + q] = q < k ? load_coherent(Xm + (int64_t)q * d.ld + (int64_t)J * NB + rr) : 0.0;
+    }
+    __syncthreads();
+    block_product(A + d.off + (int64_t)J * NB * d.ld + (int64_t)I * NB, d.ld);
+  }
+  // X_I = -acc
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int row = 32 * w + 16 * i + acc_row<double>(lane, v);
+        const int col = 16 * j + lr;
+        if (col < k) store_coherent(Xm + (int64_t)col * d.ld + (int64_t)I * NB + row, -acc[i][j][v]);
+      }
+  __syncthreads();
+  if (tid == 0) publish(flags + d.flag_off + I, epoch);
+}
+
 template <typename T>
 static void mirror_impl(const FactorPlan& P, T* A, hipStream_t st) {
   if (P.mirror_tiles > 0)
@@ -947,7 +1023,23 @@ void solve(const FactorPlan& P, const float* A, const float* Ainv, double* x, un
 }
 void solve_multi(const FactorPlan& P, const double* A, const double* Ainv, double* X, int ldk, int k,
                  unsigned* sync, unsigned* flags, DevErr* err, hipStream_t st) {
-  solve_multi_impl<double>(P, A, Ainv, X, ldk, k, sync, flags, err, st);
+  static const bool valu = [] {
+    const char* e = std::getenv("GENEO_TRSM_MULTI");
+    return e && std::string(e) == "valu";
+  }();
+  if (valu) {
+    solve_multi_impl<double>(P, A, Ainv, X, ldk, k, sync, flags, err, st);
+    return;
+  }
+  if (P.n_items == 0 || k == 0) return;
+  if (k > 32) throw Error(GENEO_EUNSUPPORTED, "more than 32 right-hand sides");
+  k_solve_begin<<<1, 1, 0, st>>>(sync);
+  k_trsm_multi_mfma<false><<<dim3((unsigned)P.n_items), dim3(256), 0, st>>>(P.d_desc.p, P.d_items_fwd.p, A, Ainv, X,
+                                                                            ldk, k, sync, flags, err);
+  k_solve_begin<<<1, 1, 0, st>>>(sync);
+  k_trsm_multi_mfma<true><<<dim3((unsigned)P.n_items), dim3(256), 0, st>>>(P.d_desc.p, P.d_items_bwd.p, A, Ainv, X,
+                                                                           ldk, k, sync, flags, err);
+  HIP_CHECK(hipGetLastError());
 }
 void solve_multi(const FactorPlan& P, const float* A, const float* Ainv, double* X, int ldk, int k,
                  unsigned* sync, unsigned* flags, DevErr* err, hipStream_t st) {

@@ -264,6 +264,7 @@ __global__ void k_gram_reduce(int m, const int64_t* __restrict__ chunk_off, cons
 
 // ---------------------------------------------------- Rayleigh-Ritz (LDS)
 constexpr int kMaxM = 72;
+constexpr int kRRThreads = 1024;   // threads of the Rayleigh-Ritz workgroup (Jacobi rotations in parallel)
 
 // Jacobi eigendecomposition of the symmetric n x n matrix a (row-major, ld),
 // eigenvectors in v; parallel round-robin ordering, all threads of the block.
@@ -282,16 +283,16 @@ __device__ void jacobi_eig(double* a, double* v, int n, int ld, double* rot_c, d
       if (i == j) dia += x * x; else off += x * x;
     }
     red[tid] = off;
-    red[256 + tid] = dia;
+    red[kRRThreads + tid] = dia;
     __syncthreads();
-    for (int s = 128; s > 0; s >>= 1) {
+    for (int s = kRRThreads / 2; s > 0; s >>= 1) {
       if (tid < s) {
         red[tid] += red[tid + s];
-        red[256 + tid] += red[256 + tid + s];
+        red[kRRThreads + tid] += red[kRRThreads + tid + s];
       }
       __syncthreads();
     }
-    const bool done = red[0] <= 1e-30 * red[256] || red[0] == 0.0;
+    const bool done = red[0] <= 1e-30 * red[kRRThreads] || red[0] == 0.0;
     __syncthreads();
     if (done) break;
     for (int round = 0; round < ne - 1; ++round) {
@@ -356,14 +357,14 @@ __device__ void jacobi_eig(double* a, double* v, int n, int ld, double* rot_c, d
 // column-major).  Inactive subdomains are skipped.
 // svqb != 0: only B-orthonormalise: coef = diag(dsc) U (m x n2, zero columns
 // up to k), theta untouched.
-__global__ __launch_bounds__(256) void k_rayleigh_ritz(int m, int k, const double* __restrict__ gram,
+__global__ __launch_bounds__(kRRThreads) void k_rayleigh_ritz(int m, int k, const double* __restrict__ gram,
                                                        const int32_t* __restrict__ active, double drop,
                                                        double* __restrict__ theta, double* __restrict__ coef,
                                                        int svqb) {
   const int j = blockIdx.x;
   if (active && !active[j]) return;
   __shared__ double A[kMaxM * kMaxM], B[kMaxM * kMaxM], V[kMaxM * kMaxM];
-  __shared__ double dsc[kMaxM], lam[kMaxM], rc[kMaxM / 2 + 1], rs[kMaxM / 2 + 1], red[512];
+  __shared__ double dsc[kMaxM], lam[kMaxM], rc[kMaxM / 2 + 1], rs[kMaxM / 2 + 1], red[2 * kRRThreads];
   __shared__ int pp[kMaxM / 2 + 1], qq[kMaxM / 2 + 1], keep[kMaxM], order[kMaxM];
   __shared__ int nk;
   const int tid = threadIdx.x;
@@ -371,7 +372,7 @@ __global__ __launch_bounds__(256) void k_rayleigh_ritz(int m, int k, const doubl
   const double* GA = gram + (int64_t)j * 2 * mm;
   const double* GB = GA + mm;
   // symmetrise; diagonal scaling of the B-Gram
-  for (int idx = tid; idx < mm; idx += 256) {
+  for (int idx = tid; idx < mm; idx += kRRThreads) {
     const int a = idx % m, b = idx / m;
     A[a * m + b] = 0.5 * (GA[a + b * m] + GA[b + a * m]);
     B[a * m + b] = 0.5 * (GB[a + b * m] + GB[b + a * m]);
@@ -382,7 +383,7 @@ __global__ __launch_bounds__(256) void k_rayleigh_ritz(int m, int k, const doubl
     dsc[tid] = d > 0.0 ? 1.0 / sqrt(d) : 0.0;
   }
   __syncthreads();
-  for (int idx = tid; idx < mm; idx += 256) {
+  for (int idx = tid; idx < mm; idx += kRRThreads) {
     const int a = idx / m, b = idx % m;
     A[a * m + b] *= dsc[a] * dsc[b];
     B[a * m + b] *= dsc[a] * dsc[b];
@@ -402,35 +403,35 @@ __global__ __launch_bounds__(256) void k_rayleigh_ritz(int m, int k, const doubl
   __syncthreads();
   const int n2 = nk;
   // U = V[:, keep] / sqrt(lambda) stored in B (m x n2, row-major ld m)
-  for (int idx = tid; idx < m * n2; idx += 256) {
+  for (int idx = tid; idx < m * n2; idx += kRRThreads) {
     const int r = idx / n2, c = idx % n2;
     const int col = keep[c];
     B[r * m + c] = V[r * m + col] / sqrt(lam[col]);
   }
   __syncthreads();
   if (svqb) {
-    for (int idx = tid; idx < m * k; idx += 256) {
+    for (int idx = tid; idx < m * k; idx += kRRThreads) {
       const int r = idx % m, c = idx / m;
       coef[(int64_t)j * m * k + (int64_t)c * m + r] = c < n2 ? dsc[r] * B[r * m + c] : 0.0;
     }
     return;
   }
   // V <- A U (m x n2), then A <- U^T V (n2 x n2)
-  for (int idx = tid; idx < m * n2; idx += 256) {
+  for (int idx = tid; idx < m * n2; idx += kRRThreads) {
     const int r = idx / n2, c = idx % n2;
     double s = 0.0;
     for (int t = 0; t < m; ++t) s += A[r * m + t] * B[t * m + c];
     V[r * m + c] = s;
   }
   __syncthreads();
-  for (int idx = tid; idx < n2 * n2; idx += 256) {
+  for (int idx = tid; idx < n2 * n2; idx += kRRThreads) {
     const int r = idx / n2, c = idx % n2;
     double s = 0.0;
     for (int t = 0; t < m; ++t) s += B[t * m + r] * V[t * m + c];
     A[r * m + c] = s;
   }
   __syncthreads();
-  for (int idx = tid; idx < n2 * n2; idx += 256) {
+  for (int idx = tid; idx < n2 * n2; idx += kRRThreads) {
     const int r = idx / n2, c = idx % n2;
     if (r < c) {
       const double s = 0.5 * (A[r * m + c] + A[c * m + r]);
@@ -457,7 +458,7 @@ __global__ __launch_bounds__(256) void k_rayleigh_ritz(int m, int k, const doubl
   }
   __syncthreads();
   // coef = diag(dsc) U Y[:, order[0..k)]  (m x k); missing columns -> 0
-  for (int idx = tid; idx < m * k; idx += 256) {
+  for (int idx = tid; idx < m * k; idx += kRRThreads) {
     const int r = idx % m, c = idx / m;
     double s = 0.0;
     if (c < n2) {
@@ -897,7 +898,7 @@ void solve_local_gevps(geneo_ctx* ctx, geneo_precond* pc) {
   auto svqb2 = [&](DevBuf<double>& V, DevBuf<double>& BV, const int32_t* a) {
     for (int t = 0; t < 2; ++t) {
       gram(w, 1, V.p, nullptr, nullptr, BV.p, nullptr, nullptr, BV.p, nullptr, nullptr, part, g, st);
-      k_rayleigh_ritz<<<N, 256, 0, st>>>(k, k, g.p, a, drop, theta.p, coef.p, 1);
+      k_rayleigh_ritz<<<N, kRRThreads, 0, st>>>(k, k, g.p, a, drop, theta.p, coef.p, 1);
       k_combine<<<nb256(blk), 256, 0, st>>>(w.len, k, k, 0, w.row_sub.p, w.voff_d.p, a, V.p, nullptr, nullptr,
                                             coef.p, V.p, Tv.p);
       k_combine<<<nb256(blk), 256, 0, st>>>(w.len, k, k, 0, w.row_sub.p, w.voff_d.p, a, BV.p, nullptr, nullptr,
@@ -910,7 +911,7 @@ void solve_local_gevps(geneo_ctx* ctx, geneo_precond* pc) {
   svqb2(X, BX, nullptr);
   apply_atilde(ctx, pc, w, X.p, AX.p, T1.p, T2.p, NT.p);
   gram(w, 1, X.p, nullptr, nullptr, AX.p, nullptr, nullptr, BX.p, nullptr, nullptr, part, g, st);
-  k_rayleigh_ritz<<<N, 256, 0, st>>>(k, k, g.p, nullptr, drop, theta.p, coef.p, 0);
+  k_rayleigh_ritz<<<N, kRRThreads, 0, st>>>(k, k, g.p, nullptr, drop, theta.p, coef.p, 0);
   k_combine<<<nb256(blk), 256, 0, st>>>(w.len, k, k, 0, w.row_sub.p, w.voff_d.p, nullptr, X.p, nullptr, nullptr,
                                         coef.p, nullptr, Xn.p);
   std::swap(X.p, Xn.p);
@@ -1003,7 +1004,7 @@ void solve_local_gevps(geneo_ctx* ctx, geneo_precond* pc) {
     const int m = nl * k;
     gram(w, nl, X.p, Wb.p, have_p ? P.p : nullptr, AX.p, AW.p, have_p ? AP.p : nullptr, BX.p, BW.p,
          have_p ? BP.p : nullptr, part, g, st);
-    k_rayleigh_ritz<<<N, 256, 0, st>>>(m, k, g.p, act, drop, theta.p, coef.p, 0);
+    k_rayleigh_ritz<<<N, kRRThreads, 0, st>>>(m, k, g.p, act, drop, theta.p, coef.p, 0);
     k_combine<<<nb256(blk), 256, 0, st>>>(w.len, k, m, 0, w.row_sub.p, w.voff_d.p, act, X.p, Wb.p,
                                           have_p ? P.p : nullptr, coef.p, X.p, Xn.p);
     k_combine<<<nb256(blk), 256, 0, st>>>(w.len, k, m, k, w.row_sub.p, w.voff_d.p, act, X.p, Wb.p,
