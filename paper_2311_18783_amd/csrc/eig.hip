@@ -389,26 +389,85 @@ __global__ __launch_bounds__(kRRThreads) void k_rayleigh_ritz(int m, int k, cons
     B[a * m + b] *= dsc[a] * dsc[b];
   }
   __syncthreads();
-  jacobi_eig(B, V, m, m, rc, rs, pp, qq, red);
-  if (tid < m) lam[tid] = B[tid * m + tid];
-  __syncthreads();
+  // B-orthonormal coordinates U (m x n2, stored in B, row-major ld m):
+  // Rayleigh-Ritz bases are B-orthonormal blocks by construction, so the
+  // scaled B-Gram is the identity up to rounding and a Cholesky factor
+  // B_kk = L L^T of its non-zero columns gives U = L^-T; a pivot below
+  // `drop` (near dependence) falls back to the eigen-decomposition of B.
+  __shared__ int s_fail;
   if (tid == 0) {
-    double mx = 0.0;
-    for (int i = 0; i < m; ++i) mx = fmax(mx, lam[i]);
     int c = 0;
-    for (int i = 0; i < m; ++i)
-      if (lam[i] > drop * mx) keep[c++] = i;
+    if (!svqb)
+      for (int i = 0; i < m; ++i)
+        if (dsc[i] > 0.0) keep[c++] = i;
     nk = c;
+    s_fail = svqb ? 1 : 0;
   }
   __syncthreads();
-  const int n2 = nk;
-  // U = V[:, keep] / sqrt(lambda) stored in B (m x n2, row-major ld m)
-  for (int idx = tid; idx < m * n2; idx += kRRThreads) {
-    const int r = idx / n2, c = idx % n2;
-    const int col = keep[c];
-    B[r * m + c] = V[r * m + col] / sqrt(lam[col]);
+  int n2 = nk;
+  if (!s_fail) {
+    for (int idx = tid; idx < n2 * n2; idx += kRRThreads) {
+      const int r = idx / n2, c = idx % n2;
+      V[r * m + c] = r >= c ? B[keep[r] * m + keep[c]] : 0.0;
+    }
+    __syncthreads();
+    for (int j = 0; j < n2; ++j) {
+      if (tid == 0) {
+        const double p = V[j * m + j];
+        if (!(p > drop)) s_fail = 1;
+        V[j * m + j] = p > 0.0 ? sqrt(p) : 1.0;
+      }
+      __syncthreads();
+      if (s_fail) break;
+      const double djj = V[j * m + j];
+      for (int i = j + 1 + tid; i < n2; i += kRRThreads) V[i * m + j] /= djj;
+      __syncthreads();
+      const int t = n2 - j - 1;
+      for (int idx = tid; idx < t * t; idx += kRRThreads) {
+        const int i = j + 1 + idx / t, c = j + 1 + idx % t;
+        if (i >= c) V[i * m + c] -= V[i * m + j] * V[c * m + j];
+      }
+      __syncthreads();
+    }
   }
-  __syncthreads();
+  if (!s_fail) {
+    // X = L^-1 (column c by thread c, forward substitution), U[keep[r]][c] = X[c][r]
+    for (int idx = tid; idx < m * n2; idx += kRRThreads) B[(idx / n2) * m + idx % n2] = 0.0;
+    __syncthreads();
+    if (tid < n2) {
+      // thread r: column r of X, i.e. row keep[r] of U
+      const int r = tid;
+      double* urow = B + keep[r] * m;
+      for (int i = r; i < n2; ++i) {
+        double sum = i == r ? 1.0 : 0.0;
+        for (int t = r; t < i; ++t) sum -= V[i * m + t] * urow[t];
+        urow[i] = sum / V[i * m + i];
+      }
+    }
+    __syncthreads();
+  }
+  if (s_fail) {
+    jacobi_eig(B, V, m, m, rc, rs, pp, qq, red);
+    if (tid < m) lam[tid] = B[tid * m + tid];
+    __syncthreads();
+    if (tid == 0) {
+      double mx = 0.0;
+      for (int i = 0; i < m; ++i) mx = fmax(mx, lam[i]);
+      int c = 0;
+      for (int i = 0; i < m; ++i)
+        if (lam[i] > drop * mx) keep[c++] = i;
+      nk = c;
+    }
+    __syncthreads();
+    n2 = nk;
+    // U = V[:, keep] / sqrt(lambda) stored in B (m x n2, row-major ld m)
+    for (int idx = tid; idx < m * n2; idx += kRRThreads) {
+      const int r = idx / n2, c = idx % n2;
+      const int col = keep[c];
+      B[r * m + c] = V[r * m + col] / sqrt(lam[col]);
+    }
+    __syncthreads();
+  }
   if (svqb) {
     for (int idx = tid; idx < m * k; idx += kRRThreads) {
       const int r = idx % m, c = idx / m;
