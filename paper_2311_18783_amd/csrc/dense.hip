@@ -753,6 +753,8 @@ __device__ inline void store_coherent(double* p, double v) {
   __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
+constexpr int kTrsvThreads = 512;   // 4 column groups of 32: more loads in flight per block row
+
 // One triangular solve, single right-hand side: x <- L^-1 x (UPPER = false)
 // or x <- U^-1 x (UPPER = true) on every matrix segment of the batch vector,
 // with the factor in solve form (k_qblocks): x_I = c_I - sum_J Q(I,J) x_J,
@@ -760,11 +762,14 @@ __device__ inline void store_coherent(double* p, double v) {
 // its last dependency into registers before waiting, so when that
 // dependency lands only a register-resident 128 x 128 product is left.
 template <typename T, bool UPPER>
-__global__ __launch_bounds__(256) void k_trsv(const MatDesc* __restrict__ desc, const int32_t* __restrict__ items,
-                                              const T* __restrict__ A, const T* __restrict__ Ainv, double* x,
-                                              unsigned* sync, unsigned* flags, DevErr* err) {
+__global__ __launch_bounds__(kTrsvThreads) void k_trsv(const MatDesc* __restrict__ desc,
+                                                       const int32_t* __restrict__ items, const T* __restrict__ A,
+                                                       const T* __restrict__ Ainv, double* x, unsigned* sync,
+                                                       unsigned* flags, DevErr* err) {
+  constexpr int H = kTrsvThreads / NB;   // column groups
+  constexpr int CW = NB / H;             // columns per group
   __shared__ double xs[NB];
-  __shared__ double red[256];
+  __shared__ double red[kTrsvThreads];
   __shared__ int s_t;
   __shared__ unsigned s_epoch;
   const int tid = threadIdx.x;
@@ -784,12 +789,12 @@ __global__ __launch_bounds__(256) void k_trsv(const MatDesc* __restrict__ desc, 
   const int J0 = UPPER ? d.nblk - 1 : 0, Jend = I, dir = UPPER ? -1 : 1;
   const int Jl = I - dir;
   const bool has_dep = UPPER ? I < d.nblk - 1 : I > 0;
-  // block of the last dependency, register resident: q[c] = Q(I,Jl)[r][64h + c]
-  T q[64];
+  // block of the last dependency, register resident: q[c] = Q(I,Jl)[r][CW h + c]
+  T q[CW];
   if (has_dep) {
-    const T* col = A + d.off + ((int64_t)Jl * NB + 64 * h) * d.ld + (int64_t)I * NB + r;
+    const T* col = A + d.off + ((int64_t)Jl * NB + CW * h) * d.ld + (int64_t)I * NB + r;
 #pragma unroll
-    for (int c = 0; c < 64; ++c) q[c] = col[(int64_t)c * d.ld];
+    for (int c = 0; c < CW; ++c) q[c] = col[(int64_t)c * d.ld];
   }
   // c_I = inv(D_II) b_I (b_I is this block's own entry, written before this launch)
   if (tid < NB) xs[tid] = xv[(int64_t)I * NB + tid];
@@ -797,16 +802,16 @@ __global__ __launch_bounds__(256) void k_trsv(const MatDesc* __restrict__ desc, 
   const T* inv = Ainv + d.inv_off + ((UPPER ? d.nblk : 0) + (int64_t)I) * NB * NB;
   double acc = 0.0;
 #pragma unroll 8
-  for (int c = 0; c < 64; ++c) acc -= (double)inv[(int64_t)(64 * h + c) * NB + r] * xs[64 * h + c];
+  for (int c = 0; c < CW; ++c) acc -= (double)inv[(int64_t)(CW * h + c) * NB + r] * xs[CW * h + c];
   if (tid == 0) s_front = J0;
   for (int J = J0; J != Jl && has_dep; J += dir) {
     if (tid == 0 && J == s_front) s_front = wait_frontier(flags + d.flag_off, J, Jend, dir, epoch, err);
     __syncthreads();
     if (tid < NB) xs[tid] = load_coherent(xv + (int64_t)J * NB + tid);
     __syncthreads();
-    const T* col = A + d.off + ((int64_t)J * NB + 64 * h) * d.ld + (int64_t)I * NB + r;
+    const T* col = A + d.off + ((int64_t)J * NB + CW * h) * d.ld + (int64_t)I * NB + r;
 #pragma unroll 8
-    for (int c = 0; c < 64; ++c) acc += (double)col[(int64_t)c * d.ld] * xs[64 * h + c];
+    for (int c = 0; c < CW; ++c) acc += (double)col[(int64_t)c * d.ld] * xs[CW * h + c];
   }
   if (has_dep) {
     if (tid == 0 && Jl == s_front) s_front = wait_frontier(flags + d.flag_off, Jl, Jend, dir, epoch, err);
@@ -814,11 +819,16 @@ __global__ __launch_bounds__(256) void k_trsv(const MatDesc* __restrict__ desc, 
     if (tid < NB) xs[tid] = load_coherent(xv + (int64_t)Jl * NB + tid);
     __syncthreads();
 #pragma unroll
-    for (int c = 0; c < 64; ++c) acc += (double)q[c] * xs[64 * h + c];
+    for (int c = 0; c < CW; ++c) acc += (double)q[c] * xs[CW * h + c];
   }
   red[tid] = acc;
   __syncthreads();
-  if (tid < NB) store_coherent(xv + (int64_t)I * NB + tid, -(red[tid] + red[tid + NB]));
+  if (tid < NB) {
+    double v = 0.0;
+#pragma unroll
+    for (int g = 0; g < H; ++g) v += red[g * NB + tid];
+    store_coherent(xv + (int64_t)I * NB + tid, -v);
+  }
   __syncthreads();
   if (tid == 0) publish(flags + d.flag_off + I, epoch);
 }
@@ -988,11 +998,11 @@ static void solve_impl(const FactorPlan& P, const T* A, const T* Ainv, double* x
                        DevErr* err, hipStream_t st) {
   if (P.n_items == 0) return;
   k_solve_begin<<<1, 1, 0, st>>>(sync);
-  k_trsv<T, false><<<dim3((unsigned)P.n_items), dim3(256), 0, st>>>(P.d_desc.p, P.d_items_fwd.p, A, Ainv, x, sync,
-                                                                     flags, err);
+  k_trsv<T, false><<<dim3((unsigned)P.n_items), dim3(kTrsvThreads), 0, st>>>(P.d_desc.p, P.d_items_fwd.p, A, Ainv,
+                                                                              x, sync, flags, err);
   k_solve_begin<<<1, 1, 0, st>>>(sync);
-  k_trsv<T, true><<<dim3((unsigned)P.n_items), dim3(256), 0, st>>>(P.d_desc.p, P.d_items_bwd.p, A, Ainv, x, sync,
-                                                                    flags, err);
+  k_trsv<T, true><<<dim3((unsigned)P.n_items), dim3(kTrsvThreads), 0, st>>>(P.d_desc.p, P.d_items_bwd.p, A, Ainv,
+                                                                             x, sync, flags, err);
   HIP_CHECK(hipGetLastError());
 }
 
