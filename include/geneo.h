@@ -149,7 +149,7 @@ typedef struct {
   int32_t lobpcg_maxit;
   int32_t lobpcg_guard;     /* extra block vectors beyond nev_max */
   uint64_t seed;            /* random start blocks */
-  double coarse_drop_tol;   /* relative Schur pivot below which a coarse column is dependent */
+  double coarse_drop_tol;   /* relative Schur pivot below which a coarse column is dependent (default 1e-7) */
   const double* warm_start; /* host [sum_i n_i * nev_max] start blocks (column-major per subdomain) or NULL */
   double fp32_rho_max;      /* FP32_REFINE1: a subdomain whose estimated rho(I - Ahat_i^-1 A_i) exceeds this
                                is factored in FP64 instead (default 0.5; must be < 1) */
@@ -161,6 +161,7 @@ typedef struct {
 typedef struct {
   int32_t n0;               /* coarse columns (SNK + GenEO) */
   int32_t n0_rank;          /* columns kept as a basis */
+  int32_t n0_local_dropped; /* SNK columns left out before assembling E: dependent within their node's group */
   int32_t n_snk;            /* SNK columns */
   int32_t n_geneo;          /* GenEO columns */
   int32_t lobpcg_iters;     /* LOBPCG iterations (max over subdomains) */

@@ -86,7 +86,7 @@ def geneo_vectors(Ai, Gi, Di, V):
     return Di[:, None] * (V - xi @ V)
 
 
-def greedy_cholesky(E, drop_tol=1e-8):
+def greedy_cholesky(E, drop_tol=1e-7):
     """Cholesky factor of E restricted to a basis chosen greedily from the
     columns of Z, left to right.
 
@@ -122,7 +122,7 @@ class TwoLevel:
     level, no coarse space), 'nk' / 'nk_geneo' (Z from the global G)."""
 
     def __init__(self, dec, tau=10.0, nev_max=20, variant="snk_geneo", classical=False,
-                 drop_tol=1e-8, local_precision="fp64"):
+                 drop_tol=1e-7, local_precision="fp64"):
         self.dec = dec
         sysm = dec.sys
         n = sysm.n

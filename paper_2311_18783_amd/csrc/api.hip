@@ -190,7 +190,7 @@ void geneo_setup_opts_default(geneo_setup_opts* o) {
   o->lobpcg_maxit = 100;
   o->lobpcg_guard = 4;
   o->seed = 12345;
-  o->coarse_drop_tol = 1e-8;
+  o->coarse_drop_tol = 1e-7;
   o->warm_start = nullptr;
   o->fp32_rho_max = 0.5;
   o->model = nullptr;

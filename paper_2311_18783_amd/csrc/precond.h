@@ -40,7 +40,8 @@ struct geneo_precond {
   geneo::DevBuf<int64_t> d_lnnz_off;
 
   // coarse space: SNK columns (sparse) + GenEO columns (dense local blocks)
-  int32_t n0 = 0, n_snk = 0, n_gen = 0;
+  int32_t n0 = 0, n_snk = 0, n_gen = 0;   // columns of the assembled coarse matrix (after the local test)
+  int32_t n_snk_all = 0;                    // SNK columns before it (the paper's SNK size)
   geneo::FactorPlan coarse;
   geneo::DevBuf<double> dE, dEinv, d_odiag, d_pivrel;
   geneo::DevBuf<unsigned> d_flags_coarse;

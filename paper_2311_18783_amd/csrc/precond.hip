@@ -7,8 +7,10 @@
 // extensions R_i^T uses the inverse map (free edge -> batch positions) in a
 // fixed order, so results are bitwise reproducible.
 #include <algorithm>
+#include <cstdlib>
 #include <cmath>
 #include <numeric>
+#include <string>
 
 #include "precond.h"
 
@@ -421,6 +423,79 @@ static void fp32_probe(geneo_ctx* ctx, geneo_precond* pc, const std::vector<MatD
   HIP_CHECK(hipStreamSynchronize(st));
 }
 
+// Columns of one node n, R_i^T D_i G_i(:, n) over the subdomains i that
+// contain n, live on the (at most 14) edges at n, and many are linearly
+// dependent there (e.g. all D_i constant around n).  Their span is
+// unchanged if, group by group, a column whose Gram-Schmidt residual
+// against the earlier kept columns of its group is below 1e-8 of its norm
+// is left out; the pivoted coarse factorisation then only has to find the
+// (few) dependences that span several nodes.  Keeps the original column
+// order; rewrites the CSC arrays in place.
+static void snk_local_basis(int64_t n_nodes, std::vector<int32_t>& cp, std::vector<int32_t>& ri,
+                            std::vector<double>& va, const std::vector<int32_t>& node) {
+  const int64_t nc = (int64_t)cp.size() - 1;
+  std::vector<int64_t> gp(n_nodes + 1, 0);
+  for (int64_t c = 0; c < nc; ++c) gp[node[c] + 1]++;
+  for (int64_t v = 0; v < n_nodes; ++v) gp[v + 1] += gp[v];
+  std::vector<int64_t> gc(nc);
+  {
+    std::vector<int64_t> f(gp.begin(), gp.end() - 1);
+    for (int64_t c = 0; c < nc; ++c) gc[f[node[c]]++] = c;   // ascending column order within a group
+  }
+  std::vector<uint8_t> keep(nc, 0);
+  std::vector<int32_t> edges;
+  std::vector<double> basis, u;
+  for (int64_t v = 0; v < n_nodes; ++v) {
+    const int64_t b = gp[v], e = gp[v + 1];
+    if (b == e) continue;
+    edges.clear();
+    for (int64_t t = b; t < e; ++t)
+      for (int32_t k = cp[gc[t]]; k < cp[gc[t] + 1]; ++k) edges.push_back(ri[k]);
+    std::sort(edges.begin(), edges.end());
+    edges.erase(std::unique(edges.begin(), edges.end()), edges.end());
+    const size_t m = edges.size();
+    basis.clear();
+    int nb = 0;
+    for (int64_t t = b; t < e; ++t) {
+      const int64_t c = gc[t];
+      u.assign(m, 0.0);
+      for (int32_t k = cp[c]; k < cp[c + 1]; ++k)
+        u[std::lower_bound(edges.begin(), edges.end(), ri[k]) - edges.begin()] += va[k];
+      double n0 = 0.0;
+      for (double x : u) n0 += x * x;
+      if (!(n0 > 0.0)) continue;
+      for (int pass = 0; pass < 2; ++pass)
+        for (int q = 0; q < nb; ++q) {
+          const double* w = basis.data() + (size_t)q * m;
+          double d = 0.0;
+          for (size_t i = 0; i < m; ++i) d += w[i] * u[i];
+          for (size_t i = 0; i < m; ++i) u[i] -= d * w[i];
+        }
+      double nr = 0.0;
+      for (double x : u) nr += x * x;
+      if (!(nr > 1e-16 * n0)) continue;   // residual below 1e-8 of the norm
+      nr = std::sqrt(nr);
+      for (double& x : u) x /= nr;
+      basis.insert(basis.end(), u.begin(), u.end());
+      ++nb;
+      keep[c] = 1;
+    }
+  }
+  std::vector<int32_t> cp2(1, 0), ri2;
+  std::vector<double> va2;
+  for (int64_t c = 0; c < nc; ++c) {
+    if (!keep[c]) continue;
+    for (int32_t k = cp[c]; k < cp[c + 1]; ++k) {
+      ri2.push_back(ri[k]);
+      va2.push_back(va[k]);
+    }
+    cp2.push_back((int32_t)ri2.size());
+  }
+  cp.swap(cp2);
+  ri.swap(ri2);
+  va.swap(va2);
+}
+
 void setup_precond(geneo_ctx* ctx, geneo_precond* pc) {
   hipStream_t st = ctx->stream;
   const geneo_system* s = pc->sys;
@@ -586,7 +661,7 @@ void setup_precond(geneo_ctx* ctx, geneo_precond* pc) {
   }
 
   // ---- coarse space: SNK columns R_i^T D_i G_i (one per kept local free node)
-  std::vector<int32_t> zc_ptr(1, 0), zc_row;
+  std::vector<int32_t> zc_ptr(1, 0), zc_row, col_node;
   std::vector<double> zc_val;
   {
     std::vector<int32_t> gl(s->n_free_nodes, -1);
@@ -614,11 +689,19 @@ void setup_precond(geneo_ctx* ctx, geneo_precond* pc) {
           zc_val.push_back(pr.second);
         }
         zc_ptr.push_back((int32_t)zc_row.size());
+        col_node.push_back(dec->gnodes[gb + k]);
       }
       for (int64_t k = gb; k < ge; ++k) gl[dec->gnodes[k]] = -1;
     }
   }
+  pc->n_snk_all = (int32_t)(zc_ptr.size() - 1);
+  static const bool local_basis = [] {
+    const char* e = std::getenv("GENEO_SNK_LOCAL");
+    return !(e && std::string(e) == "0");
+  }();
+  if (local_basis) snk_local_basis(s->n_free_nodes, zc_ptr, zc_row, zc_val, col_node);
   pc->n_snk = (int32_t)(zc_ptr.size() - 1);
+  pc->info.n0_local_dropped = pc->n_snk_all - pc->n_snk;
   pc->n_gen = 0;
   for (int32_t i = 0; i < N; ++i) {
     pc->gen_off[i] = pc->n_gen;
@@ -711,9 +794,9 @@ void setup_precond(geneo_ctx* ctx, geneo_precond* pc) {
       maxd = std::max(maxd, piv[c]);
     }
   }
-  pc->info.n0 = (int32_t)n0;
+  pc->info.n0 = pc->n_snk_all + pc->n_gen;
   pc->info.n0_rank = kept;
-  pc->info.n_snk = pc->n_snk;
+  pc->info.n_snk = pc->n_snk_all;
   pc->info.n_geneo = pc->n_gen;
   pc->info.min_kept_pivot = kept ? mink : 0.0;
   pc->info.max_dropped_pivot = maxd;

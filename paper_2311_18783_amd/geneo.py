@@ -72,7 +72,8 @@ class SetupOpts(C.Structure):
 
 
 class PrecondInfo(C.Structure):
-    _fields_ = [("n0", C.c_int32), ("n0_rank", C.c_int32), ("n_snk", C.c_int32), ("n_geneo", C.c_int32),
+    _fields_ = [("n0", C.c_int32), ("n0_rank", C.c_int32), ("n0_local_dropped", C.c_int32),
+                ("n_snk", C.c_int32), ("n_geneo", C.c_int32),
                 ("lobpcg_iters", C.c_int32), ("lobpcg_unconverged", C.c_int32), ("fp64_fallbacks", C.c_int32),
                 ("min_kept_pivot", C.c_double), ("max_dropped_pivot", C.c_double),
                 ("t_extract_ms", C.c_double), ("t_factor_ms", C.c_double), ("t_gevp_ms", C.c_double),
