@@ -55,50 +55,6 @@ __global__ void k_neumann_vals(int64_t nnz, int nsub, const int64_t* __restrict_
   bval[k] = acc;
 }
 
-// Y = M X (+ options) over blocks of k <= 32 columns, one thread per batch
-// row carrying all k columns (indices and values read once per nonzero):
-//   out = scale .* (M x)        if base == nullptr
-//   out = base - scale .* (M x) otherwise          (scale may be nullptr = 1)
-// M is the local CSR of subdomain j: rows lrp[rp_off[j] + r] .., values vals[t].
-__global__ __launch_bounds__(256) void k_spmm(int64_t len, int k, const int32_t* __restrict__ row_sub,
-                                              const int64_t* __restrict__ voff, const int32_t* __restrict__ nloc,
-                                              const int64_t* __restrict__ rp_off, const int32_t* __restrict__ lrp,
-                                              const int32_t* __restrict__ lcol, const double* __restrict__ vals,
-                                              const double* __restrict__ X, const double* __restrict__ base,
-                                              const double* __restrict__ scale, double* __restrict__ Y) {
-  const int64_t b = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  if (b >= len) return;
-  const int j = row_sub[b];
-  const int64_t r = b - voff[j];
-  const int64_t ld = voff[j + 1] - voff[j];
-  const double* Xj = X + voff[j] * k;
-  double acc[32];
-#pragma unroll
-  for (int q = 0; q < 32; ++q) acc[q] = 0.0;
-  if (r < nloc[j]) {
-    const int32_t* rp = lrp + rp_off[j];
-    for (int32_t t = rp[r]; t < rp[r + 1]; ++t) {
-      const double v = vals[t];
-      const double* xc = Xj + lcol[t];
-#pragma unroll
-      for (int q = 0; q < 32; ++q)
-        if (q < k) acc[q] += v * xc[(int64_t)q * ld];
-    }
-    if (scale) {
-      const double sc = scale[b];
-#pragma unroll
-      for (int q = 0; q < 32; ++q) acc[q] *= sc;
-    }
-  }
-  const int64_t o = voff[j] * k + r;
-#pragma unroll
-  for (int q = 0; q < 32; ++q)
-    if (q < k) {
-      const int64_t oq = o + (int64_t)q * ld;
-      Y[oq] = base ? base[oq] - acc[q] : acc[q];
-    }
-}
-
 __global__ void k_gather_vals(int64_t nnz, const int32_t* __restrict__ lslot, const double* __restrict__ gval,
                               double* __restrict__ out) {
   const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
@@ -678,14 +634,90 @@ struct EigWork {
   DevBuf<double> bval, aval, LB, LBinv, S, Sinv, H, Hinv;
   FactorPlan node;
   DevBuf<unsigned> flags_node, flags_local;
+  DevBuf<double> xrow;   // row-major copy of a block for the sparse products [len x 32]
   int64_t nchunks = 0;
 };
+
+// Xt[b][q] = X block entry (row b, column q), rows padded to 32 columns;
+// a workgroup transposes 64 rows through LDS so that both the column reads
+// and the row writes are contiguous.
+__global__ __launch_bounds__(256) void k_block_rowmajor(int64_t len, int k, const int32_t* __restrict__ row_sub,
+                                                        const int64_t* __restrict__ voff,
+                                                        const double* __restrict__ X, double* __restrict__ Xt) {
+  __shared__ double tile[64][33];
+  const int64_t b0 = (int64_t)blockIdx.x * 64;
+  const int tid = threadIdx.x;
+  for (int e = tid; e < 64 * 32; e += 256) {
+    const int q = e >> 6, rr = e & 63;
+    const int64_t b = b0 + rr;
+    double v = 0.0;
+    if (b < len && q < k) {
+      const int j = row_sub[b];
+      v = X[voff[j] * k + (int64_t)q * (voff[j + 1] - voff[j]) + (b - voff[j])];
+    }
+    tile[rr][q] = v;
+  }
+  __syncthreads();
+  for (int e = tid; e < 64 * 32; e += 256) {
+    const int rr = e >> 5, q = e & 31;
+    if (b0 + rr < len) Xt[(b0 + rr) * 32 + q] = tile[rr][q];
+  }
+}
+
+// Y = [base -] scale .* (A_j X) with X given row-major (Xt): every nonzero
+// reads one contiguous row of k values instead of k strided entries.
+__global__ __launch_bounds__(256) void k_spmm_rm(int64_t len, int k, const int32_t* __restrict__ row_sub,
+                                                 const int64_t* __restrict__ voff, const int32_t* __restrict__ nloc,
+                                                 const int64_t* __restrict__ rp_off, const int32_t* __restrict__ lrp,
+                                                 const int32_t* __restrict__ lcol, const double* __restrict__ vals,
+                                                 const double* __restrict__ Xt, const double* __restrict__ base,
+                                                 const double* __restrict__ scale, double* __restrict__ Y) {
+  const int64_t b = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (b >= len) return;
+  const int j = row_sub[b];
+  const int64_t r = b - voff[j];
+  const int64_t ld = voff[j + 1] - voff[j];
+  double acc[32];
+#pragma unroll
+  for (int q = 0; q < 32; ++q) acc[q] = 0.0;
+  const int kq = (k + 3) >> 2;   // double4 groups in use
+  if (r < nloc[j]) {
+    const int32_t* rp = lrp + rp_off[j];
+    for (int32_t t = rp[r]; t < rp[r + 1]; ++t) {
+      const double v = vals[t];
+      const double4* xr = reinterpret_cast<const double4*>(Xt + (voff[j] + lcol[t]) * 32);
+#pragma unroll
+      for (int g = 0; g < 8; ++g)
+        if (g < kq) {
+          const double4 x = xr[g];
+          acc[4 * g] += v * x.x;
+          acc[4 * g + 1] += v * x.y;
+          acc[4 * g + 2] += v * x.z;
+          acc[4 * g + 3] += v * x.w;
+        }
+    }
+    if (scale) {
+      const double sc = scale[b];
+#pragma unroll
+      for (int q = 0; q < 32; ++q) acc[q] *= sc;
+    }
+  }
+  const int64_t o = voff[j] * k + r;
+#pragma unroll
+  for (int q = 0; q < 32; ++q)
+    if (q < k) {
+      const int64_t oq = o + (int64_t)q * ld;
+      Y[oq] = base ? base[oq] - acc[q] : acc[q];
+    }
+}
 
 // lvals == nullptr selects the local A_j values
 static void spmm(const geneo_precond* pc, EigWork& w, const double* lvals, const double* X, const double* base,
                  const double* scale, double* Y, hipStream_t st) {
-  k_spmm<<<nb256(w.len), 256, 0, st>>>(w.len, w.k, w.row_sub.p, w.voff_d.p, w.nloc.p, w.rp_off.p, w.lrp.p,
-                                       pc->d_lcol.p, lvals ? lvals : w.aval.p, X, base, scale, Y);
+  if (!w.xrow.p) w.xrow.alloc((size_t)w.len * 32);
+  k_block_rowmajor<<<(unsigned)((w.len + 63) / 64), 256, 0, st>>>(w.len, w.k, w.row_sub.p, w.voff_d.p, X, w.xrow.p);
+  k_spmm_rm<<<nb256(w.len), 256, 0, st>>>(w.len, w.k, w.row_sub.p, w.voff_d.p, w.nloc.p, w.rp_off.p, w.lrp.p,
+                                          pc->d_lcol.p, lvals ? lvals : w.aval.p, w.xrow.p, base, scale, Y);
 }
 static void gt(EigWork& w, const double* X, double* Nn, hipStream_t st) {
   k_gt<<<nb256(w.plen * w.k), 256, 0, st>>>(w.plen, w.k, w.node_sub.p, w.poff_d.p, w.pl.p, w.voff_d.p, w.ne_off.p,
