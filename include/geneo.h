@@ -172,6 +172,8 @@ typedef struct {
   double t_extract_ms, t_factor_ms, t_gevp_ms, t_coarse_build_ms, t_coarse_factor_ms; /* device times */
   double local_factor_flops; /* sum n_i^3/3 */
   double fp32_rho_est;      /* FP32_REFINE1: largest probe estimate of rho(I - Ahat_i^-1 A_i), else 0 */
+  double coarse_factor_flops; /* flops of the coarse factorisation (on its block-sparse fill pattern) */
+  double coarse_fill;       /* fraction of the lower 128 x 128 tiles of E in that pattern (1 = dense) */
   int32_t learned_starts;   /* subdomains whose start block came from the model */
   double start_residual;    /* largest eigen-residual of the top nev_max Ritz pairs after the first
                                Rayleigh-Ritz step (start-block quality) */

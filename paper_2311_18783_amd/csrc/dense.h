@@ -37,7 +37,27 @@ struct FactorPlan {
   DevBuf<int64_t> d_prefix;
   DevBuf<int32_t> d_items_fwd, d_items_bwd;
   void build(const std::vector<MatDesc>& descs, hipStream_t st);
+
+  // Block-sparse single matrix: only the tiles of the factor's fill pattern
+  // are touched (explicit tile lists), the solves follow per-row dependency
+  // lists.  fill[I * nblk + J] (I >= J) must contain the pattern of L,
+  // i.e. be closed under the symbolic elimination.
+  bool sparse = false;
+  std::vector<int64_t> trsm_off;         // [max_blk + 1] into d_trsm_rows
+  DevBuf<int32_t> d_trsm_rows;           // row blocks of each panel step
+  std::vector<int64_t> syrk_off;         // per entry of `syrk`: offset (in pairs) into d_syrk_pairs
+  DevBuf<int32_t> d_syrk_pairs;          // (ti, tj) of every trailing-update tile
+  int64_t n_lower = 0;                   // strictly lower tiles in the pattern
+  DevBuf<int32_t> d_lower_pairs;
+  DevBuf<int32_t> d_dep_fwd_ptr, d_dep_fwd, d_dep_bwd_ptr, d_dep_bwd;
+  int64_t fill_tiles = 0;                // lower tiles (with diagonal) in the pattern
+  double sparse_flops = 0;               // factorisation flops on the pattern
+  void build_sparse(const MatDesc& d, const std::vector<uint8_t>& fill, hipStream_t st);
 };
+
+// Symbolic block elimination: closes the lower tile pattern pat[I * nb + J]
+// (I >= J) under fill-in.
+void symbolic_fill(int nb, std::vector<uint8_t>& pat);
 
 // failed: if given, a non-positive pivot of matrix m sets failed[m] = 1 and
 // the column is treated as dropped, instead of raising GENEO_ENOTSPD.

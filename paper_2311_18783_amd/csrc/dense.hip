@@ -373,15 +373,15 @@ __device__ inline int find_mat(const int64_t* __restrict__ prefix, int cnt, int6
 template <typename T, int MODE>
 __global__ __launch_bounds__(64 * TileGeo<MODE>::WAVES) __attribute__((amdgpu_waves_per_eu(1, MODE == 2 ? 1 : 4))) void k_trsm(
     const MatDesc* __restrict__ desc, const int32_t* __restrict__ order, const int64_t* __restrict__ prefix, int cnt,
-    int step, T* __restrict__ A, const T* __restrict__ Ainv) {
+    int step, T* __restrict__ A, const T* __restrict__ Ainv, const int32_t* __restrict__ rows) {
   using G = TileGeo<MODE>;
   extern __shared__ unsigned char smem_raw[];
   T* smem = reinterpret_cast<T*>(smem_raw);
-  const int j = find_mat(prefix, cnt, blockIdx.x);
+  const int j = rows ? 0 : find_mat(prefix, cnt, blockIdx.x);
   const MatDesc d = desc[order[j]];
-  const int64_t t = blockIdx.x - prefix[j];
   const int64_t k0 = (int64_t)step * NB;
-  const int64_t rt = k0 + NB + t * NB;            // first row of the tile
+  // first row of the tile: dense = every block below the panel, sparse = the listed ones
+  const int64_t rt = rows ? (int64_t)rows[blockIdx.x] * NB : k0 + NB + (blockIdx.x - prefix[j]) * NB;
   using Acc = typename AccT<T>::type;
   Acc acc[4][G::BJ];
 #pragma unroll
@@ -401,13 +401,16 @@ __global__ __launch_bounds__(64 * TileGeo<MODE>::WAVES) __attribute__((amdgpu_wa
 template <typename T, int MODE>
 __global__ __launch_bounds__(64 * TileGeo<MODE>::WAVES) __attribute__((amdgpu_waves_per_eu(1, MODE == 2 ? 1 : 4))) void k_syrk(
     const MatDesc* __restrict__ desc, const int32_t* __restrict__ order, const int64_t* __restrict__ prefix, int cnt,
-    int kcol0, int kb, int b0, int ncols, T* __restrict__ A) {
+    int kcol0, int kb, int b0, int ncols, T* __restrict__ A, const int32_t* __restrict__ pairs) {
   using G = TileGeo<MODE>;
-  const int j = find_mat(prefix, cnt, blockIdx.x);
+  const int j = pairs ? 0 : find_mat(prefix, cnt, blockIdx.x);
   const MatDesc d = desc[order[j]];
-  int64_t u = blockIdx.x - prefix[j];
+  int64_t u = pairs ? 0 : blockIdx.x - prefix[j];
   int64_t ti, tj;
-  if (ncols == 0) {
+  if (pairs) {
+    ti = pairs[2 * (int64_t)blockIdx.x];
+    tj = pairs[2 * (int64_t)blockIdx.x + 1];
+  } else if (ncols == 0) {
     ti = (int64_t)((sqrt(8.0 * (double)u + 1.0) - 1.0) * 0.5);
     while (ti * (ti + 1) / 2 > u) --ti;
     while ((ti + 1) * (ti + 2) / 2 <= u) ++ti;
@@ -526,6 +529,91 @@ void FactorPlan::build(const std::vector<MatDesc>& descs, hipStream_t st) {
   d_items_bwd.upload(bwd, st);
 }
 
+void symbolic_fill(int nb, std::vector<uint8_t>& pat) {
+  std::vector<int> rows;
+  for (int k = 0; k < nb; ++k) {
+    pat[(size_t)k * nb + k] = 1;
+    rows.clear();
+    for (int i = k + 1; i < nb; ++i)
+      if (pat[(size_t)i * nb + k]) rows.push_back(i);
+    for (size_t a = 0; a < rows.size(); ++a)
+      for (size_t b = 0; b <= a; ++b) pat[(size_t)rows[a] * nb + rows[b]] = 1;
+  }
+}
+
+void FactorPlan::build_sparse(const MatDesc& dsc, const std::vector<uint8_t>& F, hipStream_t st) {
+  build(std::vector<MatDesc>(1, dsc), st);   // dense plan of the single matrix: panel steps, items, groups
+  sparse = true;
+  const int nb = dsc.nblk;
+  auto f = [&](int i, int j) { return F[(size_t)i * nb + j] != 0; };
+  // trsm rows per step
+  std::vector<int32_t> tr;
+  trsm_off.assign(nb + 1, 0);
+  for (int s = 0; s < nb; ++s) {
+    trsm_off[s] = (int64_t)tr.size();
+    for (int i = s + 1; i < nb; ++i)
+      if (f(i, s)) tr.push_back(i);
+    trsm_tiles[s] = (int64_t)tr.size() - trsm_off[s];
+  }
+  trsm_off[nb] = (int64_t)tr.size();
+  d_trsm_rows.upload(tr.empty() ? std::vector<int32_t>(1, 0) : tr, st);
+  // trailing-update tiles of each launch of the (dense) launch sequence
+  std::vector<int32_t> pairs;
+  syrk_off.assign(syrk.size(), 0);
+  sparse_flops = 0;
+  for (size_t li = 0; li < syrk.size(); ++li) {
+    SyrkLaunch& L = syrk[li];
+    syrk_off[li] = (int64_t)pairs.size() / 2;
+    int64_t cnt = 0;
+    if (L.kb > 0) {
+      const int cend = L.ncols ? std::min(nb, L.b0 + L.ncols) : nb;
+      for (int tj = L.b0; tj < cend; ++tj)
+        for (int ti = tj; ti < nb; ++ti) {
+          bool hit = false;
+          for (int sp = L.kcol0; sp < L.kcol0 + L.kb && sp < nb && !hit; ++sp) hit = f(ti, sp) && f(tj, sp);
+          if (!hit) continue;
+          pairs.push_back(ti);
+          pairs.push_back(tj);
+          ++cnt;
+        }
+    }
+    L.tiles = cnt;
+    sparse_flops += (double)cnt * 2.0 * NB * NB * NB * L.kb;
+  }
+  d_syrk_pairs.upload(pairs.empty() ? std::vector<int32_t>(2, 0) : pairs, st);
+  // strictly lower tiles; solve dependencies
+  std::vector<int32_t> lo, fp(nb + 1, 0), fd, bp(nb + 1, 0), bd;
+  fill_tiles = 0;
+  for (int i = 0; i < nb; ++i)
+    for (int j = 0; j <= i; ++j)
+      if (f(i, j)) {
+        ++fill_tiles;
+        if (i > j) {
+          lo.push_back(i);
+          lo.push_back(j);
+        }
+      }
+  n_lower = (int64_t)lo.size() / 2;
+  mirror_tiles = n_lower;
+  d_lower_pairs.upload(lo.empty() ? std::vector<int32_t>(2, 0) : lo, st);
+  for (int i = 0; i < nb; ++i) {           // forward: J < I with L(I,J) != 0, increasing
+    for (int j = 0; j < i; ++j)
+      if (f(i, j)) fd.push_back(j);
+    fp[i + 1] = (int32_t)fd.size();
+  }
+  for (int i = 0; i < nb; ++i) {           // backward: J > I with U(I,J) = L(J,I)^T != 0, decreasing
+    for (int j = nb - 1; j > i; --j)
+      if (f(j, i)) bd.push_back(j);
+    bp[i + 1] = (int32_t)bd.size();
+  }
+  d_dep_fwd_ptr.upload(fp, st);
+  d_dep_fwd.upload(fd.empty() ? std::vector<int32_t>(1, 0) : fd, st);
+  d_dep_bwd_ptr.upload(bp, st);
+  d_dep_bwd.upload(bd.empty() ? std::vector<int32_t>(1, 0) : bd, st);
+  for (int s = 0; s < nb; ++s)
+    sparse_flops += (double)NB * NB * NB / 3.0 + (double)trsm_tiles[s] * NB * NB * NB;
+}
+
 template <typename T, int MODE>
 static void factor_run(const FactorPlan& P, T* A, T* Ainv, const double* odiag, double drop_tol, double* pivrel,
                        DevErr* err, hipStream_t st, int32_t* failed) {
@@ -545,10 +633,12 @@ static void factor_run(const FactorPlan& P, T* A, T* Ainv, const double* odiag, 
   }
   const int G = P.group;
   size_t li = 0;
+  auto li_of = [&](const SyrkLaunch& L) { return (size_t)(&L - P.syrk.data()); };
   auto run_syrk = [&](const SyrkLaunch& L) {
     if (L.tiles > 0 && L.kb > 0)
       k_syrk<T, MODE><<<dim3((unsigned)L.tiles), dim3(threads), mma_lds, st>>>(
-          P.d_desc.p, P.d_order.p, P.d_syrk_prefix.p + L.pre_off, P.nmat, L.kcol0, L.kb, L.b0, L.ncols, A);
+          P.d_desc.p, P.d_order.p, P.d_syrk_prefix.p + L.pre_off, P.nmat, L.kcol0, L.kb, L.b0, L.ncols, A,
+          P.sparse ? P.d_syrk_pairs.p + 2 * P.syrk_off[li_of(L)] : nullptr);
   };
   for (int s0 = 0; s0 < P.max_blk; s0 += G) {
     for (int g = 0; g < G && s0 + g < P.max_blk; ++g) {
@@ -557,8 +647,8 @@ static void factor_run(const FactorPlan& P, T* A, T* Ainv, const double* odiag, 
       k_potrf<T><<<dim3(P.cnt[s]), dim3(kPotrfThreads), lds, st>>>(P.d_desc.p, P.d_order.p, s, A, Ainv, odiag,
                                                                      drop_tol, pivrel, err, failed);
       if (P.trsm_tiles[s] > 0)
-        k_trsm<T, MODE><<<dim3((unsigned)P.trsm_tiles[s]), dim3(threads), mma_lds, st>>>(P.d_desc.p, P.d_order.p,
-                                                                                          pt, P.cnt[s], s, A, Ainv);
+        k_trsm<T, MODE><<<dim3((unsigned)P.trsm_tiles[s]), dim3(threads), mma_lds, st>>>(
+            P.d_desc.p, P.d_order.p, pt, P.cnt[s], s, A, Ainv, P.sparse ? P.d_trsm_rows.p + P.trsm_off[s] : nullptr);
       run_syrk(P.syrk[li++]);
     }
     run_syrk(P.syrk[li++]);
@@ -624,17 +714,29 @@ void factor(const FactorPlan& P, float* A, float* Ainv, const double* odiag, dou
 constexpr unsigned kSpinLimit = 1u << 24;
 
 // U block (J, I) = L block (I, J)^T for every I > J, through LDS 64x64 tiles.
-template <typename T>
-__global__ __launch_bounds__(256) void k_mirror(const MatDesc* __restrict__ desc, const int32_t* __restrict__ order,
-                                                const int64_t* __restrict__ prefix, int cnt, T* __restrict__ A) {
-  __shared__ T tile[64][65];
-  const int j = find_mat(prefix, cnt, blockIdx.x);
-  const MatDesc d = desc[order[j]];
-  const int64_t u = blockIdx.x - prefix[j];
-  int64_t ti = (int64_t)((sqrt(8.0 * (double)u + 1.0) + 1.0) * 0.5);
+// strictly lower tile (ti > tj) of launch index u: the full triangle, or the
+// listed pairs of a block-sparse matrix
+__device__ inline void lower_tile(const int32_t* pairs, int64_t u, int64_t& ti, int64_t& tj) {
+  if (pairs) {
+    ti = pairs[2 * u];
+    tj = pairs[2 * u + 1];
+    return;
+  }
+  ti = (int64_t)((sqrt(8.0 * (double)u + 1.0) + 1.0) * 0.5);
   while (ti * (ti - 1) / 2 > u) --ti;
   while ((ti + 1) * ti / 2 <= u) ++ti;
-  const int64_t tj = u - ti * (ti - 1) / 2;   // ti > tj
+  tj = u - ti * (ti - 1) / 2;
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_mirror(const MatDesc* __restrict__ desc, const int32_t* __restrict__ order,
+                                                const int64_t* __restrict__ prefix, int cnt, T* __restrict__ A,
+                                                const int32_t* __restrict__ pairs) {
+  __shared__ T tile[64][65];
+  const int j = pairs ? 0 : find_mat(prefix, cnt, blockIdx.x);
+  const MatDesc d = desc[order[j]];
+  int64_t ti, tj;   // ti > tj
+  lower_tile(pairs, pairs ? (int64_t)blockIdx.x : (int64_t)blockIdx.x - prefix[j], ti, tj);
   const int tid = threadIdx.x;
   for (int sub = 0; sub < 4; ++sub) {
     const int64_t r0 = ti * NB + 64 * (sub & 1), c0 = tj * NB + 64 * (sub >> 1);
@@ -684,14 +786,11 @@ __device__ inline void tile_mma_bt(const T* __restrict__ Ar, int64_t lda, const 
 template <typename T>
 __global__ __launch_bounds__(256) void k_qblocks(const MatDesc* __restrict__ desc, const int32_t* __restrict__ order,
                                                  const int64_t* __restrict__ prefix, int cnt, T* __restrict__ A,
-                                                 const T* __restrict__ Ainv) {
-  const int j = find_mat(prefix, cnt, blockIdx.x);
+                                                 const T* __restrict__ Ainv, const int32_t* __restrict__ pairs) {
+  const int j = pairs ? 0 : find_mat(prefix, cnt, blockIdx.x);
   const MatDesc d = desc[order[j]];
-  const int64_t u = blockIdx.x - prefix[j];
-  int64_t ti = (int64_t)((sqrt(8.0 * (double)u + 1.0) + 1.0) * 0.5);
-  while (ti * (ti - 1) / 2 > u) --ti;
-  while ((ti + 1) * ti / 2 <= u) ++ti;
-  const int64_t tj = u - ti * (ti - 1) / 2;   // ti > tj
+  int64_t ti, tj;   // ti > tj
+  lower_tile(pairs, pairs ? (int64_t)blockIdx.x : (int64_t)blockIdx.x - prefix[j], ti, tj);
   using Acc = typename AccT<T>::type;
   Acc lo[4][4], up[4][4];
 #pragma unroll
@@ -765,7 +864,9 @@ template <typename T, bool UPPER>
 __global__ __launch_bounds__(kTrsvThreads) void k_trsv(const MatDesc* __restrict__ desc,
                                                        const int32_t* __restrict__ items, const T* __restrict__ A,
                                                        const T* __restrict__ Ainv, double* x, unsigned* sync,
-                                                       unsigned* flags, DevErr* err) {
+                                                       unsigned* flags, DevErr* err,
+                                                       const int32_t* __restrict__ dep_ptr,
+                                                       const int32_t* __restrict__ dep) {
   constexpr int H = kTrsvThreads / NB;   // column groups
   constexpr int CW = NB / H;             // columns per group
   __shared__ double xs[NB];
@@ -785,10 +886,14 @@ __global__ __launch_bounds__(kTrsvThreads) void k_trsv(const MatDesc* __restrict
   const int r = tid & (NB - 1), h = tid >> 7;
   __shared__ int s_front;
   // dependencies: forward J = 0..I-1 (done in increasing order),
-  // backward J = nblk-1..I+1 (done in decreasing order); the last one is Jl
+  // backward J = nblk-1..I+1 (done in decreasing order), or for a
+  // block-sparse factor the listed ones in that order; the last one is Jl
   const int J0 = UPPER ? d.nblk - 1 : 0, Jend = I, dir = UPPER ? -1 : 1;
-  const int Jl = I - dir;
-  const bool has_dep = UPPER ? I < d.nblk - 1 : I > 0;
+  const int nd = dep ? dep_ptr[I + 1] - dep_ptr[I] : (UPPER ? d.nblk - 1 - I : I);
+  const int32_t* dl = dep ? dep + dep_ptr[I] : nullptr;
+  auto dep_at = [&](int e) { return dl ? dl[e] : J0 + dir * e; };
+  const bool has_dep = nd > 0;
+  const int Jl = has_dep ? dep_at(nd - 1) : I;
   // block of the last dependency, register resident: q[c] = Q(I,Jl)[r][CW h + c]
   T q[CW];
   if (has_dep) {
@@ -803,9 +908,12 @@ __global__ __launch_bounds__(kTrsvThreads) void k_trsv(const MatDesc* __restrict
   double acc = 0.0;
 #pragma unroll 8
   for (int c = 0; c < CW; ++c) acc -= (double)inv[(int64_t)(CW * h + c) * NB + r] * xs[CW * h + c];
+  // s_front: first block (in the solve's direction) not yet known done
   if (tid == 0) s_front = J0;
-  for (int J = J0; J != Jl && has_dep; J += dir) {
-    if (tid == 0 && J == s_front) s_front = wait_frontier(flags + d.flag_off, J, Jend, dir, epoch, err);
+  for (int e = 0; e + 1 < nd; ++e) {
+    const int J = dep_at(e);
+    if (tid == 0 && (dir > 0 ? J >= s_front : J <= s_front))
+      s_front = wait_frontier(flags + d.flag_off, J, Jend, dir, epoch, err);
     __syncthreads();
     if (tid < NB) xs[tid] = load_coherent(xv + (int64_t)J * NB + tid);
     __syncthreads();
@@ -814,7 +922,8 @@ __global__ __launch_bounds__(kTrsvThreads) void k_trsv(const MatDesc* __restrict
     for (int c = 0; c < CW; ++c) acc += (double)col[(int64_t)c * d.ld] * xs[CW * h + c];
   }
   if (has_dep) {
-    if (tid == 0 && Jl == s_front) s_front = wait_frontier(flags + d.flag_off, Jl, Jend, dir, epoch, err);
+    if (tid == 0 && (dir > 0 ? Jl >= s_front : Jl <= s_front))
+      s_front = wait_frontier(flags + d.flag_off, Jl, Jend, dir, epoch, err);
     __syncthreads();
     if (tid < NB) xs[tid] = load_coherent(xv + (int64_t)Jl * NB + tid);
     __syncthreads();
@@ -982,14 +1091,15 @@ template <typename T>
 static void mirror_impl(const FactorPlan& P, T* A, hipStream_t st) {
   if (P.mirror_tiles > 0)
     k_mirror<T><<<dim3((unsigned)P.mirror_tiles), dim3(256), 0, st>>>(P.d_desc.p, P.d_order.p, P.d_mirror_prefix.p,
-                                                                      P.nmat, A);
+                                                                      P.nmat, A, P.sparse ? P.d_lower_pairs.p : nullptr);
 }
 
 template <typename T>
 static void qblocks_impl(const FactorPlan& P, T* A, const T* Ainv, hipStream_t st) {
   if (P.mirror_tiles > 0)
     k_qblocks<T><<<dim3((unsigned)P.mirror_tiles), dim3(256), 0, st>>>(P.d_desc.p, P.d_order.p, P.d_mirror_prefix.p,
-                                                                       P.nmat, A, Ainv);
+                                                                       P.nmat, A, Ainv,
+                                                                       P.sparse ? P.d_lower_pairs.p : nullptr);
   HIP_CHECK(hipGetLastError());
 }
 
@@ -998,11 +1108,13 @@ static void solve_impl(const FactorPlan& P, const T* A, const T* Ainv, double* x
                        DevErr* err, hipStream_t st) {
   if (P.n_items == 0) return;
   k_solve_begin<<<1, 1, 0, st>>>(sync);
-  k_trsv<T, false><<<dim3((unsigned)P.n_items), dim3(kTrsvThreads), 0, st>>>(P.d_desc.p, P.d_items_fwd.p, A, Ainv,
-                                                                              x, sync, flags, err);
+  k_trsv<T, false><<<dim3((unsigned)P.n_items), dim3(kTrsvThreads), 0, st>>>(
+      P.d_desc.p, P.d_items_fwd.p, A, Ainv, x, sync, flags, err, P.sparse ? P.d_dep_fwd_ptr.p : nullptr,
+      P.sparse ? P.d_dep_fwd.p : nullptr);
   k_solve_begin<<<1, 1, 0, st>>>(sync);
-  k_trsv<T, true><<<dim3((unsigned)P.n_items), dim3(kTrsvThreads), 0, st>>>(P.d_desc.p, P.d_items_bwd.p, A, Ainv,
-                                                                             x, sync, flags, err);
+  k_trsv<T, true><<<dim3((unsigned)P.n_items), dim3(kTrsvThreads), 0, st>>>(
+      P.d_desc.p, P.d_items_bwd.p, A, Ainv, x, sync, flags, err, P.sparse ? P.d_dep_bwd_ptr.p : nullptr,
+      P.sparse ? P.d_dep_bwd.p : nullptr);
   HIP_CHECK(hipGetLastError());
 }
 
@@ -1043,6 +1155,7 @@ void solve_multi(const FactorPlan& P, const double* A, const double* Ainv, doubl
   }
   if (P.n_items == 0 || k == 0) return;
   if (k > 32) throw Error(GENEO_EUNSUPPORTED, "more than 32 right-hand sides");
+  if (P.sparse) throw Error(GENEO_EUNSUPPORTED, "many right-hand sides on a block-sparse factor");
   k_solve_begin<<<1, 1, 0, st>>>(sync);
   k_trsm_multi_mfma<false><<<dim3((unsigned)P.n_items), dim3(256), 0, st>>>(P.d_desc.p, P.d_items_fwd.p, A, Ainv, X,
                                                                             ldk, k, sync, flags, err);

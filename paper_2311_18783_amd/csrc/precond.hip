@@ -137,6 +137,23 @@ __global__ void k_w_n(int64_t len, int nsub, const int64_t* __restrict__ voff, c
   b[k] = acc;
 }
 
+// pat[ti * nb + tj] = 1 if the lower tile (ti >= tj) of E holds a non-zero
+__global__ __launch_bounds__(256) void k_tile_pattern(const double* __restrict__ E, int64_t ld, int nb,
+                                                      uint8_t* __restrict__ pat) {
+  const int64_t u = blockIdx.x;
+  int64_t ti = (int64_t)((sqrt(8.0 * (double)u + 1.0) - 1.0) * 0.5);
+  while (ti * (ti + 1) / 2 > u) --ti;
+  while ((ti + 1) * (ti + 2) / 2 <= u) ++ti;
+  const int64_t tj = u - ti * (ti + 1) / 2;
+  int nz = 0;
+  for (int idx = threadIdx.x; idx < NB * NB; idx += 256) {
+    const int r = idx & (NB - 1), c = idx >> 7;
+    if ((ti > tj || r >= c) && E[(tj * NB + c) * ld + ti * NB + r] != 0.0) nz = 1;
+  }
+  nz = __syncthreads_or(nz);
+  if (threadIdx.x == 0) pat[ti * nb + tj] = (uint8_t)(nz ? 1 : 0);
+}
+
 __global__ void k_axpby(int64_t n, double a, const double* __restrict__ x, double bcoef, const double* __restrict__ y,
                         double* __restrict__ out) {
   int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
@@ -777,6 +794,29 @@ void setup_precond(geneo_ctx* ctx, geneo_precond* pc) {
   }
   // the coarse plan's diag_off is 0
   HIP_CHECK(hipEventRecord(ctx->ev[1], st));
+  // block sparsity of E: only subdomains whose columns meet through A couple;
+  // the factor touches the tiles of the symbolic fill of that pattern only
+  static const bool coarse_sparse = [] {
+    const char* e = std::getenv("GENEO_COARSE_SPARSE");
+    return !(e && std::string(e) == "0");
+  }();
+  const int nbc = (int)(n0p / NB);
+  pc->info.coarse_factor_flops = (double)n0 * n0 * n0 / 3.0;
+  if (coarse_sparse && nbc > 1) {
+    DevBuf<uint8_t> d_pat;
+    d_pat.alloc((size_t)nbc * nbc);
+    HIP_CHECK(hipMemsetAsync(d_pat.p, 0, (size_t)nbc * nbc, st));
+    const int64_t ntiles = (int64_t)nbc * (nbc + 1) / 2;
+    k_tile_pattern<<<(unsigned)ntiles, 256, 0, st>>>(pc->dE.p, n0p, nbc, d_pat.p);
+    HIP_CHECK(hipGetLastError());
+    std::vector<uint8_t> pat((size_t)nbc * nbc);
+    HIP_CHECK(hipMemcpyAsync(pat.data(), d_pat.p, pat.size(), hipMemcpyDeviceToHost, st));
+    HIP_CHECK(hipStreamSynchronize(st));
+    symbolic_fill(nbc, pat);
+    pc->coarse.build_sparse(cd[0], pat, st);
+    pc->info.coarse_factor_flops = pc->coarse.sparse_flops;
+    pc->info.coarse_fill = (double)pc->coarse.fill_tiles / ((double)nbc * (nbc + 1) / 2);
+  }
   factor(pc->coarse, pc->dE.p, pc->dEinv.p, pc->d_odiag.p, pc->opts.coarse_drop_tol, pc->d_pivrel.p, ctx->d_err, st);
   HIP_CHECK(hipEventRecord(ctx->ev[2], st));
   pc->info.t_coarse_build_ms = elapsed(ctx, 0, 1);

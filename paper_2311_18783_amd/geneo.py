@@ -79,6 +79,7 @@ class PrecondInfo(C.Structure):
                 ("t_extract_ms", C.c_double), ("t_factor_ms", C.c_double), ("t_gevp_ms", C.c_double),
                 ("t_coarse_build_ms", C.c_double), ("t_coarse_factor_ms", C.c_double),
                 ("local_factor_flops", C.c_double), ("fp32_rho_est", C.c_double),
+                ("coarse_factor_flops", C.c_double), ("coarse_fill", C.c_double),
                 ("learned_starts", C.c_int32), ("start_residual", C.c_double)]
 
 
