@@ -437,6 +437,232 @@ __global__ __launch_bounds__(64 * TileGeo<MODE>::WAVES) __attribute__((amdgpu_wa
   tile_store<T, G::BJ>(C, d.ld, acc);
 }
 
+// ------------------------------------------- recursive diagonal block (FP64)
+constexpr int kRecThreads = 256;
+
+__device__ inline double rl(double v, int lane) {
+  const uint64_t u = __builtin_bit_cast(uint64_t, v);
+  const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)u, lane);
+  const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(u >> 32), lane);
+  return __builtin_bit_cast(double, ((uint64_t)hi << 32) | lo);
+}
+
+// One wavefront factors and inverts the 16 x 16 block at (r0, r0): lane i
+// (mod 16) holds row i, lanes 16..63 duplicate lanes 0..15 and store
+// nothing.  Entries above the diagonal are carried along unmasked (they
+// start at zero, stay finite and are never read back), which keeps per-lane
+// predicates out of the column loop.  Lane j keeps the pivot data of column
+// j; invd, the pivot ratios and failures are written lane-parallel at the
+// end.
+__device__ inline void leaf16(double* Ls, double* invd, const double* od, int r0, double drop_tol,
+                              double* pivrel_row, int m, int64_t gcol0, DevErr* err, int32_t* failed) {
+  const int lane = threadIdx.x & 63;
+  const int i = lane & 15;
+  const bool use_drop = drop_tol > 0.0;
+  double v[16];
+#pragma unroll
+  for (int c = 0; c < 16; ++c) v[c] = Ls[(r0 + c) * LDA + r0 + i];
+  const double my_o = od[r0 + i];
+  double my_dinv = 0.0, my_p = 0.0;
+  bool my_fail = false;
+#pragma unroll
+  for (int j = 0; j < 16; ++j) {
+    const double p = rl(v[j], j);
+    const double o = rl(my_o, j);
+    const bool drop = use_drop && (!(p > drop_tol * o) || !(o > 0.0));
+    const bool fail = !drop && !(p > 0.0);
+    const double sq = (drop || fail) ? 1.0 : sqrt(p);
+    const double sc = (drop || fail) ? 0.0 : 1.0 / sq;
+    const bool below = i > j, diag = i == j;
+    if (diag) {
+      my_dinv = sc;
+      my_p = p;
+      my_fail = fail;
+    }
+    const double l = below ? v[j] * sc : 0.0;
+    v[j] = diag ? sq : l;
+#pragma unroll
+    for (int c = j + 1; c < 16; ++c) v[c] -= l * rl(l, c);
+  }
+  // X = inv(L) column by column: lane i solves L x = e_i top to bottom (the
+  // entries above i come out as exact zeros); L[r][t] is lane r's v[t]
+  double x[16];
+#pragma unroll
+  for (int r = 0; r < 16; ++r) {
+    double acc = r == i ? 1.0 : 0.0;
+#pragma unroll
+    for (int t = 0; t < r; ++t) acc -= rl(v[t], r) * x[t];
+    x[r] = acc * rl(my_dinv, r);
+  }
+  const uint64_t fails = __ballot(my_fail && lane < 16);
+  if (lane < 16) {
+    // lower entries (c <= i) take L, upper ones X transposed (X[c][i])
+#pragma unroll
+    for (int c = 0; c < 16; ++c) Ls[(r0 + c) * LDA + r0 + i] = c <= i ? v[c] : x[c];
+    invd[r0 + i] = my_dinv;
+    if (use_drop && pivrel_row) pivrel_row[r0 + i] = my_o > 0.0 ? my_p / my_o : 0.0;
+    if (fails && lane == __builtin_ctzll(fails)) {   // first failing column of the leaf
+      if (failed)
+        failed[m] = 1;   // caller handles it (the column is treated as dropped)
+      else
+        set_err(err, GENEO_ENOTSPD, m, (int)(gcol0 + r0 + i));
+    }
+  }
+}
+
+// p x p product on the four waves (p = 16, 32, 64): 16 x 16 output tiles,
+// tile q of wave w is t = w + 4 q; f(m, n, value) receives the results.
+// STAGED: a barrier separates the last operand read from the first write,
+// for products that overwrite one of their operands.
+template <int P, bool STAGED, typename FA, typename FB, typename FO>
+__device__ inline void mma_p(FA a, FB b, FO f) {
+  constexpr int NT = P / 16;
+  constexpr int TILES = NT * NT;
+  constexpr int TPW = TILES >= 4 ? TILES / 4 : 1;
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int lr = lane & 15, lk = lane >> 4;
+  d4_t acc[TPW];
+#pragma unroll
+  for (int q = 0; q < TPW; ++q) {
+    const int t = w + 4 * q;
+    acc[q] = d4_t{0, 0, 0, 0};
+    if (t < TILES) {
+      const int ti = t / NT, tj = t % NT;
+#pragma unroll 4
+      for (int kk = 0; kk < P; kk += 4) acc[q] = mfma16(a(16 * ti + lr, kk + lk), b(kk + lk, 16 * tj + lr), acc[q]);
+    }
+  }
+  if constexpr (STAGED) __syncthreads();
+#pragma unroll
+  for (int q = 0; q < TPW; ++q) {
+    const int t = w + 4 * q;
+    if (t < TILES) {
+      const int ti = t / NT, tj = t % NT;
+#pragma unroll
+      for (int v = 0; v < 4; ++v) f(16 * ti + acc_row<double>(lane, v), 16 * tj + lr, acc[q][v]);
+    }
+  }
+}
+
+// For the block [L11 0; L21 L22] whose halves start at rows a0 and b0 = a0 + H:
+// after L11 and X11 = inv(L11) are known,
+//   L21 = A21 X11^T (in place) and A22 -= L21 L21^T (lower triangle);
+template <int H>
+__device__ inline void rec_lower(double* Ls, const double* invd, int a0, int b0) {
+  auto X11 = [&](int r, int c) -> double { return r > c ? Ls[(a0 + r) * LDA + a0 + c] : (r == c ? invd[a0 + r] : 0.0); };
+  auto L21 = [&](int r, int c) -> double { return Ls[(a0 + c) * LDA + b0 + r]; };
+  mma_p<H, true>(L21, [&](int k, int n) { return X11(n, k); },
+                 [&](int m, int n, double v) { Ls[(a0 + n) * LDA + b0 + m] = v; });
+  __syncthreads();
+  mma_p<H, false>(L21, [&](int k, int n) { return L21(n, k); }, [&](int m, int n, double v) {
+    if (m >= n) Ls[(b0 + n) * LDA + b0 + m] -= v;
+  });
+  __syncthreads();
+}
+
+// after L22 and X22 are known as well: X21 = -X22 (L21 X11), with T = L21 X11
+// staged in the free upper right block (T[m][n] at Ls[(b0 + n) * LDA + a0 + m])
+// and X21 written over it transposed (X21[m][n] at Ls[(b0 + m) * LDA + a0 + n]).
+template <int H>
+__device__ inline void rec_inverse(double* Ls, const double* invd, int a0, int b0) {
+  auto X11 = [&](int r, int c) -> double { return r > c ? Ls[(a0 + r) * LDA + a0 + c] : (r == c ? invd[a0 + r] : 0.0); };
+  auto X22 = [&](int r, int c) -> double { return r > c ? Ls[(b0 + r) * LDA + b0 + c] : (r == c ? invd[b0 + r] : 0.0); };
+  auto L21 = [&](int r, int c) -> double { return Ls[(a0 + c) * LDA + b0 + r]; };
+  mma_p<H, false>(L21, X11, [&](int m, int n, double v) { Ls[(b0 + n) * LDA + a0 + m] = v; });
+  __syncthreads();
+  mma_p<H, true>(X22, [&](int k, int n) { return Ls[(b0 + n) * LDA + a0 + k]; },
+                 [&](int m, int n, double v) { Ls[(b0 + m) * LDA + a0 + n] = -v; });
+  __syncthreads();
+}
+
+// Diagonal block factorisation and inversion, recursive in halves
+// (128 -> 64 -> 32 -> 16): with [L11 0; L21 L22] and X = inv(L),
+//   L11, X11 from the upper half;  L21 = A21 X11^T;  A22 -= L21 L21^T;
+//   L22, X22 from the lower half;  X21 = -X22 L21 X11.
+// The products run as v_mfma_f64_16x16x4 tiles on all four waves; the
+// 16 x 16 leaves are factored and inverted by one wavefront in registers
+// with cross-lane broadcasts and no barriers, so the sequential part drops
+// from 2 x 128 barrier-separated column steps (k_potrf) to 8 short leaves.
+// The recursion is run as a loop over the leaves in its post-order: after
+// leaf lf, each level whose subtree ends at lf finishes its block
+// (rec_inverse for a right half, which may close the parent too;
+// rec_lower for a left half, which hands over to the right sibling).
+// The block lives in LDS column-major; X sits transposed in the strict
+// upper triangle (X[r][c], r > c, at Ls[r * LDA + c]) with its diagonal in
+// invd.  Same pivot rule and outputs as k_potrf.
+__global__ __launch_bounds__(kRecThreads) void k_potrf_rec(const MatDesc* __restrict__ desc,
+                                                           const int32_t* __restrict__ order, int step,
+                                                           double* __restrict__ A, double* __restrict__ Ainv,
+                                                           const double* __restrict__ odiag, double drop_tol,
+                                                           double* __restrict__ pivrel, DevErr* err,
+                                                           int32_t* __restrict__ failed) {
+  extern __shared__ unsigned char smem_raw[];
+  double* Ls = reinterpret_cast<double*>(smem_raw);   // [NB * LDA], column-major
+  __shared__ double invd[NB], od[NB];
+  const int m = order[blockIdx.x];
+  const MatDesc d = desc[m];
+  const int tid = threadIdx.x;
+  const int64_t k0 = (int64_t)step * NB;
+  double* blk = A + d.off + k0 * d.ld + k0;
+  const bool have_od = odiag && d.diag_off >= 0;
+  // load the lower triangle, 16-byte loads: 64 threads per column, 4 columns per pass
+  const int rr = 2 * (tid & 63), cq = tid >> 6;
+  for (int c0 = 0; c0 < NB; c0 += 32) {
+    double2 buf[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) buf[u] = *reinterpret_cast<const double2*>(blk + (int64_t)(c0 + 4 * u + cq) * d.ld + rr);
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int c = c0 + 4 * u + cq;
+      Ls[c * LDA + rr] = rr >= c ? buf[u].x : 0.0;
+      Ls[c * LDA + rr + 1] = rr + 1 >= c ? buf[u].y : 0.0;
+    }
+  }
+  if (tid < NB) od[tid] = have_od ? odiag[d.diag_off + k0 + tid] : 0.0;
+  __syncthreads();
+  double* pivrel_row = (pivrel && d.diag_off >= 0) ? pivrel + d.diag_off + k0 : nullptr;
+  for (int lf = 0; lf < NB / 16; ++lf) {
+    if (tid < 64) leaf16(Ls, invd, od, 16 * lf, drop_tol, pivrel_row, m, k0, err, failed);
+    __syncthreads();
+    for (int s = 0; s < 3; ++s) {
+      if (((lf + 1) & ((1 << s) - 1)) != 0) break;   // lf does not end a level-s subtree
+      const int idx = lf >> s, H = 16 << s;
+      if ((idx & 1) == 0) {
+        const int a0 = idx * H;
+        if (s == 0) rec_lower<16>(Ls, invd, a0, a0 + 16);
+        else if (s == 1) rec_lower<32>(Ls, invd, a0, a0 + 32);
+        else rec_lower<64>(Ls, invd, a0, a0 + 64);
+        break;
+      }
+      const int a0 = (idx - 1) * H;
+      if (s == 0) rec_inverse<16>(Ls, invd, a0, a0 + 16);
+      else if (s == 1) rec_inverse<32>(Ls, invd, a0, a0 + 32);
+      else rec_inverse<64>(Ls, invd, a0, a0 + 64);
+    }
+  }
+  double* inv = Ainv + d.inv_off + (int64_t)step * NB * NB;
+  double* uinv = Ainv + d.inv_off + ((int64_t)d.nblk + step) * NB * NB;   // inv(U_II) = inv(L_II)^T
+  for (int c0 = 0; c0 < NB; c0 += 4) {
+    const int c = c0 + cq;
+    double2 l, x, u;
+#pragma unroll
+    for (int e = 0; e < 2; ++e) {
+      const int r = rr + e;
+      const double lv = Ls[c * LDA + r];                                         // L[r][c], r >= c
+      const double xv = r > c ? Ls[r * LDA + c] : (r == c ? invd[r] : 0.0);       // X[r][c]
+      const double uv = c > r ? Ls[c * LDA + r] : (r == c ? invd[r] : 0.0);       // X[c][r]
+      if (e == 0) { l.x = lv; x.x = xv; u.x = uv; } else { l.y = lv; x.y = xv; u.y = uv; }
+    }
+    if (rr >= c) {
+      *reinterpret_cast<double2*>(blk + (int64_t)c * d.ld + rr) = l;
+    } else if (rr + 1 == c) {
+      blk[(int64_t)c * d.ld + rr + 1] = l.y;
+    }
+    *reinterpret_cast<double2*>(inv + (int64_t)c * NB + rr) = x;
+    *reinterpret_cast<double2*>(uinv + (int64_t)c * NB + rr) = u;
+  }
+}
+
 // --------------------------------------------------------------- plan
 
 void FactorPlan::build(const std::vector<MatDesc>& descs, hipStream_t st) {
@@ -621,8 +847,15 @@ static void factor_run(const FactorPlan& P, T* A, T* Ainv, const double* odiag, 
   const size_t mma_lds = MODE == 2 ? sizeof(T) * 4 * KCH * NB : 0;   // two stages of A and B chunks
   const unsigned threads = 64 * TileGeo<MODE>::WAVES;
   static bool attr_set = false;
+  // FP64: recursive diagonal-block kernel (GENEO_POTRF=reg selects the register one)
+  static const bool rec_potrf = [] {
+    const char* e = std::getenv("GENEO_POTRF");
+    return !(e && std::string(e) == "reg");
+  }() && sizeof(T) == 8;
   if (!attr_set) {
     HIP_CHECK(hipFuncSetAttribute((const void*)k_potrf<T>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+    HIP_CHECK(hipFuncSetAttribute((const void*)k_potrf_rec, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                  (int)(sizeof(double) * NB * LDA)));
     if (MODE == 2) {
       HIP_CHECK(hipFuncSetAttribute((const void*)k_trsm<T, MODE>, hipFuncAttributeMaxDynamicSharedMemorySize,
                                     (int)mma_lds));
@@ -644,8 +877,17 @@ static void factor_run(const FactorPlan& P, T* A, T* Ainv, const double* odiag, 
     for (int g = 0; g < G && s0 + g < P.max_blk; ++g) {
       const int s = s0 + g;
       const int64_t* pt = P.d_prefix.p + P.pre_off[s];
-      k_potrf<T><<<dim3(P.cnt[s]), dim3(kPotrfThreads), lds, st>>>(P.d_desc.p, P.d_order.p, s, A, Ainv, odiag,
-                                                                     drop_tol, pivrel, err, failed);
+      if constexpr (sizeof(T) == 8) {
+        if (rec_potrf)
+          k_potrf_rec<<<dim3(P.cnt[s]), dim3(kRecThreads), sizeof(double) * NB * LDA, st>>>(
+              P.d_desc.p, P.d_order.p, s, A, Ainv, odiag, drop_tol, pivrel, err, failed);
+        else
+          k_potrf<T><<<dim3(P.cnt[s]), dim3(kPotrfThreads), lds, st>>>(P.d_desc.p, P.d_order.p, s, A, Ainv, odiag,
+                                                                         drop_tol, pivrel, err, failed);
+      } else {
+        k_potrf<T><<<dim3(P.cnt[s]), dim3(kPotrfThreads), lds, st>>>(P.d_desc.p, P.d_order.p, s, A, Ainv, odiag,
+                                                                       drop_tol, pivrel, err, failed);
+      }
       if (P.trsm_tiles[s] > 0)
         k_trsm<T, MODE><<<dim3((unsigned)P.trsm_tiles[s]), dim3(threads), mma_lds, st>>>(
             P.d_desc.p, P.d_order.p, pt, P.cnt[s], s, A, Ainv, P.sparse ? P.d_trsm_rows.p + P.trsm_off[s] : nullptr);
