@@ -447,59 +447,66 @@ __device__ inline double rl(double v, int lane) {
   return __builtin_bit_cast(double, ((uint64_t)hi << 32) | lo);
 }
 
+// Storage of the block while it is worked on (LDS, column-major, leading
+// dimension LDA): the strictly lower triangle holds L, the diagonal and the
+// strict upper triangle hold X = inv(L) transposed (X[r][c], r >= c, at
+// Ls[r * LDA + c]); the diagonal of L sits in ldg.
+
 // One wavefront factors and inverts the 16 x 16 block at (r0, r0): lane i
 // (mod 16) holds row i, lanes 16..63 duplicate lanes 0..15 and store
-// nothing.  Entries above the diagonal are carried along unmasked (they
-// start at zero, stay finite and are never read back), which keeps per-lane
-// predicates out of the column loop.  Lane j keeps the pivot data of column
-// j; invd, the pivot ratios and failures are written lane-parallel at the
-// end.
-__device__ inline void leaf16(double* Ls, double* invd, const double* od, int r0, double drop_tol,
+// nothing.  Entries above the diagonal are carried along unmasked (finite,
+// never read back), which keeps per-lane predicates out of the column loop.
+// Lane j keeps the pivot data of column j; pivot ratios and failures are
+// written lane-parallel at the end.
+__device__ inline void leaf16(double* Ls, double* ldg, const double* od, int r0, double drop_tol,
                               double* pivrel_row, int m, int64_t gcol0, DevErr* err, int32_t* failed) {
   const int lane = threadIdx.x & 63;
-  const int i = lane & 15;
+  int i = lane & 15;
+  // opaque per call: keeps the lane predicates below from being hoisted out
+  // of the caller's loop and held across all leaves
+  asm volatile("" : "+v"(i));
   const bool use_drop = drop_tol > 0.0;
   double v[16];
 #pragma unroll
   for (int c = 0; c < 16; ++c) v[c] = Ls[(r0 + c) * LDA + r0 + i];
   const double my_o = od[r0 + i];
-  double my_dinv = 0.0, my_p = 0.0;
+  double my_dinv = 0.0, my_p = 0.0, my_sq = 1.0;
   bool my_fail = false;
 #pragma unroll
   for (int j = 0; j < 16; ++j) {
     const double p = rl(v[j], j);
-    const double o = rl(my_o, j);
-    const bool drop = use_drop && (!(p > drop_tol * o) || !(o > 0.0));
+    bool drop = false;
+    if (use_drop) {
+      const double o = rl(my_o, j);
+      drop = !(p > drop_tol * o) || !(o > 0.0);
+    }
     const bool fail = !drop && !(p > 0.0);
-    const double sq = (drop || fail) ? 1.0 : sqrt(p);
-    const double sc = (drop || fail) ? 0.0 : 1.0 / sq;
+    // 1 / sqrt(p): hardware estimate and two Newton steps (relative error
+    // squares each step), then sqrt(p) = p / sqrt(p); short dependent chain
+    double y = __builtin_amdgcn_rsq(p);
+    y = y * (1.5 - 0.5 * p * y * y);
+    y = y * (1.5 - 0.5 * p * y * y);
+    const double sq = (drop || fail) ? 1.0 : p * y;
+    const double sc = (drop || fail) ? 0.0 : y;
     const bool below = i > j, diag = i == j;
     if (diag) {
       my_dinv = sc;
       my_p = p;
+      my_sq = sq;
       my_fail = fail;
     }
     const double l = below ? v[j] * sc : 0.0;
-    v[j] = diag ? sq : l;
+    v[j] = l;
 #pragma unroll
     for (int c = j + 1; c < 16; ++c) v[c] -= l * rl(l, c);
   }
-  // X = inv(L) column by column: lane i solves L x = e_i top to bottom (the
-  // entries above i come out as exact zeros); L[r][t] is lane r's v[t]
-  double x[16];
-#pragma unroll
-  for (int r = 0; r < 16; ++r) {
-    double acc = r == i ? 1.0 : 0.0;
-#pragma unroll
-    for (int t = 0; t < r; ++t) acc -= rl(v[t], r) * x[t];
-    x[r] = acc * rl(my_dinv, r);
-  }
   const uint64_t fails = __ballot(my_fail && lane < 16);
   if (lane < 16) {
-    // lower entries (c <= i) take L, upper ones X transposed (X[c][i])
 #pragma unroll
-    for (int c = 0; c < 16; ++c) Ls[(r0 + c) * LDA + r0 + i] = c <= i ? v[c] : x[c];
-    invd[r0 + i] = my_dinv;
+    for (int c = 0; c < 16; ++c)
+      if (c < i) Ls[(r0 + c) * LDA + r0 + i] = v[c];
+    Ls[(r0 + i) * LDA + r0 + i] = my_dinv;
+    ldg[r0 + i] = my_sq;
     if (use_drop && pivrel_row) pivrel_row[r0 + i] = my_o > 0.0 ? my_p / my_o : 0.0;
     if (fails && lane == __builtin_ctzll(fails)) {   // first failing column of the leaf
       if (failed)
@@ -508,70 +515,116 @@ __device__ inline void leaf16(double* Ls, double* invd, const double* od, int r0
         set_err(err, GENEO_ENOTSPD, m, (int)(gcol0 + r0 + i));
     }
   }
-}
-
-// p x p product on the four waves (p = 16, 32, 64): 16 x 16 output tiles,
-// tile q of wave w is t = w + 4 q; f(m, n, value) receives the results.
-// STAGED: a barrier separates the last operand read from the first write,
-// for products that overwrite one of their operands.
-template <int P, bool STAGED, typename FA, typename FB, typename FO>
-__device__ inline void mma_p(FA a, FB b, FO f) {
-  constexpr int NT = P / 16;
-  constexpr int TILES = NT * NT;
-  constexpr int TPW = TILES >= 4 ? TILES / 4 : 1;
-  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-  const int lr = lane & 15, lk = lane >> 4;
-  d4_t acc[TPW];
+  // X = inv(L) column by column: lane i solves L x = e_i top to bottom (the
+  // entries above i come out as exact zeros).  L[r][t] and 1 / L[r][r] are
+  // read back from LDS at the same address in every lane (a broadcast); LDS
+  // accesses of one wavefront complete in order, so the stores above are
+  // visible.  Two partial sums halve the dependent FMA chain.
+  double x[16];
 #pragma unroll
-  for (int q = 0; q < TPW; ++q) {
-    const int t = w + 4 * q;
-    acc[q] = d4_t{0, 0, 0, 0};
-    if (t < TILES) {
-      const int ti = t / NT, tj = t % NT;
-#pragma unroll 4
-      for (int kk = 0; kk < P; kk += 4) acc[q] = mfma16(a(16 * ti + lr, kk + lk), b(kk + lk, 16 * tj + lr), acc[q]);
+  for (int r = 0; r < 16; ++r) {
+    double acc0 = r == i ? 1.0 : 0.0, acc1 = 0.0;
+#pragma unroll
+    for (int t = 0; t + 1 < r; t += 2) {
+      acc0 -= Ls[(r0 + t) * LDA + r0 + r] * x[t];
+      acc1 -= Ls[(r0 + t + 1) * LDA + r0 + r] * x[t + 1];
     }
+    if (r & 1) acc0 -= Ls[(r0 + r - 1) * LDA + r0 + r] * x[r - 1];
+    x[r] = (acc0 + acc1) * Ls[(r0 + r) * LDA + r0 + r];
   }
-  if constexpr (STAGED) __syncthreads();
+  if (lane < 16) {
 #pragma unroll
-  for (int q = 0; q < TPW; ++q) {
-    const int t = w + 4 * q;
-    if (t < TILES) {
-      const int ti = t / NT, tj = t % NT;
-#pragma unroll
-      for (int v = 0; v < 4; ++v) f(16 * ti + acc_row<double>(lane, v), 16 * tj + lr, acc[q][v]);
-    }
+    for (int c = 0; c < 16; ++c)
+      if (c > i) Ls[(r0 + c) * LDA + r0 + i] = x[c];   // X[c][i]
   }
 }
 
-// For the block [L11 0; L21 L22] whose halves start at rows a0 and b0 = a0 + H:
-// after L11 and X11 = inv(L11) are known,
-//   L21 = A21 X11^T (in place) and A22 -= L21 L21^T (lower triangle);
-template <int H>
-__device__ inline void rec_lower(double* Ls, const double* invd, int a0, int b0) {
-  auto X11 = [&](int r, int c) -> double { return r > c ? Ls[(a0 + r) * LDA + a0 + c] : (r == c ? invd[a0 + r] : 0.0); };
-  auto L21 = [&](int r, int c) -> double { return Ls[(a0 + c) * LDA + b0 + r]; };
-  mma_p<H, true>(L21, [&](int k, int n) { return X11(n, k); },
-                 [&](int m, int n, double v) { Ls[(a0 + n) * LDA + b0 + m] = v; });
-  __syncthreads();
-  mma_p<H, false>(L21, [&](int k, int n) { return L21(n, k); }, [&](int m, int n, double v) {
-    if (m >= n) Ls[(b0 + n) * LDA + b0 + m] -= v;
-  });
-  __syncthreads();
+// Products of the recursion for a block [L11 0; L21 L22] whose halves start
+// at rows a0 and b0 = a0 + H (H = 16 NT).  Output tiles are 16 x 16 on
+// v_mfma_f64_16x16x4; a triangular operand contributes only its nonzero
+// k-tiles, its diagonal k-tile is masked.
+//   0: L21 = A21 X11^T (in place)       1: A22 -= L21 L21^T (lower tiles)
+//   2: T = L21 X11 (upper right block)  3: X21 = -X22 T (over T)
+// For H = 64 wave w owns tile row w (kinds 0-2, operand A shared across the
+// row) or tile column w (kind 3); for H = 32 one tile each; H = 16 wave 0.
+template <int KIND>
+struct RecOp {
+  double* Ls;
+  int a0, b0;
+  __device__ double X(int base, int r, int c) const {   // inv(L) block at (base, base), masked
+    const double v = Ls[(base + r) * LDA + base + c];
+    return r >= c ? v : 0.0;
+  }
+  __device__ double L21(int m, int k) const { return Ls[(a0 + k) * LDA + b0 + m]; }
+  __device__ double A(int m, int k) const {
+    if constexpr (KIND == 3) return X(b0, m, k);
+    else return L21(m, k);
+  }
+  __device__ double B(int k, int n) const {
+    if constexpr (KIND == 0) return X(a0, n, k);
+    else if constexpr (KIND == 1) return L21(n, k);
+    else if constexpr (KIND == 2) return X(a0, k, n);
+    else return Ls[(b0 + n) * LDA + a0 + k];   // T[k][n]
+  }
+  // nonzero k-tile range of output tile (ti, tj)
+  __device__ static int kt_lo(int ti, int tj) { return KIND == 2 ? tj : 0; }
+  __device__ static int kt_hi(int ti, int tj, int nt) { return KIND == 0 ? tj : (KIND == 3 ? ti : nt - 1); }
+  __device__ void put(int m, int n, double v) const {
+    if constexpr (KIND == 0) Ls[(a0 + n) * LDA + b0 + m] = v;
+    else if constexpr (KIND == 1) Ls[(b0 + n) * LDA + b0 + m] -= v;
+    else if constexpr (KIND == 2) Ls[(b0 + n) * LDA + a0 + m] = v;
+    else Ls[(b0 + m) * LDA + a0 + n] = -v;
+  }
+};
+
+template <int KIND>
+__device__ inline d4_t rec_tile(const RecOp<KIND>& op, int ti, int tj, int kt0, int kt1, d4_t acc) {
+  const int lane = threadIdx.x & 63, lr = lane & 15, lk = lane >> 4;
+  for (int kt = kt0; kt <= kt1; ++kt) {
+    double a[4], b[4];
+#pragma unroll
+    for (int s = 0; s < 4; ++s) {
+      a[s] = op.A(16 * ti + lr, 16 * kt + 4 * s + lk);
+      b[s] = op.B(16 * kt + 4 * s + lk, 16 * tj + lr);
+    }
+#pragma unroll
+    for (int s = 0; s < 4; ++s) acc = mfma16(a[s], b[s], acc);
+  }
+  return acc;
 }
 
-// after L22 and X22 are known as well: X21 = -X22 (L21 X11), with T = L21 X11
-// staged in the free upper right block (T[m][n] at Ls[(b0 + n) * LDA + a0 + m])
-// and X21 written over it transposed (X21[m][n] at Ls[(b0 + m) * LDA + a0 + n]).
-template <int H>
-__device__ inline void rec_inverse(double* Ls, const double* invd, int a0, int b0) {
-  auto X11 = [&](int r, int c) -> double { return r > c ? Ls[(a0 + r) * LDA + a0 + c] : (r == c ? invd[a0 + r] : 0.0); };
-  auto X22 = [&](int r, int c) -> double { return r > c ? Ls[(b0 + r) * LDA + b0 + c] : (r == c ? invd[b0 + r] : 0.0); };
-  auto L21 = [&](int r, int c) -> double { return Ls[(a0 + c) * LDA + b0 + r]; };
-  mma_p<H, false>(L21, X11, [&](int m, int n, double v) { Ls[(b0 + n) * LDA + a0 + m] = v; });
-  __syncthreads();
-  mma_p<H, true>(X22, [&](int k, int n) { return Ls[(b0 + n) * LDA + a0 + k]; },
-                 [&](int m, int n, double v) { Ls[(b0 + m) * LDA + a0 + n] = -v; });
+template <int KIND>
+__device__ inline void rec_put(const RecOp<KIND>& op, int ti, int tj, const d4_t& acc) {
+  const int lane = threadIdx.x & 63;
+  if (KIND == 1 && tj > ti) return;   // upper tiles of A22 are not needed
+#pragma unroll
+  for (int v = 0; v < 4; ++v) op.put(16 * ti + acc_row<double>(lane, v), 16 * tj + (lane & 15), acc[v]);
+}
+
+template <int H, int KIND>
+__device__ inline void rec_prod(double* Ls, int a0, int b0) {
+  constexpr int NT = H / 16;
+  constexpr bool STAGED = KIND == 0 || KIND == 3;
+  const RecOp<KIND> op{Ls, a0, b0};
+  const int w = threadIdx.x >> 6;
+  if constexpr (NT == 4) {
+    d4_t acc[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int ti = KIND == 3 ? q : w, tj = KIND == 3 ? w : q;
+      acc[q] = rec_tile(op, ti, tj, op.kt_lo(ti, tj), op.kt_hi(ti, tj, NT), d4_t{0, 0, 0, 0});
+    }
+    if constexpr (STAGED) __syncthreads();
+#pragma unroll
+    for (int q = 0; q < 4; ++q) rec_put(op, KIND == 3 ? q : w, KIND == 3 ? w : q, acc[q]);
+  } else {
+    const int ti = NT == 2 ? (w >> 1) : 0, tj = NT == 2 ? (w & 1) : 0;
+    const bool active = NT == 2 || w == 0;
+    d4_t acc = d4_t{0, 0, 0, 0};
+    if (active) acc = rec_tile(op, ti, tj, op.kt_lo(ti, tj), op.kt_hi(ti, tj, NT), acc);
+    if constexpr (STAGED) __syncthreads();
+    if (active) rec_put(op, ti, tj, acc);
+  }
   __syncthreads();
 }
 
@@ -579,17 +632,15 @@ __device__ inline void rec_inverse(double* Ls, const double* invd, int a0, int b
 // (128 -> 64 -> 32 -> 16): with [L11 0; L21 L22] and X = inv(L),
 //   L11, X11 from the upper half;  L21 = A21 X11^T;  A22 -= L21 L21^T;
 //   L22, X22 from the lower half;  X21 = -X22 L21 X11.
-// The products run as v_mfma_f64_16x16x4 tiles on all four waves; the
-// 16 x 16 leaves are factored and inverted by one wavefront in registers
-// with cross-lane broadcasts and no barriers, so the sequential part drops
-// from 2 x 128 barrier-separated column steps (k_potrf) to 8 short leaves.
-// The recursion is run as a loop over the leaves in its post-order: after
-// leaf lf, each level whose subtree ends at lf finishes its block
-// (rec_inverse for a right half, which may close the parent too;
-// rec_lower for a left half, which hands over to the right sibling).
-// The block lives in LDS column-major; X sits transposed in the strict
-// upper triangle (X[r][c], r > c, at Ls[r * LDA + c]) with its diagonal in
-// invd.  Same pivot rule and outputs as k_potrf.
+// The products run as FP64 MFMA tiles on all four waves; the 16 x 16 leaves
+// are factored and inverted by one wavefront in registers with cross-lane
+// broadcasts and no barriers, so the sequential part drops from 2 x 128
+// barrier-separated column steps (k_potrf) to 8 short leaves.  The
+// recursion runs as a loop over the leaves in its post-order: after leaf
+// lf, each level whose subtree ends at lf finishes its block (kinds 2 and 3
+// for a right half, which may close the parent too; kinds 0 and 1 for a left
+// half, which hands over to the right sibling).  Same pivot rule and outputs
+// as k_potrf.
 __global__ __launch_bounds__(kRecThreads) void k_potrf_rec(const MatDesc* __restrict__ desc,
                                                            const int32_t* __restrict__ order, int step,
                                                            double* __restrict__ A, double* __restrict__ Ainv,
@@ -598,14 +649,15 @@ __global__ __launch_bounds__(kRecThreads) void k_potrf_rec(const MatDesc* __rest
                                                            int32_t* __restrict__ failed) {
   extern __shared__ unsigned char smem_raw[];
   double* Ls = reinterpret_cast<double*>(smem_raw);   // [NB * LDA], column-major
-  __shared__ double invd[NB], od[NB];
+  __shared__ double ldg[NB], od[NB];
   const int m = order[blockIdx.x];
   const MatDesc d = desc[m];
   const int tid = threadIdx.x;
   const int64_t k0 = (int64_t)step * NB;
   double* blk = A + d.off + k0 * d.ld + k0;
   const bool have_od = odiag && d.diag_off >= 0;
-  // load the lower triangle, 16-byte loads: 64 threads per column, 4 columns per pass
+  // load the lower triangle (16-byte loads, 64 threads per column, 4 columns
+  // per pass; entries above the diagonal are replaced by zeros)
   const int rr = 2 * (tid & 63), cq = tid >> 6;
   for (int c0 = 0; c0 < NB; c0 += 32) {
     double2 buf[8];
@@ -622,22 +674,36 @@ __global__ __launch_bounds__(kRecThreads) void k_potrf_rec(const MatDesc* __rest
   __syncthreads();
   double* pivrel_row = (pivrel && d.diag_off >= 0) ? pivrel + d.diag_off + k0 : nullptr;
   for (int lf = 0; lf < NB / 16; ++lf) {
-    if (tid < 64) leaf16(Ls, invd, od, 16 * lf, drop_tol, pivrel_row, m, k0, err, failed);
+    if (tid < 64) leaf16(Ls, ldg, od, 16 * lf, drop_tol, pivrel_row, m, k0, err, failed);
     __syncthreads();
     for (int s = 0; s < 3; ++s) {
       if (((lf + 1) & ((1 << s) - 1)) != 0) break;   // lf does not end a level-s subtree
       const int idx = lf >> s, H = 16 << s;
       if ((idx & 1) == 0) {
         const int a0 = idx * H;
-        if (s == 0) rec_lower<16>(Ls, invd, a0, a0 + 16);
-        else if (s == 1) rec_lower<32>(Ls, invd, a0, a0 + 32);
-        else rec_lower<64>(Ls, invd, a0, a0 + 64);
+        if (s == 0) {
+          rec_prod<16, 0>(Ls, a0, a0 + 16);
+          rec_prod<16, 1>(Ls, a0, a0 + 16);
+        } else if (s == 1) {
+          rec_prod<32, 0>(Ls, a0, a0 + 32);
+          rec_prod<32, 1>(Ls, a0, a0 + 32);
+        } else {
+          rec_prod<64, 0>(Ls, a0, a0 + 64);
+          rec_prod<64, 1>(Ls, a0, a0 + 64);
+        }
         break;
       }
       const int a0 = (idx - 1) * H;
-      if (s == 0) rec_inverse<16>(Ls, invd, a0, a0 + 16);
-      else if (s == 1) rec_inverse<32>(Ls, invd, a0, a0 + 32);
-      else rec_inverse<64>(Ls, invd, a0, a0 + 64);
+      if (s == 0) {
+        rec_prod<16, 2>(Ls, a0, a0 + 16);
+        rec_prod<16, 3>(Ls, a0, a0 + 16);
+      } else if (s == 1) {
+        rec_prod<32, 2>(Ls, a0, a0 + 32);
+        rec_prod<32, 3>(Ls, a0, a0 + 32);
+      } else {
+        rec_prod<64, 2>(Ls, a0, a0 + 64);
+        rec_prod<64, 3>(Ls, a0, a0 + 64);
+      }
     }
   }
   double* inv = Ainv + d.inv_off + (int64_t)step * NB * NB;
@@ -648,9 +714,11 @@ __global__ __launch_bounds__(kRecThreads) void k_potrf_rec(const MatDesc* __rest
 #pragma unroll
     for (int e = 0; e < 2; ++e) {
       const int r = rr + e;
-      const double lv = Ls[c * LDA + r];                                         // L[r][c], r >= c
-      const double xv = r > c ? Ls[r * LDA + c] : (r == c ? invd[r] : 0.0);       // X[r][c]
-      const double uv = c > r ? Ls[c * LDA + r] : (r == c ? invd[r] : 0.0);       // X[c][r]
+      const double lo = Ls[c * LDA + r];   // L[r][c] for r > c, X[c][r] for r <= c
+      const double up = Ls[r * LDA + c];   // X[r][c] for r >= c
+      const double lv = r == c ? ldg[r] : lo;
+      const double xv = r >= c ? up : 0.0;
+      const double uv = r <= c ? lo : 0.0;
       if (e == 0) { l.x = lv; x.x = xv; u.x = uv; } else { l.y = lv; x.y = xv; u.y = uv; }
     }
     if (rr >= c) {
