@@ -36,6 +36,7 @@ struct FactorPlan {
   DevBuf<int32_t> d_order;
   DevBuf<int64_t> d_prefix;
   DevBuf<int32_t> d_items_fwd, d_items_bwd;
+  DevBuf<double> d_y;                // single-right-hand-side solves: intermediate vector
   void build(const std::vector<MatDesc>& descs, hipStream_t st);
 
   // Block-sparse single matrix: only the tiles of the factor's fill pattern
@@ -70,11 +71,12 @@ void factor(const FactorPlan& P, double* A, double* Ainv, const double* odiag, d
             DevErr* err, hipStream_t st, int32_t* failed = nullptr, bool for_solves = true);
 void factor(const FactorPlan& P, float* A, float* Ainv, const double* odiag, double drop_tol, double* pivrel,
             DevErr* err, hipStream_t st, int32_t* failed = nullptr, bool for_solves = true);
-// x <- (L L^T)^-1 x on every matrix segment of the batch vector x.
-void solve(const FactorPlan& P, const double* A, const double* Ainv, double* x, unsigned* sync, unsigned* flags,
-           DevErr* err, hipStream_t st);
-void solve(const FactorPlan& P, const float* A, const float* Ainv, double* x, unsigned* sync, unsigned* flags,
-           DevErr* err, hipStream_t st);
+// x <- (L L^T)^-1 x on every matrix segment of the batch vector x (other
+// segments are left as they are; the plan's d_y holds the intermediate).
+void solve(const FactorPlan& P, const double* A, const double* Ainv, double* x, unsigned* sync, DevErr* err,
+           hipStream_t st);
+void solve(const FactorPlan& P, const float* A, const float* Ainv, double* x, unsigned* sync, DevErr* err,
+           hipStream_t st);
 // X <- (L L^T)^-1 X for k <= 32 columns: the block of matrix m starts at
 // X + voff_m * ldk, column q at + q * ld_m.
 void solve_multi(const FactorPlan& P, const double* A, const double* Ainv, double* X, int ldk, int k,

@@ -769,6 +769,9 @@ void FactorPlan::build(const std::vector<MatDesc>& descs, hipStream_t st) {
   d_desc.upload(descs, st);
   d_order.upload(ord, st);
   d_prefix.upload(pre, st);
+  int64_t vec_len = 0;
+  for (const auto& dd : descs) vec_len = std::max<int64_t>(vec_len, dd.voff + dd.ld);
+  d_y.alloc(std::max<int64_t>(vec_len, 1));
   // trailing updates for panel groups of G panels: inside a group, panel g
   // updates only the group's later block columns; after the group, one
   // update with all G panels (K = G * NB) covers the rest
@@ -1164,17 +1167,45 @@ __device__ inline void store_coherent(double* p, double v) {
 
 constexpr int kTrsvThreads = 512;   // 4 column groups of 32: more loads in flight per block row
 
-// One triangular solve, single right-hand side: x <- L^-1 x (UPPER = false)
-// or x <- U^-1 x (UPPER = true) on every matrix segment of the batch vector,
-// with the factor in solve form (k_qblocks): x_I = c_I - sum_J Q(I,J) x_J,
-// c_I = inv(D_II) b_I.  The workgroup computes c_I and loads the block of
-// its last dependency into registers before waiting, so when that
-// dependency lands only a register-resident 128 x 128 product is left.
+// Values of a single-right-hand-side solve travel without flags: the output
+// vector is preset to a signalling-NaN pattern (arithmetic never produces
+// it), each finished block stores its 128 values with agent-scope atomic
+// stores, and a consumer polls the values themselves with agent-scope
+// atomic loads until none is pending.  No fences are needed: each value is
+// its own atomic object and nothing else written by the producer is read.
+constexpr uint64_t kPending = 0x7FF4DEADBEEF0001ull;
+
+__device__ inline double poll_value(const double* p, DevErr* err) {
+  unsigned spins = 0;
+  for (;;) {
+    const double v = load_coherent(p);
+    if (__builtin_bit_cast(uint64_t, v) != kPending) return v;
+    if (++spins > kSpinLimit) {
+      set_err(err, GENEO_ESYNC, -1, -1);
+      return 0.0;
+    }
+    __builtin_amdgcn_s_sleep(1);
+  }
+}
+
+// marks the segments of the solve's blocks pending (one block per item)
+__global__ void k_pending(const MatDesc* __restrict__ desc, const int32_t* __restrict__ items, double* x) {
+  const int m = items[2 * blockIdx.x], I = items[2 * blockIdx.x + 1];
+  x[desc[m].voff + (int64_t)I * NB + threadIdx.x] = __builtin_bit_cast(double, kPending);
+}
+
+// One triangular solve, single right-hand side: xout <- L^-1 xin
+// (UPPER = false) or U^-1 xin (UPPER = true) on every matrix segment of the
+// batch vector, with the factor in solve form (k_qblocks):
+// x_I = c_I - sum_J Q(I,J) x_J, c_I = inv(D_II) b_I.  The workgroup computes
+// c_I first; the blocks Q(I,J) are streamed one dependency ahead through
+// two register buffers, so the block of a dependency is already in
+// registers when its values land.
 template <typename T, bool UPPER>
 __global__ __launch_bounds__(kTrsvThreads) void k_trsv(const MatDesc* __restrict__ desc,
                                                        const int32_t* __restrict__ items, const T* __restrict__ A,
-                                                       const T* __restrict__ Ainv, double* x, unsigned* sync,
-                                                       unsigned* flags, DevErr* err,
+                                                       const T* __restrict__ Ainv, const double* __restrict__ xin,
+                                                       double* xout, unsigned* sync, DevErr* err,
                                                        const int32_t* __restrict__ dep_ptr,
                                                        const int32_t* __restrict__ dep) {
   constexpr int H = kTrsvThreads / NB;   // column groups
@@ -1182,63 +1213,48 @@ __global__ __launch_bounds__(kTrsvThreads) void k_trsv(const MatDesc* __restrict
   __shared__ double xs[NB];
   __shared__ double red[kTrsvThreads];
   __shared__ int s_t;
-  __shared__ unsigned s_epoch;
   const int tid = threadIdx.x;
-  if (tid == 0) {
-    s_t = (int)atomicAdd(&sync[0], 1u);
-    s_epoch = __hip_atomic_load(&sync[1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-  }
+  if (tid == 0) s_t = (int)atomicAdd(&sync[0], 1u);
   __syncthreads();
   const int m = items[2 * s_t], I = items[2 * s_t + 1];
-  const unsigned epoch = s_epoch;
   const MatDesc d = desc[m];
-  double* xv = x + d.voff;
+  const double* xi = xin + d.voff;
+  double* xo = xout + d.voff;
   const int r = tid & (NB - 1), h = tid >> 7;
-  __shared__ int s_front;
-  // dependencies: forward J = 0..I-1 (done in increasing order),
-  // backward J = nblk-1..I+1 (done in decreasing order), or for a
-  // block-sparse factor the listed ones in that order; the last one is Jl
-  const int J0 = UPPER ? d.nblk - 1 : 0, Jend = I, dir = UPPER ? -1 : 1;
+  // dependencies: forward J = 0..I-1 (increasing), backward J = nblk-1..I+1
+  // (decreasing), or for a block-sparse factor the listed ones in that order
+  const int J0 = UPPER ? d.nblk - 1 : 0, dir = UPPER ? -1 : 1;
   const int nd = dep ? dep_ptr[I + 1] - dep_ptr[I] : (UPPER ? d.nblk - 1 - I : I);
   const int32_t* dl = dep ? dep + dep_ptr[I] : nullptr;
   auto dep_at = [&](int e) { return dl ? dl[e] : J0 + dir * e; };
-  const bool has_dep = nd > 0;
-  const int Jl = has_dep ? dep_at(nd - 1) : I;
-  // block of the last dependency, register resident: q[c] = Q(I,Jl)[r][CW h + c]
-  T q[CW];
-  if (has_dep) {
-    const T* col = A + d.off + ((int64_t)Jl * NB + CW * h) * d.ld + (int64_t)I * NB + r;
+  auto load_block = [&](T* q, int J) {   // q[c] = Q(I,J)[r][CW h + c]
+    const T* col = A + d.off + ((int64_t)J * NB + CW * h) * d.ld + (int64_t)I * NB + r;
 #pragma unroll
     for (int c = 0; c < CW; ++c) q[c] = col[(int64_t)c * d.ld];
-  }
-  // c_I = inv(D_II) b_I (b_I is this block's own entry, written before this launch)
-  if (tid < NB) xs[tid] = xv[(int64_t)I * NB + tid];
+  };
+  T qa[CW], qb[CW];
+  if (nd > 0) load_block(qa, dep_at(0));
+  // c_I = inv(D_II) b_I
+  if (tid < NB) xs[tid] = xi[(int64_t)I * NB + tid];
   __syncthreads();
   const T* inv = Ainv + d.inv_off + ((UPPER ? d.nblk : 0) + (int64_t)I) * NB * NB;
   double acc = 0.0;
 #pragma unroll 8
   for (int c = 0; c < CW; ++c) acc -= (double)inv[(int64_t)(CW * h + c) * NB + r] * xs[CW * h + c];
-  // s_front: first block (in the solve's direction) not yet known done
-  if (tid == 0) s_front = J0;
-  for (int e = 0; e + 1 < nd; ++e) {
-    const int J = dep_at(e);
-    if (tid == 0 && (dir > 0 ? J >= s_front : J <= s_front))
-      s_front = wait_frontier(flags + d.flag_off, J, Jend, dir, epoch, err);
-    __syncthreads();
-    if (tid < NB) xs[tid] = load_coherent(xv + (int64_t)J * NB + tid);
-    __syncthreads();
-    const T* col = A + d.off + ((int64_t)J * NB + CW * h) * d.ld + (int64_t)I * NB + r;
-#pragma unroll 8
-    for (int c = 0; c < CW; ++c) acc += (double)col[(int64_t)c * d.ld] * xs[CW * h + c];
-  }
-  if (has_dep) {
-    if (tid == 0 && (dir > 0 ? Jl >= s_front : Jl <= s_front))
-      s_front = wait_frontier(flags + d.flag_off, Jl, Jend, dir, epoch, err);
-    __syncthreads();
-    if (tid < NB) xs[tid] = load_coherent(xv + (int64_t)Jl * NB + tid);
+  auto consume = [&](const T* q, int J) {
+    __syncthreads();   // the previous values in xs are consumed
+    if (tid < NB) xs[tid] = poll_value(xo + (int64_t)J * NB + tid, err);
     __syncthreads();
 #pragma unroll
     for (int c = 0; c < CW; ++c) acc += (double)q[c] * xs[CW * h + c];
+  };
+  for (int e = 0; e < nd; e += 2) {
+    if (e + 1 < nd) load_block(qb, dep_at(e + 1));
+    consume(qa, dep_at(e));
+    if (e + 1 < nd) {
+      if (e + 2 < nd) load_block(qa, dep_at(e + 2));
+      consume(qb, dep_at(e + 1));
+    }
   }
   red[tid] = acc;
   __syncthreads();
@@ -1246,10 +1262,8 @@ __global__ __launch_bounds__(kTrsvThreads) void k_trsv(const MatDesc* __restrict
     double v = 0.0;
 #pragma unroll
     for (int g = 0; g < H; ++g) v += red[g * NB + tid];
-    store_coherent(xv + (int64_t)I * NB + tid, -v);
+    store_coherent(xo + (int64_t)I * NB + tid, -v);
   }
-  __syncthreads();
-  if (tid == 0) publish(flags + d.flag_off + I, epoch);
 }
 
 // Many right-hand sides (k <= KC columns): X <- L^-1 X or U^-1 X, X in block
@@ -1414,17 +1428,21 @@ static void qblocks_impl(const FactorPlan& P, T* A, const T* Ainv, hipStream_t s
 }
 
 template <typename T>
-static void solve_impl(const FactorPlan& P, const T* A, const T* Ainv, double* x, unsigned* sync, unsigned* flags,
-                       DevErr* err, hipStream_t st) {
+static void solve_impl(const FactorPlan& P, const T* A, const T* Ainv, double* x, unsigned* sync, DevErr* err,
+                       hipStream_t st) {
   if (P.n_items == 0) return;
+  double* y = P.d_y.p;   // forward result, backward input
+  const unsigned ni = (unsigned)P.n_items;
+  k_pending<<<ni, NB, 0, st>>>(P.d_desc.p, P.d_items_fwd.p, y);
   k_solve_begin<<<1, 1, 0, st>>>(sync);
-  k_trsv<T, false><<<dim3((unsigned)P.n_items), dim3(kTrsvThreads), 0, st>>>(
-      P.d_desc.p, P.d_items_fwd.p, A, Ainv, x, sync, flags, err, P.sparse ? P.d_dep_fwd_ptr.p : nullptr,
-      P.sparse ? P.d_dep_fwd.p : nullptr);
+  k_trsv<T, false><<<ni, dim3(kTrsvThreads), 0, st>>>(P.d_desc.p, P.d_items_fwd.p, A, Ainv, x, y, sync, err,
+                                                       P.sparse ? P.d_dep_fwd_ptr.p : nullptr,
+                                                       P.sparse ? P.d_dep_fwd.p : nullptr);
+  k_pending<<<ni, NB, 0, st>>>(P.d_desc.p, P.d_items_fwd.p, x);
   k_solve_begin<<<1, 1, 0, st>>>(sync);
-  k_trsv<T, true><<<dim3((unsigned)P.n_items), dim3(kTrsvThreads), 0, st>>>(
-      P.d_desc.p, P.d_items_bwd.p, A, Ainv, x, sync, flags, err, P.sparse ? P.d_dep_bwd_ptr.p : nullptr,
-      P.sparse ? P.d_dep_bwd.p : nullptr);
+  k_trsv<T, true><<<ni, dim3(kTrsvThreads), 0, st>>>(P.d_desc.p, P.d_items_bwd.p, A, Ainv, y, x, sync, err,
+                                                      P.sparse ? P.d_dep_bwd_ptr.p : nullptr,
+                                                      P.sparse ? P.d_dep_bwd.p : nullptr);
   HIP_CHECK(hipGetLastError());
 }
 
@@ -1445,13 +1463,13 @@ static void solve_multi_impl(const FactorPlan& P, const T* A, const T* Ainv, dou
 void mirror(const FactorPlan& P, double* A, hipStream_t st) { mirror_impl<double>(P, A, st); }
 void mirror(const FactorPlan& P, float* A, hipStream_t st) { mirror_impl<float>(P, A, st); }
 
-void solve(const FactorPlan& P, const double* A, const double* Ainv, double* x, unsigned* sync, unsigned* flags,
-           DevErr* err, hipStream_t st) {
-  solve_impl<double>(P, A, Ainv, x, sync, flags, err, st);
+void solve(const FactorPlan& P, const double* A, const double* Ainv, double* x, unsigned* sync, DevErr* err,
+           hipStream_t st) {
+  solve_impl<double>(P, A, Ainv, x, sync, err, st);
 }
-void solve(const FactorPlan& P, const float* A, const float* Ainv, double* x, unsigned* sync, unsigned* flags,
-           DevErr* err, hipStream_t st) {
-  solve_impl<float>(P, A, Ainv, x, sync, flags, err, st);
+void solve(const FactorPlan& P, const float* A, const float* Ainv, double* x, unsigned* sync, DevErr* err,
+           hipStream_t st) {
+  solve_impl<float>(P, A, Ainv, x, sync, err, st);
 }
 void solve_multi(const FactorPlan& P, const double* A, const double* Ainv, double* X, int ldk, int k,
                  unsigned* sync, unsigned* flags, DevErr* err, hipStream_t st) {

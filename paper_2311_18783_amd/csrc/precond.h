@@ -21,7 +21,6 @@ struct geneo_precond {
   // in FP64 after the probe (empty when none fell back: `local` serves all)
   geneo::FactorPlan local32, local64;
   int32_t n_fallback = 0;
-  geneo::DevBuf<unsigned> d_flags_local64;
   geneo::DevBuf<int8_t> d_refine;            // batch row -> 1 if its subdomain is refined (FP32)
   // batch-row CSR of the local matrices A_i (columns = batch positions,
   // values = slots of the global CSR), for the FP64 residual of the refinement
@@ -44,7 +43,6 @@ struct geneo_precond {
   int32_t n_snk_all = 0;                    // SNK columns before it (the paper's SNK size)
   geneo::FactorPlan coarse;
   geneo::DevBuf<double> dE, dEinv, d_odiag, d_pivrel;
-  geneo::DevBuf<unsigned> d_flags_coarse;
   geneo::DevBuf<int32_t> d_zc_ptr, d_zc_row;   // SNK columns: free edges
   geneo::DevBuf<double> d_zc_val;
   geneo::DevBuf<int32_t> d_zr_ptr, d_zr_col;   // SNK rows: coarse columns

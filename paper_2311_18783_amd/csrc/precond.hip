@@ -378,7 +378,7 @@ static void fp32_probe(geneo_ctx* ctx, geneo_precond* pc, const std::vector<MatD
   for (int it = 0; it < kPowerSteps; ++it) {
     k_local_residual<<<nblocks(len), 256, 0, st>>>(len, pc->d_brp.p, pc->d_bcol.p, pc->d_bslot.p, s->d_val.p,
                                                    nullptr, v, nullptr, t);
-    solve(pc->local, pc->fL.p, pc->fLinv.p, t, ctx->d_sync, pc->d_flags_local.p, ctx->d_err, st);
+    solve(pc->local, pc->fL.p, pc->fLinv.p, t, ctx->d_sync, ctx->d_err, st);
     k_axpby<<<nblocks(len), 256, 0, st>>>(len, 1.0, v, 1.0, t, v);
     if (it >= kPowerSteps - 2) k_seg_sumsq<<<N, 256, 0, st>>>(d_voff.p, v, sq.p + (it - (kPowerSteps - 2)) * N);
   }
@@ -412,9 +412,8 @@ static void fp32_probe(geneo_ctx* ctx, geneo_precond* pc, const std::vector<MatD
   const int32_t f32 = renumber(d32), f64 = renumber(d64);
   if (!d32.empty()) pc->local32.build(d32, st);
   pc->local64.build(d64, st);
-  pc->d_flags_local64.alloc(std::max(f64, 1));
-  HIP_CHECK(hipMemsetAsync(pc->d_flags_local64.p, 0, sizeof(unsigned) * std::max(f64, 1), st));
   (void)f32;
+  (void)f64;
   // FP64 copies of the fallback matrices (extraction of every block is one
   // cheap pass; only the fallback subset is factored)
   const MatDesc& last = descs.back();
@@ -755,8 +754,6 @@ void setup_precond(geneo_ctx* ctx, geneo_precond* pc) {
   pc->dEinv.alloc(2 * n0p * NB);
   pc->d_odiag.alloc(n0p);
   pc->d_pivrel.alloc(n0p);
-  pc->d_flags_coarse.alloc(n0p / NB);
-  HIP_CHECK(hipMemsetAsync(pc->d_flags_coarse.p, 0, sizeof(unsigned) * (n0p / NB), st));
   pc->w_c1.alloc(n0p);
   pc->w_c2.alloc(n0p);
   HIP_CHECK(hipMemsetAsync(pc->w_c1.p, 0, sizeof(double) * n0p, st));
@@ -854,28 +851,28 @@ static void coarse_solve(geneo_ctx* ctx, const geneo_precond* pc, double* c) {
   // left there by an earlier call (e.g. a non-finite input) reaches the solve
   const int64_t n0p = pc->coarse.h_desc[0].ld;
   if (n0p > pc->n0) k_fill<<<nblocks(n0p - pc->n0), 256, 0, ctx->stream>>>(n0p - pc->n0, 0.0, c + pc->n0);
-  solve(pc->coarse, pc->dE.p, pc->dEinv.p, c, ctx->d_sync, pc->d_flags_coarse.p, ctx->d_err, ctx->stream);
+  solve(pc->coarse, pc->dE.p, pc->dEinv.p, c, ctx->d_sync, ctx->d_err, ctx->stream);
 }
 
 // b <- A_i^-1 b on every segment; FP32 factors get one FP64 refinement step
 static void local_solve(geneo_ctx* ctx, const geneo_precond* pc, double* b) {
   hipStream_t st = ctx->stream;
   if (pc->precision != GENEO_FP32_REFINE1) {
-    solve(pc->local, pc->dL.p, pc->dLinv.p, b, ctx->d_sync, pc->d_flags_local.p, ctx->d_err, st);
+    solve(pc->local, pc->dL.p, pc->dLinv.p, b, ctx->d_sync, ctx->d_err, st);
     return;
   }
   const int64_t len = pc->batch_len;
   const FactorPlan& p32 = pc->n_fallback ? pc->local32 : pc->local;
   double* rhs = pc->w_b3.p;
   HIP_CHECK(hipMemcpyAsync(rhs, b, sizeof(double) * len, hipMemcpyDeviceToDevice, st));
-  if (p32.nmat) solve(p32, pc->fL.p, pc->fLinv.p, b, ctx->d_sync, pc->d_flags_local.p, ctx->d_err, st);
+  if (p32.nmat) solve(p32, pc->fL.p, pc->fLinv.p, b, ctx->d_sync, ctx->d_err, st);
   if (pc->n_fallback)
-    solve(pc->local64, pc->dL.p, pc->dLinv.p, b, ctx->d_sync, pc->d_flags_local64.p, ctx->d_err, st);
+    solve(pc->local64, pc->dL.p, pc->dLinv.p, b, ctx->d_sync, ctx->d_err, st);
   if (!p32.nmat) return;
   // rhs <- rhs - A_i yhat on the refined subdomains (0 elsewhere), then the correction
   k_local_residual<<<nblocks(len), 256, 0, st>>>(len, pc->d_brp.p, pc->d_bcol.p, pc->d_bslot.p, pc->sys->d_val.p, rhs,
                                                  b, pc->n_fallback ? pc->d_refine.p : nullptr, rhs);
-  solve(p32, pc->fL.p, pc->fLinv.p, rhs, ctx->d_sync, pc->d_flags_local.p, ctx->d_err, st);
+  solve(p32, pc->fL.p, pc->fLinv.p, rhs, ctx->d_sync, ctx->d_err, st);
   k_axpby<<<nblocks(len), 256, 0, st>>>(len, 1.0, b, 1.0, rhs, b);
 }
 
