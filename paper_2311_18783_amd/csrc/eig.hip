@@ -220,15 +220,30 @@ __global__ void k_gram_reduce(int m, const int64_t* __restrict__ chunk_off, cons
 
 // ---------------------------------------------------- Rayleigh-Ritz (LDS)
 constexpr int kMaxM = 72;
+constexpr int kLd = kMaxM + 1;   // LDS row pitch bound of the Rayleigh-Ritz matrices
 constexpr int kRRThreads = 1024;   // threads of the Rayleigh-Ritz workgroup (Jacobi rotations in parallel)
 
 // Jacobi eigendecomposition of the symmetric n x n matrix a (row-major, ld),
 // eigenvectors in v; parallel round-robin ordering, all threads of the block.
+// Each round rotates ne/2 disjoint pairs: one pass applies the rotations to
+// the rows, one to the columns of a and v.  A thread owns the same
+// (pair, index) items in every round (no divisions in the passes); with an
+// odd ld the column pass walks distinct LDS banks.
+constexpr int kJacItems = (kMaxM / 2 * kMaxM + kRRThreads - 1) / kRRThreads;
+
 __device__ void jacobi_eig(double* a, double* v, int n, int ld, double* rot_c, double* rot_s, int* pp, int* qq,
                            double* red) {
   const int tid = threadIdx.x;
   for (int idx = tid; idx < n * n; idx += blockDim.x) v[(idx / n) * ld + idx % n] = (idx / n == idx % n) ? 1.0 : 0.0;
   const int ne = n + (n & 1);   // even number of slots; slot n (if odd) is a dummy
+  const int half = ne / 2;
+  int it_slot[kJacItems], it_idx[kJacItems];
+#pragma unroll
+  for (int q = 0; q < kJacItems; ++q) {
+    const int e = tid + q * kRRThreads;
+    it_slot[q] = e < half * n ? e / n : -1;
+    it_idx[q] = e < half * n ? e % n : 0;
+  }
   __syncthreads();
   for (int sweep = 0; sweep < 30; ++sweep) {
     // convergence: off-diagonal mass vs diagonal
@@ -252,7 +267,7 @@ __device__ void jacobi_eig(double* a, double* v, int n, int ld, double* rot_c, d
     __syncthreads();
     if (done) break;
     for (int round = 0; round < ne - 1; ++round) {
-      if (tid < ne / 2) {
+      if (tid < half) {
         int p, q;
         if (tid == 0) {
           p = round;
@@ -279,9 +294,11 @@ __device__ void jacobi_eig(double* a, double* v, int n, int ld, double* rot_c, d
       }
       __syncthreads();
       // rows: A <- J^T A
-      for (int idx = tid; idx < (ne / 2) * n; idx += blockDim.x) {
-        const int slot = idx / n, col = idx % n;
-        const int p = pp[slot], q = qq[slot];
+#pragma unroll
+      for (int it = 0; it < kJacItems; ++it) {
+        const int slot = it_slot[it];
+        if (slot < 0) continue;
+        const int p = pp[slot], q = qq[slot], col = it_idx[it];
         if (q >= n) continue;
         const double c = rot_c[slot], s = rot_s[slot];
         const double x = a[p * ld + col], y = a[q * ld + col];
@@ -290,9 +307,11 @@ __device__ void jacobi_eig(double* a, double* v, int n, int ld, double* rot_c, d
       }
       __syncthreads();
       // columns: A <- A J, V <- V J
-      for (int idx = tid; idx < (ne / 2) * n; idx += blockDim.x) {
-        const int slot = idx / n, row = idx % n;
-        const int p = pp[slot], q = qq[slot];
+#pragma unroll
+      for (int it = 0; it < kJacItems; ++it) {
+        const int slot = it_slot[it];
+        if (slot < 0) continue;
+        const int p = pp[slot], q = qq[slot], row = it_idx[it];
         if (q >= n) continue;
         const double c = rot_c[slot], s = rot_s[slot];
         double x = a[row * ld + p], y = a[row * ld + q];
@@ -319,33 +338,34 @@ __global__ __launch_bounds__(kRRThreads) void k_rayleigh_ritz(int m, int k, cons
                                                        int svqb) {
   const int j = blockIdx.x;
   if (active && !active[j]) return;
-  __shared__ double A[kMaxM * kMaxM], B[kMaxM * kMaxM], V[kMaxM * kMaxM];
+  __shared__ double A[kMaxM * kLd], B[kMaxM * kLd], V[kMaxM * kLd];
   __shared__ double dsc[kMaxM], lam[kMaxM], rc[kMaxM / 2 + 1], rs[kMaxM / 2 + 1], red[2 * kRRThreads];
   __shared__ int pp[kMaxM / 2 + 1], qq[kMaxM / 2 + 1], keep[kMaxM], order[kMaxM];
   __shared__ int nk;
   const int tid = threadIdx.x;
   const int mm = m * m;
+  const int ld = m | 1;   // odd row pitch: column walks hit distinct banks
   const double* GA = gram + (int64_t)j * 2 * mm;
   const double* GB = GA + mm;
   // symmetrise; diagonal scaling of the B-Gram
   for (int idx = tid; idx < mm; idx += kRRThreads) {
     const int a = idx % m, b = idx / m;
-    A[a * m + b] = 0.5 * (GA[a + b * m] + GA[b + a * m]);
-    B[a * m + b] = 0.5 * (GB[a + b * m] + GB[b + a * m]);
+    A[a * ld + b] = 0.5 * (GA[a + b * m] + GA[b + a * m]);
+    B[a * ld + b] = 0.5 * (GB[a + b * m] + GB[b + a * m]);
   }
   __syncthreads();
   if (tid < m) {
-    const double d = B[tid * m + tid];
+    const double d = B[tid * ld + tid];
     dsc[tid] = d > 0.0 ? 1.0 / sqrt(d) : 0.0;
   }
   __syncthreads();
   for (int idx = tid; idx < mm; idx += kRRThreads) {
     const int a = idx / m, b = idx % m;
-    A[a * m + b] *= dsc[a] * dsc[b];
-    B[a * m + b] *= dsc[a] * dsc[b];
+    A[a * ld + b] *= dsc[a] * dsc[b];
+    B[a * ld + b] *= dsc[a] * dsc[b];
   }
   __syncthreads();
-  // B-orthonormal coordinates U (m x n2, stored in B, row-major ld m):
+  // B-orthonormal coordinates U (m x n2, stored in B, row-major pitch ld):
   // Rayleigh-Ritz bases are B-orthonormal blocks by construction, so the
   // scaled B-Gram is the identity up to rounding and a Cholesky factor
   // B_kk = L L^T of its non-zero columns gives U = L^-T; a pivot below
@@ -364,47 +384,47 @@ __global__ __launch_bounds__(kRRThreads) void k_rayleigh_ritz(int m, int k, cons
   if (!s_fail) {
     for (int idx = tid; idx < n2 * n2; idx += kRRThreads) {
       const int r = idx / n2, c = idx % n2;
-      V[r * m + c] = r >= c ? B[keep[r] * m + keep[c]] : 0.0;
+      V[r * ld + c] = r >= c ? B[keep[r] * ld + keep[c]] : 0.0;
     }
     __syncthreads();
     for (int j = 0; j < n2; ++j) {
       if (tid == 0) {
-        const double p = V[j * m + j];
+        const double p = V[j * ld + j];
         if (!(p > drop)) s_fail = 1;
-        V[j * m + j] = p > 0.0 ? sqrt(p) : 1.0;
+        V[j * ld + j] = p > 0.0 ? sqrt(p) : 1.0;
       }
       __syncthreads();
       if (s_fail) break;
-      const double djj = V[j * m + j];
-      for (int i = j + 1 + tid; i < n2; i += kRRThreads) V[i * m + j] /= djj;
+      const double djj = V[j * ld + j];
+      for (int i = j + 1 + tid; i < n2; i += kRRThreads) V[i * ld + j] /= djj;
       __syncthreads();
       const int t = n2 - j - 1;
       for (int idx = tid; idx < t * t; idx += kRRThreads) {
         const int i = j + 1 + idx / t, c = j + 1 + idx % t;
-        if (i >= c) V[i * m + c] -= V[i * m + j] * V[c * m + j];
+        if (i >= c) V[i * ld + c] -= V[i * ld + j] * V[c * ld + j];
       }
       __syncthreads();
     }
   }
   if (!s_fail) {
     // X = L^-1 (column c by thread c, forward substitution), U[keep[r]][c] = X[c][r]
-    for (int idx = tid; idx < m * n2; idx += kRRThreads) B[(idx / n2) * m + idx % n2] = 0.0;
+    for (int idx = tid; idx < m * n2; idx += kRRThreads) B[(idx / n2) * ld + idx % n2] = 0.0;
     __syncthreads();
     if (tid < n2) {
       // thread r: column r of X, i.e. row keep[r] of U
       const int r = tid;
-      double* urow = B + keep[r] * m;
+      double* urow = B + keep[r] * ld;
       for (int i = r; i < n2; ++i) {
         double sum = i == r ? 1.0 : 0.0;
-        for (int t = r; t < i; ++t) sum -= V[i * m + t] * urow[t];
-        urow[i] = sum / V[i * m + i];
+        for (int t = r; t < i; ++t) sum -= V[i * ld + t] * urow[t];
+        urow[i] = sum / V[i * ld + i];
       }
     }
     __syncthreads();
   }
   if (s_fail) {
-    jacobi_eig(B, V, m, m, rc, rs, pp, qq, red);
-    if (tid < m) lam[tid] = B[tid * m + tid];
+    jacobi_eig(B, V, m, ld, rc, rs, pp, qq, red);
+    if (tid < m) lam[tid] = B[tid * ld + tid];
     __syncthreads();
     if (tid == 0) {
       double mx = 0.0;
@@ -416,18 +436,18 @@ __global__ __launch_bounds__(kRRThreads) void k_rayleigh_ritz(int m, int k, cons
     }
     __syncthreads();
     n2 = nk;
-    // U = V[:, keep] / sqrt(lambda) stored in B (m x n2, row-major ld m)
+    // U = V[:, keep] / sqrt(lambda) stored in B (m x n2, row-major pitch ld)
     for (int idx = tid; idx < m * n2; idx += kRRThreads) {
       const int r = idx / n2, c = idx % n2;
       const int col = keep[c];
-      B[r * m + c] = V[r * m + col] / sqrt(lam[col]);
+      B[r * ld + c] = V[r * ld + col] / sqrt(lam[col]);
     }
     __syncthreads();
   }
   if (svqb) {
     for (int idx = tid; idx < m * k; idx += kRRThreads) {
       const int r = idx % m, c = idx / m;
-      coef[(int64_t)j * m * k + (int64_t)c * m + r] = c < n2 ? dsc[r] * B[r * m + c] : 0.0;
+      coef[(int64_t)j * m * k + (int64_t)c * m + r] = c < n2 ? dsc[r] * B[r * ld + c] : 0.0;
     }
     return;
   }
@@ -435,30 +455,30 @@ __global__ __launch_bounds__(kRRThreads) void k_rayleigh_ritz(int m, int k, cons
   for (int idx = tid; idx < m * n2; idx += kRRThreads) {
     const int r = idx / n2, c = idx % n2;
     double s = 0.0;
-    for (int t = 0; t < m; ++t) s += A[r * m + t] * B[t * m + c];
-    V[r * m + c] = s;
+    for (int t = 0; t < m; ++t) s += A[r * ld + t] * B[t * ld + c];
+    V[r * ld + c] = s;
   }
   __syncthreads();
   for (int idx = tid; idx < n2 * n2; idx += kRRThreads) {
     const int r = idx / n2, c = idx % n2;
     double s = 0.0;
-    for (int t = 0; t < m; ++t) s += B[t * m + r] * V[t * m + c];
-    A[r * m + c] = s;
+    for (int t = 0; t < m; ++t) s += B[t * ld + r] * V[t * ld + c];
+    A[r * ld + c] = s;
   }
   __syncthreads();
   for (int idx = tid; idx < n2 * n2; idx += kRRThreads) {
     const int r = idx / n2, c = idx % n2;
     if (r < c) {
-      const double s = 0.5 * (A[r * m + c] + A[c * m + r]);
-      A[r * m + c] = s;
-      A[c * m + r] = s;
+      const double s = 0.5 * (A[r * ld + c] + A[c * ld + r]);
+      A[r * ld + c] = s;
+      A[c * ld + r] = s;
     }
   }
   __syncthreads();
-  jacobi_eig(A, V, n2, m, rc, rs, pp, qq, red);
+  jacobi_eig(A, V, n2, ld, rc, rs, pp, qq, red);
   if (tid == 0) {
     for (int i = 0; i < n2; ++i) {
-      lam[i] = A[i * m + i];
+      lam[i] = A[i * ld + i];
       order[i] = i;
     }
     for (int i = 1; i < n2; ++i) {   // insertion sort, descending
@@ -478,7 +498,7 @@ __global__ __launch_bounds__(kRRThreads) void k_rayleigh_ritz(int m, int k, cons
     double s = 0.0;
     if (c < n2) {
       const int col = order[c];
-      for (int t = 0; t < n2; ++t) s += B[r * m + t] * V[t * m + col];
+      for (int t = 0; t < n2; ++t) s += B[r * ld + t] * V[t * ld + col];
       s *= dsc[r];
     }
     coef[(int64_t)j * m * k + (int64_t)c * m + r] = s;
