@@ -684,51 +684,95 @@ __global__ __launch_bounds__(256) void k_block_rowmajor(int64_t len, int k, cons
   }
 }
 
-// Y = [base -] scale .* (A_j X) with X given row-major (Xt): every nonzero
-// reads one contiguous row of k values instead of k strided entries.
+// Workgroups are dealt to the 8 XCDs round-robin (id mod 8); this maps them
+// to contiguous logical ranges per XCD, so that neighbouring row blocks (and
+// the rows of X they gather) share one L2.
+__device__ inline unsigned xcd_block() {
+  const unsigned nb = gridDim.x, id = blockIdx.x, x = id & 7, per = nb >> 3, rem = nb & 7;
+  return x * per + (x < rem ? x : rem) + (id >> 3);
+}
+
+// Y = [base -] scale .* (A_j X) with X given row-major (Xt, pitch 32).  A
+// workgroup owns 64 consecutive batch rows; each wavefront takes two rows
+// at a time, one per half-wave, with lane q on column q: a nonzero costs one
+// coalesced 256-byte read of an Xt row.  Results go through LDS so that the
+// column-major block layout of Y is written in 64-row runs.
 __global__ __launch_bounds__(256) void k_spmm_rm(int64_t len, int k, const int32_t* __restrict__ row_sub,
                                                  const int64_t* __restrict__ voff, const int32_t* __restrict__ nloc,
                                                  const int64_t* __restrict__ rp_off, const int32_t* __restrict__ lrp,
                                                  const int32_t* __restrict__ lcol, const double* __restrict__ vals,
                                                  const double* __restrict__ Xt, const double* __restrict__ base,
                                                  const double* __restrict__ scale, double* __restrict__ Y) {
-  const int64_t b = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  if (b >= len) return;
-  const int j = row_sub[b];
-  const int64_t r = b - voff[j];
-  const int64_t ld = voff[j + 1] - voff[j];
-  double acc[32];
-#pragma unroll
-  for (int q = 0; q < 32; ++q) acc[q] = 0.0;
-  const int kq = (k + 3) >> 2;   // double4 groups in use
-  if (r < nloc[j]) {
-    const int32_t* rp = lrp + rp_off[j];
-    for (int32_t t = rp[r]; t < rp[r + 1]; ++t) {
-      const double v = vals[t];
-      const double4* xr = reinterpret_cast<const double4*>(Xt + (voff[j] + lcol[t]) * 32);
-#pragma unroll
-      for (int g = 0; g < 8; ++g)
-        if (g < kq) {
-          const double4 x = xr[g];
-          acc[4 * g] += v * x.x;
-          acc[4 * g + 1] += v * x.y;
-          acc[4 * g + 2] += v * x.z;
-          acc[4 * g + 3] += v * x.w;
-        }
+  __shared__ double tile[64][33];
+  __shared__ int64_t s_o[64], s_ld[64], s_x[64];
+  __shared__ int32_t s_t0[64], s_nnz[64];
+  const int64_t b0 = (int64_t)xcd_block() * 64;
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const int q = lane & 31, hw = lane >> 5;
+  // row metadata for the 64 rows, fetched once in parallel
+  if (tid < 64) {
+    const int64_t b = b0 + tid;
+    int64_t o = -1, ldj = 0, xo = 0;
+    int32_t t0 = 0, nnz = 0;
+    if (b < len) {
+      const int j = row_sub[b];
+      const int64_t vj = voff[j], r = b - vj;
+      o = vj * k + r;
+      ldj = voff[j + 1] - vj;
+      xo = vj * 32;
+      if (r < nloc[j]) {
+        const int32_t* rp = lrp + rp_off[j];
+        t0 = rp[r];
+        nnz = rp[r + 1] - t0;
+      }
     }
-    if (scale) {
-      const double sc = scale[b];
-#pragma unroll
-      for (int q = 0; q < 32; ++q) acc[q] *= sc;
-    }
+    s_o[tid] = o;
+    s_ld[tid] = ldj;
+    s_x[tid] = xo;
+    s_t0[tid] = t0;
+    s_nnz[tid] = nnz;
   }
-  const int64_t o = voff[j] * k + r;
-#pragma unroll
-  for (int q = 0; q < 32; ++q)
-    if (q < k) {
-      const int64_t oq = o + (int64_t)q * ld;
-      Y[oq] = base ? base[oq] - acc[q] : acc[q];
+  __syncthreads();
+  for (int i = 0; i < 8; ++i) {
+    const int rl = 16 * w + 2 * i + hw;
+    const int32_t t0 = s_t0[rl], nnz = s_nnz[rl];
+    const double* xb = Xt + s_x[rl] + q;
+    double acc = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+    // the row's column indices and values are fetched one per lane and
+    // broadcast inside the half-wave, so the gathers do not wait on them
+    for (int cb = 0; cb < nnz; cb += 32) {
+      int my_c = 0;
+      double my_v = 0.0;
+      if (cb + q < nnz) {
+        my_c = lcol[t0 + cb + q];
+        my_v = vals[t0 + cb + q];
+      }
+      const int n = min(32, nnz - cb);
+      int t = 0;
+      for (; t + 3 < n; t += 4) {
+        const int c0 = __shfl(my_c, t, 32), c1 = __shfl(my_c, t + 1, 32);
+        const int c2 = __shfl(my_c, t + 2, 32), c3 = __shfl(my_c, t + 3, 32);
+        const double v0 = __shfl(my_v, t, 32), v1 = __shfl(my_v, t + 1, 32);
+        const double v2 = __shfl(my_v, t + 2, 32), v3 = __shfl(my_v, t + 3, 32);
+        acc += v0 * xb[(int64_t)c0 * 32];
+        a1 += v1 * xb[(int64_t)c1 * 32];
+        a2 += v2 * xb[(int64_t)c2 * 32];
+        a3 += v3 * xb[(int64_t)c3 * 32];
+      }
+      for (; t < n; ++t) acc += __shfl(my_v, t, 32) * xb[(int64_t)__shfl(my_c, t, 32) * 32];
     }
+    acc += a1 + a2 + a3;
+    if (scale && nnz > 0) acc *= scale[b0 + rl];
+    tile[rl][q] = acc;
+  }
+  __syncthreads();
+  for (int e = tid; e < 64 * k; e += 256) {
+    const int rl = e & 63, qq = e >> 6;
+    const int64_t o = s_o[rl];
+    if (o < 0) continue;
+    const int64_t oq = o + (int64_t)qq * s_ld[rl];
+    Y[oq] = base ? base[oq] - tile[rl][qq] : tile[rl][qq];
+  }
 }
 
 // lvals == nullptr selects the local A_j values
@@ -736,8 +780,9 @@ static void spmm(const geneo_precond* pc, EigWork& w, const double* lvals, const
                  const double* scale, double* Y, hipStream_t st) {
   if (!w.xrow.p) w.xrow.alloc((size_t)w.len * 32);
   k_block_rowmajor<<<(unsigned)((w.len + 63) / 64), 256, 0, st>>>(w.len, w.k, w.row_sub.p, w.voff_d.p, X, w.xrow.p);
-  k_spmm_rm<<<nb256(w.len), 256, 0, st>>>(w.len, w.k, w.row_sub.p, w.voff_d.p, w.nloc.p, w.rp_off.p, w.lrp.p,
-                                          pc->d_lcol.p, lvals ? lvals : w.aval.p, w.xrow.p, base, scale, Y);
+  k_spmm_rm<<<(unsigned)((w.len + 63) / 64), 256, 0, st>>>(w.len, w.k, w.row_sub.p, w.voff_d.p, w.nloc.p,
+                                                          w.rp_off.p, w.lrp.p, pc->d_lcol.p,
+                                                          lvals ? lvals : w.aval.p, w.xrow.p, base, scale, Y);
 }
 static void gt(EigWork& w, const double* X, double* Nn, hipStream_t st) {
   k_gt<<<nb256(w.plen * w.k), 256, 0, st>>>(w.plen, w.k, w.node_sub.p, w.poff_d.p, w.pl.p, w.voff_d.p, w.ne_off.p,
