@@ -506,47 +506,78 @@ __global__ __launch_bounds__(kRRThreads) void k_rayleigh_ritz(int m, int k, cons
   if (tid < k) theta[j * k + tid] = tid < n2 ? lam[order[tid]] : -1e300;
 }
 
-// out = [L0 L1 L2][:, cols from coefficient rows r0..m) * coef  (per subdomain, n_pad x k)
+// Block-batch products.  Segments start at multiples of 128 rows, so a
+// workgroup of 128 rows lies in one subdomain: its coefficients are uniform
+// (scalar loads).  Thread (row rr, half qh) keeps the 16 output columns
+// 16 qh .. 16 qh + 15 of its row in registers and reads each input entry
+// once, coalesced along the rows.
+constexpr int kBR = NB;   // rows per workgroup
+
+// out = [L0 L1 L2][:, cols from coefficient rows c0..m) * coef  (per subdomain, n_pad x k)
 // i.e. out[r][q] = sum_{c = c0}^{m-1} Lblk(c)[r][c % k] * coef[c][q]; inactive: out = keep
-__global__ void k_combine(int64_t len, int k, int m, int c0, const int32_t* __restrict__ row_sub,
-                          const int64_t* __restrict__ voff, const int32_t* __restrict__ active,
-                          const double* __restrict__ L0, const double* __restrict__ L1,
-                          const double* __restrict__ L2, const double* __restrict__ coef,
-                          const double* __restrict__ keep_src, double* __restrict__ out) {
-  int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  if (idx >= len * k) return;
-  const int64_t b = idx % len;
-  const int q = (int)(idx / len);
-  const int j = row_sub[b];
-  const int64_t r = b - voff[j];
-  const int64_t ld = voff[j + 1] - voff[j];
-  const int64_t o = voff[j] * k + (int64_t)q * ld + r;
+__global__ __launch_bounds__(256) void k_combine(int64_t len, int k, int m, int c0, const int32_t* __restrict__ row_sub,
+                                                 const int64_t* __restrict__ voff, const int32_t* __restrict__ active,
+                                                 const double* __restrict__ L0, const double* __restrict__ L1,
+                                                 const double* __restrict__ L2, const double* __restrict__ coef,
+                                                 const double* __restrict__ keep_src, double* __restrict__ out) {
+  const int64_t b0 = (int64_t)blockIdx.x * kBR;
+  const int tid = threadIdx.x, rr = tid & (kBR - 1);
+  const int qh = __builtin_amdgcn_readfirstlane(tid >> 7);
+  const int j = row_sub[b0];
+  const int64_t vj = voff[j], ld = voff[j + 1] - vj, r = b0 + rr - vj;
+  double* ob = out + vj * k + r;
   if (active && !active[j]) {
-    out[o] = keep_src ? keep_src[o] : 0.0;
+    for (int qq = 0; qq < 16; ++qq) {
+      const int q = 16 * qh + qq;
+      if (q < k) ob[(int64_t)q * ld] = keep_src ? keep_src[vj * k + (int64_t)q * ld + r] : 0.0;
+    }
     return;
   }
+  const double* cf = coef + (int64_t)j * m * k + (int64_t)16 * qh * m;
+  double acc[16];
+#pragma unroll
+  for (int qq = 0; qq < 16; ++qq) acc[qq] = 0.0;
   const double* L[3] = {L0, L1, L2};
-  const double* cf = coef + (int64_t)j * m * k + (int64_t)q * m;
-  double acc = 0.0;
-  for (int c = c0; c < m; ++c) acc += L[c / k][voff[j] * k + (int64_t)(c % k) * ld + r] * cf[c];
-  out[o] = acc;
+  for (int blk = c0 / k; blk * k < m; ++blk) {
+    const double* Lb = L[blk] + vj * k + r;
+    for (int cc = blk * k < c0 ? c0 - blk * k : 0; cc < k; ++cc) {
+      const int c = blk * k + cc;
+      const double x = Lb[(int64_t)cc * ld];
+#pragma unroll
+      for (int qq = 0; qq < 16; ++qq)
+        if (16 * qh + qq < k) acc[qq] += x * cf[qq * m + c];
+    }
+  }
+#pragma unroll
+  for (int qq = 0; qq < 16; ++qq)
+    if (16 * qh + qq < k) ob[(int64_t)(16 * qh + qq) * ld] = acc[qq];
 }
 
 // out -= X C  with C = Gram block (k x k per subdomain, from gram[j] rows 0..k of the A part)
-__global__ void k_sub_xc(int64_t len, int k, const int32_t* __restrict__ row_sub, const int64_t* __restrict__ voff,
-                         const double* __restrict__ X, const double* __restrict__ C, int ldc_stride,
-                         double* __restrict__ out) {
-  int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  if (idx >= len * k) return;
-  const int64_t b = idx % len;
-  const int q = (int)(idx / len);
-  const int j = row_sub[b];
-  const int64_t r = b - voff[j];
-  const int64_t ld = voff[j + 1] - voff[j];
-  const double* cj = C + (int64_t)j * ldc_stride;   // column-major k x k
-  double acc = 0.0;
-  for (int c = 0; c < k; ++c) acc += X[voff[j] * k + (int64_t)c * ld + r] * cj[c + q * k];
-  out[voff[j] * k + (int64_t)q * ld + r] -= acc;
+__global__ __launch_bounds__(256) void k_sub_xc(int64_t len, int k, const int32_t* __restrict__ row_sub,
+                                                const int64_t* __restrict__ voff, const double* __restrict__ X,
+                                                const double* __restrict__ C, int ldc_stride,
+                                                double* __restrict__ out) {
+  const int64_t b0 = (int64_t)blockIdx.x * kBR;
+  const int tid = threadIdx.x, rr = tid & (kBR - 1);
+  const int qh = __builtin_amdgcn_readfirstlane(tid >> 7);
+  const int j = row_sub[b0];
+  const int64_t vj = voff[j], ld = voff[j + 1] - vj, r = b0 + rr - vj;
+  const double* cj = C + (int64_t)j * ldc_stride + (int64_t)16 * qh * k;   // column-major k x k
+  double acc[16];
+#pragma unroll
+  for (int qq = 0; qq < 16; ++qq) acc[qq] = 0.0;
+  const double* xb = X + vj * k + r;
+  for (int c = 0; c < k; ++c) {
+    const double x = xb[(int64_t)c * ld];
+#pragma unroll
+    for (int qq = 0; qq < 16; ++qq)
+      if (16 * qh + qq < k) acc[qq] += x * cj[qq * k + c];
+  }
+  double* ob = out + vj * k + r;
+#pragma unroll
+  for (int qq = 0; qq < 16; ++qq)
+    if (16 * qh + qq < k) ob[(int64_t)(16 * qh + qq) * ld] -= acc[qq];
 }
 
 // random start block (counter-based splitmix64 -> standard normal via Box-Muller), pads 0
@@ -1005,6 +1036,8 @@ void solve_local_gevps(geneo_ctx* ctx, geneo_precond* pc) {
 
   // ---- LOBPCG
   const int64_t blk = w.len * k;
+  if (w.len % kBR) throw Error(GENEO_EINVAL, "batch length not a multiple of the block size");
+  const unsigned grows = (unsigned)(w.len / kBR);   // 128-row workgroups of the block-batch products
   DevBuf<double> X, Wb, P, AX, AW, AP, BX, BW, BP, Xn, Pn, T1, T2, Tv, Tb, NT, part, g, coef, theta, nrm;
   for (auto* b : {&X, &Wb, &P, &AX, &AW, &AP, &BX, &BW, &BP, &Xn, &Pn, &T1, &T2, &Tv, &Tb}) b->alloc(blk);
   NT.alloc(w.plen * k);
@@ -1048,16 +1081,16 @@ void solve_local_gevps(geneo_ctx* ctx, geneo_precond* pc) {
   // V <- V - U (U^T B V), BV recomputed by the caller
   auto orth = [&](const double* U, double* V, const double* BV) {
     gram(w, 1, U, nullptr, nullptr, BV, nullptr, nullptr, BV, nullptr, nullptr, part, g, st);
-    k_sub_xc<<<nb256(blk), 256, 0, st>>>(w.len, k, w.row_sub.p, w.voff_d.p, U, g.p, 2 * k * k, V);
+    k_sub_xc<<<grows, 256, 0, st>>>(w.len, k, w.row_sub.p, w.voff_d.p, U, g.p, 2 * k * k, V);
   };
   // B-orthonormalise V (numerically dependent columns become zero), twice
   auto svqb2 = [&](DevBuf<double>& V, DevBuf<double>& BV, const int32_t* a) {
     for (int t = 0; t < 2; ++t) {
       gram(w, 1, V.p, nullptr, nullptr, BV.p, nullptr, nullptr, BV.p, nullptr, nullptr, part, g, st);
       k_rayleigh_ritz<<<N, kRRThreads, 0, st>>>(k, k, g.p, a, drop, theta.p, coef.p, 1);
-      k_combine<<<nb256(blk), 256, 0, st>>>(w.len, k, k, 0, w.row_sub.p, w.voff_d.p, a, V.p, nullptr, nullptr,
+      k_combine<<<grows, 256, 0, st>>>(w.len, k, k, 0, w.row_sub.p, w.voff_d.p, a, V.p, nullptr, nullptr,
                                             coef.p, V.p, Tv.p);
-      k_combine<<<nb256(blk), 256, 0, st>>>(w.len, k, k, 0, w.row_sub.p, w.voff_d.p, a, BV.p, nullptr, nullptr,
+      k_combine<<<grows, 256, 0, st>>>(w.len, k, k, 0, w.row_sub.p, w.voff_d.p, a, BV.p, nullptr, nullptr,
                                             coef.p, BV.p, Tb.p);
       std::swap(V.p, Tv.p);
       std::swap(BV.p, Tb.p);
@@ -1068,7 +1101,7 @@ void solve_local_gevps(geneo_ctx* ctx, geneo_precond* pc) {
   apply_atilde(ctx, pc, w, X.p, AX.p, T1.p, T2.p, NT.p);
   gram(w, 1, X.p, nullptr, nullptr, AX.p, nullptr, nullptr, BX.p, nullptr, nullptr, part, g, st);
   k_rayleigh_ritz<<<N, kRRThreads, 0, st>>>(k, k, g.p, nullptr, drop, theta.p, coef.p, 0);
-  k_combine<<<nb256(blk), 256, 0, st>>>(w.len, k, k, 0, w.row_sub.p, w.voff_d.p, nullptr, X.p, nullptr, nullptr,
+  k_combine<<<grows, 256, 0, st>>>(w.len, k, k, 0, w.row_sub.p, w.voff_d.p, nullptr, X.p, nullptr, nullptr,
                                         coef.p, nullptr, Xn.p);
   std::swap(X.p, Xn.p);
   // products are recomputed from the basis after every update (tracking them
@@ -1161,9 +1194,9 @@ void solve_local_gevps(geneo_ctx* ctx, geneo_precond* pc) {
     gram(w, nl, X.p, Wb.p, have_p ? P.p : nullptr, AX.p, AW.p, have_p ? AP.p : nullptr, BX.p, BW.p,
          have_p ? BP.p : nullptr, part, g, st);
     k_rayleigh_ritz<<<N, kRRThreads, 0, st>>>(m, k, g.p, act, drop, theta.p, coef.p, 0);
-    k_combine<<<nb256(blk), 256, 0, st>>>(w.len, k, m, 0, w.row_sub.p, w.voff_d.p, act, X.p, Wb.p,
+    k_combine<<<grows, 256, 0, st>>>(w.len, k, m, 0, w.row_sub.p, w.voff_d.p, act, X.p, Wb.p,
                                           have_p ? P.p : nullptr, coef.p, X.p, Xn.p);
-    k_combine<<<nb256(blk), 256, 0, st>>>(w.len, k, m, k, w.row_sub.p, w.voff_d.p, act, X.p, Wb.p,
+    k_combine<<<grows, 256, 0, st>>>(w.len, k, m, k, w.row_sub.p, w.voff_d.p, act, X.p, Wb.p,
                                           have_p ? P.p : nullptr, coef.p, have_p ? P.p : nullptr, Pn.p);
     std::swap(X.p, Xn.p);
     std::swap(P.p, Pn.p);
