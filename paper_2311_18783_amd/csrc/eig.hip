@@ -146,7 +146,15 @@ __global__ __launch_bounds__(256) void k_residual(int k, const int64_t* __restri
 //   GA[a][b] = sum_r L[r][a] RA[r][b],  GB[a][b] = sum_r L[r][a] RB[r][b]
 // where the "left" block is [L0 L1 L2] (nl blocks of k columns) and the right
 // blocks likewise.  Partials land in part[(chunk) * 2 m^2 ...].
+// 32-row slices of the three blocks are staged in LDS (columns padded with
+// zeros to mp = 16 ceil(m / 16)); the products run on v_mfma_f64_16x16x4,
+// wave w owning output tiles w, w + 4, ... of both GA and GB (the L operand
+// is shared by the two).
 constexpr int kGramRows = 512, kGramSub = 32;
+constexpr int kGramMaxTiles = 7;   // per wave: ceil(25 / 4) for m <= 80
+
+typedef double gd4_t __attribute__((ext_vector_type(4)));
+
 __global__ __launch_bounds__(256) void k_gram(int k, int nl, const int64_t* __restrict__ voff,
                                               const int64_t* __restrict__ chunk_off, int nsub,
                                               const double* __restrict__ L0, const double* __restrict__ L1,
@@ -156,9 +164,10 @@ __global__ __launch_bounds__(256) void k_gram(int k, int nl, const int64_t* __re
                                               const double* __restrict__ B2, double* __restrict__ part) {
   extern __shared__ double sm[];
   const int m = nl * k;
-  double* ls = sm;                          // [kGramSub][m]
-  double* as = ls + kGramSub * m;
-  double* bs = as + kGramSub * m;
+  const int nt = (m + 15) >> 4, mp = nt * 16;
+  double* ls = sm;                          // [kGramSub][mp]
+  double* as = ls + kGramSub * mp;
+  double* bs = as + kGramSub * mp;
   const int j = find_seg(chunk_off, nsub, blockIdx.x);
   const int64_t chunk = blockIdx.x - chunk_off[j];
   const int64_t ld = voff[j + 1] - voff[j];
@@ -167,42 +176,62 @@ __global__ __launch_bounds__(256) void k_gram(int k, int nl, const int64_t* __re
   const double* Ls[3] = {L0, L1, L2};
   const double* As[3] = {A0, A1, A2};
   const double* Bs[3] = {B0, B1, B2};
-  const int mm = m * m;
-  double accA[21], accB[21];
-  for (int t = 0; t < 21; ++t) accA[t] = accB[t] = 0.0;
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, lr = lane & 15, lk = lane >> 4;
+  const int ntt = nt * nt;
+  gd4_t accA[kGramMaxTiles], accB[kGramMaxTiles];
+#pragma unroll
+  for (int t = 0; t < kGramMaxTiles; ++t) accA[t] = accB[t] = gd4_t{0, 0, 0, 0};
   for (int64_t r0 = rbeg; r0 < rend; r0 += kGramSub) {
-    for (int idx = threadIdx.x; idx < kGramSub * m; idx += 256) {
-      const int rr = idx % kGramSub, c = idx / kGramSub;
-      const int blk = c / k, q = c % k;
+    for (int idx = threadIdx.x; idx < kGramSub * mp; idx += 256) {
+      const int rr = idx & (kGramSub - 1), c = idx / kGramSub;
       const int64_t r = r0 + rr;
-      const int64_t o = base + (int64_t)q * ld + r;
-      const bool ok = r < rend;
-      ls[rr * m + c] = ok ? Ls[blk][o] : 0.0;
-      as[rr * m + c] = ok ? As[blk][o] : 0.0;
-      bs[rr * m + c] = ok ? Bs[blk][o] : 0.0;
+      double lv = 0.0, av = 0.0, bv = 0.0;
+      if (c < m && r < rend) {
+        const int blk = c / k, q = c - blk * k;
+        const int64_t o = base + (int64_t)q * ld + r;
+        lv = Ls[blk][o];
+        av = As[blk][o];
+        bv = Bs[blk][o];
+      }
+      ls[rr * mp + c] = lv;
+      as[rr * mp + c] = av;
+      bs[rr * mp + c] = bv;
     }
     __syncthreads();
-    for (int t = 0; t < 21; ++t) {
-      const int e = threadIdx.x + 256 * t;
-      if (e >= mm) break;
-      const int a = e % m, b = e / m;
-      double sa = 0.0, sb = 0.0;
-      for (int rr = 0; rr < kGramSub; ++rr) {
-        const double l = ls[rr * m + a];
-        sa += l * as[rr * m + b];
-        sb += l * bs[rr * m + b];
+#pragma unroll 2
+    for (int kk = 0; kk < kGramSub; kk += 4) {
+      const int ro = (kk + lk) * mp;
+#pragma unroll
+      for (int q = 0; q < kGramMaxTiles; ++q) {
+        const int t = w + 4 * q;
+        if (t < ntt) {
+          const int ta = t / nt, tb = t - ta * nt;
+          const double l = ls[ro + 16 * ta + lr];
+          accA[q] = __builtin_amdgcn_mfma_f64_16x16x4f64(l, as[ro + 16 * tb + lr], accA[q], 0, 0, 0);
+          accB[q] = __builtin_amdgcn_mfma_f64_16x16x4f64(l, bs[ro + 16 * tb + lr], accB[q], 0, 0, 0);
+        }
       }
-      accA[t] += sa;
-      accB[t] += sb;
     }
     __syncthreads();
   }
+  // lane holds D[16 ta + lk + 4 v][16 tb + lr]; out is column-major m x m
+  const int mm = m * m;
   double* out = part + (int64_t)blockIdx.x * 2 * mm;
-  for (int t = 0; t < 21; ++t) {
-    const int e = threadIdx.x + 256 * t;
-    if (e >= mm) break;
-    out[e] = accA[t];
-    out[mm + e] = accB[t];
+#pragma unroll
+  for (int q = 0; q < kGramMaxTiles; ++q) {
+    const int t = w + 4 * q;
+    if (t < ntt) {
+      const int ta = t / nt, tb = t - ta * nt;
+      const int b = 16 * tb + lr;
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int a = 16 * ta + lk + 4 * v;
+        if (a < m && b < m) {
+          out[a + b * m] = accA[q][v];
+          out[mm + a + b * m] = accB[q][v];
+        }
+      }
+    }
   }
 }
 
@@ -844,7 +873,8 @@ static void gram(EigWork& w, int nl, const double* L0, const double* L1, const d
                  const double* A1, const double* A2, const double* B0, const double* B1, const double* B2,
                  DevBuf<double>& part, DevBuf<double>& g, hipStream_t st) {
   const int m = nl * w.k;
-  const size_t lds = sizeof(double) * 3 * kGramSub * m;
+  const size_t lds = sizeof(double) * 3 * kGramSub * ((m + 15) / 16 * 16);
+  if (m > 16 * 5) throw Error(GENEO_EUNSUPPORTED, "Gram blocks wider than 80 columns");
   k_gram<<<dim3((unsigned)w.nchunks), 256, lds, st>>>(w.k, nl, w.voff_d.p, w.chunk_off.p, w.N, L0, L1, L2, A0, A1,
                                                        A2, B0, B1, B2, part.p);
   dim3 grid((unsigned)((2 * m * m + 255) / 256), (unsigned)w.N);
@@ -1051,7 +1081,7 @@ void solve_local_gevps(geneo_ctx* ctx, geneo_precond* pc) {
   DevBuf<int32_t> d_active;
   d_active.upload(active, st);
   HIP_CHECK(hipFuncSetAttribute((const void*)k_gram, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                (int)(sizeof(double) * 3 * kGramSub * mmax)));
+                                (int)(sizeof(double) * 3 * kGramSub * ((mmax + 15) / 16 * 16))));
 
   // start block: warm start if given, else random; B-orthogonal projection out of span(G_j)
   if (pc->opts.warm_start) {
