@@ -691,15 +691,21 @@ __global__ void k_dense_scatter_vals(int64_t nnz, const int32_t* __restrict__ lr
   A[d.off + (int64_t)lcol[k] * d.ld + lrow[k]] = vals[k];
 }
 
-__global__ void k_fill_pad_identity(int64_t total, int nmat, const int64_t* __restrict__ mat_start,
-                                    const MatDesc* __restrict__ desc, double* __restrict__ A) {
-  int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  if (idx >= total) return;
-  const int j = find_seg(mat_start, nmat, idx);
-  const MatDesc d = desc[j];
-  const int64_t loc = idx - mat_start[j];
-  const int64_t r = loc % d.ld, c = loc / d.ld;
-  A[d.off + loc] = (r == c && r >= d.n) ? 1.0 : 0.0;
+// dense batch matrices: zero with ones on the padding diagonal; workgroup
+// (c, m) writes column c of matrix m (grid (max ld, nmat))
+__global__ __launch_bounds__(256) void k_fill_pad_identity(const MatDesc* __restrict__ desc, double* __restrict__ A) {
+  const MatDesc d = desc[blockIdx.y];
+  const int c = blockIdx.x;
+  if (c >= d.ld) return;
+  const int64_t col = d.off + (int64_t)c * d.ld;
+  for (int r = 2 * threadIdx.x; r < d.ld; r += 512)
+    *reinterpret_cast<double2*>(A + col + r) =
+        double2{(r == c && r >= d.n) ? 1.0 : 0.0, (r + 1 == c && r + 1 >= d.n) ? 1.0 : 0.0};
+}
+static dim3 fill_grid(const std::vector<MatDesc>& d) {
+  int mx = 1;
+  for (const auto& x : d) mx = std::max(mx, x.ld);
+  return dim3((unsigned)mx, (unsigned)d.size());
 }
 
 // ------------------------------------------------------------- driver
@@ -1029,13 +1035,9 @@ void solve_local_gevps(geneo_ctx* ctx, geneo_precond* pc) {
   }
   const auto& ld = pc->local.h_desc;
   const int64_t dense_total = ld.back().off + (int64_t)ld.back().ld * ld.back().ld;
-  std::vector<int64_t> mstart(N);
-  for (int j = 0; j < N; ++j) mstart[j] = ld[j].off;
-  DevBuf<int64_t> d_mstart;
-  d_mstart.upload(mstart, st);
   w.LB.alloc(dense_total);
   w.LBinv.alloc(pc->dLinv.n ? pc->dLinv.n : pc->fLinv.n);
-  k_fill_pad_identity<<<nb256(dense_total), 256, 0, st>>>(dense_total, N, d_mstart.p, pc->local.d_desc.p, w.LB.p);
+  k_fill_pad_identity<<<fill_grid(ld), 256, 0, st>>>(pc->local.d_desc.p, w.LB.p);
   k_dense_scatter_vals<<<nb256(lnnz), 256, 0, st>>>(lnnz, pc->d_lrow.p, pc->d_lcol.p, pc->d_lnnz_off.p, N,
                                                      pc->local.d_desc.p, w.bval.p, w.LB.p);
   factor(pc->local, w.LB.p, w.LBinv.p, nullptr, 0.0, nullptr, ctx->d_err, st);
@@ -1044,13 +1046,8 @@ void solve_local_gevps(geneo_ctx* ctx, geneo_precond* pc) {
 
   // ---- S_j = G^T A_j G, H_j = G^T B_j G, factor
   {
-    std::vector<int64_t> nstart(N);
-    for (int j = 0; j < N; ++j) nstart[j] = ndesc[j].off;
-    DevBuf<int64_t> d_nstart;
-    d_nstart.upload(nstart, st);
-    const int64_t tot = w.S.n;
-    k_fill_pad_identity<<<nb256(tot), 256, 0, st>>>(tot, N, d_nstart.p, w.node.d_desc.p, w.S.p);
-    k_fill_pad_identity<<<nb256(tot), 256, 0, st>>>(tot, N, d_nstart.p, w.node.d_desc.p, w.H.p);
+    k_fill_pad_identity<<<fill_grid(ndesc), 256, 0, st>>>(w.node.d_desc.p, w.S.p);
+    k_fill_pad_identity<<<fill_grid(ndesc), 256, 0, st>>>(w.node.d_desc.p, w.H.p);
     k_gmg<<<nb256(w.plen), 256, 0, st>>>(w.plen, w.node_sub.p, w.poff_d.p, w.pl.p, w.ne_off.p, w.ne_ptr.p,
                                          w.ne_edge.p, w.ne_sign.p, w.voff_d.p, w.rp_off.p, w.lrp.p, pc->d_lcol.p,
                                          pc->d_lslot.p, s->d_val.p, nullptr, w.ena.p, w.enb.p, w.node.d_desc.p,

@@ -17,21 +17,25 @@
 namespace geneo {
 
 // ---------------------------------------------------------- small kernels
-__global__ void k_fill_identity_pad(const MatDesc* __restrict__ desc, int nmat, double* __restrict__ A,
-                                    float* __restrict__ Af, int64_t total, const int64_t* __restrict__ mat_start) {
-  int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  if (idx >= total) return;
-  int lo = 0, hi = nmat - 1;
-  while (lo < hi) {
-    int mid = (lo + hi + 1) >> 1;
-    if (mat_start[mid] <= idx) lo = mid; else hi = mid - 1;
+// Dense batch matrices: zero, with ones on the diagonal of the padding rows
+// (r >= n).  Workgroup (c, m) writes column c of matrix m with 16-byte stores
+// (launch: grid (max ld, nmat)).
+__global__ __launch_bounds__(256) void k_fill_identity_pad(const MatDesc* __restrict__ desc, double* __restrict__ A,
+                                                           float* __restrict__ Af) {
+  const MatDesc d = desc[blockIdx.y];
+  const int c = blockIdx.x;
+  if (c >= d.ld) return;
+  const int64_t col = d.off + (int64_t)c * d.ld;
+  for (int r = 2 * threadIdx.x; r < d.ld; r += 512) {
+    const double v0 = (r == c && r >= d.n) ? 1.0 : 0.0, v1 = (r + 1 == c && r + 1 >= d.n) ? 1.0 : 0.0;
+    if (A) *reinterpret_cast<double2*>(A + col + r) = double2{v0, v1};
+    if (Af) *reinterpret_cast<float2*>(Af + col + r) = float2{(float)v0, (float)v1};
   }
-  const MatDesc d = desc[lo];
-  int64_t loc = idx - mat_start[lo];
-  int64_t r = loc % d.ld, c = loc / d.ld;
-  double v = (r == c && r >= d.n) ? 1.0 : 0.0;
-  if (A) A[d.off + loc] = v;
-  if (Af) Af[d.off + loc] = (float)v;
+}
+static dim3 fill_grid(const std::vector<MatDesc>& d) {
+  int mx = 1;
+  for (const auto& x : d) mx = std::max(mx, x.ld);
+  return dim3((unsigned)mx, (unsigned)d.size());
 }
 
 // dense A_i from the global CSR values through the local CSR triplets
@@ -205,31 +209,54 @@ __global__ void k_zg_scatter(int64_t len, int nsub, const int64_t* __restrict__ 
   for (int q = 0; q < gcnt[lo]; ++q) Zg[(goff[lo] + q) * n + e] = W[woff[lo] + q * ld + r];
 }
 
-// Y = A X for ncol dense columns (column-major n x ncol), one thread per (row, column)
-__global__ void k_spmm_global(int64_t n, int64_t ncol, const int32_t* __restrict__ rp, const int32_t* __restrict__ ci,
-                              const double* __restrict__ v, const double* __restrict__ X, double* __restrict__ Y) {
-  int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  if (idx >= n * ncol) return;
-  const int64_t i = idx % n, c = idx / n;
-  const double* x = X + c * n;
-  double acc = 0.0;
-  for (int32_t k = rp[i]; k < rp[i + 1]; ++k) acc += v[k] * x[ci[k]];
-  Y[c * n + i] = acc;
+// Y = A Z_gen on the rows where it can be non-zero: one thread per ring row
+// of a subdomain, computing that row for the subdomain's GenEO columns
+// (Z_gen column-major n x ngen, zero outside the column's subdomain).
+__global__ void k_spmm_ring(int64_t nring, int nsub, const int32_t* __restrict__ ring_ptr,
+                            const int32_t* __restrict__ ring, const int32_t* __restrict__ gcnt,
+                            const int64_t* __restrict__ goff, const int32_t* __restrict__ rp,
+                            const int32_t* __restrict__ ci, const double* __restrict__ v, int64_t n,
+                            const double* __restrict__ Zg, double* __restrict__ Y) {
+  const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (t >= nring) return;
+  int lo = 0, hi = nsub - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (ring_ptr[mid] <= t) lo = mid; else hi = mid - 1;
+  }
+  const int32_t e = ring[t];
+  const int32_t k0 = rp[e], k1 = rp[e + 1];
+  for (int q = 0; q < gcnt[lo]; ++q) {
+    const int64_t g = goff[lo] + q;
+    const double* z = Zg + g * n;
+    double acc = 0.0;
+    for (int32_t k = k0; k < k1; ++k) acc += v[k] * z[ci[k]];
+    Y[g * n + e] = acc;
+  }
 }
 
 // Lower triangle of the GenEO columns of E = Z^T Y, Y = A Z_gen (global,
-// n x ngen, column-major).  One thread per (coarse row c1, GenEO column g):
-// SNK rows use their sparse column; GenEO rows the dense local block of
-// their subdomain (a GenEO column lives on one subdomain's edges only).
-__global__ void k_coarse_gen(int64_t n0, int64_t nsnk, int64_t ngen, int64_t n, const int32_t* __restrict__ zc_ptr,
+// n x ngen, column-major).  Grid row blockIdx.y = GenEO column g; the
+// threads run over the candidate rows c1 of g's subdomain (the columns of
+// subdomains whose dofs meet its ring; every other entry is zero).  SNK
+// rows use their sparse column; GenEO rows the dense local block of their
+// subdomain (a GenEO column lives on one subdomain's edges only).
+__global__ void k_coarse_gen(int64_t nsnk, int64_t n, const int32_t* __restrict__ zc_ptr,
                              const int32_t* __restrict__ zc_row, const double* __restrict__ zc_val, int nsub,
-                             const int64_t* __restrict__ goff, const int64_t* __restrict__ voff,
+                             const int64_t* __restrict__ goff, const int32_t* __restrict__ cand_ptr,
+                             const int32_t* __restrict__ cand, const int64_t* __restrict__ voff,
                              const int32_t* __restrict__ nloc, const int64_t* __restrict__ woff,
                              const int32_t* __restrict__ bmap, const double* __restrict__ W,
                              const double* __restrict__ Y, double* __restrict__ E, int64_t ld) {
-  int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  if (idx >= n0 * ngen) return;
-  const int64_t c1 = idx % n0, g = idx / n0;
+  const int64_t g = blockIdx.y;
+  int j = 0, hi = nsub - 1;   // subdomain of GenEO column g
+  while (j < hi) {
+    const int mid = (j + hi + 1) >> 1;
+    if (goff[mid] <= g) j = mid; else hi = mid - 1;
+  }
+  const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (t >= cand_ptr[j + 1] - cand_ptr[j]) return;
+  const int64_t c1 = cand[cand_ptr[j] + t];
   const int64_t cg = nsnk + g;
   const double* y = Y + g * n;
   if (c1 < nsnk) {
@@ -240,9 +267,10 @@ __global__ void k_coarse_gen(int64_t n0, int64_t nsnk, int64_t ngen, int64_t n, 
   }
   if (c1 < cg) return;              // upper triangle: not needed
   const int64_t g1 = c1 - nsnk;
-  int lo = 0, hi = nsub - 1;
+  int lo = 0;
+  hi = nsub - 1;
   while (lo < hi) {
-    int mid = (lo + hi + 1) >> 1;
+    const int mid = (lo + hi + 1) >> 1;
     if (goff[mid] <= g1) lo = mid; else hi = mid - 1;
   }
   const int64_t q = g1 - goff[lo];
@@ -253,6 +281,62 @@ __global__ void k_coarse_gen(int64_t n0, int64_t nsnk, int64_t ngen, int64_t n, 
   for (int64_t r = 0; r < nloc[lo]; ++r) acc += w[r] * y[bm[r]];
   E[cg * ld + c1] = acc;            // row c1 >= cg, column cg
 }
+
+// Host side of the support restriction (k_spmm_ring / k_coarse_gen).
+struct GenSupport {
+  std::vector<int32_t> ring, ring_ptr;   // per subdomain j: free edges coupled to dofs(j) through A
+  std::vector<int32_t> cand, cand_ptr;   // per subdomain j: coarse columns of subdomains meeting ring_j
+  int64_t max_cand = 0;
+};
+
+static GenSupport gen_support(const geneo_system* s, const geneo_decomp* dec, const std::vector<int32_t>& gen_cnt,
+                              const std::vector<int32_t>& col_sub, int64_t nsnk,
+                              const std::vector<int64_t>& gen_off) {
+  const int N = dec->N;
+  const int64_t n = s->n;
+  const int Wd = (N + 63) / 64;
+  GenSupport g;
+  // subdomains holding each free edge (bit masks)
+  std::vector<uint64_t> emask((size_t)n * Wd, 0);
+  for (int i = 0; i < N; ++i)
+    for (int64_t r = dec->dofs_ptr[i]; r < dec->dofs_ptr[i + 1]; ++r)
+      emask[(size_t)dec->dofs[r] * Wd + i / 64] |= 1ull << (i % 64);
+  std::vector<uint64_t> adj((size_t)N * Wd, 0);
+  std::vector<int32_t> stamp(n, -1);
+  g.ring_ptr.assign(N + 1, 0);
+  for (int j = 0; j < N; ++j) {
+    if (gen_cnt[j] > 0) {
+      for (int64_t r = dec->dofs_ptr[j]; r < dec->dofs_ptr[j + 1]; ++r) {
+        const int32_t e = dec->dofs[r];
+        for (int32_t k = s->rowptr[e]; k < s->rowptr[e + 1]; ++k) {
+          const int32_t f = s->colind[k];
+          if (stamp[f] == j) continue;
+          stamp[f] = j;
+          g.ring.push_back(f);
+          for (int w = 0; w < Wd; ++w) adj[(size_t)j * Wd + w] |= emask[(size_t)f * Wd + w];
+        }
+      }
+    }
+    g.ring_ptr[j + 1] = (int32_t)g.ring.size();
+  }
+  // coarse columns per subdomain: SNK ranges (subdomain-major), GenEO ranges
+  std::vector<int64_t> snk_beg(N + 1, 0);
+  for (int64_t c = 0; c < nsnk; ++c) snk_beg[col_sub[c] + 1]++;
+  for (int i = 0; i < N; ++i) snk_beg[i + 1] += snk_beg[i];
+  g.cand_ptr.assign(N + 1, 0);
+  for (int j = 0; j < N; ++j) {
+    if (gen_cnt[j] > 0)
+      for (int i = 0; i < N; ++i) {
+        if (!((adj[(size_t)j * Wd + i / 64] >> (i % 64)) & 1)) continue;
+        for (int64_t c = snk_beg[i]; c < snk_beg[i + 1]; ++c) g.cand.push_back((int32_t)c);
+        for (int64_t c = gen_off[i]; c < gen_off[i + 1]; ++c) g.cand.push_back((int32_t)(nsnk + c));
+      }
+    g.cand_ptr[j + 1] = (int32_t)g.cand.size();
+    g.max_cand = std::max<int64_t>(g.max_cand, g.cand_ptr[j + 1] - g.cand_ptr[j]);
+  }
+  return g;
+}
+
 
 // ---------------------------------------------------------- dot products
 constexpr int kDotBlocks = 512;
@@ -419,13 +503,9 @@ static void fp32_probe(geneo_ctx* ctx, geneo_precond* pc, const std::vector<MatD
   const MatDesc& last = descs.back();
   const int64_t total = last.off + (int64_t)last.ld * last.ld;
   const int64_t inv_total = last.inv_off + 2 * (int64_t)last.ld * NB;
-  std::vector<int64_t> mat_start(N);
-  for (int32_t i = 0; i < N; ++i) mat_start[i] = descs[i].off;
-  DevBuf<int64_t> d_mat_start;
-  d_mat_start.upload(mat_start, st);
   pc->dL.alloc(total);
   pc->dLinv.alloc(inv_total);
-  k_fill_identity_pad<<<nblocks(total), 256, 0, st>>>(pc->local.d_desc.p, N, pc->dL.p, nullptr, total, d_mat_start.p);
+  k_fill_identity_pad<<<fill_grid(descs), 256, 0, st>>>(pc->local.d_desc.p, pc->dL.p, nullptr);
   const int64_t nnz = pc->lnnz_off[N];
   if (nnz)
     k_dense_scatter<<<nblocks(nnz), 256, 0, st>>>(nnz, pc->d_lrow.p, pc->d_lcol.p, pc->d_lslot.p, pc->d_lnnz_off.p,
@@ -448,7 +528,7 @@ static void fp32_probe(geneo_ctx* ctx, geneo_precond* pc, const std::vector<MatD
 // (few) dependences that span several nodes.  Keeps the original column
 // order; rewrites the CSC arrays in place.
 static void snk_local_basis(int64_t n_nodes, std::vector<int32_t>& cp, std::vector<int32_t>& ri,
-                            std::vector<double>& va, const std::vector<int32_t>& node) {
+                            std::vector<double>& va, const std::vector<int32_t>& node, std::vector<int32_t>& sub) {
   const int64_t nc = (int64_t)cp.size() - 1;
   std::vector<int64_t> gp(n_nodes + 1, 0);
   for (int64_t c = 0; c < nc; ++c) gp[node[c] + 1]++;
@@ -497,10 +577,11 @@ static void snk_local_basis(int64_t n_nodes, std::vector<int32_t>& cp, std::vect
       keep[c] = 1;
     }
   }
-  std::vector<int32_t> cp2(1, 0), ri2;
+  std::vector<int32_t> cp2(1, 0), ri2, sub2;
   std::vector<double> va2;
   for (int64_t c = 0; c < nc; ++c) {
     if (!keep[c]) continue;
+    sub2.push_back(sub[c]);
     for (int32_t k = cp[c]; k < cp[c + 1]; ++k) {
       ri2.push_back(ri[k]);
       va2.push_back(va[k]);
@@ -510,6 +591,7 @@ static void snk_local_basis(int64_t n_nodes, std::vector<int32_t>& cp, std::vect
   cp.swap(cp2);
   ri.swap(ri2);
   va.swap(va2);
+  sub.swap(sub2);
 }
 
 void setup_precond(geneo_ctx* ctx, geneo_precond* pc) {
@@ -613,10 +695,6 @@ void setup_precond(geneo_ctx* ctx, geneo_precond* pc) {
 
   // ---- extraction + factorisation
   const bool fp32 = pc->precision == GENEO_FP32_REFINE1;
-  std::vector<int64_t> mat_start(N);
-  for (int32_t i = 0; i < N; ++i) mat_start[i] = descs[i].off;
-  DevBuf<int64_t> d_mat_start;
-  d_mat_start.upload(mat_start, st);
   if (fp32) {
     pc->fL.alloc(off);
     pc->fLinv.alloc(inv_off);
@@ -625,8 +703,8 @@ void setup_precond(geneo_ctx* ctx, geneo_precond* pc) {
     pc->dLinv.alloc(inv_off);
   }
   HIP_CHECK(hipEventRecord(ctx->ev[0], st));
-  k_fill_identity_pad<<<nblocks(off), 256, 0, st>>>(pc->local.d_desc.p, N, fp32 ? nullptr : pc->dL.p,
-                                                    fp32 ? pc->fL.p : nullptr, off, d_mat_start.p);
+  k_fill_identity_pad<<<fill_grid(pc->local.h_desc), 256, 0, st>>>(pc->local.d_desc.p, fp32 ? nullptr : pc->dL.p,
+                                                                   fp32 ? pc->fL.p : nullptr);
   if (!lrow.empty())
     k_dense_scatter<<<nblocks((int64_t)lrow.size()), 256, 0, st>>>((int64_t)lrow.size(), pc->d_lrow.p, pc->d_lcol.p,
                                                                    pc->d_lslot.p, pc->d_lnnz_off.p, N,
@@ -677,7 +755,7 @@ void setup_precond(geneo_ctx* ctx, geneo_precond* pc) {
   }
 
   // ---- coarse space: SNK columns R_i^T D_i G_i (one per kept local free node)
-  std::vector<int32_t> zc_ptr(1, 0), zc_row, col_node;
+  std::vector<int32_t> zc_ptr(1, 0), zc_row, col_node, col_sub;
   std::vector<double> zc_val;
   {
     std::vector<int32_t> gl(s->n_free_nodes, -1);
@@ -706,6 +784,7 @@ void setup_precond(geneo_ctx* ctx, geneo_precond* pc) {
         }
         zc_ptr.push_back((int32_t)zc_row.size());
         col_node.push_back(dec->gnodes[gb + k]);
+        col_sub.push_back(i);
       }
       for (int64_t k = gb; k < ge; ++k) gl[dec->gnodes[k]] = -1;
     }
@@ -715,7 +794,7 @@ void setup_precond(geneo_ctx* ctx, geneo_precond* pc) {
     const char* e = std::getenv("GENEO_SNK_LOCAL");
     return !(e && std::string(e) == "0");
   }();
-  if (local_basis) snk_local_basis(s->n_free_nodes, zc_ptr, zc_row, zc_val, col_node);
+  if (local_basis) snk_local_basis(s->n_free_nodes, zc_ptr, zc_row, zc_val, col_node, col_sub);
   pc->n_snk = (int32_t)(zc_ptr.size() - 1);
   pc->info.n0_local_dropped = pc->n_snk_all - pc->n_snk;
   pc->n_gen = 0;
@@ -758,12 +837,8 @@ void setup_precond(geneo_ctx* ctx, geneo_precond* pc) {
   pc->w_c2.alloc(n0p);
   HIP_CHECK(hipMemsetAsync(pc->w_c1.p, 0, sizeof(double) * n0p, st));
   HIP_CHECK(hipMemsetAsync(pc->w_c2.p, 0, sizeof(double) * n0p, st));
-  std::vector<int64_t> zero1(1, 0);
-  DevBuf<int64_t> d_zero1;
-  d_zero1.upload(zero1, st);
   HIP_CHECK(hipEventRecord(ctx->ev[0], st));
-  k_fill_identity_pad<<<nblocks(n0p * n0p), 256, 0, st>>>(pc->coarse.d_desc.p, 1, pc->dE.p, nullptr, n0p * n0p,
-                                                          d_zero1.p);
+  k_fill_identity_pad<<<fill_grid(cd), 256, 0, st>>>(pc->coarse.d_desc.p, pc->dE.p, nullptr);
   if (pc->n_snk)
     k_coarse_snk<<<nblocks(pc->n_snk), 256, 0, st>>>(pc->n_snk, pc->d_zc_ptr.p, pc->d_zc_row.p, pc->d_zc_val.p,
                                                       s->d_rowptr.p, s->d_colind.p, s->d_val.p, pc->d_zr_ptr.p,
@@ -776,12 +851,24 @@ void setup_precond(geneo_ctx* ctx, geneo_precond* pc) {
     HIP_CHECK(hipMemsetAsync(Zg.p, 0, sizeof(double) * n * pc->n_gen, st));
     k_zg_scatter<<<nblocks(voff), 256, 0, st>>>(voff, N, pc->d_voff.p, pc->d_n.p, pc->d_gen_cnt.p, pc->d_gen_off.p,
                                                 pc->d_w_off.p, pc->d_bmap.p, pc->d_W.p, n, Zg.p);
-    k_spmm_global<<<nblocks(n * pc->n_gen), 256, 0, st>>>(n, pc->n_gen, s->d_rowptr.p, s->d_colind.p, s->d_val.p,
-                                                          Zg.p, Y.p);
-    k_coarse_gen<<<nblocks(n0 * pc->n_gen), 256, 0, st>>>(n0, pc->n_snk, pc->n_gen, n, pc->d_zc_ptr.p,
-                                                          pc->d_zc_row.p, pc->d_zc_val.p, N, pc->d_gen_off.p,
-                                                          pc->d_voff.p, pc->d_n.p, pc->d_w_off.p, pc->d_bmap.p,
-                                                          pc->d_W.p, Y.p, pc->dE.p, n0p);
+    // supports: a GenEO column of subdomain j lives on its dofs, so A Z_gen
+    // is non-zero only on ring_j (the dofs coupled to them through A) and
+    // E(c1, g) only for columns c1 of subdomains i whose dofs meet ring_j
+    const GenSupport sup = gen_support(s, dec, pc->gen_cnt, col_sub, pc->n_snk, pc->gen_off);
+    DevBuf<int32_t> d_ring, d_ring_ptr, d_cand, d_cand_ptr;
+    d_ring.upload(sup.ring, st);
+    d_ring_ptr.upload(sup.ring_ptr, st);
+    d_cand.upload(sup.cand, st);
+    d_cand_ptr.upload(sup.cand_ptr, st);
+    HIP_CHECK(hipMemsetAsync(Y.p, 0, sizeof(double) * n * pc->n_gen, st));
+    if (!sup.ring.empty())
+      k_spmm_ring<<<nblocks((int64_t)sup.ring.size()), 256, 0, st>>>(
+          (int64_t)sup.ring.size(), N, d_ring_ptr.p, d_ring.p, pc->d_gen_cnt.p, pc->d_gen_off.p, s->d_rowptr.p,
+          s->d_colind.p, s->d_val.p, n, Zg.p, Y.p);
+    if (sup.max_cand > 0)
+      k_coarse_gen<<<dim3((unsigned)((sup.max_cand + 255) / 256), (unsigned)pc->n_gen), 256, 0, st>>>(
+          pc->n_snk, n, pc->d_zc_ptr.p, pc->d_zc_row.p, pc->d_zc_val.p, N, pc->d_gen_off.p, d_cand_ptr.p, d_cand.p,
+          pc->d_voff.p, pc->d_n.p, pc->d_w_off.p, pc->d_bmap.p, pc->d_W.p, Y.p, pc->dE.p, n0p);
     HIP_CHECK(hipStreamSynchronize(st));
   }
   HIP_CHECK(hipGetLastError());
