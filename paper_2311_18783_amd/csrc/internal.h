@@ -3,10 +3,13 @@
 
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+#include <atomic>
 #include <cstdint>
 #include <cstdio>
 #include <stdexcept>
 #include <string>
+#include <thread>
 #include <vector>
 
 #include "../../include/geneo.h"
@@ -15,6 +18,26 @@ namespace geneo {
 
 // Panel / tile width of the dense factorisations and triangular solves.
 constexpr int NB = 128;
+
+// Host loop f(i), i in [0, n), on up to 16 threads (indices handed out
+// dynamically); f may only write data owned by its index and must not throw.
+template <class F>
+void parallel_for(int n, F&& f) {
+  const int hw = (int)std::max(1u, std::thread::hardware_concurrency());
+  const int nt = std::max(1, std::min({n, 16, hw}));
+  if (nt <= 1) {
+    for (int i = 0; i < n; ++i) f(i);
+    return;
+  }
+  std::atomic<int> next{0};
+  auto worker = [&] {
+    for (int i; (i = next.fetch_add(1)) < n;) f(i);
+  };
+  std::vector<std::thread> th;
+  for (int t = 1; t < nt; ++t) th.emplace_back(worker);
+  worker();
+  for (auto& t : th) t.join();
+}
 
 struct Error : std::runtime_error {
   int code;

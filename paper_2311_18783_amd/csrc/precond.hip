@@ -9,7 +9,9 @@
 #include <algorithm>
 #include <cstdlib>
 #include <cmath>
+#include <exception>
 #include <numeric>
+#include <thread>
 #include <string>
 
 #include "precond.h"
@@ -594,6 +596,74 @@ static void snk_local_basis(int64_t n_nodes, std::vector<int32_t>& cp, std::vect
   sub.swap(sub2);
 }
 
+// Host part of the SNK coarse columns R_i^T D_i G_i: sparse columns (one
+// per kept local free node, subdomain-major), exactly dependent ones dropped
+// within their node's group, and the row-wise transpose.
+struct SnkHost {
+  std::vector<int32_t> zc_ptr{0}, zc_row, col_node, col_sub, zr_ptr, zr_col;
+  std::vector<double> zc_val, zr_val;
+  int32_t n_all = 0;
+};
+
+static void build_snk_host(const geneo_system* s, const geneo_decomp* dec, SnkHost& h) {
+  const int32_t N = dec->N;
+  const int64_t n = s->n;
+  std::vector<int32_t>& zc_ptr = h.zc_ptr;
+  std::vector<int32_t>& zc_row = h.zc_row;
+  std::vector<double>& zc_val = h.zc_val;
+  {
+    std::vector<int32_t> gl(s->n_free_nodes, -1);
+    for (int32_t i = 0; i < N; ++i) {
+      const int64_t gb = dec->gn_ptr[i], ge = dec->gn_ptr[i + 1];
+      const int32_t base = (int32_t)(zc_ptr.size() - 1);
+      for (int64_t k = gb; k < ge; ++k) gl[dec->gnodes[k]] = base + (int32_t)(k - gb);
+      const int64_t nk = ge - gb;
+      std::vector<std::vector<std::pair<int32_t, double>>> cols(nk);
+      for (int64_t r = dec->dofs_ptr[i]; r < dec->dofs_ptr[i + 1]; ++r) {
+        const int32_t fe = dec->dofs[r];
+        const int32_t e = s->free_edges[fe];
+        for (int q = 0; q < 2; ++q) {
+          const int32_t fnode = s->node_to_free[s->edges[2 * (int64_t)e + q]];
+          if (fnode < 0) continue;
+          const int32_t c = gl[fnode];
+          if (c < 0) continue;
+          const double g = q == 0 ? -1.0 : 1.0;
+          cols[c - base].push_back({fe, dec->pou[r] * g});
+        }
+      }
+      for (int64_t k = 0; k < nk; ++k) {
+        for (auto& pr : cols[k]) {
+          zc_row.push_back(pr.first);
+          zc_val.push_back(pr.second);
+        }
+        zc_ptr.push_back((int32_t)zc_row.size());
+        h.col_node.push_back(dec->gnodes[gb + k]);
+        h.col_sub.push_back(i);
+      }
+      for (int64_t k = gb; k < ge; ++k) gl[dec->gnodes[k]] = -1;
+    }
+  }
+  h.n_all = (int32_t)(zc_ptr.size() - 1);
+  static const bool local_basis = [] {
+    const char* e = std::getenv("GENEO_SNK_LOCAL");
+    return !(e && std::string(e) == "0");
+  }();
+  if (local_basis) snk_local_basis(s->n_free_nodes, zc_ptr, zc_row, zc_val, h.col_node, h.col_sub);
+  const int32_t nsnk = (int32_t)(zc_ptr.size() - 1);
+  // SNK rows (transpose of the columns)
+  h.zr_ptr.assign(n + 1, 0);
+  h.zr_col.resize(zc_row.size());
+  h.zr_val.resize(zc_row.size());
+  for (auto e : zc_row) h.zr_ptr[e + 1]++;
+  for (int64_t e = 0; e < n; ++e) h.zr_ptr[e + 1] += h.zr_ptr[e];
+  std::vector<int32_t> f(h.zr_ptr.begin(), h.zr_ptr.end() - 1);
+  for (int32_t c = 0; c < nsnk; ++c)
+    for (int32_t k = zc_ptr[c]; k < zc_ptr[c + 1]; ++k) {
+      h.zr_col[f[zc_row[k]]] = c;
+      h.zr_val[f[zc_row[k]]++] = zc_val[k];
+    }
+}
+
 void setup_precond(geneo_ctx* ctx, geneo_precond* pc) {
   hipStream_t st = ctx->stream;
   const geneo_system* s = pc->sys;
@@ -653,36 +723,46 @@ void setup_precond(geneo_ctx* ctx, geneo_precond* pc) {
   pc->d_inv_ptr.upload(cnt, st);
   pc->d_inv_idx.upload(inv, st);
 
-  // local CSR triplets: rows/cols local, slot = global CSR position
-  std::vector<int32_t> lrow, lcol, lslot;
+  // local CSR triplets: rows/cols local, slot = global CSR position (one
+  // pass counts, one fills; subdomains in parallel)
   std::vector<int64_t> lnnz_off(N + 1, 0);
-  std::vector<int32_t> g2l(n, -1);
-  for (int32_t i = 0; i < N; ++i) {
+  auto local_triplets = [&](int32_t i, int32_t* lr, int32_t* lc, int32_t* ls) {
+    std::vector<int32_t> g2l(n, -1);
     const int64_t b = dec->dofs_ptr[i], e = dec->dofs_ptr[i + 1];
     for (int64_t r = b; r < e; ++r) g2l[dec->dofs[r]] = (int32_t)(r - b);
+    int64_t cnt = 0;
     for (int64_t r = b; r < e; ++r) {
       const int32_t ge = dec->dofs[r];
       for (int32_t sl = s->rowptr[ge]; sl < s->rowptr[ge + 1]; ++sl) {
         const int32_t c = g2l[s->colind[sl]];
         if (c < 0) continue;
-        lrow.push_back((int32_t)(r - b));
-        lcol.push_back(c);
-        lslot.push_back(sl);
+        if (lr) {
+          lr[cnt] = (int32_t)(r - b);
+          lc[cnt] = c;
+          ls[cnt] = sl;
+        }
+        ++cnt;
       }
     }
-    for (int64_t r = b; r < e; ++r) g2l[dec->dofs[r]] = -1;
-    lnnz_off[i + 1] = (int64_t)lrow.size();
-  }
+    return cnt;
+  };
+  parallel_for(N, [&](int i) { lnnz_off[i + 1] = local_triplets(i, nullptr, nullptr, nullptr); });
+  for (int32_t i = 0; i < N; ++i) lnnz_off[i + 1] += lnnz_off[i];
+  std::vector<int32_t> lrow(lnnz_off[N]), lcol(lnnz_off[N]), lslot(lnnz_off[N]);
+  parallel_for(N, [&](int i) {
+    local_triplets(i, lrow.data() + lnnz_off[i], lcol.data() + lnnz_off[i], lslot.data() + lnnz_off[i]);
+  });
   pc->lnnz_off = lnnz_off;
   {
     // the triplets come row by row: batch-row pointers, batch columns
     std::vector<int64_t> brp(voff + 1, 0);
     std::vector<int32_t> bcol(lrow.size());
-    for (int32_t i = 0; i < N; ++i)
+    parallel_for(N, [&](int i) {
       for (int64_t t = lnnz_off[i]; t < lnnz_off[i + 1]; ++t) {
         brp[pc->voff[i] + lrow[t] + 1]++;
         bcol[t] = (int32_t)(pc->voff[i] + lcol[t]);
       }
+    });
     for (int64_t r = 0; r < voff; ++r) brp[r + 1] += brp[r];
     pc->d_brp.upload(brp, st);
     pc->d_bcol.upload(bcol, st);
@@ -692,6 +772,25 @@ void setup_precond(geneo_ctx* ctx, geneo_precond* pc) {
   pc->d_lcol.upload(lcol, st);
   pc->d_lslot.upload(lslot, st);
   pc->d_lnnz_off.upload(lnnz_off, st);
+
+  // the SNK columns depend on the mesh and the decomposition only
+  SnkHost snk;
+  std::exception_ptr snk_err;
+  std::thread snk_thread;
+  if (pc->opts.coarse != GENEO_COARSE_NONE)
+    snk_thread = std::thread([&] {
+      try {
+        build_snk_host(s, dec, snk);
+      } catch (...) {
+        snk_err = std::current_exception();
+      }
+    });
+  struct Joiner {   // joined on every exit path (errors included)
+    std::thread& t;
+    ~Joiner() {
+      if (t.joinable()) t.join();
+    }
+  } snk_join{snk_thread};
 
   // ---- extraction + factorisation
   const bool fp32 = pc->precision == GENEO_FP32_REFINE1;
@@ -754,47 +853,18 @@ void setup_precond(geneo_ctx* ctx, geneo_precond* pc) {
     return;
   }
 
-  // ---- coarse space: SNK columns R_i^T D_i G_i (one per kept local free node)
-  std::vector<int32_t> zc_ptr(1, 0), zc_row, col_node, col_sub;
-  std::vector<double> zc_val;
-  {
-    std::vector<int32_t> gl(s->n_free_nodes, -1);
-    for (int32_t i = 0; i < N; ++i) {
-      const int64_t gb = dec->gn_ptr[i], ge = dec->gn_ptr[i + 1];
-      const int32_t base = (int32_t)(zc_ptr.size() - 1);
-      for (int64_t k = gb; k < ge; ++k) gl[dec->gnodes[k]] = base + (int32_t)(k - gb);
-      const int64_t nk = ge - gb;
-      std::vector<std::vector<std::pair<int32_t, double>>> cols(nk);
-      for (int64_t r = dec->dofs_ptr[i]; r < dec->dofs_ptr[i + 1]; ++r) {
-        const int32_t fe = dec->dofs[r];
-        const int32_t e = s->free_edges[fe];
-        for (int q = 0; q < 2; ++q) {
-          const int32_t fnode = s->node_to_free[s->edges[2 * (int64_t)e + q]];
-          if (fnode < 0) continue;
-          const int32_t c = gl[fnode];
-          if (c < 0) continue;
-          const double g = q == 0 ? -1.0 : 1.0;
-          cols[c - base].push_back({fe, dec->pou[r] * g});
-        }
-      }
-      for (int64_t k = 0; k < nk; ++k) {
-        for (auto& pr : cols[k]) {
-          zc_row.push_back(pr.first);
-          zc_val.push_back(pr.second);
-        }
-        zc_ptr.push_back((int32_t)zc_row.size());
-        col_node.push_back(dec->gnodes[gb + k]);
-        col_sub.push_back(i);
-      }
-      for (int64_t k = gb; k < ge; ++k) gl[dec->gnodes[k]] = -1;
-    }
-  }
-  pc->n_snk_all = (int32_t)(zc_ptr.size() - 1);
-  static const bool local_basis = [] {
-    const char* e = std::getenv("GENEO_SNK_LOCAL");
-    return !(e && std::string(e) == "0");
-  }();
-  if (local_basis) snk_local_basis(s->n_free_nodes, zc_ptr, zc_row, zc_val, col_node, col_sub);
+  // ---- coarse space: SNK columns R_i^T D_i G_i (one per kept local free node),
+  // built on a host thread while the device ran the factorisations and GEVPs
+  snk_thread.join();
+  if (snk_err) std::rethrow_exception(snk_err);
+  std::vector<int32_t>& zc_ptr = snk.zc_ptr;
+  std::vector<int32_t>& zc_row = snk.zc_row;
+  std::vector<double>& zc_val = snk.zc_val;
+  std::vector<int32_t>& col_sub = snk.col_sub;
+  std::vector<int32_t>& zr_ptr = snk.zr_ptr;
+  std::vector<int32_t>& zr_col = snk.zr_col;
+  std::vector<double>& zr_val = snk.zr_val;
+  pc->n_snk_all = snk.n_all;
   pc->n_snk = (int32_t)(zc_ptr.size() - 1);
   pc->info.n0_local_dropped = pc->n_snk_all - pc->n_snk;
   pc->n_gen = 0;
@@ -804,19 +874,6 @@ void setup_precond(geneo_ctx* ctx, geneo_precond* pc) {
   }
   pc->gen_off[N] = pc->n_gen;
   pc->n0 = pc->n_snk + pc->n_gen;
-  // SNK rows (transpose of the columns)
-  std::vector<int32_t> zr_ptr(n + 1, 0), zr_col(zc_row.size());
-  std::vector<double> zr_val(zc_row.size());
-  for (auto e : zc_row) zr_ptr[e + 1]++;
-  for (int64_t e = 0; e < n; ++e) zr_ptr[e + 1] += zr_ptr[e];
-  {
-    std::vector<int32_t> f(zr_ptr.begin(), zr_ptr.end() - 1);
-    for (int32_t c = 0; c < pc->n_snk; ++c)
-      for (int32_t k = zc_ptr[c]; k < zc_ptr[c + 1]; ++k) {
-        zr_col[f[zc_row[k]]] = c;
-        zr_val[f[zc_row[k]]++] = zc_val[k];
-      }
-  }
   pc->d_zc_ptr.upload(zc_ptr, st);
   pc->d_zc_row.upload(zc_row, st);
   pc->d_zc_val.upload(zc_val, st);
