@@ -51,6 +51,18 @@ struct FactorPlan {
   int64_t n_lower = 0;                   // strictly lower tiles in the pattern
   DevBuf<int32_t> d_lower_pairs;
   DevBuf<int32_t> d_dep_fwd_ptr, d_dep_fwd, d_dep_bwd_ptr, d_dep_bwd;
+  // Split rows of the single-RHS solves (per direction, 0 forward, 1
+  // backward): a row with many dependencies hands the leading chunks of its
+  // list to helper work items that post partial sums Q(I, J) x_J, and keeps
+  // the last ones itself.  Work items (m, I) in ticket order, a helper h
+  // encoded as (-1 - h, I) right before its row.
+  int64_t n_sitems[2] = {0, 0};
+  int32_t n_help[2] = {0, 0};
+  DevBuf<int32_t> d_sitems[2];
+  DevBuf<int32_t> d_help_rng[2];     // helper h: dependency index range [lo, hi) of its row
+  DevBuf<int32_t> d_row_lo[2];       // row I: first dependency index it handles itself
+  DevBuf<int32_t> d_row_help[2];     // row I: its helpers [beg, end) (pairs)
+  DevBuf<double> d_part;             // partial sums, 128 per helper
   int64_t fill_tiles = 0;                // lower tiles (with diagonal) in the pattern
   double sparse_flops = 0;               // factorisation flops on the pattern
   void build_sparse(const MatDesc& d, const std::vector<uint8_t>& fill, hipStream_t st);

@@ -907,6 +907,41 @@ void FactorPlan::build_sparse(const MatDesc& dsc, const std::vector<uint8_t>& F,
   d_dep_fwd.upload(fd.empty() ? std::vector<int32_t>(1, 0) : fd, st);
   d_dep_bwd_ptr.upload(bp, st);
   d_dep_bwd.upload(bd.empty() ? std::vector<int32_t>(1, 0) : bd, st);
+  // split rows: more than kSplitMin dependencies -> helpers of kSplitChunk
+  // dependencies each over all but the row's last kSplitKeep
+  constexpr int kSplitMin = 48, kSplitChunk = 32, kSplitKeep = 16;
+  int32_t max_help = 0;
+  for (int d = 0; d < 2; ++d) {
+    const std::vector<int32_t>& ptr = d == 0 ? fp : bp;
+    std::vector<int32_t> items, rng, rlo(nb, 0), rhelp(2 * (size_t)nb, 0);
+    int32_t nh = 0;
+    for (int k = 0; k < nb; ++k) {
+      const int I = d == 0 ? k : nb - 1 - k;
+      const int nd = ptr[I + 1] - ptr[I];
+      rhelp[2 * I] = nh;
+      if (nd > kSplitMin) {
+        for (int c = 0; c < nd - kSplitKeep; c += kSplitChunk) {
+          items.push_back(-1 - nh);
+          items.push_back(I);
+          rng.push_back(c);
+          rng.push_back(std::min(c + kSplitChunk, nd - kSplitKeep));
+          ++nh;
+        }
+        rlo[I] = nd - kSplitKeep;
+      }
+      rhelp[2 * I + 1] = nh;
+      items.push_back(0);
+      items.push_back(I);
+    }
+    n_sitems[d] = (int64_t)items.size() / 2;
+    n_help[d] = nh;
+    max_help = std::max(max_help, nh);
+    d_sitems[d].upload(items, st);
+    d_help_rng[d].upload(rng.empty() ? std::vector<int32_t>(2, 0) : rng, st);
+    d_row_lo[d].upload(rlo, st);
+    d_row_help[d].upload(rhelp, st);
+  }
+  d_part.alloc(std::max<int64_t>((int64_t)max_help * NB, 1));
   for (int s = 0; s < nb; ++s)
     sparse_flops += (double)NB * NB * NB / 3.0 + (double)trsm_tiles[s] * NB * NB * NB;
 }
@@ -1201,13 +1236,19 @@ __global__ void k_pending(const MatDesc* __restrict__ desc, const int32_t* __res
 // c_I first; the blocks Q(I,J) are streamed one dependency ahead through
 // two register buffers, so the block of a dependency is already in
 // registers when its values land.
+// Split rows (block-sparse plans, help_rng != nullptr): a helper item
+// accumulates its dependency range and stores the partial sum to part; the
+// row itself starts at row_lo[I] and adds its helpers' partials at the end.
 template <typename T, bool UPPER>
 __global__ __launch_bounds__(kTrsvThreads) void k_trsv(const MatDesc* __restrict__ desc,
                                                        const int32_t* __restrict__ items, const T* __restrict__ A,
                                                        const T* __restrict__ Ainv, const double* __restrict__ xin,
                                                        double* xout, unsigned* sync, DevErr* err,
                                                        const int32_t* __restrict__ dep_ptr,
-                                                       const int32_t* __restrict__ dep) {
+                                                       const int32_t* __restrict__ dep,
+                                                       const int32_t* __restrict__ help_rng,
+                                                       const int32_t* __restrict__ row_lo,
+                                                       const int32_t* __restrict__ row_help, double* part) {
   constexpr int H = kTrsvThreads / NB;   // column groups
   constexpr int CW = NB / H;             // columns per group
   __shared__ double xs[NB];
@@ -1216,8 +1257,10 @@ __global__ __launch_bounds__(kTrsvThreads) void k_trsv(const MatDesc* __restrict
   const int tid = threadIdx.x;
   if (tid == 0) s_t = (int)atomicAdd(&sync[0], 1u);
   __syncthreads();
-  const int m = items[2 * s_t], I = items[2 * s_t + 1];
-  const MatDesc d = desc[m];
+  const int mi = items[2 * s_t], I = items[2 * s_t + 1];
+  const bool helper = mi < 0;
+  const int hid = -1 - mi;
+  const MatDesc d = desc[helper ? 0 : mi];
   const double* xi = xin + d.voff;
   double* xo = xout + d.voff;
   const int r = tid & (NB - 1), h = tid >> 7;
@@ -1232,15 +1275,26 @@ __global__ __launch_bounds__(kTrsvThreads) void k_trsv(const MatDesc* __restrict
 #pragma unroll
     for (int c = 0; c < CW; ++c) q[c] = col[(int64_t)c * d.ld];
   };
+  int e0 = 0, e1 = nd;
+  if (help_rng) {
+    if (helper) {
+      e0 = help_rng[2 * hid];
+      e1 = help_rng[2 * hid + 1];
+    } else {
+      e0 = row_lo[I];
+    }
+  }
   T qa[CW], qb[CW];
-  if (nd > 0) load_block(qa, dep_at(0));
-  // c_I = inv(D_II) b_I
-  if (tid < NB) xs[tid] = xi[(int64_t)I * NB + tid];
-  __syncthreads();
-  const T* inv = Ainv + d.inv_off + ((UPPER ? d.nblk : 0) + (int64_t)I) * NB * NB;
+  if (e1 > e0) load_block(qa, dep_at(e0));
   double acc = 0.0;
+  if (!helper) {
+    // c_I = inv(D_II) b_I
+    if (tid < NB) xs[tid] = xi[(int64_t)I * NB + tid];
+    __syncthreads();
+    const T* inv = Ainv + d.inv_off + ((UPPER ? d.nblk : 0) + (int64_t)I) * NB * NB;
 #pragma unroll 8
-  for (int c = 0; c < CW; ++c) acc -= (double)inv[(int64_t)(CW * h + c) * NB + r] * xs[CW * h + c];
+    for (int c = 0; c < CW; ++c) acc -= (double)inv[(int64_t)(CW * h + c) * NB + r] * xs[CW * h + c];
+  }
   auto consume = [&](const T* q, int J) {
     __syncthreads();   // the previous values in xs are consumed
     if (tid < NB) xs[tid] = poll_value(xo + (int64_t)J * NB + tid, err);
@@ -1248,11 +1302,11 @@ __global__ __launch_bounds__(kTrsvThreads) void k_trsv(const MatDesc* __restrict
 #pragma unroll
     for (int c = 0; c < CW; ++c) acc += (double)q[c] * xs[CW * h + c];
   };
-  for (int e = 0; e < nd; e += 2) {
-    if (e + 1 < nd) load_block(qb, dep_at(e + 1));
+  for (int e = e0; e < e1; e += 2) {
+    if (e + 1 < e1) load_block(qb, dep_at(e + 1));
     consume(qa, dep_at(e));
-    if (e + 1 < nd) {
-      if (e + 2 < nd) load_block(qa, dep_at(e + 2));
+    if (e + 1 < e1) {
+      if (e + 2 < e1) load_block(qa, dep_at(e + 2));
       consume(qb, dep_at(e + 1));
     }
   }
@@ -1262,8 +1316,20 @@ __global__ __launch_bounds__(kTrsvThreads) void k_trsv(const MatDesc* __restrict
     double v = 0.0;
 #pragma unroll
     for (int g = 0; g < H; ++g) v += red[g * NB + tid];
-    store_coherent(xo + (int64_t)I * NB + tid, -v);
+    if (helper) {
+      store_coherent(part + (int64_t)hid * NB + tid, v);
+    } else {
+      if (help_rng)
+        for (int hh = row_help[2 * I]; hh < row_help[2 * I + 1]; ++hh)
+          v += poll_value(part + (int64_t)hh * NB + tid, err);
+      store_coherent(xo + (int64_t)I * NB + tid, -v);
+    }
   }
+}
+
+// marks n slots of 128 values pending
+__global__ void k_pending_slots(double* p) {
+  p[(int64_t)blockIdx.x * NB + threadIdx.x] = __builtin_bit_cast(double, kPending);
 }
 
 // Many right-hand sides (k <= KC columns): X <- L^-1 X or U^-1 X, X in block
@@ -1433,16 +1499,27 @@ static void solve_impl(const FactorPlan& P, const T* A, const T* Ainv, double* x
   if (P.n_items == 0) return;
   double* y = P.d_y.p;   // forward result, backward input
   const unsigned ni = (unsigned)P.n_items;
-  k_pending<<<ni, NB, 0, st>>>(P.d_desc.p, P.d_items_fwd.p, y);
-  k_solve_begin<<<1, 1, 0, st>>>(sync);
-  k_trsv<T, false><<<ni, dim3(kTrsvThreads), 0, st>>>(P.d_desc.p, P.d_items_fwd.p, A, Ainv, x, y, sync, err,
-                                                       P.sparse ? P.d_dep_fwd_ptr.p : nullptr,
-                                                       P.sparse ? P.d_dep_fwd.p : nullptr);
-  k_pending<<<ni, NB, 0, st>>>(P.d_desc.p, P.d_items_fwd.p, x);
-  k_solve_begin<<<1, 1, 0, st>>>(sync);
-  k_trsv<T, true><<<ni, dim3(kTrsvThreads), 0, st>>>(P.d_desc.p, P.d_items_bwd.p, A, Ainv, y, x, sync, err,
-                                                      P.sparse ? P.d_dep_bwd_ptr.p : nullptr,
-                                                      P.sparse ? P.d_dep_bwd.p : nullptr);
+  for (int dir = 0; dir < 2; ++dir) {
+    const bool split = P.sparse;
+    const int32_t* items = split ? P.d_sitems[dir].p : (dir == 0 ? P.d_items_fwd.p : P.d_items_bwd.p);
+    const unsigned nw = split ? (unsigned)P.n_sitems[dir] : ni;
+    const int32_t* dptr = P.sparse ? (dir == 0 ? P.d_dep_fwd_ptr.p : P.d_dep_bwd_ptr.p) : nullptr;
+    const int32_t* dl = P.sparse ? (dir == 0 ? P.d_dep_fwd.p : P.d_dep_bwd.p) : nullptr;
+    const int32_t* hr = split ? P.d_help_rng[dir].p : nullptr;
+    const int32_t* rlo = split ? P.d_row_lo[dir].p : nullptr;
+    const int32_t* rh = split ? P.d_row_help[dir].p : nullptr;
+    double* xin = dir == 0 ? x : y;
+    double* xout = dir == 0 ? y : x;
+    k_pending<<<ni, NB, 0, st>>>(P.d_desc.p, P.d_items_fwd.p, xout);
+    if (split && P.n_help[dir] > 0) k_pending_slots<<<(unsigned)P.n_help[dir], NB, 0, st>>>(P.d_part.p);
+    k_solve_begin<<<1, 1, 0, st>>>(sync);
+    if (dir == 0)
+      k_trsv<T, false><<<nw, dim3(kTrsvThreads), 0, st>>>(P.d_desc.p, items, A, Ainv, xin, xout, sync, err, dptr, dl,
+                                                           hr, rlo, rh, P.d_part.p);
+    else
+      k_trsv<T, true><<<nw, dim3(kTrsvThreads), 0, st>>>(P.d_desc.p, items, A, Ainv, xin, xout, sync, err, dptr, dl,
+                                                          hr, rlo, rh, P.d_part.p);
+  }
   HIP_CHECK(hipGetLastError());
 }
 
