@@ -29,6 +29,11 @@ struct FactorPlan {
   int64_t n_items = 0;               // triangular-solve work items (blocks)
   int64_t mirror_tiles = 0;          // strictly-lower 128x128 blocks
   int group = 8;                     // panels per trailing update
+  // solve form (off-diagonal blocks premultiplied by their row's diagonal
+  // inverse, shorter dependency chain; the coarse factor) or plain form
+  // (x_I = inv(D_II) (b_I - sum L(I,J) x_J); the batched local factors,
+  // whose solves are bandwidth bound)
+  bool solve_form = true;
   std::vector<SyrkLaunch> syrk;      // trailing-update launches in execution order
   DevBuf<int64_t> d_syrk_prefix;
   DevBuf<int64_t> d_mirror_prefix;

@@ -1034,14 +1034,14 @@ void factor(const FactorPlan& P, double* A, double* Ainv, const double* odiag, d
   factor_impl<double>(P, A, Ainv, odiag, drop_tol, pivrel, err, st, failed);
   if (!for_solves) return;
   mirror_impl<double>(P, A, st);
-  qblocks_impl<double>(P, A, Ainv, st);
+  if (P.solve_form) qblocks_impl<double>(P, A, Ainv, st);
 }
 void factor(const FactorPlan& P, float* A, float* Ainv, const double* odiag, double drop_tol, double* pivrel,
             DevErr* err, hipStream_t st, int32_t* failed, bool for_solves) {
   factor_impl<float>(P, A, Ainv, odiag, drop_tol, pivrel, err, st, failed);
   if (!for_solves) return;
   mirror_impl<float>(P, A, st);
-  qblocks_impl<float>(P, A, Ainv, st);
+  if (P.solve_form) qblocks_impl<float>(P, A, Ainv, st);
 }
 
 // ------------------------------------------------------- triangular solves
@@ -1248,7 +1248,8 @@ __global__ __launch_bounds__(kTrsvThreads) void k_trsv(const MatDesc* __restrict
                                                        const int32_t* __restrict__ dep,
                                                        const int32_t* __restrict__ help_rng,
                                                        const int32_t* __restrict__ row_lo,
-                                                       const int32_t* __restrict__ row_help, double* part) {
+                                                       const int32_t* __restrict__ row_help, double* part,
+                                                       int qform) {
   constexpr int H = kTrsvThreads / NB;   // column groups
   constexpr int CW = NB / H;             // columns per group
   __shared__ double xs[NB];
@@ -1287,11 +1288,11 @@ __global__ __launch_bounds__(kTrsvThreads) void k_trsv(const MatDesc* __restrict
   T qa[CW], qb[CW];
   if (e1 > e0) load_block(qa, dep_at(e0));
   double acc = 0.0;
-  if (!helper) {
+  const T* inv = Ainv + d.inv_off + ((UPPER ? d.nblk : 0) + (int64_t)I) * NB * NB;
+  if (!helper && qform) {
     // c_I = inv(D_II) b_I
     if (tid < NB) xs[tid] = xi[(int64_t)I * NB + tid];
     __syncthreads();
-    const T* inv = Ainv + d.inv_off + ((UPPER ? d.nblk : 0) + (int64_t)I) * NB * NB;
 #pragma unroll 8
     for (int c = 0; c < CW; ++c) acc -= (double)inv[(int64_t)(CW * h + c) * NB + r] * xs[CW * h + c];
   }
@@ -1312,18 +1313,35 @@ __global__ __launch_bounds__(kTrsvThreads) void k_trsv(const MatDesc* __restrict
   }
   red[tid] = acc;
   __syncthreads();
+  double v = 0.0;
   if (tid < NB) {
-    double v = 0.0;
 #pragma unroll
     for (int g = 0; g < H; ++g) v += red[g * NB + tid];
     if (helper) {
       store_coherent(part + (int64_t)hid * NB + tid, v);
-    } else {
-      if (help_rng)
-        for (int hh = row_help[2 * I]; hh < row_help[2 * I + 1]; ++hh)
-          v += poll_value(part + (int64_t)hh * NB + tid, err);
-      store_coherent(xo + (int64_t)I * NB + tid, -v);
+    } else if (help_rng) {
+      for (int hh = row_help[2 * I]; hh < row_help[2 * I + 1]; ++hh)
+        v += poll_value(part + (int64_t)hh * NB + tid, err);
     }
+  }
+  if (helper) return;
+  if (qform) {
+    if (tid < NB) store_coherent(xo + (int64_t)I * NB + tid, -v);
+    return;
+  }
+  // plain form: x_I = inv(D_II) (b_I - sum_J L(I,J) x_J)
+  if (tid < NB) xs[tid] = xi[(int64_t)I * NB + tid] - v;
+  __syncthreads();
+  double a2 = 0.0;
+#pragma unroll 8
+  for (int c = 0; c < CW; ++c) a2 += (double)inv[(int64_t)(CW * h + c) * NB + r] * xs[CW * h + c];
+  red[tid] = a2;
+  __syncthreads();
+  if (tid < NB) {
+    double x = 0.0;
+#pragma unroll
+    for (int g = 0; g < H; ++g) x += red[g * NB + tid];
+    store_coherent(xo + (int64_t)I * NB + tid, x);
   }
 }
 
@@ -1409,7 +1427,7 @@ __global__ __launch_bounds__(256) void k_trsm_multi_mfma(const MatDesc* __restri
                                                          const int32_t* __restrict__ items,
                                                          const double* __restrict__ A,
                                                          const double* __restrict__ Ainv, double* X, int ldk, int k,
-                                                         unsigned* sync, unsigned* flags, DevErr* err) {
+                                                         unsigned* sync, unsigned* flags, DevErr* err, int qform) {
   constexpr int KC = 32, XP = KC + 1;
   __shared__ double xs[NB * XP];   // [row][column]
   __shared__ int s_t;
@@ -1443,13 +1461,16 @@ __global__ __launch_bounds__(256) void k_trsm_multi_mfma(const MatDesc* __restri
       acc[1][1] = mfma16(a1, b1, acc[1][1]);
     }
   };
-  // -c_I = -inv(D_II) B_I
-  for (int idx = tid; idx < NB * KC; idx += 256) {
-    const int rr = idx & (NB - 1), q = idx >> 7;
-    xs[rr * XP + q] = q < k ? -Xm[(int64_t)q * d.ld + (int64_t)I * NB + rr] : 0.0;
+  const double* inv = Ainv + d.inv_off + ((UPPER ? d.nblk : 0) + (int64_t)I) * NB * NB;
+  if (qform) {
+    // -c_I = -inv(D_II) B_I
+    for (int idx = tid; idx < NB * KC; idx += 256) {
+      const int rr = idx & (NB - 1), q = idx >> 7;
+      xs[rr * XP + q] = q < k ? -Xm[(int64_t)q * d.ld + (int64_t)I * NB + rr] : 0.0;
+    }
+    __syncthreads();
+    block_product(inv, NB);
   }
-  __syncthreads();
-  block_product(Ainv + d.inv_off + ((UPPER ? d.nblk : 0) + (int64_t)I) * NB * NB, NB);
   const int J0 = UPPER ? d.nblk - 1 : 0, Jend = I, dir = UPPER ? -1 : 1;
   if (tid == 0) s_front = J0;
   for (int J = J0; J != Jend; J += dir) {
@@ -1461,6 +1482,29 @@ __global__ __launch_bounds__(256) void k_trsm_multi_mfma(const MatDesc* __restri
     }
     __syncthreads();
     block_product(A + d.off + (int64_t)J * NB * d.ld + (int64_t)I * NB, d.ld);
+  }
+  if (!qform) {
+    // plain form: X_I = inv(D_II) (B_I - acc)
+    __syncthreads();   // every wave is done with the last X_J in xs
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+      for (int j = 0; j < 2; ++j)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int row = 32 * w + 16 * i + acc_row<double>(lane, v);
+          const int col = 16 * j + lr;
+          xs[row * XP + col] = col < k ? Xm[(int64_t)col * d.ld + (int64_t)I * NB + row] - acc[i][j][v] : 0.0;
+          acc[i][j][v] = 0.0;
+        }
+    __syncthreads();
+    block_product(inv, NB);
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+      for (int j = 0; j < 2; ++j)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) acc[i][j][v] = -acc[i][j][v];
   }
   // X_I = -acc
 #pragma unroll
@@ -1515,10 +1559,10 @@ static void solve_impl(const FactorPlan& P, const T* A, const T* Ainv, double* x
     k_solve_begin<<<1, 1, 0, st>>>(sync);
     if (dir == 0)
       k_trsv<T, false><<<nw, dim3(kTrsvThreads), 0, st>>>(P.d_desc.p, items, A, Ainv, xin, xout, sync, err, dptr, dl,
-                                                           hr, rlo, rh, P.d_part.p);
+                                                           hr, rlo, rh, P.d_part.p, P.solve_form ? 1 : 0);
     else
       k_trsv<T, true><<<nw, dim3(kTrsvThreads), 0, st>>>(P.d_desc.p, items, A, Ainv, xin, xout, sync, err, dptr, dl,
-                                                          hr, rlo, rh, P.d_part.p);
+                                                          hr, rlo, rh, P.d_part.p, P.solve_form ? 1 : 0);
   }
   HIP_CHECK(hipGetLastError());
 }
@@ -1555,6 +1599,7 @@ void solve_multi(const FactorPlan& P, const double* A, const double* Ainv, doubl
     return e && std::string(e) == "valu";
   }();
   if (valu) {
+    if (!P.solve_form) throw Error(GENEO_EUNSUPPORTED, "VALU many-RHS solve needs a factor in solve form");
     solve_multi_impl<double>(P, A, Ainv, X, ldk, k, sync, flags, err, st);
     return;
   }
@@ -1563,14 +1608,17 @@ void solve_multi(const FactorPlan& P, const double* A, const double* Ainv, doubl
   if (P.sparse) throw Error(GENEO_EUNSUPPORTED, "many right-hand sides on a block-sparse factor");
   k_solve_begin<<<1, 1, 0, st>>>(sync);
   k_trsm_multi_mfma<false><<<dim3((unsigned)P.n_items), dim3(256), 0, st>>>(P.d_desc.p, P.d_items_fwd.p, A, Ainv, X,
-                                                                            ldk, k, sync, flags, err);
+                                                                            ldk, k, sync, flags, err,
+                                                                            P.solve_form ? 1 : 0);
   k_solve_begin<<<1, 1, 0, st>>>(sync);
   k_trsm_multi_mfma<true><<<dim3((unsigned)P.n_items), dim3(256), 0, st>>>(P.d_desc.p, P.d_items_bwd.p, A, Ainv, X,
-                                                                           ldk, k, sync, flags, err);
+                                                                           ldk, k, sync, flags, err,
+                                                                           P.solve_form ? 1 : 0);
   HIP_CHECK(hipGetLastError());
 }
 void solve_multi(const FactorPlan& P, const float* A, const float* Ainv, double* X, int ldk, int k,
                  unsigned* sync, unsigned* flags, DevErr* err, hipStream_t st) {
+  if (!P.solve_form) throw Error(GENEO_EUNSUPPORTED, "FP32 many-RHS solve needs a factor in solve form");
   solve_multi_impl<float>(P, A, Ainv, X, ldk, k, sync, flags, err, st);
 }
 

@@ -498,6 +498,7 @@ static void fp32_probe(geneo_ctx* ctx, geneo_precond* pc, const std::vector<MatD
   const int32_t f32 = renumber(d32), f64 = renumber(d64);
   if (!d32.empty()) pc->local32.build(d32, st);
   pc->local64.build(d64, st);
+  pc->local32.solve_form = pc->local64.solve_form = false;
   (void)f32;
   (void)f64;
   // FP64 copies of the fallback matrices (extraction of every block is one
@@ -696,6 +697,7 @@ void setup_precond(geneo_ctx* ctx, geneo_precond* pc) {
   pc->batch_len = voff;
   pc->info.local_factor_flops = flops;
   pc->local.build(descs, st);
+  pc->local.solve_form = false;   // bandwidth-bound local solves: no premultiplied blocks
   pc->d_flags_local.alloc(flag_off);
   HIP_CHECK(hipMemsetAsync(pc->d_flags_local.p, 0, sizeof(unsigned) * flag_off, st));
 
