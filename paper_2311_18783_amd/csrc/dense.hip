@@ -72,6 +72,7 @@ __global__ __launch_bounds__(kPotrfThreads) void k_potrf(const MatDesc* __restri
   __shared__ double od[NB];                 // original diagonal (drop rule)
   constexpr int H = kPotrfThreads / NB;     // column phases (8)
   const int m = order[blockIdx.x];
+  if (failed && failed[m]) return;          // abandoned at an earlier step
   const MatDesc d = desc[m];
   const int t = threadIdx.x;
   // wave w holds rows 64 rh .. 64 rh + 63 for column phase h; rh alternates
@@ -373,11 +374,13 @@ __device__ inline int find_mat(const int64_t* __restrict__ prefix, int cnt, int6
 template <typename T, int MODE>
 __global__ __launch_bounds__(64 * TileGeo<MODE>::WAVES) __attribute__((amdgpu_waves_per_eu(1, MODE == 2 ? 1 : 4))) void k_trsm(
     const MatDesc* __restrict__ desc, const int32_t* __restrict__ order, const int64_t* __restrict__ prefix, int cnt,
-    int step, T* __restrict__ A, const T* __restrict__ Ainv, const int32_t* __restrict__ rows) {
+    int step, T* __restrict__ A, const T* __restrict__ Ainv, const int32_t* __restrict__ rows,
+    const int32_t* __restrict__ skip) {
   using G = TileGeo<MODE>;
   extern __shared__ unsigned char smem_raw[];
   T* smem = reinterpret_cast<T*>(smem_raw);
   const int j = rows ? 0 : find_mat(prefix, cnt, blockIdx.x);
+  if (skip && skip[order[j]]) return;   // factor already abandoned (non-positive pivot)
   const MatDesc d = desc[order[j]];
   const int64_t k0 = (int64_t)step * NB;
   // first row of the tile: dense = every block below the panel, sparse = the listed ones
@@ -401,9 +404,11 @@ __global__ __launch_bounds__(64 * TileGeo<MODE>::WAVES) __attribute__((amdgpu_wa
 template <typename T, int MODE>
 __global__ __launch_bounds__(64 * TileGeo<MODE>::WAVES) __attribute__((amdgpu_waves_per_eu(1, MODE == 2 ? 1 : 4))) void k_syrk(
     const MatDesc* __restrict__ desc, const int32_t* __restrict__ order, const int64_t* __restrict__ prefix, int cnt,
-    int kcol0, int kb, int b0, int ncols, T* __restrict__ A, const int32_t* __restrict__ pairs) {
+    int kcol0, int kb, int b0, int ncols, T* __restrict__ A, const int32_t* __restrict__ pairs,
+    const int32_t* __restrict__ skip) {
   using G = TileGeo<MODE>;
   const int j = pairs ? 0 : find_mat(prefix, cnt, blockIdx.x);
+  if (skip && skip[order[j]]) return;   // factor already abandoned (non-positive pivot)
   const MatDesc d = desc[order[j]];
   int64_t u = pairs ? 0 : blockIdx.x - prefix[j];
   int64_t ti, tj;
@@ -651,6 +656,7 @@ __global__ __launch_bounds__(kRecThreads) void k_potrf_rec(const MatDesc* __rest
   double* Ls = reinterpret_cast<double*>(smem_raw);   // [NB * LDA], column-major
   __shared__ double ldg[NB], od[NB];
   const int m = order[blockIdx.x];
+  if (failed && failed[m]) return;   // abandoned at an earlier step
   const MatDesc d = desc[m];
   const int tid = threadIdx.x;
   const int64_t k0 = (int64_t)step * NB;
@@ -977,7 +983,7 @@ static void factor_run(const FactorPlan& P, T* A, T* Ainv, const double* odiag, 
     if (L.tiles > 0 && L.kb > 0)
       k_syrk<T, MODE><<<dim3((unsigned)L.tiles), dim3(threads), mma_lds, st>>>(
           P.d_desc.p, P.d_order.p, P.d_syrk_prefix.p + L.pre_off, P.nmat, L.kcol0, L.kb, L.b0, L.ncols, A,
-          P.sparse ? P.d_syrk_pairs.p + 2 * P.syrk_off[li_of(L)] : nullptr);
+          P.sparse ? P.d_syrk_pairs.p + 2 * P.syrk_off[li_of(L)] : nullptr, failed);
   };
   for (int s0 = 0; s0 < P.max_blk; s0 += G) {
     for (int g = 0; g < G && s0 + g < P.max_blk; ++g) {
@@ -996,7 +1002,8 @@ static void factor_run(const FactorPlan& P, T* A, T* Ainv, const double* odiag, 
       }
       if (P.trsm_tiles[s] > 0)
         k_trsm<T, MODE><<<dim3((unsigned)P.trsm_tiles[s]), dim3(threads), mma_lds, st>>>(
-            P.d_desc.p, P.d_order.p, pt, P.cnt[s], s, A, Ainv, P.sparse ? P.d_trsm_rows.p + P.trsm_off[s] : nullptr);
+            P.d_desc.p, P.d_order.p, pt, P.cnt[s], s, A, Ainv, P.sparse ? P.d_trsm_rows.p + P.trsm_off[s] : nullptr,
+            failed);
       run_syrk(P.syrk[li++]);
     }
     run_syrk(P.syrk[li++]);

@@ -460,8 +460,13 @@ static void fp32_probe(geneo_ctx* ctx, geneo_precond* pc, const std::vector<MatD
   sq.alloc(2 * (int64_t)N);
   DevBuf<int64_t> d_voff;
   d_voff.upload(pc->voff, st);
+  std::vector<int32_t> failed(N);
+  HIP_CHECK(hipMemcpyAsync(failed.data(), d_failed, sizeof(int32_t) * N, hipMemcpyDeviceToHost, st));
+  HIP_CHECK(hipStreamSynchronize(st));
+  const bool any_ok = std::find(failed.begin(), failed.end(), 0) != failed.end();
+  // the power iteration only matters for factors that completed
   k_hash_fill<<<nblocks(len), 256, 0, st>>>(len, pc->d_bmap.p, pc->opts.seed ^ 0x5eedull, v);
-  for (int it = 0; it < kPowerSteps; ++it) {
+  for (int it = 0; it < (any_ok ? kPowerSteps : 0); ++it) {
     k_local_residual<<<nblocks(len), 256, 0, st>>>(len, pc->d_brp.p, pc->d_bcol.p, pc->d_bslot.p, s->d_val.p,
                                                    nullptr, v, nullptr, t);
     solve(pc->local, pc->fL.p, pc->fLinv.p, t, ctx->d_sync, ctx->d_err, st);
@@ -469,10 +474,8 @@ static void fp32_probe(geneo_ctx* ctx, geneo_precond* pc, const std::vector<MatD
     if (it >= kPowerSteps - 2) k_seg_sumsq<<<N, 256, 0, st>>>(d_voff.p, v, sq.p + (it - (kPowerSteps - 2)) * N);
   }
   HIP_CHECK(hipGetLastError());
-  std::vector<double> h(2 * (size_t)N);
-  std::vector<int32_t> failed(N);
-  HIP_CHECK(hipMemcpyAsync(h.data(), sq.p, sizeof(double) * 2 * N, hipMemcpyDeviceToHost, st));
-  HIP_CHECK(hipMemcpyAsync(failed.data(), d_failed, sizeof(int32_t) * N, hipMemcpyDeviceToHost, st));
+  std::vector<double> h(2 * (size_t)N, 0.0);
+  if (any_ok) HIP_CHECK(hipMemcpyAsync(h.data(), sq.p, sizeof(double) * 2 * N, hipMemcpyDeviceToHost, st));
   HIP_CHECK(hipStreamSynchronize(st));
   check_device_error(ctx);
   std::vector<MatDesc> d32, d64;
