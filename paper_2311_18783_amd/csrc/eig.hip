@@ -151,10 +151,13 @@ __global__ __launch_bounds__(256) void k_residual(int k, const int64_t* __restri
 // wave w owning output tiles w, w + 4, ... of both GA and GB (the L operand
 // is shared by the two).
 constexpr int kGramRows = 512, kGramSub = 32;
-constexpr int kGramMaxTiles = 7;   // per wave: ceil(25 / 4) for m <= 80
 
 typedef double gd4_t __attribute__((ext_vector_type(4)));
 
+// MAXT: output tiles per wave (1 for m <= 32, 7 for m <= 80); PER: staged
+// entries per thread and block (32 mp / 256).  The next slice is fetched
+// into registers while the current one runs on the MFMAs.
+template <int MAXT, int PER>
 __global__ __launch_bounds__(256) void k_gram(int k, int nl, const int64_t* __restrict__ voff,
                                               const int64_t* __restrict__ chunk_off, int nsub,
                                               const double* __restrict__ L0, const double* __restrict__ L1,
@@ -178,31 +181,50 @@ __global__ __launch_bounds__(256) void k_gram(int k, int nl, const int64_t* __re
   const double* Bs[3] = {B0, B1, B2};
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, lr = lane & 15, lk = lane >> 4;
   const int ntt = nt * nt;
-  gd4_t accA[kGramMaxTiles], accB[kGramMaxTiles];
+  // this thread's staged entries: slice row rr, column c (fixed per slice)
+  int ublk[PER];
+  int64_t uoff[PER];
 #pragma unroll
-  for (int t = 0; t < kGramMaxTiles; ++t) accA[t] = accB[t] = gd4_t{0, 0, 0, 0};
+  for (int u = 0; u < PER; ++u) {
+    const int idx = threadIdx.x + 256 * u, c = idx >> 5;
+    const bool ok = idx < kGramSub * mp && c < m;
+    const int bl = ok ? c / k : -1;
+    ublk[u] = bl;
+    uoff[u] = ok ? base + (int64_t)(c - bl * k) * ld + (idx & (kGramSub - 1)) : 0;
+  }
+  double pl[PER], pa[PER], pb[PER];
+  auto fetch = [&](int64_t r0) {
+#pragma unroll
+    for (int u = 0; u < PER; ++u) {
+      const int idx = threadIdx.x + 256 * u;
+      const bool ok = ublk[u] >= 0 && r0 + (idx & (kGramSub - 1)) < rend;
+      pl[u] = ok ? Ls[ublk[u]][uoff[u] + r0] : 0.0;
+      pa[u] = ok ? As[ublk[u]][uoff[u] + r0] : 0.0;
+      pb[u] = ok ? Bs[ublk[u]][uoff[u] + r0] : 0.0;
+    }
+  };
+  gd4_t accA[MAXT], accB[MAXT];
+#pragma unroll
+  for (int t = 0; t < MAXT; ++t) accA[t] = accB[t] = gd4_t{0, 0, 0, 0};
+  fetch(rbeg);
   for (int64_t r0 = rbeg; r0 < rend; r0 += kGramSub) {
-    for (int idx = threadIdx.x; idx < kGramSub * mp; idx += 256) {
-      const int rr = idx & (kGramSub - 1), c = idx / kGramSub;
-      const int64_t r = r0 + rr;
-      double lv = 0.0, av = 0.0, bv = 0.0;
-      if (c < m && r < rend) {
-        const int blk = c / k, q = c - blk * k;
-        const int64_t o = base + (int64_t)q * ld + r;
-        lv = Ls[blk][o];
-        av = As[blk][o];
-        bv = Bs[blk][o];
+#pragma unroll
+    for (int u = 0; u < PER; ++u) {
+      const int idx = threadIdx.x + 256 * u;
+      if (idx < kGramSub * mp) {
+        const int o = (idx & (kGramSub - 1)) * mp + (idx >> 5);
+        ls[o] = pl[u];
+        as[o] = pa[u];
+        bs[o] = pb[u];
       }
-      ls[rr * mp + c] = lv;
-      as[rr * mp + c] = av;
-      bs[rr * mp + c] = bv;
     }
     __syncthreads();
+    if (r0 + kGramSub < rend) fetch(r0 + kGramSub);
 #pragma unroll 2
     for (int kk = 0; kk < kGramSub; kk += 4) {
       const int ro = (kk + lk) * mp;
 #pragma unroll
-      for (int q = 0; q < kGramMaxTiles; ++q) {
+      for (int q = 0; q < MAXT; ++q) {
         const int t = w + 4 * q;
         if (t < ntt) {
           const int ta = t / nt, tb = t - ta * nt;
@@ -218,7 +240,7 @@ __global__ __launch_bounds__(256) void k_gram(int k, int nl, const int64_t* __re
   const int mm = m * m;
   double* out = part + (int64_t)blockIdx.x * 2 * mm;
 #pragma unroll
-  for (int q = 0; q < kGramMaxTiles; ++q) {
+  for (int q = 0; q < MAXT; ++q) {
     const int t = w + 4 * q;
     if (t < ntt) {
       const int ta = t / nt, tb = t - ta * nt;
@@ -881,8 +903,12 @@ static void gram(EigWork& w, int nl, const double* L0, const double* L1, const d
   const int m = nl * w.k;
   const size_t lds = sizeof(double) * 3 * kGramSub * ((m + 15) / 16 * 16);
   if (m > 16 * 5) throw Error(GENEO_EUNSUPPORTED, "Gram blocks wider than 80 columns");
-  k_gram<<<dim3((unsigned)w.nchunks), 256, lds, st>>>(w.k, nl, w.voff_d.p, w.chunk_off.p, w.N, L0, L1, L2, A0, A1,
-                                                       A2, B0, B1, B2, part.p);
+  if (m <= 32)
+    k_gram<1, 4><<<dim3((unsigned)w.nchunks), 256, lds, st>>>(w.k, nl, w.voff_d.p, w.chunk_off.p, w.N, L0, L1, L2,
+                                                              A0, A1, A2, B0, B1, B2, part.p);
+  else
+    k_gram<7, 10><<<dim3((unsigned)w.nchunks), 256, lds, st>>>(w.k, nl, w.voff_d.p, w.chunk_off.p, w.N, L0, L1, L2,
+                                                               A0, A1, A2, B0, B1, B2, part.p);
   dim3 grid((unsigned)((2 * m * m + 255) / 256), (unsigned)w.N);
   k_gram_reduce<<<grid, 256, 0, st>>>(m, w.chunk_off.p, part.p, g.p);
 }
@@ -1077,8 +1103,9 @@ void solve_local_gevps(geneo_ctx* ctx, geneo_precond* pc) {
   std::vector<int32_t> active(N, 1);
   DevBuf<int32_t> d_active;
   d_active.upload(active, st);
-  HIP_CHECK(hipFuncSetAttribute((const void*)k_gram, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                (int)(sizeof(double) * 3 * kGramSub * ((mmax + 15) / 16 * 16))));
+  for (const void* kf : {(const void*)k_gram<1, 4>, (const void*)k_gram<7, 10>})
+    HIP_CHECK(hipFuncSetAttribute(kf, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                  (int)(sizeof(double) * 3 * kGramSub * ((mmax + 15) / 16 * 16))));
 
   // start block: warm start if given, else random; B-orthogonal projection out of span(G_j)
   if (pc->opts.warm_start) {
