@@ -42,6 +42,7 @@ struct FactorPlan {
   DevBuf<int64_t> d_prefix;
   DevBuf<int32_t> d_items_fwd, d_items_bwd;
   DevBuf<double> d_y;                // single-right-hand-side solves: intermediate vector
+  mutable DevBuf<double> d_ym;       // many-right-hand-side solves: intermediate block (on first use)
   void build(const std::vector<MatDesc>& descs, hipStream_t st);
 
   // Block-sparse single matrix: only the tiles of the factor's fill pattern

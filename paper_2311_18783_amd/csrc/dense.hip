@@ -1433,24 +1433,20 @@ template <bool UPPER>
 __global__ __launch_bounds__(256) void k_trsm_multi_mfma(const MatDesc* __restrict__ desc,
                                                          const int32_t* __restrict__ items,
                                                          const double* __restrict__ A,
-                                                         const double* __restrict__ Ainv, double* X, int ldk, int k,
-                                                         unsigned* sync, unsigned* flags, DevErr* err, int qform) {
+                                                         const double* __restrict__ Ainv,
+                                                         const double* __restrict__ Xin, double* Xout, int ldk, int k,
+                                                         unsigned* sync, DevErr* err, int qform) {
   constexpr int KC = 32, XP = KC + 1;
   __shared__ double xs[NB * XP];   // [row][column]
   __shared__ int s_t;
-  __shared__ unsigned s_epoch;
-  __shared__ int s_front;
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   const int lr = lane & 15, lk = lane >> 4;
-  if (tid == 0) {
-    s_t = (int)atomicAdd(&sync[0], 1u);
-    s_epoch = __hip_atomic_load(&sync[1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-  }
+  if (tid == 0) s_t = (int)atomicAdd(&sync[0], 1u);
   __syncthreads();
   const int m = items[2 * s_t], I = items[2 * s_t + 1];
-  const unsigned epoch = s_epoch;
   const MatDesc d = desc[m];
-  double* Xm = X + d.voff * (int64_t)ldk;
+  const double* Xm = Xin + d.voff * (int64_t)ldk;   // right-hand sides
+  double* Ym = Xout + d.voff * (int64_t)ldk;        // results (preset pending, polled by later blocks)
   d4_t acc[2][2];
 #pragma unroll
   for (int i = 0; i < 2; ++i)
@@ -1479,13 +1475,37 @@ __global__ __launch_bounds__(256) void k_trsm_multi_mfma(const MatDesc* __restri
     block_product(inv, NB);
   }
   const int J0 = UPPER ? d.nblk - 1 : 0, Jend = I, dir = UPPER ? -1 : 1;
-  if (tid == 0) s_front = J0;
+  constexpr int PER = NB * KC / 256;   // values of X_J per thread
   for (int J = J0; J != Jend; J += dir) {
-    if (tid == 0 && J == s_front) s_front = wait_frontier(flags + d.flag_off, J, Jend, dir, epoch, err);
-    __syncthreads();   // also: every wave is done with the previous xs
-    for (int idx = tid; idx < NB * KC; idx += 256) {
-      const int rr = idx & (NB - 1), q = idx >> 7;
-      xs[rr * XP + q] = q < k ? load_coherent(Xm + (int64_t)q * d.ld + (int64_t)J * NB + rr) : 0.0;
+    __syncthreads();   // every wave is done with the previous xs
+    // all loads in flight at once; only values still pending are polled again
+    double vals[PER];
+    const double* yj = Ym + (int64_t)J * NB;
+#pragma unroll
+    for (int u = 0; u < PER; ++u) {
+      const int idx = tid + 256 * u, rr = idx & (NB - 1), q = idx >> 7;
+      vals[u] = q < k ? load_coherent(yj + (int64_t)q * d.ld + rr) : 0.0;
+    }
+    for (unsigned spins = 0;; ++spins) {
+      bool pend = false;
+#pragma unroll
+      for (int u = 0; u < PER; ++u) pend |= __builtin_bit_cast(uint64_t, vals[u]) == kPending;
+      if (!pend) break;
+      if (spins > kSpinLimit) {
+        set_err(err, GENEO_ESYNC, -1, -1);
+        break;
+      }
+      __builtin_amdgcn_s_sleep(1);
+#pragma unroll
+      for (int u = 0; u < PER; ++u) {
+        const int idx = tid + 256 * u, rr = idx & (NB - 1), q = idx >> 7;
+        if (__builtin_bit_cast(uint64_t, vals[u]) == kPending) vals[u] = load_coherent(yj + (int64_t)q * d.ld + rr);
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < PER; ++u) {
+      const int idx = tid + 256 * u, rr = idx & (NB - 1), q = idx >> 7;
+      xs[rr * XP + q] = vals[u];
     }
     __syncthreads();
     block_product(A + d.off + (int64_t)J * NB * d.ld + (int64_t)I * NB, d.ld);
@@ -1522,10 +1542,18 @@ __global__ __launch_bounds__(256) void k_trsm_multi_mfma(const MatDesc* __restri
       for (int v = 0; v < 4; ++v) {
         const int row = 32 * w + 16 * i + acc_row<double>(lane, v);
         const int col = 16 * j + lr;
-        if (col < k) store_coherent(Xm + (int64_t)col * d.ld + (int64_t)I * NB + row, -acc[i][j][v]);
+        if (col < k) store_coherent(Ym + (int64_t)col * d.ld + (int64_t)I * NB + row, -acc[i][j][v]);
       }
-  __syncthreads();
-  if (tid == 0) publish(flags + d.flag_off + I, epoch);
+}
+
+// marks the k columns of the solve's blocks pending (many right-hand sides)
+__global__ void k_pending_multi(const MatDesc* __restrict__ desc, const int32_t* __restrict__ items, double* X,
+                                int ldk, int k) {
+  const int m = items[2 * blockIdx.x], I = items[2 * blockIdx.x + 1];
+  const MatDesc d = desc[m];
+  for (int idx = threadIdx.x; idx < NB * k; idx += blockDim.x)
+    X[d.voff * (int64_t)ldk + (int64_t)(idx >> 7) * d.ld + (int64_t)I * NB + (idx & (NB - 1))] =
+        __builtin_bit_cast(double, kPending);
 }
 
 template <typename T>
@@ -1611,17 +1639,22 @@ void solve_multi(const FactorPlan& P, const double* A, const double* Ainv, doubl
     return;
   }
   if (P.n_items == 0 || k == 0) return;
-  if (k > 32) throw Error(GENEO_EUNSUPPORTED, "more than 32 right-hand sides");
+  if (k > 32 || ldk < k) throw Error(GENEO_EUNSUPPORTED, "more than 32 right-hand sides");
   if (P.sparse) throw Error(GENEO_EUNSUPPORTED, "many right-hand sides on a block-sparse factor");
+  // intermediate block (forward result, backward input), one per plan
+  const int64_t need = P.d_y.n * (int64_t)ldk;
+  if ((int64_t)P.d_ym.n < need) P.d_ym.alloc(need);
+  double* Y = P.d_ym.p;
+  const unsigned ni = (unsigned)P.n_items;
+  const int qf = P.solve_form ? 1 : 0;
+  k_pending_multi<<<ni, 256, 0, st>>>(P.d_desc.p, P.d_items_fwd.p, Y, ldk, k);
   k_solve_begin<<<1, 1, 0, st>>>(sync);
-  k_trsm_multi_mfma<false><<<dim3((unsigned)P.n_items), dim3(256), 0, st>>>(P.d_desc.p, P.d_items_fwd.p, A, Ainv, X,
-                                                                            ldk, k, sync, flags, err,
-                                                                            P.solve_form ? 1 : 0);
+  k_trsm_multi_mfma<false><<<ni, 256, 0, st>>>(P.d_desc.p, P.d_items_fwd.p, A, Ainv, X, Y, ldk, k, sync, err, qf);
+  k_pending_multi<<<ni, 256, 0, st>>>(P.d_desc.p, P.d_items_fwd.p, X, ldk, k);
   k_solve_begin<<<1, 1, 0, st>>>(sync);
-  k_trsm_multi_mfma<true><<<dim3((unsigned)P.n_items), dim3(256), 0, st>>>(P.d_desc.p, P.d_items_bwd.p, A, Ainv, X,
-                                                                           ldk, k, sync, flags, err,
-                                                                           P.solve_form ? 1 : 0);
+  k_trsm_multi_mfma<true><<<ni, 256, 0, st>>>(P.d_desc.p, P.d_items_bwd.p, A, Ainv, Y, X, ldk, k, sync, err, qf);
   HIP_CHECK(hipGetLastError());
+  (void)flags;
 }
 void solve_multi(const FactorPlan& P, const float* A, const float* Ainv, double* X, int ldk, int k,
                  unsigned* sync, unsigned* flags, DevErr* err, hipStream_t st) {
