@@ -196,11 +196,14 @@ def main():
     head = run[0]
     last = res[head][-1]
     plain = res["fp64"] if "fp64" in res else res[head]
-    # dominant kernel family: the FP64 coarse Cholesky (potrf/trsm/syrk launches of one factorisation)
+    # dominant kernel family: the batched FP64 Cholesky (potrf/trsm/syrk launches); reported
+    # on the local factorisation of all subdomain matrices (plain FP64 path: sum n_i^3 / 3
+    # flop over the HIP-event time of that factorisation), the coarse one beside it
+    lf_ms = float(np.mean([r["t_factor_ms"] for r in plain]))
+    achieved = plain[-1]["local_flops"] / (lf_ms * 1e-3) / 1e12
     cf_ms = float(np.mean([r["t_coarse_factor_ms"] for r in plain]))
-    # flops of the factorisation as performed: on the block-sparse fill pattern of E
-    # (47,127 columns after the node-local basis test)
-    achieved = plain[-1]["coarse_flops"] / (cf_ms * 1e-3) / 1e12
+    # flops of the coarse factorisation as performed: on the block-sparse fill pattern of E
+    achieved_coarse = plain[-1]["coarse_flops"] / (cf_ms * 1e-3) / 1e12
     line = {
         "metric": METRIC,
         "value": summ[head]["setup_solve_s"],
@@ -222,9 +225,13 @@ def main():
                    "n0_rank": last["n0_rank"],
                    "n_geneo": last["n_geneo"], "parallelism": "1 GPU"},
         "variants": summ,
-        "roofline": {"bound": "mfma", "kernel": "FP64 coarse Cholesky of E (potrf/trsm/syrk launches)",
+        "roofline": {"bound": "mfma",
+                     "kernel": "batched FP64 local Cholesky of the 64 subdomain matrices (potrf/trsm/syrk/mirror)",
                      "achieved": achieved, "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
                      "frac": achieved / PEAK_FP64_TFLOPS, "traffic": None},
+        "roofline_coarse": {"bound": "mfma", "kernel": "block-sparse FP64 coarse Cholesky of E",
+                            "achieved": achieved_coarse, "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
+                            "frac": achieved_coarse / PEAK_FP64_TFLOPS},
     }
     if "fp64" in summ and head != "fp64":
         line["speedup_vs_plain_fp64"] = summ["fp64"]["setup_solve_s"] / summ[head]["setup_solve_s"]
