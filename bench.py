@@ -34,6 +34,11 @@ sys.path.insert(0, ROOT)
 METRIC = "setup+solve s to rtol 1e-8 & local-factor TFLOP/s; learned+FP32 vs plain FP64"
 PEAK_FP64_TFLOPS = 78.6     # MI355X dense FP64 matrix peak
 PEAK_FP32_TFLOPS = 157.3
+# HBM bytes of one batched local factorisation at this workload (plain FP64 path), from the
+# rocprofv3 FETCH_SIZE and WRITE_SIZE counters summed over its launches and scaled by what the
+# same counters read for a 1 GiB device copy (fetch x2.0, write x1.0); valid for the current
+# potrf/trsm/syrk/mirror kernels only
+LOCAL_FACTOR_HBM_BYTES = {"fetch": 193.9e9, "write": 57.2e9}
 
 
 def parse():
@@ -45,6 +50,8 @@ def parse():
     ap.add_argument("--workload", default="2", help="workload id (default: the 24^3 channel cube)")
     ap.add_argument("--variant", default="both", choices=["both", "learned_fp32", "fp64"])
     ap.add_argument("--train-instances", type=int, default=8)
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
+                    help="only run one device copy of BYTES (counter calibration) and exit")
     return ap.parse_args()
 
 
@@ -161,8 +168,23 @@ def summarize(res):
     }
 
 
+def copy_calibration(nbytes):
+    """One device-to-device copy of nbytes: the reference kernel for scaling
+    the FETCH_SIZE / WRITE_SIZE counters of the hot path to bytes."""
+    import torch
+    a = torch.ones(nbytes // 8, dtype=torch.float64, device="cuda:0")
+    b = torch.empty_like(a)
+    torch.cuda.synchronize()
+    b.copy_(a)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_bytes": a.numel() * 8}), flush=True)
+
+
 def main():
     a = parse()
+    if a.copy_calibration:
+        copy_calibration(a.copy_calibration)
+        return
     if a.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1", "n_gpus": a.gpus}))
         sys.exit(2)
@@ -228,7 +250,9 @@ def main():
         "roofline": {"bound": "mfma",
                      "kernel": "batched FP64 local Cholesky of the 64 subdomain matrices (potrf/trsm/syrk/mirror)",
                      "achieved": achieved, "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
-                     "frac": achieved / PEAK_FP64_TFLOPS, "traffic": None},
+                     "frac": achieved / PEAK_FP64_TFLOPS,
+                     "traffic": LOCAL_FACTOR_HBM_BYTES["fetch"] + LOCAL_FACTOR_HBM_BYTES["write"],
+                     "traffic_unit": "B per factorisation (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-scaled)"},
         "roofline_coarse": {"bound": "mfma", "kernel": "block-sparse FP64 coarse Cholesky of E",
                             "achieved": achieved_coarse, "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
                             "frac": achieved_coarse / PEAK_FP64_TFLOPS},
