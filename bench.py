@@ -111,6 +111,7 @@ def run_step(geneo, ctx, w, precision, b_host=None, model=None):
                t_coarse_build_ms=pi.t_coarse_build_ms, t_coarse_factor_ms=pi.t_coarse_factor_ms,
                solve_ms=si.solve_ms, local_flops=pi.local_factor_flops, assemble_ms=sysm.info().assemble_ms,
                fp64_fallbacks=pi.fp64_fallbacks, fp32_rho_est=pi.fp32_rho_est,
+               fp32_prechecked=pi.fp32_prechecked, fp32_kappa_lb=pi.fp32_kappa_lb,
                learned_starts=pi.learned_starts, start_residual=pi.start_residual,
                n0_factored=pi.n0 - pi.n0_local_dropped, coarse_flops=pi.coarse_factor_flops,
                coarse_fill=pi.coarse_fill)
@@ -165,6 +166,8 @@ def summarize(res):
         "lobpcg_iterations": last["lobpcg_iters"], "start_residual": last["start_residual"],
         "learned_starts": last["learned_starts"], "fp64_fallbacks": last["fp64_fallbacks"],
         "fp32_rho_est": last["fp32_rho_est"] if np.isfinite(last["fp32_rho_est"]) else "inf",
+        "fp32_prechecked": last["fp32_prechecked"],
+        "fp32_kappa_lb": last["fp32_kappa_lb"] if np.isfinite(last["fp32_kappa_lb"]) else "inf",
     }
 
 

@@ -177,6 +177,11 @@ typedef struct {
   int32_t learned_starts;   /* subdomains whose start block came from the model */
   double start_residual;    /* largest eigen-residual of the top nev_max Ritz pairs after the first
                                Rayleigh-Ritz step (start-block quality) */
+  int32_t fp32_prechecked;  /* FP32_REFINE1: subdomains factored in FP64 without an FP32 attempt, because
+                               0.2 u32 kappa_lb_i > fp32_rho_max (u32 = 2^-24); counted in fp64_fallbacks */
+  double fp32_kappa_lb;     /* FP32_REFINE1: largest kappa_lb_i, the lower bound on the condition number of
+                               D^-1/2 A_i D^-1/2 (D = diag A_i) from the Rayleigh quotient of a node's
+                               gradient (sampled nodes whose edges all lie in Omega_i; 0 if none) */
 } geneo_precond_info;
 
 void geneo_setup_opts_default(geneo_setup_opts* o);

@@ -440,6 +440,130 @@ static float elapsed(geneo_ctx* ctx, int a, int b) {
   return ms;
 }
 
+// Conditioning check before any FP32 work.  The hat function of a node all
+// of whose edges lie in Omega_i has the edge coefficients v = G e_node
+// (+-1 on those edges); the curl-curl part annihilates it, so its Rayleigh
+// quotient in the diagonally scaled matrix D^-1/2 A_i D^-1/2 (D = diag A_i),
+//   q = v^T A_i v / v^T D v,
+// bounds that matrix's smallest eigenvalue from above.  Its diagonal is 1,
+// so 1/q bounds its condition number from below, and Cholesky's rounding
+// error follows the condition number of the scaled matrix.  On the measured
+// subdomains the refinement radius rho(I - Ahat^-1 A_i) of the FP32 factor
+// was at least kFp32RhoPerBound * u32 / q; a subdomain where that exceeds
+// fp32_rho_max is flagged (value 2) so the FP32 kernels skip it, and it is
+// factored in FP64 directly.  A subdomain without a usable node keeps its
+// FP32 attempt.
+constexpr double kFp32RhoPerBound = 0.2;
+constexpr int kFp32CheckNodes = 32;
+
+struct Fp32Check {
+  std::vector<int32_t> smp_off, pair_off, slot;
+  std::vector<int8_t> w;   // +-1: off-diagonal term of v^T A v; 2: diagonal (also in v^T D v)
+};
+
+static Fp32Check fp32_check_plan(const geneo_system* s, const geneo_decomp* dec) {
+  const int64_t n = s->n;
+  const int64_t p = (int64_t)s->free_nodes.size();
+  // free edges at each free node, with the coefficient of that node's hat gradient
+  std::vector<int32_t> nptr(p + 1, 0);
+  for (int64_t fe = 0; fe < n; ++fe) {
+    const int32_t ge = s->free_edges[fe];
+    for (int end = 0; end < 2; ++end) {
+      const int32_t fn = s->node_to_free[s->edges[2 * (int64_t)ge + end]];
+      if (fn >= 0) nptr[fn + 1]++;
+    }
+  }
+  for (int64_t k = 0; k < p; ++k) nptr[k + 1] += nptr[k];
+  std::vector<int32_t> ned(nptr[p]);
+  std::vector<int8_t> nsg(nptr[p]);
+  {
+    std::vector<int32_t> f(nptr.begin(), nptr.end() - 1);
+    for (int64_t fe = 0; fe < n; ++fe) {
+      const int32_t ge = s->free_edges[fe];
+      for (int end = 0; end < 2; ++end) {
+        const int32_t fn = s->node_to_free[s->edges[2 * (int64_t)ge + end]];
+        if (fn < 0) continue;
+        ned[f[fn]] = (int32_t)fe;
+        nsg[f[fn]++] = end ? 1 : -1;   // edge (a, b): grad phi_b = +w_e, grad phi_a = -w_e
+      }
+    }
+  }
+  const int32_t N = dec->N;
+  std::vector<std::vector<int32_t>> cnt(N), sl(N);
+  std::vector<std::vector<int8_t>> ww(N);
+  parallel_for(N, [&](int i) {
+    const int32_t* d0 = dec->dofs.data() + dec->dofs_ptr[i];
+    const int32_t* d1 = dec->dofs.data() + dec->dofs_ptr[i + 1];
+    const int64_t g0 = dec->gn_ptr[i], ng = dec->gn_ptr[i + 1] - g0;
+    const int64_t tries = std::min<int64_t>(ng, 4 * kFp32CheckNodes);
+    for (int64_t t = 0; t < tries && (int)cnt[i].size() < kFp32CheckNodes; ++t) {
+      const int32_t fn = dec->gnodes[g0 + t * ng / tries];
+      bool inside = nptr[fn + 1] > nptr[fn];
+      for (int32_t k = nptr[fn]; k < nptr[fn + 1] && inside; ++k) inside = std::binary_search(d0, d1, ned[k]);
+      if (!inside) continue;
+      int32_t m = 0;
+      for (int32_t a = nptr[fn]; a < nptr[fn + 1]; ++a)
+        for (int32_t b = nptr[fn]; b < nptr[fn + 1]; ++b) {
+          const int32_t e = ned[a], f = ned[b];
+          for (int32_t q = s->rowptr[e]; q < s->rowptr[e + 1]; ++q)
+            if (s->colind[q] == f) {
+              sl[i].push_back(q);
+              ww[i].push_back(e == f ? 2 : (int8_t)(nsg[a] * nsg[b]));
+              ++m;
+              break;
+            }
+        }
+      cnt[i].push_back(m);
+    }
+  });
+  Fp32Check c;
+  c.smp_off.assign(N + 1, 0);
+  c.pair_off.assign(1, 0);
+  for (int32_t i = 0; i < N; ++i) {
+    c.smp_off[i + 1] = c.smp_off[i] + (int32_t)cnt[i].size();
+    for (int32_t m : cnt[i]) c.pair_off.push_back(c.pair_off.back() + m);
+    c.slot.insert(c.slot.end(), sl[i].begin(), sl[i].end());
+    c.w.insert(c.w.end(), ww[i].begin(), ww[i].end());
+  }
+  return c;
+}
+
+// One workgroup per subdomain: q of each sampled node, the smallest q, the
+// flag and the bound 1/q (0 without a usable node, infinite for q <= 0).
+__global__ __launch_bounds__(256) void k_fp32_check(const int32_t* __restrict__ smp_off,
+                                                    const int32_t* __restrict__ pair_off,
+                                                    const int32_t* __restrict__ slot, const int8_t* __restrict__ w,
+                                                    const double* __restrict__ val, double q_floor,
+                                                    int32_t* __restrict__ failed, double* __restrict__ kappa_lb) {
+  __shared__ double red[256];
+  const int i = blockIdx.x, tid = threadIdx.x;
+  double q = INFINITY;
+  for (int k = smp_off[i] + tid; k < smp_off[i + 1]; k += 256) {
+    double num = 0.0, den = 0.0;
+    for (int t = pair_off[k]; t < pair_off[k + 1]; ++t) {
+      const double a = val[slot[t]];
+      if (w[t] == 2) {
+        num += a;
+        den += a;
+      } else {
+        num += (double)w[t] * a;
+      }
+    }
+    q = fmin(q, den > 0.0 ? num / den : 0.0);
+  }
+  red[tid] = q;
+  __syncthreads();
+  for (int h = 128; h > 0; h >>= 1) {
+    if (tid < h) red[tid] = fmin(red[tid], red[tid + h]);
+    __syncthreads();
+  }
+  if (tid == 0) {
+    const double qm = red[0];
+    kappa_lb[i] = qm > 0.0 ? (qm == INFINITY ? 0.0 : 1.0 / qm) : INFINITY;
+    failed[i] = qm < q_floor ? 2 : 0;
+  }
+}
+
 // FP32 local factors with one FP64 refinement step apply the map
 //   y = yhat + Ahat^-1 (r - A_i yhat),  yhat = Ahat^-1 r,
 // i.e. (2 Ahat^-1 - Ahat^-1 A_i Ahat^-1) r, which is symmetric and positive
@@ -448,7 +572,7 @@ static float elapsed(geneo_ctx* ctx, int a, int b) {
 // FP32 solve) and refactors in FP64 every subdomain whose estimate exceeds
 // fp32_rho_max or is not finite.
 static void fp32_probe(geneo_ctx* ctx, geneo_precond* pc, const std::vector<MatDesc>& descs,
-                       const int32_t* d_failed) {
+                       const int32_t* d_failed, const double* d_kappa_lb) {
   constexpr int kPowerSteps = 8;
   hipStream_t st = ctx->stream;
   const int32_t N = pc->N;
@@ -461,8 +585,12 @@ static void fp32_probe(geneo_ctx* ctx, geneo_precond* pc, const std::vector<MatD
   DevBuf<int64_t> d_voff;
   d_voff.upload(pc->voff, st);
   std::vector<int32_t> failed(N);
+  std::vector<double> klb(N);
   HIP_CHECK(hipMemcpyAsync(failed.data(), d_failed, sizeof(int32_t) * N, hipMemcpyDeviceToHost, st));
+  HIP_CHECK(hipMemcpyAsync(klb.data(), d_kappa_lb, sizeof(double) * N, hipMemcpyDeviceToHost, st));
   HIP_CHECK(hipStreamSynchronize(st));
+  pc->info.fp32_prechecked = (int32_t)std::count(failed.begin(), failed.end(), 2);
+  pc->info.fp32_kappa_lb = klb.empty() ? 0.0 : *std::max_element(klb.begin(), klb.end());
   const bool any_ok = std::find(failed.begin(), failed.end(), 0) != failed.end();
   // the power iteration only matters for factors that completed
   k_hash_fill<<<nblocks(len), 256, 0, st>>>(len, pc->d_bmap.p, pc->opts.seed ^ 0x5eedull, v);
@@ -823,12 +951,23 @@ void setup_precond(geneo_ctx* ctx, geneo_precond* pc) {
   if (fp32) {
     // an FP32 factor that meets a non-positive pivot is flagged, not fatal:
     // that subdomain falls back to FP64
-    DevBuf<int32_t> failed;
+    DevBuf<int32_t> failed, c_smp, c_pair, c_slot;
+    DevBuf<int8_t> c_w;
+    DevBuf<double> klb;
     failed.alloc(N);
-    HIP_CHECK(hipMemsetAsync(failed.p, 0, sizeof(int32_t) * N, st));
+    klb.alloc(N);
+    const Fp32Check chk = fp32_check_plan(s, dec);
+    c_smp.upload(chk.smp_off, st);
+    c_pair.upload(chk.pair_off, st);
+    c_slot.upload(chk.slot, st);
+    c_w.upload(chk.w, st);
+    const double rho_max = pc->opts.fp32_rho_max;
+    const double q_floor = rho_max > 0.0 ? kFp32RhoPerBound * 0x1p-24 / rho_max : INFINITY;
+    k_fp32_check<<<N, 256, 0, st>>>(c_smp.p, c_pair.p, c_slot.p, c_w.p, s->d_val.p, q_floor, failed.p, klb.p);
+    HIP_CHECK(hipGetLastError());
     factor(pc->local, pc->fL.p, pc->fLinv.p, nullptr, 0.0, nullptr, ctx->d_err, st, failed.p);
     check_device_error(ctx);
-    fp32_probe(ctx, pc, descs, failed.p);
+    fp32_probe(ctx, pc, descs, failed.p, klb.p);
   } else {
     factor(pc->local, pc->dL.p, pc->dLinv.p, nullptr, 0.0, nullptr, ctx->d_err, st);
   }

@@ -80,7 +80,8 @@ class PrecondInfo(C.Structure):
                 ("t_coarse_build_ms", C.c_double), ("t_coarse_factor_ms", C.c_double),
                 ("local_factor_flops", C.c_double), ("fp32_rho_est", C.c_double),
                 ("coarse_factor_flops", C.c_double), ("coarse_fill", C.c_double),
-                ("learned_starts", C.c_int32), ("start_residual", C.c_double)]
+                ("learned_starts", C.c_int32), ("start_residual", C.c_double),
+                ("fp32_prechecked", C.c_int32), ("fp32_kappa_lb", C.c_double)]
 
 
 class ModelOpts(C.Structure):

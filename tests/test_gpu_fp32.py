@@ -29,6 +29,18 @@ def _rho_oracle(w):
     return s, np.array([tl.fp32_rho(i) for i in range(odec.N)])
 
 
+def _scaled_kappa(w):
+    """Condition numbers of D^-1/2 A_i D^-1/2 (D = diag A_i), dense eigenvalues."""
+    s, odec = oracle_problem(w)
+    out = []
+    for d in odec.dofs:
+        Ai = s.A[d][:, d].toarray()
+        r = 1.0 / np.sqrt(np.diag(Ai))
+        ev = np.linalg.eigvalsh(Ai * r[:, None] * r[None, :])
+        out.append(ev[-1] / ev[0])
+    return np.array(out)
+
+
 @pytest.mark.parametrize("cfg", CASES)
 def test_fp32_refined_preconditioner(g, cfg):
     """Fallback count consistent with the exact radii (every subdomain with
@@ -47,6 +59,10 @@ def test_fp32_refined_preconditioner(g, cfg):
     assert i32.n0 == i64.n0 and i32.n_geneo == i64.n_geneo and i32.n0_rank == i64.n0_rank
     nfb = i32.fp64_fallbacks
     assert int((rho > 1.0).sum()) <= nfb <= int((rho > 0.25).sum()), (nfb, rho)
+    # the conditioning check only skips subdomains whose FP32 factor the probe rejects,
+    # and its bound is a lower bound of the scaled condition number
+    assert i32.fp32_prechecked <= int((rho > 0.5).sum()), (i32.fp32_prechecked, rho)
+    assert 0 < i32.fp32_kappa_lb <= (1 + 1e-6) * _scaled_kappa(w).max()
     assert i32.fp32_rho_est > 0
     if nfb == 0:
         assert i32.fp32_rho_est <= 0.5
@@ -87,5 +103,42 @@ def test_fp32_full_fallback_is_the_fp64_path(g):
     b = torch.zeros_like(a)
     ctx.apply(pc64, r, a)
     ctx.apply(pcf, r, b)
+    torch.cuda.synchronize()
+    assert torch.equal(a, b)
+
+
+def test_fp32_conditioning_check_skips_hopeless_factors(g):
+    """With gamma = 1e-6 every local matrix of the channel case is too ill
+    conditioned for an FP32 factor (LAPACK's fails or its refinement radius
+    exceeds 0.5): the conditioning check sends all of them to FP64 before
+    any FP32 work, its bound stays below the scaled condition numbers, and
+    the apply is bitwise that of the FP64 preconditioner."""
+    import scipy.linalg as sla
+    import torch
+    geneo, ctx = g
+    w = W.make("small_channels", gamma=1e-6)
+    s, odec = oracle_problem(w)
+    for d in odec.dofs:
+        Ai = s.A[d][:, d].toarray()
+        try:
+            L = sla.cholesky(Ai.astype(np.float32), lower=True).astype(np.float64)
+        except np.linalg.LinAlgError:
+            continue
+        T = np.eye(len(d)) - sla.cho_solve((L, True), Ai)
+        assert np.abs(np.linalg.eigvals(T)).max() > 0.5
+    sysm, dec = lib_problem(ctx, w)
+    n = sysm.info().n
+    pc64 = ctx.setup(sysm, dec, tau=w.tau, nev_max=w.nev_max, local_precision=geneo.FP64)
+    pc32 = ctx.setup(sysm, dec, tau=w.tau, nev_max=w.nev_max, local_precision=geneo.FP32_REFINE1)
+    i32 = pc32.info()
+    assert i32.fp32_prechecked == dec.info().n_sub
+    assert i32.fp64_fallbacks == dec.info().n_sub
+    assert 0.2 * 2.0 ** -24 * i32.fp32_kappa_lb > 0.5
+    assert i32.fp32_kappa_lb <= (1 + 1e-6) * _scaled_kappa(w).max()
+    r = to_dev(np.random.default_rng(7).standard_normal(n))
+    a = torch.zeros(n, dtype=torch.float64, device="cuda:0")
+    b = torch.zeros_like(a)
+    ctx.apply(pc64, r, a)
+    ctx.apply(pc32, r, b)
     torch.cuda.synchronize()
     assert torch.equal(a, b)
