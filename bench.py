@@ -105,6 +105,7 @@ def run_step(geneo, ctx, w, precision, b_host=None, model=None):
     di = dec.info()
     out = dict(assemble_s=t1 - t0, partition_s=t2 - t1, setup_s=t3 - t2, solve_s=t4 - t3,
                setup_solve_s=t4 - t2, step_s=t4 - t0, iterations=si.iterations, rel_residual=si.rel_residual,
+               graph_replays=si.graph_replays,
                n=n, n_sub=di.n_sub, n_min=di.n_min, n_max=di.n_max, n0=pi.n0, n0_rank=pi.n0_rank,
                n_snk=pi.n_snk, n_geneo=pi.n_geneo, lobpcg_iters=pi.lobpcg_iters,
                t_extract_ms=pi.t_extract_ms, t_factor_ms=pi.t_factor_ms, t_gevp_ms=pi.t_gevp_ms,
@@ -163,6 +164,7 @@ def summarize(res):
         "coarse_factor_tflops": last["coarse_flops"] / (mean("t_coarse_factor_ms") * 1e-3) / 1e12,
         "coarse_fill": last["coarse_fill"],
         "pcg_iterations": last["iterations"], "rel_residual": last["rel_residual"],
+        "pcg_graph_replays": last["graph_replays"],
         "lobpcg_iterations": last["lobpcg_iters"], "start_residual": last["start_residual"],
         "learned_starts": last["learned_starts"], "fp64_fallbacks": last["fp64_fallbacks"],
         "fp32_rho_est": last["fp32_rho_est"] if np.isfinite(last["fp32_rho_est"]) else "inf",

@@ -219,12 +219,18 @@ int geneo_apply(geneo_ctx* ctx, const geneo_precond* pc, const double* r, double
 typedef struct {
   double rtol;      /* stop at the first k with ||r_k||_2 <= rtol ||b||_2 */
   int32_t maxit;
+  int32_t graph;    /* 1: from the second iteration on, replay one iteration (preconditioner apply,
+                       products, updates, copy of ||r||^2 to the host) captured as a HIP graph, on a
+                       stream of the library's own that is ordered after the context stream's earlier
+                       work and before its later work; 0: launch kernel by kernel on the context
+                       stream.  Both run the same kernels in the same order (bitwise equal results). */
 } geneo_solve_opts;
 
 typedef struct {
   int32_t iterations;
   double rel_residual;   /* recurrence residual ||r_k|| / ||b|| at exit */
   double solve_ms;       /* device wall time of the iteration */
+  int32_t graph_replays; /* iterations run as graph replays */
 } geneo_solve_info;
 
 /* Solve A x = b from x0 = 0 with PCG preconditioned by pc (or plain CG if pc

@@ -269,7 +269,7 @@ int geneo_apply(geneo_ctx* ctx, const geneo_precond* pc, const double* r, double
 int geneo_solve(geneo_ctx* ctx, const geneo_system* s, const geneo_precond* pc, const double* b, double* x,
                 const geneo_solve_opts* o, geneo_solve_info* info) {
   if (!ctx || !s || !b || !x || !info) return GENEO_EINVAL;
-  geneo_solve_opts def{1e-8, 1000};
+  geneo_solve_opts def{1e-8, 1000, 1};
   const geneo_solve_opts* op = o ? o : &def;
   if (!(op->rtol > 0) || op->maxit < 1) return GENEO_EINVAL;
   std::memset(info, 0, sizeof(*info));

@@ -160,6 +160,11 @@ __global__ __launch_bounds__(256) void k_tile_pattern(const double* __restrict__
   if (threadIdx.x == 0) pat[ti * nb + tj] = (uint8_t)(nz ? 1 : 0);
 }
 
+__global__ void k_copy(int64_t n, const double* __restrict__ x, double* __restrict__ out) {
+  int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i < n) out[i] = x[i];
+}
+
 __global__ void k_axpby(int64_t n, double a, const double* __restrict__ x, double bcoef, const double* __restrict__ y,
                         double* __restrict__ out) {
   int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
@@ -1152,7 +1157,7 @@ static void local_solve(geneo_ctx* ctx, const geneo_precond* pc, double* b) {
   const int64_t len = pc->batch_len;
   const FactorPlan& p32 = pc->n_fallback ? pc->local32 : pc->local;
   double* rhs = pc->w_b3.p;
-  HIP_CHECK(hipMemcpyAsync(rhs, b, sizeof(double) * len, hipMemcpyDeviceToDevice, st));
+  k_copy<<<nblocks(len), 256, 0, st>>>(len, b, rhs);
   if (p32.nmat) solve(p32, pc->fL.p, pc->fLinv.p, b, ctx->d_sync, ctx->d_err, st);
   if (pc->n_fallback)
     solve(pc->local64, pc->dL.p, pc->dLinv.p, b, ctx->d_sync, ctx->d_err, st);
@@ -1244,8 +1249,51 @@ __global__ void k_pcg_shift(double* S) { S[0] = S[3]; }
 
 void pcg(geneo_ctx* ctx, const geneo_system* sys, const geneo_precond* pc, const double* b, double* x,
          const geneo_solve_opts* o, geneo_solve_info* info) {
-  hipStream_t st = ctx->stream;
   const int64_t n = sys->n;
+  // Graph mode runs the solve on a library stream of its own (a capture
+  // cannot use the legacy default stream): it starts after the work queued
+  // on the context stream and the context stream waits for its end.
+  const bool use_graph = o->graph != 0;
+  hipStream_t user = ctx->stream, gs = nullptr;
+  hipEvent_t ev_in = nullptr, ev_out = nullptr;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  struct Restore {
+    geneo_ctx* ctx;
+    hipStream_t user, gs;
+    hipEvent_t a, b;
+    hipGraph_t& g;
+    hipGraphExec_t& e;
+    ~Restore() {
+      if (gs) {
+        hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+        if (hipStreamIsCapturing(gs, &cs) == hipSuccess && cs != hipStreamCaptureStatusNone) {
+          hipGraph_t tmp = nullptr;
+          (void)hipStreamEndCapture(gs, &tmp);
+          if (tmp) (void)hipGraphDestroy(tmp);
+        }
+        (void)hipStreamSynchronize(gs);
+      }
+      if (e) (void)hipGraphExecDestroy(e);
+      if (g) (void)hipGraphDestroy(g);
+      ctx->stream = user;
+      if (gs) (void)hipStreamDestroy(gs);
+      if (a) (void)hipEventDestroy(a);
+      if (b) (void)hipEventDestroy(b);
+    }
+  };
+  if (use_graph) {
+    HIP_CHECK(hipStreamCreateWithFlags(&gs, hipStreamNonBlocking));
+    HIP_CHECK(hipEventCreateWithFlags(&ev_in, hipEventDisableTiming));
+    HIP_CHECK(hipEventCreateWithFlags(&ev_out, hipEventDisableTiming));
+  }
+  Restore restore{ctx, user, gs, ev_in, ev_out, graph, exec};
+  if (use_graph) {
+    HIP_CHECK(hipEventRecord(ev_in, user));
+    HIP_CHECK(hipStreamWaitEvent(gs, ev_in, 0));
+    ctx->stream = gs;
+  }
+  hipStream_t st = ctx->stream;
   DevBuf<double> r, z, p, q, part, S;
   r.alloc(n);
   z.alloc(n);
@@ -1275,28 +1323,46 @@ void pcg(geneo_ctx* ctx, const geneo_system* sys, const geneo_precond* pc, const
       if (pc)
         apply_precond(ctx, pc, in, out);
       else
-        HIP_CHECK(hipMemcpyAsync(out, in, sizeof(double) * n, hipMemcpyDeviceToDevice, st));
+        k_copy<<<nblocks(n), 256, 0, st>>>(n, in, out);
     };
-    precond(r.p, z.p);
-    dot(r.p, z.p, n, part.p, S.p + 3, st);
-    k_pcg_dir<<<nblocks(n), 256, 0, st>>>(n, p.p, z.p, S.p, 1);
-    k_pcg_shift<<<1, 1, 0, st>>>(S.p);
-    for (it = 1; it <= o->maxit; ++it) {
+    // z = M^-1 r, the new direction (end of one iteration) ...
+    auto tail = [&](int first) {
+      precond(r.p, z.p);
+      dot(r.p, z.p, n, part.p, S.p + 3, st);
+      k_pcg_dir<<<nblocks(n), 256, 0, st>>>(n, p.p, z.p, S.p, first);
+      k_pcg_shift<<<1, 1, 0, st>>>(S.p);
+    };
+    // ... then q = A p, the step, ||r||^2 to the host (start of the next)
+    auto head = [&] {
       launch_spmv(sys, p.p, q.p, st);
       dot(p.p, q.p, n, part.p, S.p + 1, st);
       k_pcg_update<<<nblocks(n), 256, 0, st>>>(n, x, r.p, p.p, q.p, S.p);
       dot(r.p, r.p, n, part.p, S.p + 2, st);
       HIP_CHECK(hipMemcpyAsync(h + 2, S.p + 2, sizeof(double), hipMemcpyDeviceToHost, st));
+    };
+    tail(1);
+    for (it = 1; it <= o->maxit; ++it) {
+      if (it == 1 || !use_graph) {
+        if (it > 1) tail(0);
+        head();
+      } else {
+        if (!exec) {
+          // one iteration as a graph: kernel nodes and the copy of ||r||^2
+          HIP_CHECK(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
+          tail(0);
+          head();
+          HIP_CHECK(hipStreamEndCapture(st, &graph));
+          HIP_CHECK(hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0));
+        }
+        HIP_CHECK(hipGraphLaunch(exec, st));
+      }
+      HIP_CHECK(hipGetLastError());
       HIP_CHECK(hipStreamSynchronize(st));
       rel = std::sqrt(h[2]) / bnorm;
       if (std::sqrt(h[2]) <= tol) {
         conv = true;
         break;
       }
-      precond(r.p, z.p);
-      dot(r.p, z.p, n, part.p, S.p + 3, st);
-      k_pcg_dir<<<nblocks(n), 256, 0, st>>>(n, p.p, z.p, S.p, 0);
-      k_pcg_shift<<<1, 1, 0, st>>>(S.p);
     }
   }
   HIP_CHECK(hipEventRecord(ctx->ev[1], st));
@@ -1304,6 +1370,11 @@ void pcg(geneo_ctx* ctx, const geneo_system* sys, const geneo_precond* pc, const
   info->iterations = conv ? (it > o->maxit ? o->maxit : it) : o->maxit;
   if (bnorm == 0.0) info->iterations = 0;
   info->rel_residual = bnorm == 0.0 ? 0.0 : rel;
+  info->graph_replays = exec ? std::max(0, std::min(it, o->maxit) - 1) : 0;
+  if (use_graph) {
+    HIP_CHECK(hipEventRecord(ev_out, st));
+    HIP_CHECK(hipStreamWaitEvent(user, ev_out, 0));
+  }
   check_device_error(ctx);
   if (!conv) throw Error(GENEO_ENOCONV, "PCG did not reach rtol in maxit iterations");
 }

@@ -103,11 +103,12 @@ class TrainInfo(C.Structure):
 
 
 class SolveOpts(C.Structure):
-    _fields_ = [("rtol", C.c_double), ("maxit", C.c_int32)]
+    _fields_ = [("rtol", C.c_double), ("maxit", C.c_int32), ("graph", C.c_int32)]
 
 
 class SolveInfo(C.Structure):
-    _fields_ = [("iterations", C.c_int32), ("rel_residual", C.c_double), ("solve_ms", C.c_double)]
+    _fields_ = [("iterations", C.c_int32), ("rel_residual", C.c_double), ("solve_ms", C.c_double),
+                ("graph_replays", C.c_int32)]
 
 
 _vp = C.c_void_p
@@ -251,8 +252,8 @@ class Context:
     def spmv(self, system, x, y):
         self._check(lib.geneo_spmv(self.h, system.h, _dptr(x), _dptr(y)))
 
-    def solve(self, system, pc, b, x, rtol=1e-8, maxit=1000, allow_noconv=False):
-        o = SolveOpts(float(rtol), int(maxit))
+    def solve(self, system, pc, b, x, rtol=1e-8, maxit=1000, allow_noconv=False, graph=True):
+        o = SolveOpts(float(rtol), int(maxit), 1 if graph else 0)
         info = SolveInfo()
         rc = lib.geneo_solve(self.h, system.h, pc.h if pc is not None else None, _dptr(b), _dptr(x),
                              C.byref(o), C.byref(info))

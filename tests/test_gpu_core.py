@@ -160,3 +160,34 @@ def test_solve_is_deterministic(g):
     i2 = ctx.solve(sysm, pc, b, x2)
     assert i1.iterations == i2.iterations
     assert torch.equal(x1, x2)
+
+
+@pytest.mark.parametrize("cfg,prec", [("1", "fp64"), ("small_channels", "fp64"), ("small_floating", "fp32")])
+def test_pcg_graph_replays_match_eager(g, cfg, prec):
+    """PCG with one iteration captured as a HIP graph and replayed (the
+    library default) against kernel-by-kernel launches: same kernels in the
+    same order, so the iterates are bitwise equal; every replay feeds the
+    next, so a wrong replay would show in x.  Eager work on the context
+    stream runs between two graph solves."""
+    import torch
+    geneo, ctx = g
+    print("graph", cfg, prec, flush=True)
+    w = W.make(int(cfg) if cfg.isdigit() else cfg)
+    sysm, dec = lib_problem(ctx, w)
+    lp = geneo.FP32_REFINE1 if prec == "fp32" else geneo.FP64
+    pc = ctx.setup(sysm, dec, tau=w.tau, nev_max=w.nev_max, local_precision=lp)
+    n = sysm.info().n
+    rng = np.random.default_rng(11)
+    for rep in range(2):
+        b = to_dev(rng.standard_normal(n))
+        xe = torch.zeros(n, dtype=torch.float64, device="cuda:0")
+        xg = torch.full_like(xe, 7.0)
+        ie = ctx.solve(sysm, pc, b, xe, rtol=1e-8, graph=False)
+        z = torch.zeros_like(xe)
+        ctx.apply(pc, b, z)   # eager work on the context stream between the solves
+        ig = ctx.solve(sysm, pc, b, xg, rtol=1e-8, graph=True)
+        torch.cuda.synchronize()
+        assert ie.graph_replays == 0
+        assert ig.iterations == ie.iterations and ig.graph_replays == ig.iterations - 1
+        assert torch.equal(xe, xg)
+        assert torch.isfinite(z).all()
