@@ -271,50 +271,61 @@ __global__ void k_gram_reduce(int m, const int64_t* __restrict__ chunk_off, cons
 
 // ---------------------------------------------------- Rayleigh-Ritz (LDS)
 constexpr int kMaxM = 72;
-constexpr int kLd = kMaxM + 1;   // LDS row pitch bound of the Rayleigh-Ritz matrices
-constexpr int kRRThreads = 1024;   // threads of the Rayleigh-Ritz workgroup (Jacobi rotations in parallel)
+constexpr int kRRThreads = 1024;   // threads of the large Rayleigh-Ritz workgroup (m <= kMaxM)
+constexpr int kRRSmallM = 32;      // bases up to this size run on kRRSmallThreads threads
+constexpr int kRRSmallThreads = 256;
 
 // Jacobi eigendecomposition of the symmetric n x n matrix a (row-major, ld),
-// eigenvectors in v; parallel round-robin ordering, all threads of the block.
-// Each round rotates ne/2 disjoint pairs: one pass applies the rotations to
-// the rows, one to the columns of a and v.  A thread owns the same
-// (pair, index) items in every round (no divisions in the passes); with an
-// odd ld the column pass walks distinct LDS banks.
-constexpr int kJacItems = (kMaxM / 2 * kMaxM + kRRThreads - 1) / kRRThreads;
-
+// eigenvectors in v; parallel round-robin ordering, all NT threads of the
+// block.  Each round rotates ne/2 disjoint pairs (p, q) at once: one pass
+// applies A <- J^T A J on the 2 x 2 blocks (rows of one pair, columns of
+// another; one thread per block, rows rotated first, then columns) and
+// V <- V J on the row pairs of V.  A thread owns the same items in every
+// round (no divisions in the passes); with an odd ld the column walks hit
+// distinct LDS banks.
+template <int NT, int MAXM>
 __device__ void jacobi_eig(double* a, double* v, int n, int ld, double* rot_c, double* rot_s, int* pp, int* qq,
                            double* red) {
+  constexpr int kHalf = MAXM / 2;
+  constexpr int kBlk = (kHalf * kHalf + NT - 1) / NT;
+  constexpr int kVit = (kHalf * MAXM + NT - 1) / NT;
   const int tid = threadIdx.x;
-  for (int idx = tid; idx < n * n; idx += blockDim.x) v[(idx / n) * ld + idx % n] = (idx / n == idx % n) ? 1.0 : 0.0;
+  for (int idx = tid; idx < n * n; idx += NT) v[(idx / n) * ld + idx % n] = (idx / n == idx % n) ? 1.0 : 0.0;
   const int ne = n + (n & 1);   // even number of slots; slot n (if odd) is a dummy
   const int half = ne / 2;
-  int it_slot[kJacItems], it_idx[kJacItems];
+  int b_s1[kBlk], b_s2[kBlk], v_slot[kVit], v_row[kVit];
 #pragma unroll
-  for (int q = 0; q < kJacItems; ++q) {
-    const int e = tid + q * kRRThreads;
-    it_slot[q] = e < half * n ? e / n : -1;
-    it_idx[q] = e < half * n ? e % n : 0;
+  for (int q = 0; q < kBlk; ++q) {
+    const int e = tid + q * NT;
+    b_s1[q] = e < half * half ? e / half : -1;
+    b_s2[q] = e < half * half ? e % half : 0;
+  }
+#pragma unroll
+  for (int q = 0; q < kVit; ++q) {
+    const int e = tid + q * NT;
+    v_slot[q] = e < half * n ? e / n : -1;
+    v_row[q] = e < half * n ? e % n : 0;
   }
   __syncthreads();
   for (int sweep = 0; sweep < 30; ++sweep) {
     // convergence: off-diagonal mass vs diagonal
     double off = 0.0, dia = 0.0;
-    for (int idx = tid; idx < n * n; idx += blockDim.x) {
+    for (int idx = tid; idx < n * n; idx += NT) {
       const int i = idx / n, j = idx % n;
       const double x = a[i * ld + j];
       if (i == j) dia += x * x; else off += x * x;
     }
     red[tid] = off;
-    red[kRRThreads + tid] = dia;
+    red[NT + tid] = dia;
     __syncthreads();
-    for (int s = kRRThreads / 2; s > 0; s >>= 1) {
+    for (int s = NT / 2; s > 0; s >>= 1) {
       if (tid < s) {
         red[tid] += red[tid + s];
-        red[kRRThreads + tid] += red[kRRThreads + tid + s];
+        red[NT + tid] += red[NT + tid + s];
       }
       __syncthreads();
     }
-    const bool done = red[0] <= 1e-30 * red[kRRThreads] || red[0] == 0.0;
+    const bool done = red[0] <= 1e-30 * red[NT] || red[0] == 0.0;
     __syncthreads();
     if (done) break;
     for (int round = 0; round < ne - 1; ++round) {
@@ -344,32 +355,38 @@ __device__ void jacobi_eig(double* a, double* v, int n, int ld, double* rot_c, d
         rot_s[tid] = s;
       }
       __syncthreads();
-      // rows: A <- J^T A
+      // A <- J^T A J: block (rows p1, q1) x (columns p2, q2); the dummy slot
+      // (q = n) has c = 1, s = 0 and no row or column
 #pragma unroll
-      for (int it = 0; it < kJacItems; ++it) {
-        const int slot = it_slot[it];
-        if (slot < 0) continue;
-        const int p = pp[slot], q = qq[slot], col = it_idx[it];
-        if (q >= n) continue;
-        const double c = rot_c[slot], s = rot_s[slot];
-        const double x = a[p * ld + col], y = a[q * ld + col];
-        a[p * ld + col] = c * x - s * y;
-        a[q * ld + col] = s * x + c * y;
+      for (int it = 0; it < kBlk; ++it) {
+        const int s1 = b_s1[it];
+        if (s1 < 0) continue;
+        const int s2 = b_s2[it];
+        const int p1 = pp[s1], q1 = qq[s1], p2 = pp[s2], q2 = qq[s2];
+        const double c1 = rot_c[s1], sn1 = rot_s[s1], c2 = rot_c[s2], sn2 = rot_s[s2];
+        const bool h1 = q1 < n, h2 = q2 < n;
+        const double xpp = a[p1 * ld + p2];
+        const double xpq = h2 ? a[p1 * ld + q2] : 0.0;
+        const double xqp = h1 ? a[q1 * ld + p2] : 0.0;
+        const double xqq = h1 && h2 ? a[q1 * ld + q2] : 0.0;
+        const double rpp = c1 * xpp - sn1 * xqp, rqp = sn1 * xpp + c1 * xqp;
+        const double rpq = c1 * xpq - sn1 * xqq, rqq = sn1 * xpq + c1 * xqq;
+        a[p1 * ld + p2] = c2 * rpp - sn2 * rpq;
+        if (h2) a[p1 * ld + q2] = sn2 * rpp + c2 * rpq;
+        if (h1) {
+          a[q1 * ld + p2] = c2 * rqp - sn2 * rqq;
+          if (h2) a[q1 * ld + q2] = sn2 * rqp + c2 * rqq;
+        }
       }
-      __syncthreads();
-      // columns: A <- A J, V <- V J
+      // V <- V J
 #pragma unroll
-      for (int it = 0; it < kJacItems; ++it) {
-        const int slot = it_slot[it];
+      for (int it = 0; it < kVit; ++it) {
+        const int slot = v_slot[it];
         if (slot < 0) continue;
-        const int p = pp[slot], q = qq[slot], row = it_idx[it];
+        const int p = pp[slot], q = qq[slot], row = v_row[it];
         if (q >= n) continue;
         const double c = rot_c[slot], s = rot_s[slot];
-        double x = a[row * ld + p], y = a[row * ld + q];
-        a[row * ld + p] = c * x - s * y;
-        a[row * ld + q] = s * x + c * y;
-        x = v[row * ld + p];
-        y = v[row * ld + q];
+        const double x = v[row * ld + p], y = v[row * ld + q];
         v[row * ld + p] = c * x - s * y;
         v[row * ld + q] = s * x + c * y;
       }
@@ -383,15 +400,17 @@ __device__ void jacobi_eig(double* a, double* v, int n, int ld, double* rot_c, d
 // column-major).  Inactive subdomains are skipped.
 // svqb != 0: only B-orthonormalise: coef = diag(dsc) U (m x n2, zero columns
 // up to k), theta untouched.
-__global__ __launch_bounds__(kRRThreads) void k_rayleigh_ritz(int m, int k, const double* __restrict__ gram,
+template <int NT, int MAXM>
+__global__ __launch_bounds__(NT) void k_rayleigh_ritz(int m, int k, const double* __restrict__ gram,
                                                        const int32_t* __restrict__ active, double drop,
                                                        double* __restrict__ theta, double* __restrict__ coef,
                                                        int svqb) {
   const int j = blockIdx.x;
   if (active && !active[j]) return;
-  __shared__ double A[kMaxM * kLd], B[kMaxM * kLd], V[kMaxM * kLd];
-  __shared__ double dsc[kMaxM], lam[kMaxM], rc[kMaxM / 2 + 1], rs[kMaxM / 2 + 1], red[2 * kRRThreads];
-  __shared__ int pp[kMaxM / 2 + 1], qq[kMaxM / 2 + 1], keep[kMaxM], order[kMaxM];
+  constexpr int LD = MAXM + 1;   // LDS row pitch bound
+  __shared__ double A[MAXM * LD], B[MAXM * LD], V[MAXM * LD];
+  __shared__ double dsc[MAXM], lam[MAXM], rc[MAXM / 2 + 1], rs[MAXM / 2 + 1], red[2 * NT];
+  __shared__ int pp[MAXM / 2 + 1], qq[MAXM / 2 + 1], keep[MAXM], order[MAXM];
   __shared__ int nk;
   const int tid = threadIdx.x;
   const int mm = m * m;
@@ -399,7 +418,7 @@ __global__ __launch_bounds__(kRRThreads) void k_rayleigh_ritz(int m, int k, cons
   const double* GA = gram + (int64_t)j * 2 * mm;
   const double* GB = GA + mm;
   // symmetrise; diagonal scaling of the B-Gram
-  for (int idx = tid; idx < mm; idx += kRRThreads) {
+  for (int idx = tid; idx < mm; idx += NT) {
     const int a = idx % m, b = idx / m;
     A[a * ld + b] = 0.5 * (GA[a + b * m] + GA[b + a * m]);
     B[a * ld + b] = 0.5 * (GB[a + b * m] + GB[b + a * m]);
@@ -410,7 +429,7 @@ __global__ __launch_bounds__(kRRThreads) void k_rayleigh_ritz(int m, int k, cons
     dsc[tid] = d > 0.0 ? 1.0 / sqrt(d) : 0.0;
   }
   __syncthreads();
-  for (int idx = tid; idx < mm; idx += kRRThreads) {
+  for (int idx = tid; idx < mm; idx += NT) {
     const int a = idx / m, b = idx % m;
     A[a * ld + b] *= dsc[a] * dsc[b];
     B[a * ld + b] *= dsc[a] * dsc[b];
@@ -433,7 +452,7 @@ __global__ __launch_bounds__(kRRThreads) void k_rayleigh_ritz(int m, int k, cons
   __syncthreads();
   int n2 = nk;
   if (!s_fail) {
-    for (int idx = tid; idx < n2 * n2; idx += kRRThreads) {
+    for (int idx = tid; idx < n2 * n2; idx += NT) {
       const int r = idx / n2, c = idx % n2;
       V[r * ld + c] = r >= c ? B[keep[r] * ld + keep[c]] : 0.0;
     }
@@ -447,10 +466,10 @@ __global__ __launch_bounds__(kRRThreads) void k_rayleigh_ritz(int m, int k, cons
       __syncthreads();
       if (s_fail) break;
       const double djj = V[j * ld + j];
-      for (int i = j + 1 + tid; i < n2; i += kRRThreads) V[i * ld + j] /= djj;
+      for (int i = j + 1 + tid; i < n2; i += NT) V[i * ld + j] /= djj;
       __syncthreads();
       const int t = n2 - j - 1;
-      for (int idx = tid; idx < t * t; idx += kRRThreads) {
+      for (int idx = tid; idx < t * t; idx += NT) {
         const int i = j + 1 + idx / t, c = j + 1 + idx % t;
         if (i >= c) V[i * ld + c] -= V[i * ld + j] * V[c * ld + j];
       }
@@ -459,7 +478,7 @@ __global__ __launch_bounds__(kRRThreads) void k_rayleigh_ritz(int m, int k, cons
   }
   if (!s_fail) {
     // X = L^-1 (column c by thread c, forward substitution), U[keep[r]][c] = X[c][r]
-    for (int idx = tid; idx < m * n2; idx += kRRThreads) B[(idx / n2) * ld + idx % n2] = 0.0;
+    for (int idx = tid; idx < m * n2; idx += NT) B[(idx / n2) * ld + idx % n2] = 0.0;
     __syncthreads();
     if (tid < n2) {
       // thread r: column r of X, i.e. row keep[r] of U
@@ -474,7 +493,7 @@ __global__ __launch_bounds__(kRRThreads) void k_rayleigh_ritz(int m, int k, cons
     __syncthreads();
   }
   if (s_fail) {
-    jacobi_eig(B, V, m, ld, rc, rs, pp, qq, red);
+    jacobi_eig<NT, MAXM>(B, V, m, ld, rc, rs, pp, qq, red);
     if (tid < m) lam[tid] = B[tid * ld + tid];
     __syncthreads();
     if (tid == 0) {
@@ -488,7 +507,7 @@ __global__ __launch_bounds__(kRRThreads) void k_rayleigh_ritz(int m, int k, cons
     __syncthreads();
     n2 = nk;
     // U = V[:, keep] / sqrt(lambda) stored in B (m x n2, row-major pitch ld)
-    for (int idx = tid; idx < m * n2; idx += kRRThreads) {
+    for (int idx = tid; idx < m * n2; idx += NT) {
       const int r = idx / n2, c = idx % n2;
       const int col = keep[c];
       B[r * ld + c] = V[r * ld + col] / sqrt(lam[col]);
@@ -496,28 +515,28 @@ __global__ __launch_bounds__(kRRThreads) void k_rayleigh_ritz(int m, int k, cons
     __syncthreads();
   }
   if (svqb) {
-    for (int idx = tid; idx < m * k; idx += kRRThreads) {
+    for (int idx = tid; idx < m * k; idx += NT) {
       const int r = idx % m, c = idx / m;
       coef[(int64_t)j * m * k + (int64_t)c * m + r] = c < n2 ? dsc[r] * B[r * ld + c] : 0.0;
     }
     return;
   }
   // V <- A U (m x n2), then A <- U^T V (n2 x n2)
-  for (int idx = tid; idx < m * n2; idx += kRRThreads) {
+  for (int idx = tid; idx < m * n2; idx += NT) {
     const int r = idx / n2, c = idx % n2;
     double s = 0.0;
     for (int t = 0; t < m; ++t) s += A[r * ld + t] * B[t * ld + c];
     V[r * ld + c] = s;
   }
   __syncthreads();
-  for (int idx = tid; idx < n2 * n2; idx += kRRThreads) {
+  for (int idx = tid; idx < n2 * n2; idx += NT) {
     const int r = idx / n2, c = idx % n2;
     double s = 0.0;
     for (int t = 0; t < m; ++t) s += B[t * ld + r] * V[t * ld + c];
     A[r * ld + c] = s;
   }
   __syncthreads();
-  for (int idx = tid; idx < n2 * n2; idx += kRRThreads) {
+  for (int idx = tid; idx < n2 * n2; idx += NT) {
     const int r = idx / n2, c = idx % n2;
     if (r < c) {
       const double s = 0.5 * (A[r * ld + c] + A[c * ld + r]);
@@ -526,7 +545,7 @@ __global__ __launch_bounds__(kRRThreads) void k_rayleigh_ritz(int m, int k, cons
     }
   }
   __syncthreads();
-  jacobi_eig(A, V, n2, ld, rc, rs, pp, qq, red);
+  jacobi_eig<NT, MAXM>(A, V, n2, ld, rc, rs, pp, qq, red);
   if (tid == 0) {
     for (int i = 0; i < n2; ++i) {
       lam[i] = A[i * ld + i];
@@ -544,7 +563,7 @@ __global__ __launch_bounds__(kRRThreads) void k_rayleigh_ritz(int m, int k, cons
   }
   __syncthreads();
   // coef = diag(dsc) U Y[:, order[0..k)]  (m x k); missing columns -> 0
-  for (int idx = tid; idx < m * k; idx += kRRThreads) {
+  for (int idx = tid; idx < m * k; idx += NT) {
     const int r = idx % m, c = idx / m;
     double s = 0.0;
     if (c < n2) {
@@ -555,6 +574,19 @@ __global__ __launch_bounds__(kRRThreads) void k_rayleigh_ritz(int m, int k, cons
     coef[(int64_t)j * m * k + (int64_t)c * m + r] = s;
   }
   if (tid < k) theta[j * k + tid] = tid < n2 ? lam[order[tid]] : -1e300;
+}
+
+// One Rayleigh-Ritz (or B-orthonormalisation) launch over the N subdomains:
+// bases of up to kRRSmallM vectors on a quarter of the threads (shorter
+// barriers, less LDS), larger ones (m <= kMaxM) on kRRThreads.
+static void rayleigh_ritz(int N, int m, int k, const double* gram, const int32_t* active, double drop, double* theta,
+                          double* coef, int svqb, hipStream_t st) {
+  if (m < 1 || m > kMaxM || k > m) throw Error(GENEO_EUNSUPPORTED, "Rayleigh-Ritz basis size out of range");
+  if (m <= kRRSmallM)
+    k_rayleigh_ritz<kRRSmallThreads, kRRSmallM><<<N, kRRSmallThreads, 0, st>>>(m, k, gram, active, drop, theta, coef,
+                                                                              svqb);
+  else
+    k_rayleigh_ritz<kRRThreads, kMaxM><<<N, kRRThreads, 0, st>>>(m, k, gram, active, drop, theta, coef, svqb);
 }
 
 // Block-batch products.  Segments start at multiples of 128 rows, so a
@@ -742,8 +774,16 @@ struct EigWork {
   DevBuf<double> bval, aval, LB, LBinv, S, Sinv, H, Hinv;
   FactorPlan node;
   DevBuf<unsigned> flags_node, flags_local;
-  DevBuf<double> xrow;   // row-major copy of a block for the sparse products [len x 32]
+  DevBuf<double> xrow;   // row-major copy of a block for the sparse products [len x 32] (gather path)
   int64_t nchunks = 0;
+  // LDS-staged sparse products: per 64-row block the sorted distinct local
+  // columns of its rows, and per nonzero its position in that list
+  DevBuf<int32_t> ublk_ptr, ucols;
+  DevBuf<uint16_t> nz_slot;
+  int u_max = 0;
+  bool spmm_lds = false;
+  std::vector<int32_t> h_ublk_ptr, h_ucols;   // host sources of the uploads (alive until the work ends)
+  std::vector<uint16_t> h_nz_slot;
 };
 
 // Xt[b][q] = X block entry (row b, column q), rows padded to 32 columns;
@@ -863,9 +903,122 @@ __global__ __launch_bounds__(256) void k_spmm_rm(int64_t len, int k, const int32
   }
 }
 
+// Y = [base -] scale .* (A_j X), X in its column-major block layout.  A
+// workgroup owns 64 consecutive batch rows (one subdomain: segments are
+// multiples of 128 rows).  It first copies the X rows of the block's
+// distinct columns into LDS (column by column, reading runs of the sorted
+// column list), then each wavefront takes two rows at a time, one per
+// half-wave, lane q on column q, every nonzero read from LDS; the sums run
+// in the same order as the gather kernel's.  Results are kept in registers,
+// then staged through the same LDS so that Y is written in 64-row runs.
+constexpr int kSpmmThreads = 512;
+constexpr int kSpmmRows = 64 / (kSpmmThreads / 32);   // rows per half-wave
+__global__ __launch_bounds__(kSpmmThreads) void k_spmm_lds(int64_t len, int k, int pitch, const int32_t* __restrict__ row_sub,
+                                                  const int64_t* __restrict__ voff, const int32_t* __restrict__ nloc,
+                                                  const int64_t* __restrict__ rp_off, const int32_t* __restrict__ lrp,
+                                                  const uint16_t* __restrict__ nz_slot,
+                                                  const double* __restrict__ vals,
+                                                  const int32_t* __restrict__ ublk_ptr,
+                                                  const int32_t* __restrict__ ucols, const double* __restrict__ X,
+                                                  const double* __restrict__ base, const double* __restrict__ scale,
+                                                  double* __restrict__ Y) {
+  extern __shared__ double xs[];   // [U * pitch], later the 64 x 33 output tile
+  __shared__ int32_t s_t0[64], s_nnz[64];
+  const int64_t blk = (int64_t)xcd_block();
+  const int64_t b0 = blk * 64;
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const int q = lane & 31, hw = lane >> 5;
+  const int j = row_sub[b0];
+  const int64_t vj = voff[j], ldj = voff[j + 1] - vj, r0 = b0 - vj;
+  const double* Xj = X + vj * k;
+  const int u0 = ublk_ptr[blk], U = ublk_ptr[blk + 1] - u0;
+  {
+    // at most kSpmmThreads distinct columns; eight columns of X in flight per row
+    const bool hA = tid < U;
+    const int64_t cA = hA ? ucols[u0 + tid] : 0;
+    for (int c0 = 0; c0 < k; c0 += 8) {
+      double va[8];
+#pragma unroll
+      for (int i = 0; i < 8; ++i) va[i] = hA && c0 + i < k ? Xj[(int64_t)(c0 + i) * ldj + cA] : 0.0;
+#pragma unroll
+      for (int i = 0; i < 8; ++i)
+        if (hA && c0 + i < k) xs[tid * pitch + c0 + i] = va[i];
+    }
+  }
+  if (tid < 64) {
+    int32_t t0 = 0, nnz = 0;
+    const int64_t r = r0 + tid;
+    if (r < nloc[j]) {
+      const int32_t* rp = lrp + rp_off[j];
+      t0 = rp[r];
+      nnz = rp[r + 1] - t0;
+    }
+    s_t0[tid] = t0;
+    s_nnz[tid] = nnz;
+  }
+  __syncthreads();
+  const bool live = q < k;
+  double res[kSpmmRows];
+#pragma unroll
+  for (int i = 0; i < kSpmmRows; ++i) {
+    const int rl = 2 * kSpmmRows * w + 2 * i + hw;
+    const int32_t t0 = s_t0[rl], nnz = s_nnz[rl];
+    double acc = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+    for (int cb = 0; cb < nnz; cb += 32) {
+      int my_s = 0;
+      double my_v = 0.0;
+      if (cb + q < nnz) {
+        my_s = nz_slot[t0 + cb + q];
+        my_v = vals[t0 + cb + q];
+      }
+      const int n = min(32, nnz - cb);
+      int t = 0;
+      for (; t + 3 < n; t += 4) {
+        const int c0 = __shfl(my_s, t, 32), c1 = __shfl(my_s, t + 1, 32);
+        const int c2 = __shfl(my_s, t + 2, 32), c3 = __shfl(my_s, t + 3, 32);
+        const double v0 = __shfl(my_v, t, 32), v1 = __shfl(my_v, t + 1, 32);
+        const double v2 = __shfl(my_v, t + 2, 32), v3 = __shfl(my_v, t + 3, 32);
+        if (live) {
+          acc += v0 * xs[c0 * pitch + q];
+          a1 += v1 * xs[c1 * pitch + q];
+          a2 += v2 * xs[c2 * pitch + q];
+          a3 += v3 * xs[c3 * pitch + q];
+        }
+      }
+      for (; t < n; ++t) {
+        const int c0 = __shfl(my_s, t, 32);
+        const double v0 = __shfl(my_v, t, 32);
+        if (live) acc += v0 * xs[c0 * pitch + q];
+      }
+    }
+    acc += a1 + a2 + a3;
+    if (scale && nnz > 0) acc *= scale[b0 + rl];
+    res[i] = acc;
+  }
+  __syncthreads();
+#pragma unroll
+  for (int i = 0; i < kSpmmRows; ++i) xs[(2 * kSpmmRows * w + 2 * i + hw) * 33 + q] = res[i];
+  __syncthreads();
+  for (int e = tid; e < 64 * k; e += kSpmmThreads) {
+    const int rl = e & 63, qq = e >> 6;
+    if (b0 + rl >= len) continue;
+    const int64_t oq = vj * k + (int64_t)qq * ldj + r0 + rl;
+    Y[oq] = base ? base[oq] - xs[rl * 33 + qq] : xs[rl * 33 + qq];
+  }
+}
+
 // lvals == nullptr selects the local A_j values
 static void spmm(const geneo_precond* pc, EigWork& w, const double* lvals, const double* X, const double* base,
                  const double* scale, double* Y, hipStream_t st) {
+  if (w.spmm_lds) {
+    const int pitch = w.k | 1;
+    const size_t lds = sizeof(double) * std::max<size_t>((size_t)w.u_max * pitch, 64 * 33);
+    k_spmm_lds<<<(unsigned)(w.len / 64), kSpmmThreads, lds, st>>>(w.len, w.k, pitch, w.row_sub.p, w.voff_d.p, w.nloc.p,
+                                                         w.rp_off.p, w.lrp.p, w.nz_slot.p,
+                                                         lvals ? lvals : w.aval.p, w.ublk_ptr.p, w.ucols.p, X, base,
+                                                         scale, Y);
+    return;
+  }
   if (!w.xrow.p) w.xrow.alloc((size_t)w.len * 32);
   k_block_rowmajor<<<(unsigned)((w.len + 63) / 64), 256, 0, st>>>(w.len, w.k, w.row_sub.p, w.voff_d.p, X, w.xrow.p);
   k_spmm_rm<<<(unsigned)((w.len + 63) / 64), 256, 0, st>>>(w.len, w.k, w.row_sub.p, w.voff_d.p, w.nloc.p,
@@ -941,8 +1094,7 @@ void solve_local_gevps(geneo_ctx* ctx, geneo_precond* pc) {
     rp_off[j + 1] = (int64_t)lrp.size();
   }
   {
-    std::vector<int32_t> hrow(pc->d_lrow.n);
-    HIP_CHECK(hipMemcpy(hrow.data(), pc->d_lrow.p, sizeof(int32_t) * hrow.size(), hipMemcpyDeviceToHost));
+    const std::vector<int32_t>& hrow = pc->h_lrow;
     for (int j = 0; j < N; ++j) {
       const int64_t n = nloc[j];
       int32_t* rp = lrp.data() + rp_off[j];
@@ -1024,6 +1176,53 @@ void solve_local_gevps(geneo_ctx* ctx, geneo_precond* pc) {
   w.nloc.upload(nloc, st);
   w.rp_off.upload(rp_off, st);
   w.lrp.upload(lrp, st);
+  {
+    // distinct local columns of every 64-row block (the LDS-staged products
+    // stage those rows of X once per block)
+    const std::vector<int32_t>& hcol = pc->h_lcol;
+    std::vector<uint16_t> slot(hcol.size(), 0);
+    std::vector<std::vector<int32_t>> ub(N), ucnt(N);
+    std::vector<int> submax(N, 0);
+    parallel_for(N, [&](int j) {
+      const int64_t n = nloc[j];
+      const int64_t nb = (w.voff[j + 1] - w.voff[j]) / 64;
+      std::vector<int32_t> pos(std::max<int64_t>(n, 1), -1), list;
+      const int32_t* rp = lrp.data() + rp_off[j];
+      for (int64_t bb = 0; bb < nb; ++bb) {
+        list.clear();
+        const int64_t ra = bb * 64, rb = std::min<int64_t>(n, ra + 64);
+        for (int64_t r = ra; r < rb; ++r)
+          for (int32_t t = rp[r]; t < rp[r + 1]; ++t)
+            if (pos[hcol[t]] < 0) {
+              pos[hcol[t]] = 0;
+              list.push_back(hcol[t]);
+            }
+        std::sort(list.begin(), list.end());
+        for (size_t u = 0; u < list.size(); ++u) pos[list[u]] = (int32_t)u;
+        for (int64_t r = ra; r < rb; ++r)
+          for (int32_t t = rp[r]; t < rp[r + 1]; ++t) slot[t] = (uint16_t)std::min(pos[hcol[t]], 65535);
+        for (int32_t c : list) pos[c] = -1;
+        ucnt[j].push_back((int32_t)list.size());
+        ub[j].insert(ub[j].end(), list.begin(), list.end());
+        submax[j] = std::max(submax[j], (int)list.size());
+      }
+    });
+    w.u_max = N ? *std::max_element(submax.begin(), submax.end()) : 0;
+    const int pitch = w.k | 1;
+    // dynamic LDS of one workgroup stays within 64 KiB; wider blocks take the gather kernel
+    w.spmm_lds = w.len % 64 == 0 && w.u_max <= kSpmmThreads && (size_t)w.u_max * pitch * sizeof(double) <= 65536;
+    if (w.spmm_lds) {
+      w.h_ublk_ptr.assign(1, 0);
+      for (int j = 0; j < N; ++j) {
+        for (int32_t c : ucnt[j]) w.h_ublk_ptr.push_back(w.h_ublk_ptr.back() + c);
+        w.h_ucols.insert(w.h_ucols.end(), ub[j].begin(), ub[j].end());
+      }
+      w.h_nz_slot = std::move(slot);
+      w.ublk_ptr.upload(w.h_ublk_ptr, st);
+      w.ucols.upload(w.h_ucols, st);
+      w.nz_slot.upload(w.h_nz_slot, st);
+    }
+  }
   w.voff_d.upload(w.voff, st);
   w.poff_d.upload(w.poff, st);
   w.pl.upload(pl, st);
@@ -1141,7 +1340,7 @@ void solve_local_gevps(geneo_ctx* ctx, geneo_precond* pc) {
   auto svqb2 = [&](DevBuf<double>& V, DevBuf<double>& BV, const int32_t* a) {
     for (int t = 0; t < 2; ++t) {
       gram(w, 1, V.p, nullptr, nullptr, BV.p, nullptr, nullptr, BV.p, nullptr, nullptr, part, g, st);
-      k_rayleigh_ritz<<<N, kRRThreads, 0, st>>>(k, k, g.p, a, drop, theta.p, coef.p, 1);
+      rayleigh_ritz(N, k, k, g.p, a, drop, theta.p, coef.p, 1, st);
       k_combine<<<grows, 256, 0, st>>>(w.len, k, k, 0, w.row_sub.p, w.voff_d.p, a, V.p, nullptr, nullptr,
                                             coef.p, V.p, Tv.p);
       k_combine<<<grows, 256, 0, st>>>(w.len, k, k, 0, w.row_sub.p, w.voff_d.p, a, BV.p, nullptr, nullptr,
@@ -1154,7 +1353,7 @@ void solve_local_gevps(geneo_ctx* ctx, geneo_precond* pc) {
   svqb2(X, BX, nullptr);
   apply_atilde(ctx, pc, w, X.p, AX.p, T1.p, T2.p, NT.p);
   gram(w, 1, X.p, nullptr, nullptr, AX.p, nullptr, nullptr, BX.p, nullptr, nullptr, part, g, st);
-  k_rayleigh_ritz<<<N, kRRThreads, 0, st>>>(k, k, g.p, nullptr, drop, theta.p, coef.p, 0);
+  rayleigh_ritz(N, k, k, g.p, nullptr, drop, theta.p, coef.p, 0, st);
   k_combine<<<grows, 256, 0, st>>>(w.len, k, k, 0, w.row_sub.p, w.voff_d.p, nullptr, X.p, nullptr, nullptr,
                                         coef.p, nullptr, Xn.p);
   std::swap(X.p, Xn.p);
@@ -1247,7 +1446,7 @@ void solve_local_gevps(geneo_ctx* ctx, geneo_precond* pc) {
     const int m = nl * k;
     gram(w, nl, X.p, Wb.p, have_p ? P.p : nullptr, AX.p, AW.p, have_p ? AP.p : nullptr, BX.p, BW.p,
          have_p ? BP.p : nullptr, part, g, st);
-    k_rayleigh_ritz<<<N, kRRThreads, 0, st>>>(m, k, g.p, act, drop, theta.p, coef.p, 0);
+    rayleigh_ritz(N, m, k, g.p, act, drop, theta.p, coef.p, 0, st);
     k_combine<<<grows, 256, 0, st>>>(w.len, k, m, 0, w.row_sub.p, w.voff_d.p, act, X.p, Wb.p,
                                           have_p ? P.p : nullptr, coef.p, X.p, Xn.p);
     k_combine<<<grows, 256, 0, st>>>(w.len, k, m, k, w.row_sub.p, w.voff_d.p, act, X.p, Wb.p,

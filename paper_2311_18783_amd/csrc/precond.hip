@@ -886,7 +886,11 @@ void setup_precond(geneo_ctx* ctx, geneo_precond* pc) {
   };
   parallel_for(N, [&](int i) { lnnz_off[i + 1] = local_triplets(i, nullptr, nullptr, nullptr); });
   for (int32_t i = 0; i < N; ++i) lnnz_off[i + 1] += lnnz_off[i];
-  std::vector<int32_t> lrow(lnnz_off[N]), lcol(lnnz_off[N]), lslot(lnnz_off[N]);
+  pc->h_lrow.assign(lnnz_off[N], 0);
+  pc->h_lcol.assign(lnnz_off[N], 0);
+  std::vector<int32_t>& lrow = pc->h_lrow;
+  std::vector<int32_t>& lcol = pc->h_lcol;
+  std::vector<int32_t> lslot(lnnz_off[N]);
   parallel_for(N, [&](int i) {
     local_triplets(i, lrow.data() + lnnz_off[i], lcol.data() + lnnz_off[i], lslot.data() + lnnz_off[i]);
   });
@@ -939,7 +943,17 @@ void setup_precond(geneo_ctx* ctx, geneo_precond* pc) {
     pc->dL.alloc(off);
     pc->dLinv.alloc(inv_off);
   }
-  HIP_CHECK(hipEventRecord(ctx->ev[0], st));
+  // the local phase's events are read only after the eigensolver's host
+  // planning, which so runs while the device factors
+  struct PhaseEvents {
+    hipEvent_t e[3] = {nullptr, nullptr, nullptr};
+    ~PhaseEvents() {
+      for (auto& x : e)
+        if (x) (void)hipEventDestroy(x);
+    }
+  } lev;
+  for (auto& x : lev.e) HIP_CHECK(hipEventCreate(&x));
+  HIP_CHECK(hipEventRecord(lev.e[0], st));
   k_fill_identity_pad<<<fill_grid(pc->local.h_desc), 256, 0, st>>>(pc->local.d_desc.p, fp32 ? nullptr : pc->dL.p,
                                                                    fp32 ? pc->fL.p : nullptr);
   if (!lrow.empty())
@@ -948,7 +962,7 @@ void setup_precond(geneo_ctx* ctx, geneo_precond* pc) {
                                                                    pc->local.d_desc.p, s->d_val.p,
                                                                    fp32 ? nullptr : pc->dL.p, fp32 ? pc->fL.p : nullptr);
   HIP_CHECK(hipGetLastError());
-  HIP_CHECK(hipEventRecord(ctx->ev[1], st));
+  HIP_CHECK(hipEventRecord(lev.e[1], st));
   // work vectors
   pc->w_b1.alloc(voff);
   pc->w_b2.alloc(voff);
@@ -976,10 +990,7 @@ void setup_precond(geneo_ctx* ctx, geneo_precond* pc) {
   } else {
     factor(pc->local, pc->dL.p, pc->dLinv.p, nullptr, 0.0, nullptr, ctx->d_err, st);
   }
-  HIP_CHECK(hipEventRecord(ctx->ev[2], st));
-  pc->info.t_extract_ms = elapsed(ctx, 0, 1);
-  pc->info.t_factor_ms = elapsed(ctx, 1, 2);
-  check_device_error(ctx);
+  HIP_CHECK(hipEventRecord(lev.e[2], st));
 
   pc->w_n1.alloc(n);
   pc->w_n2.alloc(n);
@@ -997,6 +1008,15 @@ void setup_precond(geneo_ctx* ctx, geneo_precond* pc) {
     HIP_CHECK(hipEventRecord(ctx->ev[1], st));
     pc->info.t_gevp_ms = elapsed(ctx, 0, 1);
   }
+  {
+    float ms = 0;
+    HIP_CHECK(hipEventSynchronize(lev.e[2]));
+    HIP_CHECK(hipEventElapsedTime(&ms, lev.e[0], lev.e[1]));
+    pc->info.t_extract_ms = ms;
+    HIP_CHECK(hipEventElapsedTime(&ms, lev.e[1], lev.e[2]));
+    pc->info.t_factor_ms = ms;
+  }
+  check_device_error(ctx);   // a local factor's error surfaces here at the latest
   if (pc->opts.coarse == GENEO_COARSE_NONE) {
     pc->n0 = 0;
     return;
