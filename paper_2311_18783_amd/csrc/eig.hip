@@ -1104,6 +1104,51 @@ void solve_local_gevps(geneo_ctx* ctx, geneo_precond* pc) {
       // rp[r] now = lnnz_off[j] + count of rows < r  (absolute)
     }
   }
+  {
+    // distinct local columns of every 64-row block (the LDS-staged products
+    // stage those rows of X once per block); host work only, planned before
+    // the first upload, which waits for the local factorisation queued ahead
+    const std::vector<int32_t>& hcol = pc->h_lcol;
+    std::vector<uint16_t> slot(hcol.size(), 0);
+    std::vector<std::vector<int32_t>> ub(N), ucnt(N);
+    std::vector<int> submax(N, 0);
+    parallel_for(N, [&](int j) {
+      const int64_t n = nloc[j];
+      const int64_t nb = (w.voff[j + 1] - w.voff[j]) / 64;
+      std::vector<int32_t> pos(std::max<int64_t>(n, 1), -1), list;
+      const int32_t* rp = lrp.data() + rp_off[j];
+      for (int64_t bb = 0; bb < nb; ++bb) {
+        list.clear();
+        const int64_t ra = bb * 64, rb = std::min<int64_t>(n, ra + 64);
+        for (int64_t r = ra; r < rb; ++r)
+          for (int32_t t = rp[r]; t < rp[r + 1]; ++t)
+            if (pos[hcol[t]] < 0) {
+              pos[hcol[t]] = 0;
+              list.push_back(hcol[t]);
+            }
+        std::sort(list.begin(), list.end());
+        for (size_t u = 0; u < list.size(); ++u) pos[list[u]] = (int32_t)u;
+        for (int64_t r = ra; r < rb; ++r)
+          for (int32_t t = rp[r]; t < rp[r + 1]; ++t) slot[t] = (uint16_t)std::min(pos[hcol[t]], 65535);
+        for (int32_t c : list) pos[c] = -1;
+        ucnt[j].push_back((int32_t)list.size());
+        ub[j].insert(ub[j].end(), list.begin(), list.end());
+        submax[j] = std::max(submax[j], (int)list.size());
+      }
+    });
+    w.u_max = N ? *std::max_element(submax.begin(), submax.end()) : 0;
+    const int pitch = w.k | 1;
+    // dynamic LDS of one workgroup stays within 64 KiB; wider blocks take the gather kernel
+    w.spmm_lds = w.len % 64 == 0 && w.u_max <= kSpmmThreads && (size_t)w.u_max * pitch * sizeof(double) <= 65536;
+    if (w.spmm_lds) {
+      w.h_ublk_ptr.assign(1, 0);
+      for (int j = 0; j < N; ++j) {
+        for (int32_t c : ucnt[j]) w.h_ublk_ptr.push_back(w.h_ublk_ptr.back() + c);
+        w.h_ucols.insert(w.h_ucols.end(), ub[j].begin(), ub[j].end());
+      }
+      w.h_nz_slot = std::move(slot);
+    }
+  }
   w.poff.assign(N + 1, 0);
   std::vector<int32_t> pl(N), node_sub, ne_ptr, ne_edge, ena(w.len, -1), enb(w.len, -1);
   std::vector<int8_t> ne_sign;
@@ -1176,52 +1221,10 @@ void solve_local_gevps(geneo_ctx* ctx, geneo_precond* pc) {
   w.nloc.upload(nloc, st);
   w.rp_off.upload(rp_off, st);
   w.lrp.upload(lrp, st);
-  {
-    // distinct local columns of every 64-row block (the LDS-staged products
-    // stage those rows of X once per block)
-    const std::vector<int32_t>& hcol = pc->h_lcol;
-    std::vector<uint16_t> slot(hcol.size(), 0);
-    std::vector<std::vector<int32_t>> ub(N), ucnt(N);
-    std::vector<int> submax(N, 0);
-    parallel_for(N, [&](int j) {
-      const int64_t n = nloc[j];
-      const int64_t nb = (w.voff[j + 1] - w.voff[j]) / 64;
-      std::vector<int32_t> pos(std::max<int64_t>(n, 1), -1), list;
-      const int32_t* rp = lrp.data() + rp_off[j];
-      for (int64_t bb = 0; bb < nb; ++bb) {
-        list.clear();
-        const int64_t ra = bb * 64, rb = std::min<int64_t>(n, ra + 64);
-        for (int64_t r = ra; r < rb; ++r)
-          for (int32_t t = rp[r]; t < rp[r + 1]; ++t)
-            if (pos[hcol[t]] < 0) {
-              pos[hcol[t]] = 0;
-              list.push_back(hcol[t]);
-            }
-        std::sort(list.begin(), list.end());
-        for (size_t u = 0; u < list.size(); ++u) pos[list[u]] = (int32_t)u;
-        for (int64_t r = ra; r < rb; ++r)
-          for (int32_t t = rp[r]; t < rp[r + 1]; ++t) slot[t] = (uint16_t)std::min(pos[hcol[t]], 65535);
-        for (int32_t c : list) pos[c] = -1;
-        ucnt[j].push_back((int32_t)list.size());
-        ub[j].insert(ub[j].end(), list.begin(), list.end());
-        submax[j] = std::max(submax[j], (int)list.size());
-      }
-    });
-    w.u_max = N ? *std::max_element(submax.begin(), submax.end()) : 0;
-    const int pitch = w.k | 1;
-    // dynamic LDS of one workgroup stays within 64 KiB; wider blocks take the gather kernel
-    w.spmm_lds = w.len % 64 == 0 && w.u_max <= kSpmmThreads && (size_t)w.u_max * pitch * sizeof(double) <= 65536;
-    if (w.spmm_lds) {
-      w.h_ublk_ptr.assign(1, 0);
-      for (int j = 0; j < N; ++j) {
-        for (int32_t c : ucnt[j]) w.h_ublk_ptr.push_back(w.h_ublk_ptr.back() + c);
-        w.h_ucols.insert(w.h_ucols.end(), ub[j].begin(), ub[j].end());
-      }
-      w.h_nz_slot = std::move(slot);
-      w.ublk_ptr.upload(w.h_ublk_ptr, st);
-      w.ucols.upload(w.h_ucols, st);
-      w.nz_slot.upload(w.h_nz_slot, st);
-    }
+  if (w.spmm_lds) {
+    w.ublk_ptr.upload(w.h_ublk_ptr, st);
+    w.ucols.upload(w.h_ucols, st);
+    w.nz_slot.upload(w.h_nz_slot, st);
   }
   w.voff_d.upload(w.voff, st);
   w.poff_d.upload(w.poff, st);

@@ -7,6 +7,8 @@
 // extensions R_i^T uses the inverse map (free edge -> batch positions) in a
 // fixed order, so results are bitwise reproducible.
 #include <algorithm>
+#include <chrono>
+#include <cstdio>
 #include <cstdlib>
 #include <cmath>
 #include <exception>
@@ -801,7 +803,21 @@ static void build_snk_host(const geneo_system* s, const geneo_decomp* dec, SnkHo
     }
 }
 
+// Host-side phase clock of the setup (GENEO_VERBOSE set: printed to stderr).
+struct HostClock {
+  bool on = std::getenv("GENEO_VERBOSE") != nullptr;
+  std::chrono::steady_clock::time_point t = std::chrono::steady_clock::now();
+  void mark(const char* what) {
+    if (!on) return;
+    const auto now = std::chrono::steady_clock::now();
+    std::fprintf(stderr, "[setup] %-28s %8.2f ms\n", what,
+                 std::chrono::duration<double, std::milli>(now - t).count());
+    t = now;
+  }
+};
+
 void setup_precond(geneo_ctx* ctx, geneo_precond* pc) {
+  HostClock hc;
   hipStream_t st = ctx->stream;
   const geneo_system* s = pc->sys;
   const geneo_decomp* dec = pc->dec;
@@ -834,6 +850,7 @@ void setup_precond(geneo_ctx* ctx, geneo_precond* pc) {
   pc->info.local_factor_flops = flops;
   pc->local.build(descs, st);
   pc->local.solve_form = false;   // bandwidth-bound local solves: no premultiplied blocks
+  hc.mark("layout + local plan");
   pc->d_flags_local.alloc(flag_off);
   HIP_CHECK(hipMemsetAsync(pc->d_flags_local.p, 0, sizeof(unsigned) * flag_off, st));
 
@@ -860,6 +877,7 @@ void setup_precond(geneo_ctx* ctx, geneo_precond* pc) {
   pc->d_bpou.upload(bpou, st);
   pc->d_inv_ptr.upload(cnt, st);
   pc->d_inv_idx.upload(inv, st);
+  hc.mark("batch maps");
 
   // local CSR triplets: rows/cols local, slot = global CSR position (one
   // pass counts, one fills; subdomains in parallel)
@@ -914,6 +932,7 @@ void setup_precond(geneo_ctx* ctx, geneo_precond* pc) {
   pc->d_lcol.upload(lcol, st);
   pc->d_lslot.upload(lslot, st);
   pc->d_lnnz_off.upload(lnnz_off, st);
+  hc.mark("local triplets");
 
   // the SNK columns depend on the mesh and the decomposition only
   SnkHost snk;
@@ -934,6 +953,7 @@ void setup_precond(geneo_ctx* ctx, geneo_precond* pc) {
     }
   } snk_join{snk_thread};
 
+  hc.mark("snk thread start");
   // ---- extraction + factorisation
   const bool fp32 = pc->precision == GENEO_FP32_REFINE1;
   if (fp32) {
@@ -953,6 +973,7 @@ void setup_precond(geneo_ctx* ctx, geneo_precond* pc) {
     }
   } lev;
   for (auto& x : lev.e) HIP_CHECK(hipEventCreate(&x));
+  hc.mark("local buffers");
   HIP_CHECK(hipEventRecord(lev.e[0], st));
   k_fill_identity_pad<<<fill_grid(pc->local.h_desc), 256, 0, st>>>(pc->local.d_desc.p, fp32 ? nullptr : pc->dL.p,
                                                                    fp32 ? pc->fL.p : nullptr);
@@ -991,6 +1012,7 @@ void setup_precond(geneo_ctx* ctx, geneo_precond* pc) {
     factor(pc->local, pc->dL.p, pc->dLinv.p, nullptr, 0.0, nullptr, ctx->d_err, st);
   }
   HIP_CHECK(hipEventRecord(lev.e[2], st));
+  hc.mark("local factor queued");
 
   pc->w_n1.alloc(n);
   pc->w_n2.alloc(n);
@@ -1007,6 +1029,7 @@ void setup_precond(geneo_ctx* ctx, geneo_precond* pc) {
     solve_local_gevps(ctx, pc);
     HIP_CHECK(hipEventRecord(ctx->ev[1], st));
     pc->info.t_gevp_ms = elapsed(ctx, 0, 1);
+    hc.mark("gevp done");
   }
   {
     float ms = 0;
@@ -1025,6 +1048,7 @@ void setup_precond(geneo_ctx* ctx, geneo_precond* pc) {
   // ---- coarse space: SNK columns R_i^T D_i G_i (one per kept local free node),
   // built on a host thread while the device ran the factorisations and GEVPs
   snk_thread.join();
+  hc.mark("snk thread joined");
   if (snk_err) std::rethrow_exception(snk_err);
   std::vector<int32_t>& zc_ptr = snk.zc_ptr;
   std::vector<int32_t>& zc_row = snk.zc_row;
@@ -1122,13 +1146,17 @@ void setup_precond(geneo_ctx* ctx, geneo_precond* pc) {
     std::vector<uint8_t> pat((size_t)nbc * nbc);
     HIP_CHECK(hipMemcpyAsync(pat.data(), d_pat.p, pat.size(), hipMemcpyDeviceToHost, st));
     HIP_CHECK(hipStreamSynchronize(st));
+    hc.mark("coarse E assembled");
     symbolic_fill(nbc, pat);
+    hc.mark("coarse symbolic fill");
     pc->coarse.build_sparse(cd[0], pat, st);
+    hc.mark("coarse plan");
     pc->info.coarse_factor_flops = pc->coarse.sparse_flops;
     pc->info.coarse_fill = (double)pc->coarse.fill_tiles / ((double)nbc * (nbc + 1) / 2);
   }
   factor(pc->coarse, pc->dE.p, pc->dEinv.p, pc->d_odiag.p, pc->opts.coarse_drop_tol, pc->d_pivrel.p, ctx->d_err, st);
   HIP_CHECK(hipEventRecord(ctx->ev[2], st));
+  hc.mark("coarse factor queued");
   pc->info.t_coarse_build_ms = elapsed(ctx, 0, 1);
   pc->info.t_coarse_factor_ms = elapsed(ctx, 1, 2);
   check_device_error(ctx);
