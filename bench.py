@@ -155,6 +155,9 @@ def summarize(res):
     last = res[-1]
     return {
         "setup_solve_s": mean("setup_solve_s"),
+        "setup_solve_steps_s": [r["setup_solve_s"] for r in res],
+        "gevp_steps_ms": [r["t_gevp_ms"] for r in res],
+        "local_factor_steps_ms": [r["t_factor_ms"] for r in res],
         "phases_ms": {"assemble": mean("assemble_s") * 1e3, "partition_host": mean("partition_s") * 1e3,
                       "setup": mean("setup_s") * 1e3, "solve": mean("solve_s") * 1e3,
                       "extract": mean("t_extract_ms"), "local_factor": mean("t_factor_ms"),

@@ -7,6 +7,7 @@
 #include <atomic>
 #include <cstdint>
 #include <cstdio>
+#include <mutex>
 #include <stdexcept>
 #include <string>
 #include <thread>
@@ -53,29 +54,117 @@ struct Error : std::runtime_error {
 
 inline int64_t round_up(int64_t v, int64_t m) { return (v + m - 1) / m * m; }
 
+// Large device blocks (the dense local and coarse matrices of a setup, 2 GiB
+// and up) are kept after release and handed to a later allocation on the
+// same device that fits (the smallest cached block of 1x to 2x the request),
+// so repeated setups do not map and unmap them again.  A block is handed out
+// after a device synchronisation (all work queued before its release has
+// finished, whatever its stream), as hipFree would have done at release;
+// when hipMalloc fails the cached blocks are freed and the call is retried.
+constexpr size_t kPoolMinBytes = size_t(2) << 30;   // below: hipMalloc / hipFree (no synchronisation at reuse)
+
+struct BlockPool {
+  struct Block {
+    int dev;
+    size_t bytes;
+    void* p;
+  };
+  std::mutex m;
+  std::vector<Block> free_blocks;
+  static BlockPool& get() {
+    static BlockPool* pool = new BlockPool;   // lives until the process ends
+    return *pool;
+  }
+  // a cached block for `bytes` on the current device, or nullptr
+  void* take(size_t bytes, size_t* got) {
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return nullptr;
+    std::lock_guard<std::mutex> g(m);
+    int best = -1;
+    for (int i = 0; i < (int)free_blocks.size(); ++i) {
+      const Block& b = free_blocks[i];
+      if (b.dev == dev && b.bytes >= bytes && b.bytes <= 2 * bytes &&
+          (best < 0 || b.bytes < free_blocks[best].bytes))
+        best = i;
+    }
+    if (best < 0) return nullptr;
+    if (hipDeviceSynchronize() != hipSuccess) return nullptr;
+    void* p = free_blocks[best].p;
+    *got = free_blocks[best].bytes;
+    free_blocks.erase(free_blocks.begin() + best);
+    return p;
+  }
+  void give(void* p, size_t bytes) {
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) {
+      (void)hipFree(p);
+      return;
+    }
+    std::lock_guard<std::mutex> g(m);
+    free_blocks.push_back({dev, bytes, p});
+  }
+  // free every cached block of the current device (before retrying a failed hipMalloc)
+  void trim() {
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return;
+    std::lock_guard<std::mutex> g(m);
+    for (auto it = free_blocks.begin(); it != free_blocks.end();) {
+      if (it->dev == dev) {
+        (void)hipFree(it->p);
+        it = free_blocks.erase(it);
+      } else {
+        ++it;
+      }
+    }
+  }
+};
+
 // Device buffer owned by a handle.
 template <typename T>
 struct DevBuf {
   T* p = nullptr;
   size_t n = 0;
+  size_t cap = 0;   // bytes of the underlying block
   DevBuf() = default;
   DevBuf(const DevBuf&) = delete;
   DevBuf& operator=(const DevBuf&) = delete;
   ~DevBuf() { release(); }
   void release() {
-    if (p) (void)hipFree(p);
+    if (p) {
+      if (cap >= kPoolMinBytes)
+        BlockPool::get().give(p, cap);
+      else
+        (void)hipFree(p);
+    }
     p = nullptr;
     n = 0;
+    cap = 0;
   }
   void alloc(size_t count) {
     release();
     if (count == 0) return;
-    hipError_t e = hipMalloc(&p, count * sizeof(T));
+    const size_t bytes = count * sizeof(T);
+    if (bytes >= kPoolMinBytes) {
+      size_t got = 0;
+      if (void* q = BlockPool::get().take(bytes, &got)) {
+        p = static_cast<T*>(q);
+        n = count;
+        cap = got;
+        return;
+      }
+    }
+    hipError_t e = hipMalloc(&p, bytes);
+    if (e != hipSuccess && bytes >= kPoolMinBytes) {
+      (void)hipGetLastError();
+      BlockPool::get().trim();
+      e = hipMalloc(&p, bytes);
+    }
     if (e != hipSuccess) {
       p = nullptr;
-      throw Error(GENEO_EOOM, "device allocation of " + std::to_string(count * sizeof(T)) + " bytes failed");
+      throw Error(GENEO_EOOM, "device allocation of " + std::to_string(bytes) + " bytes failed");
     }
     n = count;
+    cap = bytes;
   }
   void upload(const std::vector<T>& h, hipStream_t s) {
     alloc(h.size());

@@ -25,7 +25,7 @@ struct geneo_precond {
   // batch-row CSR of the local matrices A_i (columns = batch positions,
   // values = slots of the global CSR), for the FP64 residual of the refinement
   geneo::DevBuf<int64_t> d_brp;
-  geneo::DevBuf<int32_t> d_bcol, d_bslot;
+  geneo::DevBuf<int32_t> d_bcol;                // FP32 path: batch columns of the local triplets
   int64_t batch_len = 0;                     // sum of n_pad
   std::vector<int64_t> voff;                 // batch offset of each subdomain
   geneo::DevBuf<int32_t> d_bmap;             // batch index -> free edge (-1 in pads)

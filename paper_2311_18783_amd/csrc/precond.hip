@@ -602,7 +602,7 @@ static void fp32_probe(geneo_ctx* ctx, geneo_precond* pc, const std::vector<MatD
   // the power iteration only matters for factors that completed
   k_hash_fill<<<nblocks(len), 256, 0, st>>>(len, pc->d_bmap.p, pc->opts.seed ^ 0x5eedull, v);
   for (int it = 0; it < (any_ok ? kPowerSteps : 0); ++it) {
-    k_local_residual<<<nblocks(len), 256, 0, st>>>(len, pc->d_brp.p, pc->d_bcol.p, pc->d_bslot.p, s->d_val.p,
+    k_local_residual<<<nblocks(len), 256, 0, st>>>(len, pc->d_brp.p, pc->d_bcol.p, pc->d_lslot.p, s->d_val.p,
                                                    nullptr, v, nullptr, t);
     solve(pc->local, pc->fL.p, pc->fLinv.p, t, ctx->d_sync, ctx->d_err, st);
     k_axpby<<<nblocks(len), 256, 0, st>>>(len, 1.0, v, 1.0, t, v);
@@ -913,8 +913,9 @@ void setup_precond(geneo_ctx* ctx, geneo_precond* pc) {
     local_triplets(i, lrow.data() + lnnz_off[i], lcol.data() + lnnz_off[i], lslot.data() + lnnz_off[i]);
   });
   pc->lnnz_off = lnnz_off;
-  {
-    // the triplets come row by row: batch-row pointers, batch columns
+  if (pc->precision == GENEO_FP32_REFINE1) {
+    // FP64 residuals of the refinement step: the triplets come row by row,
+    // batch-row pointers and batch columns (slots are d_lslot)
     std::vector<int64_t> brp(voff + 1, 0);
     std::vector<int32_t> bcol(lrow.size());
     parallel_for(N, [&](int i) {
@@ -926,7 +927,6 @@ void setup_precond(geneo_ctx* ctx, geneo_precond* pc) {
     for (int64_t r = 0; r < voff; ++r) brp[r + 1] += brp[r];
     pc->d_brp.upload(brp, st);
     pc->d_bcol.upload(bcol, st);
-    pc->d_bslot.upload(lslot, st);
   }
   pc->d_lrow.upload(lrow, st);
   pc->d_lcol.upload(lcol, st);
@@ -1211,7 +1211,7 @@ static void local_solve(geneo_ctx* ctx, const geneo_precond* pc, double* b) {
     solve(pc->local64, pc->dL.p, pc->dLinv.p, b, ctx->d_sync, ctx->d_err, st);
   if (!p32.nmat) return;
   // rhs <- rhs - A_i yhat on the refined subdomains (0 elsewhere), then the correction
-  k_local_residual<<<nblocks(len), 256, 0, st>>>(len, pc->d_brp.p, pc->d_bcol.p, pc->d_bslot.p, pc->sys->d_val.p, rhs,
+  k_local_residual<<<nblocks(len), 256, 0, st>>>(len, pc->d_brp.p, pc->d_bcol.p, pc->d_lslot.p, pc->sys->d_val.p, rhs,
                                                  b, pc->n_fallback ? pc->d_refine.p : nullptr, rhs);
   solve(p32, pc->fL.p, pc->fLinv.p, rhs, ctx->d_sync, ctx->d_err, st);
   k_axpby<<<nblocks(len), 256, 0, st>>>(len, 1.0, b, 1.0, rhs, b);
