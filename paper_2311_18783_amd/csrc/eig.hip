@@ -1348,8 +1348,8 @@ void solve_local_gevps(geneo_ctx* ctx, geneo_precond* pc) {
                                             coef.p, V.p, Tv.p);
       k_combine<<<grows, 256, 0, st>>>(w.len, k, k, 0, w.row_sub.p, w.voff_d.p, a, BV.p, nullptr, nullptr,
                                             coef.p, BV.p, Tb.p);
-      std::swap(V.p, Tv.p);
-      std::swap(BV.p, Tb.p);
+      V.swap(Tv);
+      BV.swap(Tb);
     }
   };
   bmul(X.p, BX.p);
@@ -1359,7 +1359,7 @@ void solve_local_gevps(geneo_ctx* ctx, geneo_precond* pc) {
   rayleigh_ritz(N, k, k, g.p, nullptr, drop, theta.p, coef.p, 0, st);
   k_combine<<<grows, 256, 0, st>>>(w.len, k, k, 0, w.row_sub.p, w.voff_d.p, nullptr, X.p, nullptr, nullptr,
                                         coef.p, nullptr, Xn.p);
-  std::swap(X.p, Xn.p);
+  X.swap(Xn);
   // products are recomputed from the basis after every update (tracking them
   // through the Rayleigh-Ritz coefficients drifts once the basis becomes
   // ill-conditioned near convergence)
@@ -1454,8 +1454,8 @@ void solve_local_gevps(geneo_ctx* ctx, geneo_precond* pc) {
                                           have_p ? P.p : nullptr, coef.p, X.p, Xn.p);
     k_combine<<<grows, 256, 0, st>>>(w.len, k, m, k, w.row_sub.p, w.voff_d.p, act, X.p, Wb.p,
                                           have_p ? P.p : nullptr, coef.p, have_p ? P.p : nullptr, Pn.p);
-    std::swap(X.p, Xn.p);
-    std::swap(P.p, Pn.p);
+    X.swap(Xn);
+    P.swap(Pn);
     apply_atilde(ctx, pc, w, X.p, AX.p, T1.p, T2.p, NT.p);
     bmul(X.p, BX.p);
     have_p = true;

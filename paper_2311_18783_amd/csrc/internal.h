@@ -54,14 +54,15 @@ struct Error : std::runtime_error {
 
 inline int64_t round_up(int64_t v, int64_t m) { return (v + m - 1) / m * m; }
 
-// Large device blocks (the dense local and coarse matrices of a setup, 2 GiB
-// and up) are kept after release and handed to a later allocation on the
-// same device that fits (the smallest cached block of 1x to 2x the request),
-// so repeated setups do not map and unmap them again.  A block is handed out
-// after a device synchronisation (all work queued before its release has
-// finished, whatever its stream), as hipFree would have done at release;
-// when hipMalloc fails the cached blocks are freed and the call is retried.
-constexpr size_t kPoolMinBytes = size_t(2) << 30;   // below: hipMalloc / hipFree (no synchronisation at reuse)
+// Large device blocks (64 MiB and up: dense local, Neumann and coarse
+// matrices, the eigensolver's block vectors, coarse temporaries) are kept
+// after release and handed to a later allocation on the same device that
+// fits (the smallest cached block of 1x to 2x the request), so repeated
+// setups do not map and unmap them again.  Release synchronises the device
+// first, as hipFree would have done: work queued on any stream before the
+// release has finished before the block is handed out again.  When
+// hipMalloc fails the cached blocks are freed and the call is retried.
+constexpr size_t kPoolMinBytes = size_t(64) << 20;
 
 struct BlockPool {
   struct Block {
@@ -88,7 +89,6 @@ struct BlockPool {
         best = i;
     }
     if (best < 0) return nullptr;
-    if (hipDeviceSynchronize() != hipSuccess) return nullptr;
     void* p = free_blocks[best].p;
     *got = free_blocks[best].bytes;
     free_blocks.erase(free_blocks.begin() + best);
@@ -96,7 +96,7 @@ struct BlockPool {
   }
   void give(void* p, size_t bytes) {
     int dev = 0;
-    if (hipGetDevice(&dev) != hipSuccess) {
+    if (hipGetDevice(&dev) != hipSuccess || hipDeviceSynchronize() != hipSuccess) {
       (void)hipFree(p);
       return;
     }
@@ -129,6 +129,13 @@ struct DevBuf {
   DevBuf(const DevBuf&) = delete;
   DevBuf& operator=(const DevBuf&) = delete;
   ~DevBuf() { release(); }
+  // exchange buffers (pointer, count and block size together: a pooled
+  // block may be larger than its request)
+  void swap(DevBuf& o) {
+    std::swap(p, o.p);
+    std::swap(n, o.n);
+    std::swap(cap, o.cap);
+  }
   void release() {
     if (p) {
       if (cap >= kPoolMinBytes)
