@@ -250,3 +250,39 @@ def test_fp32_refined_two_level_pcg(stiff):
         x, it[prec], _ = geneo.pcg(s.A, b, tl.apply, rtol=1e-8)
         assert np.linalg.norm(b - s.A @ x) <= 1.01e-8 * np.linalg.norm(b)
     assert it["fp32_refine1"] <= it["fp64"] + 1
+
+
+def test_node_gradient_rayleigh_quotient_bounds_scaled_condition(tiny, floating):
+    """The FP32 conditioning check's premise, on the oracle's matrices: for a
+    free node whose edges all lie in Omega_i, v = G e_node is annihilated by
+    the curl-curl part (K G = 0), so v^T A_i v = gamma v^T M v, and
+    q = v^T A_i v / v^T diag(A_i) v bounds the smallest eigenvalue of
+    D^-1/2 A_i D^-1/2 from above (a Rayleigh quotient); that matrix has a
+    unit diagonal, so its largest eigenvalue is >= 1 and 1/q <= its
+    condition number.  The bound is tight within a factor ~50 here."""
+    for s, dec in (tiny, floating):
+        A = s.A.tocsr()
+        G = s.G.tocsc()
+        for i in range(dec.N):
+            d = np.asarray(dec.dofs[i])
+            inside = np.zeros(s.n, bool)
+            inside[d] = True
+            Ai = A[d][:, d].toarray()
+            dg = np.diag(Ai)
+            r = 1.0 / np.sqrt(dg)
+            ev = np.linalg.eigvalsh(Ai * r[:, None] * r[None, :])
+            kappa = ev[-1] / ev[0]
+            qmin = np.inf
+            for c in np.unique(G[d].nonzero()[1]):
+                rows = G[:, c].nonzero()[0]
+                if not inside[rows].all():
+                    continue
+                v = G[:, c].toarray().ravel()
+                assert abs(v @ (s.K @ v)) <= 1e-12 * (np.abs(v) @ (abs(s.K) @ np.abs(v)))
+                assert np.isclose(v @ (A @ v), s.gamma * (v @ (s.M @ v)), rtol=1e-10)
+                q = (v @ (A @ v)) / (v @ (A.diagonal() * v))
+                assert q >= ev[0] * (1 - 1e-10)
+                qmin = min(qmin, q)
+            assert np.isfinite(qmin)
+            assert 1.0 / qmin <= kappa * (1 + 1e-10)
+            assert kappa <= 50.0 / qmin
