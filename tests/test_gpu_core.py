@@ -220,3 +220,29 @@ def test_setup_on_reused_blocks_is_bitwise_identical(g):
     assert (i1.n0, i1.n0_rank, i1.n_geneo) == (i2.n0, i2.n0_rank, i2.n_geneo)
     assert torch.equal(z1, z2)
     del pc
+
+
+def test_pcg_maxit_exit_in_graph_mode(g):
+    """PCG stopped by maxit: both launch modes report no convergence with the
+    same 3 iterations and bitwise equal iterates, and a full solve on the
+    same context afterwards (its stream restored) converges."""
+    import torch
+    geneo, ctx = g
+    w = W.make(1)
+    sysm, dec = lib_problem(ctx, w)
+    pc = ctx.setup(sysm, dec, coarse=geneo.COARSE_SNK)
+    n = sysm.info().n
+    b = to_dev(w.rhs(n))
+    xs = []
+    for graph in (False, True):
+        x = torch.zeros(n, dtype=torch.float64, device="cuda:0")
+        si = ctx.solve(sysm, pc, b, x, rtol=1e-14, maxit=3, allow_noconv=True, graph=graph)
+        assert si.iterations == 3 and si.rel_residual > 1e-14
+        assert si.graph_replays == (2 if graph else 0)
+        xs.append(x)
+    torch.cuda.synchronize()
+    assert torch.equal(xs[0], xs[1])
+    x = torch.zeros(n, dtype=torch.float64, device="cuda:0")
+    si = ctx.solve(sysm, pc, b, x, rtol=1e-8)
+    torch.cuda.synchronize()
+    assert si.rel_residual <= 1e-8
