@@ -194,7 +194,8 @@ def main():
         copy_calibration(a.copy_calibration)
         return
     if a.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1", "n_gpus": a.gpus}))
+        print(json.dumps({"error": "single-GPU benchmark: the batched per-subdomain work runs on one GPU; "
+                                   "--gpus must be 1", "n_gpus": a.gpus}))
         sys.exit(2)
     import torch
     from paper_2311_18783_amd import geneo
