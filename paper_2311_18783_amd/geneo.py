@@ -253,6 +253,11 @@ class Context:
         self._check(lib.geneo_spmv(self.h, system.h, _dptr(x), _dptr(y)))
 
     def solve(self, system, pc, b, x, rtol=1e-8, maxit=1000, allow_noconv=False, graph=True):
+        """geneo_solve: PCG from x = 0 (b, x: float64 device tensors of length n).
+        graph=True replays one captured iteration as a HIP graph from the
+        second iteration on; graph=False launches kernel by kernel (same
+        kernels, bitwise equal iterates).  allow_noconv returns the info of a
+        run stopped by maxit instead of raising."""
         o = SolveOpts(float(rtol), int(maxit), 1 if graph else 0)
         info = SolveInfo()
         rc = lib.geneo_solve(self.h, system.h, pc.h if pc is not None else None, _dptr(b), _dptr(x),
