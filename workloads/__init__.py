@@ -262,6 +262,19 @@ def make(cfg, family=0, **over):
         w = Workload("beam128_slabs", mesh, mu, np.ones(T), 1e-6,
                      dirichlet_flags(mesh["bface_tag"], "all"),
                      {"kind": "rcb", "nparts": 256, "jitter": jit}, 1, seed=1005)
+    elif isinstance(cfg, str) and cfg.startswith("beam") and cfg[4:].isdigit():
+        # The paper's weak-scaling beam (Section 5, influence of geometry):
+        # N/2 x 1 x 1 with h = 1/16 (8N x 16 x 16 hexes), N strip subdomains
+        # along the length, one overlap layer, mu = eps = 1, gamma = 1e-3,
+        # Dirichlet on all faces (rule "mixed": Neumann on two opposing
+        # lateral faces instead).
+        N = int(cfg[4:])
+        dims = (8 * N, 16, 16)
+        mesh = hex_box_mesh(dims, h=1.0 / 16)
+        T = mesh["tets"].shape[0]
+        w = Workload(f"beam{N}_strips", mesh, np.ones(T), np.ones(T), 1e-3,
+                     dirichlet_flags(mesh["bface_tag"], "all"),
+                     {"kind": "box", "p": (N, 1, 1)}, 1, seed=3000 + N)
     elif cfg == "small_channels":
         # A small heterogeneous case whose GenEO space is not empty.
         dims = (8, 8, 8)
