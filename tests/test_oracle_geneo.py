@@ -286,3 +286,58 @@ def test_node_gradient_rayleigh_quotient_bounds_scaled_condition(tiny, floating)
             assert np.isfinite(qmin)
             assert 1.0 / qmin <= kappa * (1 + 1e-10)
             assert kappa <= 50.0 / qmin
+
+
+def test_gmres_minimal_residual_and_special_cases():
+    """Right-preconditioned GMRES (the paper's solver): on a non-symmetric
+    system it reaches the direct solution within n steps, its residual
+    history never increases (minimal residual over a growing Krylov space),
+    the residual it reads from the rotations is the true ||b - A x||; the
+    exact inverse as preconditioner solves in one step; restarted, it
+    reaches the same solution."""
+    rng = np.random.default_rng(3)
+    n = 40
+    A = 8.0 * np.eye(n) + rng.standard_normal((n, n))
+    b = rng.standard_normal(n)
+    xs = np.linalg.solve(A, b)
+    x, it, hist = geneo.gmres(A, b, rtol=1e-12)
+    assert it <= n
+    assert all(hist[k + 1] <= hist[k] * (1 + 1e-12) for k in range(len(hist) - 1))
+    true = np.linalg.norm(b - A @ x) / np.linalg.norm(b)
+    assert abs(true - hist[-1]) <= 1e-3 * hist[-1] + 1e-15
+    assert np.linalg.norm(x - xs) <= 1e-10 * np.linalg.norm(xs)
+    Ainv = np.linalg.inv(A)
+    x1, it1, _ = geneo.gmres(A, b, M=lambda v: Ainv @ v, rtol=1e-10)
+    assert it1 == 1 and np.linalg.norm(x1 - xs) <= 1e-10 * np.linalg.norm(xs)
+    x2, it2, _ = geneo.gmres(A, b, rtol=1e-12, restart=7, maxit=2000)
+    assert it2 > it and np.linalg.norm(x2 - xs) <= 1e-10 * np.linalg.norm(xs)
+
+
+def test_restricted_weights(tiny):
+    """weight="pou" puts D_i into the one-level sum: the operator is no longer
+    symmetric (with identity weights it is); with a single subdomain
+    (D = I, A_1 = A) it is A^-1 itself and GMRES stops after one step;
+    as right preconditioner of the two-level method it reaches the direct
+    solution on the tiny case."""
+    s, dec = tiny
+    n = s.n
+    E = np.eye(n)
+    sym = geneo.TwoLevel(dec, variant="as")
+    ras = geneo.TwoLevel(dec, variant="as", weight="pou")
+    Ms = np.column_stack([sym.one_level(e) for e in E])
+    Mr = np.column_stack([ras.one_level(e) for e in E])
+    assert np.abs(Ms - Ms.T).max() <= 1e-10 * np.abs(Ms).max()
+    assert np.abs(Mr - Mr.T).max() >= 1e-3 * np.abs(Mr).max()
+    s1, dec1 = _case((4, 4, 4), (1, 1, 1))
+    one = geneo.TwoLevel(dec1, variant="as", weight="pou")
+    b = np.random.default_rng(4).standard_normal(s1.n)
+    xs = spla.splu(s1.A.tocsc()).solve(b)
+    assert np.linalg.norm(one.one_level(b) - xs) <= 1e-10 * np.linalg.norm(xs)
+    x, it, _ = geneo.gmres(s1.A, b, M=one.apply, rtol=1e-10)
+    assert it == 1 and np.linalg.norm(x - xs) <= 1e-9 * np.linalg.norm(xs)
+    two = geneo.TwoLevel(dec, weight="pou")
+    b = np.random.default_rng(5).standard_normal(n)
+    xs = spla.splu(s.A.tocsc()).solve(b)
+    x, it, hist = geneo.gmres(s.A, b, M=two.apply, rtol=1e-10)
+    assert hist[-1] <= 1e-10 and it < n
+    assert np.linalg.norm(x - xs) <= 1e-7 * np.linalg.norm(xs)
