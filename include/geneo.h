@@ -46,7 +46,7 @@ typedef struct geneo_system geneo_system;
 typedef struct geneo_decomp geneo_decomp;
 typedef struct geneo_precond geneo_precond;
 
-/* Tetrahedral mesh (Section 1: Omega with boundary Gamma; Section 5:
+/* Tetrahedral mesh (Section 1: Omega with boundary Gamma; Section 4, Numerical results:
  * Cartesian meshes).  Cells group tets (e.g. the 6 tets of a hex); the
  * overlap of the decomposition is grown by whole cells. */
 typedef struct {
@@ -108,7 +108,7 @@ typedef struct {
   int32_t nparts;            /* RCB: number of parts */
   const double* rcb_jitter;  /* RCB: [nparts-1] host, relative shift of each split, preorder */
   const int32_t* part_of_cell; /* EXPLICIT: [n_cells] host */
-  int32_t overlap;           /* layers of vertex-adjacent cells added (Section 5: one layer) */
+  int32_t overlap;           /* layers of vertex-adjacent cells added (Section 4, Numerical results: one layer) */
 } geneo_partition_opts;
 
 typedef struct {
@@ -141,7 +141,7 @@ typedef enum { GENEO_FP64 = 0, GENEO_FP32_REFINE1 = 1 } geneo_precision;
 typedef enum { GENEO_COARSE_SNK_GENEO = 0, GENEO_COARSE_SNK = 1, GENEO_COARSE_NONE = 2 } geneo_coarse_kind;
 
 typedef struct {
-  double tau;               /* GenEO threshold, keep lambda > tau (Section 5: 10) */
+  double tau;               /* GenEO threshold, keep lambda > tau (Section 4, Numerical results: 10) */
   int32_t nev_max;          /* at most this many eigenvectors per subdomain */
   int32_t coarse;           /* geneo_coarse_kind */
   int32_t local_precision;  /* geneo_precision of the local factors and solves */

@@ -15,8 +15,13 @@ fusion or reordering beyond the definitions.
 
 Pins (tests/test_oracle_*.py): K G = 0, element identities for constant and
 linear fields, first-order convergence to a manufactured solution, the
-paper's dof / NK / SNK counts, the partition-of-unity identity, projector
-identities, the GEVP bound lemma, the condition-number theorem, brute-force
-dense cross-checks on tiny meshes.  Parity unpinned: none of the functions
-below; the MLP (oracle/mlp.py) is pinned by central finite differences.
+paper's dof / NK / SNK counts (the SNK count through the overlapping
+subdomains of Decomposition), hand-computed recursive-bisection parts,
+overlap layers and smooth partition-of-unity values, the partition-of-unity
+identity, k0 / k1 on geometries where they follow by hand, projector
+identities, the GEVP bound lemma, the condition-number theorem (spectrum of
+M^-1 A in [1/81, 8] on the 8^3 cube), brute-force dense cross-checks on tiny
+meshes, GMRES against its defining minimal-residual property.  Parity
+unpinned: none of the functions below; the MLP (oracle/mlp.py) has no
+counterpart in the paper and is pinned by central finite differences.
 """

@@ -7,7 +7,7 @@ zero; the algebraic partition of unity sum_i R_i^T D_i R_i = I
 (eq. (PoU)); the Dirichlet matrix A_i = R_i A R_i^T (after eq. (AS)); the
 Neumann matrix A_i^Neu = the bilinear form integrated over Omega_i only,
 with the global boundary conditions kept on the part of the boundary of
-Omega_i that lies on the boundary of Omega.  Section 5: one layer of
+Omega_i that lies on the boundary of Omega.  Section 4 (Numerical results): one layer of
 elements is added around each non-overlapping subdomain; the paper's
 elements are hexes of a Cartesian mesh, so one layer = every hex that
 shares a vertex with the subdomain.  G_i = R_i G (Definition "Split

@@ -5,7 +5,7 @@ Paper passages: the boundary value problem and the discrete system
 A U = (K + gamma M) U = f (Section 1, eq. (positivemaxwell) and
 eq. (discretemaxwell)); the bilinear form a(u,v) (Section 2,
 eq. (bilinearformposmax)); lowest-order edge elements on a Cartesian mesh
-(Section 5); G is the "gradient matrix", the exact null space of the discrete
+(Section 4, Numerical results); G is the "gradient matrix", the exact null space of the discrete
 curl-curl operator (Section 1, the AMS formula).  The paper does not print
 the element formulas; the ones below are the textbook Whitney-form ones:
   w_ab = l_a grad l_b - l_b grad l_a,  curl w_ab = 2 grad l_a x grad l_b,

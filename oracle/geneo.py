@@ -8,7 +8,7 @@ Paper passages:
   * the generalised eigenproblem (I - xi_j^T) D_j A_j D_j (I - xi_j) V =
     lambda A_j^Neu V, eigenvectors with lambda > tau, coarse vectors
     R_j^T D_j (I - xi_j) V (Section 3.2, GEVP "tauthresholdAS",
-    eq. (eigAtildeBAS)); tau = 10 (Section 5);
+    eq. (eigAtildeBAS)); tau = 10 (Section 4, Numerical results);
   * the classical GenEO pencil D_j A_j D_j V = lambda A_j^Neu V (Section 3.2,
     eq. (eigGenEOClassis)) for comparison;
   * the split near-kernel space V_G = span(R_i^T D_i G_i) (Definition
@@ -28,7 +28,7 @@ rho(I - Ahat^-1 A_i) < 1).  The triangular solves use the FP32 factor with
 FP64 vectors.
 
 Readings: the paper solves with right-preconditioned GMRES at rtol 1e-6
-(Section 5, with the reason that the residual is then minimised in the same
+(Section 4, Numerical results, with the reason that the residual is then minimised in the same
 norm whatever the preconditioner); `gmres` below is that solver.  The
 measured path runs preconditioned conjugate gradients (the preconditioner
 is symmetric positive definite) from x0 = 0, stopping at the first iterate
@@ -218,7 +218,8 @@ class TwoLevel:
         for i in range(len(self.local_L)):
             d = self.dec.dofs[i]
             yi = self.local_solve(i, r[d])
-            y[d] += self.dec.D[i] * yi if self.weight == "pou" else yi
+            Di = self.dec.D[i] if yi.ndim == 1 else self.dec.D[i][:, None]
+            y[d] += Di * yi if self.weight == "pou" else yi
         return y
 
     def fp32_rho(self, i):
@@ -236,10 +237,15 @@ class TwoLevel:
         c2 = self.coarse_solve(self.AZ.T @ y)
         return self.Z @ c + y - self.Z @ c2
 
-    def matrix(self):
-        """Dense M^-1 (tiny cases only)."""
+    def matrix(self, block=512):
+        """Dense M^-1, applied to blocks of unit vectors (small cases only)."""
         n = self.dec.sys.n
-        return np.column_stack([self.apply(e) for e in np.eye(n)])
+        out = np.empty((n, n))
+        for j in range(0, n, block):
+            e = np.zeros((n, min(block, n - j)))
+            e[np.arange(j, j + e.shape[1]), np.arange(e.shape[1])] = 1.0
+            out[:, j:j + e.shape[1]] = self.apply(e)
+        return out
 
 
 def pcg(A, b, M=None, rtol=1e-8, maxit=1000):
@@ -269,7 +275,7 @@ def pcg(A, b, M=None, rtol=1e-8, maxit=1000):
 
 
 def gmres(A, b, M=None, rtol=1e-6, maxit=1000, restart=None):
-    """Right-preconditioned GMRES from x0 = 0 (the paper's solver, Section 5):
+    """Right-preconditioned GMRES from x0 = 0 (the paper's solver, Section 4, Numerical results):
     Arnoldi with modified Gram-Schmidt on A M^-1, Givens rotations on the
     Hessenberg matrix, x = M^-1 V y.  With right preconditioning the
     minimised quantity is the true residual ||b - A x||_2, so the stop test

@@ -75,6 +75,9 @@ void geneo_destroy(geneo_ctx* ctx) {
   if (ctx->h_err) (void)hipHostFree(ctx->h_err);
   if (ctx->d_sync) (void)hipFree(ctx->d_sync);
   if (ctx->own_stream && ctx->stream) (void)hipStreamDestroy(ctx->stream);
+  // cached large blocks of this device go back to the device (blocks still
+  // held by live handles of other contexts are not cached, so not touched)
+  BlockPool::get().trim();
   delete ctx;
 }
 
@@ -273,7 +276,10 @@ int geneo_solve(geneo_ctx* ctx, const geneo_system* s, const geneo_precond* pc, 
   const geneo_solve_opts* op = o ? o : &def;
   if (!(op->rtol > 0) || op->maxit < 1) return GENEO_EINVAL;
   std::memset(info, 0, sizeof(*info));
-  return guarded(ctx, [&] { pcg(ctx, s, pc, b, x, op, info); });
+  return guarded(ctx, [&] {
+    if (pc && pc->sys != s) throw Error(GENEO_EINVAL, "the preconditioner was built on another system");
+    pcg(ctx, s, pc, b, x, op, info);
+  });
 }
 
 int geneo_potrf_batched(geneo_ctx* ctx, int32_t batch, const int32_t* n_host, const int64_t* off_host, void* A,

@@ -1294,6 +1294,9 @@ __global__ void k_pcg_dir(int64_t n, double* __restrict__ p, const double* __res
   p[i] = first ? z[i] : z[i] + (S[3] / S[0]) * p[i];
 }
 __global__ void k_pcg_shift(double* S) { S[0] = S[3]; }
+// the device error record's status next to ||r||^2, so that one copy per
+// iteration brings both to the host
+__global__ void k_pcg_status(const DevErr* __restrict__ err, double* S) { S[5] = (double)err->code; }
 
 void pcg(geneo_ctx* ctx, const geneo_system* sys, const geneo_precond* pc, const double* b, double* x,
          const geneo_solve_opts* o, geneo_solve_info* info) {
@@ -1386,7 +1389,8 @@ void pcg(geneo_ctx* ctx, const geneo_system* sys, const geneo_precond* pc, const
       dot(p.p, q.p, n, part.p, S.p + 1, st);
       k_pcg_update<<<nblocks(n), 256, 0, st>>>(n, x, r.p, p.p, q.p, S.p);
       dot(r.p, r.p, n, part.p, S.p + 2, st);
-      HIP_CHECK(hipMemcpyAsync(h + 2, S.p + 2, sizeof(double), hipMemcpyDeviceToHost, st));
+      k_pcg_status<<<1, 1, 0, st>>>(ctx->d_err, S.p);
+      HIP_CHECK(hipMemcpyAsync(h + 2, S.p + 2, 4 * sizeof(double), hipMemcpyDeviceToHost, st));
     };
     tail(1);
     for (it = 1; it <= o->maxit; ++it) {
@@ -1406,6 +1410,9 @@ void pcg(geneo_ctx* ctx, const geneo_system* sys, const geneo_precond* pc, const
       }
       HIP_CHECK(hipGetLastError());
       HIP_CHECK(hipStreamSynchronize(st));
+      // a failed device-side wait (or any kernel error) stops the iteration
+      // at once instead of iterating on invalid vectors
+      if (h[5] != 0.0) break;
       rel = std::sqrt(h[2]) / bnorm;
       if (std::sqrt(h[2]) <= tol) {
         conv = true;

@@ -172,6 +172,24 @@ def _dptr(t):
     return C.c_void_p(t.data_ptr())
 
 
+def check_vector(t, n, device, name="vector"):
+    """Reject a tensor the library cannot take as a device vector of length
+    n: it must be a contiguous torch float64 tensor on HIP device `device`
+    with exactly n elements.  Raises ValueError before any library call, so
+    a wrong dtype, length or device never reaches a kernel."""
+    import torch
+    if not isinstance(t, torch.Tensor):
+        raise ValueError(f"{name}: expected a torch tensor, got {type(t).__name__}")
+    if t.dtype != torch.float64:
+        raise ValueError(f"{name}: dtype {t.dtype}, expected torch.float64")
+    if not t.is_contiguous():
+        raise ValueError(f"{name}: not contiguous")
+    if t.numel() != n:
+        raise ValueError(f"{name}: {t.numel()} elements, expected n = {n}")
+    if t.device.type != "cuda" or (t.device.index if t.device.index is not None else 0) != device:
+        raise ValueError(f"{name}: on {t.device}, expected cuda:{device}")
+
+
 class Context:
     """A library context bound to one device and one HIP stream."""
 
@@ -244,12 +262,19 @@ class Context:
             o.warm_start = _ptr(ws, C.c_double)
         h = C.c_void_p()
         self._check(lib.geneo_setup(self.h, system.h, decomp.h, C.byref(o), C.byref(h)))
-        return Precond(self, h)
+        pc = Precond(self, h)
+        pc.system, pc.n = system, system.info().n
+        return pc
 
     def apply(self, pc, r, z):
+        check_vector(r, pc.n, self.device, "r")
+        check_vector(z, pc.n, self.device, "z")
         self._check(lib.geneo_apply(self.h, pc.h, _dptr(r), _dptr(z)))
 
     def spmv(self, system, x, y):
+        n = system.info().n
+        check_vector(x, n, self.device, "x")
+        check_vector(y, n, self.device, "y")
         self._check(lib.geneo_spmv(self.h, system.h, _dptr(x), _dptr(y)))
 
     def solve(self, system, pc, b, x, rtol=1e-8, maxit=1000, allow_noconv=False, graph=True):
@@ -258,6 +283,11 @@ class Context:
         second iteration on; graph=False launches kernel by kernel (same
         kernels, bitwise equal iterates).  allow_noconv returns the info of a
         run stopped by maxit instead of raising."""
+        n = system.info().n
+        if pc is not None and pc.system is not system:
+            raise ValueError("the preconditioner was built on another system")
+        check_vector(b, n, self.device, "b")
+        check_vector(x, n, self.device, "x")
         o = SolveOpts(float(rtol), int(maxit), 1 if graph else 0)
         info = SolveInfo()
         rc = lib.geneo_solve(self.h, system.h, pc.h if pc is not None else None, _dptr(b), _dptr(x),
@@ -268,8 +298,16 @@ class Context:
         return info
 
     def potrf_batched(self, A, sizes, offsets, precision=FP64):
+        import torch
         n = np.ascontiguousarray(sizes, dtype=np.int32)
         off = np.ascontiguousarray(offsets, dtype=np.int64)
+        want = torch.float64 if precision == FP64 else torch.float32
+        if not isinstance(A, torch.Tensor) or A.dtype != want or not A.is_contiguous() \
+                or A.device.type != "cuda":
+            raise ValueError(f"A: expected a contiguous {want} device tensor")
+        ld = (n.astype(np.int64) + 127) // 128 * 128
+        if n.size == 0 or (n < 1).any() or (off < 0).any() or int((off + ld * ld).max()) > A.numel():
+            raise ValueError("A: matrix sizes / offsets run past the buffer")
         ms = C.c_double()
         self._check(lib.geneo_potrf_batched(self.h, len(n), _ptr(n, C.c_int32), _ptr(off, C.c_int64),
                                             _dptr(A), int(precision), C.byref(ms)))

@@ -1,4 +1,4 @@
-"""GPU: the paper's weak-scaling beam (Section 5, influence of geometry):
+"""GPU: the paper's weak-scaling beam (Section 4 "Numerical results", influence of the geometry):
 N/2 x 1 x 1 with h = 1/16, N strip subdomains, one overlap layer,
 mu = eps = 1, gamma = 1e-3.  The paper reports, for AS-SNK-GenEO on the
 homogeneous beam, iteration counts that stay nearly constant as N grows

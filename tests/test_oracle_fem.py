@@ -19,7 +19,7 @@ def _system(dims, rule="all", h=None, removed=None, mu=None, gamma=1.0):
 
 @pytest.mark.parametrize("N,edges,nodes", [(8, 121_696, 18_785), (16, 242_592, 37_281)])
 def test_paper_beam_counts(N, edges, nodes):
-    """Section 5, Table 1: the beam N/2 x 1 x 1 at h = 1/16 has 122K / 243K
+    """Section 4 (Numerical results), Table 1: the beam N/2 x 1 x 1 at h = 1/16 has 122K / 243K
     dofs (all edges) and NK size 19K / 37K (all nodes) for N = 8 / 16; the
     closed-form counts of the Kuhn-split hex grid are 121,696 / 242,592 edges
     and 18,785 / 37,281 nodes.  The text gives 121,696 exactly."""

@@ -33,24 +33,6 @@ def floating():
     return _case((6, 6, 6), (3, 3, 3), gamma=1e-2, contrast=1e2, seed=1)
 
 
-def test_paper_snk_count_beam_n8():
-    """Section 5, Table 1: SNK size 25K for N = 8 strips of the 64x16x16-hex
-    beam with one layer of overlap.  SNK counts every node of every
-    overlapping subdomain (end strips 9 hexes, inner strips 10 hexes long):
-    2*10*289 + 6*11*289 = 24,854."""
-    mesh = W.hex_box_mesh((64, 16, 16), h=1.0 / 16)
-    part = decomp.box_partition(mesh, (8, 1, 1))
-    adj = decomp.cell_adjacency(mesh)
-    hot = mesh["hex_of_tet"]
-    total = 0
-    for i in range(8):
-        inside = part == i
-        inside = inside | (adj @ inside.astype(float) > 0)
-        tets = np.nonzero(inside[hot])[0]
-        total += np.unique(mesh["tets"][tets]).size
-    assert total == 24_854
-
-
 def test_partition_of_unity(tiny, floating):
     """sum_i R_i^T D_i R_i = I (Section 2, eq. (PoU))."""
     for s, dec in (tiny, floating):

@@ -7,7 +7,7 @@ the coefficient fields mu / eps and the right-hand side, and states the
 decomposition options of each workload.  Both the CPU oracle and the HIP
 library read what it returns.
 
-Mesh conventions (the paper only says "Cartesian mesh", Section 5):
+Mesh conventions (the paper only says "Cartesian mesh", Section 4 "Numerical results"):
   * node (i, j, k) of an X*Y*Z hex grid has id i + (X+1)*(j + (Y+1)*k), with
     coordinates h*(i, j, k); nodes used by no kept hex are dropped and the
     remaining ids compacted in increasing order;
@@ -263,7 +263,7 @@ def make(cfg, family=0, **over):
                      dirichlet_flags(mesh["bface_tag"], "all"),
                      {"kind": "rcb", "nparts": 256, "jitter": jit}, 1, seed=1005)
     elif isinstance(cfg, str) and cfg.startswith("beam") and cfg[4:].isdigit():
-        # The paper's weak-scaling beam (Section 5, influence of geometry):
+        # The paper's weak-scaling beam (Section 4 "Numerical results", influence of the geometry):
         # N/2 x 1 x 1 with h = 1/16 (8N x 16 x 16 hexes), N strip subdomains
         # along the length, one overlap layer, mu = eps = 1, gamma = 1e-3,
         # Dirichlet on all faces (rule "mixed": Neumann on two opposing
