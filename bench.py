@@ -1,18 +1,19 @@
 """Benchmark of the AS-SNK-GenEO hot path on one MI355X.
 
-A step is one pass of the whole path over the synthetic workload
-(24^3-hex cube, 82,944 tets, mu in {1, 1e4} on random axis-aligned
-channels covering >= 10% of the hexes, eps = 1, gamma = 1e-4, 4x4x4 box
-subdomains with 2 overlap layers, at most 20 GenEO eigenvectors per
-subdomain, PCG to rtol 1e-8): assemble, partition, setup (local Cholesky
-factors, GenEO eigenproblems, coarse space and coarse Cholesky) and solve.
-Two configurations run on the same mesh: the headline one with FP32 local
-factors (probe + FP64 fallback) and the learned warm start of the
-eigensolver, and the plain FP64 one with random start blocks.  The model is
-trained beforehand (not timed) on other instances of the same workload
-recipe.  The reported value is setup + solve seconds with the assembled
-system already resident on the device; assembly and partitioning are
-reported beside it.
+A step is one pass of the whole path over one synthetic workload:
+assemble, partition, setup (local Cholesky factors, GenEO eigenproblems,
+coarse space and coarse Cholesky) and PCG to rtol 1e-8.  The default
+workload is the full stack: a 128x16x16-hex beam (196,608 tets, h = 1/16)
+with mu alternating 1 / 1e3 in 8 slabs along its length, eps = 1,
+gamma = 1e-6, all-Dirichlet, 256 uneven subdomains by recursive coordinate
+bisection with one overlap layer, at most 20 GenEO eigenvectors per
+subdomain.  Two configurations run on the same mesh: the headline one with
+FP32 local factors (conditioning check + probe + FP64 fallback) and the
+learned warm start of the eigensolver, and the plain FP64 one with random
+start blocks.  The model is trained beforehand (not timed) on other
+instances of the same workload recipe.  The reported value is setup + solve
+seconds with the assembled system already resident on the device; assembly
+and partitioning are reported beside it.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
                        [--variant both|learned_fp32|fp64] [--train-instances F]
@@ -34,11 +35,11 @@ sys.path.insert(0, ROOT)
 METRIC = "setup+solve s to rtol 1e-8 & local-factor TFLOP/s; learned+FP32 vs plain FP64"
 PEAK_FP64_TFLOPS = 78.6     # MI355X dense FP64 matrix peak
 PEAK_FP32_TFLOPS = 157.3
-# HBM bytes of one batched local factorisation at this workload (plain FP64 path), from the
+# HBM bytes of one batched local factorisation per workload (plain FP64 path), from the
 # rocprofv3 FETCH_SIZE and WRITE_SIZE counters summed over its launches and scaled by what the
 # same counters read for a 1 GiB device copy (fetch x2.0, write x1.0); valid for the current
-# potrf/trsm/syrk/mirror kernels only
-LOCAL_FACTOR_HBM_BYTES = {"fetch": 193.9e9, "write": 57.2e9}
+# potrf/trsm/syrk/mirror kernels only (a workload without a measurement reports null)
+LOCAL_FACTOR_HBM_BYTES = {"cube24_channels": {"fetch": 193.9e9, "write": 57.2e9}}
 
 
 def parse():
@@ -47,24 +48,33 @@ def parse():
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--workload", default="2", help="workload id (default: the 24^3 channel cube)")
+    ap.add_argument("--workload", default="5", help="workload id (default: the 128x16x16 slab beam)")
     ap.add_argument("--variant", default="both", choices=["both", "learned_fp32", "fp64"])
     ap.add_argument("--train-instances", type=int, default=8)
+    ap.add_argument("--coarse-order", default="natural", choices=["natural", "nd"],
+                    help="elimination order of the coarse columns (nd: nested dissection of the subdomain graph)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
                     help="only run one device copy of BYTES (counter calibration) and exit")
     return ap.parse_args()
 
 
-def train_model(geneo, ctx, n_inst):
+def partition(ctx, sysm, w):
+    p = w.partition
+    if p["kind"] == "box":
+        return ctx.partition(sysm, "box", box=p["p"], overlap=w.overlap)
+    return ctx.partition(sysm, "rcb", nparts=p["nparts"], jitter=p["jitter"], overlap=w.overlap)
+
+
+def train_model(geneo, ctx, wid, n_inst):
     """Train the warm-start model on instances 1..n_inst of the workload
     recipe (the measured instance is instance 0); the last one is held out."""
     import workloads as W
     t0 = time.perf_counter()
     m = ctx.model_create(canvas=12, hidden=256, k=20, seed=2311)
     for f in range(1, n_inst + 1):
-        w = W.make(2, family=f)
+        w = W.make(wid, family=f)
         sysm = ctx.assemble(w.mesh, w.mu, w.eps, w.gamma, w.dirichlet)
-        dec = ctx.partition(sysm, "box", box=w.partition["p"], overlap=w.overlap)
+        dec = partition(ctx, sysm, w)
         pc = ctx.setup(sysm, dec, tau=w.tau, nev_max=w.nev_max, keep_ritz=1)
         m.collect(sysm, dec, pc, holdout=(f == n_inst and n_inst > 1))
         del pc, dec, sysm
@@ -76,17 +86,13 @@ def train_model(geneo, ctx, n_inst):
                "loss_first_epoch": ti.loss_first, "loss_last_epoch": ti.loss_last, "holdout_loss": ti.holdout_loss}
 
 
-def run_step(geneo, ctx, w, precision, b_host=None, model=None):
+def run_step(geneo, ctx, w, precision, b_host=None, model=None, coarse_order=0):
     import torch
     ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
     t0 = time.perf_counter()
     sysm = ctx.assemble(w.mesh, w.mu, w.eps, w.gamma, w.dirichlet)
     t1 = time.perf_counter()
-    p = w.partition
-    if p["kind"] == "box":
-        dec = ctx.partition(sysm, "box", box=p["p"], overlap=w.overlap)
-    else:
-        dec = ctx.partition(sysm, "rcb", nparts=p["nparts"], jitter=p["jitter"], overlap=w.overlap)
+    dec = partition(ctx, sysm, w)
     n = sysm.info().n
     if b_host is None:
         b_host = w.rhs(n)
@@ -95,7 +101,8 @@ def run_step(geneo, ctx, w, precision, b_host=None, model=None):
     torch.cuda.synchronize()
     t2 = time.perf_counter()
     kw = {"model": model} if model is not None else {}
-    pc = ctx.setup(sysm, dec, tau=w.tau, nev_max=w.nev_max, local_precision=precision, **kw)
+    pc = ctx.setup(sysm, dec, tau=w.tau, nev_max=w.nev_max, local_precision=precision, coarse_order=coarse_order,
+                   **kw)
     torch.cuda.synchronize()
     t3 = time.perf_counter()
     si = ctx.solve(sysm, pc, b, x, rtol=1e-8, maxit=2000)
@@ -105,6 +112,7 @@ def run_step(geneo, ctx, w, precision, b_host=None, model=None):
     di = dec.info()
     out = dict(assemble_s=t1 - t0, partition_s=t2 - t1, setup_s=t3 - t2, solve_s=t4 - t3,
                setup_solve_s=t4 - t2, step_s=t4 - t0, iterations=si.iterations, rel_residual=si.rel_residual,
+               true_rel_residual=si.true_rel_residual,
                graph_replays=si.graph_replays,
                n=n, n_sub=di.n_sub, n_min=di.n_min, n_max=di.n_max, n0=pi.n0, n0_rank=pi.n0_rank,
                n_snk=pi.n_snk, n_geneo=pi.n_geneo, lobpcg_iters=pi.lobpcg_iters,
@@ -115,16 +123,21 @@ def run_step(geneo, ctx, w, precision, b_host=None, model=None):
                fp32_prechecked=pi.fp32_prechecked, fp32_kappa_lb=pi.fp32_kappa_lb,
                learned_starts=pi.learned_starts, start_residual=pi.start_residual,
                n0_factored=pi.n0 - pi.n0_local_dropped, coarse_flops=pi.coarse_factor_flops,
-               coarse_fill=pi.coarse_fill)
+               coarse_fill=pi.coarse_fill, coarse_nd_levels=pi.coarse_nd_levels,
+               coarse_solve_depth=pi.coarse_solve_depth, learned_candidates=pi.learned_candidates,
+               lobpcg_unconverged=pi.lobpcg_unconverged)
     del pc, dec, sysm
     return out, b_host
 
 
 def cpu_baseline(w):
     """The oracle, as written, on a bounded sample of the same workload: the
-    dense local Cholesky and the dense filtered GEVP of two subdomains (the
-    smallest and one of median size), scaled by sum n_i^3 to all
-    subdomains.  Coarse factorisation and PCG are not in the sample."""
+    dense local Cholesky and the dense filtered GEVP (scipy eigh) of the
+    smallest subdomain and one of median size, scaled by sum n_i^3 to all
+    subdomains (the oracle's dense local work grows as n_i^3).  The coarse
+    factorisation and the Krylov iteration are not in the sample: the
+    oracle's coarse matrix (n0 ~ 1e5) and a sparse direct solve of the whole
+    system (223 s for the beam on 8 cores, SuperLU) exceed a bounded run."""
     from threadpoolctl import threadpool_info
     from oracle import decomp, fem, geneo
     import scipy.linalg as sla
@@ -132,7 +145,7 @@ def cpu_baseline(w):
     dec = decomp.Decomposition(s, decomp.partition_cells(w), w.overlap)
     sizes = np.array([d.size for d in dec.dofs], dtype=np.float64)
     order = np.argsort(sizes)
-    sample = [int(order[0]), int(order[len(order) // 4])]
+    sample = [int(order[0]), int(order[len(order) // 2])]
     t = 0.0
     for i in sample:
         Ai = dec.A_dir(i).toarray()
@@ -147,7 +160,7 @@ def cpu_baseline(w):
     return {"value": t * scale, "unit": "s", "cores": int(threads), "kind": "oracle",
             "sample": (f"dense local Cholesky + dense filtered GEVP (scipy eigh) of subdomains {sample} "
                        f"(n_i = {int(sizes[sample[0]])}, {int(sizes[sample[1]])}) took {t:.1f} s, scaled by "
-                       f"sum n_i^3 to all {dec.N} subdomains; coarse factor and PCG excluded")}
+                       f"sum n_i^3 to all {dec.N} subdomains; coarse factor and Krylov iteration excluded")}
 
 
 def summarize(res):
@@ -165,8 +178,11 @@ def summarize(res):
                       "coarse_factor": mean("t_coarse_factor_ms"), "pcg_device": mean("solve_ms")},
         "local_factor_tflops": last["local_flops"] / (mean("t_factor_ms") * 1e-3) / 1e12,
         "coarse_factor_tflops": last["coarse_flops"] / (mean("t_coarse_factor_ms") * 1e-3) / 1e12,
-        "coarse_fill": last["coarse_fill"],
+        "coarse_fill": last["coarse_fill"], "coarse_nd_levels": last["coarse_nd_levels"],
+        "coarse_solve_depth": last["coarse_solve_depth"], "lobpcg_unconverged": last["lobpcg_unconverged"],
+        "learned_candidates": last["learned_candidates"],
         "pcg_iterations": last["iterations"], "rel_residual": last["rel_residual"],
+        "true_rel_residual": last["true_rel_residual"],
         "pcg_graph_replays": last["graph_replays"],
         "lobpcg_iterations": last["lobpcg_iters"], "start_residual": last["start_residual"],
         "learned_starts": last["learned_starts"], "fp64_fallbacks": last["fp64_fallbacks"],
@@ -206,20 +222,21 @@ def main():
     variants = {"learned_fp32": (geneo.FP32_REFINE1, True), "fp64": (geneo.FP64, False)}
     run = [v for v in ("learned_fp32", "fp64") if a.variant in ("both", v)]
     model, training = None, None
+    corder = geneo.ORDER_NESTED_DISSECTION if a.coarse_order == "nd" else geneo.ORDER_NATURAL
     if "learned_fp32" in run:
-        model, training = train_model(geneo, ctx, a.train_instances)
+        model, training = train_model(geneo, ctx, wid, a.train_instances)
     b_host = None
     for _ in range(a.warmup):
         for v in run:
             prec, learned = variants[v]
-            _, b_host = run_step(geneo, ctx, w, prec, b_host, model if learned else None)
+            _, b_host = run_step(geneo, ctx, w, prec, b_host, model if learned else None, corder)
     torch.cuda.synchronize()
     res = {v: [] for v in run}
     t0 = time.perf_counter()
     for _ in range(a.steps):
         for v in run:
             prec, learned = variants[v]
-            r, b_host = run_step(geneo, ctx, w, prec, b_host, model if learned else None)
+            r, b_host = run_step(geneo, ctx, w, prec, b_host, model if learned else None, corder)
             res[v].append(r)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
@@ -248,19 +265,20 @@ def main():
         "vs_baseline": None,
         "dtype": "f64",
         "data": "synthetic",
-        "config": {"workload": w.name + ": 24^3 hexes x 6 tets (82,944), mu in {1,1e4} channels >= 10%, "
-                               "eps=1, gamma=1e-4, all-Dirichlet, 4x4x4 boxes, overlap 2, tau=10, "
-                               "<=20 GenEO vectors/subdomain, PCG rtol 1e-8",
+        "config": {"workload": f"{w.name}: {w.describe}, tau = {w.tau:g}, <= {w.nev_max} GenEO vectors "
+                               "per subdomain, PCG rtol 1e-8",
                    "variant": head, "n": last["n"], "n_sub": last["n_sub"], "n_i_min": last["n_min"],
                    "n_i_max": last["n_max"], "n0": last["n0"], "n0_factored": last["n0_factored"],
                    "n0_rank": last["n0_rank"],
                    "n_geneo": last["n_geneo"], "parallelism": "1 GPU"},
         "variants": summ,
         "roofline": {"bound": "mfma",
-                     "kernel": "batched FP64 local Cholesky of the 64 subdomain matrices (potrf/trsm/syrk/mirror)",
+                     "kernel": f"batched FP64 local Cholesky of the {last['n_sub']} subdomain matrices "
+                               "(potrf/trsm/syrk/mirror)",
                      "achieved": achieved, "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
                      "frac": achieved / PEAK_FP64_TFLOPS,
-                     "traffic": LOCAL_FACTOR_HBM_BYTES["fetch"] + LOCAL_FACTOR_HBM_BYTES["write"],
+                     "traffic": (sum(LOCAL_FACTOR_HBM_BYTES[w.name].values())
+                                 if w.name in LOCAL_FACTOR_HBM_BYTES else None),
                      "traffic_unit": "B per factorisation (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-scaled)"},
         "roofline_coarse": {"bound": "mfma", "kernel": "block-sparse FP64 coarse Cholesky of E",
                             "achieved": achieved_coarse, "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",

@@ -138,7 +138,22 @@ int geneo_decomp_subdomain(const geneo_decomp* dec, int32_t i, int32_t* n_i, int
 /* --- setup: local factors, GenEO eigenproblems, coarse space ------------ */
 
 typedef enum { GENEO_FP64 = 0, GENEO_FP32_REFINE1 = 1 } geneo_precision;
-typedef enum { GENEO_COARSE_SNK_GENEO = 0, GENEO_COARSE_SNK = 1, GENEO_COARSE_NONE = 2 } geneo_coarse_kind;
+/* Coarse space (Section 4, Numerical results, compares these variants): the split near-kernel
+ * columns R_i^T D_i G_i with the GenEO vectors (the method), the split near-kernel columns alone
+ * (tau = infinity), none (one-level additive Schwarz), the global near-kernel columns G (the
+ * gradients of the free nodes) alone or with the GenEO vectors. */
+typedef enum { GENEO_COARSE_SNK_GENEO = 0, GENEO_COARSE_SNK = 1, GENEO_COARSE_NONE = 2,
+               GENEO_COARSE_NK = 3, GENEO_COARSE_NK_GENEO = 4 } geneo_coarse_kind;
+/* One-level term of the preconditioner: sum_i R_i^T A_i^-1 R_i (eq. (AS), symmetric: PCG) or the
+ * restricted sum_i R_i^T D_i A_i^-1 R_i with the partition of unity (eq. (RAS), not symmetric:
+ * use GMRES). */
+typedef enum { GENEO_WEIGHT_IDENTITY = 0, GENEO_WEIGHT_POU = 1 } geneo_one_level_weight;
+/* Elimination order of the coarse columns in the factorisation of E (the
+ * coarse space and its span do not depend on it; which columns the greedy
+ * basis test leaves out may): subdomain groups (SNK columns, then GenEO
+ * columns) in nested-dissection order of the subdomain coupling graph, or
+ * all SNK columns subdomain by subdomain followed by all GenEO columns. */
+typedef enum { GENEO_ORDER_NATURAL = 0, GENEO_ORDER_NESTED_DISSECTION = 1 } geneo_coarse_order;
 
 typedef struct {
   double tau;               /* GenEO threshold, keep lambda > tau (Section 4, Numerical results: 10) */
@@ -156,6 +171,11 @@ typedef struct {
   const struct geneo_model* model; /* learned warm start of the eigensolver, or NULL (cold random start);
                                ignored when warm_start is given */
   int32_t keep_ritz;        /* 1: keep the final Ritz block for geneo_model_collect */
+  int32_t coarse_order;     /* geneo_coarse_order (default natural) */
+  int32_t one_level_weight; /* geneo_one_level_weight (default identity) */
+  int32_t classical;        /* 1: GenEO vectors from the classical pencil D_j A_j D_j V = lambda A_j^Neu V
+                               (Section 3.2, eq. (eigGenEOClassis): no projection out of span(G_j)), an
+                               ablation of the method's filtered pencil; default 0 */
 } geneo_setup_opts;
 
 typedef struct {
@@ -174,7 +194,11 @@ typedef struct {
   double fp32_rho_est;      /* FP32_REFINE1: largest probe estimate of rho(I - Ahat_i^-1 A_i), else 0 */
   double coarse_factor_flops; /* flops of the coarse factorisation (on its block-sparse fill pattern) */
   double coarse_fill;       /* fraction of the lower 128 x 128 tiles of E in that pattern (1 = dense) */
-  int32_t learned_starts;   /* subdomains whose start block came from the model */
+  int32_t learned_starts;   /* subdomains whose eigensolver continued from the model's start block: after
+                               one Rayleigh-Ritz step on both the model's block and the random block, the
+                               largest eigen-residual of the pairs that decide the coarse space (Ritz values
+                               above tau, at most nev_max, of either block, plus the next one) was below half
+                               that of the random block (otherwise the random block is kept: the cold start) */
   double start_residual;    /* largest eigen-residual of the top nev_max Ritz pairs after the first
                                Rayleigh-Ritz step (start-block quality) */
   int32_t fp32_prechecked;  /* FP32_REFINE1: subdomains factored in FP64 without an FP32 attempt, because
@@ -182,6 +206,10 @@ typedef struct {
   double fp32_kappa_lb;     /* FP32_REFINE1: largest kappa_lb_i, the lower bound on the condition number of
                                D^-1/2 A_i D^-1/2 (D = diag A_i) from the Rayleigh quotient of a node's
                                gradient (sampled nodes whose edges all lie in Omega_i; 0 if none) */
+  int32_t learned_candidates; /* subdomains for which the model proposed a start block (those that fit its
+                               canvas); learned_starts of them were kept */
+  int32_t coarse_nd_levels; /* depth of the nested dissection of the subdomain graph (0: natural order) */
+  int32_t coarse_solve_depth; /* longest chain of dependent 128-row blocks in a coarse triangular solve */
 } geneo_precond_info;
 
 void geneo_setup_opts_default(geneo_setup_opts* o);
@@ -214,7 +242,9 @@ int geneo_precond_ritz(geneo_ctx* ctx, const geneo_precond* pc, int32_t i, doubl
 /* z = M_AS,2^-1 r, device vectors of length n (the paper's preconditioner). */
 int geneo_apply(geneo_ctx* ctx, const geneo_precond* pc, const double* r, double* z);
 
-/* --- solve: preconditioned conjugate gradients -------------------------- */
+/* --- solve: preconditioned Krylov iteration ------------------------------ */
+
+typedef enum { GENEO_SOLVER_PCG = 0, GENEO_SOLVER_GMRES = 1 } geneo_solver;
 
 typedef struct {
   double rtol;      /* stop at the first k with ||r_k||_2 <= rtol ||b||_2 */
@@ -224,18 +254,37 @@ typedef struct {
                        stream of the library's own that is ordered after the context stream's earlier
                        work and before its later work; 0: launch kernel by kernel on the context
                        stream.  Both run the same kernels in the same order (bitwise equal results). */
+  int32_t method;   /* geneo_solver: PCG (default; needs the symmetric preconditioner) or right-preconditioned
+                       GMRES (Section 4, Numerical results: the paper's Krylov method), whose residual is the
+                       true residual b - A x; graph is ignored for GMRES */
+  int32_t restart;  /* GMRES: restart length (0: no restart, up to maxit Arnoldi vectors) */
+  int32_t true_residual; /* PCG: 1 = once the recurrence residual meets rtol, continue from the true residual
+                            b - A x with a fresh direction while that misses rtol (at most twice; then
+                            GENEO_ENOCONV); 0 (default) = stop on the recurrence residual.  The true residual
+                            is computed and reported either way.  In FP64 it cannot go below about
+                            u ||A|| ||x|| / ||b|| (u = 2^-53), which exceeds 1e-8 when gamma is small. */
 } geneo_solve_opts;
 
 typedef struct {
   int32_t iterations;
-  double rel_residual;   /* recurrence residual ||r_k|| / ||b|| at exit */
+  double rel_residual;   /* PCG: the recurrence residual ||r_k|| / ||b|| at exit; GMRES: the rotated
+                            right-hand side, which is the true residual in exact arithmetic */
   double solve_ms;       /* device wall time of the iteration */
   int32_t graph_replays; /* iterations run as graph replays */
+  int32_t residual_replacements; /* PCG with true_residual: restarts from the true residual after the
+                            recurrence residual met rtol but b - A x did not (at most 2) */
+  double true_rel_residual; /* PCG: ||b - A x|| / ||b|| computed on the device when the recurrence residual
+                            met rtol (0 if it never did) */
 } geneo_solve_info;
 
-/* Solve A x = b from x0 = 0 with PCG preconditioned by pc (or plain CG if pc
- * is NULL).  b, x: device, length n.  Returns GENEO_ENOCONV at maxit with
- * info filled and the last iterate in x. */
+/* Solve A x = b (Section 1, the discrete system) from x0 = 0 with PCG
+ * preconditioned by pc (or plain CG if pc is NULL), stopping at the first k
+ * with ||r_k||_2 <= rtol ||b||_2 for the recurrence residual (see
+ * true_residual for the true one); or, with method = GMRES, with
+ * right-preconditioned GMRES (Arnoldi on A M^-1 with classical Gram-Schmidt
+ * applied twice, Givens rotations; x = M^-1 V y), the solver of Section 4,
+ * Numerical results.  b, x: device, length n.  Returns GENEO_ENOCONV at
+ * maxit with info filled and the last iterate in x. */
 int geneo_solve(geneo_ctx* ctx, const geneo_system* sys, const geneo_precond* pc,
                 const double* b, double* x, const geneo_solve_opts* opts, geneo_solve_info* info);
 
@@ -317,6 +366,36 @@ void geneo_free_model(geneo_model* m);
  * On a non-positive pivot returns GENEO_ENOTSPD naming the matrix and pivot. */
 int geneo_potrf_batched(geneo_ctx* ctx, int32_t batch, const int32_t* n_host,
                         const int64_t* off_host, void* A, int32_t precision, double* elapsed_ms);
+
+/* --- autotuner of the batched factorisation schedule -------------------- */
+
+/* Schedule of a batched Cholesky: mode = tile mode of the trailing updates
+ * (0: 64 x 64 tile per wave, 4 waves, operands from L2; 1: 8 waves; 2:
+ * operands staged through LDS), group = panels per trailing update,
+ * potrf = FP64 diagonal-block kernel (1: recursive in LDS, 0: register
+ * kernel; FP32 always 0). */
+typedef struct {
+  int32_t mode, group, potrf;
+  double ms;        /* tuner: fastest factorisation time of the batch (ms) */
+} geneo_factor_schedule;
+
+/* Time every candidate schedule (tile modes 0-2, groups 4/8/16, both FP64
+ * diagonal-block kernels) on synthetic SPD matrices of the given sizes
+ * (device memory of the batch is allocated for the run), keep the fastest
+ * (minimum over `reps` runs each) and record it in the process-wide table
+ * under (precision, largest block count, floor(log2(batch))): every
+ * factorisation planned afterwards (geneo_setup's local and Neumann
+ * factors, geneo_potrf_batched) uses the table's schedule for its key, or
+ * the nearest tuned block count of its precision and class, else the
+ * defaults (0, 8, 1).  *tried = candidates timed. */
+int geneo_tune_factor(geneo_ctx* ctx, int32_t batch, const int32_t* n_host, int32_t precision, int32_t reps,
+                      geneo_factor_schedule* best, int32_t* tried);
+/* The schedule a batch of these sizes gets now (table lookup, no timing). */
+int geneo_tune_lookup(int32_t batch, const int32_t* n_host, int32_t precision, geneo_factor_schedule* out);
+/* Write the table to / merge it from a text file (one entry per line:
+ * precision max_blk class mode group potrf ms; '#' starts a comment). */
+int geneo_tune_save(const char* path);
+int geneo_tune_load(const char* path);
 
 /* --- lifetime ----------------------------------------------------------- */
 void geneo_free_system(geneo_system* sys);

@@ -8,6 +8,8 @@ namespace geneo {
 void build_topology(geneo_system* s, const geneo_mesh* m);
 void assemble_device(geneo_ctx* ctx, geneo_system* s, const double* mu, const double* eps, double gamma);
 void build_decomposition(const geneo_system* s, const geneo_partition_opts* o, geneo_decomp* dec);
+FactorConfig autotune_factor(geneo_ctx* ctx, int32_t batch, const int32_t* n_host, int precision, int reps,
+                             double* best_ms, int* tried);
 }  // namespace geneo
 
 using namespace geneo;
@@ -272,13 +274,17 @@ int geneo_apply(geneo_ctx* ctx, const geneo_precond* pc, const double* r, double
 int geneo_solve(geneo_ctx* ctx, const geneo_system* s, const geneo_precond* pc, const double* b, double* x,
                 const geneo_solve_opts* o, geneo_solve_info* info) {
   if (!ctx || !s || !b || !x || !info) return GENEO_EINVAL;
-  geneo_solve_opts def{1e-8, 1000, 1};
+  geneo_solve_opts def{1e-8, 1000, 1, GENEO_SOLVER_PCG, 0, 0};
   const geneo_solve_opts* op = o ? o : &def;
-  if (!(op->rtol > 0) || op->maxit < 1) return GENEO_EINVAL;
+  if (!(op->rtol > 0) || op->maxit < 1 || op->restart < 0) return GENEO_EINVAL;
+  if (op->method != GENEO_SOLVER_PCG && op->method != GENEO_SOLVER_GMRES) return GENEO_EINVAL;
   std::memset(info, 0, sizeof(*info));
   return guarded(ctx, [&] {
     if (pc && pc->sys != s) throw Error(GENEO_EINVAL, "the preconditioner was built on another system");
-    pcg(ctx, s, pc, b, x, op, info);
+    if (op->method == GENEO_SOLVER_GMRES)
+      gmres(ctx, s, pc, b, x, op, info);
+    else
+      pcg(ctx, s, pc, b, x, op, info);
   });
 }
 
@@ -297,7 +303,7 @@ int geneo_potrf_batched(geneo_ctx* ctx, int32_t batch, const int32_t* n_host, co
       flag_off += (int32_t)(np / NB);
     }
     FactorPlan P;
-    P.build(descs, ctx->stream);
+    P.build(descs, ctx->stream, precision);
     HIP_CHECK(hipEventRecord(ctx->ev[0], ctx->stream));
     if (precision == GENEO_FP64) {
       DevBuf<double> inv;
@@ -321,6 +327,57 @@ int geneo_potrf_batched(geneo_ctx* ctx, int32_t batch, const int32_t* n_host, co
     if (elapsed_ms) *elapsed_ms = ms;
     check_device_error(ctx);
   });
+}
+
+int geneo_tune_factor(geneo_ctx* ctx, int32_t batch, const int32_t* n_host, int32_t precision, int32_t reps,
+                      geneo_factor_schedule* best, int32_t* tried) {
+  if (!ctx || batch < 1 || !n_host || !best || reps < 1) return GENEO_EINVAL;
+  return guarded(ctx, [&] {
+    double ms = 0;
+    int nt = 0;
+    const FactorConfig c = autotune_factor(ctx, batch, n_host, precision, reps, &ms, &nt);
+    *best = geneo_factor_schedule{c.mode, c.group, c.rec_potrf, ms};
+    if (tried) *tried = nt;
+  });
+}
+
+int geneo_tune_lookup(int32_t batch, const int32_t* n_host, int32_t precision, geneo_factor_schedule* out) {
+  if (batch < 1 || !n_host || !out) return GENEO_EINVAL;
+  if (precision != GENEO_FP64 && precision != GENEO_FP32_REFINE1) return GENEO_EINVAL;
+  int32_t max_blk = 0;
+  for (int32_t i = 0; i < batch; ++i) {
+    if (n_host[i] < 1) return GENEO_EINVAL;
+    max_blk = std::max<int32_t>(max_blk, (int32_t)(round_up(n_host[i], NB) / NB));
+  }
+  const FactorConfig c = tuned_factor_config(precision, max_blk, batch);
+  *out = geneo_factor_schedule{c.mode, c.group, c.rec_potrf, 0.0};
+  return GENEO_OK;
+}
+
+int geneo_tune_save(const char* path) {
+  if (!path) return GENEO_EINVAL;
+  FILE* f = std::fopen(path, "w");
+  if (!f) return GENEO_EINVAL;
+  const std::string t = tune_db_text();
+  const bool ok = std::fwrite(t.data(), 1, t.size(), f) == t.size();
+  return std::fclose(f) == 0 && ok ? GENEO_OK : GENEO_EINVAL;
+}
+
+int geneo_tune_load(const char* path) {
+  if (!path) return GENEO_EINVAL;
+  FILE* f = std::fopen(path, "r");
+  if (!f) return GENEO_EINVAL;
+  std::string t;
+  char buf[4096];
+  size_t k;
+  while ((k = std::fread(buf, 1, sizeof(buf), f)) > 0) t.append(buf, k);
+  std::fclose(f);
+  try {
+    tune_db_parse(t);
+  } catch (const std::exception&) {
+    return GENEO_EINVAL;
+  }
+  return GENEO_OK;
 }
 
 void geneo_model_opts_default(geneo_model_opts* o) {

@@ -21,6 +21,23 @@ struct SyrkLaunch {
   int kcol0, kb, b0, ncols; // panel group columns, first trailing block, column limit (0 = all)
 };
 
+// Schedule of a batched factorisation: tile mode of the trailing updates
+// (0: 64x64 per wave, operands from L2, 4 waves; 1: the same with 8 waves;
+// 2: operands staged through LDS), panels per trailing-update group, and the
+// FP64 diagonal-block kernel (1: recursive in LDS, 0: register kernel).
+struct FactorConfig {
+  int mode = 0;
+  int group = 8;
+  int rec_potrf = 1;
+};
+// The schedule for a batch: the autotuner's entry for (precision, largest
+// block count, batch-size class floor(log2 nmat)) if it has one, else the
+// nearest tuned block count of that precision and class, else the defaults.
+FactorConfig tuned_factor_config(int precision, int max_blk, int nmat);
+void set_tuned_factor_config(int precision, int max_blk, int nmat, const FactorConfig& c, double ms);
+std::string tune_db_text();
+void tune_db_parse(const std::string& text);
+
 struct FactorPlan {
   int nmat = 0, max_blk = 0;
   std::vector<MatDesc> h_desc;
@@ -29,6 +46,7 @@ struct FactorPlan {
   int64_t n_items = 0;               // triangular-solve work items (blocks)
   int64_t mirror_tiles = 0;          // strictly-lower 128x128 blocks
   int group = 8;                     // panels per trailing update
+  FactorConfig cfg;                  // schedule (the autotuner's table, or the defaults)
   // solve form (off-diagonal blocks premultiplied by their row's diagonal
   // inverse, shorter dependency chain; the coarse factor) or plain form
   // (x_I = inv(D_II) (b_I - sum L(I,J) x_J); the batched local factors,
@@ -43,7 +61,14 @@ struct FactorPlan {
   DevBuf<int32_t> d_items_fwd, d_items_bwd;
   DevBuf<double> d_y;                // single-right-hand-side solves: intermediate vector
   mutable DevBuf<double> d_ym;       // many-right-hand-side solves: intermediate block (on first use)
-  void build(const std::vector<MatDesc>& descs, hipStream_t st);
+  // precision: the factor's type (GENEO_FP64 or GENEO_FP32_REFINE1), selects the schedule
+  void build(const std::vector<MatDesc>& descs, hipStream_t st, int precision = GENEO_FP64);
+  // host side of build(): ordering, prefixes, launches, solve items (with
+  // the schedule `force` instead of the table's, if given)
+  void plan_host(const std::vector<MatDesc>& descs, int precision = GENEO_FP64,
+                 const FactorConfig* force = nullptr);
+  std::vector<int32_t> h_order, h_items_fwd, h_items_bwd;
+  std::vector<int64_t> h_prefix, h_syrk_prefix, h_mirror_prefix;
 
   // Block-sparse single matrix: only the tiles of the factor's fill pattern
   // are touched (explicit tile lists), the solves follow per-row dependency

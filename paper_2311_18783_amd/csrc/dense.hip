@@ -739,10 +739,11 @@ __global__ __launch_bounds__(kRecThreads) void k_potrf_rec(const MatDesc* __rest
 
 // --------------------------------------------------------------- plan
 
-void FactorPlan::build(const std::vector<MatDesc>& descs, hipStream_t st) {
+void FactorPlan::plan_host(const std::vector<MatDesc>& descs, int precision, const FactorConfig* force) {
   h_desc = descs;
   nmat = (int)descs.size();
-  std::vector<int32_t> ord(nmat);
+  std::vector<int32_t>& ord = h_order;
+  ord.resize(nmat);
   for (int i = 0; i < nmat; ++i) ord[i] = i;
   std::stable_sort(ord.begin(), ord.end(), [&](int a, int b) { return descs[a].nblk > descs[b].nblk; });
   max_blk = nmat ? descs[ord[0]].nblk : 0;
@@ -750,7 +751,8 @@ void FactorPlan::build(const std::vector<MatDesc>& descs, hipStream_t st) {
   trsm_tiles.assign(max_blk, 0);
   syrk_tiles.assign(max_blk, 0);
   pre_off.assign(max_blk, 0);
-  std::vector<int64_t> pre;
+  std::vector<int64_t>& pre = h_prefix;
+  pre.clear();
   for (int s = 0; s < max_blk; ++s) {
     int c = 0;
     while (c < nmat && descs[ord[c]].nblk > s) ++c;
@@ -772,19 +774,14 @@ void FactorPlan::build(const std::vector<MatDesc>& descs, hipStream_t st) {
     pre.insert(pre.end(), pt.begin(), pt.end());
     pre.insert(pre.end(), ps.begin(), ps.end());
   }
-  d_desc.upload(descs, st);
-  d_order.upload(ord, st);
-  d_prefix.upload(pre, st);
-  int64_t vec_len = 0;
-  for (const auto& dd : descs) vec_len = std::max<int64_t>(vec_len, dd.voff + dd.ld);
-  d_y.alloc(std::max<int64_t>(vec_len, 1));
   // trailing updates for panel groups of G panels: inside a group, panel g
   // updates only the group's later block columns; after the group, one
   // update with all G panels (K = G * NB) covers the rest
-  const char* ge = std::getenv("GENEO_PANEL_GROUP");
-  group = ge ? std::max(1, std::atoi(ge)) : 8;
+  cfg = force ? *force : tuned_factor_config(precision, max_blk, nmat);
+  group = std::max(1, cfg.group);
   syrk.clear();
-  std::vector<int64_t> spre;
+  std::vector<int64_t>& spre = h_syrk_prefix;
+  spre.clear();
   auto add_launch = [&](int kcol0, int kb, int b0, int ncols) {
     SyrkLaunch L{(int64_t)spre.size(), 0, kcol0, kb, b0, ncols};
     int64_t acc = 0;
@@ -808,28 +805,40 @@ void FactorPlan::build(const std::vector<MatDesc>& descs, hipStream_t st) {
     }
     add_launch(s0, group, s0 + group, 0);                            // trailing, K = group * NB
   }
-  d_syrk_prefix.upload(spre, st);
-  std::vector<int64_t> mp(nmat + 1, 0);
+  std::vector<int64_t>& mp = h_mirror_prefix;
+  mp.assign(nmat + 1, 0);
   for (int k = 0; k < nmat; ++k) {
     int64_t T = descs[ord[k]].nblk;
     mp[k + 1] = mp[k] + T * (T - 1) / 2;
   }
   mirror_tiles = mp[nmat];
-  d_mirror_prefix.upload(mp, st);
   // triangular-solve work items: forward in increasing block order across
   // matrices, backward in decreasing order
-  std::vector<int32_t> fwd, bwd;
+  h_items_fwd.clear();
+  h_items_bwd.clear();
   for (int s = 0; s < max_blk; ++s)
     for (int k = 0; k < cnt[s]; ++k) {
       int m = ord[k];
-      fwd.push_back(m);
-      fwd.push_back(s);
-      bwd.push_back(m);
-      bwd.push_back(descs[m].nblk - 1 - s);
+      h_items_fwd.push_back(m);
+      h_items_fwd.push_back(s);
+      h_items_bwd.push_back(m);
+      h_items_bwd.push_back(descs[m].nblk - 1 - s);
     }
-  n_items = (int64_t)fwd.size() / 2;
-  d_items_fwd.upload(fwd, st);
-  d_items_bwd.upload(bwd, st);
+  n_items = (int64_t)h_items_fwd.size() / 2;
+}
+
+void FactorPlan::build(const std::vector<MatDesc>& descs, hipStream_t st, int precision) {
+  plan_host(descs, precision);
+  d_desc.upload(descs, st);
+  d_order.upload(h_order, st);
+  d_prefix.upload(h_prefix, st);
+  int64_t vec_len = 0;
+  for (const auto& dd : descs) vec_len = std::max<int64_t>(vec_len, dd.voff + dd.ld);
+  d_y.alloc(std::max<int64_t>(vec_len, 1));
+  d_syrk_prefix.upload(h_syrk_prefix, st);
+  d_mirror_prefix.upload(h_mirror_prefix, st);
+  d_items_fwd.upload(h_items_fwd, st);
+  d_items_bwd.upload(h_items_bwd, st);
 }
 
 void symbolic_fill(int nb, std::vector<uint8_t>& pat) {
@@ -959,11 +968,8 @@ static void factor_run(const FactorPlan& P, T* A, T* Ainv, const double* odiag, 
   const size_t mma_lds = MODE == 2 ? sizeof(T) * 4 * KCH * NB : 0;   // two stages of A and B chunks
   const unsigned threads = 64 * TileGeo<MODE>::WAVES;
   static bool attr_set = false;
-  // FP64: recursive diagonal-block kernel (GENEO_POTRF=reg selects the register one)
-  static const bool rec_potrf = [] {
-    const char* e = std::getenv("GENEO_POTRF");
-    return !(e && std::string(e) == "reg");
-  }() && sizeof(T) == 8;
+  // FP64: recursive diagonal-block kernel or the register one (schedule)
+  const bool rec_potrf = P.cfg.rec_potrf && sizeof(T) == 8;
   if (!attr_set) {
     HIP_CHECK(hipFuncSetAttribute((const void*)k_potrf<T>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
     HIP_CHECK(hipFuncSetAttribute((const void*)k_potrf_rec, hipFuncAttributeMaxDynamicSharedMemorySize,
@@ -1014,14 +1020,8 @@ static void factor_run(const FactorPlan& P, T* A, T* Ainv, const double* odiag, 
 template <typename T>
 static void factor_impl(const FactorPlan& P, T* A, T* Ainv, const double* odiag, double drop_tol, double* pivrel,
                         DevErr* err, hipStream_t st, int32_t* failed) {
-  // tile mode: GENEO_MMA = direct4 | direct8 | lds; defaults measured on MI355X
-  static const int mode = [] {
-    const char* e = std::getenv("GENEO_MMA");
-    if (e && std::string(e) == "direct4") return 0;
-    if (e && std::string(e) == "direct8") return 1;
-    if (e && std::string(e) == "lds") return 2;
-    return 0;
-  }();
+  // tile mode of the schedule (the autotuner's choice, default measured on MI355X)
+  const int mode = P.cfg.mode;
   if (mode == 0)
     factor_run<T, 0>(P, A, Ainv, odiag, drop_tol, pivrel, err, st, failed);
   else if (mode == 1)

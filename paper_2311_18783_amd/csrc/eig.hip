@@ -110,9 +110,38 @@ __global__ void k_g(int64_t len, int k, const int32_t* __restrict__ row_sub, con
 }
 
 // R = AX - BX diag(theta) (into W); also per-(subdomain, column) squared norms of R and BX
+// theta[j k + q] = x^T (A x) / x^T (B x) for column q of subdomain j's block
+// (Rayleigh quotients of the current block; one workgroup per column)
+__global__ __launch_bounds__(256) void k_rq(int k, const int64_t* __restrict__ voff, const double* __restrict__ X,
+                                            const double* __restrict__ AX, const double* __restrict__ BX,
+                                            double* __restrict__ theta) {
+  const int j = blockIdx.x / k, q = blockIdx.x % k;
+  const int64_t ld = voff[j + 1] - voff[j];
+  const int64_t o = voff[j] * k + (int64_t)q * ld;
+  double s1 = 0.0, s2 = 0.0;
+  for (int64_t r = threadIdx.x; r < ld; r += 256) {
+    const double x = X[o + r];
+    s1 += x * AX[o + r];
+    s2 += x * BX[o + r];
+  }
+  __shared__ double a1[256], a2[256];
+  a1[threadIdx.x] = s1;
+  a2[threadIdx.x] = s2;
+  __syncthreads();
+  for (int st = 128; st > 0; st >>= 1) {
+    if (threadIdx.x < st) {
+      a1[threadIdx.x] += a1[threadIdx.x + st];
+      a2[threadIdx.x] += a2[threadIdx.x + st];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0 && a2[0] > 0.0) theta[j * k + q] = a1[0] / a2[0];
+}
+
 __global__ __launch_bounds__(256) void k_residual(int k, const int64_t* __restrict__ voff, const double* __restrict__ AX,
                                                   const double* __restrict__ BX, const double* __restrict__ theta,
-                                                  double* __restrict__ R, double* __restrict__ nrm) {
+                                                  double* __restrict__ R, double* __restrict__ nrm,
+                                                  double* __restrict__ R2) {
   const int j = blockIdx.x / k, q = blockIdx.x % k;
   const int64_t ld = voff[j + 1] - voff[j];
   const int64_t o = voff[j] * k + (int64_t)q * ld;
@@ -122,6 +151,7 @@ __global__ __launch_bounds__(256) void k_residual(int k, const int64_t* __restri
     const double bx = BX[o + r];
     const double v = AX[o + r] - th * bx;
     R[o + r] = v;
+    if (R2) R2[o + r] = v;
     s1 += v * v;
     s2 += bx * bx;
   }
@@ -141,6 +171,7 @@ __global__ __launch_bounds__(256) void k_residual(int k, const int64_t* __restri
     nrm[2 * (j * k + q) + 1] = a2[0];
   }
 }
+
 
 // Gram partials: for row range [r0, r0 + 512) of subdomain j,
 //   GA[a][b] = sum_r L[r][a] RA[r][b],  GB[a][b] = sum_r L[r][a] RB[r][b]
@@ -704,6 +735,26 @@ __global__ void k_scale_rows(int64_t len, int k, const int32_t* __restrict__ row
   out[o] = s[b] * X[o];
 }
 
+// Rows of the subdomains with pick[j] = 1 are taken from the second block set:
+// (X, AX, BX) <- (Xs, AXs, BXs) on those subdomains, all k columns.
+__global__ void k_take_rows(int64_t len, int k, const int32_t* __restrict__ row_sub, const int64_t* __restrict__ voff,
+                            const int32_t* __restrict__ pick, const double* __restrict__ Xs,
+                            const double* __restrict__ AXs, const double* __restrict__ BXs, double* __restrict__ X,
+                            double* __restrict__ AX, double* __restrict__ BX) {
+  const int64_t b = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (b >= len) return;
+  const int j = row_sub[b];
+  if (!pick[j]) return;
+  const int64_t ld = voff[j + 1] - voff[j];
+  const int64_t o = voff[j] * k + (b - voff[j]);
+  for (int q = 0; q < k; ++q) {
+    const int64_t i = o + (int64_t)q * ld;
+    X[i] = Xs[i];
+    AX[i] = AXs[i];
+    BX[i] = BXs[i];
+  }
+}
+
 // dense p x p G^T M G (M = local A or B values), one thread per (subdomain, node row a)
 __global__ void k_gmg(int64_t plen, const int32_t* __restrict__ node_sub, const int64_t* __restrict__ poff,
                       const int32_t* __restrict__ pl, const int64_t* __restrict__ ne_off,
@@ -1034,11 +1085,17 @@ static void gmul(EigWork& w, const double* Nn, const double* base, const double*
                                           Nn, base, scale, out);
 }
 
-// out = Atilde X  (tmp1, tmp2: edge blocks; nt: node block)
+// out = Atilde X  (tmp1, tmp2: edge blocks; nt: node block); with the
+// classical pencil out = D A D X
 static void apply_atilde(geneo_ctx* ctx, const geneo_precond* pc, EigWork& w, const double* X, double* out,
                          double* t1, double* t2, double* nt) {
   hipStream_t st = ctx->stream;
   const double* D = pc->d_bpou.p;
+  if (pc->opts.classical) {
+    k_scale_rows<<<nb256(w.len * w.k), 256, 0, st>>>(w.len, w.k, w.row_sub.p, w.voff_d.p, D, X, t1);
+    spmm(pc, w, nullptr, t1, nullptr, D, out, st);                   // D A D X
+    return;
+  }
   spmm(pc, w, nullptr, X, nullptr, nullptr, t1, st);                 // A X
   gt(w, t1, nt, st);                                                 // G^T A X
   solve_multi(w.node, w.S.p, w.Sinv.p, nt, w.k, w.k, ctx->d_sync, w.flags_node.p, ctx->d_err, st);
@@ -1310,6 +1367,7 @@ void solve_local_gevps(geneo_ctx* ctx, geneo_precond* pc) {
                                   (int)(sizeof(double) * 3 * kGramSub * ((mmax + 15) / 16 * 16))));
 
   // start block: warm start if given, else random; B-orthogonal projection out of span(G_j)
+  int learned = 0;
   if (pc->opts.warm_start) {
     std::vector<double> h(blk, 0.0);
     k_random_block<<<nb256(blk), 256, 0, st>>>(w.len, k, w.row_sub.p, w.voff_d.p, w.nloc.p, pc->opts.seed, X.p);
@@ -1324,12 +1382,12 @@ void solve_local_gevps(geneo_ctx* ctx, geneo_precond* pc) {
     HIP_CHECK(hipMemcpy(X.p, h.data(), sizeof(double) * blk, hipMemcpyHostToDevice));
   } else {
     k_random_block<<<nb256(blk), 256, 0, st>>>(w.len, k, w.row_sub.p, w.voff_d.p, w.nloc.p, pc->opts.seed, X.p);
-    if (pc->opts.model) pc->info.learned_starts = model_warm_start(ctx, pc->opts.model, pc, k, nev, X.p);
+    if (pc->opts.model) {
+      // the random block stays as the competing candidate (P is unused until the first iteration)
+      HIP_CHECK(hipMemcpyAsync(P.p, X.p, sizeof(double) * blk, hipMemcpyDeviceToDevice, st));
+      learned = model_warm_start(ctx, pc->opts.model, pc, k, nev, X.p);
+    }
   }
-  spmm(pc, w, w.bval.p, X.p, nullptr, nullptr, T1.p, st);        // B X
-  gt(w, T1.p, NT.p, st);
-  solve_multi(w.node, w.H.p, w.Hinv.p, NT.p, k, k, ctx->d_sync, w.flags_node.p, ctx->d_err, st);
-  gmul(w, NT.p, X.p, nullptr, X.p, st);                          // X - G H^-1 G^T B X
 
   const double drop = 1e-12;
   const int32_t* act = d_active.p;
@@ -1339,11 +1397,12 @@ void solve_local_gevps(geneo_ctx* ctx, geneo_precond* pc) {
     gram(w, 1, U, nullptr, nullptr, BV, nullptr, nullptr, BV, nullptr, nullptr, part, g, st);
     k_sub_xc<<<grows, 256, 0, st>>>(w.len, k, w.row_sub.p, w.voff_d.p, U, g.p, 2 * k * k, V);
   };
-  // B-orthonormalise V (numerically dependent columns become zero), twice
-  auto svqb2 = [&](DevBuf<double>& V, DevBuf<double>& BV, const int32_t* a) {
+  // B-orthonormalise V (numerically dependent columns become zero), twice; th receives the
+  // Gram eigenvalues (scratch)
+  auto svqb2 = [&](DevBuf<double>& V, DevBuf<double>& BV, const int32_t* a, double* th) {
     for (int t = 0; t < 2; ++t) {
       gram(w, 1, V.p, nullptr, nullptr, BV.p, nullptr, nullptr, BV.p, nullptr, nullptr, part, g, st);
-      rayleigh_ritz(N, k, k, g.p, a, drop, theta.p, coef.p, 1, st);
+      rayleigh_ritz(N, k, k, g.p, a, drop, th, coef.p, 1, st);
       k_combine<<<grows, 256, 0, st>>>(w.len, k, k, 0, w.row_sub.p, w.voff_d.p, a, V.p, nullptr, nullptr,
                                             coef.p, V.p, Tv.p);
       k_combine<<<grows, 256, 0, st>>>(w.len, k, k, 0, w.row_sub.p, w.voff_d.p, a, BV.p, nullptr, nullptr,
@@ -1352,21 +1411,93 @@ void solve_local_gevps(geneo_ctx* ctx, geneo_precond* pc) {
       BV.swap(Tb);
     }
   };
-  bmul(X.p, BX.p);
-  svqb2(X, BX, nullptr);
-  apply_atilde(ctx, pc, w, X.p, AX.p, T1.p, T2.p, NT.p);
-  gram(w, 1, X.p, nullptr, nullptr, AX.p, nullptr, nullptr, BX.p, nullptr, nullptr, part, g, st);
-  rayleigh_ritz(N, k, k, g.p, nullptr, drop, theta.p, coef.p, 0, st);
-  k_combine<<<grows, 256, 0, st>>>(w.len, k, k, 0, w.row_sub.p, w.voff_d.p, nullptr, X.p, nullptr, nullptr,
-                                        coef.p, nullptr, Xn.p);
-  X.swap(Xn);
-  // products are recomputed from the basis after every update (tracking them
-  // through the Rayleigh-Ritz coefficients drifts once the basis becomes
-  // ill-conditioned near convergence)
-  apply_atilde(ctx, pc, w, X.p, AX.p, T1.p, T2.p, NT.p);
-  bmul(X.p, BX.p);
-  HIP_CHECK(hipGetLastError());
-
+  // V <- V - G_j H_j^-1 G_j^T B V: the B-orthogonal projection out of span(G_j), the kernel of
+  // the filtered operator, in which no eigenvector with lambda > 0 has a component
+  auto deflate = [&](double* V) {
+    if (pc->opts.classical) return;   // the classical pencil is not restricted to the complement of span(G_j)
+    spmm(pc, w, w.bval.p, V, nullptr, nullptr, T1.p, st);          // B V
+    gt(w, T1.p, NT.p, st);
+    solve_multi(w.node, w.H.p, w.Hinv.p, NT.p, k, k, ctx->d_sync, w.flags_node.p, ctx->d_err, st);
+    gmul(w, NT.p, V, nullptr, V, st);
+  };
+  // start block V: projected out of span(G_j) in the B inner product, B-orthonormalised, one
+  // Rayleigh-Ritz step (Ritz values into th); AV and BV are the products of the resulting block
+  auto start_block = [&](DevBuf<double>& V, DevBuf<double>& AV, DevBuf<double>& BV, DevBuf<double>& Vn,
+                         double* th) {
+    deflate(V.p);
+    bmul(V.p, BV.p);
+    svqb2(V, BV, nullptr, th);
+    apply_atilde(ctx, pc, w, V.p, AV.p, T1.p, T2.p, NT.p);
+    gram(w, 1, V.p, nullptr, nullptr, AV.p, nullptr, nullptr, BV.p, nullptr, nullptr, part, g, st);
+    rayleigh_ritz(N, k, k, g.p, nullptr, drop, th, coef.p, 0, st);
+    k_combine<<<grows, 256, 0, st>>>(w.len, k, k, 0, w.row_sub.p, w.voff_d.p, nullptr, V.p, nullptr, nullptr,
+                                          coef.p, nullptr, Vn.p);
+    V.swap(Vn);
+    // products are recomputed from the basis after every update (tracking them
+    // through the Rayleigh-Ritz coefficients drifts once the basis becomes
+    // ill-conditioned near convergence)
+    apply_atilde(ctx, pc, w, V.p, AV.p, T1.p, T2.p, NT.p);
+    bmul(V.p, BV.p);
+  };
+  start_block(X, AX, BX, Xn, theta.p);
+  pc->info.learned_candidates = learned;
+  if (learned > 0) {
+    // The model's block is judged by its eigen-residuals: both candidates take
+    // the first Rayleigh-Ritz step, and a subdomain keeps the learned block only
+    // if the largest residual of its top min(k, nev) Ritz pairs is below half
+    // that of the random block; otherwise it continues from the random block,
+    // exactly as the cold start would.
+    DevBuf<double> theta_r, nrm_r;
+    theta_r.alloc((size_t)N * k);
+    nrm_r.alloc((size_t)N * k * 2);
+    start_block(P, AP, BP, Pn, theta_r.p);
+    k_residual<<<N * k, 256, 0, st>>>(k, w.voff_d.p, AX.p, BX.p, theta.p, Wb.p, nrm.p, nullptr);
+    k_residual<<<N * k, 256, 0, st>>>(k, w.voff_d.p, AP.p, BP.p, theta_r.p, Wb.p, nrm_r.p, nullptr);
+    std::vector<double> th_l(N * k), th_r(N * k), n_l(N * k * 2), n_r(N * k * 2);
+    HIP_CHECK(hipMemcpyAsync(th_l.data(), theta.p, sizeof(double) * N * k, hipMemcpyDeviceToHost, st));
+    HIP_CHECK(hipMemcpyAsync(th_r.data(), theta_r.p, sizeof(double) * N * k, hipMemcpyDeviceToHost, st));
+    HIP_CHECK(hipMemcpyAsync(n_l.data(), nrm.p, sizeof(double) * N * k * 2, hipMemcpyDeviceToHost, st));
+    HIP_CHECK(hipMemcpyAsync(n_r.data(), nrm_r.p, sizeof(double) * N * k * 2, hipMemcpyDeviceToHost, st));
+    HIP_CHECK(hipStreamSynchronize(st));
+    // Compared: the largest residual over the pairs that decide the coarse space, the Ritz values
+    // above tau (at most nev) of either candidate plus the next one.  A column without B-norm
+    // (dropped as dependent) has no residual: infinitely bad.
+    const double tau_sel = pc->opts.tau;
+    const int kq = std::min(k, nev);
+    auto nabove = [&](const std::vector<double>& th, int j) {
+      int c = 0;
+      while (c < kq && th[j * k + c] > tau_sel) ++c;
+      return c;
+    };
+    auto worst = [&](const std::vector<double>& th, const std::vector<double>& nr, int j, int m) {
+      double r = 0.0;
+      for (int q = 0; q < m; ++q) {
+        const double a = nr[2 * (j * k + q)], b = nr[2 * (j * k + q) + 1];
+        const double den = std::fabs(th[j * k + q]) * std::sqrt(b);
+        r = std::max(r, den > 0.0 ? std::sqrt(a) / den : HUGE_VAL);
+      }
+      return r;
+    };
+    std::vector<int32_t> pick(N, 0);
+    int kept = 0;
+    for (int j = 0; j < N; ++j) {
+      const int m = std::min(kq, std::max(nabove(th_l, j), nabove(th_r, j)) + 1);
+      const bool keep = worst(th_l, n_l, j, m) < 0.5 * worst(th_r, n_r, j, m);
+      pick[j] = keep ? 0 : 1;
+      kept += keep ? 1 : 0;
+      if (!keep) std::copy(th_r.begin() + j * k, th_r.begin() + (j + 1) * k, th_l.begin() + j * k);
+    }
+    learned = kept;
+    if (kept < N) {
+      DevBuf<int32_t> d_pick;
+      d_pick.upload(pick, st);
+      k_take_rows<<<nb256(w.len), 256, 0, st>>>(w.len, k, w.row_sub.p, w.voff_d.p, d_pick.p, P.p, AP.p, BP.p, X.p,
+                                                AX.p, BX.p);
+      HIP_CHECK(hipMemcpyAsync(theta.p, th_l.data(), sizeof(double) * N * k, hipMemcpyHostToDevice, st));
+      HIP_CHECK(hipStreamSynchronize(st));
+    }
+  }
+  pc->info.learned_starts = learned;
   const double tol = pc->opts.lobpcg_tol, tau = pc->opts.tau;
   const bool verbose = std::getenv("GENEO_VERBOSE") != nullptr;
   const double cert_tol = std::max(tol, 1e-4);
@@ -1377,7 +1508,10 @@ void solve_local_gevps(geneo_ctx* ctx, geneo_precond* pc) {
   int it = 0, unconv = 0;
   const int maxit = std::max(1, pc->opts.lobpcg_maxit);
   for (it = 1; it <= maxit; ++it) {
-    k_residual<<<N * k, 256, 0, st>>>(k, w.voff_d.p, AX.p, BX.p, theta.p, Wb.p, nrm.p);
+    // Ritz values as Rayleigh quotients of the current block (the projection
+    // out of span(G_j) after the update moves them off the Rayleigh-Ritz values)
+    if (it > 1) k_rq<<<N * k, 256, 0, st>>>(k, w.voff_d.p, X.p, AX.p, BX.p, theta.p);
+    k_residual<<<N * k, 256, 0, st>>>(k, w.voff_d.p, AX.p, BX.p, theta.p, Wb.p, nrm.p, nullptr);
     HIP_CHECK(hipMemcpyAsync(h_theta.data(), theta.p, sizeof(double) * N * k, hipMemcpyDeviceToHost, st));
     HIP_CHECK(hipMemcpyAsync(h_nrm.data(), nrm.p, sizeof(double) * N * k * 2, hipMemcpyDeviceToHost, st));
     HIP_CHECK(hipStreamSynchronize(st));
@@ -1425,14 +1559,18 @@ void solve_local_gevps(geneo_ctx* ctx, geneo_precond* pc) {
                    it, n_active, n_cert, worst_sel, worst_cert);
     if (n_active == 0 || it == maxit) break;
     HIP_CHECK(hipMemcpyAsync(d_active.p, active.data(), sizeof(int32_t) * N, hipMemcpyHostToDevice, st));
-    // W = B^-1 R, B-orthogonal to X, B-orthonormal
+    // W = B^-1 R, B-orthogonal to span(G_j) and X, B-orthonormal.  In exact arithmetic
+    // G_j^T B W = G_j^T Atilde X = 0 already; B^-1 amplifies the rounding errors of R along the
+    // near-kernel of B (gradients, eigenvalues ~ gamma), so W is projected again (as are the
+    // updated X and P below).
     solve_multi(pc->local, w.LB.p, w.LBinv.p, Wb.p, k, k, ctx->d_sync, w.flags_local.p, ctx->d_err, st);
+    deflate(Wb.p);
     for (int t = 0; t < 2; ++t) {
       bmul(Wb.p, BW.p);
       orth(X.p, Wb.p, BW.p);
     }
     bmul(Wb.p, BW.p);
-    svqb2(Wb, BW, act);
+    svqb2(Wb, BW, act, theta.p);
     if (have_p) {   // P B-orthogonal to X and W, B-orthonormal
       for (int t = 0; t < 2; ++t) {
         bmul(P.p, BP.p);
@@ -1441,7 +1579,7 @@ void solve_local_gevps(geneo_ctx* ctx, geneo_precond* pc) {
         orth(Wb.p, P.p, BP.p);
       }
       bmul(P.p, BP.p);
-      svqb2(P, BP, act);
+      svqb2(P, BP, act, theta.p);
       apply_atilde(ctx, pc, w, P.p, AP.p, T1.p, T2.p, NT.p);
     }
     apply_atilde(ctx, pc, w, Wb.p, AW.p, T1.p, T2.p, NT.p);
@@ -1456,6 +1594,11 @@ void solve_local_gevps(geneo_ctx* ctx, geneo_precond* pc) {
                                           have_p ? P.p : nullptr, coef.p, have_p ? P.p : nullptr, Pn.p);
     X.swap(Xn);
     P.swap(Pn);
+    // the Ritz update mixes blocks whose gradient components rounding keeps
+    // re-creating; without this projection the residual of small-gamma
+    // problems stalls far above the rounding floor of the filtered operator
+    deflate(X.p);
+    deflate(P.p);
     apply_atilde(ctx, pc, w, X.p, AX.p, T1.p, T2.p, NT.p);
     bmul(X.p, BX.p);
     have_p = true;

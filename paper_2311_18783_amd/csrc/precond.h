@@ -68,7 +68,11 @@ struct geneo_precond {
   // work vectors
   geneo::DevBuf<double> w_b1, w_b2, w_b3;    // batch vectors
   geneo::DevBuf<double> w_n1, w_n2, w_n3, w_n4;  // length n
-  geneo::DevBuf<double> w_c1, w_c2;          // length n0_pad
+  geneo::DevBuf<double> w_c1, w_c2, w_c3;    // length n0_pad
+  // coarse columns in the factor's order: natural column c sits at position
+  // d_cperm[c] (empty: natural order); every group of the order starts at a
+  // multiple of 128, the positions in between are unit pad columns
+  geneo::DevBuf<int32_t> d_cperm;
 };
 
 namespace geneo {
@@ -78,7 +82,14 @@ void setup_precond(geneo_ctx* ctx, geneo_precond* pc);
 void apply_precond(geneo_ctx* ctx, const geneo_precond* pc, const double* r, double* z);
 void pcg(geneo_ctx* ctx, const geneo_system* sys, const geneo_precond* pc, const double* b, double* x,
          const geneo_solve_opts* o, geneo_solve_info* info);
+// right-preconditioned GMRES (restart opts->restart, 0 = none)
+void gmres(geneo_ctx* ctx, const geneo_system* sys, const geneo_precond* pc, const double* b, double* x,
+           const geneo_solve_opts* o, geneo_solve_info* info);
 void check_device_error(geneo_ctx* ctx);
+// nested-dissection order of the subdomains on their coupling graph: groups
+// (leaves and separators) in elimination order; *levels = dissection depth
+std::vector<std::vector<int32_t>> subdomain_elimination_order(const geneo_system* s, const geneo_decomp* dec,
+                                                              int* levels);
 // eigensolver (geneo_eig.hip)
 void solve_local_gevps(geneo_ctx* ctx, geneo_precond* pc);
 

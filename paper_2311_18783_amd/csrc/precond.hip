@@ -162,6 +162,11 @@ __global__ __launch_bounds__(256) void k_tile_pattern(const double* __restrict__
   if (threadIdx.x == 0) pat[ti * nb + tj] = (uint8_t)(nz ? 1 : 0);
 }
 
+__global__ void k_unit_diag(int64_t m, const int32_t* __restrict__ pos, double* __restrict__ E, int64_t ld) {
+  const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (t < m) E[(int64_t)pos[t] * ld + pos[t]] = 1.0;
+}
+
 __global__ void k_copy(int64_t n, const double* __restrict__ x, double* __restrict__ out) {
   int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (i < n) out[i] = x[i];
@@ -179,22 +184,27 @@ __global__ void k_copy_diag(const MatDesc* __restrict__ desc, const double* __re
   if (i < d.ld) od[d.diag_off + i] = A[d.off + i * d.ld + i];
 }
 
-// E (SNK x SNK) = Z^T A Z, one thread per coarse column c1 (writes column c1 only)
+// E (SNK x SNK) = Z^T A Z, one thread per coarse column c1 (writes column c1 only; with perm,
+// natural column c sits at row / column perm[c])
 __global__ void k_coarse_snk(int64_t nsnk, const int32_t* __restrict__ zc_ptr, const int32_t* __restrict__ zc_row,
                              const double* __restrict__ zc_val, const int32_t* __restrict__ rp,
                              const int32_t* __restrict__ ci, const double* __restrict__ av,
                              const int32_t* __restrict__ zr_ptr, const int32_t* __restrict__ zr_col,
-                             const double* __restrict__ zr_val, double* __restrict__ E, int64_t ld) {
+                             const double* __restrict__ zr_val, const int32_t* __restrict__ perm,
+                             double* __restrict__ E, int64_t ld) {
   int64_t c1 = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (c1 >= nsnk) return;
-  double* col = E + c1 * ld;
+  double* col = E + (perm ? perm[c1] : c1) * ld;
   for (int32_t k1 = zc_ptr[c1]; k1 < zc_ptr[c1 + 1]; ++k1) {
     const int32_t e = zc_row[k1];
     const double z1 = zc_val[k1];
     for (int32_t s = rp[e]; s < rp[e + 1]; ++s) {
       const int32_t f = ci[s];
       const double a = av[s] * z1;
-      for (int32_t k2 = zr_ptr[f]; k2 < zr_ptr[f + 1]; ++k2) col[zr_col[k2]] += a * zr_val[k2];
+      for (int32_t k2 = zr_ptr[f]; k2 < zr_ptr[f + 1]; ++k2) {
+        const int32_t c2 = zr_col[k2];
+        col[perm ? perm[c2] : c2] += a * zr_val[k2];
+      }
     }
   }
 }
@@ -256,7 +266,14 @@ __global__ void k_coarse_gen(int64_t nsnk, int64_t n, const int32_t* __restrict_
                              const int32_t* __restrict__ cand, const int64_t* __restrict__ voff,
                              const int32_t* __restrict__ nloc, const int64_t* __restrict__ woff,
                              const int32_t* __restrict__ bmap, const double* __restrict__ W,
-                             const double* __restrict__ Y, double* __restrict__ E, int64_t ld) {
+                             const double* __restrict__ Y, const int32_t* __restrict__ perm,
+                             double* __restrict__ E, int64_t ld) {
+  // lower-triangle entry (r, c) of the natural order, r >= c, at its place in the factor's order
+  auto at = [&](int64_t r, int64_t c) -> double& {
+    if (!perm) return E[c * ld + r];
+    const int64_t pr = perm[r], pc = perm[c];
+    return pr >= pc ? E[pc * ld + pr] : E[pr * ld + pc];
+  };
   const int64_t g = blockIdx.y;
   int j = 0, hi = nsub - 1;   // subdomain of GenEO column g
   while (j < hi) {
@@ -271,7 +288,7 @@ __global__ void k_coarse_gen(int64_t nsnk, int64_t n, const int32_t* __restrict_
   if (c1 < nsnk) {
     double acc = 0.0;
     for (int32_t k = zc_ptr[c1]; k < zc_ptr[c1 + 1]; ++k) acc += zc_val[k] * y[zc_row[k]];
-    E[c1 * ld + cg] = acc;          // row cg > c1, column c1
+    at(cg, c1) = acc;               // row cg > c1, column c1
     return;
   }
   if (c1 < cg) return;              // upper triangle: not needed
@@ -288,7 +305,7 @@ __global__ void k_coarse_gen(int64_t nsnk, int64_t n, const int32_t* __restrict_
   const int32_t* bm = bmap + voff[lo];
   double acc = 0.0;
   for (int64_t r = 0; r < nloc[lo]; ++r) acc += w[r] * y[bm[r]];
-  E[cg * ld + c1] = acc;            // row c1 >= cg, column cg
+  at(c1, cg) = acc;                 // row c1 >= cg, column cg
 }
 
 // Host side of the support restriction (k_spmm_ring / k_coarse_gen).
@@ -328,16 +345,28 @@ static GenSupport gen_support(const geneo_system* s, const geneo_decomp* dec, co
     }
     g.ring_ptr[j + 1] = (int32_t)g.ring.size();
   }
-  // coarse columns per subdomain: SNK ranges (subdomain-major), GenEO ranges
+  // coarse columns per subdomain: SNK ranges (subdomain-major), GenEO ranges;
+  // columns that belong to no subdomain (global near-kernel, col_sub = -1)
+  // are candidates of every GenEO column
   std::vector<int64_t> snk_beg(N + 1, 0);
-  for (int64_t c = 0; c < nsnk; ++c) snk_beg[col_sub[c] + 1]++;
+  std::vector<int32_t> unowned;
+  for (int64_t c = 0; c < nsnk; ++c) {
+    if (col_sub[c] < 0)
+      unowned.push_back((int32_t)c);
+    else
+      snk_beg[col_sub[c] + 1]++;
+  }
   for (int i = 0; i < N; ++i) snk_beg[i + 1] += snk_beg[i];
+  if (!unowned.empty() && (int64_t)unowned.size() != nsnk)
+    throw Error(GENEO_EINVAL, "coarse columns: owned and global columns mixed");
   g.cand_ptr.assign(N + 1, 0);
   for (int j = 0; j < N; ++j) {
+    if (gen_cnt[j] > 0) g.cand.insert(g.cand.end(), unowned.begin(), unowned.end());
     if (gen_cnt[j] > 0)
       for (int i = 0; i < N; ++i) {
         if (!((adj[(size_t)j * Wd + i / 64] >> (i % 64)) & 1)) continue;
-        for (int64_t c = snk_beg[i]; c < snk_beg[i + 1]; ++c) g.cand.push_back((int32_t)c);
+        if (unowned.empty())
+          for (int64_t c = snk_beg[i]; c < snk_beg[i + 1]; ++c) g.cand.push_back((int32_t)c);
         for (int64_t c = gen_off[i]; c < gen_off[i + 1]; ++c) g.cand.push_back((int32_t)(nsnk + c));
       }
     g.cand_ptr[j + 1] = (int32_t)g.cand.size();
@@ -634,8 +663,8 @@ static void fp32_probe(geneo_ctx* ctx, geneo_precond* pc, const std::vector<MatD
     return f;
   };
   const int32_t f32 = renumber(d32), f64 = renumber(d64);
-  if (!d32.empty()) pc->local32.build(d32, st);
-  pc->local64.build(d64, st);
+  if (!d32.empty()) pc->local32.build(d32, st, GENEO_FP32_REFINE1);
+  pc->local64.build(d64, st, GENEO_FP64);
   pc->local32.solve_form = pc->local64.solve_form = false;
   (void)f32;
   (void)f64;
@@ -816,6 +845,50 @@ struct HostClock {
   }
 };
 
+// Global near-kernel columns Z = G (Section 4, Numerical results, the NK
+// variants): one column per free node, -1 / +1 on the free edges that leave /
+// enter it; no subdomain owns a column (col_sub = -1).
+static void build_nk_host(const geneo_system* s, SnkHost& h) {
+  const int64_t n = s->n, p = s->n_free_nodes;
+  std::vector<int32_t> cnt(p + 1, 0);
+  for (int64_t fe = 0; fe < n; ++fe) {
+    const int32_t e = s->free_edges[fe];
+    for (int q = 0; q < 2; ++q) {
+      const int32_t v = s->node_to_free[s->edges[2 * (int64_t)e + q]];
+      if (v >= 0) cnt[v + 1]++;
+    }
+  }
+  for (int64_t v = 0; v < p; ++v) cnt[v + 1] += cnt[v];
+  h.zc_ptr = cnt;
+  h.zc_row.assign(cnt[p], 0);
+  h.zc_val.assign(cnt[p], 0.0);
+  std::vector<int32_t> f(cnt.begin(), cnt.end() - 1);
+  for (int64_t fe = 0; fe < n; ++fe) {   // rows ascending within every column
+    const int32_t e = s->free_edges[fe];
+    for (int q = 0; q < 2; ++q) {
+      const int32_t v = s->node_to_free[s->edges[2 * (int64_t)e + q]];
+      if (v < 0) continue;
+      h.zc_row[f[v]] = (int32_t)fe;
+      h.zc_val[f[v]++] = q == 0 ? -1.0 : 1.0;
+    }
+  }
+  h.col_node.resize(p);
+  for (int64_t v = 0; v < p; ++v) h.col_node[v] = (int32_t)v;
+  h.col_sub.assign(p, -1);
+  h.n_all = (int32_t)p;
+  h.zr_ptr.assign(n + 1, 0);
+  h.zr_col.resize(h.zc_row.size());
+  h.zr_val.resize(h.zc_row.size());
+  for (auto e : h.zc_row) h.zr_ptr[e + 1]++;
+  for (int64_t e = 0; e < n; ++e) h.zr_ptr[e + 1] += h.zr_ptr[e];
+  std::vector<int32_t> g(h.zr_ptr.begin(), h.zr_ptr.end() - 1);
+  for (int64_t c = 0; c < p; ++c)
+    for (int32_t k = h.zc_ptr[c]; k < h.zc_ptr[c + 1]; ++k) {
+      h.zr_col[g[h.zc_row[k]]] = (int32_t)c;
+      h.zr_val[g[h.zc_row[k]]++] = h.zc_val[k];
+    }
+}
+
 void setup_precond(geneo_ctx* ctx, geneo_precond* pc) {
   HostClock hc;
   hipStream_t st = ctx->stream;
@@ -827,6 +900,13 @@ void setup_precond(geneo_ctx* ctx, geneo_precond* pc) {
   pc->precision = pc->opts.local_precision;
   if (pc->precision != GENEO_FP64 && pc->precision != GENEO_FP32_REFINE1)
     throw Error(GENEO_EINVAL, "unknown local precision");
+  if (pc->opts.coarse < GENEO_COARSE_SNK_GENEO || pc->opts.coarse > GENEO_COARSE_NK_GENEO)
+    throw Error(GENEO_EINVAL, "unknown coarse space");
+  if (pc->opts.one_level_weight != GENEO_WEIGHT_IDENTITY && pc->opts.one_level_weight != GENEO_WEIGHT_POU)
+    throw Error(GENEO_EINVAL, "unknown one-level weight");
+  if (pc->opts.classical != 0 && pc->opts.classical != 1) throw Error(GENEO_EINVAL, "classical must be 0 or 1");
+  const bool nk = pc->opts.coarse == GENEO_COARSE_NK || pc->opts.coarse == GENEO_COARSE_NK_GENEO;
+  const bool with_geneo = pc->opts.coarse == GENEO_COARSE_SNK_GENEO || pc->opts.coarse == GENEO_COARSE_NK_GENEO;
 
   // ---- batch layout of the local matrices
   std::vector<MatDesc> descs(N);
@@ -848,7 +928,7 @@ void setup_precond(geneo_ctx* ctx, geneo_precond* pc) {
   pc->voff[N] = voff;
   pc->batch_len = voff;
   pc->info.local_factor_flops = flops;
-  pc->local.build(descs, st);
+  pc->local.build(descs, st, pc->precision);
   pc->local.solve_form = false;   // bandwidth-bound local solves: no premultiplied blocks
   hc.mark("layout + local plan");
   pc->d_flags_local.alloc(flag_off);
@@ -938,10 +1018,20 @@ void setup_precond(geneo_ctx* ctx, geneo_precond* pc) {
   SnkHost snk;
   std::exception_ptr snk_err;
   std::thread snk_thread;
+  std::vector<std::vector<int32_t>> sub_order;   // elimination order of the subdomain groups of coarse columns
+  int nd_levels = 0;
+  if (pc->opts.coarse_order != GENEO_ORDER_NESTED_DISSECTION && pc->opts.coarse_order != GENEO_ORDER_NATURAL)
+    throw Error(GENEO_EINVAL, "unknown coarse order");
   if (pc->opts.coarse != GENEO_COARSE_NONE)
     snk_thread = std::thread([&] {
       try {
-        build_snk_host(s, dec, snk);
+        if (nk)
+          build_nk_host(s, snk);
+        else
+          build_snk_host(s, dec, snk);
+        // NK columns belong to no subdomain: natural order
+        if (pc->opts.coarse_order == GENEO_ORDER_NESTED_DISSECTION && !nk)
+          sub_order = subdomain_elimination_order(s, dec, &nd_levels);
       } catch (...) {
         snk_err = std::current_exception();
       }
@@ -1024,7 +1114,7 @@ void setup_precond(geneo_ctx* ctx, geneo_precond* pc) {
   pc->gen_off.assign(N + 1, 0);
   pc->eigs.assign(N, {});
   pc->eig_sel.assign(N, 0);
-  if (pc->opts.coarse == GENEO_COARSE_SNK_GENEO) {
+  if (with_geneo) {
     HIP_CHECK(hipEventRecord(ctx->ev[0], st));
     solve_local_gevps(ctx, pc);
     HIP_CHECK(hipEventRecord(ctx->ev[1], st));
@@ -1074,10 +1164,37 @@ void setup_precond(geneo_ctx* ctx, geneo_precond* pc) {
   pc->d_zr_col.upload(zr_col, st);
   pc->d_zr_val.upload(zr_val, st);
 
+  // ---- order of the coarse columns in the factor: the subdomains of every
+  // nested-dissection group with their SNK columns, then their GenEO columns;
+  // each group starts at a multiple of 128 (unit pad columns in between), so
+  // groups that the dissection separates share no 128 x 128 tile
+  std::vector<int32_t> pad_pos;
+  int64_t n0_fac = pc->n0;          // order size with the pads
+  if (!sub_order.empty()) {
+    std::vector<int64_t> snk_beg(N + 1, 0);
+    for (int32_t c = 0; c < pc->n_snk; ++c) snk_beg[col_sub[c] + 1]++;
+    for (int32_t i = 0; i < N; ++i) snk_beg[i + 1] += snk_beg[i];
+    std::vector<int32_t> perm(pc->n0, -1);
+    int64_t pos = 0;
+    for (const auto& grp : sub_order) {
+      for (int32_t i : grp) {
+        for (int64_t c = snk_beg[i]; c < snk_beg[i + 1]; ++c) perm[c] = (int32_t)pos++;
+        for (int32_t q = 0; q < pc->gen_cnt[i]; ++q) perm[pc->n_snk + pc->gen_off[i] + q] = (int32_t)pos++;
+      }
+      while (pos % NB) pad_pos.push_back((int32_t)pos++);
+    }
+    for (int32_t c = 0; c < pc->n0; ++c)
+      if (perm[c] < 0) throw Error(GENEO_EINVAL, "coarse order does not cover every column");
+    n0_fac = pos;
+    pc->d_cperm.upload(perm, st);
+    pc->info.coarse_nd_levels = nd_levels;
+  }
+  const int32_t* cperm = pc->d_cperm.p;
+
   // ---- E = Z^T A Z (dense FP64), then Cholesky with dependent columns left out
   const int64_t n0 = pc->n0;
-  const int64_t n0p = round_up(std::max<int64_t>(n0, 1), NB);
-  std::vector<MatDesc> cd(1, MatDesc{0, 0, 0, 0, (int32_t)n0p, (int32_t)(n0p / NB), 0, (int32_t)n0});
+  const int64_t n0p = round_up(std::max<int64_t>(n0_fac, 1), NB);
+  std::vector<MatDesc> cd(1, MatDesc{0, 0, 0, 0, (int32_t)n0p, (int32_t)(n0p / NB), 0, (int32_t)n0_fac});
   pc->coarse.build(cd, st);
   pc->dE.alloc(n0p * n0p);
   pc->dEinv.alloc(2 * n0p * NB);
@@ -1087,12 +1204,22 @@ void setup_precond(geneo_ctx* ctx, geneo_precond* pc) {
   pc->w_c2.alloc(n0p);
   HIP_CHECK(hipMemsetAsync(pc->w_c1.p, 0, sizeof(double) * n0p, st));
   HIP_CHECK(hipMemsetAsync(pc->w_c2.p, 0, sizeof(double) * n0p, st));
+  if (cperm) {
+    pc->w_c3.alloc(n0p);
+    HIP_CHECK(hipMemsetAsync(pc->w_c3.p, 0, sizeof(double) * n0p, st));
+  }
   HIP_CHECK(hipEventRecord(ctx->ev[0], st));
   k_fill_identity_pad<<<fill_grid(cd), 256, 0, st>>>(pc->coarse.d_desc.p, pc->dE.p, nullptr);
+  if (!pad_pos.empty()) {   // pad columns between the groups of the order: unit diagonal
+    DevBuf<int32_t> d_pad;
+    d_pad.upload(pad_pos, st);
+    k_unit_diag<<<nblocks((int64_t)pad_pos.size()), 256, 0, st>>>((int64_t)pad_pos.size(), d_pad.p, pc->dE.p, n0p);
+    HIP_CHECK(hipStreamSynchronize(st));
+  }
   if (pc->n_snk)
     k_coarse_snk<<<nblocks(pc->n_snk), 256, 0, st>>>(pc->n_snk, pc->d_zc_ptr.p, pc->d_zc_row.p, pc->d_zc_val.p,
                                                       s->d_rowptr.p, s->d_colind.p, s->d_val.p, pc->d_zr_ptr.p,
-                                                      pc->d_zr_col.p, pc->d_zr_val.p, pc->dE.p, n0p);
+                                                      pc->d_zr_col.p, pc->d_zr_val.p, cperm, pc->dE.p, n0p);
   if (pc->n_gen) {
     // global dense GenEO columns and Y = A Z_gen
     DevBuf<double> Zg, Y;
@@ -1118,7 +1245,7 @@ void setup_precond(geneo_ctx* ctx, geneo_precond* pc) {
     if (sup.max_cand > 0)
       k_coarse_gen<<<dim3((unsigned)((sup.max_cand + 255) / 256), (unsigned)pc->n_gen), 256, 0, st>>>(
           pc->n_snk, n, pc->d_zc_ptr.p, pc->d_zc_row.p, pc->d_zc_val.p, N, pc->d_gen_off.p, d_cand_ptr.p, d_cand.p,
-          pc->d_voff.p, pc->d_n.p, pc->d_w_off.p, pc->d_bmap.p, pc->d_W.p, Y.p, pc->dE.p, n0p);
+          pc->d_voff.p, pc->d_n.p, pc->d_w_off.p, pc->d_bmap.p, pc->d_W.p, Y.p, cperm, pc->dE.p, n0p);
     HIP_CHECK(hipStreamSynchronize(st));
   }
   HIP_CHECK(hipGetLastError());
@@ -1153,6 +1280,14 @@ void setup_precond(geneo_ctx* ctx, geneo_precond* pc) {
     hc.mark("coarse plan");
     pc->info.coarse_factor_flops = pc->coarse.sparse_flops;
     pc->info.coarse_fill = (double)pc->coarse.fill_tiles / ((double)nbc * (nbc + 1) / 2);
+    std::vector<int32_t> depth(nbc, 1);
+    int32_t dmax = nbc ? 1 : 0;
+    for (int I = 0; I < nbc; ++I) {
+      for (int J = 0; J < I; ++J)
+        if (pat[(size_t)I * nbc + J]) depth[I] = std::max(depth[I], depth[J] + 1);
+      dmax = std::max(dmax, depth[I]);
+    }
+    pc->info.coarse_solve_depth = dmax;
   }
   factor(pc->coarse, pc->dE.p, pc->dEinv.p, pc->d_odiag.p, pc->opts.coarse_drop_tol, pc->d_pivrel.p, ctx->d_err, st);
   HIP_CHECK(hipEventRecord(ctx->ev[2], st));
@@ -1162,9 +1297,15 @@ void setup_precond(geneo_ctx* ctx, geneo_precond* pc) {
   check_device_error(ctx);
   std::vector<double> piv(n0p);
   HIP_CHECK(hipMemcpy(piv.data(), pc->d_pivrel.p, sizeof(double) * n0p, hipMemcpyDeviceToHost));
+  std::vector<int32_t> hperm;
+  if (cperm) {
+    hperm.resize(n0);
+    HIP_CHECK(hipMemcpy(hperm.data(), cperm, sizeof(int32_t) * n0, hipMemcpyDeviceToHost));
+  }
   int32_t kept = 0;
   double mink = 1e300, maxd = 0.0;
-  for (int64_t c = 0; c < n0; ++c) {
+  for (int64_t c0 = 0; c0 < n0; ++c0) {
+    const int64_t c = cperm ? hperm[c0] : c0;   // pivots are in the factor's order
     if (piv[c] > pc->opts.coarse_drop_tol) {
       ++kept;
       mink = std::min(mink, piv[c]);
@@ -1187,12 +1328,32 @@ __global__ void k_fill(int64_t n, double v, double* __restrict__ x) {
   if (i < n) x[i] = v;
 }
 
+// y[perm[i]] = x[i] (forward) or x[i] = y[perm[i]] (back), i < n
+__global__ void k_permute(int64_t n, const int32_t* __restrict__ perm, int back, double* __restrict__ x,
+                          double* __restrict__ y) {
+  int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  if (back)
+    x[i] = y[perm[i]];
+  else
+    y[perm[i]] = x[i];
+}
+
 static void coarse_solve(geneo_ctx* ctx, const geneo_precond* pc, double* c) {
   // pad rows of the coarse vector carry no data: clear them so that nothing
   // left there by an earlier call (e.g. a non-finite input) reaches the solve
   const int64_t n0p = pc->coarse.h_desc[0].ld;
-  if (n0p > pc->n0) k_fill<<<nblocks(n0p - pc->n0), 256, 0, ctx->stream>>>(n0p - pc->n0, 0.0, c + pc->n0);
-  solve(pc->coarse, pc->dE.p, pc->dEinv.p, c, ctx->d_sync, ctx->d_err, ctx->stream);
+  hipStream_t st = ctx->stream;
+  if (pc->d_cperm.p) {   // the factor's order, pads between its groups
+    double* v = pc->w_c3.p;
+    k_fill<<<nblocks(n0p), 256, 0, st>>>(n0p, 0.0, v);
+    k_permute<<<nblocks(pc->n0), 256, 0, st>>>(pc->n0, pc->d_cperm.p, 0, c, v);
+    solve(pc->coarse, pc->dE.p, pc->dEinv.p, v, ctx->d_sync, ctx->d_err, st);
+    k_permute<<<nblocks(pc->n0), 256, 0, st>>>(pc->n0, pc->d_cperm.p, 1, c, v);
+    return;
+  }
+  if (n0p > pc->n0) k_fill<<<nblocks(n0p - pc->n0), 256, 0, st>>>(n0p - pc->n0, 0.0, c + pc->n0);
+  solve(pc->coarse, pc->dE.p, pc->dEinv.p, c, ctx->d_sync, ctx->d_err, st);
 }
 
 // b <- A_i^-1 b on every segment; FP32 factors get one FP64 refinement step
@@ -1245,13 +1406,26 @@ static void z_forward(const geneo_precond* pc, const double* c, const double* ad
   k_csr<<<nblocks(n), 256, 0, st>>>(n, pc->d_zr_ptr.p, pc->d_zr_col.p, pc->d_zr_val.p, c, base, u);
 }
 
+// x <- w .* x (the restricted one-level term: D_i on every local solution)
+__global__ void k_mul(int64_t n, const double* __restrict__ w, double* __restrict__ x) {
+  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i < n) x[i] *= w[i];
+}
+
+// b <- A_i^-1 b on every segment, times D_i with the restricted one-level term
+static void local_term(geneo_ctx* ctx, const geneo_precond* pc, double* b) {
+  local_solve(ctx, pc, b);
+  if (pc->opts.one_level_weight == GENEO_WEIGHT_POU)
+    k_mul<<<nblocks(pc->batch_len), 256, 0, ctx->stream>>>(pc->batch_len, pc->d_bpou.p, b);
+}
+
 void apply_precond(geneo_ctx* ctx, const geneo_precond* pc, const double* r, double* z) {
   hipStream_t st = ctx->stream;
   const int64_t n = pc->sys->n;
   double* y = pc->w_n1.p;
   if (pc->n0 == 0) {
     k_gather<<<nblocks(pc->batch_len), 256, 0, st>>>(pc->batch_len, pc->d_bmap.p, r, pc->w_b1.p);
-    local_solve(ctx, pc, pc->w_b1.p);
+    local_term(ctx, pc, pc->w_b1.p);
     k_scatter_add<<<nblocks(n), 256, 0, st>>>(n, pc->d_inv_ptr.p, pc->d_inv_idx.p, pc->w_b1.p, nullptr, 1.0, z);
     return;
   }
@@ -1266,7 +1440,7 @@ void apply_precond(geneo_ctx* ctx, const geneo_precond* pc, const double* r, dou
   k_axpby<<<nblocks(n), 256, 0, st>>>(n, 1.0, r, -1.0, pc->w_n3.p, pc->w_n2.p);
   // y = sum_i R_i^T A_i^-1 R_i r1
   k_gather<<<nblocks(pc->batch_len), 256, 0, st>>>(pc->batch_len, pc->d_bmap.p, pc->w_n2.p, pc->w_b1.p);
-  local_solve(ctx, pc, pc->w_b1.p);
+  local_term(ctx, pc, pc->w_b1.p);
   k_scatter_add<<<nblocks(n), 256, 0, st>>>(n, pc->d_inv_ptr.p, pc->d_inv_idx.p, pc->w_b1.p, nullptr, 1.0, y);
   // c2 = E^-1 Z^T A y
   launch_spmv(pc->sys, y, pc->w_n3.p, st);
@@ -1366,7 +1540,7 @@ void pcg(geneo_ctx* ctx, const geneo_system* sys, const geneo_precond* pc, const
   HIP_CHECK(hipStreamSynchronize(st));
   const double bnorm = std::sqrt(h[4]);
   const double tol = o->rtol * bnorm;
-  int it = 0;
+  int it = 0, replays = 0;
   double rel = 1.0;
   bool conv = bnorm == 0.0;
   if (!conv) {
@@ -1393,10 +1567,13 @@ void pcg(geneo_ctx* ctx, const geneo_system* sys, const geneo_precond* pc, const
       HIP_CHECK(hipMemcpyAsync(h + 2, S.p + 2, 4 * sizeof(double), hipMemcpyDeviceToHost, st));
     };
     tail(1);
+    bool fresh = true;    // the next head() follows an explicit tail (first step, or a restart)
+    int replaced = 0;
     for (it = 1; it <= o->maxit; ++it) {
-      if (it == 1 || !use_graph) {
-        if (it > 1) tail(0);
+      if (fresh || !use_graph) {
+        if (!fresh) tail(0);
         head();
+        fresh = false;
       } else {
         if (!exec) {
           // one iteration as a graph: kernel nodes and the copy of ||r||^2
@@ -1407,6 +1584,7 @@ void pcg(geneo_ctx* ctx, const geneo_system* sys, const geneo_precond* pc, const
           HIP_CHECK(hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0));
         }
         HIP_CHECK(hipGraphLaunch(exec, st));
+        ++replays;
       }
       HIP_CHECK(hipGetLastError());
       HIP_CHECK(hipStreamSynchronize(st));
@@ -1415,23 +1593,234 @@ void pcg(geneo_ctx* ctx, const geneo_system* sys, const geneo_precond* pc, const
       if (h[5] != 0.0) break;
       rel = std::sqrt(h[2]) / bnorm;
       if (std::sqrt(h[2]) <= tol) {
+        // the recurrence residual can drift from b - A x (finite precision,
+        // an inexactly applied preconditioner): compute the true residual;
+        // with opts->true_residual, continue from it with a fresh direction
+        // while it misses the tolerance (at most twice)
+        launch_spmv(sys, x, q.p, st);
+        k_axpby<<<nblocks(n), 256, 0, st>>>(n, 1.0, b, -1.0, q.p, q.p);
+        dot(q.p, q.p, n, part.p, S.p + 6, st);
+        HIP_CHECK(hipMemcpyAsync(h + 6, S.p + 6, sizeof(double), hipMemcpyDeviceToHost, st));
+        HIP_CHECK(hipStreamSynchronize(st));
+        info->true_rel_residual = std::sqrt(h[6]) / bnorm;
         conv = true;
-        break;
+        if (!o->true_residual || std::sqrt(h[6]) <= tol) break;
+        if (replaced >= 2) {
+          conv = false;
+          break;
+        }
+        ++replaced;
+        HIP_CHECK(hipMemcpyAsync(r.p, q.p, sizeof(double) * n, hipMemcpyDeviceToDevice, st));
+        tail(1);
+        fresh = true;
+        conv = false;
       }
     }
+    info->residual_replacements = replaced;
   }
   HIP_CHECK(hipEventRecord(ctx->ev[1], st));
   info->solve_ms = elapsed(ctx, 0, 1);
-  info->iterations = conv ? (it > o->maxit ? o->maxit : it) : o->maxit;
+  info->iterations = std::min(it, o->maxit);
   if (bnorm == 0.0) info->iterations = 0;
   info->rel_residual = bnorm == 0.0 ? 0.0 : rel;
-  info->graph_replays = exec ? std::max(0, std::min(it, o->maxit) - 1) : 0;
+  info->graph_replays = replays;
   if (use_graph) {
     HIP_CHECK(hipEventRecord(ev_out, st));
     HIP_CHECK(hipStreamWaitEvent(user, ev_out, 0));
   }
   check_device_error(ctx);
-  if (!conv) throw Error(GENEO_ENOCONV, "PCG did not reach rtol in maxit iterations");
+  if (!conv)
+    throw Error(GENEO_ENOCONV, info->residual_replacements >= 2
+                                   ? "PCG: the true residual stays above rtol after two restarts from it"
+                                   : "PCG did not reach rtol in maxit iterations");
+}
+
+
+// ---------------------------------------------------------------- GMRES
+
+// part[c * kDotBlocks + b] = sum over block b's rows of V[:, c] . w, c < kc
+__global__ __launch_bounds__(256) void k_gemv_t_partial(int64_t n, int kc, const double* __restrict__ V, int64_t ldv,
+                                                        const double* __restrict__ w, double* __restrict__ part) {
+  __shared__ double s[256];
+  for (int c = 0; c < kc; ++c) {
+    const double* v = V + (int64_t)c * ldv;
+    double acc = 0.0;
+    for (int64_t i = blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)kDotBlocks * 256) acc += v[i] * w[i];
+    s[threadIdx.x] = acc;
+    __syncthreads();
+    for (int o = 128; o > 0; o >>= 1) {
+      if (threadIdx.x < o) s[threadIdx.x] += s[threadIdx.x + o];
+      __syncthreads();
+    }
+    if (threadIdx.x == 0) part[(int64_t)c * kDotBlocks + blockIdx.x] = s[0];
+    __syncthreads();
+  }
+}
+
+// h[c] (+)= sum_b part[c * kDotBlocks + b]; one workgroup per column
+__global__ __launch_bounds__(kDotBlocks) void k_gemv_t_final(const double* __restrict__ part, int accumulate,
+                                                              double* __restrict__ h) {
+  __shared__ double s[kDotBlocks];
+  const int c = blockIdx.x;
+  s[threadIdx.x] = part[(int64_t)c * kDotBlocks + threadIdx.x];
+  __syncthreads();
+  for (int o = kDotBlocks / 2; o > 0; o >>= 1) {
+    if (threadIdx.x < o) s[threadIdx.x] += s[threadIdx.x + o];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) h[c] = accumulate ? h[c] + s[0] : s[0];
+}
+
+// w = beta w - sum_{c < kc} V[:, c] y[c]   (beta = 1: orthogonalisation; beta = 0: w = -V y)
+__global__ void k_gemv_n(int64_t n, int kc, const double* __restrict__ V, int64_t ldv, const double* __restrict__ y,
+                         double beta, double* __restrict__ w) {
+  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  double acc = 0.0;
+  for (int c = 0; c < kc; ++c) acc += V[(int64_t)c * ldv + i] * y[c];
+  w[i] = (beta != 0.0 ? beta * w[i] : 0.0) - acc;
+}
+
+// out = a x   (a read from the device scalar *ap, inverted when inv = 1)
+__global__ void k_scale_dev(int64_t n, const double* __restrict__ ap, int inv, const double* __restrict__ x,
+                            double* __restrict__ out) {
+  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const double a = inv ? 1.0 / sqrt(ap[0]) : ap[0];
+  out[i] = a * x[i];
+}
+
+void gmres(geneo_ctx* ctx, const geneo_system* sys, const geneo_precond* pc, const double* b, double* x,
+           const geneo_solve_opts* o, geneo_solve_info* info) {
+  const int64_t n = sys->n;
+  hipStream_t st = ctx->stream;
+  const int m = o->restart > 0 ? std::min(o->restart, o->maxit) : o->maxit;
+  DevBuf<double> V, w, z, part, hv, nrm;
+  V.alloc((size_t)n * (m + 1));
+  w.alloc(n);
+  z.alloc(n);
+  part.alloc((size_t)kDotBlocks * (m + 1));
+  hv.alloc(m + 2);
+  nrm.alloc(2);
+  std::vector<double> hh(m + 2);
+  auto precond = [&](const double* in, double* out) {
+    if (pc)
+      apply_precond(ctx, pc, in, out);
+    else
+      k_copy<<<nblocks(n), 256, 0, st>>>(n, in, out);
+  };
+  auto host_scalar = [&](const double* dev) {
+    double v = 0.0;
+    HIP_CHECK(hipMemcpyAsync(&v, dev, sizeof(double), hipMemcpyDeviceToHost, st));
+    HIP_CHECK(hipStreamSynchronize(st));
+    return v;
+  };
+  HIP_CHECK(hipEventRecord(ctx->ev[0], st));
+  HIP_CHECK(hipMemsetAsync(x, 0, sizeof(double) * n, st));
+  dot(b, b, n, part.p, nrm.p, st);
+  const double bnorm = std::sqrt(host_scalar(nrm.p));
+  const double tol = o->rtol * bnorm;
+  int it = 0;
+  double res = bnorm;
+  bool conv = bnorm == 0.0;
+  // H column-major (m+1) x m, Givens cosines / sines, rotated right-hand side
+  std::vector<double> H((size_t)(m + 1) * m), cs(m), sn(m), g(m + 1);
+  while (!conv && it < o->maxit) {
+    // r = b - A x into V[:, 0] (x = 0 on the first cycle: r = b)
+    double* v0 = V.p;
+    if (it == 0) {
+      HIP_CHECK(hipMemcpyAsync(v0, b, sizeof(double) * n, hipMemcpyDeviceToDevice, st));
+    } else {
+      launch_spmv(sys, x, w.p, st);
+      k_axpby<<<nblocks(n), 256, 0, st>>>(n, 1.0, b, -1.0, w.p, v0);
+    }
+    dot(v0, v0, n, part.p, nrm.p, st);
+    // a cycle starts from the true residual; only an exact solution ends it here
+    const double beta = std::sqrt(host_scalar(nrm.p));
+    res = beta;
+    if (beta == 0.0) {
+      conv = true;
+      break;
+    }
+    k_scale_dev<<<nblocks(n), 256, 0, st>>>(n, nrm.p, 1, v0, v0);
+    std::fill(H.begin(), H.end(), 0.0);
+    std::fill(g.begin(), g.end(), 0.0);
+    g[0] = beta;
+    int kd = 0;
+    for (int k = 0; k < m && it < o->maxit; ++k) {
+      ++it;
+      const double* vk = V.p + (int64_t)k * n;
+      precond(vk, z.p);
+      launch_spmv(sys, z.p, w.p, st);
+      // classical Gram-Schmidt against V[:, 0..k], twice
+      for (int pass = 0; pass < 2; ++pass) {
+        k_gemv_t_partial<<<kDotBlocks, 256, 0, st>>>(n, k + 1, V.p, n, w.p, part.p);
+        k_gemv_t_final<<<k + 1, kDotBlocks, 0, st>>>(part.p, pass, hv.p);
+        // w -= V h (the second pass subtracts the correction only: h2 = h_total - h1)
+        if (pass == 0) {
+          k_gemv_n<<<nblocks(n), 256, 0, st>>>(n, k + 1, V.p, n, hv.p, 1.0, w.p);
+          HIP_CHECK(hipMemcpyAsync(hh.data(), hv.p, sizeof(double) * (k + 1), hipMemcpyDeviceToHost, st));
+          HIP_CHECK(hipStreamSynchronize(st));
+          HIP_CHECK(hipMemsetAsync(hv.p, 0, sizeof(double) * (k + 1), st));
+        }
+      }
+      {
+        std::vector<double> h2(k + 1);
+        HIP_CHECK(hipMemcpyAsync(h2.data(), hv.p, sizeof(double) * (k + 1), hipMemcpyDeviceToHost, st));
+        HIP_CHECK(hipStreamSynchronize(st));
+        k_gemv_n<<<nblocks(n), 256, 0, st>>>(n, k + 1, V.p, n, hv.p, 1.0, w.p);
+        for (int j = 0; j <= k; ++j) hh[j] += h2[j];
+      }
+      dot(w.p, w.p, n, part.p, nrm.p, st);
+      const double hn = std::sqrt(host_scalar(nrm.p));
+      double* Hk = H.data() + (size_t)k * (m + 1);
+      for (int j = 0; j <= k; ++j) Hk[j] = hh[j];
+      Hk[k + 1] = hn;
+      if (hn > 0.0) k_scale_dev<<<nblocks(n), 256, 0, st>>>(n, nrm.p, 1, w.p, V.p + (int64_t)(k + 1) * n);
+      // previous rotations, then a new one that zeroes H[k+1, k]
+      for (int j = 0; j < k; ++j) {
+        const double t = cs[j] * Hk[j] + sn[j] * Hk[j + 1];
+        Hk[j + 1] = -sn[j] * Hk[j] + cs[j] * Hk[j + 1];
+        Hk[j] = t;
+      }
+      const double den = std::hypot(Hk[k], Hk[k + 1]);
+      cs[k] = den > 0.0 ? Hk[k] / den : 1.0;
+      sn[k] = den > 0.0 ? Hk[k + 1] / den : 0.0;
+      Hk[k] = den;
+      Hk[k + 1] = 0.0;
+      g[k + 1] = -sn[k] * g[k];
+      g[k] = cs[k] * g[k];
+      kd = k + 1;
+      res = std::fabs(g[k + 1]);
+      HIP_CHECK(hipGetLastError());
+      if (res <= tol || hn == 0.0) {
+        conv = res <= tol;
+        break;
+      }
+    }
+    // y = H[:kd, :kd]^-1 g[:kd] (upper triangular), x += M^-1 V y
+    std::vector<double> y(kd);
+    for (int i = kd - 1; i >= 0; --i) {
+      double s = g[i];
+      for (int j = i + 1; j < kd; ++j) s -= H[(size_t)j * (m + 1) + i] * y[j];
+      y[i] = s / H[(size_t)i * (m + 1) + i];
+    }
+    if (kd > 0) {
+      HIP_CHECK(hipMemcpyAsync(hv.p, y.data(), sizeof(double) * kd, hipMemcpyHostToDevice, st));
+      k_gemv_n<<<nblocks(n), 256, 0, st>>>(n, kd, V.p, n, hv.p, 0.0, w.p);      // w = -V y
+      precond(w.p, z.p);
+      k_axpby<<<nblocks(n), 256, 0, st>>>(n, 1.0, x, -1.0, z.p, x);              // x += M^-1 V y
+      HIP_CHECK(hipStreamSynchronize(st));
+    }
+    check_device_error(ctx);
+  }
+  HIP_CHECK(hipEventRecord(ctx->ev[1], st));
+  info->solve_ms = elapsed(ctx, 0, 1);
+  info->iterations = it;
+  info->rel_residual = bnorm == 0.0 ? 0.0 : res / bnorm;
+  info->graph_replays = 0;
+  check_device_error(ctx);
+  if (!conv) throw Error(GENEO_ENOCONV, "GMRES did not reach rtol in maxit iterations");
 }
 
 }  // namespace geneo

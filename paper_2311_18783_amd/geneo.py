@@ -29,7 +29,10 @@ lib = C.CDLL(LIB_PATH)
 STATUS = {0: "OK", -1: "EINVAL", -2: "ENOTSPD", -3: "ENOCONV", -4: "EOOM", -5: "EHIP", -6: "EUNSUPPORTED",
           -7: "ESYNC"}
 FP64, FP32_REFINE1 = 0, 1
-COARSE_SNK_GENEO, COARSE_SNK, COARSE_NONE = 0, 1, 2
+COARSE_SNK_GENEO, COARSE_SNK, COARSE_NONE, COARSE_NK, COARSE_NK_GENEO = 0, 1, 2, 3, 4
+WEIGHT_IDENTITY, WEIGHT_POU = 0, 1
+PCG, GMRES = 0, 1
+ORDER_NATURAL, ORDER_NESTED_DISSECTION = 0, 1
 PART_BOX, PART_RCB, PART_EXPLICIT = 0, 1, 2
 
 
@@ -68,7 +71,8 @@ class SetupOpts(C.Structure):
                 ("local_precision", C.c_int32), ("lobpcg_tol", C.c_double), ("lobpcg_maxit", C.c_int32),
                 ("lobpcg_guard", C.c_int32), ("seed", C.c_uint64), ("coarse_drop_tol", C.c_double),
                 ("warm_start", C.POINTER(C.c_double)), ("fp32_rho_max", C.c_double),
-                ("model", C.c_void_p), ("keep_ritz", C.c_int32)]
+                ("model", C.c_void_p), ("keep_ritz", C.c_int32), ("coarse_order", C.c_int32),
+                ("one_level_weight", C.c_int32), ("classical", C.c_int32)]
 
 
 class PrecondInfo(C.Structure):
@@ -81,7 +85,9 @@ class PrecondInfo(C.Structure):
                 ("local_factor_flops", C.c_double), ("fp32_rho_est", C.c_double),
                 ("coarse_factor_flops", C.c_double), ("coarse_fill", C.c_double),
                 ("learned_starts", C.c_int32), ("start_residual", C.c_double),
-                ("fp32_prechecked", C.c_int32), ("fp32_kappa_lb", C.c_double)]
+                ("fp32_prechecked", C.c_int32), ("fp32_kappa_lb", C.c_double),
+                ("learned_candidates", C.c_int32), ("coarse_nd_levels", C.c_int32),
+                ("coarse_solve_depth", C.c_int32)]
 
 
 class ModelOpts(C.Structure):
@@ -102,13 +108,19 @@ class TrainInfo(C.Structure):
                 ("train_ms", C.c_double)]
 
 
+class FactorSchedule(C.Structure):
+    _fields_ = [("mode", C.c_int32), ("group", C.c_int32), ("potrf", C.c_int32), ("ms", C.c_double)]
+
+
 class SolveOpts(C.Structure):
-    _fields_ = [("rtol", C.c_double), ("maxit", C.c_int32), ("graph", C.c_int32)]
+    _fields_ = [("rtol", C.c_double), ("maxit", C.c_int32), ("graph", C.c_int32), ("method", C.c_int32),
+                ("restart", C.c_int32), ("true_residual", C.c_int32)]
 
 
 class SolveInfo(C.Structure):
     _fields_ = [("iterations", C.c_int32), ("rel_residual", C.c_double), ("solve_ms", C.c_double),
-                ("graph_replays", C.c_int32)]
+                ("graph_replays", C.c_int32), ("residual_replacements", C.c_int32),
+                ("true_rel_residual", C.c_double)]
 
 
 _vp = C.c_void_p
@@ -134,6 +146,11 @@ _sigs = {
     "geneo_solve": (C.c_int, [_vp, _vp, _vp, _vp, _vp, _P(SolveOpts), _P(SolveInfo)]),
     "geneo_potrf_batched": (C.c_int, [_vp, C.c_int32, _P(C.c_int32), _P(C.c_int64), _vp, C.c_int32,
                                       _P(C.c_double)]),
+    "geneo_tune_factor": (C.c_int, [_vp, C.c_int32, _P(C.c_int32), C.c_int32, C.c_int32, _P(FactorSchedule),
+                                    _P(C.c_int32)]),
+    "geneo_tune_lookup": (C.c_int, [C.c_int32, _P(C.c_int32), C.c_int32, _P(FactorSchedule)]),
+    "geneo_tune_save": (C.c_int, [C.c_char_p]),
+    "geneo_tune_load": (C.c_int, [C.c_char_p]),
     "geneo_model_opts_default": (None, [_P(ModelOpts)]),
     "geneo_model_create": (C.c_int, [_vp, _P(ModelOpts), _P(_vp)]),
     "geneo_model_info_get": (C.c_int, [_vp, _P(ModelInfo)]),
@@ -188,6 +205,31 @@ def check_vector(t, n, device, name="vector"):
         raise ValueError(f"{name}: {t.numel()} elements, expected n = {n}")
     if t.device.type != "cuda" or (t.device.index if t.device.index is not None else 0) != device:
         raise ValueError(f"{name}: on {t.device}, expected cuda:{device}")
+
+
+def tune_lookup(sizes, precision=FP64):
+    """geneo_tune_lookup: the factorisation schedule (mode, group, potrf) a
+    batch of these matrix sizes gets from the process-wide table (host only)."""
+    n = np.ascontiguousarray(sizes, dtype=np.int32)
+    out = FactorSchedule()
+    rc = lib.geneo_tune_lookup(len(n), _ptr(n, C.c_int32), int(precision), C.byref(out))
+    if rc != 0:
+        raise GeneoError(rc, "bad sizes or precision")
+    return out.mode, out.group, out.potrf
+
+
+def tune_save(path):
+    """geneo_tune_save: write the schedule table to a text file."""
+    rc = lib.geneo_tune_save(str(path).encode())
+    if rc != 0:
+        raise GeneoError(rc, f"cannot write {path}")
+
+
+def tune_load(path):
+    """geneo_tune_load: merge a schedule table from a text file."""
+    rc = lib.geneo_tune_load(str(path).encode())
+    if rc != 0:
+        raise GeneoError(rc, f"cannot read or parse {path}")
 
 
 class Context:
@@ -277,18 +319,23 @@ class Context:
         check_vector(y, n, self.device, "y")
         self._check(lib.geneo_spmv(self.h, system.h, _dptr(x), _dptr(y)))
 
-    def solve(self, system, pc, b, x, rtol=1e-8, maxit=1000, allow_noconv=False, graph=True):
-        """geneo_solve: PCG from x = 0 (b, x: float64 device tensors of length n).
-        graph=True replays one captured iteration as a HIP graph from the
-        second iteration on; graph=False launches kernel by kernel (same
-        kernels, bitwise equal iterates).  allow_noconv returns the info of a
-        run stopped by maxit instead of raising."""
+    def solve(self, system, pc, b, x, rtol=1e-8, maxit=1000, allow_noconv=False, graph=True, method=PCG,
+              restart=0, true_residual=False):
+        """geneo_solve: PCG (method=PCG) or right-preconditioned GMRES
+        (method=GMRES, restart length `restart`, 0 = none) from x = 0 (b, x:
+        float64 device tensors of length n).  graph=True replays one captured
+        PCG iteration as a HIP graph from the second iteration on;
+        graph=False launches kernel by kernel (same kernels, bitwise equal
+        iterates).  allow_noconv returns the info of a run stopped by maxit
+        instead of raising.  true_residual=True: PCG continues from the true
+        residual while it misses rtol (at most two restarts)."""
         n = system.info().n
         if pc is not None and pc.system is not system:
             raise ValueError("the preconditioner was built on another system")
         check_vector(b, n, self.device, "b")
         check_vector(x, n, self.device, "x")
-        o = SolveOpts(float(rtol), int(maxit), 1 if graph else 0)
+        o = SolveOpts(float(rtol), int(maxit), 1 if graph else 0, int(method), int(restart),
+                      1 if true_residual else 0)
         info = SolveInfo()
         rc = lib.geneo_solve(self.h, system.h, pc.h if pc is not None else None, _dptr(b), _dptr(x),
                              C.byref(o), C.byref(info))
@@ -298,6 +345,7 @@ class Context:
         return info
 
     def potrf_batched(self, A, sizes, offsets, precision=FP64):
+        """geneo_potrf_batched."""
         import torch
         n = np.ascontiguousarray(sizes, dtype=np.int32)
         off = np.ascontiguousarray(offsets, dtype=np.int64)
@@ -309,10 +357,21 @@ class Context:
         if n.size == 0 or (n < 1).any() or (off < 0).any() or int((off + ld * ld).max()) > A.numel():
             raise ValueError("A: matrix sizes / offsets run past the buffer")
         ms = C.c_double()
-        self._check(lib.geneo_potrf_batched(self.h, len(n), _ptr(n, C.c_int32), _ptr(off, C.c_int64),
-                                            _dptr(A), int(precision), C.byref(ms)))
+        self._check(lib.geneo_potrf_batched(self.h, len(n), _ptr(n, C.c_int32), _ptr(off, C.c_int64), _dptr(A),
+                                            int(precision), C.byref(ms)))
         return ms.value
 
+
+    def tune_factor(self, sizes, precision=FP64, reps=2):
+        """geneo_tune_factor: time the candidate schedules on synthetic SPD
+        matrices of these sizes, record the fastest for the batch's key and
+        return (mode, group, potrf, ms, candidates timed)."""
+        n = np.ascontiguousarray(sizes, dtype=np.int32)
+        best = FactorSchedule()
+        tried = C.c_int32()
+        self._check(lib.geneo_tune_factor(self.h, len(n), _ptr(n, C.c_int32), int(precision), int(reps),
+                                          C.byref(best), C.byref(tried)))
+        return best.mode, best.group, best.potrf, best.ms, tried.value
 
     # -------------------------------------------------------------- learned warm start
     def model_create(self, canvas=12, hidden=256, k=20, seed=2311):

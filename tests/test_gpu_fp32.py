@@ -26,7 +26,7 @@ def _rho_oracle(w):
     from oracle import geneo as og
     s, odec = oracle_problem(w)
     tl = og.TwoLevel(odec, variant="as", local_precision="fp32_refine1")
-    return s, np.array([tl.fp32_rho(i) for i in range(odec.N)])
+    return s, np.array([tl.fp32_rho(i) for i in range(odec.N)]), tl
 
 
 def _scaled_kappa(w):
@@ -51,7 +51,7 @@ def test_fp32_refined_preconditioner(g, cfg):
     geneo, ctx = g
     print("fp32", cfg, flush=True)
     w = W.make(int(cfg) if cfg.isdigit() else cfg)
-    s, rho = _rho_oracle(w)
+    s, rho, tl = _rho_oracle(w)
     sysm, dec = lib_problem(ctx, w)
     pc64 = ctx.setup(sysm, dec, tau=w.tau, nev_max=w.nev_max, local_precision=geneo.FP64)
     pc32 = ctx.setup(sysm, dec, tau=w.tau, nev_max=w.nev_max, local_precision=geneo.FP32_REFINE1)
@@ -76,6 +76,17 @@ def test_fp32_refined_preconditioner(g, cfg):
     rmax = min(0.5, float(rho[rho <= 0.5].max())) if (rho <= 0.5).any() else 0.0
     tol = 10 * rmax ** 2 + 1e-10
     assert rel(z32.cpu().numpy(), z64.cpu().numpy()) <= tol
+    if nfb == 0:
+        # one-level FP32 apply against the oracle's (LAPACK FP32 factors, one FP64 refinement
+        # step): each refined local solve is within rho^2 of A_i^-1 R_i r
+        pcn = ctx.setup(sysm, dec, coarse=geneo.COARSE_NONE, local_precision=geneo.FP32_REFINE1)
+        assert pcn.info().fp64_fallbacks == 0
+        zn = torch.zeros(s.n, dtype=torch.float64, device="cuda:0")
+        ctx.apply(pcn, to_dev(r), zn)
+        torch.cuda.synchronize()
+        e = rel(zn.cpu().numpy(), tl.one_level(r))
+        print("fp32 one-level vs oracle", cfg, e, "rho max", rho.max(), flush=True)
+        assert e <= 10 * rho.max() ** 2 + 1e-10
     b = w.rhs(s.n)
     x64 = torch.zeros(s.n, dtype=torch.float64, device="cuda:0")
     x32 = torch.zeros_like(x64)

@@ -1,0 +1,192 @@
+"""GPU parity at the benchmark sizes: the batched Cholesky over several panel
+groups (matrices of 9 to 62 block columns), and the 24^3 channel cube
+(64 subdomains, n_i = 3,584 .. 7,930): GenEO eigenvalues of its smallest and
+largest subdomain against the oracle's dense eigensolver, the one-level
+apply against sparse direct solves of every local matrix, the PCG solution's
+true residual with the oracle's matrix, and the stability of the coarse
+basis across eigensolver start blocks."""
+import numpy as np
+import pytest
+import scipy.sparse.linalg as spla
+
+import workloads as W
+from cases import lib_problem, oracle_problem, rel, to_dev
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def g():
+    import torch
+    from paper_2311_18783_amd import geneo
+    assert torch.cuda.is_available()
+    ctx = geneo.Context(0)
+    yield geneo, ctx
+    ctx.close()
+
+
+@pytest.fixture(scope="module")
+def cube24():
+    """The oracle's system and decomposition of the 24^3 channel cube."""
+    w = W.make(2)
+    s, odec = oracle_problem(w)
+    return w, s, odec
+
+
+def _spd(n, rng, delta):
+    """M M^T / n + delta I: eigenvalues in [delta, ~4 + delta] (Marchenko-Pastur)."""
+    M = rng.standard_normal((n, n))
+    return M @ M.T / n + delta * np.eye(n)
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_potrf_batched_several_panel_groups(g, prec):
+    """Matrices of 9, 18, 28, 40 and 62 block columns (panel groups of 8:
+    the cross-group trailing update with K = 8 x 128 and a partial last
+    group).  Backward error ||L L^T - A||_F <= 2 n u ||A||_F (Cholesky is
+    backward stable) and the factor agrees with LAPACK's FP64 factor to
+    10 kappa(A) u; pad rows and columns keep the identity."""
+    import torch
+    geneo, ctx = g
+    rng = np.random.default_rng(7)
+    sizes = [1100, 2200, 3584, 5000, 7930]
+    delta = 1e-3 if prec == "fp64" else 1e-1
+    mats = [_spd(n, rng, delta) for n in sizes]
+    dt = np.float64 if prec == "fp64" else np.float32
+    u = np.finfo(dt).eps / 2
+    lds = [((n + 127) // 128) * 128 for n in sizes]
+    offs = np.cumsum([0] + [l * l for l in lds])
+    buf = np.zeros(offs[-1], dtype=dt)
+    for m, ld, o in zip(mats, lds, offs):
+        full = np.eye(ld)
+        full[:m.shape[0], :m.shape[0]] = m
+        buf[o:o + ld * ld] = full.T.ravel()
+    print("potrf", prec, sizes, flush=True)
+    A = torch.as_tensor(buf, device="cuda:0")
+    ctx.potrf_batched(A, sizes, offs[:-1], geneo.FP64 if prec == "fp64" else geneo.FP32_REFINE1)
+    torch.cuda.synchronize()
+    out = A.cpu().numpy()
+    for m, n, ld, o in zip(mats, sizes, lds, offs):
+        Lf = np.tril(out[o:o + ld * ld].reshape(ld, ld).T).astype(np.float64)
+        L = Lf[:n, :n]
+        back = np.linalg.norm(L @ L.T - m) / np.linalg.norm(m)
+        assert back <= 2 * n * u, (n, prec, back)
+        ev = np.linalg.eigvalsh(m)
+        kappa = ev[-1] / ev[0]
+        Lref = np.linalg.cholesky(m)
+        fwd = np.linalg.norm(L - Lref) / np.linalg.norm(Lref)
+        assert fwd <= 10 * kappa * u, (n, prec, fwd, kappa)
+        assert np.array_equal(Lf[n:, n:], np.eye(ld - n)) and not Lf[n:, :n].any()
+
+
+def test_cube24_gevp_eigenvalues_smallest_and_largest_subdomain(g, cube24):
+    """Eigenvalues above tau (at most 20) of the filtered GEVP, eq.
+    (eigAtildeBAS), on the smallest (n_i = 3,584) and the largest
+    (n_i = 7,930) subdomain of the 24^3 channel cube against the oracle's
+    dense generalised eigensolver: the selected counts agree outside a tie
+    band of 1e-6 around tau, and every selected eigenvalue agrees to 1e-8
+    relative or to the a posteriori bound of its Ritz pair in the oracle's
+    own pencil, ||r||_{B^-1}^2 / gap (x B-normalised, r = Atilde x - theta
+    B x, gap = distance of theta to the nearest other eigenvalue), whichever
+    is larger.  At gamma = 1e-4 the B^-1-norm residual of any FP64
+    evaluation of the filtered operator stalls near 1e-5 theta (the oracle's
+    own eigenvectors show it under the library's sequence of products), so
+    clustered eigenvalues are determined to a few 1e-9 relative, not to
+    arbitrary precision."""
+    import scipy.linalg as sla
+    from oracle import geneo as og
+    geneo, ctx = g
+    w, s, odec = cube24
+    sizes = np.array([d.size for d in odec.dofs])
+    picks = [int(np.argmin(sizes)), int(np.argmax(sizes))]
+    print("cube24 gevp", picks, sizes[picks], flush=True)
+    sysm, dec = lib_problem(ctx, w)
+    pc = ctx.setup(sysm, dec, tau=w.tau, nev_max=w.nev_max, keep_ritz=1)
+    assert pc.info().lobpcg_unconverged == 0
+    for i in picks:
+        Gi, _, _ = odec.G_local(i)
+        Ai, Bn = odec.A_dir(i).toarray(), odec.A_neu(i).toarray()
+        lam_o, _, sel_o = og.gevp(Ai, Bn, odec.D[i], Gi, w.tau, w.nev_max)
+        lam_g, sel_g = pc.eigs(i)
+        near = np.abs(lam_o[:w.nev_max + 1] / w.tau - 1.0) < 1e-6
+        if not near.any():
+            assert sel_g == sel_o, (i, sel_g, sel_o)
+        m = min(sel_g, sel_o)
+        assert m > 0
+        At, _ = og.filtered_pencil(Ai, Bn, odec.D[i], Gi)
+        V = pc.ritz(i, Ai.shape[0], cap=w.nev_max)[:, :m]
+        V = V / np.sqrt(np.einsum("ij,ij->j", V, Bn @ V))
+        R = At @ V - (Bn @ V) * lam_g[:m]
+        cB = sla.cho_factor(Bn)
+        rb2 = np.einsum("ij,ij->j", R, sla.cho_solve(cB, R))
+        gap = np.array([np.min(np.abs(np.delete(lam_o, q) - lam_g[q])) for q in range(m)])
+        err = np.abs(lam_g[:m] - lam_o[:m])
+        bound = np.maximum(1e-8 * np.abs(lam_o[:m]), 2.0 * np.maximum(rb2, 0.0) / gap)
+        print("subdomain", i, "n_i", sizes[i], "selected", sel_g, "max rel err", (err / np.abs(lam_o[:m])).max(),
+              "within 1e-8:", int((err <= 1e-8 * np.abs(lam_o[:m])).sum()), "of", m,
+              "max bound / 1e-8 lambda", (bound / (1e-8 * np.abs(lam_o[:m]))).max(), flush=True)
+        assert (err <= bound).all(), (i, err / np.abs(lam_o[:m]), bound / np.abs(lam_o[:m]))
+
+
+def test_cube24_one_level_apply_matches_sparse_direct_local_solves(g, cube24):
+    """z = sum_i R_i^T A_i^-1 R_i r (eq. (AS) without coarse space) on the
+    24^3 cube, every A_i^-1 applied by SuperLU on the oracle's local matrix:
+    agreement to 10 u max_i kappa_1(A_i) (forward errors of two backward
+    stable solves; kappa_1 by Hager's estimator on the LU solves)."""
+    import torch
+    geneo, ctx = g
+    w, s, odec = cube24
+    print("cube24 one-level", flush=True)
+    sysm, dec = lib_problem(ctx, w)
+    pc = ctx.setup(sysm, dec, coarse=geneo.COARSE_NONE)
+    r = np.random.default_rng(13).standard_normal(s.n)
+    z = torch.zeros(s.n, dtype=torch.float64, device="cuda:0")
+    ctx.apply(pc, to_dev(r), z)
+    torch.cuda.synchronize()
+    zo = np.zeros(s.n)
+    kmax = 0.0
+    for i in range(odec.N):
+        d = odec.dofs[i]
+        Ai = odec.A_dir(i).tocsc()
+        lu = spla.splu(Ai)
+        zo[d] += lu.solve(r[d])
+        inv = spla.LinearOperator(Ai.shape, matvec=lu.solve, rmatvec=lambda v, lu=lu: lu.solve(v, trans="T"))
+        kmax = max(kmax, spla.norm(Ai, 1) * spla.onenormest(inv))
+    tol = 10 * np.finfo(float).eps / 2 * kmax
+    err = rel(z.cpu().numpy(), zo)
+    print("one-level rel err", err, "tol", tol, "max kappa_1", kmax, flush=True)
+    assert err <= tol
+
+
+def test_cube24_pcg_residual_and_coarse_basis_stable_across_start_blocks(g, cube24):
+    """AS-SNK-GenEO PCG on the 24^3 cube (eq. (AS2)) from two eigensolver
+    start seeds, continuing from the true residual while it misses rtol:
+    both reach a true relative residual ||b - A x|| / ||b|| <= 1.05e-8 with
+    the oracle's assembled A, as the library reports it (a property at any size; a
+    sparse direct solve of this system takes longer than the test budget),
+    the coarse spaces have the same size, rank and per-subdomain GenEO
+    counts, and the iteration counts agree within one."""
+    import torch
+    geneo, ctx = g
+    w, s, odec = cube24
+    sysm, dec = lib_problem(ctx, w)
+    b = w.rhs(s.n)
+    res = []
+    for seed in (1, 2):
+        print("cube24 pcg seed", seed, flush=True)
+        pc = ctx.setup(sysm, dec, tau=w.tau, nev_max=w.nev_max, seed=seed)
+        x = torch.zeros(s.n, dtype=torch.float64, device="cuda:0")
+        si = ctx.solve(sysm, pc, to_dev(b), x, rtol=1e-8, true_residual=True)
+        xg = x.cpu().numpy()
+        tr = np.linalg.norm(b - s.A @ xg) / np.linalg.norm(b)
+        assert abs(tr - si.true_rel_residual) <= 1e-3 * tr
+        inf = pc.info()
+        print("seed", seed, "iterations", si.iterations, "true residual", tr, "n0", inf.n0, "rank", inf.n0_rank,
+              "geneo", inf.n_geneo, flush=True)
+        assert tr <= 1.05e-8
+        res.append((si.iterations, inf.n0, inf.n0_rank, inf.n_geneo, [pc.eigs(i)[1] for i in range(odec.N)]))
+        del pc
+    (it1, n01, rk1, ng1, sel1), (it2, n02, rk2, ng2, sel2) = res
+    assert (n01, rk1, ng1) == (n02, rk2, ng2)
+    assert sel1 == sel2
+    assert abs(it1 - it2) <= 1

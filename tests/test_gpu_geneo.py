@@ -65,8 +65,9 @@ def test_gevp_eigenvalues_match_dense_oracle(g, oracle_cache, cfg):
 def test_geneo_preconditioner_and_solve(g, oracle_cache, cfg):
     """The two-level AS-SNK-GenEO apply matches the oracle's to the accuracy
     of the eigenvectors (LOBPCG residual 1e-6 -> ~1e-5 in the coarse space),
-    PCG needs the same number of iterations (+-1) and reaches rtol 1e-8 on
-    the true residual; the solution agrees with a sparse direct solve."""
+    PCG needs the same number of iterations as the oracle's PCG and reaches
+    rtol 1e-8 on the true residual; the solution agrees with the oracle's
+    PCG iterate to 1e-7 and with a sparse direct solve."""
     import torch
     from oracle import geneo as og
     geneo, ctx = g
@@ -85,9 +86,12 @@ def test_geneo_preconditioner_and_solve(g, oracle_cache, cfg):
     b = w.rhs(s.n)
     x = torch.zeros(s.n, dtype=torch.float64, device="cuda:0")
     si = ctx.solve(sysm, pc, to_dev(b), x, rtol=1e-8)
-    _, ito, _ = og.pcg(s.A, b, opc.apply, rtol=1e-8)
+    xo, ito, _ = og.pcg(s.A, b, opc.apply, rtol=1e-8)
     xg = x.cpu().numpy()
-    assert abs(si.iterations - ito) <= 1, (si.iterations, ito)
+    print("geneo solve", cfg, "iterations", si.iterations, "oracle", ito, "x vs oracle iterate", rel(xg, xo),
+          flush=True)
+    assert si.iterations == ito, (si.iterations, ito)
+    assert rel(xg, xo) <= 1e-7
     assert np.linalg.norm(b - s.A @ xg) <= 1.01e-8 * np.linalg.norm(b)
     xs = spla.spsolve(s.A.tocsc(), b)
     kappa_bound = 1e-8 * np.linalg.cond(s.A.toarray()) if s.n <= 5000 else np.inf

@@ -84,11 +84,16 @@ def test_save_load_roundtrip(g):
 
 
 def test_learned_start_feeds_the_eigensolver(g):
-    """A model trained on one instance's Ritz vectors supplies the start
-    blocks of every subdomain (the canvas fits), the eigensolver still
-    converges from them to the same eigenvalues (1e-8) and coarse space, and
-    the exported Ritz vectors are A_i^Neu-orthonormal eigenvectors of the
-    filtered pencil (checked against the oracle's dense pencil)."""
+    """A model trained on one instance's Ritz vectors proposes start blocks
+    for every subdomain (the canvas fits); each is judged against the random
+    block by its eigen-residuals after one Rayleigh-Ritz step and kept where
+    it wins (on this instance: some but not all subdomains; the BF16 network
+    reproduces the Ritz vectors to about three digits, and the residual of
+    the pencil is far more sensitive than the Euclidean span loss it was
+    trained on).  Either way the eigensolver converges to the same
+    eigenvalues (1e-8) and coarse space, and the exported Ritz vectors are
+    A_i^Neu-orthonormal eigenvectors of the filtered pencil (checked against
+    the oracle's dense pencil)."""
     from cases import oracle_problem
     from oracle import geneo as og
     geneo, ctx = g
@@ -103,8 +108,9 @@ def test_learned_start_feeds_the_eigensolver(g):
     assert ti.loss_last < 0.05 * ti.loss_first, (ti.loss_first, ti.loss_last)
     pc2 = ctx.setup(sysm, dec, tau=w.tau, nev_max=w.nev_max, model=m)
     warm = pc2.info()
-    print("cold", cold.lobpcg_iters, "warm", warm.lobpcg_iters, flush=True)
-    assert warm.learned_starts == dec.info().n_sub
+    print("cold", cold.lobpcg_iters, "warm", warm.lobpcg_iters, "kept", warm.learned_starts, flush=True)
+    assert warm.learned_candidates == dec.info().n_sub
+    assert 1 <= warm.learned_starts <= dec.info().n_sub
     assert warm.lobpcg_unconverged == 0
     assert warm.n_geneo == cold.n_geneo and warm.n0_rank == cold.n0_rank
     for i in range(dec.info().n_sub):
@@ -128,3 +134,27 @@ def test_learned_start_feeds_the_eigensolver(g):
     R = At @ V[:, :sel] - (Bn @ V[:, :sel]) * lam[:sel]
     rel = np.linalg.norm(R, axis=0) / (np.abs(lam[:sel]) * np.linalg.norm(Bn @ V[:, :sel], axis=0))
     assert rel.max() <= 1e-6, rel.max()
+
+
+def test_useless_model_falls_back_to_the_cold_start(g):
+    """A model whose prediction carries no information (all parameters zero:
+    its start block is 1e-4 times the random block, the same span) loses the
+    eigen-residual test on every subdomain, so the eigensolver continues from
+    the random block exactly as the cold start does: same iteration count,
+    bitwise equal eigenvalues and coarse space."""
+    geneo, ctx = g
+    w = W.make("small_channels")
+    sysm, dec = lib_problem(ctx, w)
+    cold = ctx.setup(sysm, dec, tau=w.tau, nev_max=w.nev_max)
+    m = ctx.model_create(canvas=8, hidden=64, k=w.nev_max, seed=1)
+    m.set_params(np.zeros(m.info().n_params, np.float32))
+    warm = ctx.setup(sysm, dec, tau=w.tau, nev_max=w.nev_max, model=m)
+    ci, wi = cold.info(), warm.info()
+    assert wi.learned_candidates == dec.info().n_sub
+    assert wi.learned_starts == 0
+    assert wi.lobpcg_iters == ci.lobpcg_iters
+    assert wi.n_geneo == ci.n_geneo and wi.n0_rank == ci.n0_rank
+    for i in range(dec.info().n_sub):
+        a, sa = cold.eigs(i)
+        b, sb = warm.eigs(i)
+        assert sa == sb and np.array_equal(a, b)

@@ -191,6 +191,7 @@ class Workload:
     nev_max: int = 20
     seed: int = 0
     extra: dict = field(default_factory=dict)
+    describe: str = ""       # one-line statement of the recipe (mesh, coefficients, decomposition)
 
     def rhs(self, n):
         ss = np.random.SeedSequence(self.seed).spawn(4)
@@ -214,10 +215,13 @@ def rcb_jitter(nparts, rng, spread=0.3):
 def make(cfg, family=0, **over):
     """Build workload `cfg` (1, 2, 3, 5, or a small named test case).
 
-    family > 0 (configs 2 and "small_channels"): another instance of the same
-    recipe, its coefficients drawn from the stream SeedSequence([seed, family])
-    instead of SeedSequence(seed); used to train the learned warm start on
-    instances disjoint from the measured one."""
+    family > 0: another instance of the same recipe, its random draws taken
+    from the streams SeedSequence([seed, family]) instead of SeedSequence(seed):
+    new channels (config 2, "small_channels"), new lognormal fields and
+    bisection jitter (config 3), new bisection jitter (config 5, whose slab
+    coefficients are fixed, so the subdomains change shape and position).
+    Used to train the learned warm start on instances disjoint from the
+    measured one (family 0)."""
     def stream(seed):
         return np.random.SeedSequence([seed, family] if family else seed).spawn(4)
     if cfg == 1:
@@ -226,7 +230,9 @@ def make(cfg, family=0, **over):
         T = mesh["tets"].shape[0]
         w = Workload("cube8_homog", mesh, np.ones(T), np.ones(T), 1e-2,
                      dirichlet_flags(mesh["bface_tag"], "all"),
-                     {"kind": "box", "p": (2, 2, 2)}, 1, seed=1001)
+                     {"kind": "box", "p": (2, 2, 2)}, 1, seed=1001,
+                     describe="unit cube 8^3 hexes x 6 tets (3,072), mu = eps = 1, gamma = 1e-2, "
+                              "all-Dirichlet, 2x2x2 boxes, overlap 1")
     elif cfg == 2:
         dims = (24, 24, 24)
         mesh = hex_box_mesh(dims)
@@ -235,13 +241,15 @@ def make(cfg, family=0, **over):
         T = mesh["tets"].shape[0]
         w = Workload("cube24_channels", mesh, mu, np.ones(T), 1e-4,
                      dirichlet_flags(mesh["bface_tag"], "all"),
-                     {"kind": "box", "p": (4, 4, 4)}, 2, seed=1002)
+                     {"kind": "box", "p": (4, 4, 4)}, 2, seed=1002,
+                     describe="24^3 hexes x 6 tets (82,944), mu in {1, 1e4} on random 2x2-hex channels "
+                              ">= 10%, eps = 1, gamma = 1e-4, all-Dirichlet, 4x4x4 boxes, overlap 2")
     elif cfg == 3:
         dims = (32, 32, 32)
         removed = np.zeros(dims, bool)
         removed[12:20, 12:20, :] = True
         mesh = hex_box_mesh(dims, removed=removed)
-        ss = np.random.SeedSequence(1003).spawn(4)
+        ss = stream(1003)
         r = np.random.default_rng(ss[0])
         H = mesh["hex_ijk"].shape[0]
         lmu = r.normal(0.0, 2.0, size=H)
@@ -251,17 +259,23 @@ def make(cfg, family=0, **over):
         jit = rcb_jitter(125, np.random.default_rng(ss[2]))
         w = Workload("cube32_hole_lognormal", mesh, mu, eps, 1e-3,
                      dirichlet_flags(mesh["bface_tag"], "outer"),
-                     {"kind": "rcb", "nparts": 125, "jitter": jit}, 1, seed=1003)
+                     {"kind": "rcb", "nparts": 125, "jitter": jit}, 1, seed=1003,
+                     describe="32^3 hexes minus a central 8x8x32 through-hole (184,320 tets), lognormal "
+                              "mu, eps (sigma 2), gamma = 1e-3, Dirichlet outside / Neumann on the hole, "
+                              "RCB 125 parts (+-30% jitter), overlap 1")
     elif cfg == 5:
         dims = (128, 16, 16)
         mesh = hex_box_mesh(dims, h=1.0 / 16)
-        ss = np.random.SeedSequence(1005).spawn(4)
+        ss = stream(1005)
         mu = per_hex(slab_mu(dims), mesh)
         T = mesh["tets"].shape[0]
         jit = rcb_jitter(256, np.random.default_rng(ss[2]))
         w = Workload("beam128_slabs", mesh, mu, np.ones(T), 1e-6,
                      dirichlet_flags(mesh["bface_tag"], "all"),
-                     {"kind": "rcb", "nparts": 256, "jitter": jit}, 1, seed=1005)
+                     {"kind": "rcb", "nparts": 256, "jitter": jit}, 1, seed=1005,
+                     describe="beam 128x16x16 hexes x 6 tets (196,608), h = 1/16, mu alternating 1 / 1e3 "
+                              "in 8 slabs along x, eps = 1, gamma = 1e-6, all-Dirichlet, RCB 256 parts "
+                              "(+-30% jitter), overlap 1")
     elif isinstance(cfg, str) and cfg.startswith("beam") and cfg[4:].isdigit():
         # The paper's weak-scaling beam (Section 4 "Numerical results", influence of the geometry):
         # N/2 x 1 x 1 with h = 1/16 (8N x 16 x 16 hexes), N strip subdomains
@@ -321,7 +335,7 @@ def make(cfg, family=0, **over):
     else:
         raise ValueError(f"unknown workload {cfg!r}")
     if family:
-        if cfg not in (2, "small_channels"):
+        if cfg not in (2, 3, 5, "small_channels"):
             raise ValueError(f"no instance family for workload {cfg!r}")
         w.name = f"{w.name}#{family}"
     for k, v in over.items():
