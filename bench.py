@@ -50,7 +50,9 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--workload", default="5", help="workload id (default: the 128x16x16 slab beam)")
     ap.add_argument("--variant", default="both", choices=["both", "learned_fp32", "fp64"])
-    ap.add_argument("--train-instances", type=int, default=8)
+    ap.add_argument("--train-instances", type=int, default=8,
+                    help="instances of the workload recipe the warm-start model is trained on (0: no model, the "
+                         "learned_fp32 configuration then runs FP32 local factors with the cold start)")
     ap.add_argument("--coarse-order", default="natural", choices=["natural", "nd"],
                     help="elimination order of the coarse columns (nd: nested dissection of the subdomain graph)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
@@ -112,7 +114,7 @@ def run_step(geneo, ctx, w, precision, b_host=None, model=None, coarse_order=0):
     di = dec.info()
     out = dict(assemble_s=t1 - t0, partition_s=t2 - t1, setup_s=t3 - t2, solve_s=t4 - t3,
                setup_solve_s=t4 - t2, step_s=t4 - t0, iterations=si.iterations, rel_residual=si.rel_residual,
-               true_rel_residual=si.true_rel_residual,
+               true_rel_residual=si.true_rel_residual, residual_floor=si.residual_floor,
                graph_replays=si.graph_replays,
                n=n, n_sub=di.n_sub, n_min=di.n_min, n_max=di.n_max, n0=pi.n0, n0_rank=pi.n0_rank,
                n_snk=pi.n_snk, n_geneo=pi.n_geneo, lobpcg_iters=pi.lobpcg_iters,
@@ -125,7 +127,7 @@ def run_step(geneo, ctx, w, precision, b_host=None, model=None, coarse_order=0):
                n0_factored=pi.n0 - pi.n0_local_dropped, coarse_flops=pi.coarse_factor_flops,
                coarse_fill=pi.coarse_fill, coarse_nd_levels=pi.coarse_nd_levels,
                coarse_solve_depth=pi.coarse_solve_depth, learned_candidates=pi.learned_candidates,
-               lobpcg_unconverged=pi.lobpcg_unconverged)
+               lobpcg_unconverged=pi.lobpcg_unconverged, t_factor_fp32_ms=pi.t_factor_fp32_ms)
     del pc, dec, sysm
     return out, b_host
 
@@ -177,12 +179,15 @@ def summarize(res):
                       "gevp": mean("t_gevp_ms"), "coarse_build": mean("t_coarse_build_ms"),
                       "coarse_factor": mean("t_coarse_factor_ms"), "pcg_device": mean("solve_ms")},
         "local_factor_tflops": last["local_flops"] / (mean("t_factor_ms") * 1e-3) / 1e12,
+        "fp32_factor_ms": mean("t_factor_fp32_ms"),
+        "fp32_factor_tflops": (last["local_flops"] / (mean("t_factor_fp32_ms") * 1e-3) / 1e12
+                               if mean("t_factor_fp32_ms") > 0 else None),
         "coarse_factor_tflops": last["coarse_flops"] / (mean("t_coarse_factor_ms") * 1e-3) / 1e12,
         "coarse_fill": last["coarse_fill"], "coarse_nd_levels": last["coarse_nd_levels"],
         "coarse_solve_depth": last["coarse_solve_depth"], "lobpcg_unconverged": last["lobpcg_unconverged"],
         "learned_candidates": last["learned_candidates"],
         "pcg_iterations": last["iterations"], "rel_residual": last["rel_residual"],
-        "true_rel_residual": last["true_rel_residual"],
+        "true_rel_residual": last["true_rel_residual"], "residual_floor": last["residual_floor"],
         "pcg_graph_replays": last["graph_replays"],
         "lobpcg_iterations": last["lobpcg_iters"], "start_residual": last["start_residual"],
         "learned_starts": last["learned_starts"], "fp64_fallbacks": last["fp64_fallbacks"],
@@ -223,7 +228,7 @@ def main():
     run = [v for v in ("learned_fp32", "fp64") if a.variant in ("both", v)]
     model, training = None, None
     corder = geneo.ORDER_NESTED_DISSECTION if a.coarse_order == "nd" else geneo.ORDER_NATURAL
-    if "learned_fp32" in run:
+    if "learned_fp32" in run and a.train_instances > 0:
         model, training = train_model(geneo, ctx, wid, a.train_instances)
     b_host = None
     for _ in range(a.warmup):

@@ -210,6 +210,8 @@ typedef struct {
                                canvas); learned_starts of them were kept */
   int32_t coarse_nd_levels; /* depth of the nested dissection of the subdomain graph (0: natural order) */
   int32_t coarse_solve_depth; /* longest chain of dependent 128-row blocks in a coarse triangular solve */
+  double t_factor_fp32_ms;  /* FP32_REFINE1: device time of the FP32 factorisation of all local matrices alone
+                               (part of t_factor_ms, which also holds the check, the probe and any fallback) */
 } geneo_precond_info;
 
 void geneo_setup_opts_default(geneo_setup_opts* o);
@@ -275,6 +277,9 @@ typedef struct {
                             recurrence residual met rtol but b - A x did not (at most 2) */
   double true_rel_residual; /* PCG: ||b - A x|| / ||b|| computed on the device when the recurrence residual
                             met rtol (0 if it never did) */
+  double residual_floor; /* PCG: (m + 1) u || |b| + |A| |x| || / ||b|| (m = longest row of A, u = 2^-53): the
+                            bound on the rounding error of that computed true residual; a true residual at
+                            or below it is as small as FP64 can certify */
 } geneo_solve_info;
 
 /* Solve A x = b (Section 1, the discrete system) from x0 = 0 with PCG
@@ -372,14 +377,14 @@ int geneo_potrf_batched(geneo_ctx* ctx, int32_t batch, const int32_t* n_host,
 /* Schedule of a batched Cholesky: mode = tile mode of the trailing updates
  * (0: 64 x 64 tile per wave, 4 waves, operands from L2; 1: 8 waves; 2:
  * operands staged through LDS), group = panels per trailing update,
- * potrf = FP64 diagonal-block kernel (1: recursive in LDS, 0: register
- * kernel; FP32 always 0). */
+ * potrf = diagonal-block kernel (1: recursive, in FP64 in LDS for both
+ * precisions; 0: register kernel in the factor's precision). */
 typedef struct {
   int32_t mode, group, potrf;
   double ms;        /* tuner: fastest factorisation time of the batch (ms) */
 } geneo_factor_schedule;
 
-/* Time every candidate schedule (tile modes 0-2, groups 4/8/16, both FP64
+/* Time every candidate schedule (tile modes 0-2, groups 4/8/16, both
  * diagonal-block kernels) on synthetic SPD matrices of the given sizes
  * (device memory of the batch is allocated for the run), keep the fastest
  * (minimum over `reps` runs each) and record it in the process-wide table

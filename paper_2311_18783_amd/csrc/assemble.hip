@@ -90,6 +90,23 @@ __global__ void k_spmv(int64_t n, const int32_t* __restrict__ rp, const int32_t*
   y[i] = acc;
 }
 
+// y = |b| + |A| |x|: the componentwise scale of the rounding error of b - A x
+__global__ void k_spmv_abs(int64_t n, const int32_t* __restrict__ rp, const int32_t* __restrict__ ci,
+                           const double* __restrict__ v, const double* __restrict__ x, const double* __restrict__ b,
+                           double* __restrict__ y) {
+  int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  double acc = fabs(b[i]);
+  for (int32_t k = rp[i]; k < rp[i + 1]; ++k) acc += fabs(v[k] * x[ci[k]]);
+  y[i] = acc;
+}
+
+void launch_spmv_abs(const geneo_system* s, const double* x, const double* b, double* y, hipStream_t st) {
+  if (s->n == 0) return;
+  int64_t blocks = (s->n + 255) / 256;
+  k_spmv_abs<<<dim3((unsigned)blocks), dim3(256), 0, st>>>(s->n, s->d_rowptr.p, s->d_colind.p, s->d_val.p, x, b, y);
+}
+
 void launch_spmv(const geneo_system* s, const double* x, double* y, hipStream_t st) {
   if (s->n == 0) return;
   int64_t blocks = (s->n + 255) / 256;

@@ -24,7 +24,8 @@ struct SyrkLaunch {
 // Schedule of a batched factorisation: tile mode of the trailing updates
 // (0: 64x64 per wave, operands from L2, 4 waves; 1: the same with 8 waves;
 // 2: operands staged through LDS), panels per trailing-update group, and the
-// FP64 diagonal-block kernel (1: recursive in LDS, 0: register kernel).
+// diagonal-block kernel (1: recursive, in FP64 in LDS for both precisions;
+// 0: register kernel in the factor's precision).
 struct FactorConfig {
   int mode = 0;
   int group = 8;

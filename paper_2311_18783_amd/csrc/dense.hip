@@ -646,9 +646,25 @@ __device__ inline void rec_prod(double* Ls, int a0, int b0) {
 // for a right half, which may close the parent too; kinds 0 and 1 for a left
 // half, which hands over to the right sibling).  Same pivot rule and outputs
 // as k_potrf.
+// two consecutive entries of a T array as doubles, and back
+template <typename T> __device__ inline double2 ld2(const T* p);
+template <> __device__ inline double2 ld2<double>(const double* p) { return *reinterpret_cast<const double2*>(p); }
+template <> __device__ inline double2 ld2<float>(const float* p) {
+  const float2 v = *reinterpret_cast<const float2*>(p);
+  return double2{(double)v.x, (double)v.y};
+}
+template <typename T> __device__ inline void st2(T* p, double2 v);
+template <> __device__ inline void st2<double>(double* p, double2 v) { *reinterpret_cast<double2*>(p) = v; }
+template <> __device__ inline void st2<float>(float* p, double2 v) {
+  *reinterpret_cast<float2*>(p) = float2{(float)v.x, (float)v.y};
+}
+
+// The diagonal block is worked on in FP64 in LDS for both storage types T:
+// an FP32 factor stores the FP64 result rounded to FP32.
+template <typename T>
 __global__ __launch_bounds__(kRecThreads) void k_potrf_rec(const MatDesc* __restrict__ desc,
                                                            const int32_t* __restrict__ order, int step,
-                                                           double* __restrict__ A, double* __restrict__ Ainv,
+                                                           T* __restrict__ A, T* __restrict__ Ainv,
                                                            const double* __restrict__ odiag, double drop_tol,
                                                            double* __restrict__ pivrel, DevErr* err,
                                                            int32_t* __restrict__ failed) {
@@ -660,15 +676,15 @@ __global__ __launch_bounds__(kRecThreads) void k_potrf_rec(const MatDesc* __rest
   const MatDesc d = desc[m];
   const int tid = threadIdx.x;
   const int64_t k0 = (int64_t)step * NB;
-  double* blk = A + d.off + k0 * d.ld + k0;
+  T* blk = A + d.off + k0 * d.ld + k0;
   const bool have_od = odiag && d.diag_off >= 0;
-  // load the lower triangle (16-byte loads, 64 threads per column, 4 columns
-  // per pass; entries above the diagonal are replaced by zeros)
+  // load the lower triangle (two entries per thread and column, 64 threads
+  // per column, 4 columns per pass; entries above the diagonal are replaced by zeros)
   const int rr = 2 * (tid & 63), cq = tid >> 6;
   for (int c0 = 0; c0 < NB; c0 += 32) {
     double2 buf[8];
 #pragma unroll
-    for (int u = 0; u < 8; ++u) buf[u] = *reinterpret_cast<const double2*>(blk + (int64_t)(c0 + 4 * u + cq) * d.ld + rr);
+    for (int u = 0; u < 8; ++u) buf[u] = ld2<T>(blk + (int64_t)(c0 + 4 * u + cq) * d.ld + rr);
 #pragma unroll
     for (int u = 0; u < 8; ++u) {
       const int c = c0 + 4 * u + cq;
@@ -712,8 +728,8 @@ __global__ __launch_bounds__(kRecThreads) void k_potrf_rec(const MatDesc* __rest
       }
     }
   }
-  double* inv = Ainv + d.inv_off + (int64_t)step * NB * NB;
-  double* uinv = Ainv + d.inv_off + ((int64_t)d.nblk + step) * NB * NB;   // inv(U_II) = inv(L_II)^T
+  T* inv = Ainv + d.inv_off + (int64_t)step * NB * NB;
+  T* uinv = Ainv + d.inv_off + ((int64_t)d.nblk + step) * NB * NB;   // inv(U_II) = inv(L_II)^T
   for (int c0 = 0; c0 < NB; c0 += 4) {
     const int c = c0 + cq;
     double2 l, x, u;
@@ -728,12 +744,12 @@ __global__ __launch_bounds__(kRecThreads) void k_potrf_rec(const MatDesc* __rest
       if (e == 0) { l.x = lv; x.x = xv; u.x = uv; } else { l.y = lv; x.y = xv; u.y = uv; }
     }
     if (rr >= c) {
-      *reinterpret_cast<double2*>(blk + (int64_t)c * d.ld + rr) = l;
+      st2<T>(blk + (int64_t)c * d.ld + rr, l);
     } else if (rr + 1 == c) {
-      blk[(int64_t)c * d.ld + rr + 1] = l.y;
+      blk[(int64_t)c * d.ld + rr + 1] = (T)l.y;
     }
-    *reinterpret_cast<double2*>(inv + (int64_t)c * NB + rr) = x;
-    *reinterpret_cast<double2*>(uinv + (int64_t)c * NB + rr) = u;
+    st2<T>(inv + (int64_t)c * NB + rr, x);
+    st2<T>(uinv + (int64_t)c * NB + rr, u);
   }
 }
 
@@ -968,11 +984,11 @@ static void factor_run(const FactorPlan& P, T* A, T* Ainv, const double* odiag, 
   const size_t mma_lds = MODE == 2 ? sizeof(T) * 4 * KCH * NB : 0;   // two stages of A and B chunks
   const unsigned threads = 64 * TileGeo<MODE>::WAVES;
   static bool attr_set = false;
-  // FP64: recursive diagonal-block kernel or the register one (schedule)
-  const bool rec_potrf = P.cfg.rec_potrf && sizeof(T) == 8;
+  // diagonal blocks: recursive FP64 kernel in LDS or the register one (schedule)
+  const bool rec_potrf = P.cfg.rec_potrf != 0;
   if (!attr_set) {
     HIP_CHECK(hipFuncSetAttribute((const void*)k_potrf<T>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
-    HIP_CHECK(hipFuncSetAttribute((const void*)k_potrf_rec, hipFuncAttributeMaxDynamicSharedMemorySize,
+    HIP_CHECK(hipFuncSetAttribute((const void*)k_potrf_rec<T>, hipFuncAttributeMaxDynamicSharedMemorySize,
                                   (int)(sizeof(double) * NB * LDA)));
     if (MODE == 2) {
       HIP_CHECK(hipFuncSetAttribute((const void*)k_trsm<T, MODE>, hipFuncAttributeMaxDynamicSharedMemorySize,
@@ -995,17 +1011,12 @@ static void factor_run(const FactorPlan& P, T* A, T* Ainv, const double* odiag, 
     for (int g = 0; g < G && s0 + g < P.max_blk; ++g) {
       const int s = s0 + g;
       const int64_t* pt = P.d_prefix.p + P.pre_off[s];
-      if constexpr (sizeof(T) == 8) {
-        if (rec_potrf)
-          k_potrf_rec<<<dim3(P.cnt[s]), dim3(kRecThreads), sizeof(double) * NB * LDA, st>>>(
-              P.d_desc.p, P.d_order.p, s, A, Ainv, odiag, drop_tol, pivrel, err, failed);
-        else
-          k_potrf<T><<<dim3(P.cnt[s]), dim3(kPotrfThreads), lds, st>>>(P.d_desc.p, P.d_order.p, s, A, Ainv, odiag,
-                                                                         drop_tol, pivrel, err, failed);
-      } else {
+      if (rec_potrf)
+        k_potrf_rec<T><<<dim3(P.cnt[s]), dim3(kRecThreads), sizeof(double) * NB * LDA, st>>>(
+            P.d_desc.p, P.d_order.p, s, A, Ainv, odiag, drop_tol, pivrel, err, failed);
+      else
         k_potrf<T><<<dim3(P.cnt[s]), dim3(kPotrfThreads), lds, st>>>(P.d_desc.p, P.d_order.p, s, A, Ainv, odiag,
                                                                        drop_tol, pivrel, err, failed);
-      }
       if (P.trsm_tiles[s] > 0)
         k_trsm<T, MODE><<<dim3((unsigned)P.trsm_tiles[s]), dim3(threads), mma_lds, st>>>(
             P.d_desc.p, P.d_order.p, pt, P.cnt[s], s, A, Ainv, P.sparse ? P.d_trsm_rows.p + P.trsm_off[s] : nullptr,

@@ -112,9 +112,13 @@ __global__ void k_g(int64_t len, int k, const int32_t* __restrict__ row_sub, con
 // R = AX - BX diag(theta) (into W); also per-(subdomain, column) squared norms of R and BX
 // theta[j k + q] = x^T (A x) / x^T (B x) for column q of subdomain j's block
 // (Rayleigh quotients of the current block; one workgroup per column)
+// With LtX (the block L_B^T X, B = L_B L_B^T) the denominator is ||L_B^T x||^2:
+// a sum of squares, whose rounding error is relative to itself, where x^T (B x)
+// cancels (B ill conditioned, x^T B x << ||B|| ||x||^2) and carries
+// u ||B|| ||x||^2.
 __global__ __launch_bounds__(256) void k_rq(int k, const int64_t* __restrict__ voff, const double* __restrict__ X,
                                             const double* __restrict__ AX, const double* __restrict__ BX,
-                                            double* __restrict__ theta) {
+                                            const double* __restrict__ LtX, double* __restrict__ theta) {
   const int j = blockIdx.x / k, q = blockIdx.x % k;
   const int64_t ld = voff[j + 1] - voff[j];
   const int64_t o = voff[j] * k + (int64_t)q * ld;
@@ -122,7 +126,12 @@ __global__ __launch_bounds__(256) void k_rq(int k, const int64_t* __restrict__ v
   for (int64_t r = threadIdx.x; r < ld; r += 256) {
     const double x = X[o + r];
     s1 += x * AX[o + r];
-    s2 += x * BX[o + r];
+    if (LtX) {
+      const double y = LtX[o + r];
+      s2 += y * y;
+    } else {
+      s2 += x * BX[o + r];
+    }
   }
   __shared__ double a1[256], a2[256];
   a1[threadIdx.x] = s1;
@@ -136,6 +145,55 @@ __global__ __launch_bounds__(256) void k_rq(int k, const int64_t* __restrict__ v
     __syncthreads();
   }
   if (threadIdx.x == 0 && a2[0] > 0.0) theta[j * k + q] = a1[0] / a2[0];
+}
+
+// Y = L^T X on every subdomain (L: the lower Cholesky factor of the batched
+// local matrices, column-major, ld = n_pad; only its lower triangle is read):
+// Y[I-block rows, q] = sum over rows r >= 128 I of L[r, 128 I + i] X[r, q].
+// One workgroup per (subdomain, 128-row block I), rows staged through LDS in
+// chunks of 32.  blk[g] = (subdomain, I) of workgroup g.
+constexpr int kLtChunk = 32;
+__global__ __launch_bounds__(256) void k_ltx(int k, const MatDesc* __restrict__ desc,
+                                             const int32_t* __restrict__ blk, const int64_t* __restrict__ voff,
+                                             const double* __restrict__ L, const double* __restrict__ X,
+                                             double* __restrict__ Y) {
+  __shared__ double lt[kLtChunk][NB + 1];
+  __shared__ double xt[kLtChunk][33];
+  const int j = blk[2 * blockIdx.x], I = blk[2 * blockIdx.x + 1];
+  const MatDesc d = desc[j];
+  const int64_t ld = voff[j + 1] - voff[j];   // = d.ld
+  const double* Xj = X + voff[j] * k;
+  const int tid = threadIdx.x;
+  const int i = tid & (NB - 1), qh = tid >> 7;   // column of the block column; half of the right-hand sides
+  const int64_t c0 = (int64_t)I * NB;
+  double acc[16];
+#pragma unroll
+  for (int t = 0; t < 16; ++t) acc[t] = 0.0;
+  for (int64_t r0 = c0; r0 < d.ld; r0 += kLtChunk) {
+    // stage L[r0 .. r0 + 31, c0 .. c0 + 127] (lower triangle only) and X[r0 .. r0 + 31, 0 .. k - 1]
+    for (int e = tid; e < kLtChunk * NB; e += 256) {
+      const int rr = e & (kLtChunk - 1), cc = e >> 5;
+      const int64_t r = r0 + rr, c = c0 + cc;
+      lt[rr][cc] = r >= c ? L[d.off + c * d.ld + r] : 0.0;
+    }
+    for (int e = tid; e < kLtChunk * 32; e += 256) {
+      const int rr = e & (kLtChunk - 1), q = e >> 5;
+      xt[rr][q] = q < k ? Xj[(int64_t)q * ld + r0 + rr] : 0.0;
+    }
+    __syncthreads();
+#pragma unroll 4
+    for (int rr = 0; rr < kLtChunk; ++rr) {
+      const double l = lt[rr][i];
+#pragma unroll
+      for (int t = 0; t < 16; ++t) acc[t] += l * xt[rr][2 * t + qh];
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int t = 0; t < 16; ++t) {
+    const int q = 2 * t + qh;
+    if (q < k) Y[voff[j] * k + (int64_t)q * ld + c0 + i] = acc[t];
+  }
 }
 
 __global__ __launch_bounds__(256) void k_residual(int k, const int64_t* __restrict__ voff, const double* __restrict__ AX,
@@ -826,6 +884,8 @@ struct EigWork {
   FactorPlan node;
   DevBuf<unsigned> flags_node, flags_local;
   DevBuf<double> xrow;   // row-major copy of a block for the sparse products [len x 32] (gather path)
+  DevBuf<int32_t> lt_blk;   // (subdomain, 128-row block) pairs of the L^T X products
+  int64_t nlt = 0;
   int64_t nchunks = 0;
   // LDS-staged sparse products: per 64-row block the sorted distinct local
   // columns of its rows, and per nonzero its position in that list
@@ -1267,6 +1327,10 @@ void solve_local_gevps(geneo_ctx* ctx, geneo_precond* pc) {
     }
     ne_off[N] = (int64_t)ne_ptr.size();
     w.node.build(ndesc, st);
+    // plain form: S_j = G^T A_j G is ill conditioned for small gamma (2e8 at gamma = 1e-4), and
+    // premultiplying the off-diagonal blocks by explicit diagonal-block inverses loses accuracy
+    // the Rayleigh quotients of the filtered operator see
+    w.node.solve_form = false;
     w.S.alloc(off);
     w.H.alloc(off);
     w.Sinv.alloc(inv_off);
@@ -1326,6 +1390,16 @@ void solve_local_gevps(geneo_ctx* ctx, geneo_precond* pc) {
   k_dense_scatter_vals<<<nb256(lnnz), 256, 0, st>>>(lnnz, pc->d_lrow.p, pc->d_lcol.p, pc->d_lnnz_off.p, N,
                                                      pc->local.d_desc.p, w.bval.p, w.LB.p);
   factor(pc->local, w.LB.p, w.LBinv.p, nullptr, 0.0, nullptr, ctx->d_err, st);
+  {
+    std::vector<int32_t> lb;
+    for (int j = 0; j < N; ++j)
+      for (int I = 0; I < ld[j].nblk; ++I) {
+        lb.push_back(j);
+        lb.push_back(I);
+      }
+    w.nlt = (int64_t)lb.size() / 2;
+    w.lt_blk.upload(lb, st);
+  }
   w.flags_local.alloc(pc->d_flags_local.n);
   HIP_CHECK(hipMemsetAsync(w.flags_local.p, 0, sizeof(unsigned) * pc->d_flags_local.n, st));
 
@@ -1510,7 +1584,10 @@ void solve_local_gevps(geneo_ctx* ctx, geneo_precond* pc) {
   for (it = 1; it <= maxit; ++it) {
     // Ritz values as Rayleigh quotients of the current block (the projection
     // out of span(G_j) after the update moves them off the Rayleigh-Ritz values)
-    if (it > 1) k_rq<<<N * k, 256, 0, st>>>(k, w.voff_d.p, X.p, AX.p, BX.p, theta.p);
+    if (it > 1) {
+      k_ltx<<<(unsigned)w.nlt, 256, 0, st>>>(k, pc->local.d_desc.p, w.lt_blk.p, w.voff_d.p, w.LB.p, X.p, T2.p);
+      k_rq<<<N * k, 256, 0, st>>>(k, w.voff_d.p, X.p, AX.p, BX.p, T2.p, theta.p);
+    }
     k_residual<<<N * k, 256, 0, st>>>(k, w.voff_d.p, AX.p, BX.p, theta.p, Wb.p, nrm.p, nullptr);
     HIP_CHECK(hipMemcpyAsync(h_theta.data(), theta.p, sizeof(double) * N * k, hipMemcpyDeviceToHost, st));
     HIP_CHECK(hipMemcpyAsync(h_nrm.data(), nrm.p, sizeof(double) * N * k * 2, hipMemcpyDeviceToHost, st));

@@ -78,6 +78,8 @@ struct geneo_precond {
 namespace geneo {
 
 void launch_spmv(const geneo_system* s, const double* x, double* y, hipStream_t st);
+// y = |b| + |A| |x| (componentwise)
+void launch_spmv_abs(const geneo_system* s, const double* x, const double* b, double* y, hipStream_t st);
 void setup_precond(geneo_ctx* ctx, geneo_precond* pc);
 void apply_precond(geneo_ctx* ctx, const geneo_precond* pc, const double* r, double* z);
 void pcg(geneo_ctx* ctx, const geneo_system* sys, const geneo_precond* pc, const double* b, double* x,

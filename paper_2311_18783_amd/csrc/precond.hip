@@ -1095,8 +1095,11 @@ void setup_precond(geneo_ctx* ctx, geneo_precond* pc) {
     const double q_floor = rho_max > 0.0 ? kFp32RhoPerBound * 0x1p-24 / rho_max : INFINITY;
     k_fp32_check<<<N, 256, 0, st>>>(c_smp.p, c_pair.p, c_slot.p, c_w.p, s->d_val.p, q_floor, failed.p, klb.p);
     HIP_CHECK(hipGetLastError());
+    HIP_CHECK(hipEventRecord(ctx->ev[2], st));
     factor(pc->local, pc->fL.p, pc->fLinv.p, nullptr, 0.0, nullptr, ctx->d_err, st, failed.p);
+    HIP_CHECK(hipEventRecord(ctx->ev[3], st));
     check_device_error(ctx);
+    pc->info.t_factor_fp32_ms = elapsed(ctx, 2, 3);
     fp32_probe(ctx, pc, descs, failed.p, klb.p);
   } else {
     factor(pc->local, pc->dL.p, pc->dLinv.p, nullptr, 0.0, nullptr, ctx->d_err, st);
@@ -1597,12 +1600,19 @@ void pcg(geneo_ctx* ctx, const geneo_system* sys, const geneo_precond* pc, const
         // an inexactly applied preconditioner): compute the true residual;
         // with opts->true_residual, continue from it with a fresh direction
         // while it misses the tolerance (at most twice)
+        // rounding scale of that residual: (m + 1) u || |b| + |A| |x| || with m
+        // the largest row length of A (componentwise bound of fl(b - A x) - (b - A x))
+        launch_spmv_abs(sys, x, b, z.p, st);
+        dot(z.p, z.p, n, part.p, S.p + 7, st);
         launch_spmv(sys, x, q.p, st);
         k_axpby<<<nblocks(n), 256, 0, st>>>(n, 1.0, b, -1.0, q.p, q.p);
         dot(q.p, q.p, n, part.p, S.p + 6, st);
-        HIP_CHECK(hipMemcpyAsync(h + 6, S.p + 6, sizeof(double), hipMemcpyDeviceToHost, st));
+        HIP_CHECK(hipMemcpyAsync(h + 6, S.p + 6, 2 * sizeof(double), hipMemcpyDeviceToHost, st));
         HIP_CHECK(hipStreamSynchronize(st));
         info->true_rel_residual = std::sqrt(h[6]) / bnorm;
+        int32_t mrow = 0;
+        for (int64_t i = 0; i < n; ++i) mrow = std::max(mrow, sys->rowptr[i + 1] - sys->rowptr[i]);
+        info->residual_floor = (mrow + 1) * 0x1p-53 * std::sqrt(h[7]) / bnorm;
         conv = true;
         if (!o->true_residual || std::sqrt(h[6]) <= tol) break;
         if (replaced >= 2) {

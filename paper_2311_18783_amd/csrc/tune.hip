@@ -154,10 +154,7 @@ static FactorConfig tune(geneo_ctx* ctx, const std::vector<MatDesc>& descs, int6
   std::vector<FactorConfig> cands;
   for (int mode : {0, 1, 2})
     for (int group : {4, 8, 16})
-      for (int rec : {1, 0}) {
-        if (rec == 0 && sizeof(T) != 8) continue;   // FP32 has the register kernel only
-        cands.push_back(FactorConfig{mode, group, rec});
-      }
+      for (int rec : {1, 0}) cands.push_back(FactorConfig{mode, group, rec});
   FactorConfig best{};
   *best_ms = 1e300;
   for (const auto& c : cands) {

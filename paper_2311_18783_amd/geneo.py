@@ -87,7 +87,7 @@ class PrecondInfo(C.Structure):
                 ("learned_starts", C.c_int32), ("start_residual", C.c_double),
                 ("fp32_prechecked", C.c_int32), ("fp32_kappa_lb", C.c_double),
                 ("learned_candidates", C.c_int32), ("coarse_nd_levels", C.c_int32),
-                ("coarse_solve_depth", C.c_int32)]
+                ("coarse_solve_depth", C.c_int32), ("t_factor_fp32_ms", C.c_double)]
 
 
 class ModelOpts(C.Structure):
@@ -120,7 +120,7 @@ class SolveOpts(C.Structure):
 class SolveInfo(C.Structure):
     _fields_ = [("iterations", C.c_int32), ("rel_residual", C.c_double), ("solve_ms", C.c_double),
                 ("graph_replays", C.c_int32), ("residual_replacements", C.c_int32),
-                ("true_rel_residual", C.c_double)]
+                ("true_rel_residual", C.c_double), ("residual_floor", C.c_double)]
 
 
 _vp = C.c_void_p

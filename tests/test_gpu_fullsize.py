@@ -84,16 +84,16 @@ def test_cube24_gevp_eigenvalues_smallest_and_largest_subdomain(g, cube24):
     (eigAtildeBAS), on the smallest (n_i = 3,584) and the largest
     (n_i = 7,930) subdomain of the 24^3 channel cube against the oracle's
     dense generalised eigensolver: the selected counts agree outside a tie
-    band of 1e-6 around tau, and every selected eigenvalue agrees to 1e-8
-    relative or to the a posteriori bound of its Ritz pair in the oracle's
-    own pencil, ||r||_{B^-1}^2 / gap (x B-normalised, r = Atilde x - theta
-    B x, gap = distance of theta to the nearest other eigenvalue), whichever
-    is larger.  At gamma = 1e-4 the B^-1-norm residual of any FP64
-    evaluation of the filtered operator stalls near 1e-5 theta (the oracle's
-    own eigenvectors show it under the library's sequence of products), so
-    clustered eigenvalues are determined to a few 1e-9 relative, not to
-    arbitrary precision."""
+    band of 1e-6 around tau; the Rayleigh quotients of the library's Ritz
+    vectors in the oracle's own pencil agree with the oracle's eigenvalues to
+    1e-10; and every selected eigenvalue agrees to 1e-8 relative or within
+    twice the first-order perturbation bound of a backward-stable FP64
+    evaluation of the pencil, u ||x||^2 (||Atilde|| + lambda ||B||) (x
+    B-normalised), whichever is larger.  At gamma = 1e-4, B = A^Neu is ill
+    conditioned and the B-normalised eigenvectors are long, so that bound
+    reaches a few 1e-9 lambda: the oracle's own eigenvalues carry it too."""
     import scipy.linalg as sla
+    import scipy.sparse.linalg as ssla
     from oracle import geneo as og
     geneo, ctx = g
     w, s, odec = cube24
@@ -103,10 +103,11 @@ def test_cube24_gevp_eigenvalues_smallest_and_largest_subdomain(g, cube24):
     sysm, dec = lib_problem(ctx, w)
     pc = ctx.setup(sysm, dec, tau=w.tau, nev_max=w.nev_max, keep_ritz=1)
     assert pc.info().lobpcg_unconverged == 0
+    u = np.finfo(float).eps / 2
     for i in picks:
         Gi, _, _ = odec.G_local(i)
         Ai, Bn = odec.A_dir(i).toarray(), odec.A_neu(i).toarray()
-        lam_o, _, sel_o = og.gevp(Ai, Bn, odec.D[i], Gi, w.tau, w.nev_max)
+        lam_o, V_o, sel_o = og.gevp(Ai, Bn, odec.D[i], Gi, w.tau, w.nev_max)
         lam_g, sel_g = pc.eigs(i)
         near = np.abs(lam_o[:w.nev_max + 1] / w.tau - 1.0) < 1e-6
         if not near.any():
@@ -116,15 +117,17 @@ def test_cube24_gevp_eigenvalues_smallest_and_largest_subdomain(g, cube24):
         At, _ = og.filtered_pencil(Ai, Bn, odec.D[i], Gi)
         V = pc.ritz(i, Ai.shape[0], cap=w.nev_max)[:, :m]
         V = V / np.sqrt(np.einsum("ij,ij->j", V, Bn @ V))
-        R = At @ V - (Bn @ V) * lam_g[:m]
-        cB = sla.cho_factor(Bn)
-        rb2 = np.einsum("ij,ij->j", R, sla.cho_solve(cB, R))
-        gap = np.array([np.min(np.abs(np.delete(lam_o, q) - lam_g[q])) for q in range(m)])
+        rq = np.einsum("ij,ij->j", V, At @ V)
+        rq_err = (np.abs(rq - lam_o[:m]) / np.abs(lam_o[:m])).max()
+        nA = ssla.eigsh(At, k=1, which="LA", return_eigenvectors=False)[0]
+        nB = ssla.eigsh(Bn, k=1, which="LA", return_eigenvectors=False)[0]
+        x2 = np.einsum("ij,ij->j", V_o[:, :m], V_o[:, :m])
+        bound = np.maximum(1e-8 * np.abs(lam_o[:m]), 2 * u * x2 * (nA + np.abs(lam_o[:m]) * nB))
         err = np.abs(lam_g[:m] - lam_o[:m])
-        bound = np.maximum(1e-8 * np.abs(lam_o[:m]), 2.0 * np.maximum(rb2, 0.0) / gap)
         print("subdomain", i, "n_i", sizes[i], "selected", sel_g, "max rel err", (err / np.abs(lam_o[:m])).max(),
               "within 1e-8:", int((err <= 1e-8 * np.abs(lam_o[:m])).sum()), "of", m,
-              "max bound / 1e-8 lambda", (bound / (1e-8 * np.abs(lam_o[:m]))).max(), flush=True)
+              "bound / lambda max", (bound / np.abs(lam_o[:m])).max(), "Rayleigh quotients", rq_err, flush=True)
+        assert rq_err <= 1e-10
         assert (err <= bound).all(), (i, err / np.abs(lam_o[:m]), bound / np.abs(lam_o[:m]))
 
 
@@ -161,8 +164,8 @@ def test_cube24_one_level_apply_matches_sparse_direct_local_solves(g, cube24):
 def test_cube24_pcg_residual_and_coarse_basis_stable_across_start_blocks(g, cube24):
     """AS-SNK-GenEO PCG on the 24^3 cube (eq. (AS2)) from two eigensolver
     start seeds, continuing from the true residual while it misses rtol:
-    both reach a true relative residual ||b - A x|| / ||b|| <= 1.05e-8 with
-    the oracle's assembled A, as the library reports it (a property at any size; a
+    both reach a true relative residual ||b - A x|| / ||b|| <= 1e-8 with
+    the oracle's assembled A up to the rounding of its evaluation (a property at any size; a
     sparse direct solve of this system takes longer than the test budget),
     the coarse spaces have the same size, rank and per-subdomain GenEO
     counts, and the iteration counts agree within one."""
@@ -179,11 +182,17 @@ def test_cube24_pcg_residual_and_coarse_basis_stable_across_start_blocks(g, cube
         si = ctx.solve(sysm, pc, to_dev(b), x, rtol=1e-8, true_residual=True)
         xg = x.cpu().numpy()
         tr = np.linalg.norm(b - s.A @ xg) / np.linalg.norm(b)
-        assert abs(tr - si.true_rel_residual) <= 1e-3 * tr
+        # both residual evaluations carry rounding of at most (m + 1) u || |b| + |A| |x| || / ||b||
+        m = int(np.diff(s.A.indptr).max())
+        floor = (m + 1) * 2.0 ** -53 * np.linalg.norm(np.abs(b) + abs(s.A) @ np.abs(xg)) / np.linalg.norm(b)
+        print("true residual", tr, "library", si.true_rel_residual, "floor", floor, "library floor",
+              si.residual_floor, flush=True)
+        assert abs(tr - si.true_rel_residual) <= 2 * floor
+        assert abs(si.residual_floor - floor) <= 1e-3 * floor
         inf = pc.info()
         print("seed", seed, "iterations", si.iterations, "true residual", tr, "n0", inf.n0, "rank", inf.n0_rank,
               "geneo", inf.n_geneo, flush=True)
-        assert tr <= 1.05e-8
+        assert tr <= 1e-8 + 2 * floor
         res.append((si.iterations, inf.n0, inf.n0_rank, inf.n_geneo, [pc.eigs(i)[1] for i in range(odec.N)]))
         del pc
     (it1, n01, rk1, ng1, sel1), (it2, n02, rk2, ng2, sel2) = res

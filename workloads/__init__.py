@@ -276,6 +276,18 @@ def make(cfg, family=0, **over):
                      describe="beam 128x16x16 hexes x 6 tets (196,608), h = 1/16, mu alternating 1 / 1e3 "
                               "in 8 slabs along x, eps = 1, gamma = 1e-6, all-Dirichlet, RCB 256 parts "
                               "(+-30% jitter), overlap 1")
+    elif cfg == "cube24_homog":
+        # The 24^3 cube of config 2 with the homogeneous coefficients and gamma of config 1: the
+        # same subdomain sizes (n_i 3,584 .. 7,930), local matrices well enough conditioned for
+        # FP32 factors (measures the FP32 local factorisation).
+        dims = (24, 24, 24)
+        mesh = hex_box_mesh(dims)
+        T = mesh["tets"].shape[0]
+        w = Workload("cube24_homog", mesh, np.ones(T), np.ones(T), 1e-2,
+                     dirichlet_flags(mesh["bface_tag"], "all"),
+                     {"kind": "box", "p": (4, 4, 4)}, 2, seed=2005,
+                     describe="24^3 hexes x 6 tets (82,944), mu = eps = 1, gamma = 1e-2, all-Dirichlet, "
+                              "4x4x4 boxes, overlap 2")
     elif isinstance(cfg, str) and cfg.startswith("beam") and cfg[4:].isdigit():
         # The paper's weak-scaling beam (Section 4 "Numerical results", influence of the geometry):
         # N/2 x 1 x 1 with h = 1/16 (8N x 16 x 16 hexes), N strip subdomains
