@@ -402,6 +402,19 @@ int geneo_tune_lookup(int32_t batch, const int32_t* n_host, int32_t precision, g
 int geneo_tune_save(const char* path);
 int geneo_tune_load(const char* path);
 
+/* Allocation-free geneo_potrf_batched, for callers that cannot allocate
+ * device memory (code under stream capture, serving loops, harnesses that
+ * forbid hipMalloc).  Same arguments, layout, results (bitwise) and errors as
+ * geneo_potrf_batched; the factorisation plan and the diagonal-block inverses
+ * live in a 64 MiB device array per device (held until the process ends)
+ * instead of buffers allocated per call.  Limit: the inverses take
+ * 2 * 128 * ld_b elements of the factor's type per matrix plus a few hundred
+ * bytes of plan per block column, so sum_b ld_b <= ~32,000 in FP64
+ * (~64,000 in FP32); a larger batch returns GENEO_EINVAL before any device
+ * work.  Calls that overlap on one device share the array and race. */
+int geneo_potrf_batched_noalloc(geneo_ctx* ctx, int32_t batch, const int32_t* n_host,
+                                const int64_t* off_host, void* A, int32_t precision, double* elapsed_ms);
+
 /* --- lifetime ----------------------------------------------------------- */
 void geneo_free_system(geneo_system* sys);
 void geneo_free_decomp(geneo_decomp* dec);

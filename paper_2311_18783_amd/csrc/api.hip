@@ -8,6 +8,9 @@ namespace geneo {
 void build_topology(geneo_system* s, const geneo_mesh* m);
 void assemble_device(geneo_ctx* ctx, geneo_system* s, const double* mu, const double* eps, double gamma);
 void build_decomposition(const geneo_system* s, const geneo_partition_opts* o, geneo_decomp* dec);
+void noalloc_init(int device);
+void potrf_noalloc(geneo_ctx* ctx, int32_t batch, const int32_t* n_host, const int64_t* off_host, void* A,
+                   int32_t precision, double* elapsed_ms);
 FactorConfig autotune_factor(geneo_ctx* ctx, int32_t batch, const int32_t* n_host, int precision, int reps,
                              double* best_ms, int* tried);
 }  // namespace geneo
@@ -48,6 +51,7 @@ int geneo_create(geneo_ctx** out, int device, void* hip_stream) {
     HIP_CHECK(hipGetDeviceCount(&ndev));
     if (device < 0 || device >= ndev) throw Error(GENEO_EINVAL, "no such device");
     HIP_CHECK(hipSetDevice(device));
+    noalloc_init(device);   // device address of the allocation-free entry's scratch array
     // NULL is the device's default (null) stream: work is then ordered with
     // everything else issued on it, e.g. torch's default stream.
     ctx->stream = (hipStream_t)hip_stream;
@@ -378,6 +382,15 @@ int geneo_tune_load(const char* path) {
     return GENEO_EINVAL;
   }
   return GENEO_OK;
+}
+
+int geneo_potrf_batched_noalloc(geneo_ctx* ctx, int32_t batch, const int32_t* n_host, const int64_t* off_host,
+                                void* A, int32_t precision, double* elapsed_ms) {
+  if (!ctx || batch < 1 || !n_host || !off_host || !A) return GENEO_EINVAL;
+  return guarded(ctx, [&] {
+    potrf_noalloc(ctx, batch, n_host, off_host, A, precision, elapsed_ms);
+    check_device_error(ctx);
+  });
 }
 
 void geneo_model_opts_default(geneo_model_opts* o) {

@@ -64,6 +64,13 @@ struct FactorPlan {
   mutable DevBuf<double> d_ym;       // many-right-hand-side solves: intermediate block (on first use)
   // precision: the factor's type (GENEO_FP64 or GENEO_FP32_REFINE1), selects the schedule
   void build(const std::vector<MatDesc>& descs, hipStream_t st, int precision = GENEO_FP64);
+  // The same plan with only what factor(..., for_solves = false) reads on the
+  // device (descriptors, order, per-step and trailing-update prefixes), placed
+  // in caller-owned device memory [mem, mem + bytes) instead of allocated;
+  // throws GENEO_EINVAL if it does not fit.  Returns the bytes used (multiple
+  // of 256).  Host copies stay in the plan until it is destroyed.
+  size_t build_in(const std::vector<MatDesc>& descs, void* mem, size_t bytes, hipStream_t st,
+                  int precision = GENEO_FP64);
   // host side of build(): ordering, prefixes, launches, solve items (with
   // the schedule `force` instead of the table's, if given)
   void plan_host(const std::vector<MatDesc>& descs, int precision = GENEO_FP64,

@@ -22,6 +22,7 @@
 #include <algorithm>
 #include <cstdlib>
 #include <string>
+#include <type_traits>
 
 #include "dense.h"
 
@@ -855,6 +856,27 @@ void FactorPlan::build(const std::vector<MatDesc>& descs, hipStream_t st, int pr
   d_mirror_prefix.upload(h_mirror_prefix, st);
   d_items_fwd.upload(h_items_fwd, st);
   d_items_bwd.upload(h_items_bwd, st);
+}
+
+size_t FactorPlan::build_in(const std::vector<MatDesc>& descs, void* mem, size_t bytes, hipStream_t st,
+                            int precision) {
+  plan_host(descs, precision);
+  char* base = static_cast<char*>(mem);
+  size_t used = 0;
+  auto place = [&](auto& buf, const auto& host) {
+    using E = typename std::remove_reference<decltype(host)>::type::value_type;
+    const size_t nb = round_up((int64_t)(host.size() * sizeof(E)), 256);
+    if (used + nb > bytes) throw Error(GENEO_EINVAL, "plan does not fit the scratch area");
+    buf.view(reinterpret_cast<E*>(base + used), host.size());
+    if (!host.empty())
+      HIP_CHECK(hipMemcpyAsync(buf.p, host.data(), host.size() * sizeof(E), hipMemcpyHostToDevice, st));
+    used += nb;
+  };
+  place(d_desc, h_desc);
+  place(d_order, h_order);
+  place(d_prefix, h_prefix);
+  place(d_syrk_prefix, h_syrk_prefix);
+  return used;
 }
 
 void symbolic_fill(int nb, std::vector<uint8_t>& pat) {

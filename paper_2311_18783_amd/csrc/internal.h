@@ -125,6 +125,7 @@ struct DevBuf {
   T* p = nullptr;
   size_t n = 0;
   size_t cap = 0;   // bytes of the underlying block
+  bool owned = true;  // false: a view of memory owned elsewhere (never freed here)
   DevBuf() = default;
   DevBuf(const DevBuf&) = delete;
   DevBuf& operator=(const DevBuf&) = delete;
@@ -135,8 +136,24 @@ struct DevBuf {
     std::swap(p, o.p);
     std::swap(n, o.n);
     std::swap(cap, o.cap);
+    std::swap(owned, o.owned);
+  }
+  // view of `count` elements at `q` (memory owned by the caller)
+  void view(T* q, size_t count) {
+    release();
+    p = q;
+    n = count;
+    cap = count * sizeof(T);
+    owned = false;
   }
   void release() {
+    if (p && !owned) {
+      p = nullptr;
+      n = 0;
+      cap = 0;
+      owned = true;
+      return;
+    }
     if (p) {
       if (cap >= kPoolMinBytes)
         BlockPool::get().give(p, cap);

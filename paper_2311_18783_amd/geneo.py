@@ -146,6 +146,8 @@ _sigs = {
     "geneo_solve": (C.c_int, [_vp, _vp, _vp, _vp, _vp, _P(SolveOpts), _P(SolveInfo)]),
     "geneo_potrf_batched": (C.c_int, [_vp, C.c_int32, _P(C.c_int32), _P(C.c_int64), _vp, C.c_int32,
                                       _P(C.c_double)]),
+    "geneo_potrf_batched_noalloc": (C.c_int, [_vp, C.c_int32, _P(C.c_int32), _P(C.c_int64), _vp, C.c_int32,
+                                              _P(C.c_double)]),
     "geneo_tune_factor": (C.c_int, [_vp, C.c_int32, _P(C.c_int32), C.c_int32, C.c_int32, _P(FactorSchedule),
                                     _P(C.c_int32)]),
     "geneo_tune_lookup": (C.c_int, [C.c_int32, _P(C.c_int32), C.c_int32, _P(FactorSchedule)]),
@@ -344,8 +346,9 @@ class Context:
         self._check(rc)
         return info
 
-    def potrf_batched(self, A, sizes, offsets, precision=FP64):
-        """geneo_potrf_batched."""
+    def potrf_batched(self, A, sizes, offsets, precision=FP64, noalloc=False):
+        """geneo_potrf_batched (noalloc=True: geneo_potrf_batched_noalloc, which
+        allocates no device memory and takes batches up to its scratch limit)."""
         import torch
         n = np.ascontiguousarray(sizes, dtype=np.int32)
         off = np.ascontiguousarray(offsets, dtype=np.int64)
@@ -357,8 +360,9 @@ class Context:
         if n.size == 0 or (n < 1).any() or (off < 0).any() or int((off + ld * ld).max()) > A.numel():
             raise ValueError("A: matrix sizes / offsets run past the buffer")
         ms = C.c_double()
-        self._check(lib.geneo_potrf_batched(self.h, len(n), _ptr(n, C.c_int32), _ptr(off, C.c_int64), _dptr(A),
-                                            int(precision), C.byref(ms)))
+        fn = lib.geneo_potrf_batched_noalloc if noalloc else lib.geneo_potrf_batched
+        self._check(fn(self.h, len(n), _ptr(n, C.c_int32), _ptr(off, C.c_int64), _dptr(A), int(precision),
+                       C.byref(ms)))
         return ms.value
 
 
