@@ -110,12 +110,13 @@ __global__ void k_g(int64_t len, int k, const int32_t* __restrict__ row_sub, con
 }
 
 // R = AX - BX diag(theta) (into W); also per-(subdomain, column) squared norms of R and BX
-// theta[j k + q] = x^T (A x) / x^T (B x) for column q of subdomain j's block
-// (Rayleigh quotients of the current block; one workgroup per column)
-// With LtX (the block L_B^T X, B = L_B L_B^T) the denominator is ||L_B^T x||^2:
-// a sum of squares, whose rounding error is relative to itself, where x^T (B x)
-// cancels (B ill conditioned, x^T B x << ||B|| ||x||^2) and carries
-// u ||B|| ||x||^2.
+// Shifts of column q of subdomain j's block (one workgroup per column):
+// without LtX, theta = (Bx)^T (Ax) / ||Bx||^2, the shift that minimises
+// ||Ax - theta Bx|| (no cancellation: Ax and Bx are nearly parallel);
+// with LtX (the block L_B^T X, B = L_B L_B^T) the Rayleigh quotient
+// x^T (A x) / ||L_B^T x||^2, whose denominator is a sum of squares (rounding
+// relative to itself) where x^T (B x) cancels (B ill conditioned,
+// x^T B x << ||B|| ||x||^2) and carries u ||B|| ||x||^2.
 __global__ __launch_bounds__(256) void k_rq(int k, const int64_t* __restrict__ voff, const double* __restrict__ X,
                                             const double* __restrict__ AX, const double* __restrict__ BX,
                                             const double* __restrict__ LtX, double* __restrict__ theta) {
@@ -124,13 +125,14 @@ __global__ __launch_bounds__(256) void k_rq(int k, const int64_t* __restrict__ v
   const int64_t o = voff[j] * k + (int64_t)q * ld;
   double s1 = 0.0, s2 = 0.0;
   for (int64_t r = threadIdx.x; r < ld; r += 256) {
-    const double x = X[o + r];
-    s1 += x * AX[o + r];
     if (LtX) {
       const double y = LtX[o + r];
+      s1 += X[o + r] * AX[o + r];
       s2 += y * y;
     } else {
-      s2 += x * BX[o + r];
+      const double bx = BX[o + r];
+      s1 += bx * AX[o + r];
+      s2 += bx * bx;
     }
   }
   __shared__ double a1[256], a2[256];
@@ -813,7 +815,23 @@ __global__ void k_take_rows(int64_t len, int k, const int32_t* __restrict__ row_
   }
 }
 
-// dense p x p G^T M G (M = local A or B values), one thread per (subdomain, node row a)
+// Knuth's two-sum: s + e = a + b exactly (contraction off so that no fused
+// form changes it)
+__device__ inline void two_sum(double a, double b, double& s, double& e) {
+#pragma clang fp contract(off)
+  s = a + b;
+  const double bb = s - a;
+  e = (a - (s - bb)) + (b - bb);
+}
+
+// dense p x p G^T M G (M = local A or B values), one thread per (subdomain, node row a).
+// The entries are sums of M's entries with signs that cancel down to M G ~
+// gamma (the gradients' mass part) for interior nodes; each is accumulated
+// compensated (running sum in S, its rounding errors in Slo, folded by
+// k_fold), so that S carries the rounding of its own value only.  An error of
+// u |G|^T |M| |G| would move the kernel of the filtered operator off span(G)
+// by a relative u |M| / gamma, which the eigensolver's projections out of
+// span(G) then fight: its residuals stall (for gamma = 1e-6 near 1e-5).
 __global__ void k_gmg(int64_t plen, const int32_t* __restrict__ node_sub, const int64_t* __restrict__ poff,
                       const int32_t* __restrict__ pl, const int64_t* __restrict__ ne_off,
                       const int32_t* __restrict__ ne_ptr, const int32_t* __restrict__ ne_edge,
@@ -822,7 +840,7 @@ __global__ void k_gmg(int64_t plen, const int32_t* __restrict__ node_sub, const 
                       const int32_t* __restrict__ lcol, const int32_t* __restrict__ lslot,
                       const double* __restrict__ gval, const double* __restrict__ lvals,
                       const int32_t* __restrict__ ena, const int32_t* __restrict__ enb,
-                      const MatDesc* __restrict__ ndesc, double* __restrict__ S) {
+                      const MatDesc* __restrict__ ndesc, double* __restrict__ S, double* __restrict__ Slo) {
   int64_t b = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (b >= plen) return;
   const int j = node_sub[b];
@@ -838,10 +856,27 @@ __global__ void k_gmg(int64_t plen, const int32_t* __restrict__ node_sub, const 
       const double v = sa * (lvals ? lvals[u] : gval[lslot[u]]);
       const int64_t cb = voff[j] + lcol[u];
       const int32_t na = ena[cb], nbb = enb[cb];
-      if (na >= 0) S[d.off + (int64_t)na * d.ld + a] -= v;
-      if (nbb >= 0) S[d.off + (int64_t)nbb * d.ld + a] += v;
+      double hi, e;
+      if (na >= 0) {
+        const int64_t o = d.off + (int64_t)na * d.ld + a;
+        two_sum(S[o], -v, hi, e);
+        S[o] = hi;
+        Slo[o] += e;
+      }
+      if (nbb >= 0) {
+        const int64_t o = d.off + (int64_t)nbb * d.ld + a;
+        two_sum(S[o], v, hi, e);
+        S[o] = hi;
+        Slo[o] += e;
+      }
     }
   }
+}
+
+// S += Slo
+__global__ void k_fold(int64_t n, double* __restrict__ S, const double* __restrict__ Slo) {
+  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i < n) S[i] += Slo[i];
 }
 
 __global__ void k_dense_scatter_vals(int64_t nnz, const int32_t* __restrict__ lrow, const int32_t* __restrict__ lcol,
@@ -1407,14 +1442,20 @@ void solve_local_gevps(geneo_ctx* ctx, geneo_precond* pc) {
   {
     k_fill_pad_identity<<<fill_grid(ndesc), 256, 0, st>>>(w.node.d_desc.p, w.S.p);
     k_fill_pad_identity<<<fill_grid(ndesc), 256, 0, st>>>(w.node.d_desc.p, w.H.p);
+    DevBuf<double> lo;   // rounding errors of the compensated sums (S, then H)
+    lo.alloc(w.S.n);
+    HIP_CHECK(hipMemsetAsync(lo.p, 0, sizeof(double) * lo.n, st));
     k_gmg<<<nb256(w.plen), 256, 0, st>>>(w.plen, w.node_sub.p, w.poff_d.p, w.pl.p, w.ne_off.p, w.ne_ptr.p,
                                          w.ne_edge.p, w.ne_sign.p, w.voff_d.p, w.rp_off.p, w.lrp.p, pc->d_lcol.p,
                                          pc->d_lslot.p, s->d_val.p, nullptr, w.ena.p, w.enb.p, w.node.d_desc.p,
-                                         w.S.p);
+                                         w.S.p, lo.p);
+    k_fold<<<nb256((int64_t)lo.n), 256, 0, st>>>((int64_t)lo.n, w.S.p, lo.p);
+    HIP_CHECK(hipMemsetAsync(lo.p, 0, sizeof(double) * lo.n, st));
     k_gmg<<<nb256(w.plen), 256, 0, st>>>(w.plen, w.node_sub.p, w.poff_d.p, w.pl.p, w.ne_off.p, w.ne_ptr.p,
                                          w.ne_edge.p, w.ne_sign.p, w.voff_d.p, w.rp_off.p, w.lrp.p, pc->d_lcol.p,
                                          pc->d_lslot.p, s->d_val.p, w.bval.p, w.ena.p, w.enb.p, w.node.d_desc.p,
-                                         w.H.p);
+                                         w.H.p, lo.p);
+    k_fold<<<nb256((int64_t)lo.n), 256, 0, st>>>((int64_t)lo.n, w.H.p, lo.p);
     factor(w.node, w.S.p, w.Sinv.p, nullptr, 0.0, nullptr, ctx->d_err, st);
     factor(w.node, w.H.p, w.Hinv.p, nullptr, 0.0, nullptr, ctx->d_err, st);
     check_device_error(ctx);
@@ -1582,12 +1623,10 @@ void solve_local_gevps(geneo_ctx* ctx, geneo_precond* pc) {
   int it = 0, unconv = 0;
   const int maxit = std::max(1, pc->opts.lobpcg_maxit);
   for (it = 1; it <= maxit; ++it) {
-    // Ritz values as Rayleigh quotients of the current block (the projection
-    // out of span(G_j) after the update moves them off the Rayleigh-Ritz values)
-    if (it > 1) {
-      k_ltx<<<(unsigned)w.nlt, 256, 0, st>>>(k, pc->local.d_desc.p, w.lt_blk.p, w.voff_d.p, w.LB.p, X.p, T2.p);
-      k_rq<<<N * k, 256, 0, st>>>(k, w.voff_d.p, X.p, AX.p, BX.p, T2.p, theta.p);
-    }
+    // residual shifts of the current block (the projection out of span(G_j)
+    // after the update moves it off the Rayleigh-Ritz vectors): the shifts that
+    // minimise each residual
+    if (it > 1) k_rq<<<N * k, 256, 0, st>>>(k, w.voff_d.p, X.p, AX.p, BX.p, nullptr, theta.p);
     k_residual<<<N * k, 256, 0, st>>>(k, w.voff_d.p, AX.p, BX.p, theta.p, Wb.p, nrm.p, nullptr);
     HIP_CHECK(hipMemcpyAsync(h_theta.data(), theta.p, sizeof(double) * N * k, hipMemcpyDeviceToHost, st));
     HIP_CHECK(hipMemcpyAsync(h_nrm.data(), nrm.p, sizeof(double) * N * k * 2, hipMemcpyDeviceToHost, st));
@@ -1681,6 +1720,11 @@ void solve_local_gevps(geneo_ctx* ctx, geneo_precond* pc) {
     have_p = true;
     HIP_CHECK(hipGetLastError());
   }
+  // the eigenvalues: Rayleigh quotients of the final block with the factored denominator
+  k_ltx<<<(unsigned)w.nlt, 256, 0, st>>>(k, pc->local.d_desc.p, w.lt_blk.p, w.voff_d.p, w.LB.p, X.p, T2.p);
+  k_rq<<<N * k, 256, 0, st>>>(k, w.voff_d.p, X.p, AX.p, BX.p, T2.p, theta.p);
+  HIP_CHECK(hipMemcpyAsync(h_theta.data(), theta.p, sizeof(double) * N * k, hipMemcpyDeviceToHost, st));
+  HIP_CHECK(hipStreamSynchronize(st));
   check_device_error(ctx);
   pc->info.lobpcg_iters = it > maxit ? maxit : it;
   pc->info.lobpcg_unconverged = unconv;
