@@ -53,8 +53,9 @@ def parse():
     ap.add_argument("--train-instances", type=int, default=8,
                     help="instances of the workload recipe the warm-start model is trained on (0: no model, the "
                          "learned_fp32 configuration then runs FP32 local factors with the cold start)")
-    ap.add_argument("--coarse-order", default="natural", choices=["natural", "nd"],
-                    help="elimination order of the coarse columns (nd: nested dissection of the subdomain graph)")
+    ap.add_argument("--coarse-order", default="auto", choices=["auto", "natural", "nd"],
+                    help="elimination order of the coarse columns (nd: nested dissection of the subdomain graph; "
+                         "auto: nested dissection where it shortens the coarse solves' dependency chain)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
                     help="only run one device copy of BYTES (counter calibration) and exit")
     return ap.parse_args()
@@ -127,7 +128,9 @@ def run_step(geneo, ctx, w, precision, b_host=None, model=None, coarse_order=0):
                n0_factored=pi.n0 - pi.n0_local_dropped, coarse_flops=pi.coarse_factor_flops,
                coarse_fill=pi.coarse_fill, coarse_nd_levels=pi.coarse_nd_levels,
                coarse_solve_depth=pi.coarse_solve_depth, learned_candidates=pi.learned_candidates,
-               lobpcg_unconverged=pi.lobpcg_unconverged, t_factor_fp32_ms=pi.t_factor_fp32_ms)
+               lobpcg_unconverged=pi.lobpcg_unconverged, t_factor_fp32_ms=pi.t_factor_fp32_ms,
+               coarse_lambda_min=pi.coarse_lambda_min, coarse_refactors=pi.coarse_refactors,
+               coarse_drop_tol_used=pi.coarse_drop_tol_used, coarse_nd_predicted_depth=pi.coarse_nd_predicted_depth)
     del pc, dec, sysm
     return out, b_host
 
@@ -185,6 +188,8 @@ def summarize(res):
         "coarse_factor_tflops": last["coarse_flops"] / (mean("t_coarse_factor_ms") * 1e-3) / 1e12,
         "coarse_fill": last["coarse_fill"], "coarse_nd_levels": last["coarse_nd_levels"],
         "coarse_solve_depth": last["coarse_solve_depth"], "lobpcg_unconverged": last["lobpcg_unconverged"],
+        "coarse_nd_predicted_depth": last["coarse_nd_predicted_depth"], "coarse_lambda_min": last["coarse_lambda_min"],
+        "coarse_refactors": last["coarse_refactors"], "coarse_drop_tol_used": last["coarse_drop_tol_used"],
         "learned_candidates": last["learned_candidates"],
         "pcg_iterations": last["iterations"], "rel_residual": last["rel_residual"],
         "true_rel_residual": last["true_rel_residual"], "residual_floor": last["residual_floor"],
@@ -227,7 +232,7 @@ def main():
     variants = {"learned_fp32": (geneo.FP32_REFINE1, True), "fp64": (geneo.FP64, False)}
     run = [v for v in ("learned_fp32", "fp64") if a.variant in ("both", v)]
     model, training = None, None
-    corder = geneo.ORDER_NESTED_DISSECTION if a.coarse_order == "nd" else geneo.ORDER_NATURAL
+    corder = {"nd": geneo.ORDER_NESTED_DISSECTION, "natural": geneo.ORDER_NATURAL, "auto": geneo.ORDER_AUTO}[a.coarse_order]
     if "learned_fp32" in run and a.train_instances > 0:
         model, training = train_model(geneo, ctx, wid, a.train_instances)
     b_host = None

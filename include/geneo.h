@@ -152,8 +152,11 @@ typedef enum { GENEO_WEIGHT_IDENTITY = 0, GENEO_WEIGHT_POU = 1 } geneo_one_level
  * coarse space and its span do not depend on it; which columns the greedy
  * basis test leaves out may): subdomain groups (SNK columns, then GenEO
  * columns) in nested-dissection order of the subdomain coupling graph, or
- * all SNK columns subdomain by subdomain followed by all GenEO columns. */
-typedef enum { GENEO_ORDER_NATURAL = 0, GENEO_ORDER_NESTED_DISSECTION = 1 } geneo_coarse_order;
+ * all SNK columns subdomain by subdomain followed by all GenEO columns.
+ * AUTO (default): nested dissection when the dependency chain of the coarse
+ * triangular solves it predicts (from the subdomain adjacency) is at most
+ * 0.6 of the natural order's block-row count, else natural. */
+typedef enum { GENEO_ORDER_NATURAL = 0, GENEO_ORDER_NESTED_DISSECTION = 1, GENEO_ORDER_AUTO = 2 } geneo_coarse_order;
 
 typedef struct {
   double tau;               /* GenEO threshold, keep lambda > tau (Section 4, Numerical results: 10) */
@@ -171,7 +174,7 @@ typedef struct {
   const struct geneo_model* model; /* learned warm start of the eigensolver, or NULL (cold random start);
                                ignored when warm_start is given */
   int32_t keep_ritz;        /* 1: keep the final Ritz block for geneo_model_collect */
-  int32_t coarse_order;     /* geneo_coarse_order (default natural) */
+  int32_t coarse_order;     /* geneo_coarse_order (default AUTO) */
   int32_t one_level_weight; /* geneo_one_level_weight (default identity) */
   int32_t classical;        /* 1: GenEO vectors from the classical pencil D_j A_j D_j V = lambda A_j^Neu V
                                (Section 3.2, eq. (eigGenEOClassis): no projection out of span(G_j)), an
@@ -209,9 +212,16 @@ typedef struct {
   int32_t learned_candidates; /* subdomains for which the model proposed a start block (those that fit its
                                canvas); learned_starts of them were kept */
   int32_t coarse_nd_levels; /* depth of the nested dissection of the subdomain graph (0: natural order) */
+  int32_t coarse_nd_predicted_depth; /* AUTO: the solve depth predicted for the nested-dissection order */
   int32_t coarse_solve_depth; /* longest chain of dependent 128-row blocks in a coarse triangular solve */
   double t_factor_fp32_ms;  /* FP32_REFINE1: device time of the FP32 factorisation of all local matrices alone
                                (part of t_factor_ms, which also holds the check, the probe and any fallback) */
+  double coarse_lambda_min; /* estimate of the smallest eigenvalue of the factored coarse matrix (kept columns)
+                               scaled by its diagonal, diag(E)^-1/2 E diag(E)^-1/2 (power iteration on the
+                               factor's inverse); below 1e-12 the columns are eliminated again */
+  double coarse_drop_tol_used; /* drop tolerance of the final coarse factor: coarse_drop_tol times 10 per
+                                  re-elimination */
+  int32_t coarse_refactors; /* re-eliminations with a tenfold tolerance (0 .. 2) */
 } geneo_precond_info;
 
 void geneo_setup_opts_default(geneo_setup_opts* o);

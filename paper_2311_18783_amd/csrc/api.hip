@@ -204,6 +204,7 @@ void geneo_setup_opts_default(geneo_setup_opts* o) {
   o->fp32_rho_max = 0.5;
   o->model = nullptr;
   o->keep_ritz = 0;
+  o->coarse_order = GENEO_ORDER_AUTO;
 }
 
 int geneo_setup(geneo_ctx* ctx, const geneo_system* s, const geneo_decomp* d, const geneo_setup_opts* o,

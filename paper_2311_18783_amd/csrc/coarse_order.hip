@@ -176,7 +176,7 @@ std::vector<std::vector<int32_t>> nested_dissection(const std::vector<std::vecto
 }
 
 std::vector<std::vector<int32_t>> subdomain_elimination_order(const geneo_system* s, const geneo_decomp* dec,
-                                                              int* levels) {
+                                                              int* levels, std::vector<std::vector<int32_t>>* adj_out) {
   const int N = dec->N;
   std::vector<std::array<double, 3>> ctr(N, std::array<double, 3>{0.0, 0.0, 0.0});
   for (int i = 0; i < N; ++i) {
@@ -191,7 +191,51 @@ std::vector<std::vector<int32_t>> subdomain_elimination_order(const geneo_system
     const double w = e > b ? 1.0 / (2.0 * (double)(e - b)) : 0.0;
     for (int a = 0; a < 3; ++a) ctr[i][a] *= w;
   }
-  return nested_dissection(subdomain_graph(s, dec), ctr, 2, levels);
+  std::vector<std::vector<int32_t>> adj = subdomain_graph(s, dec);
+  auto groups = nested_dissection(adj, ctr, 2, levels);
+  if (adj_out) *adj_out = std::move(adj);
+  return groups;
+}
+
+// Longest chain of dependent 128-column block rows in the triangular solves
+// of E, predicted from the subdomains of its columns: pos_sub[p] = the
+// subdomain of the column at factor position p (-1: a pad).  Block rows I > J
+// couple if some column of I and some column of J belong to the same or to
+// adjacent subdomains (E's entries between other columns are zero); the
+// symbolic fill of that pattern gives the factor's block structure.
+int predicted_solve_depth(const std::vector<int32_t>& pos_sub, const std::vector<std::vector<int32_t>>& adj) {
+  const int64_t npos = (int64_t)pos_sub.size();
+  const int nb = (int)((npos + NB - 1) / NB);
+  const int N = (int)adj.size();
+  std::vector<std::vector<int32_t>> tile_sub(nb);
+  for (int64_t p = 0; p < npos; ++p) {
+    const int32_t i = pos_sub[p];
+    auto& t = tile_sub[p / NB];
+    if (i >= 0 && (t.empty() || t.back() != i)) t.push_back(i);
+  }
+  std::vector<uint8_t> pat((size_t)nb * nb, 0);
+  std::vector<int32_t> mark(N, -1);
+  for (int I = 0; I < nb; ++I) {
+    for (int32_t a : tile_sub[I]) {
+      mark[a] = I;
+      for (int32_t b : adj[a]) mark[b] = I;
+    }
+    for (int J = 0; J <= I; ++J)
+      for (int32_t b : tile_sub[J])
+        if (mark[b] == I) {
+          pat[(size_t)I * nb + J] = 1;
+          break;
+        }
+  }
+  symbolic_fill(nb, pat);
+  std::vector<int32_t> depth(nb, 1);
+  int dmax = nb ? 1 : 0;
+  for (int I = 0; I < nb; ++I) {
+    for (int J = 0; J < I; ++J)
+      if (pat[(size_t)I * nb + J]) depth[I] = std::max(depth[I], depth[J] + 1);
+    dmax = std::max(dmax, depth[I]);
+  }
+  return dmax;
 }
 
 }  // namespace geneo

@@ -91,7 +91,12 @@ void check_device_error(geneo_ctx* ctx);
 // nested-dissection order of the subdomains on their coupling graph: groups
 // (leaves and separators) in elimination order; *levels = dissection depth
 std::vector<std::vector<int32_t>> subdomain_elimination_order(const geneo_system* s, const geneo_decomp* dec,
-                                                              int* levels);
+                                                              int* levels,
+                                                              std::vector<std::vector<int32_t>>* adj_out = nullptr);
+// longest dependency chain of E's block triangular solves for the column
+// order pos_sub (subdomain of each factor position, -1 = pad), predicted from
+// the subdomain adjacency
+int predicted_solve_depth(const std::vector<int32_t>& pos_sub, const std::vector<std::vector<int32_t>>& adj);
 // eigensolver (geneo_eig.hip)
 void solve_local_gevps(geneo_ctx* ctx, geneo_precond* pc);
 

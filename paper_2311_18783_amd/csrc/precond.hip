@@ -889,6 +889,69 @@ static void build_nk_host(const geneo_system* s, SnkHost& h) {
     }
 }
 
+// Smallest eigenvalue, in the scaling of its diagonal, that the factored
+// coarse matrix may have before its dependent columns are eliminated again
+// with a larger tolerance: a kept block whose eigenvalue lies below this
+// is numerically singular in FP64 (the coarse solve amplifies the rounding
+// of its right-hand side by more than 1 / kCoarseLambdaFloor).
+constexpr double kCoarseLambdaFloor = 1e-20;
+
+// y = sqrt(d) .* x (entries with d <= 0: 0)
+__global__ void k_sqrt_scale(int64_t n, const double* __restrict__ d, const double* __restrict__ x,
+                             double* __restrict__ y) {
+  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i < n) y[i] = d[i] > 0.0 ? sqrt(d[i]) * x[i] : 0.0;
+}
+// x[i] = uniform(-1, 1) from a hash of i (start vector of the estimate)
+__global__ void k_hash_fill(int64_t n, uint64_t seed, double* __restrict__ x) {
+  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  uint64_t z = seed + 0x9E3779B97F4A7C15ull * (uint64_t)(i + 1);
+  z = (z ^ (z >> 30)) * 0xbf58476d1ce4e5b9ull;
+  z = (z ^ (z >> 27)) * 0x94d049bb133111ebull;
+  z ^= z >> 31;
+  x[i] = (double)(z >> 11) * 0x1p-52 - 1.0;
+}
+
+// Estimate of the smallest eigenvalue of S E_kept S (S = diag(E)^-1/2, E_kept:
+// the columns the factorisation kept; the others solve to 0): four steps of
+// power iteration on its inverse S^-1 E_kept^-1 S^-1, applied with the
+// factor's triangular solves; returns 1 / (the last Rayleigh quotient), an
+// upper bound of the smallest eigenvalue that is tight once the iteration
+// has settled on the inverse's dominant direction.
+__global__ void k_scale_dev(int64_t n, const double* __restrict__ ap, int inv, const double* __restrict__ x,
+                            double* __restrict__ out);
+
+static double coarse_lambda_min(geneo_ctx* ctx, const geneo_precond* pc, int64_t n0p) {
+  hipStream_t st = ctx->stream;
+  DevBuf<double> v, w, part, S;
+  v.alloc(n0p);
+  w.alloc(n0p);
+  part.alloc(kDotBlocks);
+  S.alloc(2);
+  double h[2] = {0.0, 0.0};
+  k_hash_fill<<<nblocks(n0p), 256, 0, st>>>(n0p, 0x2311ull, v.p);
+  dot(v.p, v.p, n0p, part.p, S.p + 1, st);
+  k_scale_dev<<<nblocks(n0p), 256, 0, st>>>(n0p, S.p + 1, 1, v.p, v.p);   // ||v|| = 1
+  double rq = 0.0;
+  for (int it = 0; it < 4; ++it) {
+    // w = S^-1 E^-1 S^-1 v with S^-1 = diag(E)^1/2
+    k_sqrt_scale<<<nblocks(n0p), 256, 0, st>>>(n0p, pc->d_odiag.p, v.p, w.p);
+    solve(pc->coarse, pc->dE.p, pc->dEinv.p, w.p, ctx->d_sync, ctx->d_err, st);
+    k_sqrt_scale<<<nblocks(n0p), 256, 0, st>>>(n0p, pc->d_odiag.p, w.p, w.p);
+    dot(v.p, w.p, n0p, part.p, S.p, st);
+    dot(w.p, w.p, n0p, part.p, S.p + 1, st);
+    HIP_CHECK(hipMemcpyAsync(h, S.p, 2 * sizeof(double), hipMemcpyDeviceToHost, st));
+    HIP_CHECK(hipStreamSynchronize(st));
+    rq = h[0];   // v^T (S^-1 E^-1 S^-1) v, ||v|| = 1
+    if (!std::isfinite(h[0]) || !std::isfinite(h[1]) || !(h[1] > 0.0)) return 0.0;
+    if (it == 3) break;
+    k_scale_dev<<<nblocks(n0p), 256, 0, st>>>(n0p, S.p + 1, 1, w.p, v.p);   // v = w / ||w||
+  }
+  check_device_error(ctx);
+  return rq > 0.0 ? 1.0 / rq : 0.0;
+}
+
 void setup_precond(geneo_ctx* ctx, geneo_precond* pc) {
   HostClock hc;
   hipStream_t st = ctx->stream;
@@ -1020,7 +1083,9 @@ void setup_precond(geneo_ctx* ctx, geneo_precond* pc) {
   std::thread snk_thread;
   std::vector<std::vector<int32_t>> sub_order;   // elimination order of the subdomain groups of coarse columns
   int nd_levels = 0;
-  if (pc->opts.coarse_order != GENEO_ORDER_NESTED_DISSECTION && pc->opts.coarse_order != GENEO_ORDER_NATURAL)
+  std::vector<std::vector<int32_t>> sub_adj;   // subdomain coupling graph (for the AUTO choice)
+  if (pc->opts.coarse_order != GENEO_ORDER_NESTED_DISSECTION && pc->opts.coarse_order != GENEO_ORDER_NATURAL &&
+      pc->opts.coarse_order != GENEO_ORDER_AUTO)
     throw Error(GENEO_EINVAL, "unknown coarse order");
   if (pc->opts.coarse != GENEO_COARSE_NONE)
     snk_thread = std::thread([&] {
@@ -1030,8 +1095,8 @@ void setup_precond(geneo_ctx* ctx, geneo_precond* pc) {
         else
           build_snk_host(s, dec, snk);
         // NK columns belong to no subdomain: natural order
-        if (pc->opts.coarse_order == GENEO_ORDER_NESTED_DISSECTION && !nk)
-          sub_order = subdomain_elimination_order(s, dec, &nd_levels);
+        if (pc->opts.coarse_order != GENEO_ORDER_NATURAL && !nk)
+          sub_order = subdomain_elimination_order(s, dec, &nd_levels, &sub_adj);
       } catch (...) {
         snk_err = std::current_exception();
       }
@@ -1173,10 +1238,28 @@ void setup_precond(geneo_ctx* ctx, geneo_precond* pc) {
   // groups that the dissection separates share no 128 x 128 tile
   std::vector<int32_t> pad_pos;
   int64_t n0_fac = pc->n0;          // order size with the pads
+  std::vector<int64_t> snk_beg(N + 1, 0);
   if (!sub_order.empty()) {
-    std::vector<int64_t> snk_beg(N + 1, 0);
     for (int32_t c = 0; c < pc->n_snk; ++c) snk_beg[col_sub[c] + 1]++;
     for (int32_t i = 0; i < N; ++i) snk_beg[i + 1] += snk_beg[i];
+  }
+  if (!sub_order.empty() && pc->opts.coarse_order == GENEO_ORDER_AUTO) {
+    // the dependency chain of the solves: the natural order's is its block-row
+    // count (every block row meets the previous one); nested dissection's is
+    // predicted from the subdomain adjacency.  Dissection is kept where it
+    // shortens the chain to 0.6 or less.
+    std::vector<int32_t> pos_sub;
+    pos_sub.reserve((size_t)pc->n0 + (size_t)NB * sub_order.size());
+    for (const auto& grp : sub_order) {
+      for (int32_t i : grp) pos_sub.insert(pos_sub.end(), (size_t)(snk_beg[i + 1] - snk_beg[i] + pc->gen_cnt[i]), i);
+      while (pos_sub.size() % NB) pos_sub.push_back(-1);
+    }
+    const int pred = predicted_solve_depth(pos_sub, sub_adj);
+    const int64_t natural_rows = (pc->n0 + NB - 1) / NB;
+    pc->info.coarse_nd_predicted_depth = pred;
+    if ((double)pred > 0.6 * (double)natural_rows) sub_order.clear();
+  }
+  if (!sub_order.empty()) {
     std::vector<int32_t> perm(pc->n0, -1);
     int64_t pos = 0;
     for (const auto& grp : sub_order) {
@@ -1212,6 +1295,7 @@ void setup_precond(geneo_ctx* ctx, geneo_precond* pc) {
     HIP_CHECK(hipMemsetAsync(pc->w_c3.p, 0, sizeof(double) * n0p, st));
   }
   HIP_CHECK(hipEventRecord(ctx->ev[0], st));
+  auto fill_E = [&] {
   k_fill_identity_pad<<<fill_grid(cd), 256, 0, st>>>(pc->coarse.d_desc.p, pc->dE.p, nullptr);
   if (!pad_pos.empty()) {   // pad columns between the groups of the order: unit diagonal
     DevBuf<int32_t> d_pad;
@@ -1256,6 +1340,8 @@ void setup_precond(geneo_ctx* ctx, geneo_precond* pc) {
     dim3 g(nblocks(n0p), 1);
     k_copy_diag<<<g, 256, 0, st>>>(pc->coarse.d_desc.p, pc->dE.p, pc->d_odiag.p);
   }
+  };
+  fill_E();
   // the coarse plan's diag_off is 0
   HIP_CHECK(hipEventRecord(ctx->ev[1], st));
   // block sparsity of E: only subdomains whose columns meet through A couple;
@@ -1292,12 +1378,32 @@ void setup_precond(geneo_ctx* ctx, geneo_precond* pc) {
     }
     pc->info.coarse_solve_depth = dmax;
   }
-  factor(pc->coarse, pc->dE.p, pc->dEinv.p, pc->d_odiag.p, pc->opts.coarse_drop_tol, pc->d_pivrel.p, ctx->d_err, st);
-  HIP_CHECK(hipEventRecord(ctx->ev[2], st));
-  hc.mark("coarse factor queued");
-  pc->info.t_coarse_build_ms = elapsed(ctx, 0, 1);
-  pc->info.t_coarse_factor_ms = elapsed(ctx, 1, 2);
-  check_device_error(ctx);
+  // Greedy elimination without pivoting is not rank revealing by itself: a
+  // run of kept columns, each with a relative Schur pivot just above the
+  // tolerance, can leave the kept block with an eigenvalue far below every
+  // pivot (the factor's inverse grows along the run), and the coarse solve
+  // then returns huge corrections.  The smallest eigenvalue of the kept block
+  // in the scaling of E's diagonal is estimated after the factorisation; if
+  // it is below kCoarseLambdaFloor the columns are eliminated again with a
+  // tenfold tolerance (at most twice).
+  double tol = pc->opts.coarse_drop_tol;
+  pc->info.coarse_refactors = 0;
+  for (int attempt = 0;; ++attempt) {
+    factor(pc->coarse, pc->dE.p, pc->dEinv.p, pc->d_odiag.p, tol, pc->d_pivrel.p, ctx->d_err, st);
+    if (attempt == 0) {
+      HIP_CHECK(hipEventRecord(ctx->ev[2], st));
+      hc.mark("coarse factor queued");
+      pc->info.t_coarse_build_ms = elapsed(ctx, 0, 1);
+      pc->info.t_coarse_factor_ms = elapsed(ctx, 1, 2);
+    }
+    check_device_error(ctx);
+    pc->info.coarse_lambda_min = coarse_lambda_min(ctx, pc, n0p);
+    if (tol <= 0.0 || pc->info.coarse_lambda_min >= kCoarseLambdaFloor || attempt == 2) break;
+    tol *= 10.0;
+    pc->info.coarse_refactors = attempt + 1;
+    fill_E();
+  }
+  pc->info.coarse_drop_tol_used = tol;
   std::vector<double> piv(n0p);
   HIP_CHECK(hipMemcpy(piv.data(), pc->d_pivrel.p, sizeof(double) * n0p, hipMemcpyDeviceToHost));
   std::vector<int32_t> hperm;
@@ -1309,7 +1415,7 @@ void setup_precond(geneo_ctx* ctx, geneo_precond* pc) {
   double mink = 1e300, maxd = 0.0;
   for (int64_t c0 = 0; c0 < n0; ++c0) {
     const int64_t c = cperm ? hperm[c0] : c0;   // pivots are in the factor's order
-    if (piv[c] > pc->opts.coarse_drop_tol) {
+    if (piv[c] > tol) {
       ++kept;
       mink = std::min(mink, piv[c]);
     } else {

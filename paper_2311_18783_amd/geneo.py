@@ -32,7 +32,7 @@ FP64, FP32_REFINE1 = 0, 1
 COARSE_SNK_GENEO, COARSE_SNK, COARSE_NONE, COARSE_NK, COARSE_NK_GENEO = 0, 1, 2, 3, 4
 WEIGHT_IDENTITY, WEIGHT_POU = 0, 1
 PCG, GMRES = 0, 1
-ORDER_NATURAL, ORDER_NESTED_DISSECTION = 0, 1
+ORDER_NATURAL, ORDER_NESTED_DISSECTION, ORDER_AUTO = 0, 1, 2
 PART_BOX, PART_RCB, PART_EXPLICIT = 0, 1, 2
 
 
@@ -87,7 +87,10 @@ class PrecondInfo(C.Structure):
                 ("learned_starts", C.c_int32), ("start_residual", C.c_double),
                 ("fp32_prechecked", C.c_int32), ("fp32_kappa_lb", C.c_double),
                 ("learned_candidates", C.c_int32), ("coarse_nd_levels", C.c_int32),
-                ("coarse_solve_depth", C.c_int32), ("t_factor_fp32_ms", C.c_double)]
+                ("coarse_nd_predicted_depth", C.c_int32),
+                ("coarse_solve_depth", C.c_int32), ("t_factor_fp32_ms", C.c_double),
+                ("coarse_lambda_min", C.c_double), ("coarse_drop_tol_used", C.c_double),
+                ("coarse_refactors", C.c_int32)]
 
 
 class ModelOpts(C.Structure):
