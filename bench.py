@@ -35,11 +35,14 @@ sys.path.insert(0, ROOT)
 METRIC = "setup+solve s to rtol 1e-8 & local-factor TFLOP/s; learned+FP32 vs plain FP64"
 PEAK_FP64_TFLOPS = 78.6     # MI355X dense FP64 matrix peak
 PEAK_FP32_TFLOPS = 157.3
+PEAK_HBM_GBS = 8000.0       # MI355X HBM3E
 # HBM bytes of one batched local factorisation per workload (plain FP64 path), from the
 # rocprofv3 FETCH_SIZE and WRITE_SIZE counters summed over its launches and scaled by what the
 # same counters read for a 1 GiB device copy (fetch x2.0, write x1.0); valid for the current
 # potrf/trsm/syrk/mirror kernels only (a workload without a measurement reports null)
 LOCAL_FACTOR_HBM_BYTES = {"cube24_channels": {"fetch": 193.9e9, "write": 57.2e9}}
+# HBM bytes per coarse triangular-solve launch (the same counters, copy-scaled); none taken yet
+COARSE_SOLVE_HBM_BYTES = {}
 
 
 def parse():
@@ -130,7 +133,8 @@ def run_step(geneo, ctx, w, precision, b_host=None, model=None, coarse_order=0):
                coarse_solve_depth=pi.coarse_solve_depth, learned_candidates=pi.learned_candidates,
                lobpcg_unconverged=pi.lobpcg_unconverged, t_factor_fp32_ms=pi.t_factor_fp32_ms,
                coarse_lambda_min=pi.coarse_lambda_min, coarse_refactors=pi.coarse_refactors,
-               coarse_drop_tol_used=pi.coarse_drop_tol_used, coarse_nd_predicted_depth=pi.coarse_nd_predicted_depth)
+               coarse_drop_tol_used=pi.coarse_drop_tol_used, coarse_nd_predicted_depth=pi.coarse_nd_predicted_depth,
+               coarse_solve_ms=si.coarse_solve_ms, coarse_solve_bytes=pi.coarse_solve_bytes)
     del pc, dec, sysm
     return out, b_host
 
@@ -190,6 +194,7 @@ def summarize(res):
         "coarse_solve_depth": last["coarse_solve_depth"], "lobpcg_unconverged": last["lobpcg_unconverged"],
         "coarse_nd_predicted_depth": last["coarse_nd_predicted_depth"], "coarse_lambda_min": last["coarse_lambda_min"],
         "coarse_refactors": last["coarse_refactors"], "coarse_drop_tol_used": last["coarse_drop_tol_used"],
+        "coarse_solve_ms": mean("coarse_solve_ms"), "coarse_solve_bytes": last["coarse_solve_bytes"],
         "learned_candidates": last["learned_candidates"],
         "pcg_iterations": last["iterations"], "rel_residual": last["rel_residual"],
         "true_rel_residual": last["true_rel_residual"], "residual_floor": last["residual_floor"],
@@ -254,14 +259,39 @@ def main():
     head = run[0]
     last = res[head][-1]
     plain = res["fp64"] if "fp64" in res else res[head]
-    # dominant kernel family: the batched FP64 Cholesky (potrf/trsm/syrk launches); reported
-    # on the local factorisation of all subdomain matrices (plain FP64 path: sum n_i^3 / 3
-    # flop over the HIP-event time of that factorisation), the coarse one beside it
+    # The two candidate dominant kernels, on the plain FP64 path: the batched local Cholesky
+    # (sum n_i^3 / 3 flop over the HIP-event time of the factorisation of all subdomain
+    # matrices) and the coarse triangular solves (k_trsv: every tile of the factor's pattern
+    # read once per sweep, over the HIP-event time of a solve in PCG's first application; two
+    # solves per application, one application per iteration plus the first).  "roofline" is
+    # the one with the larger device time per step; the coarse factorisation beside them.
     lf_ms = float(np.mean([r["t_factor_ms"] for r in plain]))
     achieved = plain[-1]["local_flops"] / (lf_ms * 1e-3) / 1e12
     cf_ms = float(np.mean([r["t_coarse_factor_ms"] for r in plain]))
     # flops of the coarse factorisation as performed: on the block-sparse fill pattern of E
     achieved_coarse = plain[-1]["coarse_flops"] / (cf_ms * 1e-3) / 1e12
+    cs_ms = float(np.mean([r["coarse_solve_ms"] for r in plain]))
+    cs_bytes = plain[-1]["coarse_solve_bytes"]
+    cs_step_ms = cs_ms * 2 * (plain[-1]["iterations"] + 1)
+    roof_local = {"bound": "mfma",
+                  "kernel": f"batched FP64 local Cholesky of the {last['n_sub']} subdomain matrices "
+                            "(potrf/trsm/syrk/mirror)",
+                  "achieved": achieved, "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
+                  "frac": achieved / PEAK_FP64_TFLOPS,
+                  "traffic": (sum(LOCAL_FACTOR_HBM_BYTES[w.name].values())
+                              if w.name in LOCAL_FACTOR_HBM_BYTES else None),
+                  "traffic_unit": "B per factorisation (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-scaled)",
+                  "ms_per_step": lf_ms}
+    cs_gbs = (cs_bytes / 2) / (cs_ms / 2 * 1e-3) / 1e9 if cs_ms > 0 else None
+    roof_solve = {"bound": "hbm",
+                  "kernel": "coarse block triangular solves (k_trsv, forward and backward sweeps over the "
+                            "factor's tiles)",
+                  "achieved": cs_gbs, "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                  "frac": cs_gbs / PEAK_HBM_GBS if cs_gbs else None,
+                  "bytes_per_launch": cs_bytes / 2, "ms_per_launch": cs_ms / 2,
+                  "traffic": COARSE_SOLVE_HBM_BYTES.get(w.name), "traffic_unit": "B per launch (copy-scaled)",
+                  "ms_per_step": cs_step_ms}
+    solve_dominant = cs_step_ms > lf_ms
     line = {
         "metric": METRIC,
         "value": summ[head]["setup_solve_s"],
@@ -282,14 +312,9 @@ def main():
                    "n0_rank": last["n0_rank"],
                    "n_geneo": last["n_geneo"], "parallelism": "1 GPU"},
         "variants": summ,
-        "roofline": {"bound": "mfma",
-                     "kernel": f"batched FP64 local Cholesky of the {last['n_sub']} subdomain matrices "
-                               "(potrf/trsm/syrk/mirror)",
-                     "achieved": achieved, "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
-                     "frac": achieved / PEAK_FP64_TFLOPS,
-                     "traffic": (sum(LOCAL_FACTOR_HBM_BYTES[w.name].values())
-                                 if w.name in LOCAL_FACTOR_HBM_BYTES else None),
-                     "traffic_unit": "B per factorisation (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-scaled)"},
+        "roofline": roof_solve if solve_dominant else roof_local,
+        ("roofline_local_factor" if solve_dominant else "roofline_coarse_solve"):
+            roof_local if solve_dominant else roof_solve,
         "roofline_coarse": {"bound": "mfma", "kernel": "block-sparse FP64 coarse Cholesky of E",
                             "achieved": achieved_coarse, "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
                             "frac": achieved_coarse / PEAK_FP64_TFLOPS},

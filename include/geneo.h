@@ -189,7 +189,7 @@ typedef struct {
   int32_t n_geneo;          /* GenEO columns */
   int32_t lobpcg_iters;     /* LOBPCG iterations (max over subdomains) */
   int32_t lobpcg_unconverged; /* subdomains whose selected Ritz pairs were not converged at exit */
-  int32_t fp64_fallbacks;   /* FP32 local factors replaced by FP64 */
+  int32_t fp64_fallbacks;   /* FP32 local factors replaced by FP64 (all of them when fewer than 1 in 8 would stay FP32) */
   double min_kept_pivot;    /* smallest relative Schur pivot kept in the coarse factor */
   double max_dropped_pivot; /* largest relative Schur pivot dropped */
   double t_extract_ms, t_factor_ms, t_gevp_ms, t_coarse_build_ms, t_coarse_factor_ms; /* device times */
@@ -222,6 +222,8 @@ typedef struct {
   double coarse_drop_tol_used; /* drop tolerance of the final coarse factor: coarse_drop_tol times 10 per
                                   re-elimination */
   int32_t coarse_refactors; /* re-eliminations with a tenfold tolerance (0 .. 2) */
+  double coarse_solve_bytes; /* algorithmic bytes of one coarse solve: every tile of the factor's pattern read
+                                once per sweep (forward and backward), 128 x 128 FP64 each */
 } geneo_precond_info;
 
 void geneo_setup_opts_default(geneo_setup_opts* o);
@@ -290,6 +292,8 @@ typedef struct {
   double residual_floor; /* PCG: (m + 1) u || |b| + |A| |x| || / ||b|| (m = longest row of A, u = 2^-53): the
                             bound on the rounding error of that computed true residual; a true residual at
                             or below it is as small as FP64 can certify */
+  double coarse_solve_ms; /* PCG: device time of one coarse solve (forward and backward sweeps), the mean of
+                             the two in the first preconditioner application (HIP events) */
 } geneo_solve_info;
 
 /* Solve A x = b (Section 1, the discrete system) from x0 = 0 with PCG

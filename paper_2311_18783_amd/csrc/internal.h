@@ -211,7 +211,9 @@ struct geneo_ctx {
   geneo::DevErr* d_err = nullptr;     // device error record
   geneo::DevErr* h_err = nullptr;     // pinned host mirror
   unsigned* d_sync = nullptr;         // [0] ticket counter, [1] epoch (sync-free solves)
-  hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
+  // 0-3: phase timers; 4-7: the first two coarse solves of a PCG run
+  hipEvent_t ev[8] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
+  int cs_timing = -1;   // >= 0: the next coarse solves record ev[4 + 2 cs_timing], ev[5 + 2 cs_timing]
 };
 
 struct geneo_system {

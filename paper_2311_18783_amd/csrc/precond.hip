@@ -607,6 +607,8 @@ __global__ __launch_bounds__(256) void k_fp32_check(const int32_t* __restrict__ 
 // radius per subdomain by power iteration on I - Ahat^-1 A_i (FP64 residual,
 // FP32 solve) and refactors in FP64 every subdomain whose estimate exceeds
 // fp32_rho_max or is not finite.
+constexpr int64_t kFp32MinShare = 8;   // FP32 factors are kept only on at least 1 / 8 of the subdomains
+
 static void fp32_probe(geneo_ctx* ctx, geneo_precond* pc, const std::vector<MatDesc>& descs,
                        const int32_t* d_failed, const double* d_kappa_lb) {
   constexpr int kPowerSteps = 8;
@@ -651,6 +653,13 @@ static void fp32_probe(geneo_ctx* ctx, geneo_precond* pc, const std::vector<MatD
     (rho <= pc->opts.fp32_rho_max ? d32 : d64).push_back(descs[i]);
   }
   pc->info.fp32_rho_est = rho_max;
+  // with fewer than 1 in 8 subdomains left on FP32 factors the mixed apply's
+  // fixed cost (the FP64 residual and the second solve pass over the whole
+  // batch) exceeds what the FP32 solves save: every subdomain goes to FP64
+  if (!d32.empty() && (int64_t)d32.size() * kFp32MinShare < N) {
+    d64 = descs;
+    d32.clear();
+  }
   pc->n_fallback = (int32_t)d64.size();
   pc->info.fp64_fallbacks = pc->n_fallback;
   if (d64.empty()) return;
@@ -1352,6 +1361,8 @@ void setup_precond(geneo_ctx* ctx, geneo_precond* pc) {
   }();
   const int nbc = (int)(n0p / NB);
   pc->info.coarse_factor_flops = (double)n0 * n0 * n0 / 3.0;
+  // a solve reads every factor tile once per sweep (the diagonal ones as their inverses)
+  pc->info.coarse_solve_bytes = 2.0 * ((double)nbc * (nbc + 1) / 2) * NB * NB * sizeof(double);
   if (coarse_sparse && nbc > 1) {
     DevBuf<uint8_t> d_pat;
     d_pat.alloc((size_t)nbc * nbc);
@@ -1369,6 +1380,7 @@ void setup_precond(geneo_ctx* ctx, geneo_precond* pc) {
     hc.mark("coarse plan");
     pc->info.coarse_factor_flops = pc->coarse.sparse_flops;
     pc->info.coarse_fill = (double)pc->coarse.fill_tiles / ((double)nbc * (nbc + 1) / 2);
+    pc->info.coarse_solve_bytes = 2.0 * (double)pc->coarse.fill_tiles * NB * NB * sizeof(double);
     std::vector<int32_t> depth(nbc, 1);
     int32_t dmax = nbc ? 1 : 0;
     for (int I = 0; I < nbc; ++I) {
@@ -1453,16 +1465,23 @@ static void coarse_solve(geneo_ctx* ctx, const geneo_precond* pc, double* c) {
   // left there by an earlier call (e.g. a non-finite input) reaches the solve
   const int64_t n0p = pc->coarse.h_desc[0].ld;
   hipStream_t st = ctx->stream;
+  // the triangular sweeps, timed by events when a PCG run asks for it
+  const int t = ctx->cs_timing >= 0 && ctx->cs_timing < 2 ? ctx->cs_timing++ : -1;
+  auto sweeps = [&](double* v) {
+    if (t >= 0) HIP_CHECK(hipEventRecord(ctx->ev[4 + 2 * t], st));
+    solve(pc->coarse, pc->dE.p, pc->dEinv.p, v, ctx->d_sync, ctx->d_err, st);
+    if (t >= 0) HIP_CHECK(hipEventRecord(ctx->ev[5 + 2 * t], st));
+  };
   if (pc->d_cperm.p) {   // the factor's order, pads between its groups
     double* v = pc->w_c3.p;
     k_fill<<<nblocks(n0p), 256, 0, st>>>(n0p, 0.0, v);
     k_permute<<<nblocks(pc->n0), 256, 0, st>>>(pc->n0, pc->d_cperm.p, 0, c, v);
-    solve(pc->coarse, pc->dE.p, pc->dEinv.p, v, ctx->d_sync, ctx->d_err, st);
+    sweeps(v);
     k_permute<<<nblocks(pc->n0), 256, 0, st>>>(pc->n0, pc->d_cperm.p, 1, c, v);
     return;
   }
   if (n0p > pc->n0) k_fill<<<nblocks(n0p - pc->n0), 256, 0, st>>>(n0p - pc->n0, 0.0, c + pc->n0);
-  solve(pc->coarse, pc->dE.p, pc->dEinv.p, c, ctx->d_sync, ctx->d_err, st);
+  sweeps(c);
 }
 
 // b <- A_i^-1 b on every segment; FP32 factors get one FP64 refinement step
@@ -1675,7 +1694,11 @@ void pcg(geneo_ctx* ctx, const geneo_system* sys, const geneo_precond* pc, const
       k_pcg_status<<<1, 1, 0, st>>>(ctx->d_err, S.p);
       HIP_CHECK(hipMemcpyAsync(h + 2, S.p + 2, 4 * sizeof(double), hipMemcpyDeviceToHost, st));
     };
+    // the first application runs eagerly: its two coarse solves are timed
+    ctx->cs_timing = pc && pc->n0 > 0 ? 0 : -1;
     tail(1);
+    const int cs_timed = ctx->cs_timing;
+    ctx->cs_timing = -1;
     bool fresh = true;    // the next head() follows an explicit tail (first step, or a restart)
     int replaced = 0;
     for (it = 1; it <= o->maxit; ++it) {
@@ -1697,6 +1720,12 @@ void pcg(geneo_ctx* ctx, const geneo_system* sys, const geneo_precond* pc, const
       }
       HIP_CHECK(hipGetLastError());
       HIP_CHECK(hipStreamSynchronize(st));
+      if (it == 1 && cs_timed == 2) {
+        float a = 0.f, b2 = 0.f;
+        HIP_CHECK(hipEventElapsedTime(&a, ctx->ev[4], ctx->ev[5]));
+        HIP_CHECK(hipEventElapsedTime(&b2, ctx->ev[6], ctx->ev[7]));
+        info->coarse_solve_ms = 0.5 * ((double)a + (double)b2);
+      }
       // a failed device-side wait (or any kernel error) stops the iteration
       // at once instead of iterating on invalid vectors
       if (h[5] != 0.0) break;
