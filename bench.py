@@ -124,6 +124,7 @@ def run_step(geneo, ctx, w, precision, b_host=None, model=None, coarse_order=0):
                n_snk=pi.n_snk, n_geneo=pi.n_geneo, lobpcg_iters=pi.lobpcg_iters,
                t_extract_ms=pi.t_extract_ms, t_factor_ms=pi.t_factor_ms, t_gevp_ms=pi.t_gevp_ms,
                t_coarse_build_ms=pi.t_coarse_build_ms, t_coarse_factor_ms=pi.t_coarse_factor_ms,
+               t_coarse_refactor_ms=pi.t_coarse_refactor_ms,
                solve_ms=si.solve_ms, local_flops=pi.local_factor_flops, assemble_ms=sysm.info().assemble_ms,
                fp64_fallbacks=pi.fp64_fallbacks, fp32_rho_est=pi.fp32_rho_est,
                fp32_prechecked=pi.fp32_prechecked, fp32_kappa_lb=pi.fp32_kappa_lb,
@@ -184,11 +185,14 @@ def summarize(res):
                       "setup": mean("setup_s") * 1e3, "solve": mean("solve_s") * 1e3,
                       "extract": mean("t_extract_ms"), "local_factor": mean("t_factor_ms"),
                       "gevp": mean("t_gevp_ms"), "coarse_build": mean("t_coarse_build_ms"),
-                      "coarse_factor": mean("t_coarse_factor_ms"), "pcg_device": mean("solve_ms")},
+                      "coarse_factor": mean("t_coarse_factor_ms"),
+                      "coarse_refactor": mean("t_coarse_refactor_ms"), "pcg_device": mean("solve_ms")},
         "local_factor_tflops": last["local_flops"] / (mean("t_factor_ms") * 1e-3) / 1e12,
         "fp32_factor_ms": mean("t_factor_fp32_ms"),
+        # FP32 factorisation rate: only when every subdomain went through it (none routed to FP64
+        # by the conditioning check before the FP32 factorisation)
         "fp32_factor_tflops": (last["local_flops"] / (mean("t_factor_fp32_ms") * 1e-3) / 1e12
-                               if mean("t_factor_fp32_ms") > 0 else None),
+                               if mean("t_factor_fp32_ms") > 0 and last["fp32_prechecked"] == 0 else None),
         "coarse_factor_tflops": last["coarse_flops"] / (mean("t_coarse_factor_ms") * 1e-3) / 1e12,
         "coarse_fill": last["coarse_fill"], "coarse_nd_levels": last["coarse_nd_levels"],
         "coarse_solve_depth": last["coarse_solve_depth"], "lobpcg_unconverged": last["lobpcg_unconverged"],

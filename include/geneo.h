@@ -221,7 +221,9 @@ typedef struct {
                                factor's inverse); below 1e-12 the columns are eliminated again */
   double coarse_drop_tol_used; /* drop tolerance of the final coarse factor: coarse_drop_tol times 10 per
                                   re-elimination */
-  int32_t coarse_refactors; /* re-eliminations with a tenfold tolerance (0 .. 2) */
+  int32_t coarse_refactors; /* re-eliminations with a tenfold tolerance (0 .. 4) */
+  double t_coarse_refactor_ms; /* device time from the end of the first coarse factorisation to the end of the
+                                  last (estimates, refills of E, re-eliminations; 0 without re-elimination) */
   double coarse_solve_bytes; /* algorithmic bytes of one coarse solve: every tile of the factor's pattern read
                                 once per sweep (forward and backward), 128 x 128 FP64 each */
 } geneo_precond_info;

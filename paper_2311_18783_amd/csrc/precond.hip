@@ -904,6 +904,7 @@ static void build_nk_host(const geneo_system* s, SnkHost& h) {
 // is numerically singular in FP64 (the coarse solve amplifies the rounding
 // of its right-hand side by more than 1 / kCoarseLambdaFloor).
 constexpr double kCoarseLambdaFloor = 1e-20;
+constexpr int kCoarseMaxRefactors = 4;
 
 // y = sqrt(d) .* x (entries with d <= 0: 0)
 __global__ void k_sqrt_scale(int64_t n, const double* __restrict__ d, const double* __restrict__ x,
@@ -1397,7 +1398,7 @@ void setup_precond(geneo_ctx* ctx, geneo_precond* pc) {
   // then returns huge corrections.  The smallest eigenvalue of the kept block
   // in the scaling of E's diagonal is estimated after the factorisation; if
   // it is below kCoarseLambdaFloor the columns are eliminated again with a
-  // tenfold tolerance (at most twice).
+  // tenfold tolerance (at most four times, up to 1e4 times the given one).
   double tol = pc->opts.coarse_drop_tol;
   pc->info.coarse_refactors = 0;
   for (int attempt = 0;; ++attempt) {
@@ -1410,10 +1411,15 @@ void setup_precond(geneo_ctx* ctx, geneo_precond* pc) {
     }
     check_device_error(ctx);
     pc->info.coarse_lambda_min = coarse_lambda_min(ctx, pc, n0p);
-    if (tol <= 0.0 || pc->info.coarse_lambda_min >= kCoarseLambdaFloor || attempt == 2) break;
+    if (tol <= 0.0 || pc->info.coarse_lambda_min >= kCoarseLambdaFloor || attempt == kCoarseMaxRefactors) break;
     tol *= 10.0;
     pc->info.coarse_refactors = attempt + 1;
     fill_E();
+  }
+  if (pc->info.coarse_refactors) {   // the estimate and the re-eliminations after the first factorisation
+    HIP_CHECK(hipEventRecord(ctx->ev[3], st));
+    HIP_CHECK(hipEventSynchronize(ctx->ev[3]));
+    pc->info.t_coarse_refactor_ms = elapsed(ctx, 2, 3);
   }
   pc->info.coarse_drop_tol_used = tol;
   std::vector<double> piv(n0p);

@@ -90,7 +90,8 @@ class PrecondInfo(C.Structure):
                 ("coarse_nd_predicted_depth", C.c_int32),
                 ("coarse_solve_depth", C.c_int32), ("t_factor_fp32_ms", C.c_double),
                 ("coarse_lambda_min", C.c_double), ("coarse_drop_tol_used", C.c_double),
-                ("coarse_refactors", C.c_int32), ("coarse_solve_bytes", C.c_double)]
+                ("coarse_refactors", C.c_int32), ("t_coarse_refactor_ms", C.c_double),
+                ("coarse_solve_bytes", C.c_double)]
 
 
 class ModelOpts(C.Structure):
