@@ -140,24 +140,35 @@ def run_step(geneo, ctx, w, precision, b_host=None, model=None, coarse_order=0):
     return out, b_host
 
 
-def cpu_baseline(w):
+def cpu_baseline(w, budget_s=10.0, max_sample=32):
     """The oracle, as written, on a bounded sample of the same workload: the
-    dense local Cholesky and the dense filtered GEVP (scipy eigh) of the
-    smallest subdomain and one of median size, scaled by sum n_i^3 to all
-    subdomains (the oracle's dense local work grows as n_i^3).  The coarse
+    dense local Cholesky and the dense filtered GEVP (scipy eigh) of
+    subdomains taken at evenly spaced quantiles of the subdomain sizes
+    (smallest, largest, then the quantiles in between, bisected) until about
+    `budget_s` seconds of oracle work, scaled by sum n_i^3 to all subdomains
+    (the oracle's dense local work grows as n_i^3).  The coarse
     factorisation and the Krylov iteration are not in the sample: the
-    oracle's coarse matrix (n0 ~ 1e5) and a sparse direct solve of the whole
-    system (223 s for the beam on 8 cores, SuperLU) exceed a bounded run."""
+    oracle's coarse matrix (n0 ~ 1e5, dense) and a sparse direct solve of the
+    whole system (223 s for the beam on 8 cores, SuperLU) exceed a bounded run."""
     from threadpoolctl import threadpool_info
     from oracle import decomp, fem, geneo
     import scipy.linalg as sla
     s = fem.System(w.mesh, w.mu, w.eps, w.gamma, w.dirichlet)
     dec = decomp.Decomposition(s, decomp.partition_cells(w), w.overlap)
     sizes = np.array([d.size for d in dec.dofs], dtype=np.float64)
-    order = np.argsort(sizes)
-    sample = [int(order[0]), int(order[len(order) // 2])]
-    t = 0.0
-    for i in sample:
+    order = np.argsort(sizes, kind="stable")
+    # quantile positions in bisection order: 0, 1, 1/2, 1/4, 3/4, 1/8, ...
+    fr, k = [0.0, 1.0], 2
+    while len(fr) < dec.N:
+        fr += [(2 * j + 1) / k for j in range(k // 2)]
+        k *= 2
+    picks = []
+    for f in fr:
+        i = int(order[int(round(f * (dec.N - 1)))])
+        if i not in picks:
+            picks.append(i)
+    t, sample = 0.0, []
+    for i in picks[:max_sample]:
         Ai = dec.A_dir(i).toarray()
         Neu = dec.A_neu(i).toarray()
         Gi, _, _ = dec.G_local(i)
@@ -165,12 +176,16 @@ def cpu_baseline(w):
         sla.cholesky(Ai, lower=True)
         geneo.gevp(Ai, Neu, dec.D[i], Gi, w.tau, w.nev_max)
         t += time.perf_counter() - t0
+        sample.append(i)
+        if t >= budget_s:
+            break
     scale = float((sizes ** 3).sum() / (sizes[sample] ** 3).sum())
     threads = max([p.get("num_threads", 1) for p in threadpool_info()] + [1])
     return {"value": t * scale, "unit": "s", "cores": int(threads), "kind": "oracle",
-            "sample": (f"dense local Cholesky + dense filtered GEVP (scipy eigh) of subdomains {sample} "
-                       f"(n_i = {int(sizes[sample[0]])}, {int(sizes[sample[1]])}) took {t:.1f} s, scaled by "
-                       f"sum n_i^3 to all {dec.N} subdomains; coarse factor and Krylov iteration excluded")}
+            "sample": (f"dense local Cholesky + dense filtered GEVP (scipy eigh) of {len(sample)} subdomains at "
+                       f"size quantiles (n_i {int(sizes[sample].min())} .. {int(sizes[sample].max())}) took "
+                       f"{t:.1f} s, scaled by sum n_i^3 to all {dec.N} subdomains; coarse factor and Krylov "
+                       "iteration excluded")}
 
 
 def summarize(res):
