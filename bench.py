@@ -59,6 +59,18 @@ def parse():
     ap.add_argument("--coarse-order", default="auto", choices=["auto", "natural", "nd"],
                     help="elimination order of the coarse columns (nd: nested dissection of the subdomain graph; "
                          "auto: nested dissection where it shortens the coarse solves' dependency chain)")
+    ap.add_argument("--paper-table", default=None, choices=["gamma", "eps", "mu"],
+                    help="instead of the benchmark: the paper's beam sweeps (Section 4, Numerical results: the "
+                         "gamma sweep, alternating eps layers, alternating mu layers), one JSON line per case")
+    ap.add_argument("--table-n", default="8,16", help="subdomain counts N of the paper-table beams")
+    ap.add_argument("--table-cells", type=int, default=16, help="cells per unit length (the paper: 16)")
+    ap.add_argument("--table-coarse", default="snk_geneo,snk",
+                    help="coarse spaces of the paper-table runs (snk_geneo, snk, none, nk, nk_geneo)")
+    ap.add_argument("--learned-study", default=None, metavar="TRAIN,HOLDOUT",
+                    help="instead of the benchmark: train the warm-start model on TRAIN instances of workload 4 "
+                         "(12^3-cell subdomains with random inclusions, gamma in [1e-6, 1]) and compare cold and "
+                         "learned setups on HOLDOUT further instances; one JSON line")
+    ap.add_argument("--study-epochs", type=int, default=30, help="training epochs of --learned-study")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
                     help="only run one device copy of BYTES (counter calibration) and exit")
     return ap.parse_args()
@@ -238,10 +250,108 @@ def copy_calibration(nbytes):
     print(json.dumps({"copy_bytes": a.numel() * 8}), flush=True)
 
 
+def paper_tables(a):
+    """The paper's beam sweeps on the GPU: for each case, AS with the chosen
+    coarse spaces, right-preconditioned GMRES to 1e-6 (the paper's solver and
+    tolerance) and PCG to 1e-8; one JSON line per (case, coarse space) with
+    the iteration counts and the coarse space sizes."""
+    import torch
+    from paper_2311_18783_amd import geneo
+    import workloads as W
+    kinds = {"snk_geneo": geneo.COARSE_SNK_GENEO, "snk": geneo.COARSE_SNK, "none": geneo.COARSE_NONE,
+             "nk": geneo.COARSE_NK, "nk_geneo": geneo.COARSE_NK_GENEO}
+    if a.paper_table == "gamma":
+        cases = [dict(gamma=g, bc="all") for g in (1e-5, 1e-4, 1e-3, 1e-2, 1e-1, 1.0, 10.0, 100.0)]
+    else:
+        cases = [dict(gamma=1e-3, bc=bc, layers=a.paper_table, alt=v)
+                 for bc in ("all", "mixed") for v in (1e-4, 1e-3, 1e-2, 1e-1, 1.0, 10.0, 1e2, 1e3, 1e4)]
+    ctx = geneo.Context(0)
+    for N in [int(x) for x in a.table_n.split(",")]:
+        for c in cases:
+            w = W.paper_beam(N, cells=a.table_cells, **c)
+            sysm = ctx.assemble(w.mesh, w.mu, w.eps, w.gamma, w.dirichlet)
+            dec = ctx.partition(sysm, "box", box=w.partition["p"], overlap=w.overlap)
+            n = sysm.info().n
+            b = torch.as_tensor(w.rhs(n), device="cuda:0")
+            for kname in a.table_coarse.split(","):
+                pc = ctx.setup(sysm, dec, tau=w.tau, nev_max=w.nev_max, coarse=kinds[kname])
+                pi = pc.info()
+                row = {"table": a.paper_table, "N": N, "cells": a.table_cells, **c, "coarse": kname, "n": n,
+                       "n_snk": pi.n_snk, "n_geneo": pi.n_geneo, "n0_rank": pi.n0_rank,
+                       "lobpcg_unconverged": pi.lobpcg_unconverged}
+                for meth, rtol, key in ((geneo.GMRES, 1e-6, "gmres_1e-6"), (geneo.PCG, 1e-8, "pcg_1e-8")):
+                    x = torch.zeros(n, dtype=torch.float64, device="cuda:0")
+                    si = ctx.solve(sysm, pc, b, x, rtol=rtol, maxit=500, method=meth, allow_noconv=True)
+                    row[key] = si.iterations if si.rel_residual <= rtol else None
+                print(json.dumps(row), flush=True)
+                del pc
+            del dec, sysm
+    ctx.close()
+
+
+def learned_study(a):
+    """Learned warm start on workload 4: the model is trained on GEVP solutions
+    of TRAIN instances (the cold eigensolver's Ritz vectors), its loss checked
+    on HOLDOUT other instances, and the eigensolver run on those HOLDOUT
+    instances from the cold start and from the judged learned start."""
+    from paper_2311_18783_amd import geneo
+    import workloads as W
+    n_train, n_hold = (int(x) for x in a.learned_study.split(","))
+    ctx = geneo.Context(0)
+    m = ctx.model_create(canvas=12, hidden=256, k=20, seed=2311)
+    t0 = time.perf_counter()
+    for f in range(1, n_train + n_hold + 1):
+        w = W.make(4, family=f)
+        sysm = ctx.assemble(w.mesh, w.mu, w.eps, w.gamma, w.dirichlet)
+        dec = partition(ctx, sysm, w)
+        pc = ctx.setup(sysm, dec, tau=w.tau, nev_max=w.nev_max, keep_ritz=1)
+        m.collect(sysm, dec, pc, holdout=f > n_train)
+        del pc, dec, sysm
+        if f % 25 == 0:
+            print(f"[learned-study] collected {f} instances, {time.perf_counter() - t0:.0f} s", file=sys.stderr,
+                  flush=True)
+    t1 = time.perf_counter()
+    ti = m.train(epochs=a.study_epochs, batch=32, lr=1e-3, seed=0)
+    inf = m.info()
+    rows = []
+    for f in range(n_train + 1, n_train + n_hold + 1):
+        w = W.make(4, family=f)
+        sysm = ctx.assemble(w.mesh, w.mu, w.eps, w.gamma, w.dirichlet)
+        dec = partition(ctx, sysm, w)
+        r = {"gamma": w.gamma}
+        for tag, kw in (("cold", {}), ("learned", {"model": m})):
+            pc = ctx.setup(sysm, dec, tau=w.tau, nev_max=w.nev_max, **kw)
+            pi = pc.info()
+            r[tag] = {"lobpcg_iterations": pi.lobpcg_iters, "gevp_ms": pi.t_gevp_ms,
+                      "unconverged": pi.lobpcg_unconverged, "n_geneo": pi.n_geneo,
+                      "learned_starts": pi.learned_starts, "start_residual": pi.start_residual}
+            del pc
+        rows.append(r)
+        del dec, sysm
+    mean = lambda tag, k: float(np.mean([r[tag][k] for r in rows]))
+    line = {"study": "learned warm start, workload 4", "train_instances": n_train, "holdout_instances": n_hold,
+            "samples_train": inf.n_train, "samples_holdout": inf.n_holdout, "params": inf.n_params,
+            "data_s": t1 - t0, "train_ms": ti.train_ms, "epochs": a.study_epochs,
+            "loss_first_epoch": ti.loss_first, "loss_last_epoch": ti.loss_last, "holdout_loss": ti.holdout_loss,
+            "loss_of_a_zero_prediction": 20,
+            "cold": {k: mean("cold", k) for k in ("lobpcg_iterations", "gevp_ms", "start_residual")},
+            "learned": {k: mean("learned", k) for k in ("lobpcg_iterations", "gevp_ms", "start_residual",
+                                                          "learned_starts")},
+            "per_instance": rows}
+    print(json.dumps(line), flush=True)
+    ctx.close()
+
+
 def main():
     a = parse()
+    if a.learned_study:
+        learned_study(a)
+        return
     if a.copy_calibration:
         copy_calibration(a.copy_calibration)
+        return
+    if a.paper_table:
+        paper_tables(a)
         return
     if a.gpus != 1:
         print(json.dumps({"error": "single-GPU benchmark: the batched per-subdomain work runs on one GPU; "

@@ -323,3 +323,38 @@ def test_restricted_weights(tiny):
     x, it, hist = geneo.gmres(s.A, b, M=two.apply, rtol=1e-10)
     assert hist[-1] <= 1e-10 and it < n
     assert np.linalg.norm(x - xs) <= 1e-7 * np.linalg.norm(xs)
+
+
+def test_mixed_beam_geneo_columns_are_the_relative_harmonic_field():
+    """The paper's beam with Neumann conditions on the lateral faces -y/+y
+    (Section 4, Numerical results; here N = 4 strips at h = 1/8): an
+    interior strip's Dirichlet boundary (faces z = 0 and z = 1) has two
+    components, so grad z is curl-free, satisfies the strip's boundary
+    conditions and is no gradient of a free nodal function (z is 1 on the
+    Dirichlet face z = 1).  Its B-orthogonal part off span(G_i), h, has
+    B h = gamma M h but D_i breaks its curl-freeness under Atilde: the
+    filtered GEVP (eq. (eigAtildeBAS)) has exactly one eigenvalue above tau
+    there, of order 1 / gamma, whose eigenvector is h (B-cosine 1 - 1e-5).
+    The end strips (Dirichlet face x = 0 or x = L: grad z is not admissible)
+    and every strip of the all-Dirichlet beam select nothing.  This is the
+    N - 2 GenEO columns of the mixed beam."""
+    for bc, expect in (("mixed", [0, 1, 1, 0]), ("all", [0, 0, 0, 0])):
+        w = W.paper_beam(4, bc=bc, cells=8)
+        s = fem.System(w.mesh, w.mu, w.eps, w.gamma, w.dirichlet)
+        dec = decomp.Decomposition(s, decomp.partition_cells(w), w.overlap)
+        assert dec.N == 4
+        for i in range(4):
+            Gi, _, _ = dec.G_local(i)
+            A, B, D = dec.A_dir(i).toarray(), dec.A_neu(i).toarray(), dec.D[i]
+            lam, V, sel = geneo.gevp(A, B, D, Gi, w.tau, w.nev_max)
+            assert sel == expect[i], (bc, i, sel, lam[:3])
+            if sel:
+                assert lam[0] > 0.1 / w.gamma and lam[1] < w.tau
+                ab = s.edges[s.free_edges[dec.dofs[i]]]
+                z = s.mesh["xyz"][:, 2]
+                t = z[ab[:, 1]] - z[ab[:, 0]]          # edge dofs of grad z
+                Gd = Gi.toarray()
+                h = t - Gd @ np.linalg.solve(Gd.T @ B @ Gd, Gd.T @ (B @ t))
+                v = V[:, 0]
+                cos = abs(v @ B @ h) / np.sqrt((v @ B @ v) * (h @ B @ h))
+                assert cos > 1 - 1e-4, cos

@@ -203,6 +203,36 @@ class Workload:
         return np.random.default_rng(ss[3])
 
 
+def paper_beam(N, gamma=1e-3, bc="all", layers=None, alt=1.0, cells=16):
+    """The paper's beam (Section 4, Numerical results): N/2 x 1 x 1 with
+    h = 1 / cells (the paper: 16), i.e. (cells N / 2) x cells x cells hexes,
+    N strip subdomains along its length, one overlap layer, tau = 10.
+    bc: "all" (Dirichlet on every face) or "mixed" (Neumann on the two
+    opposing lateral faces -y / +y).  layers: None (mu = eps = 1), "eps" or
+    "mu": eight alternating layers along the length, the coefficient 1 in
+    the first and `alt` in the second (Tables 7 and 8 of the paper's
+    heterogeneity study); gamma as in its gamma sweep (Table 5)."""
+    X = cells * N // 2
+    if X % 8 and layers:
+        raise ValueError("eight layers need a length divisible by 8 cells")
+    dims = (X, cells, cells)
+    mesh = hex_box_mesh(dims, h=1.0 / cells)
+    T = mesh["tets"].shape[0]
+    mu, eps = np.ones(T), np.ones(T)
+    if layers == "mu":
+        mu = per_hex(slab_mu(dims, nslab=8, lo=1.0, hi=alt), mesh)
+    elif layers == "eps":
+        eps = per_hex(slab_mu(dims, nslab=8, lo=1.0, hi=alt), mesh)
+    elif layers is not None:
+        raise ValueError(f"unknown layers {layers!r}")
+    name = f"paper_beam{N}_h{cells}_{bc}" + (f"_{layers}{alt:g}" if layers else "") + f"_g{gamma:g}"
+    desc = (f"beam {X}x{cells}x{cells} hexes x 6 tets, h = 1/{cells}, {N} strips, overlap 1, gamma = {gamma:g}, "
+            + ("all-Dirichlet" if bc == "all" else "Neumann on -y/+y, Dirichlet elsewhere")
+            + (f", {layers} alternating 1 / {alt:g} in 8 layers" if layers else ", mu = eps = 1"))
+    return Workload(name, mesh, mu, eps, float(gamma), dirichlet_flags(mesh["bface_tag"], bc),
+                    {"kind": "box", "p": (N, 1, 1)}, 1, seed=4000 + N, describe=desc)
+
+
 def rcb_jitter(nparts, rng, spread=0.3):
     """Per-split size jitter for recursive coordinate bisection, one value per
     internal node of the bisection tree in preorder (nparts-1 values).  The
@@ -213,12 +243,13 @@ def rcb_jitter(nparts, rng, spread=0.3):
 
 
 def make(cfg, family=0, **over):
-    """Build workload `cfg` (1, 2, 3, 5, or a small named test case).
+    """Build workload `cfg` (1 - 5, or a small named test case).
 
     family > 0: another instance of the same recipe, its random draws taken
     from the streams SeedSequence([seed, family]) instead of SeedSequence(seed):
     new channels (config 2, "small_channels"), new lognormal fields and
-    bisection jitter (config 3), new bisection jitter (config 5, whose slab
+    bisection jitter (config 3), new inclusions and gamma (config 4), new
+    bisection jitter (config 5, whose slab
     coefficients are fixed, so the subdomains change shape and position).
     Used to train the learned warm start on instances disjoint from the
     measured one (family 0)."""
@@ -263,6 +294,27 @@ def make(cfg, family=0, **over):
                      describe="32^3 hexes minus a central 8x8x32 through-hole (184,320 tets), lognormal "
                               "mu, eps (sigma 2), gamma = 1e-3, Dirichlet outside / Neumann on the hole, "
                               "RCB 125 parts (+-30% jitter), overlap 1")
+    elif cfg == 4:
+        # Training instances of the learned warm start: subdomains of 12^3 cells (11^3-hex boxes
+        # plus one overlap layer) of a 22^3 cube, mu = 10^U(0, 5) on 4..8 seeded random box
+        # inclusions of 2..6 cells per side (1 elsewhere), eps = 1, gamma = 10^U(-6, 0).
+        dims = (22, 22, 22)
+        mesh = hex_box_mesh(dims)
+        ss = stream(1004)
+        r = np.random.default_rng(ss[0])
+        mu3 = np.ones(dims)
+        for _ in range(int(r.integers(4, 9))):
+            size = r.integers(2, 7, size=3)
+            lo = [int(r.integers(0, dims[a] - size[a] + 1)) for a in range(3)]
+            mu3[lo[0]:lo[0] + size[0], lo[1]:lo[1] + size[1], lo[2]:lo[2] + size[2]] = 10.0 ** r.uniform(0, 5)
+        gamma = 10.0 ** r.uniform(-6, 0)
+        T = mesh["tets"].shape[0]
+        w = Workload("cube22_inclusions", mesh, per_hex(mu3, mesh), np.ones(T), gamma,
+                     dirichlet_flags(mesh["bface_tag"], "all"),
+                     {"kind": "box", "p": (2, 2, 2)}, 1, seed=1004,
+                     describe=f"22^3 hexes x 6 tets (63,888), mu = 10^U(0,5) on 4-8 random box inclusions, eps = 1, "
+                              f"gamma = {gamma:.3g} (10^U(-6,0)), all-Dirichlet, 2x2x2 boxes (12^3 cells with "
+                              "the overlap layer), overlap 1")
     elif cfg == 5:
         dims = (128, 16, 16)
         mesh = hex_box_mesh(dims, h=1.0 / 16)
@@ -347,7 +399,7 @@ def make(cfg, family=0, **over):
     else:
         raise ValueError(f"unknown workload {cfg!r}")
     if family:
-        if cfg not in (2, 3, 5, "small_channels"):
+        if cfg not in (2, 3, 4, 5, "small_channels"):
             raise ValueError(f"no instance family for workload {cfg!r}")
         w.name = f"{w.name}#{family}"
     for k, v in over.items():
