@@ -879,6 +879,49 @@ __global__ void k_fold(int64_t n, double* __restrict__ S, const double* __restri
   if (i < n) S[i] += Slo[i];
 }
 
+// C_j = A_j G_j, one thread per batch row (edge r of subdomain j): entry e of
+// the row (node c_node[e]) sums +-A_j(r, c) over the columns c of the row
+// with that node as their end (-: first, +: second), compensated (running
+// sum in C, rounding errors in Clo; the row's entries belong to the thread).
+// For a node whose whole star is in the row's pattern the sum cancels down
+// to gamma (M G)(r, node); here it is formed once, from the matrix values,
+// instead of cancelling again in every G^T A X and A G c of the eigensolver.
+__global__ void k_c_vals(int64_t len, const int32_t* __restrict__ row_sub, const int64_t* __restrict__ voff,
+                         const int32_t* __restrict__ nloc, const int64_t* __restrict__ rp_off,
+                         const int32_t* __restrict__ lrp, const int32_t* __restrict__ lcol,
+                         const double* __restrict__ aval, const int32_t* __restrict__ ena,
+                         const int32_t* __restrict__ enb, const int64_t* __restrict__ c_rp,
+                         const int32_t* __restrict__ c_node, double* __restrict__ C, double* __restrict__ Clo) {
+  const int64_t b = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (b >= len) return;
+  const int j = row_sub[b];
+  const int64_t vj = voff[j], r = b - vj;
+  const int64_t e0 = c_rp[b], e1 = c_rp[b + 1];
+  for (int64_t e = e0; e < e1; ++e) {
+    C[e] = 0.0;
+    Clo[e] = 0.0;
+  }
+  if (r >= nloc[j]) return;
+  const int32_t* rp = lrp + rp_off[j];
+  for (int32_t t = rp[r]; t < rp[r + 1]; ++t) {
+    const double v = aval[t];
+    const int64_t cb = vj + lcol[t];
+    const int32_t nd[2] = {ena[cb], enb[cb]};
+    for (int q = 0; q < 2; ++q) {
+      if (nd[q] < 0) continue;
+      int64_t e = e0;
+      while (e < e1 && c_node[e] != nd[q]) ++e;
+      if (e == e1) continue;   // unreachable: the pattern holds every end node of the row's columns
+      double hi, lo;
+      two_sum(C[e], q ? v : -v, hi, lo);
+      C[e] = hi;
+      Clo[e] += lo;
+    }
+  }
+  for (int64_t e = e0; e < e1; ++e) C[e] += Clo[e];
+}
+
+
 __global__ void k_dense_scatter_vals(int64_t nnz, const int32_t* __restrict__ lrow, const int32_t* __restrict__ lcol,
                                      const int64_t* __restrict__ nnz_off, int nmat, const MatDesc* __restrict__ desc,
                                      const double* __restrict__ vals, double* __restrict__ A) {
@@ -919,6 +962,13 @@ struct EigWork {
   FactorPlan node;
   DevBuf<unsigned> flags_node, flags_local;
   DevBuf<double> xrow;   // row-major copy of a block for the sparse products [len x 32] (gather path)
+  // C_j = A_j G_j by edge rows (c_*) and by node rows (ct_*)
+  DevBuf<int64_t> c_rp, ct_rp;
+  DevBuf<int32_t> c_node, ct_row, ct_src;
+  DevBuf<double> c_val, ct_val;
+  DevBuf<double> nrow;   // row-major copy of a node block [plen x 32]
+  std::vector<int64_t> h_c_rp, h_ct_rp;
+  std::vector<int32_t> h_c_node, h_ct_row, h_ct_src;
   DevBuf<int32_t> lt_blk;   // (subdomain, 128-row block) pairs of the L^T X products
   int64_t nlt = 0;
   int64_t nchunks = 0;
@@ -1049,6 +1099,83 @@ __global__ __launch_bounds__(256) void k_spmm_rm(int64_t len, int k, const int32
   }
 }
 
+// Products with C_j = A_j G_j, lane q on column q of a row-major block
+// (pitch 32): NODE_ROWS: Y = C_j^T X, rows are the node rows of the node
+// block (node_sub / poff, p_j live rows), the row's entries index edge rows
+// of Xt (at voff); else Y = base - C_j N, rows are the edge rows of the edge
+// block (row_sub / voff, n_j live rows), entries index node rows of Nt (at
+// poff).  Workgroup = 64 rows, one per half-wave at a time; results staged
+// through LDS and written in column runs, as in k_spmm_rm.
+template <bool NODE_ROWS>
+__global__ __launch_bounds__(256) void k_csr_rm(int64_t nrows, int k, const int32_t* __restrict__ rsub,
+                                                const int64_t* __restrict__ roff, const int32_t* __restrict__ rlive,
+                                                const int64_t* __restrict__ xoff, const int64_t* __restrict__ rp,
+                                                const int32_t* __restrict__ cidx, const double* __restrict__ vals,
+                                                const double* __restrict__ Xt, const double* __restrict__ base,
+                                                double* __restrict__ Y) {
+  __shared__ double tile[64][33];
+  __shared__ int64_t s_o[64], s_ld[64], s_x[64], s_t0[64];
+  __shared__ int32_t s_nnz[64];
+  const int64_t b0 = (int64_t)xcd_block() * 64;
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const int q = lane & 31, hw = lane >> 5;
+  if (tid < 64) {
+    const int64_t b = b0 + tid;
+    int64_t o = -1, ldj = 0, xo = 0, t0 = 0;
+    int32_t nnz = 0;
+    if (b < nrows) {
+      const int j = rsub[b];
+      const int64_t rj = roff[j], r = b - rj;
+      o = rj * k + r;
+      ldj = roff[j + 1] - rj;
+      xo = xoff[j] * 32;
+      if (r < rlive[j]) {
+        t0 = rp[b];
+        nnz = (int32_t)(rp[b + 1] - t0);
+      }
+    }
+    s_o[tid] = o;
+    s_ld[tid] = ldj;
+    s_x[tid] = xo;
+    s_t0[tid] = t0;
+    s_nnz[tid] = nnz;
+  }
+  __syncthreads();
+  for (int i = 0; i < 8; ++i) {
+    const int rl = 16 * w + 2 * i + hw;
+    const int64_t t0 = s_t0[rl];
+    const int32_t nnz = s_nnz[rl];
+    const double* xb = Xt + s_x[rl] + q;
+    double acc = 0.0, a1 = 0.0;
+    for (int cb = 0; cb < nnz; cb += 32) {
+      int my_c = 0;
+      double my_v = 0.0;
+      if (cb + q < nnz) {
+        my_c = cidx[t0 + cb + q];
+        my_v = vals[t0 + cb + q];
+      }
+      const int n = min(32, nnz - cb);
+      int t = 0;
+      for (; t + 1 < n; t += 2) {
+        const int c0 = __shfl(my_c, t, 32), c1 = __shfl(my_c, t + 1, 32);
+        const double v0 = __shfl(my_v, t, 32), v1 = __shfl(my_v, t + 1, 32);
+        acc += v0 * xb[(int64_t)c0 * 32];
+        a1 += v1 * xb[(int64_t)c1 * 32];
+      }
+      if (t < n) acc += __shfl(my_v, t, 32) * xb[(int64_t)__shfl(my_c, t, 32) * 32];
+    }
+    tile[rl][q] = acc + a1;
+  }
+  __syncthreads();
+  for (int e = tid; e < 64 * k; e += 256) {
+    const int rl = e & 63, qq = e >> 6;
+    const int64_t o = s_o[rl];
+    if (o < 0) continue;
+    const int64_t oq = o + (int64_t)qq * s_ld[rl];
+    Y[oq] = NODE_ROWS ? tile[rl][qq] : base[oq] - tile[rl][qq];
+  }
+}
+
 // Y = [base -] scale .* (A_j X), X in its column-major block layout.  A
 // workgroup owns 64 consecutive batch rows (one subdomain: segments are
 // multiples of 128 rows).  It first copies the X rows of the block's
@@ -1175,13 +1302,35 @@ static void gt(EigWork& w, const double* X, double* Nn, hipStream_t st) {
   k_gt<<<nb256(w.plen * w.k), 256, 0, st>>>(w.plen, w.k, w.node_sub.p, w.poff_d.p, w.pl.p, w.voff_d.p, w.ne_off.p,
                                             w.ne_ptr.p, w.ne_edge.p, w.ne_sign.p, X, Nn);
 }
+// Nn = C_j^T X (X through its row-major copy)
+static void ctx_mul(EigWork& w, const double* X, double* Nn, hipStream_t st) {
+  if (!w.xrow.p) w.xrow.alloc((size_t)w.len * 32);
+  k_block_rowmajor<<<(unsigned)((w.len + 63) / 64), 256, 0, st>>>(w.len, w.k, w.row_sub.p, w.voff_d.p, X, w.xrow.p);
+  k_csr_rm<true><<<(unsigned)((w.plen + 63) / 64), 256, 0, st>>>(w.plen, w.k, w.node_sub.p, w.poff_d.p, w.pl.p,
+                                                                 w.voff_d.p, w.ct_rp.p, w.ct_row.p, w.ct_val.p,
+                                                                 w.xrow.p, nullptr, Nn);
+}
+// out = base - C_j Nn (Nn through its row-major copy)
+static void cn_mul(EigWork& w, const double* Nn, const double* base, double* out, hipStream_t st) {
+  if (!w.nrow.p) w.nrow.alloc((size_t)w.plen * 32);
+  k_block_rowmajor<<<(unsigned)((w.plen + 63) / 64), 256, 0, st>>>(w.plen, w.k, w.node_sub.p, w.poff_d.p, Nn,
+                                                                   w.nrow.p);
+  k_csr_rm<false><<<(unsigned)((w.len + 63) / 64), 256, 0, st>>>(w.len, w.k, w.row_sub.p, w.voff_d.p, w.nloc.p,
+                                                                 w.poff_d.p, w.c_rp.p, w.c_node.p, w.c_val.p,
+                                                                 w.nrow.p, base, out);
+}
 static void gmul(EigWork& w, const double* Nn, const double* base, const double* scale, double* out, hipStream_t st) {
   k_g<<<nb256(w.len * w.k), 256, 0, st>>>(w.len, w.k, w.row_sub.p, w.voff_d.p, w.nloc.p, w.poff_d.p, w.ena.p, w.enb.p,
                                           Nn, base, scale, out);
 }
 
 // out = Atilde X  (tmp1, tmp2: edge blocks; nt: node block); with the
-// classical pencil out = D A D X
+// classical pencil out = D A D X.  G^T A X and A G c go through C = A G
+// (k_c_vals): formed as G^T (A X) and A (G c) their sums cancel (A G ~
+// gamma M G for interior nodes while A's entries are of the curl-curl
+// size) and the FP64 rounding, amplified by S^-1 ~ 1 / gamma, makes the
+// operator non-linear at a level that stalls the eigensolver on strongly
+// heterogeneous subdomains.
 static void apply_atilde(geneo_ctx* ctx, const geneo_precond* pc, EigWork& w, const double* X, double* out,
                          double* t1, double* t2, double* nt) {
   hipStream_t st = ctx->stream;
@@ -1191,15 +1340,13 @@ static void apply_atilde(geneo_ctx* ctx, const geneo_precond* pc, EigWork& w, co
     spmm(pc, w, nullptr, t1, nullptr, D, out, st);                   // D A D X
     return;
   }
-  spmm(pc, w, nullptr, X, nullptr, nullptr, t1, st);                 // A X
-  gt(w, t1, nt, st);                                                 // G^T A X
+  ctx_mul(w, X, nt, st);                                             // G^T A X = C^T X
   solve_multi(w.node, w.S.p, w.Sinv.p, nt, w.k, w.k, ctx->d_sync, w.flags_node.p, ctx->d_err, st);
   gmul(w, nt, X, D, t1, st);                                         // D (X - G S^-1 G^T A X)
   spmm(pc, w, nullptr, t1, nullptr, D, t2, st);                      // y = D A D u
   gt(w, t2, nt, st);
   solve_multi(w.node, w.S.p, w.Sinv.p, nt, w.k, w.k, ctx->d_sync, w.flags_node.p, ctx->d_err, st);
-  gmul(w, nt, nullptr, nullptr, t1, st);                             // G S^-1 G^T y
-  spmm(pc, w, nullptr, t1, t2, nullptr, out, st);                    // y - A G S^-1 G^T y
+  cn_mul(w, nt, t2, out, st);                                        // y - A G S^-1 G^T y = y - C c
 }
 
 static void gram(EigWork& w, int nl, const double* L0, const double* L1, const double* L2, const double* A0,
@@ -1373,6 +1520,74 @@ void solve_local_gevps(geneo_ctx* ctx, geneo_precond* pc) {
     w.flags_node.alloc(flag_off);
     HIP_CHECK(hipMemsetAsync(w.flags_node.p, 0, sizeof(unsigned) * flag_off, st));
   }
+  // ---- patterns of C_j = A_j G_j: the entries of edge row r are the distinct
+  // end nodes of the row's columns; by node rows, the transpose (edge row,
+  // entry index)
+  {
+    const std::vector<int32_t>& hcol = pc->h_lcol;
+    std::vector<std::vector<int32_t>> rowlen(N), nodes(N), trow(N), tsrc(N);
+    std::vector<std::vector<int64_t>> tpre(N);
+    parallel_for(N, [&](int j) {
+      const int64_t n = nloc[j], p = pl[j];
+      const int32_t* rp = lrp.data() + rp_off[j];
+      const int64_t vj = w.voff[j];
+      auto& rl = rowlen[j];
+      auto& nd = nodes[j];
+      rl.assign(n, 0);
+      std::vector<int32_t> cand;
+      for (int64_t r = 0; r < n; ++r) {
+        cand.clear();
+        for (int32_t t = rp[r]; t < rp[r + 1]; ++t) {
+          const int64_t cb = vj + hcol[t];
+          if (ena[cb] >= 0) cand.push_back(ena[cb]);
+          if (enb[cb] >= 0) cand.push_back(enb[cb]);
+        }
+        std::sort(cand.begin(), cand.end());
+        cand.erase(std::unique(cand.begin(), cand.end()), cand.end());
+        rl[r] = (int32_t)cand.size();
+        nd.insert(nd.end(), cand.begin(), cand.end());
+      }
+      auto& pre = tpre[j];
+      pre.assign(p + 1, 0);
+      for (int32_t a : nd) pre[a + 1]++;
+      for (int64_t a = 0; a < p; ++a) pre[a + 1] += pre[a];
+      trow[j].assign(nd.size(), 0);
+      tsrc[j].assign(nd.size(), 0);
+      std::vector<int64_t> f(pre.begin(), pre.end() - 1);
+      int64_t e = 0;
+      for (int64_t r = 0; r < n; ++r)
+        for (int32_t q = 0; q < rl[r]; ++q, ++e) {
+          const int32_t a = nd[e];
+          trow[j][f[a]] = (int32_t)r;
+          tsrc[j][f[a]++] = (int32_t)e;
+        }
+    });
+    int64_t tot = 0;
+    for (int j = 0; j < N; ++j) tot += (int64_t)nodes[j].size();
+    if (tot >= (int64_t)INT32_MAX) throw Error(GENEO_EUNSUPPORTED, "pattern of A_j G_j beyond 2^31 entries");
+    w.h_c_rp.assign(w.len + 1, 0);
+    w.h_ct_rp.assign(w.plen + 1, 0);
+    w.h_c_node.reserve(tot);
+    w.h_ct_row.reserve(tot);
+    w.h_ct_src.reserve(tot);
+    int64_t e_base = 0;
+    for (int j = 0; j < N; ++j) {
+      const int64_t vj = w.voff[j];
+      for (int64_t r = 0; r < nloc[j]; ++r) w.h_c_rp[vj + r + 1] = rowlen[j][r];
+      for (int64_t a = 0; a < pl[j]; ++a) w.h_ct_rp[w.poff[j] + a + 1] = tpre[j][a + 1] - tpre[j][a];
+      w.h_c_node.insert(w.h_c_node.end(), nodes[j].begin(), nodes[j].end());
+      w.h_ct_row.insert(w.h_ct_row.end(), trow[j].begin(), trow[j].end());
+      for (int32_t e : tsrc[j]) w.h_ct_src.push_back((int32_t)(e_base + e));
+      e_base += (int64_t)nodes[j].size();
+    }
+    for (int64_t b = 0; b < w.len; ++b) w.h_c_rp[b + 1] += w.h_c_rp[b];
+    for (int64_t b = 0; b < w.plen; ++b) w.h_ct_rp[b + 1] += w.h_ct_rp[b];
+  }
+  w.c_rp.upload(w.h_c_rp, st);
+  w.c_node.upload(w.h_c_node, st);
+  w.ct_rp.upload(w.h_ct_rp, st);
+  w.ct_row.upload(w.h_ct_row, st);
+  w.ct_src.upload(w.h_ct_src, st);
   w.row_sub.upload(row_sub, st);
   w.nloc.upload(nloc, st);
   w.rp_off.upload(rp_off, st);
@@ -1415,6 +1630,16 @@ void solve_local_gevps(geneo_ctx* ctx, geneo_precond* pc) {
     k_neumann_vals<<<nb256(lnnz), 256, 0, st>>>(lnnz, N, pc->d_lnnz_off.p, pc->d_lslot.p, s->d_contrib_ptr.p,
                                                  s->d_contrib.p, s->d_elem.p, s->d_tet_cell.p, dbits.p, words,
                                                  w.bval.p);
+    // C_j = A_j G_j, then its values in node-row order
+    const int64_t nc = (int64_t)w.h_c_node.size();
+    w.c_val.alloc(std::max<int64_t>(nc, 1));
+    w.ct_val.alloc(std::max<int64_t>(nc, 1));
+    DevBuf<double> clo;
+    clo.alloc(std::max<int64_t>(nc, 1));
+    k_c_vals<<<nb256(w.len), 256, 0, st>>>(w.len, w.row_sub.p, w.voff_d.p, w.nloc.p, w.rp_off.p, w.lrp.p,
+                                           pc->d_lcol.p, w.aval.p, w.ena.p, w.enb.p, w.c_rp.p, w.c_node.p,
+                                           w.c_val.p, clo.p);
+    if (nc) k_gather_vals<<<nb256(nc), 256, 0, st>>>(nc, w.ct_src.p, w.c_val.p, w.ct_val.p);
     HIP_CHECK(hipStreamSynchronize(st));
   }
   const auto& ld = pc->local.h_desc;
@@ -1746,8 +1971,7 @@ void solve_local_gevps(geneo_ctx* ctx, geneo_precond* pc) {
     pc->eig_sel[j] = c;
   }
   // u = D (X - G S^-1 G^T A X) into T1 (all k columns), then pack the selected ones
-  spmm(pc, w, nullptr, X.p, nullptr, nullptr, T2.p, st);
-  gt(w, T2.p, NT.p, st);
+  ctx_mul(w, X.p, NT.p, st);
   solve_multi(w.node, w.S.p, w.Sinv.p, NT.p, k, k, ctx->d_sync, w.flags_node.p, ctx->d_err, st);
   gmul(w, NT.p, X.p, pc->d_bpou.p, T1.p, st);
   check_device_error(ctx);
