@@ -261,6 +261,14 @@ int geneo_apply(geneo_ctx* ctx, const geneo_precond* pc, const double* r, double
 /* --- solve: preconditioned Krylov iteration ------------------------------ */
 
 typedef enum { GENEO_SOLVER_PCG = 0, GENEO_SOLVER_GMRES = 1 } geneo_solver;
+/* How PCG applies the two-level preconditioner.  DEFLATED (default): from
+ * x0 = Q b with (I - Q A) M_AS + Q, Q = Z E^-1 Z^T, M_AS = sum_i R_i^T A_i^-1 R_i
+ * (one coarse solve per iteration); in exact arithmetic PCG then produces the
+ * iterates of PCG with M_AS,2 (eq. (AS2)) from x0 = 0, since every residual has
+ * Z^T r = 0, where the two operators agree.  BALANCED: M_AS,2 itself from
+ * x0 = 0 (two coarse solves per iteration).  geneo_apply always applies
+ * M_AS,2; GMRES always uses M_AS,2. */
+typedef enum { GENEO_PCG_DEFLATED = 0, GENEO_PCG_BALANCED = 1 } geneo_pcg_form;
 
 typedef struct {
   double rtol;      /* stop at the first k with ||r_k||_2 <= rtol ||b||_2 */
@@ -279,6 +287,7 @@ typedef struct {
                             GENEO_ENOCONV); 0 (default) = stop on the recurrence residual.  The true residual
                             is computed and reported either way.  In FP64 it cannot go below about
                             u ||A|| ||x|| / ||b|| (u = 2^-53), which exceeds 1e-8 when gamma is small. */
+  int32_t pcg_form;      /* geneo_pcg_form (default DEFLATED) */
 } geneo_solve_opts;
 
 typedef struct {
@@ -295,7 +304,7 @@ typedef struct {
                             bound on the rounding error of that computed true residual; a true residual at
                             or below it is as small as FP64 can certify */
   double coarse_solve_ms; /* PCG: device time of one coarse solve (forward and backward sweeps), the mean of
-                             the two in the first preconditioner application (HIP events) */
+                             the first two (HIP events) */
 } geneo_solve_info;
 
 /* Solve A x = b (Section 1, the discrete system) from x0 = 0 with PCG

@@ -32,7 +32,10 @@ Readings: the paper solves with right-preconditioned GMRES at rtol 1e-6
 norm whatever the preconditioner); `gmres` below is that solver.  The
 measured path runs preconditioned conjugate gradients (the preconditioner
 is symmetric positive definite) from x0 = 0, stopping at the first iterate
-with ||r_k||_2 <= rtol ||b||_2 (recurrence residual).  weight="pou" puts the
+with ||r_k||_2 <= rtol ||b||_2 (recurrence residual); `apply_deflated` with
+x0 = Q b (`deflated_start`) is the one-coarse-solve form with the same PCG
+iterates in exact arithmetic (every residual then has Z^T r = 0, where it
+equals M_AS,2).  weight="pou" puts the
 partition of unity D_i of Section 2 into the one-level sum,
 sum_i R_i^T D_i A_i^-1 R_i (the restricted additive Schwarz variant; not
 symmetric, so it goes with GMRES).
@@ -237,6 +240,24 @@ class TwoLevel:
         c2 = self.coarse_solve(self.AZ.T @ y)
         return self.Z @ c + y - self.Z @ c2
 
+    def apply_deflated(self, r):
+        """z = M_AS^-1 r + Q (r - A M_AS^-1 r), Q = Z E^-1 Z^T: the deflated
+        form (I - Q A) M_AS^-1 + Q of the preconditioner, one coarse solve.
+        Where Z^T r = 0, (I - A Q) r = r and Q r = 0, and this equals
+        M_AS,2^-1 r (eq. (AS2), as in `apply`); PCG from x0 = Q b keeps Z^T r = 0
+        on every residual in exact arithmetic."""
+        if self.Z is None:
+            return self.one_level(r)
+        y = self.one_level(r)
+        t = r - self.dec.sys.A @ y
+        return y + self.Z @ self.coarse_solve(self.Z.T @ t)
+
+    def deflated_start(self, b):
+        """x0 = Q b = Z E^-1 Z^T b (0 without a coarse space)."""
+        if self.Z is None:
+            return np.zeros_like(b)
+        return self.Z @ self.coarse_solve(self.Z.T @ b)
+
     def matrix(self, block=512):
         """Dense M^-1, applied to blocks of unit vectors (small cases only)."""
         n = self.dec.sys.n
@@ -248,11 +269,12 @@ class TwoLevel:
         return out
 
 
-def pcg(A, b, M=None, rtol=1e-8, maxit=1000):
-    """Preconditioned conjugate gradients (Hestenes-Stiefel) from x0 = 0.
-    Returns (x, iterations, residual history ||r_k||/||b||)."""
-    x = np.zeros_like(b)
-    r = b.copy()
+def pcg(A, b, M=None, rtol=1e-8, maxit=1000, x0=None):
+    """Preconditioned conjugate gradients (Hestenes-Stiefel) from x0 (default
+    0).  Stops at ||r_k|| <= rtol ||b||.  Returns (x, iterations, residual
+    history ||r_k||/||b||)."""
+    x = np.zeros_like(b) if x0 is None else np.array(x0, dtype=np.float64, copy=True)
+    r = b - A @ x if x0 is not None else b.copy()
     nb = np.linalg.norm(b)
     z = M(r) if M is not None else r.copy()
     p = z.copy()

@@ -279,9 +279,10 @@ int geneo_apply(geneo_ctx* ctx, const geneo_precond* pc, const double* r, double
 int geneo_solve(geneo_ctx* ctx, const geneo_system* s, const geneo_precond* pc, const double* b, double* x,
                 const geneo_solve_opts* o, geneo_solve_info* info) {
   if (!ctx || !s || !b || !x || !info) return GENEO_EINVAL;
-  geneo_solve_opts def{1e-8, 1000, 1, GENEO_SOLVER_PCG, 0, 0};
+  geneo_solve_opts def{1e-8, 1000, 1, GENEO_SOLVER_PCG, 0, 0, GENEO_PCG_DEFLATED};
   const geneo_solve_opts* op = o ? o : &def;
   if (!(op->rtol > 0) || op->maxit < 1 || op->restart < 0) return GENEO_EINVAL;
+  if (op->pcg_form != GENEO_PCG_DEFLATED && op->pcg_form != GENEO_PCG_BALANCED) return GENEO_EINVAL;
   if (op->method != GENEO_SOLVER_PCG && op->method != GENEO_SOLVER_GMRES) return GENEO_EINVAL;
   std::memset(info, 0, sizeof(*info));
   return guarded(ctx, [&] {

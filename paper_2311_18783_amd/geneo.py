@@ -32,6 +32,7 @@ FP64, FP32_REFINE1 = 0, 1
 COARSE_SNK_GENEO, COARSE_SNK, COARSE_NONE, COARSE_NK, COARSE_NK_GENEO = 0, 1, 2, 3, 4
 WEIGHT_IDENTITY, WEIGHT_POU = 0, 1
 PCG, GMRES = 0, 1
+PCG_DEFLATED, PCG_BALANCED = 0, 1
 ORDER_NATURAL, ORDER_NESTED_DISSECTION, ORDER_AUTO = 0, 1, 2
 PART_BOX, PART_RCB, PART_EXPLICIT = 0, 1, 2
 
@@ -118,7 +119,7 @@ class FactorSchedule(C.Structure):
 
 class SolveOpts(C.Structure):
     _fields_ = [("rtol", C.c_double), ("maxit", C.c_int32), ("graph", C.c_int32), ("method", C.c_int32),
-                ("restart", C.c_int32), ("true_residual", C.c_int32)]
+                ("restart", C.c_int32), ("true_residual", C.c_int32), ("pcg_form", C.c_int32)]
 
 
 class SolveInfo(C.Structure):
@@ -327,7 +328,7 @@ class Context:
         self._check(lib.geneo_spmv(self.h, system.h, _dptr(x), _dptr(y)))
 
     def solve(self, system, pc, b, x, rtol=1e-8, maxit=1000, allow_noconv=False, graph=True, method=PCG,
-              restart=0, true_residual=False):
+              restart=0, true_residual=False, pcg_form=None):
         """geneo_solve: PCG (method=PCG) or right-preconditioned GMRES
         (method=GMRES, restart length `restart`, 0 = none) from x = 0 (b, x:
         float64 device tensors of length n).  graph=True replays one captured
@@ -335,14 +336,16 @@ class Context:
         graph=False launches kernel by kernel (same kernels, bitwise equal
         iterates).  allow_noconv returns the info of a run stopped by maxit
         instead of raising.  true_residual=True: PCG continues from the true
-        residual while it misses rtol (at most two restarts)."""
+        residual while it misses rtol (at most two restarts).  pcg_form:
+        PCG_DEFLATED (default: from x0 = Q b with (I - Q A) M_AS + Q, one
+        coarse solve per iteration) or PCG_BALANCED (M_AS,2 from x0 = 0)."""
         n = system.info().n
         if pc is not None and pc.system is not system:
             raise ValueError("the preconditioner was built on another system")
         check_vector(b, n, self.device, "b")
         check_vector(x, n, self.device, "x")
         o = SolveOpts(float(rtol), int(maxit), 1 if graph else 0, int(method), int(restart),
-                      1 if true_residual else 0)
+                      1 if true_residual else 0, PCG_DEFLATED if pcg_form is None else int(pcg_form))
         info = SolveInfo()
         rc = lib.geneo_solve(self.h, system.h, pc.h if pc is not None else None, _dptr(b), _dptr(x),
                              C.byref(o), C.byref(info))

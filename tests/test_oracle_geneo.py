@@ -358,3 +358,28 @@ def test_mixed_beam_geneo_columns_are_the_relative_harmonic_field():
                 v = V[:, 0]
                 cos = abs(v @ B @ h) / np.sqrt((v @ B @ v) * (h @ B @ h))
                 assert cos > 1 - 1e-4, cos
+
+
+@pytest.mark.parametrize("cfg", ["small_channels", "small_floating", "small_hole"])
+def test_deflated_pcg_follows_the_balanced_iterates(cfg):
+    """PCG with the deflated form (I - Q A) M_AS^-1 + Q from x0 = Q b against
+    PCG with M_AS,2 (eq. (AS2)) from x0 = 0: the same iteration count, the
+    same solution to 1e-7 relative, and Z^T r stays at rounding level along
+    the deflated run (the property that makes the two operators agree)."""
+    w = W.make(cfg)
+    s = fem.System(w.mesh, w.mu, w.eps, w.gamma, w.dirichlet)
+    dec = decomp.Decomposition(s, decomp.partition_cells(w), w.overlap)
+    opc = geneo.TwoLevel(dec, tau=w.tau, nev_max=w.nev_max)
+    b = w.rhs(s.n)
+    xb, itb, _ = geneo.pcg(s.A, b, opc.apply, rtol=1e-8)
+    zr = []
+    zn = spla.norm(opc.Z)   # Frobenius norm, >= the spectral one
+
+    def M(r):
+        zr.append(np.linalg.norm(opc.Z.T @ r) / (zn * np.linalg.norm(r)))
+        return opc.apply_deflated(r)
+
+    xd, itd, _ = geneo.pcg(s.A, b, M, rtol=1e-8, x0=opc.deflated_start(b))
+    assert itd == itb, (itd, itb)
+    assert np.linalg.norm(xd - xb) <= 1e-7 * np.linalg.norm(xb)
+    assert max(zr) <= 1e-10
