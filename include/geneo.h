@@ -218,7 +218,7 @@ typedef struct {
                                (part of t_factor_ms, which also holds the check, the probe and any fallback) */
   double coarse_lambda_min; /* estimate of the smallest eigenvalue of the factored coarse matrix (kept columns)
                                scaled by its diagonal, diag(E)^-1/2 E diag(E)^-1/2 (power iteration on the
-                               factor's inverse); below 1e-12 the columns are eliminated again */
+                               factor's inverse); below 1e-20 the columns are eliminated again */
   double coarse_drop_tol_used; /* drop tolerance of the final coarse factor: coarse_drop_tol times 10 per
                                   re-elimination */
   int32_t coarse_refactors; /* re-eliminations with a tenfold tolerance (0 .. 4) */
@@ -226,6 +226,13 @@ typedef struct {
                                   last (estimates, refills of E, re-eliminations; 0 without re-elimination) */
   double coarse_solve_bytes; /* algorithmic bytes of one coarse solve: every tile of the factor's pattern read
                                 once per sweep (forward and backward), 128 x 128 FP64 each */
+  double t_lobpcg_loop_ms;  /* device time of the eigensolver's iteration loop (part of t_gevp_ms, which also
+                               holds the Neumann factorisation, the node matrices and the start block) */
+  double lobpcg_solve_ms;   /* device time of one application of B^-1 = (A_j^Neu)^-1 to the block of k
+                               vectors of every subdomain (forward and backward sweep), on the second
+                               iteration (0 if the loop stopped after one) */
+  double lobpcg_solve_bytes; /* algorithmic bytes of that application: each local Neumann factor's lower
+                                triangle read once per sweep, sum n_j (n_j + 1) 8 */
 } geneo_precond_info;
 
 void geneo_setup_opts_default(geneo_setup_opts* o);
@@ -305,6 +312,8 @@ typedef struct {
                             or below it is as small as FP64 can certify */
   double coarse_solve_ms; /* PCG: device time of one coarse solve (forward and backward sweeps), the mean of
                              the first two (HIP events) */
+  int64_t coarse_solves;  /* PCG: coarse solves run (DEFLATED: one per preconditioner application plus the
+                             start x0 = Q b; BALANCED: two per application) */
 } geneo_solve_info;
 
 /* Solve A x = b (Section 1, the discrete system) from x0 = 0 with PCG

@@ -1847,6 +1847,19 @@ void solve_local_gevps(geneo_ctx* ctx, geneo_precond* pc) {
   bool have_p = false;
   int it = 0, unconv = 0;
   const int maxit = std::max(1, pc->opts.lobpcg_maxit);
+  // device time of the iteration loop, and of one application of B^-1 to the
+  // k-column block (both triangular sweeps over every local factor), timed on
+  // the second iteration
+  struct LoopEvents {
+    hipEvent_t e[4] = {nullptr, nullptr, nullptr, nullptr};
+    ~LoopEvents() {
+      for (auto& x : e)
+        if (x) (void)hipEventDestroy(x);
+    }
+  } lt;
+  for (auto& x : lt.e) HIP_CHECK(hipEventCreate(&x));
+  bool solve_timed = false;
+  HIP_CHECK(hipEventRecord(lt.e[0], st));
   for (it = 1; it <= maxit; ++it) {
     // residual shifts of the current block (the projection out of span(G_j)
     // after the update moves it off the Rayleigh-Ritz vectors): the shifts that
@@ -1904,7 +1917,12 @@ void solve_local_gevps(geneo_ctx* ctx, geneo_precond* pc) {
     // G_j^T B W = G_j^T Atilde X = 0 already; B^-1 amplifies the rounding errors of R along the
     // near-kernel of B (gradients, eigenvalues ~ gamma), so W is projected again (as are the
     // updated X and P below).
+    if (it == 2) HIP_CHECK(hipEventRecord(lt.e[2], st));
     solve_multi(pc->local, w.LB.p, w.LBinv.p, Wb.p, k, k, ctx->d_sync, w.flags_local.p, ctx->d_err, st);
+    if (it == 2) {
+      HIP_CHECK(hipEventRecord(lt.e[3], st));
+      solve_timed = true;
+    }
     deflate(Wb.p);
     for (int t = 0; t < 2; ++t) {
       bmul(Wb.p, BW.p);
@@ -1948,9 +1966,22 @@ void solve_local_gevps(geneo_ctx* ctx, geneo_precond* pc) {
   // the eigenvalues: Rayleigh quotients of the final block with the factored denominator
   k_ltx<<<(unsigned)w.nlt, 256, 0, st>>>(k, pc->local.d_desc.p, w.lt_blk.p, w.voff_d.p, w.LB.p, X.p, T2.p);
   k_rq<<<N * k, 256, 0, st>>>(k, w.voff_d.p, X.p, AX.p, BX.p, T2.p, theta.p);
+  HIP_CHECK(hipEventRecord(lt.e[1], st));
   HIP_CHECK(hipMemcpyAsync(h_theta.data(), theta.p, sizeof(double) * N * k, hipMemcpyDeviceToHost, st));
   HIP_CHECK(hipStreamSynchronize(st));
   check_device_error(ctx);
+  {
+    float ms = 0.0f;
+    HIP_CHECK(hipEventElapsedTime(&ms, lt.e[0], lt.e[1]));
+    pc->info.t_lobpcg_loop_ms = ms;
+    if (solve_timed) {
+      HIP_CHECK(hipEventElapsedTime(&ms, lt.e[2], lt.e[3]));
+      pc->info.lobpcg_solve_ms = ms;
+    }
+    double bytes = 0.0;
+    for (int j = 0; j < N; ++j) bytes += (double)nloc[j] * ((double)nloc[j] + 1.0) * 8.0;
+    pc->info.lobpcg_solve_bytes = bytes;
+  }
   pc->info.lobpcg_iters = it > maxit ? maxit : it;
   pc->info.lobpcg_unconverged = unconv;
 

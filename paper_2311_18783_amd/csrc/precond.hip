@@ -1718,6 +1718,8 @@ void pcg(geneo_ctx* ctx, const geneo_system* sys, const geneo_precond* pc, const
   const double bnorm = std::sqrt(h[4]);
   const double tol = o->rtol * bnorm;
   int it = 0, replays = 0;
+  int64_t applies = 0;   // preconditioner applications run (graph captures excluded)
+  bool capturing = false;
   double rel = 1.0;
   bool conv = bnorm == 0.0;
   if (!conv) {
@@ -1731,6 +1733,7 @@ void pcg(geneo_ctx* ctx, const geneo_system* sys, const geneo_precond* pc, const
     };
     // z = M^-1 r, the new direction (end of one iteration) ...
     auto tail = [&](int first) {
+      if (!capturing) ++applies;
       precond(r.p, z.p);
       dot(r.p, z.p, n, part.p, S.p + 3, st);
       k_pcg_dir<<<nblocks(n), 256, 0, st>>>(n, p.p, z.p, S.p, first);
@@ -1760,13 +1763,16 @@ void pcg(geneo_ctx* ctx, const geneo_system* sys, const geneo_precond* pc, const
         if (!exec) {
           // one iteration as a graph: kernel nodes and the copy of ||r||^2
           HIP_CHECK(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
+          capturing = true;
           tail(0);
           head();
+          capturing = false;
           HIP_CHECK(hipStreamEndCapture(st, &graph));
           HIP_CHECK(hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0));
         }
         HIP_CHECK(hipGraphLaunch(exec, st));
         ++replays;
+        ++applies;
       }
       HIP_CHECK(hipGetLastError());
       HIP_CHECK(hipStreamSynchronize(st));
@@ -1819,6 +1825,9 @@ void pcg(geneo_ctx* ctx, const geneo_system* sys, const geneo_precond* pc, const
   if (bnorm == 0.0) info->iterations = 0;
   info->rel_residual = bnorm == 0.0 ? 0.0 : rel;
   info->graph_replays = replays;
+  // one coarse solve per deflated application plus the start x0 = Q b; two per
+  // balanced application
+  info->coarse_solves = !(pc && pc->n0 > 0) ? 0 : deflated ? 1 + applies : 2 * applies;
   if (use_graph) {
     HIP_CHECK(hipEventRecord(ev_out, st));
     HIP_CHECK(hipStreamWaitEvent(user, ev_out, 0));

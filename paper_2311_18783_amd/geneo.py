@@ -92,7 +92,8 @@ class PrecondInfo(C.Structure):
                 ("coarse_solve_depth", C.c_int32), ("t_factor_fp32_ms", C.c_double),
                 ("coarse_lambda_min", C.c_double), ("coarse_drop_tol_used", C.c_double),
                 ("coarse_refactors", C.c_int32), ("t_coarse_refactor_ms", C.c_double),
-                ("coarse_solve_bytes", C.c_double)]
+                ("coarse_solve_bytes", C.c_double), ("t_lobpcg_loop_ms", C.c_double),
+                ("lobpcg_solve_ms", C.c_double), ("lobpcg_solve_bytes", C.c_double)]
 
 
 class ModelOpts(C.Structure):
@@ -126,7 +127,7 @@ class SolveInfo(C.Structure):
     _fields_ = [("iterations", C.c_int32), ("rel_residual", C.c_double), ("solve_ms", C.c_double),
                 ("graph_replays", C.c_int32), ("residual_replacements", C.c_int32),
                 ("true_rel_residual", C.c_double), ("residual_floor", C.c_double),
-                ("coarse_solve_ms", C.c_double)]
+                ("coarse_solve_ms", C.c_double), ("coarse_solves", C.c_int64)]
 
 
 _vp = C.c_void_p

@@ -43,3 +43,42 @@ def test_binding_rejects_bad_vectors_before_the_library():
         geneo.check_vector(torch.zeros(20, dtype=torch.float64)[::2], 10, 0)
     with pytest.raises(ValueError, match="elements"):
         geneo.check_vector(torch.zeros(9, dtype=torch.float64), 10, 0)
+
+
+# binding structure -> C typedef in include/geneo.h
+_STRUCTS = {"Mesh": "geneo_mesh", "SystemInfo": "geneo_system_info", "PartitionOpts": "geneo_partition_opts",
+            "DecompInfo": "geneo_decomp_info", "SetupOpts": "geneo_setup_opts",
+            "PrecondInfo": "geneo_precond_info", "ModelOpts": "geneo_model_opts", "ModelInfo": "geneo_model_info",
+            "TrainOpts": "geneo_train_opts", "TrainInfo": "geneo_train_info",
+            "FactorSchedule": "geneo_factor_schedule", "SolveOpts": "geneo_solve_opts",
+            "SolveInfo": "geneo_solve_info"}
+
+
+def test_binding_structures_match_the_header(tmp_path):
+    """Every ctypes structure of the binding has the size and field offsets
+    of its C typedef, as the host C compiler lays it out from the header: a
+    field added to one side only would shift every later field."""
+    import shutil
+    import subprocess
+    from paper_2311_18783_amd import geneo
+    cc = shutil.which("gcc") or shutil.which("cc")
+    if cc is None:
+        pytest.skip("no host C compiler")
+    lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "geneo.h"', "int main(void) {"]
+    expect = []
+    for py, c in _STRUCTS.items():
+        cls = getattr(geneo, py)
+        lines.append(f'  printf("%zu\\n", sizeof({c}));')
+        expect.append((f"sizeof {c}", ctypes.sizeof(cls)))
+        for f in cls._fields_:
+            lines.append(f'  printf("%zu\\n", offsetof({c}, {f[0]}));')
+            expect.append((f"{c}.{f[0]}", getattr(cls, f[0]).offset))
+    lines += ["  return 0;", "}"]
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines) + "\n")
+    exe = tmp_path / "layout"
+    subprocess.run([cc, "-std=c11", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)], check=True)
+    got = [int(v) for v in subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout.split()]
+    assert len(got) == len(expect)
+    bad = [(name, want, g) for (name, want), g in zip(expect, got) if want != g]
+    assert not bad, bad
