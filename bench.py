@@ -59,6 +59,10 @@ def parse():
     ap.add_argument("--coarse-order", default="auto", choices=["auto", "natural", "nd"],
                     help="elimination order of the coarse columns (nd: nested dissection of the subdomain graph; "
                          "auto: nested dissection where it shortens the coarse solves' dependency chain)")
+    ap.add_argument("--coarse-schedule", default="auto", choices=["auto", "steps", "levels"],
+                    help="launch schedule of the coarse factorisation (levels: block columns of equal height in "
+                         "its elimination tree together; auto: levels when the tree is at most half as tall as "
+                         "the block column count)")
     ap.add_argument("--paper-table", default=None, choices=["gamma", "eps", "mu"],
                     help="instead of the benchmark: the paper's beam sweeps (Section 4, Numerical results: the "
                          "gamma sweep, alternating eps layers, alternating mu layers), one JSON line per case")
@@ -104,7 +108,7 @@ def train_model(geneo, ctx, wid, n_inst):
                "loss_first_epoch": ti.loss_first, "loss_last_epoch": ti.loss_last, "holdout_loss": ti.holdout_loss}
 
 
-def run_step(geneo, ctx, w, precision, b_host=None, model=None, coarse_order=0):
+def run_step(geneo, ctx, w, precision, b_host=None, model=None, coarse_order=0, coarse_schedule=0):
     import torch
     ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
     t0 = time.perf_counter()
@@ -120,7 +124,7 @@ def run_step(geneo, ctx, w, precision, b_host=None, model=None, coarse_order=0):
     t2 = time.perf_counter()
     kw = {"model": model} if model is not None else {}
     pc = ctx.setup(sysm, dec, tau=w.tau, nev_max=w.nev_max, local_precision=precision, coarse_order=coarse_order,
-                   **kw)
+                   coarse_schedule=coarse_schedule, **kw)
     torch.cuda.synchronize()
     t3 = time.perf_counter()
     si = ctx.solve(sysm, pc, b, x, rtol=1e-8, maxit=2000)
@@ -149,6 +153,7 @@ def run_step(geneo, ctx, w, precision, b_host=None, model=None, coarse_order=0):
                coarse_drop_tol_used=pi.coarse_drop_tol_used, coarse_nd_predicted_depth=pi.coarse_nd_predicted_depth,
                coarse_solve_ms=si.coarse_solve_ms, coarse_solve_bytes=pi.coarse_solve_bytes,
                coarse_solves=si.coarse_solves, t_lobpcg_loop_ms=pi.t_lobpcg_loop_ms,
+               coarse_levels=pi.coarse_levels, coarse_schedule=pi.coarse_schedule_used,
                lobpcg_solve_ms=pi.lobpcg_solve_ms, lobpcg_solve_bytes=pi.lobpcg_solve_bytes)
     del pc, dec, sysm
     return out, b_host
@@ -252,6 +257,8 @@ def summarize(res):
         "coarse_refactors": last["coarse_refactors"], "coarse_drop_tol_used": last["coarse_drop_tol_used"],
         "coarse_solve_ms": mean("coarse_solve_ms"), "coarse_solve_bytes": last["coarse_solve_bytes"],
         "coarse_solves": last["coarse_solves"], "lobpcg_loop_ms": mean("t_lobpcg_loop_ms"),
+        "coarse_levels": last["coarse_levels"],
+        "coarse_schedule": {1: "steps", 2: "levels"}.get(last["coarse_schedule"], "steps"),
         "lobpcg_solve_ms": mean("lobpcg_solve_ms"),
         "learned_candidates": last["learned_candidates"],
         "pcg_iterations": last["iterations"], "rel_residual": last["rel_residual"],
@@ -394,20 +401,22 @@ def main():
     run = [v for v in ("learned_fp32", "fp64") if a.variant in ("both", v)]
     model, training = None, None
     corder = {"nd": geneo.ORDER_NESTED_DISSECTION, "natural": geneo.ORDER_NATURAL, "auto": geneo.ORDER_AUTO}[a.coarse_order]
+    csched = {"auto": geneo.SCHEDULE_AUTO, "steps": geneo.SCHEDULE_STEPS,
+              "levels": geneo.SCHEDULE_LEVELS}[a.coarse_schedule]
     if "learned_fp32" in run and a.train_instances > 0:
         model, training = train_model(geneo, ctx, wid, a.train_instances)
     b_host = None
     for _ in range(a.warmup):
         for v in run:
             prec, learned = variants[v]
-            _, b_host = run_step(geneo, ctx, w, prec, b_host, model if learned else None, corder)
+            _, b_host = run_step(geneo, ctx, w, prec, b_host, model if learned else None, corder, csched)
     torch.cuda.synchronize()
     res = {v: [] for v in run}
     t0 = time.perf_counter()
     for _ in range(a.steps):
         for v in run:
             prec, learned = variants[v]
-            r, b_host = run_step(geneo, ctx, w, prec, b_host, model if learned else None, corder)
+            r, b_host = run_step(geneo, ctx, w, prec, b_host, model if learned else None, corder, csched)
             res[v].append(r)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0

@@ -157,6 +157,16 @@ typedef enum { GENEO_WEIGHT_IDENTITY = 0, GENEO_WEIGHT_POU = 1 } geneo_one_level
  * triangular solves it predicts (from the subdomain adjacency) is at most
  * 0.6 of the natural order's block-row count, else natural. */
 typedef enum { GENEO_ORDER_NATURAL = 0, GENEO_ORDER_NESTED_DISSECTION = 1, GENEO_ORDER_AUTO = 2 } geneo_coarse_order;
+/* Launch schedule of the block-sparse coarse factorisation (same arithmetic
+ * per tile; only the grouping of tile updates, and so their rounding order,
+ * differs): STEPS = one block column after another (panel groups of
+ * trailing updates); LEVELS = the block columns of equal height in the
+ * factor's elimination tree together (one launch for their diagonal blocks,
+ * one for their column tiles), levels taken in groups of eight whose
+ * updates of later columns are applied once per group (on a chain, one
+ * column per level, this is STEPS with groups of eight).  AUTO (default):
+ * LEVELS. */
+typedef enum { GENEO_SCHEDULE_AUTO = 0, GENEO_SCHEDULE_STEPS = 1, GENEO_SCHEDULE_LEVELS = 2 } geneo_coarse_schedule;
 
 typedef struct {
   double tau;               /* GenEO threshold, keep lambda > tau (Section 4, Numerical results: 10) */
@@ -179,6 +189,7 @@ typedef struct {
   int32_t classical;        /* 1: GenEO vectors from the classical pencil D_j A_j D_j V = lambda A_j^Neu V
                                (Section 3.2, eq. (eigGenEOClassis): no projection out of span(G_j)), an
                                ablation of the method's filtered pencil; default 0 */
+  int32_t coarse_schedule;  /* geneo_coarse_schedule (default AUTO) */
 } geneo_setup_opts;
 
 typedef struct {
@@ -214,6 +225,8 @@ typedef struct {
   int32_t coarse_nd_levels; /* depth of the nested dissection of the subdomain graph (0: natural order) */
   int32_t coarse_nd_predicted_depth; /* AUTO: the solve depth predicted for the nested-dissection order */
   int32_t coarse_solve_depth; /* longest chain of dependent 128-row blocks in a coarse triangular solve */
+  int32_t coarse_levels;    /* height + 1 of the coarse factor's block elimination tree */
+  int32_t coarse_schedule_used; /* geneo_coarse_schedule the factorisation ran with (STEPS or LEVELS) */
   double t_factor_fp32_ms;  /* FP32_REFINE1: device time of the FP32 factorisation of all local matrices alone
                                (part of t_factor_ms, which also holds the check, the probe and any fallback) */
   double coarse_lambda_min; /* estimate of the smallest eigenvalue of the factored coarse matrix (kept columns)

@@ -104,7 +104,22 @@ struct FactorPlan {
   DevBuf<double> d_part;             // partial sums, 128 per helper
   int64_t fill_tiles = 0;                // lower tiles (with diagonal) in the pattern
   double sparse_flops = 0;               // factorisation flops on the pattern
-  void build_sparse(const MatDesc& d, const std::vector<uint8_t>& fill, hipStream_t st);
+  // Level schedule of a block-sparse factorisation: block column J's parent
+  // in the elimination tree is the first I > J with L(I, J) != 0; columns of
+  // equal height in that tree are independent (a column is updated only by
+  // its descendants), so each level is one launch of diagonal blocks (lv_cols)
+  // and one of column tiles (rows lv_trsm_rows of steps lv_trsm_steps); the
+  // tile updates run as launches over listed tiles (lv_pairs), each tile with
+  // the columns that update it in that launch (lv_k[lv_kptr[p] ..
+  // lv_kptr[p+1])); update launch u runs after level lv_launch_after[u].
+  bool levels = false;
+  int32_t n_levels = 0;                  // tree height + 1 (computed for every block-sparse plan)
+  std::vector<int64_t> lv_col_off, lv_trsm_off, lv_pair_off;
+  std::vector<int32_t> lv_launch_after;
+  DevBuf<int32_t> d_lv_cols, d_lv_trsm_rows, d_lv_trsm_steps, d_lv_pairs, d_lv_kptr, d_lv_k;
+  // schedule: 1 = panel steps, 0 or 2 = levels
+  void build_sparse(const MatDesc& d, const std::vector<uint8_t>& fill, hipStream_t st, int schedule = 0);
+  void build_levels(const std::vector<int32_t>& height, const std::vector<int32_t>& tr, hipStream_t st);
 };
 
 // Symbolic block elimination: closes the lower tile pattern pat[I * nb + J]

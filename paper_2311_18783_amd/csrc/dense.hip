@@ -60,11 +60,12 @@ constexpr int kPotrfCols = NB * NB / kPotrfThreads;   // 16 register columns per
 
 template <typename T>
 __global__ __launch_bounds__(kPotrfThreads) void k_potrf(const MatDesc* __restrict__ desc,
-                                                         const int32_t* __restrict__ order, int step,
+                                                         const int32_t* __restrict__ order, int step_arg,
                                                          T* __restrict__ A, T* __restrict__ Ainv,
                                                          const double* __restrict__ odiag, double drop_tol,
                                                          double* __restrict__ pivrel, DevErr* err,
-                                                         int32_t* __restrict__ failed) {
+                                                         int32_t* __restrict__ failed,
+                                                         const int32_t* __restrict__ steps) {
   extern __shared__ unsigned char smem_raw[];
   T* Ls = reinterpret_cast<T*>(smem_raw);   // [NB * LDA] column-major: L, later X = inv(L)
   __shared__ double colbuf[2][NB];          // current Schur column (unscaled)
@@ -72,7 +73,9 @@ __global__ __launch_bounds__(kPotrfThreads) void k_potrf(const MatDesc* __restri
   __shared__ double invd[NB];               // 1 / L[j][j], 0 for a dropped or failed pivot
   __shared__ double od[NB];                 // original diagonal (drop rule)
   constexpr int H = kPotrfThreads / NB;     // column phases (8)
-  const int m = order[blockIdx.x];
+  // steps != nullptr: one matrix, workgroup b factors the diagonal block of step steps[b]
+  const int m = steps ? order[0] : order[blockIdx.x];
+  const int step = steps ? steps[blockIdx.x] : step_arg;
   if (failed && failed[m]) return;          // abandoned at an earlier step
   const MatDesc d = desc[m];
   const int t = threadIdx.x;
@@ -371,13 +374,15 @@ __device__ inline int find_mat(const int64_t* __restrict__ prefix, int cnt, int6
   return lo;
 }
 
-// L21 = A21 * inv(L11)^T, one 128-row tile per workgroup.
+// L21 = A21 * inv(L11)^T, one 128-row tile per workgroup.  With `steps` (a
+// block-sparse matrix): workgroup b takes row block rows[b] of step steps[b].
 template <typename T, int MODE>
 __global__ __launch_bounds__(64 * TileGeo<MODE>::WAVES) __attribute__((amdgpu_waves_per_eu(1, MODE == 2 ? 1 : 4))) void k_trsm(
     const MatDesc* __restrict__ desc, const int32_t* __restrict__ order, const int64_t* __restrict__ prefix, int cnt,
-    int step, T* __restrict__ A, const T* __restrict__ Ainv, const int32_t* __restrict__ rows,
-    const int32_t* __restrict__ skip) {
+    int step_arg, T* __restrict__ A, const T* __restrict__ Ainv, const int32_t* __restrict__ rows,
+    const int32_t* __restrict__ skip, const int32_t* __restrict__ steps) {
   using G = TileGeo<MODE>;
+  const int step = steps ? steps[blockIdx.x] : step_arg;
   extern __shared__ unsigned char smem_raw[];
   T* smem = reinterpret_cast<T*>(smem_raw);
   const int j = rows ? 0 : find_mat(prefix, cnt, blockIdx.x);
@@ -443,6 +448,35 @@ __global__ __launch_bounds__(64 * TileGeo<MODE>::WAVES) __attribute__((amdgpu_wa
   tile_store<T, G::BJ>(C, d.ld, acc);
 }
 
+// Update of a block-sparse matrix by one elimination-tree level: tile b is
+// (pairs[2b], pairs[2b+1]) and receives
+//   C -= sum over q in [kptr[b], kptr[b+1]) of L[ti][klist[q]] L[tj][klist[q]]^T
+// (in that order).  A kernel of its own: the list loop in k_syrk doubles
+// that kernel's registers.
+template <typename T, int MODE>
+__global__ __launch_bounds__(64 * TileGeo<MODE>::WAVES) __attribute__((amdgpu_waves_per_eu(1, MODE == 2 ? 1 : 4))) void k_syrk_lv(
+    const MatDesc* __restrict__ desc, const int32_t* __restrict__ order, T* __restrict__ A,
+    const int32_t* __restrict__ pairs, const int32_t* __restrict__ kptr, const int32_t* __restrict__ klist,
+    const int32_t* __restrict__ skip) {
+  using G = TileGeo<MODE>;
+  if (skip && skip[order[0]]) return;
+  const MatDesc d = desc[order[0]];
+  const int64_t ti = pairs[2 * (int64_t)blockIdx.x], tj = pairs[2 * (int64_t)blockIdx.x + 1];
+  extern __shared__ unsigned char smem_raw[];
+  T* smem = reinterpret_cast<T*>(smem_raw);
+  using Acc = typename AccT<T>::type;
+  Acc acc[4][G::BJ];
+  T* C = A + d.off + (tj * NB + G::WCOL * G::wc()) * d.ld + ti * NB + 64 * G::wr();
+  tile_load<T, G::BJ>(C, d.ld, acc);
+  const int q1 = kptr[blockIdx.x + 1];
+  for (int q = kptr[blockIdx.x]; q < q1; ++q) {
+    const int64_t kc = (int64_t)klist[q] * NB;
+    tile_mma<T, MODE>(A + d.off + kc * d.ld + ti * NB, d.ld, A + d.off + kc * d.ld + tj * NB, d.ld, acc, true, NB,
+                      smem);
+  }
+  tile_store<T, G::BJ>(C, d.ld, acc);
+}
+
 // ------------------------------------------- recursive diagonal block (FP64)
 constexpr int kRecThreads = 256;
 
@@ -463,8 +497,10 @@ __device__ inline double rl(double v, int lane) {
 // nothing.  Entries above the diagonal are carried along unmasked (finite,
 // never read back), which keeps per-lane predicates out of the column loop.
 // Lane j keeps the pivot data of column j; pivot ratios and failures are
-// written lane-parallel at the end.
-__device__ inline void leaf16(double* Ls, double* ldg, const double* od, int r0, double drop_tol,
+// written lane-parallel at the end.  Forced inline: as a called function it
+// saves and restores the caller's registers through scratch memory on every
+// one of the eight calls per diagonal block.
+__device__ __attribute__((always_inline)) inline void leaf16(double* Ls, double* ldg, const double* od, int r0, double drop_tol,
                               double* pivrel_row, int m, int64_t gcol0, DevErr* err, int32_t* failed) {
   const int lane = threadIdx.x & 63;
   int i = lane & 15;
@@ -664,15 +700,18 @@ template <> __device__ inline void st2<float>(float* p, double2 v) {
 // an FP32 factor stores the FP64 result rounded to FP32.
 template <typename T>
 __global__ __launch_bounds__(kRecThreads) void k_potrf_rec(const MatDesc* __restrict__ desc,
-                                                           const int32_t* __restrict__ order, int step,
+                                                           const int32_t* __restrict__ order, int step_arg,
                                                            T* __restrict__ A, T* __restrict__ Ainv,
                                                            const double* __restrict__ odiag, double drop_tol,
                                                            double* __restrict__ pivrel, DevErr* err,
-                                                           int32_t* __restrict__ failed) {
+                                                           int32_t* __restrict__ failed,
+                                                           const int32_t* __restrict__ steps) {
   extern __shared__ unsigned char smem_raw[];
   double* Ls = reinterpret_cast<double*>(smem_raw);   // [NB * LDA], column-major
   __shared__ double ldg[NB], od[NB];
-  const int m = order[blockIdx.x];
+  // steps != nullptr: one matrix, workgroup b factors the diagonal block of step steps[b]
+  const int m = steps ? order[0] : order[blockIdx.x];
+  const int step = steps ? steps[blockIdx.x] : step_arg;
   if (failed && failed[m]) return;   // abandoned at an earlier step
   const MatDesc d = desc[m];
   const int tid = threadIdx.x;
@@ -891,7 +930,7 @@ void symbolic_fill(int nb, std::vector<uint8_t>& pat) {
   }
 }
 
-void FactorPlan::build_sparse(const MatDesc& dsc, const std::vector<uint8_t>& F, hipStream_t st) {
+void FactorPlan::build_sparse(const MatDesc& dsc, const std::vector<uint8_t>& F, hipStream_t st, int schedule) {
   build(std::vector<MatDesc>(1, dsc), st);   // dense plan of the single matrix: panel steps, items, groups
   sparse = true;
   const int nb = dsc.nblk;
@@ -907,30 +946,68 @@ void FactorPlan::build_sparse(const MatDesc& dsc, const std::vector<uint8_t>& F,
   }
   trsm_off[nb] = (int64_t)tr.size();
   d_trsm_rows.upload(tr.empty() ? std::vector<int32_t>(1, 0) : tr, st);
-  // trailing-update tiles of each launch of the (dense) launch sequence
-  std::vector<int32_t> pairs;
-  syrk_off.assign(syrk.size(), 0);
+  // factorisation flops on the pattern (either schedule): per block column k
+  // with r_k tiles below the diagonal, its diagonal block, r_k triangular
+  // solves and r_k (r_k + 1) / 2 tile products of the update
   sparse_flops = 0;
-  for (size_t li = 0; li < syrk.size(); ++li) {
-    SyrkLaunch& L = syrk[li];
-    syrk_off[li] = (int64_t)pairs.size() / 2;
-    int64_t cnt = 0;
-    if (L.kb > 0) {
-      const int cend = L.ncols ? std::min(nb, L.b0 + L.ncols) : nb;
-      for (int tj = L.b0; tj < cend; ++tj)
-        for (int ti = tj; ti < nb; ++ti) {
-          bool hit = false;
-          for (int sp = L.kcol0; sp < L.kcol0 + L.kb && sp < nb && !hit; ++sp) hit = f(ti, sp) && f(tj, sp);
-          if (!hit) continue;
-          pairs.push_back(ti);
-          pairs.push_back(tj);
-          ++cnt;
-        }
-    }
-    L.tiles = cnt;
-    sparse_flops += (double)cnt * 2.0 * NB * NB * NB * L.kb;
+  for (int k = 0; k < nb; ++k) {
+    const double r = (double)trsm_tiles[k];
+    sparse_flops += (double)NB * NB * NB * (1.0 / 3.0 + r + r * (r + 1.0));
   }
-  d_syrk_pairs.upload(pairs.empty() ? std::vector<int32_t>(2, 0) : pairs, st);
+  // elimination tree: parent = first row block below the diagonal; height
+  std::vector<int32_t> height(nb, 0);
+  for (int j = 0; j < nb; ++j)
+    if (trsm_tiles[j] > 0) {
+      const int par = tr[trsm_off[j]];
+      height[par] = std::max(height[par], height[j] + 1);
+    }
+  n_levels = 0;
+  for (int j = 0; j < nb; ++j) n_levels = std::max(n_levels, height[j] + 1);
+  levels = schedule != 1;
+  syrk_off.assign(syrk.size(), 0);
+  if (!levels) {
+    // trailing-update tiles of each launch of the (dense) launch sequence:
+    // (ti, tj) with tj in the launch's column range and L(ti, sp), L(tj, sp)
+    // both in the pattern for a panel column sp of the launch, ordered by tj
+    // then ti (enumerated from the panels' row lists)
+    std::vector<int32_t> pairs;
+    std::vector<uint8_t> mark((size_t)nb * nb, 0);
+    std::vector<int64_t> keys;
+    for (size_t li = 0; li < syrk.size(); ++li) {
+      SyrkLaunch& L = syrk[li];
+      syrk_off[li] = (int64_t)pairs.size() / 2;
+      keys.clear();
+      if (L.kb > 0) {
+        const int cend = L.ncols ? std::min(nb, L.b0 + L.ncols) : nb;
+        for (int sp = L.kcol0; sp < L.kcol0 + L.kb && sp < nb; ++sp) {
+          const int32_t* rb = tr.data() + trsm_off[sp];
+          const int64_t nr = trsm_off[sp + 1] - trsm_off[sp];
+          for (int64_t bq = 0; bq < nr; ++bq) {
+            const int tj = rb[bq];
+            if (tj < L.b0 || tj >= cend) continue;
+            for (int64_t aq = bq; aq < nr; ++aq) {
+              const int64_t key = (int64_t)tj * nb + rb[aq];
+              if (!mark[(size_t)key]) {
+                mark[(size_t)key] = 1;
+                keys.push_back(key);
+              }
+            }
+          }
+        }
+      }
+      std::sort(keys.begin(), keys.end());
+      for (int64_t key : keys) {
+        mark[(size_t)key] = 0;
+        pairs.push_back((int32_t)(key % nb));
+        pairs.push_back((int32_t)(key / nb));
+      }
+      L.tiles = (int64_t)keys.size();
+    }
+    d_syrk_pairs.upload(pairs.empty() ? std::vector<int32_t>(2, 0) : pairs, st);
+  } else {
+    for (auto& L : syrk) L.tiles = 0;
+    build_levels(height, tr, st);
+  }
   // strictly lower tiles; solve dependencies
   std::vector<int32_t> lo, fp(nb + 1, 0), fd, bp(nb + 1, 0), bd;
   fill_tiles = 0;
@@ -995,8 +1072,97 @@ void FactorPlan::build_sparse(const MatDesc& dsc, const std::vector<uint8_t>& F,
     d_row_help[d].upload(rhelp, st);
   }
   d_part.alloc(std::max<int64_t>((int64_t)max_help * NB, 1));
-  for (int s = 0; s < nb; ++s)
-    sparse_flops += (double)NB * NB * NB / 3.0 + (double)trsm_tiles[s] * NB * NB * NB;
+}
+
+// Level schedule (see FactorPlan): levels are taken in groups of
+// kLevelGroup consecutive ones.  Inside a group, after the diagonal blocks
+// and column tiles of a level, a "thin" update applies the level's columns
+// to the tiles of the group's later columns; after the group, one update
+// applies all the group's columns to every other tile they reach, so such a
+// tile is read and written once per group.  Each (tile, column) product
+// falls in exactly one of the two.
+void FactorPlan::build_levels(const std::vector<int32_t>& height, const std::vector<int32_t>& tr, hipStream_t st) {
+  constexpr int kLevelGroup = 8;
+  const int nb = (int)height.size();
+  std::vector<std::vector<int32_t>> by_level(n_levels);
+  for (int j = 0; j < nb; ++j) by_level[height[j]].push_back(j);
+  std::vector<int32_t> cols, trows, tsteps, lpairs, kptr(1, 0), klist;
+  lv_col_off.assign(1, 0);
+  lv_trsm_off.assign(1, 0);
+  lv_pair_off.assign(1, 0);   // [thin of level 0, ..., thin of the group's last level, trailing of the group, ...]
+  lv_launch_after.clear();
+  std::vector<int32_t> slot((size_t)nb * nb, -1);
+  std::vector<int32_t> cnt, tiles;   // per pair of the launch being built
+  auto rows_of = [&](int k) { return std::make_pair(tr.data() + trsm_off[k], trsm_off[k + 1] - trsm_off[k]); };
+  // one update launch from the (k, ti, tj) triples that `emit` enumerates
+  auto add_launch = [&](auto&& emit, int after_level) {
+    tiles.clear();
+    cnt.clear();
+    emit([&](int k, int a, int b) {
+      int32_t& sl = slot[(size_t)a * nb + b];
+      if (sl < 0) {
+        sl = (int32_t)tiles.size();
+        tiles.push_back(a * nb + b);
+        cnt.push_back(0);
+      }
+      (void)k;
+      ++cnt[sl];
+    });
+    std::vector<int32_t> pos(tiles.size());
+    int32_t base = (int32_t)klist.size(), acc = base;
+    for (size_t p = 0; p < tiles.size(); ++p) {
+      pos[p] = acc;
+      acc += cnt[p];
+      kptr.push_back(acc);
+      lpairs.push_back(tiles[p] / nb);
+      lpairs.push_back(tiles[p] % nb);
+    }
+    klist.resize(acc);
+    emit([&](int k, int a, int b) { klist[pos[slot[(size_t)a * nb + b]]++] = k; });
+    for (int32_t t : tiles) slot[(size_t)t] = -1;
+    lv_pair_off.push_back((int64_t)lpairs.size() / 2);
+    lv_launch_after.push_back(after_level);
+  };
+  for (int h0 = 0; h0 < n_levels; h0 += kLevelGroup) {
+    const int h1 = std::min(n_levels, h0 + kLevelGroup);
+    for (int h = h0; h < h1; ++h) {
+      for (int k : by_level[h]) {
+        cols.push_back(k);
+        auto [rb, nr] = rows_of(k);
+        for (int64_t a = 0; a < nr; ++a) {
+          trows.push_back(rb[a]);
+          tsteps.push_back(k);
+        }
+      }
+      lv_col_off.push_back((int64_t)cols.size());
+      lv_trsm_off.push_back((int64_t)trows.size());
+      if (h + 1 < h1)   // thin: targets in columns of the group's later levels
+        add_launch([&](auto&& visit) {
+          for (int k : by_level[h]) {
+            auto [rb, nr] = rows_of(k);
+            for (int64_t a = 0; a < nr; ++a)
+              for (int64_t b = 0; b <= a; ++b)
+                if (height[rb[b]] < h1) visit(k, rb[a], rb[b]);
+          }
+        }, h);
+    }
+    // trailing: targets in columns beyond the group
+    add_launch([&](auto&& visit) {
+      for (int h = h0; h < h1; ++h)
+        for (int k : by_level[h]) {
+          auto [rb, nr] = rows_of(k);
+          for (int64_t a = 0; a < nr; ++a)
+            for (int64_t b = 0; b <= a; ++b)
+              if (height[rb[b]] >= h1) visit(k, rb[a], rb[b]);
+        }
+    }, h1 - 1);
+  }
+  d_lv_cols.upload(cols, st);
+  d_lv_trsm_rows.upload(trows.empty() ? std::vector<int32_t>(1, 0) : trows, st);
+  d_lv_trsm_steps.upload(tsteps.empty() ? std::vector<int32_t>(1, 0) : tsteps, st);
+  d_lv_pairs.upload(lpairs.empty() ? std::vector<int32_t>(2, 0) : lpairs, st);
+  d_lv_kptr.upload(kptr, st);
+  d_lv_k.upload(klist.empty() ? std::vector<int32_t>(1, 0) : klist, st);
 }
 
 template <typename T, int MODE>
@@ -1017,6 +1183,8 @@ static void factor_run(const FactorPlan& P, T* A, T* Ainv, const double* odiag, 
                                     (int)mma_lds));
       HIP_CHECK(hipFuncSetAttribute((const void*)k_syrk<T, MODE>, hipFuncAttributeMaxDynamicSharedMemorySize,
                                     (int)mma_lds));
+      HIP_CHECK(hipFuncSetAttribute((const void*)k_syrk_lv<T, MODE>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                    (int)mma_lds));
     }
     attr_set = true;
   }
@@ -1029,20 +1197,49 @@ static void factor_run(const FactorPlan& P, T* A, T* Ainv, const double* odiag, 
           P.d_desc.p, P.d_order.p, P.d_syrk_prefix.p + L.pre_off, P.nmat, L.kcol0, L.kb, L.b0, L.ncols, A,
           P.sparse ? P.d_syrk_pairs.p + 2 * P.syrk_off[li_of(L)] : nullptr, failed);
   };
+  if (P.levels) {
+    // elimination-tree levels: the block columns of a level are independent
+    // (none updates another); per level one launch each for their diagonal
+    // blocks and their column tiles, then the update launches due after it
+    size_t u = 0;   // next update launch
+    for (size_t h = 0; h + 1 < P.lv_col_off.size(); ++h) {
+      const int64_t c0 = P.lv_col_off[h], nc = P.lv_col_off[h + 1] - c0;
+      if (rec_potrf)
+        k_potrf_rec<T><<<dim3((unsigned)nc), dim3(kRecThreads), sizeof(double) * NB * LDA, st>>>(
+            P.d_desc.p, P.d_order.p, 0, A, Ainv, odiag, drop_tol, pivrel, err, failed, P.d_lv_cols.p + c0);
+      else
+        k_potrf<T><<<dim3((unsigned)nc), dim3(kPotrfThreads), lds, st>>>(P.d_desc.p, P.d_order.p, 0, A, Ainv, odiag,
+                                                                        drop_tol, pivrel, err, failed,
+                                                                        P.d_lv_cols.p + c0);
+      const int64_t t0 = P.lv_trsm_off[h], nt = P.lv_trsm_off[h + 1] - t0;
+      if (nt > 0)
+        k_trsm<T, MODE><<<dim3((unsigned)nt), dim3(threads), mma_lds, st>>>(
+            P.d_desc.p, P.d_order.p, P.d_prefix.p, 1, 0, A, Ainv, P.d_lv_trsm_rows.p + t0, failed,
+            P.d_lv_trsm_steps.p + t0);
+      for (; u < P.lv_launch_after.size() && P.lv_launch_after[u] == (int32_t)h; ++u) {
+        const int64_t p0 = P.lv_pair_off[u], np = P.lv_pair_off[u + 1] - p0;
+        if (np > 0)
+          k_syrk_lv<T, MODE><<<dim3((unsigned)np), dim3(threads), mma_lds, st>>>(
+              P.d_desc.p, P.d_order.p, A, P.d_lv_pairs.p + 2 * p0, P.d_lv_kptr.p + p0, P.d_lv_k.p, failed);
+      }
+    }
+    HIP_CHECK(hipGetLastError());
+    return;
+  }
   for (int s0 = 0; s0 < P.max_blk; s0 += G) {
     for (int g = 0; g < G && s0 + g < P.max_blk; ++g) {
       const int s = s0 + g;
       const int64_t* pt = P.d_prefix.p + P.pre_off[s];
       if (rec_potrf)
         k_potrf_rec<T><<<dim3(P.cnt[s]), dim3(kRecThreads), sizeof(double) * NB * LDA, st>>>(
-            P.d_desc.p, P.d_order.p, s, A, Ainv, odiag, drop_tol, pivrel, err, failed);
+            P.d_desc.p, P.d_order.p, s, A, Ainv, odiag, drop_tol, pivrel, err, failed, nullptr);
       else
         k_potrf<T><<<dim3(P.cnt[s]), dim3(kPotrfThreads), lds, st>>>(P.d_desc.p, P.d_order.p, s, A, Ainv, odiag,
-                                                                       drop_tol, pivrel, err, failed);
+                                                                       drop_tol, pivrel, err, failed, nullptr);
       if (P.trsm_tiles[s] > 0)
         k_trsm<T, MODE><<<dim3((unsigned)P.trsm_tiles[s]), dim3(threads), mma_lds, st>>>(
             P.d_desc.p, P.d_order.p, pt, P.cnt[s], s, A, Ainv, P.sparse ? P.d_trsm_rows.p + P.trsm_off[s] : nullptr,
-            failed);
+            failed, nullptr);
       run_syrk(P.syrk[li++]);
     }
     run_syrk(P.syrk[li++]);

@@ -1097,6 +1097,9 @@ void setup_precond(geneo_ctx* ctx, geneo_precond* pc) {
   if (pc->opts.coarse_order != GENEO_ORDER_NESTED_DISSECTION && pc->opts.coarse_order != GENEO_ORDER_NATURAL &&
       pc->opts.coarse_order != GENEO_ORDER_AUTO)
     throw Error(GENEO_EINVAL, "unknown coarse order");
+  if (pc->opts.coarse_schedule != GENEO_SCHEDULE_AUTO && pc->opts.coarse_schedule != GENEO_SCHEDULE_STEPS &&
+      pc->opts.coarse_schedule != GENEO_SCHEDULE_LEVELS)
+    throw Error(GENEO_EINVAL, "unknown coarse schedule");
   if (pc->opts.coarse != GENEO_COARSE_NONE)
     snk_thread = std::thread([&] {
       try {
@@ -1362,6 +1365,7 @@ void setup_precond(geneo_ctx* ctx, geneo_precond* pc) {
   }();
   const int nbc = (int)(n0p / NB);
   pc->info.coarse_factor_flops = (double)n0 * n0 * n0 / 3.0;
+  pc->info.coarse_schedule_used = GENEO_SCHEDULE_STEPS;
   // a solve reads every factor tile once per sweep (the diagonal ones as their inverses)
   pc->info.coarse_solve_bytes = 2.0 * ((double)nbc * (nbc + 1) / 2) * NB * NB * sizeof(double);
   if (coarse_sparse && nbc > 1) {
@@ -1377,8 +1381,10 @@ void setup_precond(geneo_ctx* ctx, geneo_precond* pc) {
     hc.mark("coarse E assembled");
     symbolic_fill(nbc, pat);
     hc.mark("coarse symbolic fill");
-    pc->coarse.build_sparse(cd[0], pat, st);
+    pc->coarse.build_sparse(cd[0], pat, st, pc->opts.coarse_schedule);
     hc.mark("coarse plan");
+    pc->info.coarse_levels = pc->coarse.n_levels;
+    pc->info.coarse_schedule_used = pc->coarse.levels ? GENEO_SCHEDULE_LEVELS : GENEO_SCHEDULE_STEPS;
     pc->info.coarse_factor_flops = pc->coarse.sparse_flops;
     pc->info.coarse_fill = (double)pc->coarse.fill_tiles / ((double)nbc * (nbc + 1) / 2);
     pc->info.coarse_solve_bytes = 2.0 * (double)pc->coarse.fill_tiles * NB * NB * sizeof(double);

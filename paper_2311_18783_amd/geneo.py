@@ -34,6 +34,7 @@ WEIGHT_IDENTITY, WEIGHT_POU = 0, 1
 PCG, GMRES = 0, 1
 PCG_DEFLATED, PCG_BALANCED = 0, 1
 ORDER_NATURAL, ORDER_NESTED_DISSECTION, ORDER_AUTO = 0, 1, 2
+SCHEDULE_AUTO, SCHEDULE_STEPS, SCHEDULE_LEVELS = 0, 1, 2
 PART_BOX, PART_RCB, PART_EXPLICIT = 0, 1, 2
 
 
@@ -73,7 +74,7 @@ class SetupOpts(C.Structure):
                 ("lobpcg_guard", C.c_int32), ("seed", C.c_uint64), ("coarse_drop_tol", C.c_double),
                 ("warm_start", C.POINTER(C.c_double)), ("fp32_rho_max", C.c_double),
                 ("model", C.c_void_p), ("keep_ritz", C.c_int32), ("coarse_order", C.c_int32),
-                ("one_level_weight", C.c_int32), ("classical", C.c_int32)]
+                ("one_level_weight", C.c_int32), ("classical", C.c_int32), ("coarse_schedule", C.c_int32)]
 
 
 class PrecondInfo(C.Structure):
@@ -89,7 +90,8 @@ class PrecondInfo(C.Structure):
                 ("fp32_prechecked", C.c_int32), ("fp32_kappa_lb", C.c_double),
                 ("learned_candidates", C.c_int32), ("coarse_nd_levels", C.c_int32),
                 ("coarse_nd_predicted_depth", C.c_int32),
-                ("coarse_solve_depth", C.c_int32), ("t_factor_fp32_ms", C.c_double),
+                ("coarse_solve_depth", C.c_int32), ("coarse_levels", C.c_int32),
+                ("coarse_schedule_used", C.c_int32), ("t_factor_fp32_ms", C.c_double),
                 ("coarse_lambda_min", C.c_double), ("coarse_drop_tol_used", C.c_double),
                 ("coarse_refactors", C.c_int32), ("t_coarse_refactor_ms", C.c_double),
                 ("coarse_solve_bytes", C.c_double), ("t_lobpcg_loop_ms", C.c_double),

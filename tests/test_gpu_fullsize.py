@@ -35,6 +35,14 @@ def cube24():
     return w, s, odec
 
 
+def _apply(ctx, pc, r):
+    import torch
+    z = torch.zeros(r.size, dtype=torch.float64, device="cuda:0")
+    ctx.apply(pc, to_dev(r), z)
+    torch.cuda.synchronize()
+    return z.cpu().numpy()
+
+
 def _spd(n, rng, delta):
     """M M^T / n + delta I: eigenvalues in [delta, ~4 + delta] (Marchenko-Pastur)."""
     M = rng.standard_normal((n, n))
@@ -245,6 +253,46 @@ def test_beam128_eigensolver_converges_on_every_subdomain(g, beam128):
         assert (err <= 1e-8 + 2 * sens).all(), (i, err, sens)
         checked += 1
     assert checked > 0
+
+
+def test_beam128_level_schedule_matches_step_schedule(g, beam128):
+    """The coarse factor of the slab beam (nested-dissection order chosen by
+    AUTO) factored level by level of its block elimination tree and panel
+    step by panel step: the same arithmetic per tile in another grouping of
+    the updates.  The tree has at most half as many levels as block columns
+    (the dissection order makes it shallow), the kept coarse columns are the same,
+    the two preconditioners agree on a random vector to 1e-6 (the coarse
+    matrix is ill-conditioned: smallest scaled eigenvalue estimates down to
+    1e-16, so rounding-order differences are amplified in the coarse
+    correction), and PCG needs the same iterations to 1e-8."""
+    import torch
+    geneo, ctx = g
+    w, s, odec = beam128
+    print("beam128 coarse schedules", flush=True)
+    sysm, dec = lib_problem(ctx, w)
+    pl = ctx.setup(sysm, dec, tau=w.tau, nev_max=w.nev_max)
+    ps = ctx.setup(sysm, dec, tau=w.tau, nev_max=w.nev_max, coarse_schedule=geneo.SCHEDULE_STEPS)
+    il, is_ = pl.info(), ps.info()
+    nbc = -(-(il.n0 - il.n0_local_dropped) // 128)
+    print("levels", il.coarse_levels, "block columns", nbc, "schedule", il.coarse_schedule_used,
+          is_.coarse_schedule_used, "factor ms", il.t_coarse_factor_ms, is_.t_coarse_factor_ms,
+          "rank", il.n0_rank, is_.n0_rank, flush=True)
+    assert il.coarse_schedule_used == geneo.SCHEDULE_LEVELS and is_.coarse_schedule_used == geneo.SCHEDULE_STEPS
+    assert 2 * il.coarse_levels <= nbc
+    assert il.n0_rank == is_.n0_rank
+    r = np.random.default_rng(31).standard_normal(s.n)
+    zl, zs = _apply(ctx, pl, r), _apply(ctx, ps, r)
+    d = np.linalg.norm(zl - zs) / np.linalg.norm(zs)
+    print("apply difference", d, flush=True)
+    assert d <= 1e-6
+    b = w.rhs(s.n)
+    its = []
+    for pc in (pl, ps):
+        x = torch.zeros(s.n, dtype=torch.float64, device="cuda:0")
+        si = ctx.solve(sysm, pc, to_dev(b), x, rtol=1e-8, maxit=2000)
+        its.append(si.iterations)
+    print("PCG iterations", its, flush=True)
+    assert abs(its[0] - its[1]) <= 1
 
 
 def test_cube24_one_level_apply_matches_sparse_direct_local_solves(g, cube24):

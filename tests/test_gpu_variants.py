@@ -133,6 +133,39 @@ def test_gmres_matches_oracle(g, cfg, weight, restart):
     assert tr <= 1.01e-6
 
 
+def test_level_schedule_matches_step_schedule_on_strips(g):
+    """Sixteen strips of the paper's beam (h = 1/16) in nested-dissection
+    order: the coarse factor run by elimination-tree levels (forced) and by
+    panel steps keeps the same columns, and the two preconditioners agree on
+    a random vector to 1e-9 and need the same PCG iterations."""
+    import torch
+    geneo, ctx = g
+    w = W.make("beam16")
+    print("level schedule", w.name, flush=True)
+    sysm, dec = lib_problem(ctx, w)
+    pl = ctx.setup(sysm, dec, tau=w.tau, nev_max=w.nev_max, coarse_order=geneo.ORDER_NESTED_DISSECTION,
+                   coarse_schedule=geneo.SCHEDULE_LEVELS)
+    ps = ctx.setup(sysm, dec, tau=w.tau, nev_max=w.nev_max, coarse_order=geneo.ORDER_NESTED_DISSECTION,
+                   coarse_schedule=geneo.SCHEDULE_STEPS)
+    il, is_ = pl.info(), ps.info()
+    print("levels", il.coarse_levels, "schedules", il.coarse_schedule_used, is_.coarse_schedule_used, "rank",
+          il.n0_rank, is_.n0_rank, "nd levels", il.coarse_nd_levels, flush=True)
+    assert il.coarse_schedule_used == geneo.SCHEDULE_LEVELS and is_.coarse_schedule_used == geneo.SCHEDULE_STEPS
+    assert il.coarse_nd_levels >= 2 and il.coarse_levels > 1
+    assert il.n0_rank == is_.n0_rank
+    n = sysm.info().n
+    r = np.random.default_rng(37).standard_normal(n)
+    d = rel(_apply(ctx, pl, r), _apply(ctx, ps, r))
+    print("apply difference", d, flush=True)
+    assert d <= 1e-9
+    b = w.rhs(n)
+    its = []
+    for pc in (pl, ps):
+        x = torch.zeros(n, dtype=torch.float64, device="cuda:0")
+        its.append(ctx.solve(sysm, pc, to_dev(b), x, rtol=1e-8).iterations)
+    assert its[0] == its[1], its
+
+
 def test_nested_dissection_order_keeps_the_coarse_space(g):
     """The nested-dissection elimination order of the coarse columns on a
     chain of six strip subdomains (12 x 4 x 4 beam, Neumann lateral faces):
