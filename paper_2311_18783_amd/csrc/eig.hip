@@ -232,6 +232,35 @@ __global__ __launch_bounds__(256) void k_residual(int k, const int64_t* __restri
   }
 }
 
+// Per column (j, q): eta[2 (j k + q)] = r^T W = r^T B^-1 r (R the residual
+// block, W = B^-1 R) and eta[2 (j k + q) + 1] = x^T B x.
+__global__ __launch_bounds__(256) void k_eta(int k, const int64_t* __restrict__ voff, const double* __restrict__ R,
+                                             const double* __restrict__ W, const double* __restrict__ X,
+                                             const double* __restrict__ BX, double* __restrict__ eta) {
+  const int j = blockIdx.x / k, q = blockIdx.x % k;
+  const int64_t ld = voff[j + 1] - voff[j];
+  const int64_t o = voff[j] * k + (int64_t)q * ld;
+  double s1 = 0.0, s2 = 0.0;
+  for (int64_t r = threadIdx.x; r < ld; r += 256) {
+    s1 += R[o + r] * W[o + r];
+    s2 += X[o + r] * BX[o + r];
+  }
+  __shared__ double a1[256], a2[256];
+  a1[threadIdx.x] = s1;
+  a2[threadIdx.x] = s2;
+  __syncthreads();
+  for (int st = 128; st > 0; st >>= 1) {
+    if (threadIdx.x < st) {
+      a1[threadIdx.x] += a1[threadIdx.x + st];
+      a2[threadIdx.x] += a2[threadIdx.x + st];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    eta[2 * (j * k + q)] = a1[0];
+    eta[2 * (j * k + q) + 1] = a2[0];
+  }
+}
 
 // Gram partials: for row range [r0, r0 + 512) of subdomain j,
 //   GA[a][b] = sum_r L[r][a] RA[r][b],  GB[a][b] = sum_r L[r][a] RB[r][b]
@@ -1841,7 +1870,10 @@ void solve_local_gevps(geneo_ctx* ctx, geneo_precond* pc) {
   const double tol = pc->opts.lobpcg_tol, tau = pc->opts.tau;
   const bool verbose = std::getenv("GENEO_VERBOSE") != nullptr;
   const double cert_tol = std::max(tol, 1e-4);
-  std::vector<double> h_theta(N * k), h_nrm(N * k * 2);
+  constexpr double kCertRough = 1e-2;
+  std::vector<double> h_theta(N * k), h_nrm(N * k * 2), h_eta(N * k * 2);
+  DevBuf<double> eta;
+  eta.alloc((size_t)N * k * 2);
   std::vector<double> best(N, 1e300);
   std::vector<int> best_it(N, 0);
   bool have_p = false;
@@ -1865,11 +1897,21 @@ void solve_local_gevps(geneo_ctx* ctx, geneo_precond* pc) {
     // after the update moves it off the Rayleigh-Ritz vectors): the shifts that
     // minimise each residual
     if (it > 1) k_rq<<<N * k, 256, 0, st>>>(k, w.voff_d.p, X.p, AX.p, BX.p, nullptr, theta.p);
-    k_residual<<<N * k, 256, 0, st>>>(k, w.voff_d.p, AX.p, BX.p, theta.p, Wb.p, nrm.p, nullptr);
+    k_residual<<<N * k, 256, 0, st>>>(k, w.voff_d.p, AX.p, BX.p, theta.p, Wb.p, nrm.p, T1.p);
+    // W = B^-1 R (used below when the loop goes on) and the B^-1-norms of
+    // the residuals (r^T W, R kept in T1) for the certification bound
+    if (it == 2) HIP_CHECK(hipEventRecord(lt.e[2], st));
+    solve_multi(pc->local, w.LB.p, w.LBinv.p, Wb.p, k, k, ctx->d_sync, w.flags_local.p, ctx->d_err, st);
+    if (it == 2) {
+      HIP_CHECK(hipEventRecord(lt.e[3], st));
+      solve_timed = true;
+    }
+    k_eta<<<N * k, 256, 0, st>>>(k, w.voff_d.p, T1.p, Wb.p, X.p, BX.p, eta.p);
     HIP_CHECK(hipMemcpyAsync(h_theta.data(), theta.p, sizeof(double) * N * k, hipMemcpyDeviceToHost, st));
     HIP_CHECK(hipMemcpyAsync(h_nrm.data(), nrm.p, sizeof(double) * N * k * 2, hipMemcpyDeviceToHost, st));
+    HIP_CHECK(hipMemcpyAsync(h_eta.data(), eta.p, sizeof(double) * N * k * 2, hipMemcpyDeviceToHost, st));
     HIP_CHECK(hipStreamSynchronize(st));
-    int n_active = 0, n_cert = 0;
+    int n_active = 0, n_cert = 0, n_bound = 0;
     double worst_sel = 0.0, worst_cert = 0.0;
     unconv = 0;
     for (int j = 0; j < N; ++j) {
@@ -1892,11 +1934,25 @@ void solve_local_gevps(geneo_ctx* ctx, geneo_precond* pc) {
       const bool stalled = rsel <= 100.0 * tol && it - best_it[j] >= 5;
       bool conv = rsel <= tol || stalled;
       if (!conv) unconv += 1;
-      // the first Ritz value below tau must be settled too
+      // the first Ritz value below tau must be settled too: its residual is
+      // below 1e-4, or the pair is roughly converged (residual below 1e-2,
+      // after the first iteration) and the interval theta +- ||r||_B^-1 /
+      // ||x||_B, which holds an eigenvalue of the pencil for any shift theta,
+      // lies below tau.  The interval alone says nothing about eigenvalues
+      // the block has not yet found (from a random start every Ritz value is
+      // small and its interval below tau).
+      auto below_tau = [&](int q) {
+        const double e1 = h_eta[2 * (j * k + q)], e2 = h_eta[2 * (j * k + q) + 1];
+        return it >= 2 && resid(q) <= kCertRough && e2 > 0.0 && th[q] + std::sqrt(std::max(e1, 0.0) / e2) < tau;
+      };
       if (nsel < nev && nsel < k && !(resid(nsel) <= cert_tol)) {
-        if (conv) ++n_cert;
-        conv = false;
-        worst_cert = std::max(worst_cert, resid(nsel));
+        if (below_tau(nsel)) {
+          ++n_bound;
+        } else {
+          if (conv) ++n_cert;
+          conv = false;
+          worst_cert = std::max(worst_cert, resid(nsel));
+        }
       }
       if (rsel > tol) worst_sel = std::max(worst_sel, rsel);
       active[j] = conv ? 0 : 1;
@@ -1909,20 +1965,16 @@ void solve_local_gevps(geneo_ctx* ctx, geneo_precond* pc) {
       }
     }
     if (verbose)
-      std::fprintf(stderr, "[lobpcg] it %d active %d (certification only %d) worst selected res %.3g worst cert res %.3g\n",
-                   it, n_active, n_cert, worst_sel, worst_cert);
+      std::fprintf(stderr,
+                   "[lobpcg] it %d active %d (certification only %d, certified by the interval %d) worst selected "
+                   "res %.3g worst cert res %.3g\n",
+                   it, n_active, n_cert, n_bound, worst_sel, worst_cert);
     if (n_active == 0 || it == maxit) break;
     HIP_CHECK(hipMemcpyAsync(d_active.p, active.data(), sizeof(int32_t) * N, hipMemcpyHostToDevice, st));
     // W = B^-1 R, B-orthogonal to span(G_j) and X, B-orthonormal.  In exact arithmetic
     // G_j^T B W = G_j^T Atilde X = 0 already; B^-1 amplifies the rounding errors of R along the
     // near-kernel of B (gradients, eigenvalues ~ gamma), so W is projected again (as are the
     // updated X and P below).
-    if (it == 2) HIP_CHECK(hipEventRecord(lt.e[2], st));
-    solve_multi(pc->local, w.LB.p, w.LBinv.p, Wb.p, k, k, ctx->d_sync, w.flags_local.p, ctx->d_err, st);
-    if (it == 2) {
-      HIP_CHECK(hipEventRecord(lt.e[3], st));
-      solve_timed = true;
-    }
     deflate(Wb.p);
     for (int t = 0; t < 2; ++t) {
       bmul(Wb.p, BW.p);

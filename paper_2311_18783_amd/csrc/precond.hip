@@ -23,14 +23,15 @@ namespace geneo {
 // ---------------------------------------------------------- small kernels
 // Dense batch matrices: zero, with ones on the diagonal of the padding rows
 // (r >= n).  Workgroup (c, m) writes column c of matrix m with 16-byte stores
-// (launch: grid (max ld, nmat)).
+// (launch: grid (max ld, nmat)); lower != 0: only rows r >= c (rounded down
+// to even), the part a factorisation reads.
 __global__ __launch_bounds__(256) void k_fill_identity_pad(const MatDesc* __restrict__ desc, double* __restrict__ A,
-                                                           float* __restrict__ Af) {
+                                                           float* __restrict__ Af, int lower = 0) {
   const MatDesc d = desc[blockIdx.y];
   const int c = blockIdx.x;
   if (c >= d.ld) return;
   const int64_t col = d.off + (int64_t)c * d.ld;
-  for (int r = 2 * threadIdx.x; r < d.ld; r += 512) {
+  for (int r = (lower ? (c & ~1) : 0) + 2 * threadIdx.x; r < d.ld; r += 512) {
     const double v0 = (r == c && r >= d.n) ? 1.0 : 0.0, v1 = (r + 1 == c && r + 1 >= d.n) ? 1.0 : 0.0;
     if (A) *reinterpret_cast<double2*>(A + col + r) = double2{v0, v1};
     if (Af) *reinterpret_cast<float2*>(Af + col + r) = float2{(float)v0, (float)v1};
@@ -145,23 +146,6 @@ __global__ void k_w_n(int64_t len, int nsub, const int64_t* __restrict__ voff, c
   b[k] = acc;
 }
 
-// pat[ti * nb + tj] = 1 if the lower tile (ti >= tj) of E holds a non-zero
-__global__ __launch_bounds__(256) void k_tile_pattern(const double* __restrict__ E, int64_t ld, int nb,
-                                                      uint8_t* __restrict__ pat) {
-  const int64_t u = blockIdx.x;
-  int64_t ti = (int64_t)((sqrt(8.0 * (double)u + 1.0) - 1.0) * 0.5);
-  while (ti * (ti + 1) / 2 > u) --ti;
-  while ((ti + 1) * (ti + 2) / 2 <= u) ++ti;
-  const int64_t tj = u - ti * (ti + 1) / 2;
-  int nz = 0;
-  for (int idx = threadIdx.x; idx < NB * NB; idx += 256) {
-    const int r = idx & (NB - 1), c = idx >> 7;
-    if ((ti > tj || r >= c) && E[(tj * NB + c) * ld + ti * NB + r] != 0.0) nz = 1;
-  }
-  nz = __syncthreads_or(nz);
-  if (threadIdx.x == 0) pat[ti * nb + tj] = (uint8_t)(nz ? 1 : 0);
-}
-
 __global__ void k_unit_diag(int64_t m, const int32_t* __restrict__ pos, double* __restrict__ E, int64_t ld) {
   const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (t < m) E[(int64_t)pos[t] * ld + pos[t]] = 1.0;
@@ -191,10 +175,12 @@ __global__ void k_coarse_snk(int64_t nsnk, const int32_t* __restrict__ zc_ptr, c
                              const int32_t* __restrict__ ci, const double* __restrict__ av,
                              const int32_t* __restrict__ zr_ptr, const int32_t* __restrict__ zr_col,
                              const double* __restrict__ zr_val, const int32_t* __restrict__ perm,
-                             double* __restrict__ E, int64_t ld) {
+                             double* __restrict__ E, int64_t ld, uint8_t* __restrict__ tiles, int nbt) {
   int64_t c1 = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (c1 >= nsnk) return;
-  double* col = E + (perm ? perm[c1] : c1) * ld;
+  const int64_t pc1 = perm ? perm[c1] : c1;
+  double* col = E + pc1 * ld;
+  int64_t last = -1;   // last tile marked (consecutive writes mostly share one)
   for (int32_t k1 = zc_ptr[c1]; k1 < zc_ptr[c1 + 1]; ++k1) {
     const int32_t e = zc_row[k1];
     const double z1 = zc_val[k1];
@@ -203,7 +189,16 @@ __global__ void k_coarse_snk(int64_t nsnk, const int32_t* __restrict__ zc_ptr, c
       const double a = av[s] * z1;
       for (int32_t k2 = zr_ptr[f]; k2 < zr_ptr[f + 1]; ++k2) {
         const int32_t c2 = zr_col[k2];
-        col[perm ? perm[c2] : c2] += a * zr_val[k2];
+        const int64_t pr = perm ? perm[c2] : c2;
+        const double v = a * zr_val[k2];
+        col[pr] += v;
+        if (tiles && pr >= pc1 && v != 0.0) {
+          const int64_t t = (pr / NB) * nbt + pc1 / NB;
+          if (t != last) {
+            tiles[t] = 1;
+            last = t;
+          }
+        }
       }
     }
   }
@@ -267,12 +262,18 @@ __global__ void k_coarse_gen(int64_t nsnk, int64_t n, const int32_t* __restrict_
                              const int32_t* __restrict__ nloc, const int64_t* __restrict__ woff,
                              const int32_t* __restrict__ bmap, const double* __restrict__ W,
                              const double* __restrict__ Y, const int32_t* __restrict__ perm,
-                             double* __restrict__ E, int64_t ld) {
+                             double* __restrict__ E, int64_t ld, uint8_t* __restrict__ tiles, int nbt) {
   // lower-triangle entry (r, c) of the natural order, r >= c, at its place in the factor's order
-  auto at = [&](int64_t r, int64_t c) -> double& {
-    if (!perm) return E[c * ld + r];
-    const int64_t pr = perm[r], pc = perm[c];
-    return pr >= pc ? E[pc * ld + pr] : E[pr * ld + pc];
+  // (the tile of a non-zero marked in `tiles`)
+  auto put = [&](int64_t r, int64_t c, double v) {
+    int64_t pr = perm ? perm[r] : r, pc = perm ? perm[c] : c;
+    if (pr < pc) {
+      const int64_t t = pr;
+      pr = pc;
+      pc = t;
+    }
+    if (tiles && v != 0.0) tiles[(pr / NB) * nbt + pc / NB] = 1;
+    E[pc * ld + pr] = v;
   };
   const int64_t g = blockIdx.y;
   int j = 0, hi = nsub - 1;   // subdomain of GenEO column g
@@ -288,7 +289,7 @@ __global__ void k_coarse_gen(int64_t nsnk, int64_t n, const int32_t* __restrict_
   if (c1 < nsnk) {
     double acc = 0.0;
     for (int32_t k = zc_ptr[c1]; k < zc_ptr[c1 + 1]; ++k) acc += zc_val[k] * y[zc_row[k]];
-    at(cg, c1) = acc;               // row cg > c1, column c1
+    put(cg, c1, acc);               // row cg > c1, column c1
     return;
   }
   if (c1 < cg) return;              // upper triangle: not needed
@@ -305,7 +306,7 @@ __global__ void k_coarse_gen(int64_t nsnk, int64_t n, const int32_t* __restrict_
   const int32_t* bm = bmap + voff[lo];
   double acc = 0.0;
   for (int64_t r = 0; r < nloc[lo]; ++r) acc += w[r] * y[bm[r]];
-  at(c1, cg) = acc;                 // row c1 >= cg, column cg
+  put(c1, cg, acc);                 // row c1 >= cg, column cg
 }
 
 // Host side of the support restriction (k_spmm_ring / k_coarse_gen).
@@ -1036,7 +1037,9 @@ void setup_precond(geneo_ctx* ctx, geneo_precond* pc) {
   // pass counts, one fills; subdomains in parallel)
   std::vector<int64_t> lnnz_off(N + 1, 0);
   auto local_triplets = [&](int32_t i, int32_t* lr, int32_t* lc, int32_t* ls) {
-    std::vector<int32_t> g2l(n, -1);
+    // global -> local map, one per thread, reset to -1 after each subdomain
+    thread_local std::vector<int32_t> g2l;
+    if ((int64_t)g2l.size() < n) g2l.assign(n, -1);
     const int64_t b = dec->dofs_ptr[i], e = dec->dofs_ptr[i + 1];
     for (int64_t r = b; r < e; ++r) g2l[dec->dofs[r]] = (int32_t)(r - b);
     int64_t cnt = 0;
@@ -1053,6 +1056,7 @@ void setup_precond(geneo_ctx* ctx, geneo_precond* pc) {
         ++cnt;
       }
     }
+    for (int64_t r = b; r < e; ++r) g2l[dec->dofs[r]] = -1;
     return cnt;
   };
   parallel_for(N, [&](int i) { lnnz_off[i + 1] = local_triplets(i, nullptr, nullptr, nullptr); });
@@ -1308,8 +1312,22 @@ void setup_precond(geneo_ctx* ctx, geneo_precond* pc) {
     HIP_CHECK(hipMemsetAsync(pc->w_c3.p, 0, sizeof(double) * n0p, st));
   }
   HIP_CHECK(hipEventRecord(ctx->ev[0], st));
+  // block sparsity of E: only subdomains whose columns meet through A couple;
+  // the factor touches the tiles of the symbolic fill of that pattern only.
+  // The assembly marks every lower 128 x 128 tile it adds a non-zero to (tiles_E); E is
+  // zeroed in its lower triangle only (the factorisation reads no other part).
+  static const bool coarse_sparse = [] {
+    const char* e = std::getenv("GENEO_COARSE_SPARSE");
+    return !(e && std::string(e) == "0");
+  }();
+  const int nbc = (int)(n0p / NB);
+  DevBuf<uint8_t> tiles_E;
+  if (coarse_sparse && nbc > 1) {
+    tiles_E.alloc((size_t)nbc * nbc);
+    HIP_CHECK(hipMemsetAsync(tiles_E.p, 0, (size_t)nbc * nbc, st));
+  }
   auto fill_E = [&] {
-  k_fill_identity_pad<<<fill_grid(cd), 256, 0, st>>>(pc->coarse.d_desc.p, pc->dE.p, nullptr);
+  k_fill_identity_pad<<<fill_grid(cd), 256, 0, st>>>(pc->coarse.d_desc.p, pc->dE.p, nullptr, 1);
   if (!pad_pos.empty()) {   // pad columns between the groups of the order: unit diagonal
     DevBuf<int32_t> d_pad;
     d_pad.upload(pad_pos, st);
@@ -1319,7 +1337,8 @@ void setup_precond(geneo_ctx* ctx, geneo_precond* pc) {
   if (pc->n_snk)
     k_coarse_snk<<<nblocks(pc->n_snk), 256, 0, st>>>(pc->n_snk, pc->d_zc_ptr.p, pc->d_zc_row.p, pc->d_zc_val.p,
                                                       s->d_rowptr.p, s->d_colind.p, s->d_val.p, pc->d_zr_ptr.p,
-                                                      pc->d_zr_col.p, pc->d_zr_val.p, cperm, pc->dE.p, n0p);
+                                                      pc->d_zr_col.p, pc->d_zr_val.p, cperm, pc->dE.p, n0p,
+                                                      tiles_E.p, nbc);
   if (pc->n_gen) {
     // global dense GenEO columns and Y = A Z_gen
     DevBuf<double> Zg, Y;
@@ -1345,7 +1364,8 @@ void setup_precond(geneo_ctx* ctx, geneo_precond* pc) {
     if (sup.max_cand > 0)
       k_coarse_gen<<<dim3((unsigned)((sup.max_cand + 255) / 256), (unsigned)pc->n_gen), 256, 0, st>>>(
           pc->n_snk, n, pc->d_zc_ptr.p, pc->d_zc_row.p, pc->d_zc_val.p, N, pc->d_gen_off.p, d_cand_ptr.p, d_cand.p,
-          pc->d_voff.p, pc->d_n.p, pc->d_w_off.p, pc->d_bmap.p, pc->d_W.p, Y.p, cperm, pc->dE.p, n0p);
+          pc->d_voff.p, pc->d_n.p, pc->d_w_off.p, pc->d_bmap.p, pc->d_W.p, Y.p, cperm, pc->dE.p, n0p, tiles_E.p,
+          nbc);
     HIP_CHECK(hipStreamSynchronize(st));
   }
   HIP_CHECK(hipGetLastError());
@@ -1357,26 +1377,13 @@ void setup_precond(geneo_ctx* ctx, geneo_precond* pc) {
   fill_E();
   // the coarse plan's diag_off is 0
   HIP_CHECK(hipEventRecord(ctx->ev[1], st));
-  // block sparsity of E: only subdomains whose columns meet through A couple;
-  // the factor touches the tiles of the symbolic fill of that pattern only
-  static const bool coarse_sparse = [] {
-    const char* e = std::getenv("GENEO_COARSE_SPARSE");
-    return !(e && std::string(e) == "0");
-  }();
-  const int nbc = (int)(n0p / NB);
   pc->info.coarse_factor_flops = (double)n0 * n0 * n0 / 3.0;
   pc->info.coarse_schedule_used = GENEO_SCHEDULE_STEPS;
   // a solve reads every factor tile once per sweep (the diagonal ones as their inverses)
   pc->info.coarse_solve_bytes = 2.0 * ((double)nbc * (nbc + 1) / 2) * NB * NB * sizeof(double);
   if (coarse_sparse && nbc > 1) {
-    DevBuf<uint8_t> d_pat;
-    d_pat.alloc((size_t)nbc * nbc);
-    HIP_CHECK(hipMemsetAsync(d_pat.p, 0, (size_t)nbc * nbc, st));
-    const int64_t ntiles = (int64_t)nbc * (nbc + 1) / 2;
-    k_tile_pattern<<<(unsigned)ntiles, 256, 0, st>>>(pc->dE.p, n0p, nbc, d_pat.p);
-    HIP_CHECK(hipGetLastError());
     std::vector<uint8_t> pat((size_t)nbc * nbc);
-    HIP_CHECK(hipMemcpyAsync(pat.data(), d_pat.p, pat.size(), hipMemcpyDeviceToHost, st));
+    HIP_CHECK(hipMemcpyAsync(pat.data(), tiles_E.p, pat.size(), hipMemcpyDeviceToHost, st));
     HIP_CHECK(hipStreamSynchronize(st));
     hc.mark("coarse E assembled");
     symbolic_fill(nbc, pat);
