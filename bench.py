@@ -59,6 +59,9 @@ def parse():
     ap.add_argument("--coarse-order", default="auto", choices=["auto", "natural", "nd"],
                     help="elimination order of the coarse columns (nd: nested dissection of the subdomain graph; "
                          "auto: nested dissection where it shortens the coarse solves' dependency chain)")
+    ap.add_argument("--no-tune", action="store_true",
+                    help="skip the autotuner of the batched factorisation schedule (by default it times the "
+                         "candidate schedules on matrices of the workload's local sizes before the timed steps)")
     ap.add_argument("--coarse-schedule", default="auto", choices=["auto", "steps", "levels"],
                     help="launch schedule of the coarse factorisation (levels: block columns of equal height in "
                          "its elimination tree together; auto: levels when the tree is at most half as tall as "
@@ -403,6 +406,19 @@ def main():
     corder = {"nd": geneo.ORDER_NESTED_DISSECTION, "natural": geneo.ORDER_NATURAL, "auto": geneo.ORDER_AUTO}[a.coarse_order]
     csched = {"auto": geneo.SCHEDULE_AUTO, "steps": geneo.SCHEDULE_STEPS,
               "levels": geneo.SCHEDULE_LEVELS}[a.coarse_schedule]
+    schedules = None
+    if not a.no_tune:
+        # the local (and Neumann) matrix sizes of this workload's decomposition
+        sysm = ctx.assemble(w.mesh, w.mu, w.eps, w.gamma, w.dirichlet)
+        dec = partition(ctx, sysm, w)
+        sizes = [len(dec.subdomain(i)[0]) for i in range(dec.info().n_sub)]
+        del dec, sysm
+        schedules = {}
+        for v in run:
+            prec = variants[v][0]
+            mode, group, potrf, ms, tried = ctx.tune_factor(sizes, prec, reps=2)
+            schedules["fp32" if prec == geneo.FP32_REFINE1 else "fp64"] = {
+                "mode": mode, "group": group, "potrf": potrf, "ms": ms, "candidates": tried}
     if "learned_fp32" in run and a.train_instances > 0:
         model, training = train_model(geneo, ctx, wid, a.train_instances)
     b_host = None
@@ -489,6 +505,8 @@ def main():
         line["speedup_vs_plain_fp64"] = summ["fp64"]["setup_solve_s"] / summ[head]["setup_solve_s"]
     if training:
         line["warm_start_training"] = training
+    if schedules:
+        line["factor_schedules"] = schedules
     if not a.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(w)
     print(json.dumps(line), flush=True)

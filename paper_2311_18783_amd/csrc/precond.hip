@@ -1085,11 +1085,12 @@ void setup_precond(geneo_ctx* ctx, geneo_precond* pc) {
     pc->d_brp.upload(brp, st);
     pc->d_bcol.upload(bcol, st);
   }
+  hc.mark("local triplets");
   pc->d_lrow.upload(lrow, st);
   pc->d_lcol.upload(lcol, st);
   pc->d_lslot.upload(lslot, st);
   pc->d_lnnz_off.upload(lnnz_off, st);
-  hc.mark("local triplets");
+  hc.mark("local triplets uploaded");
 
   // the SNK columns depend on the mesh and the decomposition only
   SnkHost snk;
