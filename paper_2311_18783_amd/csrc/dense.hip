@@ -830,9 +830,11 @@ void FactorPlan::plan_host(const std::vector<MatDesc>& descs, int precision, con
     pre.insert(pre.end(), pt.begin(), pt.end());
     pre.insert(pre.end(), ps.begin(), ps.end());
   }
-  // trailing updates for panel groups of G panels: inside a group, panel g
-  // updates only the group's later block columns; after the group, one
-  // update with all G panels (K = G * NB) covers the rest
+  // trailing updates for panel groups of G panels: inside a group, block
+  // column s0 + g receives the updates of the group's earlier panels in one
+  // launch right before its diagonal block (left-looking: K = g * NB, each
+  // of its tiles read and written once); after the group, one update with
+  // all G panels (K = G * NB) covers the later columns
   cfg = force ? *force : tuned_factor_config(precision, max_blk, nmat);
   group = std::max(1, cfg.group);
   syrk.clear();
@@ -856,8 +858,8 @@ void FactorPlan::plan_host(const std::vector<MatDesc>& descs, int precision, con
   for (int s0 = 0; s0 < max_blk; s0 += group) {
     for (int g = 0; g < group && s0 + g < max_blk; ++g) {
       const int sg = s0 + g;
-      if (g + 1 < group) add_launch(sg, 1, sg + 1, group - 1 - g);   // thin, inside the group
-      else add_launch(-1, 0, 0, 0);                                   // placeholder: none
+      if (g > 0) add_launch(s0, g, sg, 1);   // column sg from panels s0 .. sg - 1
+      else add_launch(-1, 0, 0, 0);          // placeholder: none
     }
     add_launch(s0, group, s0 + group, 0);                            // trailing, K = group * NB
   }
@@ -1229,6 +1231,7 @@ static void factor_run(const FactorPlan& P, T* A, T* Ainv, const double* odiag, 
   for (int s0 = 0; s0 < P.max_blk; s0 += G) {
     for (int g = 0; g < G && s0 + g < P.max_blk; ++g) {
       const int s = s0 + g;
+      run_syrk(P.syrk[li++]);   // column s from the group's earlier panels
       const int64_t* pt = P.d_prefix.p + P.pre_off[s];
       if (rec_potrf)
         k_potrf_rec<T><<<dim3(P.cnt[s]), dim3(kRecThreads), sizeof(double) * NB * LDA, st>>>(
@@ -1240,7 +1243,6 @@ static void factor_run(const FactorPlan& P, T* A, T* Ainv, const double* odiag, 
         k_trsm<T, MODE><<<dim3((unsigned)P.trsm_tiles[s]), dim3(threads), mma_lds, st>>>(
             P.d_desc.p, P.d_order.p, pt, P.cnt[s], s, A, Ainv, P.sparse ? P.d_trsm_rows.p + P.trsm_off[s] : nullptr,
             failed, nullptr);
-      run_syrk(P.syrk[li++]);
     }
     run_syrk(P.syrk[li++]);
   }
