@@ -205,7 +205,8 @@ typedef struct {
   double max_dropped_pivot; /* largest relative Schur pivot dropped */
   double t_extract_ms, t_factor_ms, t_gevp_ms, t_coarse_build_ms, t_coarse_factor_ms; /* device times */
   double local_factor_flops; /* sum n_i^3/3 */
-  double fp32_rho_est;      /* FP32_REFINE1: largest probe estimate of rho(I - Ahat_i^-1 A_i), else 0 */
+  double fp32_rho_est;      /* FP32_REFINE1: largest probe estimate of rho(I - Ahat_i^-1 A_i) (infinite when
+                               fewer than 1 in 8 FP32 factorisations completed: no probe is run), else 0 */
   double coarse_factor_flops; /* flops of the coarse factorisation (on its block-sparse fill pattern) */
   double coarse_fill;       /* fraction of the lower 128 x 128 tiles of E in that pattern (1 = dense) */
   int32_t learned_starts;   /* subdomains whose eigensolver continued from the model's start block: after

@@ -541,15 +541,21 @@ int model_warm_start(geneo_ctx* ctx, const geneo_model* m, const geneo_precond* 
   if (!g.ok) return 0;
   std::vector<float> feat;
   std::vector<int32_t> slot(N, -1), rowmap(pc->batch_len, -1), row_sub(pc->batch_len, 0);
-  std::vector<int32_t> rm;
-  std::vector<float> f(m->in_dim);
+  // canvases of all subdomains in parallel, then packed in subdomain order
+  std::vector<std::vector<float>> fj(N);
+  std::vector<std::vector<int32_t>> rmj(N);
+  std::vector<uint8_t> okj(N, 0);
+  parallel_for(N, [&](int j) {
+    for (int64_t b = pc->voff[j]; b < pc->voff[j + 1]; ++b) row_sub[b] = j;
+    fj[j].resize(m->in_dim);
+    okj[j] = canvas_sample(m, s, dec, g, j, fj[j].data(), rmj[j]) ? 1 : 0;
+  });
   int used = 0;
   for (int j = 0; j < N; ++j) {
-    for (int64_t b = pc->voff[j]; b < pc->voff[j + 1]; ++b) row_sub[b] = j;
-    if (!canvas_sample(m, s, dec, g, j, f.data(), rm)) continue;
+    if (!okj[j]) continue;
     slot[j] = used++;
-    feat.insert(feat.end(), f.begin(), f.end());
-    for (size_t r = 0; r < rm.size(); ++r) rowmap[pc->voff[j] + r] = rm[r];
+    feat.insert(feat.end(), fj[j].begin(), fj[j].end());
+    for (size_t r = 0; r < rmj[j].size(); ++r) rowmap[pc->voff[j] + r] = rmj[j][r];
   }
   if (!used) return 0;
   Net n;

@@ -630,8 +630,12 @@ static void fp32_probe(geneo_ctx* ctx, geneo_precond* pc, const std::vector<MatD
   HIP_CHECK(hipStreamSynchronize(st));
   pc->info.fp32_prechecked = (int32_t)std::count(failed.begin(), failed.end(), 2);
   pc->info.fp32_kappa_lb = klb.empty() ? 0.0 : *std::max_element(klb.begin(), klb.end());
-  const bool any_ok = std::find(failed.begin(), failed.end(), 0) != failed.end();
-  // the power iteration only matters for factors that completed
+  // the power iteration only matters for factors that completed, and only if
+  // at least 1 in kFp32MinShare did: the survivors are among them, so with
+  // fewer the share rule below sends every subdomain to FP64 whatever the
+  // probe finds
+  const int64_t n_ok = std::count(failed.begin(), failed.end(), 0);
+  const bool any_ok = n_ok > 0 && n_ok * kFp32MinShare >= N;
   k_hash_fill<<<nblocks(len), 256, 0, st>>>(len, pc->d_bmap.p, pc->opts.seed ^ 0x5eedull, v);
   for (int it = 0; it < (any_ok ? kPowerSteps : 0); ++it) {
     k_local_residual<<<nblocks(len), 256, 0, st>>>(len, pc->d_brp.p, pc->d_bcol.p, pc->d_lslot.p, s->d_val.p,
@@ -649,7 +653,7 @@ static void fp32_probe(geneo_ctx* ctx, geneo_precond* pc, const std::vector<MatD
   double rho_max = 0.0;
   for (int32_t i = 0; i < N; ++i) {
     double rho = h[i] > 0.0 ? std::sqrt(h[N + i] / h[i]) : (h[N + i] > 0.0 ? INFINITY : 0.0);
-    if (failed[i]) rho = INFINITY;
+    if (failed[i] || !any_ok) rho = INFINITY;
     rho_max = std::max(rho_max, std::isfinite(rho) ? rho : INFINITY);
     (rho <= pc->opts.fp32_rho_max ? d32 : d64).push_back(descs[i]);
   }
