@@ -1395,6 +1395,8 @@ static void gram(EigWork& w, int nl, const double* L0, const double* L1, const d
 }
 
 void solve_local_gevps(geneo_ctx* ctx, geneo_precond* pc) {
+  HostClock hc;
+  hc.tag = "gevp";
   hipStream_t st = ctx->stream;
   const geneo_system* s = pc->sys;
   const geneo_decomp* dec = pc->dec;
@@ -1422,7 +1424,7 @@ void solve_local_gevps(geneo_ctx* ctx, geneo_precond* pc) {
     rp_off[j + 1] = (int64_t)lrp.size();
   }
   {
-    const std::vector<int32_t>& hrow = pc->h_lrow;
+    const auto& hrow = pc->h_lrow;
     for (int j = 0; j < N; ++j) {
       const int64_t n = nloc[j];
       int32_t* rp = lrp.data() + rp_off[j];
@@ -1436,7 +1438,7 @@ void solve_local_gevps(geneo_ctx* ctx, geneo_precond* pc) {
     // distinct local columns of every 64-row block (the LDS-staged products
     // stage those rows of X once per block); host work only, planned before
     // the first upload, which waits for the local factorisation queued ahead
-    const std::vector<int32_t>& hcol = pc->h_lcol;
+    const auto& hcol = pc->h_lcol;
     std::vector<uint16_t> slot(hcol.size(), 0);
     std::vector<std::vector<int32_t>> ub(N), ucnt(N);
     std::vector<int> submax(N, 0);
@@ -1553,7 +1555,7 @@ void solve_local_gevps(geneo_ctx* ctx, geneo_precond* pc) {
   // end nodes of the row's columns; by node rows, the transpose (edge row,
   // entry index)
   {
-    const std::vector<int32_t>& hcol = pc->h_lcol;
+    const auto& hcol = pc->h_lcol;
     std::vector<std::vector<int32_t>> rowlen(N), nodes(N), trow(N), tsrc(N);
     std::vector<std::vector<int64_t>> tpre(N);
     parallel_for(N, [&](int j) {
@@ -1675,6 +1677,7 @@ void solve_local_gevps(geneo_ctx* ctx, geneo_precond* pc) {
   const int64_t dense_total = ld.back().off + (int64_t)ld.back().ld * ld.back().ld;
   w.LB.alloc(dense_total);
   w.LBinv.alloc(pc->dLinv.n ? pc->dLinv.n : pc->fLinv.n);
+  hc.mark("host plans");
   k_fill_pad_identity<<<fill_grid(ld), 256, 0, st>>>(pc->local.d_desc.p, w.LB.p);
   k_dense_scatter_vals<<<nb256(lnnz), 256, 0, st>>>(lnnz, pc->d_lrow.p, pc->d_lcol.p, pc->d_lnnz_off.p, N,
                                                      pc->local.d_desc.p, w.bval.p, w.LB.p);
@@ -1755,6 +1758,7 @@ void solve_local_gevps(geneo_ctx* ctx, geneo_precond* pc) {
       // the random block stays as the competing candidate (P is unused until the first iteration)
       HIP_CHECK(hipMemcpyAsync(P.p, X.p, sizeof(double) * blk, hipMemcpyDeviceToDevice, st));
       learned = model_warm_start(ctx, pc->opts.model, pc, k, nev, X.p);
+      hc.mark("model start block");
     }
   }
 
@@ -1809,6 +1813,7 @@ void solve_local_gevps(geneo_ctx* ctx, geneo_precond* pc) {
     bmul(V.p, BV.p);
   };
   start_block(X, AX, BX, Xn, theta.p);
+  hc.mark("start block queued");
   pc->info.learned_candidates = learned;
   if (learned > 0) {
     // The model's block is judged by its eigen-residuals: both candidates take
@@ -1867,6 +1872,7 @@ void solve_local_gevps(geneo_ctx* ctx, geneo_precond* pc) {
     }
   }
   pc->info.learned_starts = learned;
+  hc.mark("start blocks judged");
   const double tol = pc->opts.lobpcg_tol, tau = pc->opts.tau;
   const bool verbose = std::getenv("GENEO_VERBOSE") != nullptr;
   const double cert_tol = std::max(tol, 1e-4);
@@ -2034,6 +2040,7 @@ void solve_local_gevps(geneo_ctx* ctx, geneo_precond* pc) {
     for (int j = 0; j < N; ++j) bytes += (double)nloc[j] * ((double)nloc[j] + 1.0) * 8.0;
     pc->info.lobpcg_solve_bytes = bytes;
   }
+  hc.mark("iterations done");
   pc->info.lobpcg_iters = it > maxit ? maxit : it;
   pc->info.lobpcg_unconverged = unconv;
 

@@ -5,6 +5,8 @@
 
 #include <algorithm>
 #include <atomic>
+#include <chrono>
+#include <cstdlib>
 #include <cstdint>
 #include <cstdio>
 #include <mutex>
@@ -39,6 +41,43 @@ void parallel_for(int n, F&& f) {
   worker();
   for (auto& t : th) t.join();
 }
+
+// std::vector storage whose elements are not value-initialised (a sized
+// construction or resize leaves them indeterminate): for large host arrays
+// that a parallel pass fills right after, without a serial zero-fill first
+template <class T>
+struct NoInitAlloc : std::allocator<T> {
+  template <class U>
+  struct rebind {
+    using other = NoInitAlloc<U>;
+  };
+  NoInitAlloc() = default;
+  template <class U>
+  NoInitAlloc(const NoInitAlloc<U>&) {}
+  template <class U, class... Args>
+  void construct(U* p, Args&&... args) {
+    if constexpr (sizeof...(Args) == 0)
+      ::new ((void*)p) U;
+    else
+      ::new ((void*)p) U(std::forward<Args>(args)...);
+  }
+};
+template <class T>
+using HostVec = std::vector<T, NoInitAlloc<T>>;
+
+// Host wall clock between marks, printed to stderr with GENEO_VERBOSE set
+struct HostClock {
+  const char* tag = "setup";
+  bool on = std::getenv("GENEO_VERBOSE") != nullptr;
+  std::chrono::steady_clock::time_point t = std::chrono::steady_clock::now();
+  void mark(const char* what) {
+    if (!on) return;
+    const auto now = std::chrono::steady_clock::now();
+    std::fprintf(stderr, "[%s] %-28s %8.2f ms\n", tag, what,
+                 std::chrono::duration<double, std::milli>(now - t).count());
+    t = now;
+  }
+};
 
 struct Error : std::runtime_error {
   int code;
@@ -190,7 +229,8 @@ struct DevBuf {
     n = count;
     cap = bytes;
   }
-  void upload(const std::vector<T>& h, hipStream_t s) {
+  template <class Alloc>
+  void upload(const std::vector<T, Alloc>& h, hipStream_t s) {
     alloc(h.size());
     if (!h.empty()) HIP_CHECK(hipMemcpyAsync(p, h.data(), h.size() * sizeof(T), hipMemcpyHostToDevice, s));
   }

@@ -36,7 +36,7 @@ struct geneo_precond {
   geneo::DevBuf<int32_t> d_lrowptr;          // [sum(n_i)+N], per subdomain rowptr segment
   geneo::DevBuf<int64_t> d_lrow_off;         // [N+1] start of each rowptr segment
   geneo::DevBuf<int32_t> d_lcol, d_lslot, d_lrow;
-  std::vector<int32_t> h_lrow, h_lcol;        // host copies of the local rows / columns (eigensolver plans)
+  geneo::HostVec<int32_t> h_lrow, h_lcol;     // host copies of the local rows / columns (eigensolver plans)
   geneo::DevBuf<int64_t> d_lnnz_off;
 
   // coarse space: SNK columns (sparse) + GenEO columns (dense local blocks)

@@ -847,17 +847,6 @@ static void build_snk_host(const geneo_system* s, const geneo_decomp* dec, SnkHo
 }
 
 // Host-side phase clock of the setup (GENEO_VERBOSE set: printed to stderr).
-struct HostClock {
-  bool on = std::getenv("GENEO_VERBOSE") != nullptr;
-  std::chrono::steady_clock::time_point t = std::chrono::steady_clock::now();
-  void mark(const char* what) {
-    if (!on) return;
-    const auto now = std::chrono::steady_clock::now();
-    std::fprintf(stderr, "[setup] %-28s %8.2f ms\n", what,
-                 std::chrono::duration<double, std::milli>(now - t).count());
-    t = now;
-  }
-};
 
 // Global near-kernel columns Z = G (Section 4, Numerical results, the NK
 // variants): one column per free node, -1 / +1 on the free edges that leave /
@@ -1065,11 +1054,12 @@ void setup_precond(geneo_ctx* ctx, geneo_precond* pc) {
   };
   parallel_for(N, [&](int i) { lnnz_off[i + 1] = local_triplets(i, nullptr, nullptr, nullptr); });
   for (int32_t i = 0; i < N; ++i) lnnz_off[i + 1] += lnnz_off[i];
-  pc->h_lrow.assign(lnnz_off[N], 0);
-  pc->h_lcol.assign(lnnz_off[N], 0);
-  std::vector<int32_t>& lrow = pc->h_lrow;
-  std::vector<int32_t>& lcol = pc->h_lcol;
-  std::vector<int32_t> lslot(lnnz_off[N]);
+  // every entry is written by the fill pass below (no zero-fill first)
+  pc->h_lrow.resize(lnnz_off[N]);
+  pc->h_lcol.resize(lnnz_off[N]);
+  HostVec<int32_t>& lrow = pc->h_lrow;
+  HostVec<int32_t>& lcol = pc->h_lcol;
+  HostVec<int32_t> lslot(lnnz_off[N]);
   parallel_for(N, [&](int i) {
     local_triplets(i, lrow.data() + lnnz_off[i], lcol.data() + lnnz_off[i], lslot.data() + lnnz_off[i]);
   });
@@ -1078,7 +1068,7 @@ void setup_precond(geneo_ctx* ctx, geneo_precond* pc) {
     // FP64 residuals of the refinement step: the triplets come row by row,
     // batch-row pointers and batch columns (slots are d_lslot)
     std::vector<int64_t> brp(voff + 1, 0);
-    std::vector<int32_t> bcol(lrow.size());
+    HostVec<int32_t> bcol(lrow.size());   // every entry written below
     parallel_for(N, [&](int i) {
       for (int64_t t = lnnz_off[i]; t < lnnz_off[i + 1]; ++t) {
         brp[pc->voff[i] + lrow[t] + 1]++;
