@@ -1425,14 +1425,14 @@ void solve_local_gevps(geneo_ctx* ctx, geneo_precond* pc) {
   }
   {
     const auto& hrow = pc->h_lrow;
-    for (int j = 0; j < N; ++j) {
+    parallel_for(N, [&](int j) {   // each subdomain writes its own segment of lrp
       const int64_t n = nloc[j];
       int32_t* rp = lrp.data() + rp_off[j];
       for (int64_t r = 0; r <= n; ++r) rp[r] = (int32_t)pc->lnnz_off[j];
       for (int64_t t = pc->lnnz_off[j]; t < pc->lnnz_off[j + 1]; ++t) rp[hrow[t] + 1]++;
       for (int64_t r = 0; r < n; ++r) rp[r + 1] += rp[r] - (int32_t)pc->lnnz_off[j];
       // rp[r] now = lnnz_off[j] + count of rows < r  (absolute)
-    }
+    });
   }
   {
     // distinct local columns of every 64-row block (the LDS-staged products
@@ -1487,10 +1487,8 @@ void solve_local_gevps(geneo_ctx* ctx, geneo_precond* pc) {
   {
     int64_t off = 0, inv_off = 0, voff = 0;
     int32_t flag_off = 0;
-    std::vector<int32_t> gl(s->n_free_nodes, -1);
     for (int j = 0; j < N; ++j) {
-      const int64_t gb = dec->gn_ptr[j], ge = dec->gn_ptr[j + 1];
-      const int64_t p = ge - gb;
+      const int64_t p = dec->gn_ptr[j + 1] - dec->gn_ptr[j];
       pl[j] = (int32_t)p;
       const int64_t pp = round_up(std::max<int64_t>(p, 1), NB);
       ndesc[j] = MatDesc{off, inv_off, -1, voff, (int32_t)pp, (int32_t)(pp / NB), flag_off, (int32_t)p};
@@ -1499,31 +1497,54 @@ void solve_local_gevps(geneo_ctx* ctx, geneo_precond* pc) {
       w.poff[j] = voff;
       voff += pp;
       flag_off += (int32_t)(pp / NB);
+    }
+    // node -> incident local edges (sign -1 at the edge's first node, +1 at its
+    // second), per subdomain in parallel, then packed in subdomain order
+    std::vector<std::vector<int32_t>> ptr_j(N), edge_j(N);
+    std::vector<std::vector<int8_t>> sign_j(N);
+    parallel_for(N, [&](int j) {
+      thread_local std::vector<int32_t> gl;   // free node -> local node, reset after use
+      if ((int64_t)gl.size() < s->n_free_nodes) gl.assign(s->n_free_nodes, -1);
+      const int64_t gb = dec->gn_ptr[j], ge = dec->gn_ptr[j + 1];
+      const int64_t p = ge - gb;
       for (int64_t t = gb; t < ge; ++t) gl[dec->gnodes[t]] = (int32_t)(t - gb);
-      std::vector<std::vector<std::pair<int32_t, int8_t>>> inc(p);
-      for (int64_t r = dec->dofs_ptr[j]; r < dec->dofs_ptr[j + 1]; ++r) {
-        const int32_t lr = (int32_t)(r - dec->dofs_ptr[j]);
+      std::vector<int32_t>& cnt = ptr_j[j];
+      cnt.assign(p + 1, 0);
+      const int64_t d0 = dec->dofs_ptr[j], d1 = dec->dofs_ptr[j + 1];
+      for (int64_t r = d0; r < d1; ++r) {
+        const int32_t lr = (int32_t)(r - d0);
         const int32_t e = s->free_edges[dec->dofs[r]];
         const int32_t fa = s->node_to_free[s->edges[2 * (int64_t)e]];
         const int32_t fb = s->node_to_free[s->edges[2 * (int64_t)e + 1]];
         const int32_t la = fa >= 0 ? gl[fa] : -1, lb = fb >= 0 ? gl[fb] : -1;
         ena[w.voff[j] + lr] = la;
         enb[w.voff[j] + lr] = lb;
-        if (la >= 0) inc[la].push_back({lr, (int8_t)-1});
-        if (lb >= 0) inc[lb].push_back({lr, (int8_t)1});
+        if (la >= 0) cnt[la + 1]++;
+        if (lb >= 0) cnt[lb + 1]++;
       }
-      ne_off[j] = (int64_t)ne_ptr.size();
-      int32_t acc = 0;
-      ne_ptr.push_back(0);
-      for (int64_t a = 0; a < p; ++a) {
-        for (auto& pr : inc[a]) {
-          ne_edge.push_back(pr.first);
-          ne_sign.push_back(pr.second);
+      for (int64_t a = 0; a < p; ++a) cnt[a + 1] += cnt[a];
+      std::vector<int32_t> pos(cnt.begin(), cnt.end() - 1);
+      edge_j[j].resize(cnt[p]);
+      sign_j[j].resize(cnt[p]);
+      for (int64_t r = d0; r < d1; ++r) {   // in edge order, as each node's list
+        const int32_t lr = (int32_t)(r - d0);
+        const int32_t la = ena[w.voff[j] + lr], lb = enb[w.voff[j] + lr];
+        if (la >= 0) {
+          edge_j[j][pos[la]] = lr;
+          sign_j[j][pos[la]++] = -1;
         }
-        acc += (int32_t)inc[a].size();
-        ne_ptr.push_back(acc);
+        if (lb >= 0) {
+          edge_j[j][pos[lb]] = lr;
+          sign_j[j][pos[lb]++] = 1;
+        }
       }
       for (int64_t t = gb; t < ge; ++t) gl[dec->gnodes[t]] = -1;
+    });
+    for (int j = 0; j < N; ++j) {
+      ne_off[j] = (int64_t)ne_ptr.size();
+      ne_ptr.insert(ne_ptr.end(), ptr_j[j].begin(), ptr_j[j].end());
+      ne_edge.insert(ne_edge.end(), edge_j[j].begin(), edge_j[j].end());
+      ne_sign.insert(ne_sign.end(), sign_j[j].begin(), sign_j[j].end());
     }
     w.poff[N] = voff;
     w.plen = voff;
@@ -1614,6 +1635,7 @@ void solve_local_gevps(geneo_ctx* ctx, geneo_precond* pc) {
     for (int64_t b = 0; b < w.len; ++b) w.h_c_rp[b + 1] += w.h_c_rp[b];
     for (int64_t b = 0; b < w.plen; ++b) w.h_ct_rp[b + 1] += w.h_ct_rp[b];
   }
+  hc.mark("host planning");
   w.c_rp.upload(w.h_c_rp, st);
   w.c_node.upload(w.h_c_node, st);
   w.ct_rp.upload(w.h_ct_rp, st);
@@ -1638,6 +1660,7 @@ void solve_local_gevps(geneo_ctx* ctx, geneo_precond* pc) {
   w.ne_sign.upload(ne_sign, st);
   w.ena.upload(ena, st);
   w.enb.upload(enb, st);
+  hc.mark("uploads");
   std::vector<int64_t> chunk_off(N + 1, 0);
   for (int j = 0; j < N; ++j) chunk_off[j + 1] = chunk_off[j] + (w.voff[j + 1] - w.voff[j] + kGramRows - 1) / kGramRows;
   w.nchunks = chunk_off[N];
