@@ -171,18 +171,40 @@ __global__ __launch_bounds__(256) void k_ltx(int k, const MatDesc* __restrict__ 
   double acc[16];
 #pragma unroll
   for (int t = 0; t < 16; ++t) acc[t] = 0.0;
-  for (int64_t r0 = c0; r0 < d.ld; r0 += kLtChunk) {
-    // stage L[r0 .. r0 + 31, c0 .. c0 + 127] (lower triangle only) and X[r0 .. r0 + 31, 0 .. k - 1]
-    for (int e = tid; e < kLtChunk * NB; e += 256) {
+  // chunk r0: L[r0 .. r0 + 31, c0 .. c0 + 127] (lower triangle only) and
+  // X[r0 .. r0 + 31, 0 .. k - 1], read into registers one chunk ahead of the
+  // one staged in LDS, so the loads overlap the products
+  constexpr int LPT = kLtChunk * NB / 256, XPT = kLtChunk * 32 / 256;
+  double lreg[LPT], xreg[XPT];
+  auto fetch = [&](int64_t r0) {
+#pragma unroll
+    for (int u = 0; u < LPT; ++u) {
+      const int e = tid + 256 * u;
       const int rr = e & (kLtChunk - 1), cc = e >> 5;
       const int64_t r = r0 + rr, c = c0 + cc;
-      lt[rr][cc] = r >= c ? L[d.off + c * d.ld + r] : 0.0;
+      lreg[u] = r >= c ? L[d.off + c * d.ld + r] : 0.0;
     }
-    for (int e = tid; e < kLtChunk * 32; e += 256) {
+#pragma unroll
+    for (int u = 0; u < XPT; ++u) {
+      const int e = tid + 256 * u;
       const int rr = e & (kLtChunk - 1), q = e >> 5;
-      xt[rr][q] = q < k ? Xj[(int64_t)q * ld + r0 + rr] : 0.0;
+      xreg[u] = q < k ? Xj[(int64_t)q * ld + r0 + rr] : 0.0;
+    }
+  };
+  fetch(c0);
+  for (int64_t r0 = c0; r0 < d.ld; r0 += kLtChunk) {
+#pragma unroll
+    for (int u = 0; u < LPT; ++u) {
+      const int e = tid + 256 * u;
+      lt[e & (kLtChunk - 1)][e >> 5] = lreg[u];
+    }
+#pragma unroll
+    for (int u = 0; u < XPT; ++u) {
+      const int e = tid + 256 * u;
+      xt[e & (kLtChunk - 1)][e >> 5] = xreg[u];
     }
     __syncthreads();
+    if (r0 + kLtChunk < d.ld) fetch(r0 + kLtChunk);
 #pragma unroll 4
     for (int rr = 0; rr < kLtChunk; ++rr) {
       const double l = lt[rr][i];
